@@ -1,0 +1,240 @@
+"""Benchmark of the micromagnetic hot path on one MI355X.
+
+Default workload: the 256x256x1 thin film (2x2x1 nm cells, Ms 5.8e5 A/m,
+A 1.5e-11 J/m, interfacial D 3e-3 J/m^2, Ku 8e5 J/m^3 along z, Hz 2e5 A/m,
+alpha 0.3; eight Neel skyrmions of radius 10 nm plus 1e-3 noise) relaxed with
+adaptive Dormand-Prince in FP32.  One step = one attempted adaptive step of the
+whole path (six effective-field + LL evaluations with the fused stage
+combinations, the FP64 error norm, the device controller and the projection),
+run under the library's captured HIP graph.  value = cells x RHS evaluations /
+second over the timed steps, with m resident in HBM.
+
+Also reported: FP64 on the same workload, the 512x512x16 demag-dominated slab
+(FP32 and FP64), per-kernel roofline figures measured with HIP events, and the
+FP64 CPU oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LLG RHS cell-evals/s, FP32 vs FP64 (field rel err ≤1e-5); batched vs 1-by-1"
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_names(nz):
+    if nz == 1:
+        return ["x_fwd", "y_fused_product", "x_inv_fused_llg"]
+    return ["x_fwd", "y_fwd", "z_product", "y_inv", "x_inv_fused_llg"]
+
+
+def pass_bytes(mesh, P, w):
+    """Algorithmic HBM bytes of each pass of one dm/dt evaluation (read + write).
+
+    w: bytes per real.  Complex = 2w.  Xp = Px/2+1 spectral columns kept in x;
+    tensor spectrum K = ncomp * (Pz/2+1) * Xp * (Py/2+1) reals.  The fused last
+    pass reads the x spectrum and m (with its halo from cache) and writes dm/dt.
+    """
+    nx, ny, nz = mesh[:3]
+    Px, Py, Pz = P
+    N = nx * ny * nz
+    Xp = Px // 2 + 1
+    sx = 3 * nz * Xp * ny * 2 * w
+    sy = 3 * nz * Xp * Py * 2 * w
+    ncomp = 4 if nz == 1 else 6
+    K = ncomp * (Pz // 2 + 1) * Xp * (Py // 2 + 1) * w
+    m = 3 * N * w
+    if nz == 1:
+        return [m + sx, sx + K + sx, sx + m + m]
+    return [m + sx, sx + sy, sy + K + sy, sy + sx, sx + m + m]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2406_16064_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2406_16064_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_workload(mm, inputs, torch, idx, prec, steps, warmup, mesh=None):
+    w = inputs.workload(idx)
+    mesh = tuple(mesh or w["mesh"])
+    dt = torch.float32 if prec == "f32" else torch.float64
+    plan = mm.Plan(mesh, prec, terms=w["terms"])
+    params = mm.make_params(terms=w["terms"], **w["params"])
+    m = torch.tensor(inputs.initial_state(idx, mesh), dtype=dt, device="cuda")
+    st = mm.new_states(1, rtol=w["rtol"])
+    t_end = w["t_end"]
+    s = plan.rk45_run(params, m, st, t_end=t_end, max_steps=warmup, check=False)
+    if s not in (mm.MM_OK, mm.MM_E_MAXSTEPS):
+        raise RuntimeError("warmup failed: %s" % mm.status_string(s))
+    torch.cuda.synchronize()
+    n0, a0 = st[0].n_rhs, st[0].n_accept + st[0].n_reject
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    s = plan.rk45_run(params, m, st, t_end=t_end, max_steps=steps, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    if s not in (mm.MM_OK, mm.MM_E_MAXSTEPS):
+        raise RuntimeError("timed run failed: %s" % mm.status_string(s))
+    ms = e0.elapsed_time(e1)
+    evals = st[0].n_rhs - n0
+    attempts = st[0].n_accept + st[0].n_reject - a0
+    N = mesh[0] * mesh[1] * mesh[2]
+    P = plan.padded()
+    us = plan.profile_passes(params, m, reps=30)
+    w_bytes = 4 if prec == "f32" else 8
+    pb = pass_bytes(mesh, P, w_bytes)
+    passes = []
+    for name, t, b in zip(pass_names(mesh[2]), us, pb):
+        passes.append({"kernel": name, "us": round(t, 3), "alg_bytes": b,
+                       "gbs": round(b / (t * 1e-6) / 1e9, 1)})
+    out = {
+        "workload": w["name"], "mesh": list(mesh), "padded": list(P), "dtype": prec,
+        "cell_evals_per_s": N * evals / (ms * 1e-3), "ms_per_step": ms / max(attempts, 1),
+        "steps": attempts, "rhs_evals": evals, "t_sim": st[0].t, "h": st[0].h,
+        "passes": passes,
+        "eval_us": round(sum(us), 3),
+        "demag_pipeline_gbs": round(sum(pb) / (sum(us) * 1e-6) / 1e9, 1),
+    }
+    return out, plan, params, m, mesh
+
+
+def roofline(res, traffic):
+    dom = max(res["passes"], key=lambda p: p["us"])
+    ach = dom["gbs"]
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["kernel"],
+            "alg_bytes_per_launch": dom["alg_bytes"], "us_per_launch": dom["us"]}
+
+
+def load_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when the summary is missing or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    rec = d.get("workloads", {}).get(workload, {}).get(kernel)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def cpu_baseline(inputs, mesh, budget_s=12.0):
+    """The FP64 oracle's dm/dt evaluation timed on this host (as it stands: NumPy +
+    scipy.fft with their default single worker)."""
+    import numpy as np
+    from oracle import fields as F
+    w = inputs.workload(1)
+    p = F.Params(terms=w["terms"], **w["params"])
+    msh = F.Mesh(*mesh)
+    t0 = time.perf_counter()
+    kern = F.DemagKernel(msh)
+    setup = time.perf_counter() - t0
+    m = inputs.initial_state(1, mesh)
+    F.llg_rhs(m, msh, p, kern)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        F.llg_rhs(m, msh, p, kern)
+        n += 1
+    dt = time.perf_counter() - t0
+    N = mesh[0] * mesh[1] * mesh[2]
+    return {"value": N * n / dt, "unit": "cell-evals/s", "cores": 1, "kind": "oracle",
+            "sample": "%d dm/dt evaluations of the %dx%dx%d thin film in %.1f s (tensor setup %.1f s "
+                      "not timed); NumPy/scipy.fft single-threaded" % (n, mesh[0], mesh[1], mesh[2], dt, setup)}, kern
+
+
+def field_error(mm, torch, plan, params, inputs, mesh, kern):
+    import numpy as np
+    from oracle import fields as F
+    w = inputs.workload(1)
+    m = torch.tensor(inputs.initial_state(1, mesh), dtype=torch.float32)
+    H = plan.effective_field(params, m.cuda()).cpu().double().numpy()
+    ref = F.effective_field(m.double().numpy(), F.Mesh(*mesh), F.Params(terms=w["terms"], **w["params"]), kern)
+    d = np.sqrt(np.sum((H - ref) ** 2, axis=0))
+    return float(np.max(d) / np.max(np.sqrt(np.sum(ref ** 2, axis=0))))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2406_16064_amd import inputs
+    from paper_2406_16064_amd import mm
+
+    torch.cuda.set_device(0)
+    print("bench: thin film fp32", file=sys.stderr, flush=True)
+    res, plan, params, m, mesh = run_workload(mm, inputs, torch, 1, "f32", args.steps, args.warmup)
+    extra = {}
+    if not args.no_extra:
+        print("bench: thin film fp64", file=sys.stderr, flush=True)
+        r64, *_ = run_workload(mm, inputs, torch, 1, "f64", max(8, args.steps // 2), 8)
+        extra["thinfilm_f64"] = r64
+        extra["fp32_over_fp64"] = res["cell_evals_per_s"] / r64["cell_evals_per_s"]
+        for prec in ("f32", "f64"):
+            print("bench: 3d slab %s" % prec, file=sys.stderr, flush=True)
+            r3, *_ = run_workload(mm, inputs, torch, 2, prec, 16, 8)
+            extra["slab3d_" + prec] = r3
+        extra["slab3d_fp32_over_fp64"] = (extra["slab3d_f32"]["cell_evals_per_s"] /
+                                          extra["slab3d_f64"]["cell_evals_per_s"])
+        extra["slab3d_f32"]["roofline"] = roofline(extra["slab3d_f32"],
+                                                   load_traffic("slab3d_f32", None))
+    cpu = None
+    if not args.no_cpu:
+        print("bench: cpu oracle", file=sys.stderr, flush=True)
+        cpu, kern = cpu_baseline(inputs, mesh)
+        extra["field_rel_err_f32"] = field_error(mm, torch, plan, params, inputs, mesh, kern)
+    rl = roofline(res, None)
+    rl["traffic"] = load_traffic("thinfilm_f32", rl["kernel"])
+    line = {
+        "metric": METRIC,
+        "value": res["cell_evals_per_s"],
+        "unit": "cell-evals/s",
+        "n_gpus": 1,
+        "steps": res["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "thinfilm-256x256x1 fp32, adaptive Dormand-Prince (rtol 1e-6), "
+                               "exchange+demag+interfacial DMI+uniaxial anisotropy+Zeeman",
+                   "mesh": list(mesh), "padded": res["padded"], "cells": mesh[0] * mesh[1] * mesh[2],
+                   "rhs_evals_timed": res["rhs_evals"]},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "passes": res["passes"],
+        "extra": extra,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

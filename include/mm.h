@@ -1,0 +1,173 @@
+/*
+ * mm.h -- C interface of the MI355X finite-difference micromagnetics hot path.
+ *
+ * The library evaluates the effective field of a regular cell mesh (demag by a
+ * zero-padded FFT convolution with the cell-averaged Newell tensor, six-neighbour
+ * exchange, interfacial DMI, uniaxial anisotropy, Zeeman), the Landau-Lifshitz
+ * right-hand side, and advances it with adaptive Dormand-Prince 5(4) plus
+ * projection onto the unit sphere.  Paper: MicroMagnetic.jl (arXiv 2406.16064),
+ * sections "Micromagnetics" (effective field, exchange, magnetostatic energy
+ * eq_demag_energy2 / eq_hd1, DMI), "Atomistic Spin Model / Anisotropy" and
+ * "Zeeman energy" (the field forms written per cell), "LLG equation" (eq_llg2,
+ * the adaptive Dormand-Prince method and projection), "Miscellaneous" (NEB).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - SI units: lengths in m, fields in A/m, Ms in A/m, A in J/m, D in J/m^2,
+ *   Ku in J/m^3, gamma in m/(A s), time in s, energies in J.
+ * - Magnetisation / field arrays are DEVICE pointers, structure of arrays
+ *   [batch][3][nz][ny][nx], x fastest, element type = the plan's precision
+ *   (float for MM_F32, double for MM_F64).  The caller owns them.
+ * - Compute calls are ordered on the given HIP stream (hipStream_t passed as
+ *   void*; NULL = the default stream) and return before the work finishes,
+ *   except where a call says it synchronises.
+ * - Every call returns an mm_status.  Arguments are validated before any HIP
+ *   call; on MM_E_ARG nothing is launched.  mm_last_error() gives a
+ *   thread-local message for the last failure.  On an integration error the
+ *   magnetisation holds the last accepted state.
+ * - Plans are not thread safe; use one plan per host thread.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MM_OK = 0,
+  MM_E_ARG = -1,            /* invalid argument (sizes, parameters, null pointers)   */
+  MM_E_NOMEM = -2,          /* device allocation failed                              */
+  MM_E_HIP = -3,            /* a HIP runtime call failed (message in mm_last_error)  */
+  MM_E_NONFINITE = -4,      /* NaN/Inf met in the error norm of a step               */
+  MM_E_STEP_UNDERFLOW = -5, /* adaptive step fell below h_min                        */
+  MM_E_MAXSTEPS = -6,       /* attempted-step limit reached before t_end             */
+  MM_E_STATE = -7           /* call not valid in the current plan state              */
+} mm_status;
+
+typedef enum { MM_F32 = 0, MM_F64 = 1 } mm_precision;
+
+/* effective-field terms (bit set) */
+enum {
+  MM_EXCHANGE = 1u,         /* six-neighbour exchange, open boundaries              */
+  MM_DEMAG = 2u,            /* Newell-tensor convolution, zero padded               */
+  MM_DMI_INTERFACIAL = 4u,  /* interfacial (C_nv) DMI, e_ij = e_z x r_ij            */
+  MM_ANIS_UNIAXIAL = 8u,    /* uniaxial anisotropy, easy axis u                     */
+  MM_ZEEMAN = 16u           /* uniform static applied field                         */
+};
+#define MM_ALL_TERMS 31u
+
+/* Regular mesh of nx*ny*nz cuboid cells of size dx*dy*dz (paper: FDMesh).
+ * Limits: 1 <= n <= 2048 per axis, nx >= 2; d > 0 and finite. */
+typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } mm_mesh;
+
+/* Uniform material and field parameters of one instance.
+ * u: easy axis (normalised by the library); H: applied field (A/m).
+ * alpha >= 0, gamma > 0 (2.21e5 is the paper's value), Ms > 0.
+ * terms: subset of the plan's terms that is switched on. */
+typedef struct {
+  double Ms, A, D, Ku;
+  double u[3];
+  double H[3];
+  double alpha, gamma;
+  uint32_t terms;
+} mm_params;
+
+/* Adaptive Dormand-Prince state of one instance (caller owned, plain data so it
+ * can be saved next to m for checkpoint/resume).
+ * Inputs:  t, h (next step to try), rtol (> 0; also the absolute tolerance,
+ *          since |m| = 1), h_min, h_max, fsal_valid (set 0 whenever m was
+ *          changed outside the library, which forces a fresh first slope).
+ * Outputs: t, h, counters, last_err (error norm / rtol of the last attempt),
+ *          last_accepted, fsal_valid. */
+typedef struct {
+  double t, h, rtol, h_min, h_max;
+  int64_t n_accept, n_reject, n_rhs;
+  double last_err;
+  int32_t last_accepted;
+  int32_t fsal_valid;
+} mm_rk45_state;
+
+typedef struct mm_plan mm_plan;
+
+/* Create a plan for `max_batch` instances that share one mesh (the tensor
+ * spectrum is shared; parameters are per instance).  Builds the Newell tensor
+ * (FP64) and its spectrum on the device, then casts it to the plan precision.
+ * `terms` is the set of terms any later call may enable.  Synchronises.
+ * Paper: section "Magnetostatic energy" (Newell tensor, FFT acceleration). */
+mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec,
+                         uint32_t terms, int32_t max_batch, void* hip_stream);
+mm_status mm_plan_destroy(mm_plan* plan);
+
+/* Padded FFT grid chosen for the plan (each P >= 2n-1; x even). */
+mm_status mm_plan_padded(const mm_plan* plan, int32_t* Px, int32_t* Py, int32_t* Pz);
+
+/* Newell tensor entries at integer displacements disp[k] = (I,J,K) (device
+ * int32 array [n][3]); out is a device double array [n][6] ordered
+ * xx, yy, zz, xy, xz, yz.  FP64; synchronous w.r.t. the stream on return of
+ * data only after a stream sync.  Paper: eq_demag_energy2 / eq_hd1. */
+mm_status mm_demag_tensor(const mm_mesh* mesh, const int32_t* disp, int64_t n,
+                          double* out, void* hip_stream);
+
+/* H_eff of `batch` instances: m, H are [batch][3][nz][ny][nx] device arrays;
+ * params is a host array of `batch` entries.  Paper: H_eff = -(1/mu0 Ms) dE/dm
+ * and the per-term formulas of section "Micromagnetics". */
+mm_status mm_effective_field(mm_plan* plan, const mm_params* params, int32_t batch,
+                             const void* m, void* H, void* hip_stream);
+
+/* dm/dt of the LL form (eq_llg2) for `batch` instances; same layout as above. */
+mm_status mm_llg_rhs(mm_plan* plan, const mm_params* params, int32_t batch,
+                     const void* m, void* dmdt, void* hip_stream);
+
+/* Energies in J of `batch` instances, E_out[batch][5] host array ordered
+ * exchange, demag, dmi, anisotropy, zeeman (disabled terms give 0).  FP64
+ * accumulation.  Synchronises.  Paper: w_i (exchange), eq_demag_energy. */
+mm_status mm_energy(mm_plan* plan, const mm_params* params, int32_t batch,
+                    const void* m, double* E_out, void* hip_stream);
+
+/* One attempted adaptive Dormand-Prince step per instance (accepted or
+ * rejected, recorded in st[b]); m is projected onto |m| = 1 after an accepted
+ * step.  st is a host array of `batch` states.  Synchronises.
+ * Paper: section "LLG equation". */
+mm_status mm_rk45_step(mm_plan* plan, const mm_params* params, int32_t batch,
+                       void* m, mm_rk45_state* st, void* hip_stream);
+
+/* Integrate every instance to t_end (or, with replay_h, take exactly the
+ * n_replay accepted steps replay_h[0..n_replay) of host memory, shared by all
+ * instances).  max_steps bounds the attempts per instance.  Steps run under a
+ * device-side controller and a captured HIP graph; the host only polls.
+ * Synchronises.  Returns the first non-OK instance status. */
+mm_status mm_rk45_run(mm_plan* plan, const mm_params* params, int32_t batch,
+                      void* m, mm_rk45_state* st, double t_end, int64_t max_steps,
+                      const double* replay_h, int64_t n_replay, void* hip_stream);
+
+/* Nudged elastic band on a chain of n_img images (n_img <= max_batch, >= 3)
+ * stored as images[n_img][3][nz][ny][nx]: n_iter iterations of the
+ * precession-free relaxation with time step h and spring constant k_spring
+ * (A/m); end images stay fixed.  E_out (host, n_img) receives the image
+ * energies before the last iteration.  Synchronises.  Paper: "Miscellaneous"
+ * (NEB); tangent, spring and distance follow the project's stated reading. */
+mm_status mm_neb_run(mm_plan* plan, const mm_params* params, void* images, int32_t n_img,
+                     double k_spring, double h, int64_t n_iter, double* E_out,
+                     void* hip_stream);
+
+/* Measurement aid: runs `reps` dm/dt evaluations of `batch` instances (output
+ * written to `work`, same layout as m) with a HIP event before every kernel
+ * pass and after the last one, and returns in us_out[0..*n_pass) the mean
+ * duration of each pass in microseconds, in launch order: x forward, y (2-D:
+ * fused forward/product/inverse; 3-D: forward, z with product, inverse),
+ * x inverse with the fused local fields and LL.  Without demag there is one
+ * pass.  us_out must hold at least 5 entries.  Synchronises. */
+mm_status mm_profile_passes(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
+                            void* work, int32_t reps, double* us_out, int32_t* n_pass,
+                            void* hip_stream);
+
+const char* mm_status_string(mm_status s);
+const char* mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MM_H */

@@ -11,6 +11,7 @@ the tableau nor the step-size controller.  The tableau is Dormand and Prince's
 * accept iff err <= 1; after an accepted step m <- y5/|y5| per cell;
 * h_new = h * min(5, max(0.2, 0.9 err^(-1/5))), growth capped at 1 on the
   step right after a rejection; h clipped to h_max and to land on t_end;
+  a remainder t_end - t not above h_min counts as arrived (no step is taken);
 * FSAL: k_7 = f(y5) (before normalisation) is reused as the next k_1;
 * a rejected step leaves m and k_1 untouched.
 """
@@ -107,7 +108,7 @@ def step(f, m, st, t_end=np.inf):
 def run(f, m, st, t_end=np.inf, max_accept=None, max_steps=10 ** 9):
     """Advance until t_end or until max_accept accepted steps."""
     n = 0
-    while st.t < t_end and (max_accept is None or st.n_accept < max_accept):
+    while t_end - st.t > st.h_min and (max_accept is None or st.n_accept < max_accept):
         if n >= max_steps:
             raise RuntimeError("maximum number of attempted steps reached")
         m, _ = step(f, m, st, t_end)

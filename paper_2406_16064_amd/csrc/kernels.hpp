@@ -1,0 +1,93 @@
+// Launch-side view of the hot-path kernels (geometry, stage arguments, launchers).
+#pragma once
+
+#include "mm_internal.hpp"
+
+namespace mmx {
+
+// Mesh and padded-grid geometry shared by every pass.
+struct Geo {
+  int nx, ny, nz;
+  int Px, Py, Pz;
+  int Lx;          // Px / 2: length of the packed complex x transform
+  int Xp;          // Lx + 1: number of kx kept after the real-to-complex transform
+  int Ky, Kz;      // Py/2 + 1, Pz/2 + 1: folded extents of the tensor spectrum
+  long long N;     // cells per instance
+  long long sx;    // complex elements of the x-pass buffer per instance: 3*nz*Xp*ny
+  long long sy;    // complex elements of the y-pass buffer per instance: 3*nz*Xp*Py
+  double dV;       // cell volume
+};
+
+enum Mode : int {
+  MODE_FIELD = 0,        // write H_eff
+  MODE_RHS = 1,          // write dm/dt
+  MODE_STAGE = 2,        // write k_s and the next Runge-Kutta stage input
+  MODE_ERROR = 3,        // write k_7 and reduce the embedded error norm
+  MODE_ENERGY = 4,       // per-term energy partial sums
+  MODE_FIELD_ENERGY = 5  // write H_eff and energy partial sums (NEB)
+};
+
+// What the fused epilogue does after H_eff is known at a cell.
+template <typename T> struct Epi {
+  int mode;
+  T* out;                 // H (FIELD*), dm/dt (RHS), k_s (STAGE/ERROR)
+  const T* mbase;         // m at the start of the step (STAGE)
+  T* msn;                 // next stage input (STAGE)
+  const T* kprev[7];      // k_1..k_7 (entries used by coef)
+  double coef[7];         // stage: a_{s+1,j}; error: b_j - bhat_j; multiplied by h_att
+  int nk;                 // number of k entries combined (including the current one)
+  double* partial;        // energy partials [batch][blocks_per_inst][5]
+  DevCtl* ctl;            // per-instance controller (skip done instances; h_att; err)
+  long long inst_stride;  // elements per instance of m-like arrays (3N)
+};
+
+struct Tuning {
+  int ty_f;     // rows per workgroup of the forward x pass (256 threads)
+  int tpc_f;
+  int ty_x;     // rows per workgroup of the inverse x pass + epilogue (512 threads)
+  int tpc_x;
+  int cb_y;     // columns per workgroup of the 3-D y passes
+  int tpc_y;
+  int cb_y2;    // kx columns per workgroup of the fused 2-D y pass (x3 components)
+  int tpc_y2;
+  int qz;       // (kx,ky) columns per workgroup of the z pass (x3 components)
+  int tpc_z;
+};
+
+template <typename T> struct HotPlan {
+  Geo g;
+  Tuning tu;
+  FftPlan<T> px, py, pz;
+  const Cx<T>* post;       // exp(-2 pi i k / Px), k = 0..Lx
+  const T* kt;             // tensor spectrum [ncomp][Kz][Xp][Ky]
+  int ncomp;               // 4 (nz = 1) or 6
+  Cx<T>* Sx;               // [batch][3][nz][Xp][ny]
+  Cx<T>* Sy;               // [batch][3][nz][Xp][Py] (3-D only)
+  const DevParams* prm;    // [batch]
+};
+
+// One effective-field evaluation followed by the fused epilogue, for `batch`
+// instances stored contiguously at m (stride 3N).  With ev != nullptr an event
+// is recorded before each pass and after the last one (pass timing).
+template <typename T>
+hipError_t launch_eval(const HotPlan<T>& hp, int batch, const T* m, const Epi<T>& epi, bool demag,
+                       hipStream_t s, hipEvent_t* ev = nullptr);
+
+template <typename T>
+hipError_t launch_begin(const Geo& g, int batch, T* m, T* ms0, const T* ms1, T* k1, const T* k7,
+                        double a21, DevCtl* ctl, hipStream_t s);
+
+hipError_t launch_controller(DevCtl* ctl, int batch, const double* replay_h, hipStream_t s);
+
+hipError_t launch_energy_reduce(const double* partial, int batch, int blocks_per_inst, double* out,
+                                hipStream_t s);
+
+int eval_blocks_per_inst(const Geo& g, const Tuning& tu);
+
+// NEB: tangent/projection sums (pass A) and the relaxation update (pass B).
+template <typename T>
+hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T* H,
+                      const double* E5, double cq, double cz, double* sums, double* partial,
+                      double k_spring, double h_g2, int pass, hipStream_t s);
+
+}  // namespace mmx

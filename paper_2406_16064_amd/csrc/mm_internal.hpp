@@ -1,0 +1,73 @@
+// Internal types shared by the HIP kernels and the host runtime of the
+// micromagnetics hot path (gfx950).  Not part of the C interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mm.h"
+
+namespace mmx {
+
+constexpr double kMu0 = 4e-7 * 3.14159265358979323846264338327950288;
+constexpr int kMaxFFT = 2048;     // longest 1-D transform supported
+constexpr int kMaxStages = 12;    // radix stages of one transform
+
+template <typename T> struct Cx { T x, y; };
+
+template <typename T> __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ Cx<T> cconj(Cx<T> a) { return {a.x, -a.y}; }
+template <typename T> __device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// Radix plan of one transform length: L = prod(rad[s]); stage s has span ns[s]
+// (product of the radices before it).  tw points at exp(-2 pi i m / L), m < L.
+template <typename T> struct FftPlan {
+  int L;
+  int nst;
+  int rad[kMaxStages];
+  int ns[kMaxStages];
+  const Cx<T>* tw;
+};
+
+// Per-instance coefficients, precomputed in FP64 on the host.
+struct DevParams {
+  double Ms;
+  double cex[3];     // 2A / (mu0 Ms d_a^2) for a = x, y, z
+  double cdmi[2];    // D / (mu0 Ms d_a) for a = x, y
+  double can;        // 2 Ku / (mu0 Ms)
+  double u[3];       // easy axis, normalised
+  double H[3];       // applied field
+  double g1, g2;     // -gamma/(1+alpha^2), -alpha gamma/(1+alpha^2)
+  double demag_scale;  // -Ms / (Px Py Pz)
+  uint32_t terms;
+  uint32_t pad;
+};
+
+// Per-instance Dormand-Prince controller state in device memory.
+struct DevCtl {
+  double t, h, t_end, rtol, h_min, h_max;
+  double h_att;           // step size of the attempt in flight
+  double last_err;        // err / rtol of the last attempt
+  unsigned long long err_bits;  // running max of ||e_i|| (bits of a non-negative double)
+  long long n_accept, n_reject, n_attempt, max_attempt;
+  long long replay_pos, replay_n;
+  int pending_finish;     // 1: the last attempt was accepted and m not yet projected
+  int after_reject;
+  int done;
+  int status;             // mm_status of this instance
+  int last_accepted;
+  int pad;
+};
+
+// Dormand-Prince 5(4) tableau (Dormand & Prince 1980), stored in double.
+struct DPTab {
+  double a[7][7];
+  double b[7];
+  double e[7];  // b - bhat
+};
+
+}  // namespace mmx

@@ -1,0 +1,235 @@
+"""Thin ctypes binding of the C interface in include/mm.h (argument marshalling only).
+
+Every computation runs in the HIP library libmmx.so; this module only converts
+Python values and torch tensors to the C structures and device pointers.
+Importing it raises if the library has not been built: there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmmx.so")
+
+MM_OK, MM_E_ARG, MM_E_NOMEM, MM_E_HIP = 0, -1, -2, -3
+MM_E_NONFINITE, MM_E_STEP_UNDERFLOW, MM_E_MAXSTEPS, MM_E_STATE = -4, -5, -6, -7
+MM_F32, MM_F64 = 0, 1
+EXCHANGE, DEMAG, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
+ALL_TERMS = 31
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmmx.so is not built; run `python -m paper_2406_16064_amd.build` "
+                      "(the HIP library is required, there is no CPU fallback)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("D", ctypes.c_double),
+                ("Ku", ctypes.c_double), ("u", ctypes.c_double * 3), ("H", ctypes.c_double * 3),
+                ("alpha", ctypes.c_double), ("gamma", ctypes.c_double), ("terms", ctypes.c_uint32)]
+
+
+class RK45State(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("h_min", ctypes.c_double), ("h_max", ctypes.c_double),
+                ("n_accept", ctypes.c_int64), ("n_reject", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
+                ("last_err", ctypes.c_double), ("last_accepted", ctypes.c_int32),
+                ("fsal_valid", ctypes.c_int32)]
+
+
+_vp, _i32, _i64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_P = ctypes.POINTER
+_sigs = {
+    "mm_plan_create": [_P(_vp), _P(Mesh), ctypes.c_int, ctypes.c_uint32, _i32, _vp],
+    "mm_plan_destroy": [_vp],
+    "mm_plan_padded": [_vp, _P(_i32), _P(_i32), _P(_i32)],
+    "mm_demag_tensor": [_P(Mesh), _vp, _i64, _vp, _vp],
+    "mm_effective_field": [_vp, _P(Params), _i32, _vp, _vp, _vp],
+    "mm_llg_rhs": [_vp, _P(Params), _i32, _vp, _vp, _vp],
+    "mm_energy": [_vp, _P(Params), _i32, _vp, _P(_dbl), _vp],
+    "mm_rk45_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _vp],
+    "mm_rk45_run": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _i64, _vp],
+    "mm_neb_run": [_vp, _P(Params), _vp, _i32, _dbl, _dbl, _i64, _P(_dbl), _vp],
+    "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
+}
+for _n, _a in _sigs.items():
+    _f = getattr(_lib, _n)
+    _f.argtypes = _a
+    _f.restype = ctypes.c_int
+_lib.mm_status_string.argtypes = [ctypes.c_int]
+_lib.mm_status_string.restype = ctypes.c_char_p
+_lib.mm_last_error.argtypes = []
+_lib.mm_last_error.restype = ctypes.c_char_p
+
+EXPORTED = tuple(_sigs) + ("mm_status_string", "mm_last_error")
+
+
+class MMError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.mm_last_error().decode()
+        super().__init__("%s: %s (%d): %s" % (where, _lib.mm_status_string(status).decode(), status, msg))
+
+
+def _check(st, where):
+    if st != MM_OK:
+        raise MMError(st, where)
+
+
+def status_string(st):
+    return _lib.mm_status_string(st).decode()
+
+
+def make_params(Ms, A=0.0, D=0.0, Ku=0.0, u=(0.0, 0.0, 1.0), H=(0.0, 0.0, 0.0), alpha=0.5,
+                gamma=2.21e5, terms=ALL_TERMS):
+    p = Params()
+    p.Ms, p.A, p.D, p.Ku = Ms, A, D, Ku
+    for k in range(3):
+        p.u[k] = u[k]
+        p.H[k] = H[k]
+    p.alpha, p.gamma, p.terms = alpha, gamma, terms
+    return p
+
+
+def _params_array(params):
+    if isinstance(params, Params):
+        params = [params]
+    arr = (Params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p if isinstance(p, Params) else make_params(**p)
+    return arr
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def new_states(n, t=0.0, h=1e-13, rtol=1e-6, h_min=1e-20, h_max=1e-10):
+    arr = (RK45State * n)()
+    for s in arr:
+        s.t, s.h, s.rtol, s.h_min, s.h_max = t, h, rtol, h_min, h_max
+    return arr
+
+
+class Plan:
+    """A plan for up to max_batch instances sharing one mesh (mm_plan_create)."""
+
+    def __init__(self, mesh, precision="f32", terms=ALL_TERMS, max_batch=1, stream=None):
+        self.mesh = Mesh(*mesh)
+        self.prec = MM_F32 if precision in ("f32", MM_F32) else MM_F64
+        self.terms = terms
+        self.max_batch = max_batch
+        self._h = ctypes.c_void_p()
+        _check(_lib.mm_plan_create(ctypes.byref(self._h), ctypes.byref(self.mesh), self.prec,
+                                   terms, max_batch, _stream(stream)), "mm_plan_create")
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.prec == MM_F32 else torch.float64
+
+    def padded(self):
+        a, b, c = _i32(), _i32(), _i32()
+        _check(_lib.mm_plan_padded(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "mm_plan_padded")
+        return a.value, b.value, c.value
+
+    def _batch(self, m):
+        return 1 if m.dim() == 4 else m.shape[0]
+
+    def effective_field(self, params, m, out=None, stream=None):
+        import torch
+        out = torch.empty_like(m) if out is None else out
+        pa = _params_array(params)
+        _check(_lib.mm_effective_field(self._h, pa, self._batch(m), _ptr(m), _ptr(out), _stream(stream)),
+               "mm_effective_field")
+        return out
+
+    def llg_rhs(self, params, m, out=None, stream=None):
+        import torch
+        out = torch.empty_like(m) if out is None else out
+        pa = _params_array(params)
+        _check(_lib.mm_llg_rhs(self._h, pa, self._batch(m), _ptr(m), _ptr(out), _stream(stream)),
+               "mm_llg_rhs")
+        return out
+
+    def energy(self, params, m, stream=None):
+        b = self._batch(m)
+        E = (ctypes.c_double * (5 * b))()
+        pa = _params_array(params)
+        _check(_lib.mm_energy(self._h, pa, b, _ptr(m), E, _stream(stream)), "mm_energy")
+        return np.array(E[:]).reshape(b, 5)
+
+    def rk45_step(self, params, m, states, stream=None):
+        pa = _params_array(params)
+        st = _lib.mm_rk45_step(self._h, pa, self._batch(m), _ptr(m), states, _stream(stream))
+        _check(st, "mm_rk45_step")
+        return states
+
+    def rk45_run(self, params, m, states, t_end=math.inf, max_steps=10 ** 9, replay_h=None,
+                 stream=None, check=True):
+        pa = _params_array(params)
+        if replay_h is not None:
+            rh = (ctypes.c_double * len(replay_h))(*replay_h)
+            n = len(replay_h)
+        else:
+            rh, n = None, 0
+        st = _lib.mm_rk45_run(self._h, pa, self._batch(m), _ptr(m), states, t_end, max_steps, rh, n,
+                              _stream(stream))
+        if check:
+            _check(st, "mm_rk45_run")
+        return st
+
+    def neb_run(self, params, images, k_spring, h, n_iter, stream=None):
+        n_img = images.shape[0]
+        E = (ctypes.c_double * n_img)()
+        _check(_lib.mm_neb_run(self._h, _params_array(params), _ptr(images), n_img, k_spring, h, n_iter,
+                               E, _stream(stream)), "mm_neb_run")
+        return np.array(E[:])
+
+    def profile_passes(self, params, m, reps=20, stream=None):
+        """Mean duration (us) of each kernel pass of one dm/dt evaluation."""
+        import torch
+        work = torch.empty_like(m)
+        us = (ctypes.c_double * 8)()
+        n = _i32()
+        _check(_lib.mm_profile_passes(self._h, _params_array(params), self._batch(m), _ptr(m), _ptr(work),
+                                      reps, us, ctypes.byref(n), _stream(stream)), "mm_profile_passes")
+        return list(us[:n.value])
+
+    def close(self):
+        if self._h:
+            _lib.mm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def demag_tensor(mesh, disp, stream=None):
+    """Newell tensor at integer displacements disp (array [n,3]) -> numpy [n,6] (FP64, device-computed)."""
+    import torch
+    d = torch.as_tensor(np.ascontiguousarray(disp, dtype=np.int32)).cuda()
+    out = torch.empty((d.shape[0], 6), dtype=torch.float64, device="cuda")
+    _check(_lib.mm_demag_tensor(ctypes.byref(Mesh(*mesh)), _ptr(d), d.shape[0], _ptr(out), _stream(stream)),
+           "mm_demag_tensor")
+    return out.cpu().numpy()

@@ -1,0 +1,61 @@
+"""C interface checks that need no GPU: the library loads, exports every symbol
+declared in include/mm.h, and rejects invalid arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2406_16064_amd", "libmmx.so")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mm_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def mm():
+    if not os.path.exists(LIB):
+        pytest.fail("libmmx.so not built (run python -m paper_2406_16064_amd.build)")
+    from paper_2406_16064_amd import mm as m
+    return m
+
+
+def test_exports_every_declared_symbol(mm):
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(mm.EXPORTED)
+
+
+def test_status_strings(mm):
+    assert mm.status_string(0) == "ok"
+    assert "argument" in mm.status_string(-1)
+    assert "h_min" in mm.status_string(-5)
+
+
+def test_invalid_arguments_rejected_before_hip(mm):
+    lib = mm._lib
+    out = ctypes.c_void_p()
+    assert lib.mm_plan_create(ctypes.byref(out), None, 0, 31, 1, None) == mm.MM_E_ARG
+    bad = [mm.Mesh(1, 4, 1, 1e-9, 1e-9, 1e-9),       # nx < 2
+           mm.Mesh(8, 0, 1, 1e-9, 1e-9, 1e-9),       # ny < 1
+           mm.Mesh(8, 8, 1, -1e-9, 1e-9, 1e-9),      # negative cell
+           mm.Mesh(8, 8, 1, float("nan"), 1e-9, 1e-9),
+           mm.Mesh(4096, 8, 1, 1e-9, 1e-9, 1e-9)]    # beyond the supported size
+    for msh in bad:
+        assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(msh), 0, 31, 1, None) == mm.MM_E_ARG
+        assert lib.mm_last_error()
+    good = mm.Mesh(8, 8, 1, 1e-9, 1e-9, 1e-9)
+    assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 7, 31, 1, None) == mm.MM_E_ARG
+    assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 64, 1, None) == mm.MM_E_ARG
+    assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 31, 0, None) == mm.MM_E_ARG
+    assert lib.mm_effective_field(None, None, 1, None, None, None) == mm.MM_E_ARG
+    assert lib.mm_plan_destroy(None) == mm.MM_E_ARG
+    assert lib.mm_neb_run(None, None, None, 3, 1e5, 1e-14, 1, None, None) == mm.MM_E_ARG
+    assert lib.mm_demag_tensor(ctypes.byref(bad[0]), None, 1, None, None) == mm.MM_E_ARG

@@ -1,0 +1,254 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C interface.
+
+Tolerances (stated per result, as max_i |dH_i| / max_i |H_i| unless noted):
+* FP64 path: 1e-11 for fields (the tensors of the two sides differ by ~1e-12
+  relative; the FFT rounding is ~1e-14), 1e-10 for energies;
+* FP32 path: 1e-5 for H_eff (the stated FP32 target), evaluated on an m that
+  is exactly representable in FP32 so both sides see the same input bits;
+* integrator: FP64 single steps to 1e-10, FP64 trajectories to 1e-9 with the
+  same accept/reject decisions; FP32 replayed trajectories to 1e-4 in m.
+Meshes span several x/y tiles with ragged tails, odd padded lengths (radix 3),
+a 1-D chain, the minimum mesh and 3-D slabs.
+"""
+import numpy as np
+import pytest
+
+from oracle import dp45, neb, newell
+from oracle import fields as F
+from paper_2406_16064_amd import inputs
+
+from _util import field_err, gpu_params, oracle_params, representable, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mm():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_2406_16064_amd import mm as m
+    return m
+
+
+PAR = dict(Ms=5.8e5, A=1.5e-11, D=3e-3, Ku=8e5, u=(0.2, -0.3, 1.0), H=(3e4, -2e4, 2e5), alpha=0.3)
+DT = {"f32": torch.float32, "f64": torch.float64}
+TOL = {"f32": 1e-5, "f64": 1e-11}
+
+MESHES = [
+    (16, 16, 1, 4e-9, 4e-9, 3e-9),
+    (18, 21, 1, 2e-9, 2e-9, 1e-9),     # ragged y tiles, Py = 48 (radix 3)
+    (24, 20, 5, 3e-9, 3e-9, 3e-9),     # 3-D, Pz = 9 (odd, radix 3)
+    (15, 6, 2, 2e-9, 3e-9, 1e-9),      # odd nx (Px = 32), nz = 2
+    (40, 1, 1, 1e-9, 1e-9, 1e-9),      # 1-D chain (Py = Pz = 1)
+    (2, 1, 1, 1e-9, 2e-9, 3e-9),       # smallest mesh
+    (96, 70, 3, 2e-9, 2e-9, 2e-9),     # several tiles in x and y, Py = 144
+]
+
+_kern_cache = {}
+
+
+def _kernel(mesh):
+    if mesh not in _kern_cache:
+        _kern_cache[mesh] = F.DemagKernel(F.Mesh(*mesh))
+    return _kern_cache[mesh]
+
+
+def _rand_m(mesh, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return inputs.random_unit(mesh[0], mesh[1], mesh[2], rng)
+
+
+@pytest.mark.parametrize("d", [(4e-9, 4e-9, 3e-9), (2e-9, 2e-9, 1e-9), (5e-9, 5e-9, 5e-9),
+                               (1e-9, 1e-9, 0.4e-9), (2e-9, 3e-9, 1e-9)])
+def test_tensor_entries(mm, d):
+    rng = np.random.default_rng(5)
+    disp = np.concatenate([
+        np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1], [2, -1, 0], [-3, 2, 1]]),
+        rng.integers(-6, 7, size=(40, 3)),
+        rng.integers(-600, 600, size=(40, 3)) * np.array([1, 1, 0]) + rng.integers(-30, 30, size=(40, 3)),
+    ]).astype(np.int32)
+    got = mm.demag_tensor((8, 8, 8) + d, disp)
+    ref = newell.tensor(disp[:, 0], disp[:, 1], disp[:, 2], *d)
+    scale = np.max(np.abs(ref), axis=1)
+    assert np.all(np.abs(got - ref) <= 1e-10 * scale[:, None] + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("mesh", MESHES)
+def test_effective_field_all_terms(mm, mesh, prec):
+    print("case", mesh, prec, flush=True)
+    m = representable(_rand_m(mesh, 11), DT[prec])
+    plan = mm.Plan(mesh, prec, terms=mm.ALL_TERMS)
+    H = plan.effective_field(gpu_params(mm, PAR, mm.ALL_TERMS), to_dev(m, DT[prec]))
+    ref = F.effective_field(m, F.Mesh(*mesh), oracle_params(PAR, F.ALL_TERMS), _kernel(mesh))
+    err = field_err(H.cpu().numpy(), ref)
+    assert err <= TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("term", [1, 2, 4, 8, 16])
+def test_each_term(mm, term, prec):
+    mesh = (24, 20, 5, 3e-9, 3e-9, 3e-9) if term == 2 else (18, 21, 1, 2e-9, 2e-9, 1e-9)
+    m = representable(_rand_m(mesh, 12), DT[prec])
+    plan = mm.Plan(mesh, prec, terms=mm.ALL_TERMS)
+    H = plan.effective_field(gpu_params(mm, PAR, term), to_dev(m, DT[prec]))
+    ref = F.effective_field(m, F.Mesh(*mesh), oracle_params(PAR, term), _kernel(mesh))
+    err = field_err(H.cpu().numpy(), ref)
+    assert err <= TOL[prec], (term, err)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_llg_rhs(mm, prec):
+    mesh = (24, 20, 5, 3e-9, 3e-9, 3e-9)
+    m = representable(_rand_m(mesh, 13), DT[prec])
+    plan = mm.Plan(mesh, prec, terms=mm.ALL_TERMS)
+    k = plan.llg_rhs(gpu_params(mm, PAR, mm.ALL_TERMS), to_dev(m, DT[prec]))
+    ref = F.llg_rhs(m, F.Mesh(*mesh), oracle_params(PAR, F.ALL_TERMS), _kernel(mesh))
+    assert field_err(k.cpu().numpy(), ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("mesh", [MESHES[1], MESHES[2]])
+def test_energies(mm, mesh, prec):
+    m = representable(_rand_m(mesh, 14), DT[prec])
+    plan = mm.Plan(mesh, prec, terms=mm.ALL_TERMS)
+    E = plan.energy(gpu_params(mm, PAR, mm.ALL_TERMS), to_dev(m, DT[prec]))[0]
+    ref = F.energies(m, F.Mesh(*mesh), oracle_params(PAR, F.ALL_TERMS), _kernel(mesh))
+    scale = np.sum(np.abs(ref))
+    tol = 1e-5 if prec == "f32" else 1e-10
+    assert np.all(np.abs(E - ref) <= tol * scale), (E, ref)
+
+
+def test_batch_matches_single_calls(mm):
+    mesh = (18, 21, 1, 2e-9, 2e-9, 1e-9)
+    ms = np.stack([_rand_m(mesh, 20 + i) for i in range(3)])
+    pars = []
+    for i in range(3):
+        p = dict(PAR)
+        p["Ms"] = PAR["Ms"] * (1 + 0.3 * i)
+        p["alpha"] = 0.1 * (i + 1)
+        pars.append(gpu_params(mm, p, mm.ALL_TERMS))
+    plan = mm.Plan(mesh, "f32", terms=mm.ALL_TERMS, max_batch=3)
+    mb = to_dev(ms, torch.float32)
+    Hb = plan.llg_rhs(pars, mb).cpu().numpy()
+    for i in range(3):
+        Hi = plan.llg_rhs(pars[i], to_dev(ms[i], torch.float32)).cpu().numpy()
+        assert np.array_equal(Hb[i], Hi)
+
+
+# ----------------------------------------------------------------------------- integrator
+
+def _c1():
+    w = inputs.workload(0)
+    return w, w["mesh"], inputs.initial_state(0)
+
+
+def test_rk45_single_step_fp64(mm):
+    w, mesh, m0 = _c1()
+    p = w["params"]
+    plan = mm.Plan(mesh, "f64", terms=w["terms"])
+    kern = _kernel(mesh)
+    op = oracle_params(p, w["terms"])
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, kern)
+    for h0 in (1e-13, 2e-11):  # an accepted and a rejected first attempt
+        md = to_dev(m0, torch.float64)
+        st = mm.new_states(1, h=h0, rtol=1e-6)
+        plan.rk45_step(gpu_params(mm, p, w["terms"]), md, st)
+        ost = dp45.State(h=h0, rtol=1e-6)
+        mo, acc = dp45.step(f, m0.copy(), ost)
+        assert bool(st[0].last_accepted) == acc
+        assert abs(st[0].last_err - ost.last_err) <= 1e-9 * max(1.0, ost.last_err)
+        assert abs(st[0].h - ost.h) <= 1e-9 * ost.h  # h_new follows err^(-1/5)
+        assert field_err(md.cpu().numpy(), mo) <= 1e-12
+
+
+def test_rk45_trajectory_fp64_c1(mm):
+    """Workload 0: 200 accepted adaptive steps, GPU FP64 against the oracle."""
+    w, mesh, m0 = _c1()
+    p = w["params"]
+    kern = _kernel(mesh)
+    op = oracle_params(p, w["terms"])
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, kern)
+    ost = dp45.State(rtol=w["rtol"])
+    mo = dp45.run(f, m0.copy(), ost, max_accept=w["accepted_steps"])
+    plan = mm.Plan(mesh, "f64", terms=w["terms"])
+    gp = gpu_params(mm, p, w["terms"])
+    md = to_dev(m0, torch.float64)
+    st = mm.new_states(1, rtol=w["rtol"])
+    plan.rk45_run(gp, md, st, t_end=ost.t)
+    # same decisions; the last step may split in two where the step sizes differ
+    # at the 1e-12 level and t_end is met from a hair below
+    assert abs(st[0].n_accept - ost.n_accept) <= 1 and st[0].n_reject == ost.n_reject
+    assert st[0].t == ost.t
+    assert np.max(np.abs(md.cpu().numpy() - mo)) <= 1e-9
+    # replay of the oracle's accepted steps
+    md2 = to_dev(m0, torch.float64)
+    st2 = mm.new_states(1, rtol=w["rtol"])
+    plan.rk45_run(gp, md2, st2, replay_h=ost.accepted_h)
+    assert st2[0].n_accept == len(ost.accepted_h)
+    assert np.max(np.abs(md2.cpu().numpy() - mo)) <= 1e-9
+    # |m| = 1 after the last accepted step
+    assert np.max(np.abs(np.linalg.norm(md.cpu().numpy(), axis=0) - 1)) < 1e-14
+
+
+def test_rk45_fp32_replay_thin_film(mm):
+    """Thin-film terms on a reduced mesh: FP32 trajectory with the oracle's steps, m within 1e-4."""
+    w = inputs.workload(1)
+    mesh = (48, 40, 1) + w["mesh"][3:]
+    p = w["params"]
+    m0 = representable(inputs.initial_state(1, mesh), torch.float32)
+    kern = _kernel(mesh)
+    op = oracle_params(p, w["terms"])
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, kern)
+    ost = dp45.State(rtol=w["rtol"])
+    mo = dp45.run(f, m0.copy(), ost, max_accept=60)
+    plan = mm.Plan(mesh, "f32", terms=w["terms"])
+    md = to_dev(m0, torch.float32)
+    st = mm.new_states(1, rtol=w["rtol"])
+    plan.rk45_run(gpu_params(mm, p, w["terms"]), md, st, replay_h=ost.accepted_h)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-4
+
+
+def test_rk45_errors(mm):
+    mesh = (16, 16, 1, 4e-9, 4e-9, 3e-9)
+    plan = mm.Plan(mesh, "f64", terms=mm.ALL_TERMS)
+    gp = gpu_params(mm, PAR, mm.ALL_TERMS)
+    m = to_dev(_rand_m(mesh, 3), torch.float64)
+    st = mm.new_states(1, rtol=1e-30, h=1e-13, h_min=1e-16)
+    s = plan.rk45_run(gp, m, st, t_end=1e-9, check=False)
+    assert s == mm.MM_E_STEP_UNDERFLOW
+    st = mm.new_states(1, rtol=1e-6)
+    s = plan.rk45_run(gp, m, st, t_end=1e-9, max_steps=5, check=False)
+    assert s == mm.MM_E_MAXSTEPS
+    bad = m.clone()
+    bad[0, 0, 3, 3] = float("nan")
+    st = mm.new_states(1, rtol=1e-6)
+    s = plan.rk45_run(gp, bad, st, t_end=1e-9, check=False)
+    assert s == mm.MM_E_NONFINITE
+
+
+# ----------------------------------------------------------------------------- NEB
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_neb_iterations(mm, prec):
+    w = inputs.workload(3)
+    mesh = (24, 20, 1) + w["mesh"][3:]
+    chain = inputs.slerp_chain(inputs.skyrmion_film(24, 20, 1, 1e-9, 1e-9, [(12e-9, 10e-9)], R=5e-9),
+                               np.concatenate([np.zeros((2, 1, 20, 24)), np.ones((1, 1, 20, 24))]), 6)
+    chain = [representable(c, DT[prec]) for c in chain]
+    p = w["params"]
+    op = oracle_params(p, w["terms"])
+    kern = _kernel(mesh)
+    imgs = [c.copy() for c in chain]
+    for _ in range(5):
+        imgs, E = neb.neb_iteration(imgs, F.Mesh(*mesh), op, kern, w["k_spring"], w["h"])
+    plan = mm.Plan(mesh, prec, terms=w["terms"], max_batch=6)
+    dev = to_dev(np.stack(chain), DT[prec])
+    Eg = plan.neb_run(gpu_params(mm, p, w["terms"]), dev, w["k_spring"], w["h"], 5)
+    out = dev.cpu().numpy()
+    tol = 1e-10 if prec == "f64" else 1e-4
+    for i in range(6):
+        assert np.max(np.linalg.norm(out[i] - imgs[i], axis=0)) <= tol, i
+    np.testing.assert_allclose(Eg, E, rtol=1e-9 if prec == "f64" else 1e-4)
