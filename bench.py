@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--only", choices=["slab3d"], default=None,
+                    help="profiling aid: run only the 512x512x16 slab (FP32) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -187,6 +189,10 @@ def main():
     from paper_2406_16064_amd import mm
 
     torch.cuda.set_device(0)
+    if args.only == "slab3d":
+        r3, *_ = run_workload(mm, inputs, torch, 2, "f32", args.steps, args.warmup)
+        print(json.dumps(r3))
+        return
     print("bench: thin film fp32", file=sys.stderr, flush=True)
     res, plan, params, m, mesh = run_workload(mm, inputs, torch, 1, "f32", args.steps, args.warmup)
     extra = {}

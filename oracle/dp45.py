@@ -13,7 +13,10 @@ the tableau nor the step-size controller.  The tableau is Dormand and Prince's
   step right after a rejection; h clipped to h_max and to land on t_end;
   a remainder t_end - t not above h_min counts as arrived (no step is taken);
 * FSAL: k_7 = f(y5) (before normalisation) is reused as the next k_1;
-* a rejected step leaves m and k_1 untouched.
+* a rejected step leaves m and k_1 untouched;
+* a non-finite error norm (the stages overflowed, or m holds NaN) counts as a
+  rejection with the smallest factor 0.2; ten such attempts in a row stop the
+  integration with a non-finite status.
 """
 from fractions import Fraction as F
 
@@ -40,6 +43,13 @@ class StepUnderflow(RuntimeError):
     pass
 
 
+class NonFinite(RuntimeError):
+    pass
+
+
+MAX_NONFINITE = 10
+
+
 class State:
     """Integrator state: time, next step size, tolerances, counters, FSAL slope."""
 
@@ -51,6 +61,7 @@ class State:
         self.k1 = None
         self.after_reject = False
         self.accepted_h = []
+        self.nonfinite = 0
 
 
 def _normalize(y):
@@ -85,8 +96,18 @@ def step(f, m, st, t_end=np.inf):
     h = min(st.h, st.h_max, t_end - st.t)
     if h < st.h_min:
         raise StepUnderflow("step size %.3e below h_min" % h)
-    y5, k7, err = attempt(f, m, st, h)
+    with np.errstate(over="ignore", invalid="ignore"):
+        y5, k7, err = attempt(f, m, st, h)
     st.last_err = err
+    if not np.isfinite(err):
+        st.nonfinite += 1
+        st.n_reject += 1
+        st.after_reject = True
+        st.h = h * FAC_MIN
+        if st.nonfinite >= MAX_NONFINITE:
+            raise NonFinite("non-finite error norm in %d attempts in a row" % st.nonfinite)
+        return m, False
+    st.nonfinite = 0
     if err <= 1.0:
         fac = FAC_MAX if err == 0.0 else min(FAC_MAX, max(FAC_MIN, SAFETY * err ** -0.2))
         if st.after_reject:

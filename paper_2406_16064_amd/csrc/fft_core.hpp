@@ -142,4 +142,146 @@ __device__ void fft_columns(Cx<T>* lds, const FftPlan<T>& p, int cs, int ncol, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Same transform with the first stage reading its inputs straight from global
+// memory (ld(c, e) -> element e of column c, zero padding included) and/or the
+// last stage writing straight to global memory (st(c, e, v)); the stages in
+// between go through LDS.  Saves one LDS round trip and one barrier at each
+// end.  The caller makes sure LDS is free before the call when GIN, and syncs
+// before reusing LDS after the call when GOUT.
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool INV, bool GIN, bool GOUT, class Load, class Store>
+__device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int L, int Ns, int lane, int tpc,
+                                             bool active, const Cx<T>* __restrict__ tw, Load& ld, Store& st) {
+  constexpr int NB = 16 / R;
+  const int nbf = L / R;
+  Cx<T> v[NB][R];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int j = lane + k * tpc;
+    if (active && j < nbf) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if constexpr (GIN) v[k][r] = ld(c, j + r * nbf);
+        else v[k][r] = col[pidx(j + r * nbf)];
+      }
+    }
+  }
+  if constexpr (!GIN) __syncthreads();
+  const int tstep = L / (Ns * R);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int j = lane + k * tpc;
+    if (active && j < nbf) {
+      const int kk = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          Cx<T> w = tw[r * kk * tstep];
+          if (INV) w.y = -w.y;
+          v[k][r] = cmul(v[k][r], w);
+        }
+      }
+      dftR<T, R, INV>(v[k]);
+      const int base = (j / Ns) * Ns * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if constexpr (GOUT) st(c, base + r * Ns, v[k][r]);
+        else col[pidx(base + r * Ns)] = v[k][r];
+      }
+    }
+  }
+  if constexpr (!GOUT) __syncthreads();
+}
+
+template <typename T, bool INV, bool GIN, bool GOUT, class Load, class Store>
+__device__ __forceinline__ void fft_stage_any(Cx<T>* col, int c, const FftPlan<T>& p, int s, int lane, int tpc,
+                                              bool active, Load& ld, Store& st) {
+  switch (p.rad[s]) {
+    case 8: fft_stage_io<T, 8, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
+    case 4: fft_stage_io<T, 4, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
+    case 3: fft_stage_io<T, 3, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
+    default: fft_stage_io<T, 2, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
+  }
+}
+
+template <typename T, bool INV, bool GIN, bool GOUT, class Load, class Store>
+__device__ void fft_columns_io(Cx<T>* lds, const FftPlan<T>& p, int cs, int ncol, int tpc, Load ld, Store st) {
+  const int c = threadIdx.x / tpc;
+  const int lane = threadIdx.x % tpc;
+  const bool active = c < ncol;
+  Cx<T>* col = lds + (active ? c : 0) * cs;
+  if (p.nst == 0) {  // length 1: identity
+    if (active && lane == 0) {
+      Cx<T> v;
+      if constexpr (GIN) v = ld(c, 0);
+      else v = col[0];
+      if constexpr (GOUT) st(c, 0, v);
+      else col[0] = v;
+    }
+    if constexpr (!GOUT) __syncthreads();
+    return;
+  }
+  if (p.nst == 1) {
+    fft_stage_any<T, INV, GIN, GOUT>(col, c, p, 0, lane, tpc, active, ld, st);
+    return;
+  }
+  fft_stage_any<T, INV, GIN, false>(col, c, p, 0, lane, tpc, active, ld, st);
+  for (int s = 1; s + 1 < p.nst; ++s) fft_stage_any<T, INV, false, false>(col, c, p, s, lane, tpc, active, ld, st);
+  fft_stage_any<T, INV, false, GOUT>(col, c, p, p.nst - 1, lane, tpc, active, ld, st);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap so that consecutive tiles -- which share cache lines and halo
+// rows -- run on the same XCD.  Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ long long xcd_tile(long long bid, long long nblk) {
+  if (nblk % 8 != 0) return bid;
+  return (bid % 8) * (nblk / 8) + bid / 8;
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident transform of compile-time length L held by one thread
+// (Stockham stages unrolled at compile time; radices 8/4/2/3; the twiddles are
+// read from the uniform table tw[m] = exp(-2 pi i m / L)).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int reg_radix(int rem) {
+  return (rem % 8 == 0 && rem != 16) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : 3;
+}
+
+template <typename T, int L, int Ns, bool INV>
+struct RegFft {
+  static __device__ __forceinline__ void run(Cx<T>* v, const Cx<T>* __restrict__ tw) {
+    constexpr int R = reg_radix(L / Ns);
+    constexpr int NB = L / R;
+    Cx<T> o[L];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int kk = j % Ns;
+      Cx<T> a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = v[j + r * NB];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          Cx<T> w = tw[r * kk * (L / (Ns * R))];
+          if (INV) w.y = -w.y;
+          a[r] = cmul(a[r], w);
+        }
+      }
+      dftR<T, R, INV>(a);
+      const int base = (j / Ns) * Ns * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[base + r * Ns] = a[r];
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) v[i] = o[i];
+    RegFft<T, L, Ns * R, INV>::run(v, tw);
+  }
+};
+
+template <typename T, int L, bool INV>
+struct RegFft<T, L, L, INV> {
+  static __device__ __forceinline__ void run(Cx<T>*, const Cx<T>*) {}
+};
+
 }  // namespace mmx

@@ -35,6 +35,7 @@ namespace mmx {
 constexpr int kNT = 256;   // threads of the forward x pass and pointwise kernels
 constexpr int kNTI = 512;  // threads of the fused x-inverse epilogue
 constexpr int kCPT = 8;    // cells owned by one thread in the fused x-inverse epilogue
+constexpr int kUnroll = 8; // global loads kept in flight per thread when filling LDS
 
 template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
 template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return 1.0f / sqrtf(v); }
@@ -53,14 +54,14 @@ __device__ __forceinline__ double wave_max(double v) {
 // x forward: real-to-complex of TY rows (fixed b, c, z), transposed store.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kNT) k_fwd_x(HotPlan<T> hp, const T* __restrict__ m,
+__global__ void __launch_bounds__(512) k_fwd_x(HotPlan<T> hp, const T* __restrict__ m,
                                                const DevCtl* __restrict__ ctl) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   const Geo& g = hp.g;
   const int TY = hp.tu.ty_f;
   const int tiles = (g.ny + TY - 1) / TY;
-  long long bid = blockIdx.x;
+  long long bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tile = bid % tiles; bid /= tiles;
   const int z = bid % g.nz; bid /= g.nz;
   const int c = bid % 3;
@@ -69,21 +70,20 @@ __global__ void __launch_bounds__(kNT) k_fwd_x(HotPlan<T> hp, const T* __restric
   const int y0 = tile * TY;
   const int cs = col_stride(g.Lx);
   const T* src = m + ((size_t)b * 3 + c) * g.N + (size_t)z * g.ny * g.nx;
-  const int tot = TY * g.Lx;
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int r = t / g.Lx, n = t - r * g.Lx;
-    const int y = y0 + r;
+  // element n of row r packs x[2n] + i x[2n+1] (zero beyond nx and past the last row)
+  auto ld = [&](int r, int n) -> Cx<T> {
     Cx<T> v = {T(0), T(0)};
+    const int y = y0 + r;
     if (y < g.ny) {
       const T* row = src + (size_t)y * g.nx;
       const int i0 = 2 * n;
       if (i0 < g.nx) v.x = row[i0];
       if (i0 + 1 < g.nx) v.y = row[i0 + 1];
     }
-    lds[r * cs + pidx(n)] = v;
-  }
-  __syncthreads();
-  fft_columns<T, false>(lds, hp.px, cs, TY, hp.tu.tpc_f);
+    return v;
+  };
+  auto st = [](int, int, Cx<T>) {};
+  fft_columns_io<T, false, true, false>(lds, hp.fp[0], cs, TY, hp.tu.tpc_f, ld, st);
   Cx<T>* dst = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny;
   const int tot2 = TY * g.Xp;
   for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
@@ -145,35 +145,28 @@ __global__ void __launch_bounds__(512) k_y_fused2d(HotPlan<T> hp, const DevCtl* 
   const int ncol = 3 * CB;
   const int cs = col_stride(g.Py);
   Cx<T>* base = hp.Sx + (size_t)b * g.sx;  // [3][1][Xp][ny]
-  // load: column col = c*CB + j holds component c of kx = kx0 + j
-  for (int t = threadIdx.x; t < ncol * g.Py; t += blockDim.x) {
-    const int col = t / g.Py, y = t - col * g.Py;
+  // column col = c*CB + j holds component c of kx = kx0 + j
+  const int Xp = g.Xp, ny = g.ny;
+  auto ld = [=](int col, int y) -> Cx<T> {
     const int c = col / CB, j = col - c * CB;
-    const int kx = kx0 + j;
-    Cx<T> v = {T(0), T(0)};
-    if (y < g.ny && kx < g.Xp) v = base[((size_t)c * g.Xp + kx) * g.ny + y];
-    lds[col * cs + pidx(y)] = v;
-  }
-  __syncthreads();
-  fft_columns<T, false>(lds, hp.py, cs, ncol, hp.tu.tpc_y2);
+    const bool ok = y < ny && kx0 + j < Xp;
+    return ok ? base[((size_t)c * Xp + kx0 + j) * ny + y] : Cx<T>{T(0), T(0)};
+  };
+  auto st = [=](int col, int y, Cx<T> v) {
+    const int c = col / CB, j = col - c * CB;
+    if (y < ny && kx0 + j < Xp) base[((size_t)c * Xp + kx0 + j) * ny + y] = v;
+  };
+  fft_columns_io<T, false, true, false>(lds, hp.fp[1], cs, ncol, hp.tu.tpc_y2, ld, st);
+  const T s = T(hp.prm[b].demag_scale);
   for (int t = threadIdx.x; t < CB * g.Py; t += blockDim.x) {
     const int j = t / g.Py, ky = t - j * g.Py;
     const int kx = kx0 + j;
     if (kx >= g.Xp) continue;
-    Cx<T>& a = lds[(0 * CB + j) * cs + pidx(ky)];
-    Cx<T>& bb = lds[(1 * CB + j) * cs + pidx(ky)];
-    Cx<T>& cc = lds[(2 * CB + j) * cs + pidx(ky)];
-    const T s = T(hp.prm[b].demag_scale);
-    tensor_apply(hp, kx, ky, 0, s, a, bb, cc);
+    tensor_apply(hp, kx, ky, 0, s, lds[(0 * CB + j) * cs + pidx(ky)], lds[(1 * CB + j) * cs + pidx(ky)],
+                 lds[(2 * CB + j) * cs + pidx(ky)]);
   }
   __syncthreads();
-  fft_columns<T, true>(lds, hp.py, cs, ncol, hp.tu.tpc_y2);
-  for (int t = threadIdx.x; t < ncol * g.ny; t += blockDim.x) {
-    const int col = t / g.ny, y = t - col * g.ny;
-    const int c = col / CB, j = col - c * CB;
-    const int kx = kx0 + j;
-    if (kx < g.Xp) base[((size_t)c * g.Xp + kx) * g.ny + y] = lds[col * cs + pidx(y)];
-  }
+  fft_columns_io<T, true, false, true>(lds, hp.fp[1], cs, ncol, hp.tu.tpc_y2, ld, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,22 +187,17 @@ __global__ void __launch_bounds__(512) k_y3d(HotPlan<T> hp, const DevCtl* __rest
   const long long row0 = tile * CB;
   const int ncol = (int)((rows_per_inst - row0) < CB ? (rows_per_inst - row0) : CB);
   const int cs = col_stride(g.Py);
-  const Cx<T>* src = INV ? hp.Sy + (size_t)b * g.sy : hp.Sx + (size_t)b * g.sx;
-  Cx<T>* dst = INV ? hp.Sx + (size_t)b * g.sx : hp.Sy + (size_t)b * g.sy;
+  const Cx<T>* src = (INV ? hp.Sy + (size_t)b * g.sy : hp.Sx + (size_t)b * g.sx) + (size_t)row0 * (INV ? g.Py : g.ny);
+  Cx<T>* dst = (INV ? hp.Sx + (size_t)b * g.sx : hp.Sy + (size_t)b * g.sy) + (size_t)row0 * (INV ? g.ny : g.Py);
   const int nin = INV ? g.Py : g.ny;
   const int nout = INV ? g.ny : g.Py;
-  for (int t = threadIdx.x; t < ncol * g.Py; t += blockDim.x) {
-    const int col = t / g.Py, y = t - col * g.Py;
-    Cx<T> v = {T(0), T(0)};
-    if (y < nin) v = src[(size_t)(row0 + col) * nin + y];
-    lds[col * cs + pidx(y)] = v;
-  }
-  __syncthreads();
-  fft_columns<T, INV>(lds, hp.py, cs, ncol, hp.tu.tpc_y);
-  for (int t = threadIdx.x; t < ncol * nout; t += blockDim.x) {
-    const int col = t / nout, y = t - col * nout;
-    dst[(size_t)(row0 + col) * nout + y] = lds[col * cs + pidx(y)];
-  }
+  auto ld = [&](int c, int e) -> Cx<T> {
+    return e < nin ? src[(size_t)c * nin + e] : Cx<T>{T(0), T(0)};
+  };
+  auto st = [&](int c, int e, Cx<T> v) {
+    if (e < nout) dst[(size_t)c * nout + e] = v;
+  };
+  fft_columns_io<T, INV, true, true>(lds, hp.fp[1], cs, ncol, hp.tu.tpc_y, ld, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,16 +221,30 @@ __global__ void __launch_bounds__(512) k_z3d(HotPlan<T> hp, const DevCtl* __rest
   Cx<T>* base = hp.Sy + (size_t)b * g.sy;  // [3][nz][Xp*Py]
   const size_t plane = (size_t)nq;
   // column col = c*QZ + j, element z
-  for (int t = threadIdx.x; t < 3 * g.Pz * QZ; t += blockDim.x) {
-    const int j = t % QZ;
-    const int cz = t / QZ;
-    const int c = cz / g.Pz, z = cz - c * g.Pz;
-    Cx<T> v = {T(0), T(0)};
-    if (z < g.nz && j < nqt) v = base[((size_t)c * g.nz + z) * plane + q0 + j];
-    lds[(c * QZ + j) * cs + pidx(z)] = v;
+  for (int t0 = threadIdx.x; t0 < 3 * g.Pz * QZ; t0 += kUnroll * blockDim.x) {
+    Cx<T> v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int t = t0 + u * blockDim.x;
+      const int j = t % QZ;
+      const int cz = t / QZ;
+      const int c = cz / g.Pz, z = cz - c * g.Pz;
+      v[u] = {T(0), T(0)};
+      if (t < 3 * g.Pz * QZ && z < g.nz && j < nqt) v[u] = base[((size_t)c * g.nz + z) * plane + q0 + j];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int t = t0 + u * blockDim.x;
+      if (t < 3 * g.Pz * QZ) {
+        const int j = t % QZ;
+        const int cz = t / QZ;
+        const int c = cz / g.Pz, z = cz - c * g.Pz;
+        lds[(c * QZ + j) * cs + pidx(z)] = v[u];
+      }
+    }
   }
   __syncthreads();
-  fft_columns<T, false>(lds, hp.pz, cs, 3 * QZ, hp.tu.tpc_z);
+  fft_columns<T, false>(lds, hp.fp[2], cs, 3 * QZ, hp.tu.tpc_z);
   const T s = T(hp.prm[b].demag_scale);
   for (int t = threadIdx.x; t < QZ * g.Pz; t += blockDim.x) {
     const int j = t % QZ, kz = t / QZ;
@@ -253,12 +255,99 @@ __global__ void __launch_bounds__(512) k_z3d(HotPlan<T> hp, const DevCtl* __rest
                  lds[(1 * QZ + j) * cs + pidx(kz)], lds[(2 * QZ + j) * cs + pidx(kz)]);
   }
   __syncthreads();
-  fft_columns<T, true>(lds, hp.pz, cs, 3 * QZ, hp.tu.tpc_z);
+  fft_columns<T, true>(lds, hp.fp[2], cs, 3 * QZ, hp.tu.tpc_z);
   for (int t = threadIdx.x; t < 3 * g.nz * QZ; t += blockDim.x) {
     const int j = t % QZ;
     const int cz = t / QZ;
     const int c = cz / g.nz, z = cz - c * g.nz;
     if (j < nqt) base[((size_t)c * g.nz + z) * plane + q0 + j] = lds[(c * QZ + j) * cs + pidx(z)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3-D z pass with the transform in registers: one thread owns the Pz-point
+// columns of the 3 components at one (kx, ky); no LDS, no barriers.
+// ---------------------------------------------------------------------------
+template <typename T, int PZ>
+__global__ void __launch_bounds__(256) k_z3d_reg(HotPlan<T> hp, const DevCtl* __restrict__ ctl) {
+  const Geo& g = hp.g;
+  const int b = blockIdx.y;
+  if (ctl && ctl[b].done) return;
+  const long long nq = (long long)g.Xp * g.Py;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  Cx<T>* base = hp.Sy + (size_t)b * g.sy + q;
+  const size_t plane = (size_t)nq;
+  Cx<T> v[3][PZ];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < PZ; ++z) {
+      v[c][z] = {T(0), T(0)};
+      if (z < g.nz) v[c][z] = base[((size_t)c * g.nz + z) * plane];
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) RegFft<T, PZ, 1, false>::run(v[c], hp.twz);
+  const int kx = (int)(q / g.Py), ky = (int)(q - (long long)kx * g.Py);
+  const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
+  const T sy = ky > g.Py - ky ? T(-1) : T(1);
+  const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
+  const T s = T(hp.prm[b].demag_scale);
+#pragma unroll
+  for (int kz = 0; kz < PZ; ++kz) {
+    constexpr int half = PZ / 2;
+    const int kzf = kz <= PZ - kz ? kz : PZ - kz;
+    const T sz = kz > PZ - kz ? T(-1) : T(1);
+    (void)half;
+    const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
+    const T kxx = hp.kt[off] * s;
+    const T kyy = hp.kt[cstride + off] * s;
+    const T kzz = hp.kt[2 * cstride + off] * s;
+    const T kxy = hp.kt[3 * cstride + off] * (s * sy);
+    const T kxz = hp.kt[4 * cstride + off] * (s * sz);
+    const T kyz = hp.kt[5 * cstride + off] * (s * sy * sz);
+    const Cx<T> a = v[0][kz], bb = v[1][kz], cc = v[2][kz];
+    v[0][kz] = {kxx * a.x + kxy * bb.x + kxz * cc.x, kxx * a.y + kxy * bb.y + kxz * cc.y};
+    v[1][kz] = {kxy * a.x + kyy * bb.x + kyz * cc.x, kxy * a.y + kyy * bb.y + kyz * cc.y};
+    v[2][kz] = {kxz * a.x + kyz * bb.x + kzz * cc.x, kxz * a.y + kyz * bb.y + kzz * cc.y};
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) RegFft<T, PZ, 1, true>::run(v[c], hp.twz);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < PZ; ++z)
+      if (z < g.nz) base[((size_t)c * g.nz + z) * plane] = v[c][z];
+}
+
+template <typename T, int PZ>
+static bool z_reg(const HotPlan<T>& hp, dim3 grid, const DevCtl* ctl, hipStream_t s) {
+  if constexpr (sizeof(T) == 8 && PZ > 16) {
+    return false;  // FP64 columns beyond 16 points do not fit in registers
+  } else {
+    k_z3d_reg<T, PZ><<<grid, 256, 0, s>>>(hp, ctl);
+    return true;
+  }
+}
+
+template <typename T>
+static bool launch_z_reg(const HotPlan<T>& hp, int batch, const DevCtl* ctl, hipStream_t s) {
+  const long long nq = (long long)hp.g.Xp * hp.g.Py;
+  const dim3 grid((unsigned)((nq + 255) / 256), (unsigned)batch);
+  switch (hp.g.Pz) {
+    case 2: return z_reg<T, 2>(hp, grid, ctl, s);
+    case 3: return z_reg<T, 3>(hp, grid, ctl, s);
+    case 4: return z_reg<T, 4>(hp, grid, ctl, s);
+    case 6: return z_reg<T, 6>(hp, grid, ctl, s);
+    case 8: return z_reg<T, 8>(hp, grid, ctl, s);
+    case 9: return z_reg<T, 9>(hp, grid, ctl, s);
+    case 12: return z_reg<T, 12>(hp, grid, ctl, s);
+    case 16: return z_reg<T, 16>(hp, grid, ctl, s);
+    case 18: return z_reg<T, 18>(hp, grid, ctl, s);
+    case 24: return z_reg<T, 24>(hp, grid, ctl, s);
+    case 27: return z_reg<T, 27>(hp, grid, ctl, s);
+    case 32: return z_reg<T, 32>(hp, grid, ctl, s);
+    default: return false;
   }
 }
 
@@ -353,7 +442,8 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
   const Geo& g = hp.g;
   const int TY = hp.tu.ty_x;
   const int tiles = (g.ny + TY - 1) / TY;
-  long long bid = blockIdx.x;
+  const long long bid0 = xcd_tile(blockIdx.x, gridDim.x);
+  long long bid = bid0;
   const int tile = bid % tiles; bid /= tiles;
   const int z = bid % g.nz;
   const int b = bid / g.nz;
@@ -368,12 +458,24 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
     const int cs = col_stride(g.Lx);
     for (int c = 0; c < 3; ++c) {
       const Cx<T>* src = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny;
-      for (int t = threadIdx.x; t < TY * g.Xp; t += blockDim.x) {
-        const int k = t / TY, r = t - k * TY;
-        const int y = y0 + r;
-        Cx<T> v = {T(0), T(0)};
-        if (y < g.ny) v = src[(size_t)k * g.ny + y];
-        lds[r * cs + pidx(k)] = v;
+      for (int t0 = threadIdx.x; t0 < TY * g.Xp; t0 += kUnroll * blockDim.x) {
+        Cx<T> v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int t = t0 + u * blockDim.x;
+          const int k = t / TY, r = t - k * TY;
+          const int y = y0 + r;
+          v[u] = {T(0), T(0)};
+          if (t < TY * g.Xp && y < g.ny) v[u] = src[(size_t)k * g.ny + y];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int t = t0 + u * blockDim.x;
+          if (t < TY * g.Xp) {
+            const int k = t / TY, r = t - k * TY;
+            lds[r * cs + pidx(k)] = v[u];
+          }
+        }
       }
       __syncthreads();
       // Z2[k] = (X[k] + conj X[Lx-k]) + i (X[k] - conj X[Lx-k]) conj(W^k), k in [0, Lx)
@@ -399,10 +501,10 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
         }
       }
       __syncthreads();
-      fft_columns<T, true>(lds, hp.px, cs, TY, hp.tu.tpc_x);
+      fft_columns<T, true>(lds, hp.fp[0], cs, TY, hp.tu.tpc_x);
 #pragma unroll
       for (int k = 0; k < kCPT; ++k) {
-        const int e = threadIdx.x + k * kNTI;
+        const int e = threadIdx.x + k * blockDim.x;
         if (e < ncell) {
           const int r = e / g.nx, x = e - r * g.nx;
           const Cx<T> v = lds[r * cs + pidx(x >> 1)];
@@ -429,7 +531,7 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
   }
 #pragma unroll
   for (int k = 0; k < kCPT; ++k) {
-    const int e = threadIdx.x + k * kNTI;
+    const int e = threadIdx.x + k * blockDim.x;
     if (e >= ncell) continue;
     const int r = e / g.nx, x = e - r * g.nx;
     const int y = y0 + r;
@@ -505,7 +607,7 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
       double v = 0;
       for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
       const int bpi = tiles * g.nz;
-      const int lb = (int)(blockIdx.x % bpi);
+      const int lb = (int)(bid0 % bpi);
       epi.partial[((size_t)b * bpi + lb) * 5 + threadIdx.x] = v;
     }
   }
@@ -566,17 +668,22 @@ __global__ void k_controller(DevCtl* ctl, int batch, const double* __restrict__ 
   C.last_err = err;
   C.n_attempt += 1;
   bool accept;
-  if (!(err <= DBL_MAX)) {  // NaN or Inf
-    C.status = MM_E_NONFINITE;
-    C.done = 1;
-    C.pending_finish = 0;
-    C.last_accepted = 0;
-    return;
-  }
-  if (C.replay_n > 0) {
-    accept = true;
+  const bool finite_err = err <= DBL_MAX;  // false for NaN and Inf
+  if (!finite_err) {
+    // overflowed stages or NaN in m: reject with the smallest factor; give up
+    // after ten in a row
+    C.nonfinite += 1;
+    if (C.nonfinite >= 10 || C.replay_n > 0) {
+      C.status = MM_E_NONFINITE;
+      C.done = 1;
+      C.pending_finish = 0;
+      C.last_accepted = 0;
+      return;
+    }
+    accept = false;
   } else {
-    accept = err <= 1.0;
+    C.nonfinite = 0;
+    accept = C.replay_n > 0 ? true : err <= 1.0;
   }
   if (accept) {
     C.t = (h == C.t_end - C.t) ? C.t_end : C.t + h;
@@ -588,7 +695,7 @@ __global__ void k_controller(DevCtl* ctl, int batch, const double* __restrict__ 
   } else {
     C.n_reject += 1;
     C.after_reject = 1;
-    C.h = h * fmax(0.2, 0.9 * pow(err, -0.2));
+    C.h = finite_err ? h * fmax(0.2, 0.9 * pow(err, -0.2)) : h * 0.2;
   }
   C.pending_finish = accept ? 1 : 0;
   C.last_accepted = accept ? 1 : 0;
@@ -749,7 +856,7 @@ hipError_t launch_eval(const HotPlan<T>& hp, int batch, const T* m, const Epi<T>
     const int ftiles = (g.ny + tu.ty_f - 1) / tu.ty_f;
     const size_t ldsf = (size_t)tu.ty_f * col_stride(g.Lx) * csz;
     mark();
-    k_fwd_x<T><<<dim3((unsigned)(batch * 3 * g.nz * ftiles)), kNT, ldsf, s>>>(hp, m, epi.ctl);
+    k_fwd_x<T><<<dim3((unsigned)(batch * 3 * g.nz * ftiles)), tu.nt_f, ldsf, s>>>(hp, m, epi.ctl);
     if (g.nz == 1) {
       const int tiles = (g.Xp + tu.cb_y2 - 1) / tu.cb_y2;
       const size_t lds = (size_t)3 * tu.cb_y2 * col_stride(g.Py) * csz;
@@ -765,15 +872,16 @@ hipError_t launch_eval(const HotPlan<T>& hp, int batch, const T* m, const Epi<T>
       const long long ztiles = (nq + tu.qz - 1) / tu.qz;
       const size_t ldsz = (size_t)3 * tu.qz * col_stride(g.Pz) * csz;
       mark();
-      k_z3d<T><<<dim3((unsigned)(batch * ztiles)), 3 * tu.qz * tu.tpc_z, ldsz, s>>>(hp, epi.ctl);
+      if (!launch_z_reg<T>(hp, batch, epi.ctl, s))
+        k_z3d<T><<<dim3((unsigned)(batch * ztiles)), 3 * tu.qz * tu.tpc_z, ldsz, s>>>(hp, epi.ctl);
       mark();
       k_y3d<T, true><<<dim3((unsigned)(batch * ytiles)), tu.cb_y * tu.tpc_y, ldsy, s>>>(hp, epi.ctl);
     }
     mark();
-    k_inv_x<T, true><<<dim3((unsigned)(batch * g.nz * xtiles)), kNTI, lds_x(g, tu, csz), s>>>(hp, m, epi);
+    k_inv_x<T, true><<<dim3((unsigned)(batch * g.nz * xtiles)), tu.nt_i, lds_x(g, tu, csz), s>>>(hp, m, epi);
   } else {
     mark();
-    k_inv_x<T, false><<<dim3((unsigned)(batch * g.nz * xtiles)), kNTI, 0, s>>>(hp, m, epi);
+    k_inv_x<T, false><<<dim3((unsigned)(batch * g.nz * xtiles)), tu.nt_i, 0, s>>>(hp, m, epi);
   }
   mark();
   return hipGetLastError();

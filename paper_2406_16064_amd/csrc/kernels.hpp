@@ -42,10 +42,12 @@ template <typename T> struct Epi {
 };
 
 struct Tuning {
-  int ty_f;     // rows per workgroup of the forward x pass (256 threads)
-  int tpc_f;
-  int ty_x;     // rows per workgroup of the inverse x pass + epilogue (512 threads)
+  int ty_f;     // rows per workgroup of the forward x pass
+  int tpc_f;    // threads per row of its transform
+  int nt_f;     // threads per workgroup
+  int ty_x;     // rows per workgroup of the inverse x pass + epilogue
   int tpc_x;
+  int nt_i;
   int cb_y;     // columns per workgroup of the 3-D y passes
   int tpc_y;
   int cb_y2;    // kx columns per workgroup of the fused 2-D y pass (x3 components)
@@ -57,7 +59,8 @@ struct Tuning {
 template <typename T> struct HotPlan {
   Geo g;
   Tuning tu;
-  FftPlan<T> px, py, pz;
+  const FftPlan<T>* fp;    // device array: x (length Px/2), y (Py), z (Pz) radix plans
+  const Cx<T>* twz;        // z twiddles (register z pass)
   const Cx<T>* post;       // exp(-2 pi i k / Px), k = 0..Lx
   const T* kt;             // tensor spectrum [ncomp][Kz][Xp][Ky]
   int ncomp;               // 4 (nz = 1) or 6

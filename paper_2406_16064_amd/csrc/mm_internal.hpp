@@ -60,14 +60,7 @@ struct DevCtl {
   int done;
   int status;             // mm_status of this instance
   int last_accepted;
-  int pad;
-};
-
-// Dormand-Prince 5(4) tableau (Dormand & Prince 1980), stored in double.
-struct DPTab {
-  double a[7][7];
-  double b[7];
-  double e[7];  // b - bhat
+  int nonfinite;          // consecutive attempts with a non-finite error norm
 };
 
 }  // namespace mmx

@@ -201,6 +201,7 @@ struct mm_plan {
   void* twx = nullptr;
   void* twy = nullptr;
   void* twz = nullptr;
+  void* fplans = nullptr;  // device FftPlan[3] (x, y, z)
   DevParams* prm = nullptr;
   DevCtl* ctl = nullptr;
   double* partial = nullptr;
@@ -286,43 +287,69 @@ mm_status upload_params(mm_plan* p, const mm_params* q, int n, hipStream_t s) {
   return MM_OK;
 }
 
-// Launch shapes: workgroup LDS <= 64 KiB, per-thread butterfly budget kept.
+// Launch shapes.  Each workgroup keeps its LDS within 80 KiB (two per CU), the
+// per-thread butterfly budget of the transforms is respected, and tiles shrink
+// until a pass has about 4 workgroups per CU (small meshes) or reach their
+// coalescing-friendly maximum (large meshes).
+int pow2ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
 mm_status choose_tuning(mm_plan* p) {
   const Geo& g = p->g;
   Tuning& t = p->tu;
   const size_t csz = p->csz;
-  const size_t budget = 65536;
+  const size_t budget = 80 * 1024;
+  const long long want = 4 * 256;  // workgroups per pass worth aiming for
   auto tpc_for = [&](int L) {
     if (p->prec == MM_F32) return min_tpc(make_fft<float>(L, nullptr));
     return min_tpc(make_fft<double>(L, nullptr));
   };
-  // x passes: rows per workgroup (forward: 256 threads; inverse + epilogue:
-  // 512 threads owning at most 8 cells each)
+  const int tpx = tpc_for(g.Lx);
+  const size_t rowb = (size_t)col_stride(g.Lx) * csz;
+  // forward x: rows of one component
   {
-    const int tpc = tpc_for(g.Lx);
-    const int lds_rows = (int)(budget / (col_stride(g.Lx) * csz));
-    int tf = std::min(std::min(16, lds_rows), std::min(256 / tpc, g.ny));
-    int ti = std::min(std::min(16, lds_rows), std::min(512 / tpc, g.ny));
-    ti = std::min(ti, 8 * 512 / g.nx);
-    if (tf < 1 || ti < 1) return fail(MM_E_ARG, "mesh too long along x for the x-pass tile");
-    t.ty_f = tf;
-    t.tpc_f = 256 / tf;
-    t.ty_x = ti;
-    t.tpc_x = 512 / ti;
+    const long long rows = 3LL * g.nz * g.ny;
+    int ty = 16;
+    while (ty > 1 && ((size_t)ty * rowb > budget || ty * tpx > 512 || rows / ty < want)) ty /= 2;
+    ty = std::min(ty, g.ny);
+    if ((size_t)ty * rowb > 160 * 1024 || ty * tpx > 512) return fail(MM_E_ARG, "mesh too long along x");
+    t.ty_f = ty;
+    t.nt_f = std::min(512, std::max(64, pow2ceil(std::max(ty * tpx, ty * g.Lx / 4))));
+    t.tpc_f = t.nt_f / ty;
+  }
+  // inverse x + epilogue: rows of all 3 components, at most 8 cells per thread
+  {
+    const long long rows = (long long)g.nz * g.ny;
+    int ty = 16;
+    while (ty > 1 && ((size_t)ty * rowb > budget || ty * tpx > 512 || ty * g.nx > 8 * 512 || rows / ty < want))
+      ty /= 2;
+    ty = std::min(ty, g.ny);
+    if ((size_t)ty * rowb > 160 * 1024 || ty * tpx > 512 || ty * g.nx > 8 * 512)
+      return fail(MM_E_ARG, "mesh too long along x");
+    t.ty_x = ty;
+    t.nt_i = std::min(512, std::max(64, pow2ceil(std::max(ty * tpx, ty * g.nx))));
+    t.tpc_x = t.nt_i / ty;
   }
   if (g.nz == 1) {
-    const int tpc = std::max(tpc_for(g.Py), std::min(2 * tpc_for(g.Py), 32));
-    int cb = (int)(budget / (3 * col_stride(g.Py) * csz));
-    cb = std::min(cb, 512 / (3 * tpc));
-    cb = std::min(cb, g.Xp);
-    if (cb < 1) return fail(MM_E_ARG, "mesh too long along y for the fused y pass");
+    const int tmin = tpc_for(g.Py);
+    const int tpc = std::max(tmin, std::min(2 * tmin, 64));
+    const size_t colb = 3 * (size_t)col_stride(g.Py) * csz;
+    int cb = 8;
+    while (cb > 1 && (cb * colb > budget || 3 * cb * tpc > 512 || g.Xp / cb < want)) cb /= 2;
+    if (cb * colb > 160 * 1024 || 3 * cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y2 = cb;
     t.tpc_y2 = tpc;
   } else {
-    const int tpc = std::max(tpc_for(g.Py), std::min(2 * tpc_for(g.Py), 64));
-    int cb = (int)(budget / (col_stride(g.Py) * csz));
-    cb = std::min(cb, 512 / tpc);
-    if (cb < 1) return fail(MM_E_ARG, "mesh too long along y for the y pass");
+    const int tmin = tpc_for(g.Py);
+    const int tpc = std::max(tmin, std::min(2 * tmin, 64));
+    const size_t colb = (size_t)col_stride(g.Py) * csz;
+    const long long rows = 3LL * g.nz * g.Xp;
+    int cb = 16;
+    while (cb > 1 && (cb * colb > budget || cb * tpc > 512 || rows / cb < want)) --cb;
+    if (cb * colb > 160 * 1024 || cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y = cb;
     t.tpc_y = tpc;
     const int tz = tpc_for(g.Pz);
@@ -341,9 +368,8 @@ HotPlan<T> hot(const mm_plan* p) {
   HotPlan<T> h{};
   h.g = p->g;
   h.tu = p->tu;
-  h.px = make_fft<T>(p->g.Lx, (const Cx<T>*)p->twx);
-  h.py = make_fft<T>(p->g.Py, (const Cx<T>*)p->twy);
-  h.pz = make_fft<T>(p->g.Pz, (const Cx<T>*)p->twz);
+  h.fp = (const FftPlan<T>*)p->fplans;
+  h.twz = (const Cx<T>*)p->twz;
   h.post = (const Cx<T>*)p->post;
   h.kt = (const T*)p->kt;
   h.ncomp = p->ncomp;
@@ -369,6 +395,10 @@ mm_status upload_tables(mm_plan* p) {
     post[k] = Cx<T>{(T)std::cos(a), (T)std::sin(a)};
   }
   MMCHK(up(&p->post, post));
+  const FftPlan<T> fp[3] = {make_fft<T>(p->g.Lx, (const Cx<T>*)p->twx), make_fft<T>(p->g.Py, (const Cx<T>*)p->twy),
+                            make_fft<T>(p->g.Pz, (const Cx<T>*)p->twz)};
+  HIPCHK(hipMalloc(&p->fplans, sizeof(fp)));
+  HIPCHK(hipMemcpy(p->fplans, fp, sizeof(fp), hipMemcpyHostToDevice));
   return MM_OK;
 }
 
@@ -432,7 +462,7 @@ mm_status build_spectrum(mm_plan* p, hipStream_t s) {
 void free_plan(mm_plan* p) {
   if (!p) return;
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-  void* bufs[] = {p->Sx, p->Sy, p->kt, p->post, p->twx, p->twy, p->twz, p->prm, p->ctl, p->partial,
+  void* bufs[] = {p->Sx, p->Sy, p->kt, p->post, p->twx, p->twy, p->twz, p->fplans, p->prm, p->ctl, p->partial,
                   p->e5, p->replay, p->stage, p->nebH, p->nebB, p->nebS, p->nebP};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
