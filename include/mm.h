@@ -153,6 +153,35 @@ mm_status mm_neb_run(mm_plan* plan, const mm_params* params, void* images, int32
                      double k_spring, double h, int64_t n_iter, double* E_out,
                      void* hip_stream);
 
+/* Batched integration of instances of different meshes (parameter sweeps).
+ * A batch is created for up to 16 distinct meshes; each run takes any number
+ * of instances, each naming its mesh, and advances all of them together:
+ * every kernel pass is one launch over all meshes' instances, each instance
+ * has its own parameters, adaptive step size, controller and t_end, and the
+ * step sequence is a captured HIP graph (finished instances idle).  This is
+ * the paper's parameter sweep (section "Design", sim_with with _s suffixes,
+ * run there one instance after the other) batched on one GPU. */
+typedef struct mm_batch mm_batch;
+typedef struct {
+  int32_t mesh_id;     /* index into the meshes of mm_batch_create            */
+  mm_params p;         /* parameters of this instance                        */
+  void* m;             /* device array [3][nz][ny][nx] (plan precision), in/out */
+  mm_rk45_state st;    /* in/out, as for mm_rk45_run                         */
+  double t_end;        /* integrate to this time                             */
+  int32_t status;      /* out: mm_status of this instance                    */
+} mm_instance;
+
+/* Builds the geometry (padded grid, tables, Newell spectrum) of every mesh.
+ * Synchronises. */
+mm_status mm_batch_create(mm_batch** out, const mm_mesh* meshes, int32_t n_meshes,
+                          mm_precision prec, uint32_t terms, void* hip_stream);
+/* Runs every instance to its t_end (at most max_steps attempts each).
+ * Synchronises; returns the first non-OK instance status (details per
+ * instance in inst[i].status). */
+mm_status mm_batch_run(mm_batch* batch, mm_instance* inst, int32_t n_inst, int64_t max_steps,
+                       void* hip_stream);
+mm_status mm_batch_destroy(mm_batch* batch);
+
 /* Measurement aid: runs `reps` dm/dt evaluations of `batch` instances (output
  * written to `work`, same layout as m) with a HIP event before every kernel
  * pass and after the last one, and returns in us_out[0..*n_pass) the mean

@@ -17,13 +17,19 @@
 //            so the y transform reads contiguous rows)
 //   y pass   3-D: Sx -> Sy[3][nz][Xp][Py];  2-D: forward y, tensor product,
 //            inverse y fused, in place in Sx
-//   z pass   3-D: forward z (zero padded in LDS), tensor product, inverse z,
-//            in place in Sy (only the nz physical planes are stored)
+//   z pass   3-D: forward z (zero padded in registers or LDS), tensor product,
+//            inverse z, in place in Sy (only the nz physical planes are stored)
 //   y inv    3-D: Sy -> Sx (only the ny physical rows)
 //   x inv    complex-to-real along x for the 3 components of TY rows, then the
 //            local fields, H_eff, LL and the integrator epilogue per cell.
+//
+// Every launch covers a set of groups (instances sharing a mesh): workgroup
+// ranges per group come with the launch, each group's geometry, tables and
+// buffers from device memory, so instances of different meshes advance in one
+// launch per pass.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -32,8 +38,7 @@
 
 namespace mmx {
 
-constexpr int kNT = 256;   // threads of the forward x pass and pointwise kernels
-constexpr int kNTI = 512;  // threads of the fused x-inverse epilogue
+constexpr int kNT = 256;   // threads of the pointwise kernels and the register z pass
 constexpr int kCPT = 8;    // cells owned by one thread in the fused x-inverse epilogue
 constexpr int kUnroll = 8; // global loads kept in flight per thread when filling LDS
 
@@ -50,40 +55,58 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Group of this workgroup and its index inside the group (XCD-ordered).
+template <typename T>
+__device__ __forceinline__ int group_of(const Launch<T>& L, long long& lb) {
+  int gi = 0;
+  while (gi + 1 < L.ngroups && (long long)blockIdx.x >= L.off[gi + 1]) ++gi;
+  const long long nb = L.off[gi + 1] - L.off[gi];
+  lb = xcd_tile((long long)blockIdx.x - L.off[gi], nb);
+  return gi;
+}
+
 // ---------------------------------------------------------------------------
 // x forward: real-to-complex of TY rows (fixed b, c, z), transposed store.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline long long fwd_blocks(const Geo& g, const Tuning& tu, int batch) {
+  return (long long)batch * 3 * g.nz * ((g.ny + tu.ty_f - 1) / tu.ty_f);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(512) k_fwd_x(HotPlan<T> hp, const T* __restrict__ m,
-                                               const DevCtl* __restrict__ ctl) {
+__global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  long long bid;
+  const int gi = group_of(L, bid);
+  const HotPlan<T>& hp = L.hps[gi];
+  const Epi<T>& ep = L.epis[gi];
   const Geo& g = hp.g;
+  if (bid >= fwd_blocks(g, hp.tu, hp.batch)) return;
   const int TY = hp.tu.ty_f;
   const int tiles = (g.ny + TY - 1) / TY;
-  long long bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tile = bid % tiles; bid /= tiles;
   const int z = bid % g.nz; bid /= g.nz;
   const int c = bid % 3;
-  const int b = bid / 3;
-  if (ctl && ctl[b].done) return;
+  const int b = (int)(bid / 3);
+  if (ep.ctl && ep.ctl[b].done) return;
   const int y0 = tile * TY;
   const int cs = col_stride(g.Lx);
-  const T* src = m + ((size_t)b * 3 + c) * g.N + (size_t)z * g.ny * g.nx;
+  const T* src = ep.in + ((size_t)b * 3 + c) * g.N + (size_t)z * g.ny * g.nx;
+  const int ny = g.ny, nx = g.nx;
   // element n of row r packs x[2n] + i x[2n+1] (zero beyond nx and past the last row)
-  auto ld = [&](int r, int n) -> Cx<T> {
+  auto ld = [=](int r, int n) -> Cx<T> {
     Cx<T> v = {T(0), T(0)};
     const int y = y0 + r;
-    if (y < g.ny) {
-      const T* row = src + (size_t)y * g.nx;
+    if (y < ny) {
+      const T* row = src + (size_t)y * nx;
       const int i0 = 2 * n;
-      if (i0 < g.nx) v.x = row[i0];
-      if (i0 + 1 < g.nx) v.y = row[i0 + 1];
+      if (i0 < nx) v.x = row[i0];
+      if (i0 + 1 < nx) v.y = row[i0 + 1];
     }
     return v;
   };
   auto st = [](int, int, Cx<T>) {};
-  fft_columns_io<T, false, true, false>(lds, hp.fp[0], cs, TY, hp.tu.tpc_f, ld, st);
+  fft_columns_io<T, false, true, false>(lds, hp.fp[0], cs, TY, (int)blockDim.x / TY, ld, st);
   Cx<T>* dst = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny;
   const int tot2 = TY * g.Xp;
   for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
@@ -128,19 +151,25 @@ __device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int k
 }
 
 // ---------------------------------------------------------------------------
-// 2-D (nz = 1): forward y, tensor product, inverse y for cb_y2 kx values and
-// the 3 components, in place in Sx.
+// y pass.  2-D groups (nz = 1): forward y, tensor product, inverse y for cb_y2
+// kx values and the 3 components, in place in Sx.  3-D groups: rows of fixed
+// (b, c, z, kx); forward Sx(ny) -> Sy(Py) or inverse Sy(Py) -> Sx(ny).
 // ---------------------------------------------------------------------------
+__host__ __device__ inline long long y2d_blocks(const Geo& g, const Tuning& tu, int batch) {
+  return (long long)batch * ((g.Xp + tu.cb_y2 - 1) / tu.cb_y2);
+}
+__host__ __device__ inline long long y3d_blocks(const Geo& g, const Tuning& tu, int batch) {
+  return (long long)batch * ((3LL * g.nz * g.Xp + tu.cb_y - 1) / tu.cb_y);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(512) k_y_fused2d(HotPlan<T> hp, const DevCtl* __restrict__ ctl) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+__device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y2;
   const int tiles = (g.Xp + CB - 1) / CB;
-  const int tile = blockIdx.x % tiles;
-  const int b = blockIdx.x / tiles;
-  if (ctl && ctl[b].done) return;
+  const int tile = (int)(bid % tiles);
+  const int b = (int)(bid / tiles);
+  if (ep.ctl && ep.ctl[b].done) return;
   const int kx0 = tile * CB;
   const int ncol = 3 * CB;
   const int cs = col_stride(g.Py);
@@ -156,7 +185,8 @@ __global__ void __launch_bounds__(512) k_y_fused2d(HotPlan<T> hp, const DevCtl* 
     const int c = col / CB, j = col - c * CB;
     if (y < ny && kx0 + j < Xp) base[((size_t)c * Xp + kx0 + j) * ny + y] = v;
   };
-  fft_columns_io<T, false, true, false>(lds, hp.fp[1], cs, ncol, hp.tu.tpc_y2, ld, st);
+  const int tpc = blockDim.x / ncol;
+  fft_columns_io<T, false, true, false>(lds, hp.fp[1], cs, ncol, tpc, ld, st);
   const T s = T(hp.prm[b].demag_scale);
   for (int t = threadIdx.x; t < CB * g.Py; t += blockDim.x) {
     const int j = t / g.Py, ky = t - j * g.Py;
@@ -166,55 +196,86 @@ __global__ void __launch_bounds__(512) k_y_fused2d(HotPlan<T> hp, const DevCtl* 
                  lds[(2 * CB + j) * cs + pidx(ky)]);
   }
   __syncthreads();
-  fft_columns_io<T, true, false, true>(lds, hp.fp[1], cs, ncol, hp.tu.tpc_y2, ld, st);
+  fft_columns_io<T, true, false, true>(lds, hp.fp[1], cs, ncol, tpc, ld, st);
 }
 
-// ---------------------------------------------------------------------------
-// 3-D y passes: rows of fixed (b, c, z, kx).  INV = false: Sx(ny) -> Sy(Py);
-// INV = true: Sy(Py) -> Sx(ny).
-// ---------------------------------------------------------------------------
 template <typename T, bool INV>
-__global__ void __launch_bounds__(512) k_y3d(HotPlan<T> hp, const DevCtl* __restrict__ ctl) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+__device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y;
   const long long rows_per_inst = 3LL * g.nz * g.Xp;
   const long long tiles = (rows_per_inst + CB - 1) / CB;
-  const long long tile = blockIdx.x % tiles;
-  const int b = blockIdx.x / tiles;
-  if (ctl && ctl[b].done) return;
+  const long long tile = bid % tiles;
+  const int b = (int)(bid / tiles);
+  if (ep.ctl && ep.ctl[b].done) return;
   const long long row0 = tile * CB;
   const int ncol = (int)((rows_per_inst - row0) < CB ? (rows_per_inst - row0) : CB);
   const int cs = col_stride(g.Py);
-  const Cx<T>* src = (INV ? hp.Sy + (size_t)b * g.sy : hp.Sx + (size_t)b * g.sx) + (size_t)row0 * (INV ? g.Py : g.ny);
-  Cx<T>* dst = (INV ? hp.Sx + (size_t)b * g.sx : hp.Sy + (size_t)b * g.sy) + (size_t)row0 * (INV ? g.ny : g.Py);
   const int nin = INV ? g.Py : g.ny;
   const int nout = INV ? g.ny : g.Py;
-  auto ld = [&](int c, int e) -> Cx<T> {
+  const Cx<T>* src = (INV ? hp.Sy + (size_t)b * g.sy : hp.Sx + (size_t)b * g.sx) + (size_t)row0 * nin;
+  Cx<T>* dst = (INV ? hp.Sx + (size_t)b * g.sx : hp.Sy + (size_t)b * g.sy) + (size_t)row0 * nout;
+  auto ld = [=](int c, int e) -> Cx<T> {
     return e < nin ? src[(size_t)c * nin + e] : Cx<T>{T(0), T(0)};
   };
-  auto st = [&](int c, int e, Cx<T> v) {
+  auto st = [=](int c, int e, Cx<T> v) {
     if (e < nout) dst[(size_t)c * nout + e] = v;
   };
-  fft_columns_io<T, INV, true, true>(lds, hp.fp[1], cs, ncol, hp.tu.tpc_y, ld, st);
+  fft_columns_io<T, INV, true, true>(lds, hp.fp[1], cs, ncol, (int)blockDim.x / CB, ld, st);
+}
+
+// Forward y pass of every group: fused 2-D or 3-D forward rows.
+template <typename T>
+__global__ void __launch_bounds__(512) k_ypass(Launch<T> L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  long long bid;
+  const int gi = group_of(L, bid);
+  const HotPlan<T>& hp = L.hps[gi];
+  if (hp.g.nz == 1) {
+    if (bid >= y2d_blocks(hp.g, hp.tu, hp.batch)) return;
+    y_fused2d(hp, L.epis[gi], bid, lds);
+  } else {
+    if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
+    y_rows3d<T, false>(hp, L.epis[gi], bid, lds);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_yinv(Launch<T> L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  long long bid;
+  const int gi = group_of(L, bid);
+  const HotPlan<T>& hp = L.hps[gi];
+  if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
+  y_rows3d<T, true>(hp, L.epis[gi], bid, lds);
 }
 
 // ---------------------------------------------------------------------------
-// 3-D z pass: forward z, tensor product, inverse z for qz consecutive (kx,ky)
-// points and the 3 components, in place in Sy (nz physical planes).
+// 3-D z pass (LDS version, any Pz): forward z, tensor product, inverse z for
+// qz consecutive (kx,ky) points and the 3 components, in place in Sy.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline long long zlds_blocks(const Geo& g, const Tuning& tu, int batch) {
+  return (long long)batch * (((long long)g.Xp * g.Py + tu.qz - 1) / tu.qz);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(512) k_z3d(HotPlan<T> hp, const DevCtl* __restrict__ ctl) {
+__global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  long long bid;
+  const int gi = group_of(L, bid);
+  const HotPlan<T>& hp = L.hps[gi];
+  const Epi<T>& ep = L.epis[gi];
   const Geo& g = hp.g;
+  if (bid >= zlds_blocks(g, hp.tu, hp.batch)) return;
   const int QZ = hp.tu.qz;
   const long long nq = (long long)g.Xp * g.Py;
   const long long tiles = (nq + QZ - 1) / QZ;
-  const long long tile = blockIdx.x % tiles;
-  const int b = blockIdx.x / tiles;
-  if (ctl && ctl[b].done) return;
+  const long long tile = bid % tiles;
+  const int b = (int)(bid / tiles);
+  if (ep.ctl && ep.ctl[b].done) return;
   const long long q0 = tile * QZ;
   const int nqt = (int)((nq - q0) < QZ ? (nq - q0) : QZ);
   const int cs = col_stride(g.Pz);
@@ -244,7 +305,8 @@ __global__ void __launch_bounds__(512) k_z3d(HotPlan<T> hp, const DevCtl* __rest
     }
   }
   __syncthreads();
-  fft_columns<T, false>(lds, hp.fp[2], cs, 3 * QZ, hp.tu.tpc_z);
+  const int tpc = blockDim.x / (3 * QZ);
+  fft_columns<T, false>(lds, hp.fp[2], cs, 3 * QZ, tpc);
   const T s = T(hp.prm[b].demag_scale);
   for (int t = threadIdx.x; t < QZ * g.Pz; t += blockDim.x) {
     const int j = t % QZ, kz = t / QZ;
@@ -255,7 +317,7 @@ __global__ void __launch_bounds__(512) k_z3d(HotPlan<T> hp, const DevCtl* __rest
                  lds[(1 * QZ + j) * cs + pidx(kz)], lds[(2 * QZ + j) * cs + pidx(kz)]);
   }
   __syncthreads();
-  fft_columns<T, true>(lds, hp.fp[2], cs, 3 * QZ, hp.tu.tpc_z);
+  fft_columns<T, true>(lds, hp.fp[2], cs, 3 * QZ, tpc);
   for (int t = threadIdx.x; t < 3 * g.nz * QZ; t += blockDim.x) {
     const int j = t % QZ;
     const int cz = t / QZ;
@@ -268,13 +330,23 @@ __global__ void __launch_bounds__(512) k_z3d(HotPlan<T> hp, const DevCtl* __rest
 // 3-D z pass with the transform in registers: one thread owns the Pz-point
 // columns of the 3 components at one (kx, ky); no LDS, no barriers.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline long long zreg_blocks(const Geo& g, int batch) {
+  return (long long)batch * (((long long)g.Xp * g.Py + kNT - 1) / kNT);
+}
+
 template <typename T, int PZ>
-__global__ void __launch_bounds__(256) k_z3d_reg(HotPlan<T> hp, const DevCtl* __restrict__ ctl) {
+__global__ void __launch_bounds__(kNT) k_z3d_reg(Launch<T> L) {
+  long long bid;
+  const int gi = group_of(L, bid);
+  const HotPlan<T>& hp = L.hps[gi];
+  const Epi<T>& ep = L.epis[gi];
   const Geo& g = hp.g;
-  const int b = blockIdx.y;
-  if (ctl && ctl[b].done) return;
+  if (bid >= zreg_blocks(g, hp.batch)) return;
   const long long nq = (long long)g.Xp * g.Py;
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long qb = (nq + kNT - 1) / kNT;
+  const int b = (int)(bid / qb);
+  if (ep.ctl && ep.ctl[b].done) return;
+  const long long q = (bid % qb) * kNT + threadIdx.x;
   if (q >= nq) return;
   Cx<T>* base = hp.Sy + (size_t)b * g.sy + q;
   const size_t plane = (size_t)nq;
@@ -295,10 +367,8 @@ __global__ void __launch_bounds__(256) k_z3d_reg(HotPlan<T> hp, const DevCtl* __
   const T s = T(hp.prm[b].demag_scale);
 #pragma unroll
   for (int kz = 0; kz < PZ; ++kz) {
-    constexpr int half = PZ / 2;
     const int kzf = kz <= PZ - kz ? kz : PZ - kz;
     const T sz = kz > PZ - kz ? T(-1) : T(1);
-    (void)half;
     const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
     const T kxx = hp.kt[off] * s;
     const T kyy = hp.kt[cstride + off] * s;
@@ -318,37 +388,6 @@ __global__ void __launch_bounds__(256) k_z3d_reg(HotPlan<T> hp, const DevCtl* __
 #pragma unroll
     for (int z = 0; z < PZ; ++z)
       if (z < g.nz) base[((size_t)c * g.nz + z) * plane] = v[c][z];
-}
-
-template <typename T, int PZ>
-static bool z_reg(const HotPlan<T>& hp, dim3 grid, const DevCtl* ctl, hipStream_t s) {
-  if constexpr (sizeof(T) == 8 && PZ > 16) {
-    return false;  // FP64 columns beyond 16 points do not fit in registers
-  } else {
-    k_z3d_reg<T, PZ><<<grid, 256, 0, s>>>(hp, ctl);
-    return true;
-  }
-}
-
-template <typename T>
-static bool launch_z_reg(const HotPlan<T>& hp, int batch, const DevCtl* ctl, hipStream_t s) {
-  const long long nq = (long long)hp.g.Xp * hp.g.Py;
-  const dim3 grid((unsigned)((nq + 255) / 256), (unsigned)batch);
-  switch (hp.g.Pz) {
-    case 2: return z_reg<T, 2>(hp, grid, ctl, s);
-    case 3: return z_reg<T, 3>(hp, grid, ctl, s);
-    case 4: return z_reg<T, 4>(hp, grid, ctl, s);
-    case 6: return z_reg<T, 6>(hp, grid, ctl, s);
-    case 8: return z_reg<T, 8>(hp, grid, ctl, s);
-    case 9: return z_reg<T, 9>(hp, grid, ctl, s);
-    case 12: return z_reg<T, 12>(hp, grid, ctl, s);
-    case 16: return z_reg<T, 16>(hp, grid, ctl, s);
-    case 18: return z_reg<T, 18>(hp, grid, ctl, s);
-    case 24: return z_reg<T, 24>(hp, grid, ctl, s);
-    case 27: return z_reg<T, 27>(hp, grid, ctl, s);
-    case 32: return z_reg<T, 32>(hp, grid, ctl, s);
-    default: return false;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -434,20 +473,34 @@ __device__ __forceinline__ V3<T> ll_rhs(V3<T> m, V3<T> H, T g1, T g2) {
 // TY rows of one z plane of one instance, 3 components.  DEMAG = false skips
 // the transform (H_d = 0) and uses no LDS for it.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline long long inv_blocks(const Geo& g, const Tuning& tu, int batch) {
+  return (long long)batch * g.nz * ((g.ny + tu.ty_x - 1) / tu.ty_x);
+}
+
+int eval_blocks_per_inst(const Geo& g, const Tuning& tu) {
+  return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz;
+}
+
 template <typename T, bool DEMAG>
-__global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restrict__ ms, Epi<T> epi) {
+__global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
-  __shared__ double red[5][kNTI / 64];
+  __shared__ double red[5][512 / 64];
+  long long bid0;
+  const int gi = group_of(L, bid0);
+  const HotPlan<T>& hp = L.hps[gi];
+  const Epi<T>& epi = L.epis[gi];
   const Geo& g = hp.g;
+  if (bid0 >= inv_blocks(g, hp.tu, hp.batch)) return;
   const int TY = hp.tu.ty_x;
   const int tiles = (g.ny + TY - 1) / TY;
-  const long long bid0 = xcd_tile(blockIdx.x, gridDim.x);
   long long bid = bid0;
   const int tile = bid % tiles; bid /= tiles;
   const int z = bid % g.nz;
-  const int b = bid / g.nz;
+  const int b = (int)(bid / g.nz);
   if (epi.ctl && epi.ctl[b].done) return;
+  const DevParams P = hp.prm[b];
+  const bool add_hd = DEMAG && (P.terms & MM_DEMAG);
   const int y0 = tile * TY;
   const int ncell = TY * g.nx;
   T Hd[3][kCPT];
@@ -456,6 +509,7 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
 
   if (DEMAG) {
     const int cs = col_stride(g.Lx);
+    const int tpc = blockDim.x / TY;
     for (int c = 0; c < 3; ++c) {
       const Cx<T>* src = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny;
       for (int t0 = threadIdx.x; t0 < TY * g.Xp; t0 += kUnroll * blockDim.x) {
@@ -485,23 +539,19 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
         Cx<T>* col = lds + r * cs;
         const int k2 = g.Lx - k;
         const Cx<T> Xa = col[pidx(k)], Xb = col[pidx(k2)];
-        // value at k
         {
           const Cx<T> s = cadd(Xa, cconj(Xb));
           const Cx<T> d = cmul(csub(Xa, cconj(Xb)), cconj(hp.post[k]));
-          const Cx<T> v = {s.x - d.y, s.y + d.x};
-          if (k < g.Lx) col[pidx(k)] = v;
+          col[pidx(k)] = Cx<T>{s.x - d.y, s.y + d.x};
         }
-        // value at Lx - k (for 0 < k < Lx - k)
         if (k > 0 && k < k2) {
           const Cx<T> s = cadd(Xb, cconj(Xa));
           const Cx<T> d = cmul(csub(Xb, cconj(Xa)), cconj(hp.post[k2]));
-          const Cx<T> v = {s.x - d.y, s.y + d.x};
-          col[pidx(k2)] = v;
+          col[pidx(k2)] = Cx<T>{s.x - d.y, s.y + d.x};
         }
       }
       __syncthreads();
-      fft_columns<T, true>(lds, hp.fp[0], cs, TY, hp.tu.tpc_x);
+      fft_columns<T, true>(lds, hp.fp[0], cs, TY, tpc);
 #pragma unroll
       for (int k = 0; k < kCPT; ++k) {
         const int e = threadIdx.x + k * blockDim.x;
@@ -516,11 +566,9 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
   }
 
   // ----- epilogue -----
-  const DevParams P = hp.prm[b];
-  const bool add_hd = DEMAG && (P.terms & MM_DEMAG);
   const T g1 = T(P.g1), g2 = T(P.g2);
   const long long N = g.N;
-  const T* mb = ms + (size_t)b * epi.inst_stride;
+  const T* mb = epi.in + (size_t)b * epi.inst_stride;
   const bool energy = epi.mode == MODE_ENERGY || epi.mode == MODE_FIELD_ENERGY;
   double esum[5] = {0, 0, 0, 0, 0};
   double emax = 0.0;
@@ -617,45 +665,52 @@ __global__ void __launch_bounds__(kNTI) k_inv_x(HotPlan<T> hp, const T* __restri
 // Step begin: finish the previous accepted attempt (project y5, FSAL copy),
 // then form the stage-2 input m + h a21 k1.  One thread per cell.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline long long begin_blocks(const Geo& g, int batch) {
+  return (long long)batch * ((g.N + kNT - 1) / kNT);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kNT) k_begin(Geo g, T* __restrict__ m, T* __restrict__ ms0,
-                                               const T* __restrict__ ms1, T* __restrict__ k1,
-                                               const T* __restrict__ k7, double a21,
-                                               const DevCtl* __restrict__ ctl) {
+__global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
+  long long bid;
+  const int gi = group_of(L, bid);
+  const HotPlan<T>& hp = L.hps[gi];
+  const Epi<T>& ep = L.epis[gi];
+  const Geo& g = hp.g;
+  if (bid >= begin_blocks(g, hp.batch)) return;
   const long long N = g.N;
   const long long blocks_per = (N + kNT - 1) / kNT;
-  const int b = blockIdx.x / blocks_per;
-  const long long i = (blockIdx.x % blocks_per) * kNT + threadIdx.x;
+  const int b = (int)(bid / blocks_per);
+  const long long i = (bid % blocks_per) * kNT + threadIdx.x;
   if (i >= N) return;
-  const DevCtl& C = ctl[b];
+  const DevCtl& C = ep.ctl[b];
   const size_t o = (size_t)b * 3 * N + i;
   V3<T> mi;
   V3<T> kv;
   if (C.pending_finish) {
-    const V3<T> y = {ms1[o], ms1[o + N], ms1[o + 2 * N]};
+    const V3<T> y = {ep.bms1[o], ep.bms1[o + N], ep.bms1[o + 2 * N]};
     const T s = rsqrt_t<T>(y.x * y.x + y.y * y.y + y.z * y.z);
     mi = {y.x * s, y.y * s, y.z * s};
-    m[o] = mi.x; m[o + N] = mi.y; m[o + 2 * N] = mi.z;
-    kv = {k7[o], k7[o + N], k7[o + 2 * N]};
-    k1[o] = kv.x; k1[o + N] = kv.y; k1[o + 2 * N] = kv.z;
+    ep.bm[o] = mi.x; ep.bm[o + N] = mi.y; ep.bm[o + 2 * N] = mi.z;
+    kv = {ep.bk7[o], ep.bk7[o + N], ep.bk7[o + 2 * N]};
+    ep.bk1[o] = kv.x; ep.bk1[o + N] = kv.y; ep.bk1[o + 2 * N] = kv.z;
   } else {
     if (C.done) return;
-    mi = {m[o], m[o + N], m[o + 2 * N]};
-    kv = {k1[o], k1[o + N], k1[o + 2 * N]};
+    mi = {ep.bm[o], ep.bm[o + N], ep.bm[o + 2 * N]};
+    kv = {ep.bk1[o], ep.bk1[o + N], ep.bk1[o + 2 * N]};
   }
   if (C.done) return;
-  const T c = T(C.h_att * a21);
-  ms0[o] = mi.x + c * kv.x;
-  ms0[o + N] = mi.y + c * kv.y;
-  ms0[o + 2 * N] = mi.z + c * kv.z;
+  const T c = T(C.h_att * ep.a21);
+  ep.bms0[o] = mi.x + c * kv.x;
+  ep.bms0[o + N] = mi.y + c * kv.y;
+  ep.bms0[o + 2 * N] = mi.z + c * kv.z;
 }
 
 // ---------------------------------------------------------------------------
 // Device-side Dormand-Prince controller, one thread per instance (FP64).
 // ---------------------------------------------------------------------------
-__global__ void k_controller(DevCtl* ctl, int batch, const double* __restrict__ replay_h) {
+__global__ void k_controller(DevCtl* ctl, int n, const double* __restrict__ replay_h) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
+  if (b >= n) return;
   DevCtl& C = ctl[b];
   if (C.done) {
     C.pending_finish = 0;
@@ -833,70 +888,186 @@ __global__ void __launch_bounds__(kNT) k_neb(Geo g, int n_img, const T* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Launchers: one launch per pass over every group that takes part in it.
 // ---------------------------------------------------------------------------
-static size_t lds_x(const Geo& g, const Tuning& tu, size_t csz) { return (size_t)tu.ty_x * col_stride(g.Lx) * csz; }
+namespace {
 
-int eval_blocks_per_inst(const Geo& g, const Tuning& tu) {
-  return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz;
+template <typename T>
+struct LaunchBuilder {
+  Launch<T> L;
+  long long total = 0;
+  LaunchBuilder(const GroupSet<T>& gs, const Epi<T>* epis) {
+    L.hps = gs.dh;
+    L.epis = epis;
+    L.ngroups = gs.n;
+    for (int i = 0; i <= kMaxGroups; ++i) L.off[i] = 0;
+  }
+  // blocks of each group (0 = the group takes no part); padded to multiples of 8
+  void set(int gi, long long nb) {
+    L.off[gi] = (int)total;
+    total += (nb + 7) / 8 * 8;
+    L.off[gi + 1] = (int)total;
+  }
+};
+
+template <typename T, int PZ>
+void z_reg_launch(const Launch<T>& L, long long total, hipStream_t s) {
+  if constexpr (!(sizeof(T) == 8 && PZ > 16)) {  // FP64 columns beyond 16 points use LDS
+    k_z3d_reg<T, PZ><<<dim3((unsigned)total), kNT, 0, s>>>(L);
+  }
 }
 
 template <typename T>
-hipError_t launch_eval(const HotPlan<T>& hp, int batch, const T* m, const Epi<T>& epi, bool demag,
-                       hipStream_t s, hipEvent_t* ev) {
-  const Geo& g = hp.g;
-  const Tuning& tu = hp.tu;
+bool z_reg_supported(int Pz) {
+  const int lim = sizeof(T) == 4 ? 32 : 16;
+  switch (Pz) {
+    case 2: case 3: case 4: case 6: case 8: case 9: case 12: case 16: case 18: case 24: case 27: case 32:
+      return Pz <= lim;
+    default:
+      return false;
+  }
+}
+
+template <typename T>
+void z_reg_dispatch(int Pz, const Launch<T>& L, long long total, hipStream_t s) {
+  switch (Pz) {
+    case 2: z_reg_launch<T, 2>(L, total, s); break;
+    case 3: z_reg_launch<T, 3>(L, total, s); break;
+    case 4: z_reg_launch<T, 4>(L, total, s); break;
+    case 6: z_reg_launch<T, 6>(L, total, s); break;
+    case 8: z_reg_launch<T, 8>(L, total, s); break;
+    case 9: z_reg_launch<T, 9>(L, total, s); break;
+    case 12: z_reg_launch<T, 12>(L, total, s); break;
+    case 16: z_reg_launch<T, 16>(L, total, s); break;
+    case 18: z_reg_launch<T, 18>(L, total, s); break;
+    case 24: z_reg_launch<T, 24>(L, total, s); break;
+    case 27: z_reg_launch<T, 27>(L, total, s); break;
+    case 32: z_reg_launch<T, 32>(L, total, s); break;
+    default: break;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hipStream_t s, hipEvent_t* ev) {
   const size_t csz = sizeof(Cx<T>);
-  const int xtiles = (g.ny + tu.ty_x - 1) / tu.ty_x;
   int e = 0;
   auto mark = [&]() {
     if (ev) (void)hipEventRecord(ev[e++], s);
   };
+  bool any3d = false;
+  for (int i = 0; i < gs.n; ++i) any3d = any3d || gs.h[i].g.nz > 1;
   if (demag) {
-    const int ftiles = (g.ny + tu.ty_f - 1) / tu.ty_f;
-    const size_t ldsf = (size_t)tu.ty_f * col_stride(g.Lx) * csz;
-    mark();
-    k_fwd_x<T><<<dim3((unsigned)(batch * 3 * g.nz * ftiles)), tu.nt_f, ldsf, s>>>(hp, m, epi.ctl);
-    if (g.nz == 1) {
-      const int tiles = (g.Xp + tu.cb_y2 - 1) / tu.cb_y2;
-      const size_t lds = (size_t)3 * tu.cb_y2 * col_stride(g.Py) * csz;
+    {  // x forward
+      LaunchBuilder<T> lb(gs, epis);
+      int nt = 64;
+      size_t lds = 0;
+      for (int i = 0; i < gs.n; ++i) {
+        const HotPlan<T>& h = gs.h[i];
+        lb.set(i, fwd_blocks(h.g, h.tu, h.batch));
+        nt = std::max(nt, h.tu.nt_f);
+        lds = std::max(lds, (size_t)h.tu.ty_f * col_stride(h.g.Lx) * csz);
+      }
       mark();
-      k_y_fused2d<T><<<dim3((unsigned)(batch * tiles)), 3 * tu.cb_y2 * tu.tpc_y2, lds, s>>>(hp, epi.ctl);
-    } else {
-      const long long rows = 3LL * g.nz * g.Xp;
-      const long long ytiles = (rows + tu.cb_y - 1) / tu.cb_y;
-      const size_t ldsy = (size_t)tu.cb_y * col_stride(g.Py) * csz;
+      k_fwd_x<T><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
+    }
+    {  // y forward (2-D groups: fused forward / product / inverse)
+      LaunchBuilder<T> lb(gs, epis);
+      int nt = 64;
+      size_t lds = 0;
+      for (int i = 0; i < gs.n; ++i) {
+        const HotPlan<T>& h = gs.h[i];
+        if (h.g.nz == 1) {
+          lb.set(i, y2d_blocks(h.g, h.tu, h.batch));
+          lds = std::max(lds, (size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) * csz);
+        } else {
+          lb.set(i, y3d_blocks(h.g, h.tu, h.batch));
+          lds = std::max(lds, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);
+        }
+        nt = std::max(nt, h.tu.nt_y);
+      }
       mark();
-      k_y3d<T, false><<<dim3((unsigned)(batch * ytiles)), tu.cb_y * tu.tpc_y, ldsy, s>>>(hp, epi.ctl);
-      const long long nq = (long long)g.Xp * g.Py;
-      const long long ztiles = (nq + tu.qz - 1) / tu.qz;
-      const size_t ldsz = (size_t)3 * tu.qz * col_stride(g.Pz) * csz;
+      k_ypass<T><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
+    }
+    if (any3d) {
+      // z: register transform for every supported Pz (one launch per distinct
+      // Pz), LDS transform for the rest
+      int done_pz[kMaxGroups];
+      int ndone = 0;
       mark();
-      if (!launch_z_reg<T>(hp, batch, epi.ctl, s))
-        k_z3d<T><<<dim3((unsigned)(batch * ztiles)), 3 * tu.qz * tu.tpc_z, ldsz, s>>>(hp, epi.ctl);
+      for (int i = 0; i < gs.n; ++i) {
+        const HotPlan<T>& hi = gs.h[i];
+        if (hi.g.nz == 1 || !z_reg_supported<T>(hi.g.Pz)) continue;
+        bool seen = false;
+        for (int k = 0; k < ndone; ++k) seen = seen || done_pz[k] == hi.g.Pz;
+        if (seen) continue;
+        done_pz[ndone++] = hi.g.Pz;
+        LaunchBuilder<T> lb(gs, epis);
+        for (int j = 0; j < gs.n; ++j) {
+          const HotPlan<T>& h = gs.h[j];
+          lb.set(j, (h.g.nz > 1 && h.g.Pz == hi.g.Pz) ? zreg_blocks(h.g, h.batch) : 0);
+        }
+        z_reg_dispatch<T>(hi.g.Pz, lb.L, lb.total, s);
+      }
+      LaunchBuilder<T> lz(gs, epis);
+      int nt = 0;
+      size_t lds = 0;
+      for (int j = 0; j < gs.n; ++j) {
+        const HotPlan<T>& h = gs.h[j];
+        const bool use = h.g.nz > 1 && !z_reg_supported<T>(h.g.Pz);
+        lz.set(j, use ? zlds_blocks(h.g, h.tu, h.batch) : 0);
+        if (use) {
+          nt = std::max(nt, 3 * h.tu.qz * h.tu.tpc_z);
+          lds = std::max(lds, (size_t)3 * h.tu.qz * col_stride(h.g.Pz) * csz);
+        }
+      }
+      if (nt > 0) k_z3d<T><<<dim3((unsigned)lz.total), nt, lds, s>>>(lz.L);
+      // y inverse
+      LaunchBuilder<T> ly(gs, epis);
+      int nty = 64;
+      size_t ldsy = 0;
+      for (int j = 0; j < gs.n; ++j) {
+        const HotPlan<T>& h = gs.h[j];
+        const bool use = h.g.nz > 1;
+        ly.set(j, use ? y3d_blocks(h.g, h.tu, h.batch) : 0);
+        if (use) {
+          nty = std::max(nty, h.tu.nt_y);
+          ldsy = std::max(ldsy, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);
+        }
+      }
       mark();
-      k_y3d<T, true><<<dim3((unsigned)(batch * ytiles)), tu.cb_y * tu.tpc_y, ldsy, s>>>(hp, epi.ctl);
+      k_yinv<T><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
+    }
+  }
+  {  // x inverse + epilogue
+    LaunchBuilder<T> lb(gs, epis);
+    int nt = 64;
+    size_t lds = 0;
+    for (int i = 0; i < gs.n; ++i) {
+      const HotPlan<T>& h = gs.h[i];
+      lb.set(i, inv_blocks(h.g, h.tu, h.batch));
+      nt = std::max(nt, h.tu.nt_i);
+      if (demag) lds = std::max(lds, (size_t)h.tu.ty_x * col_stride(h.g.Lx) * csz);
     }
     mark();
-    k_inv_x<T, true><<<dim3((unsigned)(batch * g.nz * xtiles)), tu.nt_i, lds_x(g, tu, csz), s>>>(hp, m, epi);
-  } else {
-    mark();
-    k_inv_x<T, false><<<dim3((unsigned)(batch * g.nz * xtiles)), tu.nt_i, 0, s>>>(hp, m, epi);
+    if (demag) k_inv_x<T, true><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
+    else k_inv_x<T, false><<<dim3((unsigned)lb.total), nt, 0, s>>>(lb.L);
   }
   mark();
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_begin(const Geo& g, int batch, T* m, T* ms0, const T* ms1, T* k1, const T* k7,
-                        double a21, DevCtl* ctl, hipStream_t s) {
-  const long long bpi = (g.N + kNT - 1) / kNT;
-  k_begin<T><<<dim3((unsigned)(batch * bpi)), kNT, 0, s>>>(g, m, ms0, ms1, k1, k7, a21, ctl);
+hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s) {
+  LaunchBuilder<T> lb(gs, epis);
+  for (int i = 0; i < gs.n; ++i) lb.set(i, begin_blocks(gs.h[i].g, gs.h[i].batch));
+  k_begin<T><<<dim3((unsigned)lb.total), kNT, 0, s>>>(lb.L);
   return hipGetLastError();
 }
 
-hipError_t launch_controller(DevCtl* ctl, int batch, const double* replay_h, hipStream_t s) {
-  k_controller<<<dim3((batch + 63) / 64), 64, 0, s>>>(ctl, batch, replay_h);
+hipError_t launch_controller(DevCtl* ctl, int n, const double* replay_h, hipStream_t s) {
+  k_controller<<<dim3((n + 63) / 64), 64, 0, s>>>(ctl, n, replay_h);
   return hipGetLastError();
 }
 
@@ -918,11 +1089,10 @@ hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T
   return hipGetLastError();
 }
 
-#define MMX_INST(T)                                                                                \
-  template hipError_t launch_eval<T>(const HotPlan<T>&, int, const T*, const Epi<T>&, bool,        \
-                                     hipStream_t, hipEvent_t*);                                    \
-  template hipError_t launch_begin<T>(const Geo&, int, T*, T*, const T*, T*, const T*, double,     \
-                                      DevCtl*, hipStream_t);                                       \
+#define MMX_INST(T)                                                                               \
+  template hipError_t launch_eval<T>(const GroupSet<T>&, const Epi<T>*, bool, hipStream_t,         \
+                                     hipEvent_t*);                                                \
+  template hipError_t launch_begin<T>(const GroupSet<T>&, const Epi<T>*, hipStream_t);            \
   template hipError_t launch_neb<T>(const Geo&, int, const T*, T*, const T*, const double*, double, \
                                     double, double*, double*, double, double, int, hipStream_t);
 MMX_INST(float)

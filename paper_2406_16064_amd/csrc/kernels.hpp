@@ -27,9 +27,12 @@ enum Mode : int {
   MODE_FIELD_ENERGY = 5  // write H_eff and energy partial sums (NEB)
 };
 
-// What the fused epilogue does after H_eff is known at a cell.
+// What one launch does for one group of instances (a group = instances that
+// share a mesh): the evaluated input, the fused epilogue after H_eff is known
+// at a cell, and the arguments of the step-begin kernel.
 template <typename T> struct Epi {
   int mode;
+  const T* in;            // magnetisation evaluated by this pass sequence
   T* out;                 // H (FIELD*), dm/dt (RHS), k_s (STAGE/ERROR)
   const T* mbase;         // m at the start of the step (STAGE)
   T* msn;                 // next stage input (STAGE)
@@ -39,6 +42,13 @@ template <typename T> struct Epi {
   double* partial;        // energy partials [batch][blocks_per_inst][5]
   DevCtl* ctl;            // per-instance controller (skip done instances; h_att; err)
   long long inst_stride;  // elements per instance of m-like arrays (3N)
+  // step begin
+  T* bm;
+  T* bms0;
+  const T* bms1;
+  T* bk1;
+  const T* bk7;
+  double a21;
 };
 
 struct Tuning {
@@ -52,10 +62,12 @@ struct Tuning {
   int tpc_y;
   int cb_y2;    // kx columns per workgroup of the fused 2-D y pass (x3 components)
   int tpc_y2;
-  int qz;       // (kx,ky) columns per workgroup of the z pass (x3 components)
+  int nt_y;     // threads per workgroup of the y passes
+  int qz;       // (kx,ky) columns per workgroup of the LDS z pass (x3 components)
   int tpc_z;
 };
 
+// Static description of one group (device resident, one entry per group).
 template <typename T> struct HotPlan {
   Geo g;
   Tuning tu;
@@ -64,30 +76,49 @@ template <typename T> struct HotPlan {
   const Cx<T>* post;       // exp(-2 pi i k / Px), k = 0..Lx
   const T* kt;             // tensor spectrum [ncomp][Kz][Xp][Ky]
   int ncomp;               // 4 (nz = 1) or 6
+  int batch;               // instances in the group
   Cx<T>* Sx;               // [batch][3][nz][Xp][ny]
   Cx<T>* Sy;               // [batch][3][nz][Xp][Py] (3-D only)
   const DevParams* prm;    // [batch]
 };
 
-// One effective-field evaluation followed by the fused epilogue, for `batch`
-// instances stored contiguously at m (stride 3N).  With ev != nullptr an event
-// is recorded before each pass and after the last one (pass timing).
+constexpr int kMaxGroups = 16;
+
+// Kernel argument of every hot-path launch: the groups it covers and where
+// each group's workgroups start (multiples of 8, so the XCD of a workgroup
+// follows its index inside the group).
+template <typename T> struct Launch {
+  const HotPlan<T>* hps;     // device [ngroups]
+  const Epi<T>* epis;        // device [ngroups]
+  int ngroups;
+  int off[kMaxGroups + 1];   // off[ngroups] = grid size
+};
+
+// Host-side view of a set of groups for launching.
+template <typename T> struct GroupSet {
+  int n;
+  HotPlan<T> h[kMaxGroups];  // host copies (block counts, launch shapes)
+  const HotPlan<T>* dh;      // device copies
+};
+
+// One effective-field evaluation with the fused epilogue for every group
+// (epis: device array [n]).  With ev != nullptr an event is recorded before
+// each pass and after the last one (pass timing; single group only).
 template <typename T>
-hipError_t launch_eval(const HotPlan<T>& hp, int batch, const T* m, const Epi<T>& epi, bool demag,
-                       hipStream_t s, hipEvent_t* ev = nullptr);
+hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hipStream_t s,
+                       hipEvent_t* ev = nullptr);
 
 template <typename T>
-hipError_t launch_begin(const Geo& g, int batch, T* m, T* ms0, const T* ms1, T* k1, const T* k7,
-                        double a21, DevCtl* ctl, hipStream_t s);
+hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s);
 
-hipError_t launch_controller(DevCtl* ctl, int batch, const double* replay_h, hipStream_t s);
+hipError_t launch_controller(DevCtl* ctl, int n, const double* replay_h, hipStream_t s);
 
 hipError_t launch_energy_reduce(const double* partial, int batch, int blocks_per_inst, double* out,
                                 hipStream_t s);
 
 int eval_blocks_per_inst(const Geo& g, const Tuning& tu);
 
-// NEB: tangent/projection sums (pass A) and the relaxation update (pass B).
+// NEB: tangent/projection sums (pass 0) and the relaxation update (pass 1) of one chain.
 template <typename T>
 hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T* H,
                       const double* E5, double cq, double cz, double* sums, double* partial,

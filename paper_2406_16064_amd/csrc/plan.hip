@@ -1,7 +1,12 @@
-// Host runtime and C interface (include/mm.h): validation, plan set-up
-// (padded grid, radix plans, twiddles, launch shapes, tensor spectrum),
-// effective field / LL / energy calls, device-controlled Dormand-Prince runs
-// with HIP-graph replay, and the NEB driver.
+// Host runtime and C interface (include/mm.h).
+//
+// An engine owns one or more geometry groups (instances that share a mesh:
+// padded grid, radix plans, twiddles, launch shapes, tensor spectrum, spectral
+// work buffers) plus the per-instance parameter and controller arrays.  A plan
+// is an engine with one group; a batch has one group per distinct mesh, and
+// every pass of an evaluation is a single launch over all groups.  On top:
+// validation, effective field / LL / energy calls, device-controlled
+// Dormand-Prince runs with HIP-graph replay, and the NEB driver.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -180,53 +185,6 @@ const Tableau kDP;
 
 bool is_fin(double v) { return std::isfinite(v); }
 
-}  // namespace
-
-struct mm_plan {
-  mm_mesh mesh;
-  mm_precision prec;
-  uint32_t terms;
-  int maxb;
-  int ncomp;
-  Geo g;
-  Tuning tu;
-  size_t csz, rsz;  // complex / real element sizes
-  int devid;
-  hipStream_t cap = nullptr;  // capture stream (default priority)
-  // device buffers
-  void* Sx = nullptr;
-  void* Sy = nullptr;
-  void* kt = nullptr;
-  void* post = nullptr;
-  void* twx = nullptr;
-  void* twy = nullptr;
-  void* twz = nullptr;
-  void* fplans = nullptr;  // device FftPlan[3] (x, y, z)
-  DevParams* prm = nullptr;
-  DevCtl* ctl = nullptr;
-  double* partial = nullptr;
-  double* e5 = nullptr;
-  double* replay = nullptr;
-  long long replay_cap = 0;
-  void* stage = nullptr;  // ms0, ms1, k1..k7 (9 x maxb x 3N)
-  // NEB scratch
-  void* nebH = nullptr;
-  void* nebB = nullptr;
-  double* nebS = nullptr;
-  double* nebP = nullptr;
-  // host staging (pinned)
-  DevCtl* hctl = nullptr;
-  double* he5 = nullptr;
-  // graph cache for rk45 runs
-  hipGraphExec_t gexec = nullptr;
-  const void* g_m = nullptr;
-  int g_batch = -1;
-  int g_steps = 0;
-  double imag_ratio = 0.0;  // max |Im| / max |Re| of the tensor spectrum
-  bool any_demag = false;   // some instance of the last uploaded parameters enables demag
-};
-
-namespace {
 
 mm_status check_mesh(const mm_mesh* m) {
   if (!m) return fail(MM_E_ARG, "mesh is null");
@@ -237,7 +195,81 @@ mm_status check_mesh(const mm_mesh* m) {
   return MM_OK;
 }
 
-mm_status check_params(const mm_plan* p, const mm_params* q, int n) {
+int pow2ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+constexpr int kEpiSlots = 9;  // 0: single call, 1: first slope, 2..7: stages, 8: step begin
+
+// One geometry: mesh, padded grid, launch shapes, tables, spectrum and the
+// spectral / integrator work buffers of up to `cap` instances.
+struct Group {
+  mm_mesh mesh;
+  Geo g;
+  Tuning tu;
+  int ncomp = 4;
+  int cap = 0;        // instances the work buffers hold
+  int stage_cap = 0;  // instances the Runge-Kutta buffers hold
+  int mbuf_cap = 0;
+  void* Sx = nullptr;
+  void* Sy = nullptr;
+  void* kt = nullptr;
+  void* post = nullptr;
+  void* twx = nullptr;
+  void* twy = nullptr;
+  void* twz = nullptr;
+  void* fplans = nullptr;
+  void* stage = nullptr;  // ms0, ms1, k1..k7: 9 x stage_cap x 3N
+  void* mbuf = nullptr;   // contiguous m of the group's instances (batch runs)
+  double imag_ratio = 0.0;
+};
+
+}  // namespace
+
+struct Engine {
+  mm_precision prec;
+  uint32_t terms;
+  size_t csz, rsz;
+  std::vector<Group> groups;
+  int inst_cap = 0;  // instances the parameter / controller arrays hold
+  int part_cap = 0;  // doubles the energy partial buffer holds
+  hipStream_t cap = nullptr;  // capture stream (default priority)
+  DevParams* prm = nullptr;
+  DevCtl* ctl = nullptr;
+  double* partial = nullptr;
+  double* e5 = nullptr;
+  double* replay = nullptr;
+  long long replay_cap = 0;
+  void* dhot = nullptr;  // device HotPlan<T>[kMaxGroups]
+  void* depi = nullptr;  // device Epi<T>[kEpiSlots][kMaxGroups]
+  DevCtl* hctl = nullptr;
+  double* he5 = nullptr;
+  bool any_demag = false;
+  // graph cache of the Dormand-Prince attempt sequence
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> g_key;
+  // NEB scratch (group 0)
+  void* nebH = nullptr;
+  void* nebB = nullptr;
+  double* nebS = nullptr;
+  double* nebP = nullptr;
+  int neb_cap = 0;
+};
+
+struct mm_plan {
+  Engine e;
+  int maxb;
+};
+
+struct mm_batch {
+  Engine e;
+};
+
+namespace {
+
+mm_status check_params(const Engine& E, const mm_params* q, int n) {
   if (!q) return fail(MM_E_ARG, "params is null");
   for (int b = 0; b < n; ++b) {
     const mm_params& r = q[b];
@@ -248,69 +280,53 @@ mm_status check_params(const mm_plan* p, const mm_params* q, int n) {
     if (r.alpha < 0) return fail(MM_E_ARG, "alpha must be >= 0");
     if (r.gamma <= 0) return fail(MM_E_ARG, "gamma must be > 0");
     if (r.A < 0) return fail(MM_E_ARG, "A must be >= 0");
-    if ((r.terms & ~p->terms) != 0) return fail(MM_E_ARG, "params enable a term the plan was not built for");
+    if ((r.terms & ~E.terms) != 0) return fail(MM_E_ARG, "params enable a term the plan was not built for");
     if ((r.terms & MM_ANIS_UNIAXIAL) && r.u[0] == 0 && r.u[1] == 0 && r.u[2] == 0)
       return fail(MM_E_ARG, "easy axis must be non-zero");
   }
   return MM_OK;
 }
 
-mm_status upload_params(mm_plan* p, const mm_params* q, int n, hipStream_t s) {
-  std::vector<DevParams> d(n);
-  const double P = (double)p->g.Px * p->g.Py * p->g.Pz;
-  for (int b = 0; b < n; ++b) {
-    const mm_params& r = q[b];
-    DevParams& o = d[b];
-    std::memset(&o, 0, sizeof(o));
-    o.Ms = r.Ms;
-    const double c = kMu0 * r.Ms;
-    o.cex[0] = 2 * r.A / (c * p->mesh.dx * p->mesh.dx);
-    o.cex[1] = 2 * r.A / (c * p->mesh.dy * p->mesh.dy);
-    o.cex[2] = 2 * r.A / (c * p->mesh.dz * p->mesh.dz);
-    o.cdmi[0] = r.D / (c * p->mesh.dx);
-    o.cdmi[1] = r.D / (c * p->mesh.dy);
-    o.can = 2 * r.Ku / c;
-    const double un = std::sqrt(r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
-    for (int k = 0; k < 3; ++k) {
-      o.u[k] = un > 0 ? r.u[k] / un : 0.0;
-      o.H[k] = r.H[k];
-    }
-    o.g1 = -r.gamma / (1 + r.alpha * r.alpha);
-    o.g2 = -r.alpha * r.gamma / (1 + r.alpha * r.alpha);
-    o.demag_scale = -r.Ms / P;
-    o.terms = r.terms;
+DevParams dev_params(const mm_params& r, const Group& G) {
+  DevParams o;
+  std::memset(&o, 0, sizeof(o));
+  const double P = (double)G.g.Px * G.g.Py * G.g.Pz;
+  o.Ms = r.Ms;
+  const double c = kMu0 * r.Ms;
+  o.cex[0] = 2 * r.A / (c * G.mesh.dx * G.mesh.dx);
+  o.cex[1] = 2 * r.A / (c * G.mesh.dy * G.mesh.dy);
+  o.cex[2] = 2 * r.A / (c * G.mesh.dz * G.mesh.dz);
+  o.cdmi[0] = r.D / (c * G.mesh.dx);
+  o.cdmi[1] = r.D / (c * G.mesh.dy);
+  o.can = 2 * r.Ku / c;
+  const double un = std::sqrt(r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+  for (int k = 0; k < 3; ++k) {
+    o.u[k] = un > 0 ? r.u[k] / un : 0.0;
+    o.H[k] = r.H[k];
   }
-  p->any_demag = false;
-  for (int b = 0; b < n; ++b) p->any_demag = p->any_demag || (q[b].terms & MM_DEMAG) != 0;
-  HIPCHK(hipMemcpyAsync(p->prm, d.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return MM_OK;
+  o.g1 = -r.gamma / (1 + r.alpha * r.alpha);
+  o.g2 = -r.alpha * r.gamma / (1 + r.alpha * r.alpha);
+  o.demag_scale = -r.Ms / P;
+  o.terms = r.terms;
+  return o;
 }
 
-// Launch shapes.  Each workgroup keeps its LDS within 80 KiB (two per CU), the
-// per-thread butterfly budget of the transforms is respected, and tiles shrink
-// until a pass has about 4 workgroups per CU (small meshes) or reach their
-// coalescing-friendly maximum (large meshes).
-int pow2ceil(int v) {
-  int p = 1;
-  while (p < v) p <<= 1;
-  return p;
-}
-
-mm_status choose_tuning(mm_plan* p) {
-  const Geo& g = p->g;
-  Tuning& t = p->tu;
-  const size_t csz = p->csz;
+// Launch shapes of one group.  Each workgroup keeps its LDS within 80 KiB (two
+// per CU), the per-thread butterfly budget of the transforms is respected, and
+// tiles shrink until a pass has about 4 workgroups per CU (small meshes) or
+// reach their coalescing-friendly maximum (large meshes).
+mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
+  const Geo& g = G.g;
+  Tuning& t = G.tu;
   const size_t budget = 80 * 1024;
   const long long want = 4 * 256;  // workgroups per pass worth aiming for
   auto tpc_for = [&](int L) {
-    if (p->prec == MM_F32) return min_tpc(make_fft<float>(L, nullptr));
+    if (prec == MM_F32) return min_tpc(make_fft<float>(L, nullptr));
     return min_tpc(make_fft<double>(L, nullptr));
   };
   const int tpx = tpc_for(g.Lx);
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
-  // forward x: rows of one component
-  {
+  {  // forward x: rows of one component
     const long long rows = 3LL * g.nz * g.ny;
     int ty = 16;
     while (ty > 1 && ((size_t)ty * rowb > budget || ty * tpx > 512 || rows / ty < want)) ty /= 2;
@@ -320,8 +336,7 @@ mm_status choose_tuning(mm_plan* p) {
     t.nt_f = std::min(512, std::max(64, pow2ceil(std::max(ty * tpx, ty * g.Lx / 4))));
     t.tpc_f = t.nt_f / ty;
   }
-  // inverse x + epilogue: rows of all 3 components, at most 8 cells per thread
-  {
+  {  // inverse x + epilogue: rows of all 3 components, at most 8 cells per thread
     const long long rows = (long long)g.nz * g.ny;
     int ty = 16;
     while (ty > 1 && ((size_t)ty * rowb > budget || ty * tpx > 512 || ty * g.nx > 8 * 512 || rows / ty < want))
@@ -333,8 +348,8 @@ mm_status choose_tuning(mm_plan* p) {
     t.nt_i = std::min(512, std::max(64, pow2ceil(std::max(ty * tpx, ty * g.nx))));
     t.tpc_x = t.nt_i / ty;
   }
+  const int tmin = tpc_for(g.Py);
   if (g.nz == 1) {
-    const int tmin = tpc_for(g.Py);
     const int tpc = std::max(tmin, std::min(2 * tmin, 64));
     const size_t colb = 3 * (size_t)col_stride(g.Py) * csz;
     int cb = 8;
@@ -342,8 +357,8 @@ mm_status choose_tuning(mm_plan* p) {
     if (cb * colb > 160 * 1024 || 3 * cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y2 = cb;
     t.tpc_y2 = tpc;
+    t.nt_y = 3 * cb * tpc;
   } else {
-    const int tmin = tpc_for(g.Py);
     const int tpc = std::max(tmin, std::min(2 * tmin, 64));
     const size_t colb = (size_t)col_stride(g.Py) * csz;
     const long long rows = 3LL * g.nz * g.Xp;
@@ -352,6 +367,7 @@ mm_status choose_tuning(mm_plan* p) {
     if (cb * colb > 160 * 1024 || cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y = cb;
     t.tpc_y = tpc;
+    t.nt_y = cb * tpc;
     const int tz = tpc_for(g.Pz);
     int qz = (int)(budget / (3 * col_stride(g.Pz) * csz));
     qz = std::min(qz, 512 / (3 * tz));
@@ -364,63 +380,47 @@ mm_status choose_tuning(mm_plan* p) {
 }
 
 template <typename T>
-HotPlan<T> hot(const mm_plan* p) {
-  HotPlan<T> h{};
-  h.g = p->g;
-  h.tu = p->tu;
-  h.fp = (const FftPlan<T>*)p->fplans;
-  h.twz = (const Cx<T>*)p->twz;
-  h.post = (const Cx<T>*)p->post;
-  h.kt = (const T*)p->kt;
-  h.ncomp = p->ncomp;
-  h.Sx = (Cx<T>*)p->Sx;
-  h.Sy = (Cx<T>*)p->Sy;
-  h.prm = p->prm;
-  return h;
-}
-
-template <typename T>
-mm_status upload_tables(mm_plan* p) {
+mm_status upload_tables(Group& G) {
   auto up = [&](void** dst, const std::vector<Cx<T>>& v) -> mm_status {
     HIPCHK(hipMalloc(dst, sizeof(Cx<T>) * std::max<size_t>(v.size(), 1)));
     HIPCHK(hipMemcpy(*dst, v.data(), sizeof(Cx<T>) * v.size(), hipMemcpyHostToDevice));
     return MM_OK;
   };
-  MMCHK(up(&p->twx, twiddles<T>(p->g.Lx)));
-  MMCHK(up(&p->twy, twiddles<T>(p->g.Py)));
-  MMCHK(up(&p->twz, twiddles<T>(p->g.Pz)));
-  std::vector<Cx<T>> post(p->g.Lx + 1);
-  for (int k = 0; k <= p->g.Lx; ++k) {
-    const double a = -2.0 * M_PI * k / (double)p->g.Px;
+  MMCHK(up(&G.twx, twiddles<T>(G.g.Lx)));
+  MMCHK(up(&G.twy, twiddles<T>(G.g.Py)));
+  MMCHK(up(&G.twz, twiddles<T>(G.g.Pz)));
+  std::vector<Cx<T>> post(G.g.Lx + 1);
+  for (int k = 0; k <= G.g.Lx; ++k) {
+    const double a = -2.0 * M_PI * k / (double)G.g.Px;
     post[k] = Cx<T>{(T)std::cos(a), (T)std::sin(a)};
   }
-  MMCHK(up(&p->post, post));
-  const FftPlan<T> fp[3] = {make_fft<T>(p->g.Lx, (const Cx<T>*)p->twx), make_fft<T>(p->g.Py, (const Cx<T>*)p->twy),
-                            make_fft<T>(p->g.Pz, (const Cx<T>*)p->twz)};
-  HIPCHK(hipMalloc(&p->fplans, sizeof(fp)));
-  HIPCHK(hipMemcpy(p->fplans, fp, sizeof(fp), hipMemcpyHostToDevice));
+  MMCHK(up(&G.post, post));
+  const FftPlan<T> fp[3] = {make_fft<T>(G.g.Lx, (const Cx<T>*)G.twx), make_fft<T>(G.g.Py, (const Cx<T>*)G.twy),
+                            make_fft<T>(G.g.Pz, (const Cx<T>*)G.twz)};
+  HIPCHK(hipMalloc(&G.fplans, sizeof(fp)));
+  HIPCHK(hipMemcpy(G.fplans, fp, sizeof(fp), hipMemcpyHostToDevice));
   return MM_OK;
 }
 
 // Tensor spectrum on the device: Newell grid (FP64) -> 3-D FFT (FP64) -> fold -> cast.
 template <typename T>
-mm_status build_spectrum(mm_plan* p, hipStream_t s) {
-  const Geo& g = p->g;
+mm_status build_spectrum(Group& G, hipStream_t s) {
+  const Geo& g = G.g;
   double nodes[5][20] = {}, wts[5][20] = {};
   int nn[5];
   tent_rules(nodes, wts, nn);
   HIPCHK(setup_upload_gauss(nodes, wts, nn));
   const long long tot = (long long)g.Px * g.Py * g.Pz;
   Cx<double>* F = nullptr;
-  HIPCHK(hipMalloc(&F, sizeof(Cx<double>) * tot * p->ncomp));
+  HIPCHK(hipMalloc(&F, sizeof(Cx<double>) * tot * G.ncomp));
   std::vector<void*> tws;
   mm_status st = MM_OK;
   do {
-    hipError_t e = setup_newell_grid(p->mesh, g.Px, g.Py, g.Pz, p->ncomp, F, s);
+    hipError_t e = setup_newell_grid(G.mesh, g.Px, g.Py, g.Pz, G.ncomp, F, s);
     if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("newell grid: ") + hipGetErrorString(e)); break; }
     const int Ls[3] = {g.Px, g.Py, g.Pz};
     const long long inner[3] = {1, g.Px, (long long)g.Px * g.Py};
-    const long long outer[3] = {(long long)g.Py * g.Pz * p->ncomp, (long long)g.Pz * p->ncomp, p->ncomp};
+    const long long outer[3] = {(long long)g.Py * g.Pz * G.ncomp, (long long)g.Pz * G.ncomp, G.ncomp};
     for (int a = 0; a < 3 && st == MM_OK; ++a) {
       if (Ls[a] == 1) continue;
       std::vector<Cx<double>> tw = twiddles<double>(Ls[a]);
@@ -440,8 +440,8 @@ mm_status build_spectrum(mm_plan* p, hipStream_t s) {
     if (e != hipSuccess) { st = fail(MM_E_NOMEM, "stats"); break; }
     tws.push_back(stats);
     e = hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s);
-    for (int c = 0; c < p->ncomp && e == hipSuccess; ++c)
-      e = setup_extract<T>(F + (size_t)c * tot, g.Px, g.Py, g.Pz, c, (T*)p->kt, stats, s);
+    for (int c = 0; c < G.ncomp && e == hipSuccess; ++c)
+      e = setup_extract<T>(F + (size_t)c * tot, g.Px, g.Py, g.Pz, c, (T*)G.kt, stats, s);
     if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("extract: ") + hipGetErrorString(e)); break; }
     unsigned long long hs[2];
     e = hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, s);
@@ -450,8 +450,8 @@ mm_status build_spectrum(mm_plan* p, hipStream_t s) {
     double im, re;
     std::memcpy(&im, &hs[0], 8);
     std::memcpy(&re, &hs[1], 8);
-    p->imag_ratio = re > 0 ? im / re : 0.0;
-    if (!(p->imag_ratio < 1e-9)) st = fail(MM_E_HIP, "tensor spectrum is not real (symmetry broken)");
+    G.imag_ratio = re > 0 ? im / re : 0.0;
+    if (!(G.imag_ratio < 1e-9)) st = fail(MM_E_HIP, "tensor spectrum is not real (symmetry broken)");
   } while (false);
   (void)hipStreamSynchronize(s);
   for (void* d : tws) (void)hipFree(d);
@@ -459,56 +459,231 @@ mm_status build_spectrum(mm_plan* p, hipStream_t s) {
   return st;
 }
 
-void free_plan(mm_plan* p) {
-  if (!p) return;
-  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-  void* bufs[] = {p->Sx, p->Sy, p->kt, p->post, p->twx, p->twy, p->twz, p->fplans, p->prm, p->ctl, p->partial,
-                  p->e5, p->replay, p->stage, p->nebH, p->nebB, p->nebS, p->nebP};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
-  if (p->hctl) (void)hipHostFree(p->hctl);
-  if (p->he5) (void)hipHostFree(p->he5);
-  if (p->cap) (void)hipStreamDestroy(p->cap);
-  delete p;
-}
-
-template <typename T>
-mm_status eval_call(mm_plan* p, int batch, const void* m, const Epi<T>& epi, hipStream_t s,
-                    hipEvent_t* ev = nullptr) {
-  const bool demag = (p->terms & MM_DEMAG) != 0 && p->any_demag;
-  HIPCHK(launch_eval<T>(hot<T>(p), batch, (const T*)m, epi, demag, s, ev));
+mm_status dev_alloc(void** d, size_t bytes) {
+  hipError_t e = hipMalloc(d, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MM_E_NOMEM : MM_E_HIP, hipGetErrorString(e));
   return MM_OK;
 }
 
+void free_group(Group& G) {
+  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.fplans, G.stage, G.mbuf};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  G = Group();
+}
+
+void free_engine(Engine& E) {
+  if (E.gexec) (void)hipGraphExecDestroy(E.gexec);
+  E.gexec = nullptr;
+  for (Group& G : E.groups) free_group(G);
+  void* bufs[] = {E.prm, E.ctl, E.partial, E.e5, E.replay, E.dhot, E.depi, E.nebH, E.nebB, E.nebS, E.nebP};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (E.hctl) (void)hipHostFree(E.hctl);
+  if (E.he5) (void)hipHostFree(E.he5);
+  if (E.cap) (void)hipStreamDestroy(E.cap);
+}
+
+// Geometry, tuning, tables and (with demag) the tensor spectrum of one mesh.
+mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
+  G.mesh = mesh;
+  G.ncomp = mesh.nz == 1 ? 4 : 6;
+  Geo& g = G.g;
+  g.nx = mesh.nx; g.ny = mesh.ny; g.nz = mesh.nz;
+  g.Px = pick_padded(g.nx, true);
+  g.Py = pick_padded(g.ny, false);
+  g.Pz = pick_padded(g.nz, false);
+  g.Lx = g.Px / 2;
+  g.Xp = g.Lx + 1;
+  g.Ky = g.Py / 2 + 1;
+  g.Kz = g.Pz / 2 + 1;
+  g.N = (long long)g.nx * g.ny * g.nz;
+  g.sx = 3LL * g.nz * g.Xp * g.ny;
+  g.sy = 3LL * g.nz * g.Xp * g.Py;
+  g.dV = mesh.dx * mesh.dy * mesh.dz;
+  MMCHK(choose_tuning(G, E.prec, E.csz));
+  if (E.terms & MM_DEMAG) {
+    MMCHK(dev_alloc(&G.kt, E.rsz * G.ncomp * (size_t)g.Kz * g.Xp * g.Ky));
+    MMCHK(E.prec == MM_F32 ? upload_tables<float>(G) : upload_tables<double>(G));
+    MMCHK(E.prec == MM_F32 ? build_spectrum<float>(G, s) : build_spectrum<double>(G, s));
+  }
+  return MM_OK;
+}
+
+mm_status engine_init(Engine& E, mm_precision prec, uint32_t terms) {
+  E.prec = prec;
+  E.terms = terms;
+  E.csz = prec == MM_F32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+  E.rsz = prec == MM_F32 ? sizeof(float) : sizeof(double);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(MM_E_HIP, std::string("no HIP device: ") + hipGetErrorString(e));
+  e = hipStreamCreateWithFlags(&E.cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(MM_E_HIP, hipGetErrorString(e));
+  const size_t hsz = E.prec == MM_F32 ? sizeof(HotPlan<float>) : sizeof(HotPlan<double>);
+  const size_t esz = E.prec == MM_F32 ? sizeof(Epi<float>) : sizeof(Epi<double>);
+  MMCHK(dev_alloc(&E.dhot, hsz * kMaxGroups));
+  MMCHK(dev_alloc(&E.depi, esz * kMaxGroups * kEpiSlots));
+  return MM_OK;
+}
+
+// Capacity of the per-instance arrays and of each group's spectral buffers.
+mm_status engine_reserve(Engine& E, const std::vector<int>& per_group) {
+  int total = 0, parts = 0;
+  for (size_t i = 0; i < per_group.size(); ++i) {
+    Group& G = E.groups[i];
+    const int n = per_group[i];
+    total += n;
+    parts = std::max(parts, 5 * n * eval_blocks_per_inst(G.g, G.tu));
+    if (n > G.cap && (E.terms & MM_DEMAG)) {
+      if (G.Sx) (void)hipFree(G.Sx);
+      if (G.Sy) (void)hipFree(G.Sy);
+      G.Sx = G.Sy = nullptr;
+      MMCHK(dev_alloc(&G.Sx, E.csz * G.g.sx * n));
+      if (G.g.nz > 1) MMCHK(dev_alloc(&G.Sy, E.csz * G.g.sy * n));
+      G.cap = n;
+      if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+    } else if (n > G.cap) {
+      G.cap = n;
+    }
+  }
+  if (total > E.inst_cap) {
+    if (E.prm) (void)hipFree(E.prm);
+    if (E.ctl) (void)hipFree(E.ctl);
+    if (E.e5) (void)hipFree(E.e5);
+    if (E.hctl) (void)hipHostFree(E.hctl);
+    if (E.he5) (void)hipHostFree(E.he5);
+    E.prm = nullptr; E.ctl = nullptr; E.e5 = nullptr; E.hctl = nullptr; E.he5 = nullptr;
+    MMCHK(dev_alloc((void**)&E.prm, sizeof(DevParams) * total));
+    MMCHK(dev_alloc((void**)&E.ctl, sizeof(DevCtl) * total));
+    MMCHK(dev_alloc((void**)&E.e5, sizeof(double) * 5 * total));
+    HIPCHK(hipHostMalloc((void**)&E.hctl, sizeof(DevCtl) * total));
+    HIPCHK(hipHostMalloc((void**)&E.he5, sizeof(double) * 5 * total));
+    std::memset(E.hctl, 0, sizeof(DevCtl) * total);
+    E.inst_cap = total;
+    if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+  }
+  if (parts > E.part_cap) {
+    if (E.partial) (void)hipFree(E.partial);
+    E.partial = nullptr;
+    MMCHK(dev_alloc((void**)&E.partial, sizeof(double) * parts));
+    E.part_cap = parts;
+  }
+  return MM_OK;
+}
+
+// Upload parameters (in group order) and remember whether demag is on.
+mm_status upload_params(Engine& E, const std::vector<const mm_params*>& q, const std::vector<int>& grp,
+                        hipStream_t s) {
+  std::vector<DevParams> d(q.size());
+  E.any_demag = false;
+  for (size_t b = 0; b < q.size(); ++b) {
+    d[b] = dev_params(*q[b], E.groups[grp[b]]);
+    E.any_demag = E.any_demag || (q[b]->terms & MM_DEMAG) != 0;
+  }
+  HIPCHK(hipMemcpyAsync(E.prm, d.data(), sizeof(DevParams) * d.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MM_OK;
+}
+
+// Host and device views of the groups for the given per-group instance counts
+// (instances of group i start at inst0[i] in the parameter / controller arrays).
+template <typename T>
+mm_status make_set(Engine& E, const std::vector<int>& nb, GroupSet<T>& gs, std::vector<int>& inst0,
+                   hipStream_t s) {
+  gs.n = (int)E.groups.size();
+  inst0.assign(gs.n, 0);
+  int acc = 0;
+  for (int i = 0; i < gs.n; ++i) {
+    Group& G = E.groups[i];
+    HotPlan<T>& h = gs.h[i];
+    std::memset(&h, 0, sizeof(h));
+    h.g = G.g;
+    h.tu = G.tu;
+    h.fp = (const FftPlan<T>*)G.fplans;
+    h.twz = (const Cx<T>*)G.twz;
+    h.post = (const Cx<T>*)G.post;
+    h.kt = (const T*)G.kt;
+    h.ncomp = G.ncomp;
+    h.batch = nb[i];
+    h.Sx = (Cx<T>*)G.Sx;
+    h.Sy = (Cx<T>*)G.Sy;
+    h.prm = E.prm + acc;
+    inst0[i] = acc;
+    acc += nb[i];
+  }
+  gs.dh = (const HotPlan<T>*)E.dhot;
+  HIPCHK(hipMemcpyAsync(E.dhot, gs.h, sizeof(HotPlan<T>) * gs.n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MM_OK;
+}
 
 template <typename T>
-Epi<T> epi_base(const mm_plan* p, int mode) {
-  Epi<T> e{};
+Epi<T>* epi_slot(Engine& E, int slot) {
+  return (Epi<T>*)E.depi + (size_t)slot * kMaxGroups;
+}
+
+template <typename T>
+mm_status upload_epis(Engine& E, int slot, const std::vector<Epi<T>>& ep, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(epi_slot<T>(E, slot), ep.data(), sizeof(Epi<T>) * ep.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MM_OK;
+}
+
+template <typename T>
+Epi<T> epi_base(const Group& G, int mode) {
+  Epi<T> e;
+  std::memset(&e, 0, sizeof(e));
   e.mode = mode;
-  e.inst_stride = 3 * p->g.N;
+  e.inst_stride = 3 * G.g.N;
   return e;
 }
 
-mm_status common_checks(mm_plan* p, const mm_params* q, int batch) {
-  if (!p) return fail(MM_E_ARG, "plan is null");
-  if (batch < 1 || batch > p->maxb) return fail(MM_E_ARG, "batch must be in [1, max_batch]");
-  return check_params(p, q, batch);
+bool demag_on(const Engine& E) { return (E.terms & MM_DEMAG) != 0 && E.any_demag; }
+
+// --- single-group calls (plans) ----------------------------------------------
+
+template <typename T>
+mm_status single_eval(mm_plan* p, int batch, const mm_params* q, const void* m, void* out, int mode,
+                      double* partial, hipStream_t s, hipEvent_t* ev = nullptr) {
+  Engine& E = p->e;
+  std::vector<const mm_params*> qv(batch);
+  std::vector<int> grp(batch, 0);
+  for (int b = 0; b < batch; ++b) qv[b] = &q[b];
+  MMCHK(upload_params(E, qv, grp, s));
+  GroupSet<T> gs;
+  std::vector<int> inst0;
+  MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
+  std::vector<Epi<T>> ep(1, epi_base<T>(E.groups[0], mode));
+  ep[0].in = (const T*)m;
+  ep[0].out = (T*)out;
+  ep[0].partial = partial;
+  MMCHK(upload_epis<T>(E, 0, ep, s));
+  HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 0), demag_on(E), s, ev));
+  return MM_OK;
 }
 
-int pass_count(const mm_plan* p) {
-  if (!((p->terms & MM_DEMAG) && p->any_demag)) return 1;
-  return p->g.nz == 1 ? 3 : 5;
+int pass_count(const Engine& E) {
+  if (!demag_on(E)) return 1;
+  return E.groups[0].g.nz == 1 ? 3 : 5;
 }
 
 template <typename T>
-mm_status profile_impl(mm_plan* p, int batch, const void* m, void* out, int reps, double* us, hipStream_t s) {
-  const int np = pass_count(p);
+mm_status profile_impl(mm_plan* p, const mm_params* q, int batch, const void* m, void* out, int reps, double* us,
+                       hipStream_t s) {
+  Engine& E = p->e;
+  // first call sets parameters and tables; then time `reps` evaluations
+  MMCHK(single_eval<T>(p, batch, q, m, out, MODE_RHS, nullptr, s));
+  const int np = pass_count(E);
   std::vector<hipEvent_t> ev((size_t)(np + 1) * reps);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  mm_status st = MM_OK;
-  Epi<T> e = epi_base<T>(p, MODE_RHS);
-  e.out = (T*)out;
-  for (int r = 0; r < reps && st == MM_OK; ++r) st = eval_call<T>(p, batch, m, e, s, ev.data() + (size_t)r * (np + 1));
+  GroupSet<T> gs;
+  std::vector<int> inst0;
+  mm_status st = make_set<T>(E, std::vector<int>{batch}, gs, inst0, s);
+  for (int r = 0; r < reps && st == MM_OK; ++r) {
+    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), demag_on(E), s, ev.data() + (size_t)r * (np + 1));
+    if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
+  }
   if (st == MM_OK) {
     hipError_t er = hipStreamSynchronize(s);
     if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
@@ -527,49 +702,107 @@ mm_status profile_impl(mm_plan* p, int batch, const void* m, void* out, int reps
   return st;
 }
 
-// --- Dormand-Prince ---------------------------------------------------------
 template <typename T>
-T* stage_buf(mm_plan* p, int idx) {  // 0: ms0, 1: ms1, 2..8: k1..k7
-  return (T*)p->stage + (size_t)idx * p->maxb * 3 * p->g.N;
-}
-
-template <typename T>
-mm_status ensure_stage(mm_plan* p) {
-  if (p->stage) return MM_OK;
-  HIPCHK(hipMalloc(&p->stage, sizeof(T) * 9 * (size_t)p->maxb * 3 * p->g.N));
-  return MM_OK;
-}
-
-template <typename T>
-mm_status enqueue_attempt(mm_plan* p, int batch, T* m, hipStream_t s) {
-  HIPCHK(launch_begin<T>(p->g, batch, m, stage_buf<T>(p, 0), stage_buf<T>(p, 1), stage_buf<T>(p, 2),
-                         stage_buf<T>(p, 8), kDP.a[2][0], p->ctl, s));
-  for (int st = 2; st <= 7; ++st) {
-    const int in = (st % 2 == 0) ? 0 : 1;  // ms0 feeds even stages, ms1 odd stages
-    Epi<T> e = epi_base<T>(p, st < 7 ? MODE_STAGE : MODE_ERROR);
-    e.out = stage_buf<T>(p, 2 + st - 1);
-    e.mbase = m;
-    e.msn = stage_buf<T>(p, 1 - in);
-    e.ctl = p->ctl;
-    for (int j = 0; j < st - 1; ++j) e.kprev[j] = stage_buf<T>(p, 2 + j);
-    e.nk = st;
-    for (int j = 0; j < st; ++j) e.coef[j] = st < 7 ? kDP.a[st + 1][j] : kDP.e[j];
-    MMCHK(eval_call<T>(p, batch, stage_buf<T>(p, in), e, s));
-  }
-  HIPCHK(launch_controller(p->ctl, batch, p->replay, s));
-  return MM_OK;
-}
-
-template <typename T>
-mm_status rk45_impl(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45_state* st, double t_end,
-                    long long max_steps, const double* replay_h, long long n_replay, bool single,
-                    hipStream_t s) {
-  MMCHK(ensure_stage<T>(p));
-  MMCHK(upload_params(p, q, batch, s));
-  T* m = (T*)mv;
-  bool need_k1 = false;
+mm_status energy_impl(mm_plan* p, const mm_params* q, int batch, const void* m, double* E_out, hipStream_t s) {
+  Engine& E = p->e;
+  MMCHK(single_eval<T>(p, batch, q, m, nullptr, MODE_ENERGY, E.partial, s));
+  const Group& G = E.groups[0];
+  HIPCHK(launch_energy_reduce(E.partial, batch, eval_blocks_per_inst(G.g, G.tu), E.e5, s));
+  HIPCHK(hipMemcpyAsync(E.he5, E.e5, sizeof(double) * 5 * batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   for (int b = 0; b < batch; ++b) {
-    const mm_rk45_state& r = st[b];
+    const double c = kMu0 * q[b].Ms * G.g.dV;
+    for (int k = 0; k < 5; ++k) E_out[5 * b + k] = -(k == 4 ? 1.0 : 0.5) * c * E.he5[5 * b + k];
+  }
+  return MM_OK;
+}
+
+// --- Dormand-Prince over every group -----------------------------------------
+
+template <typename T>
+T* stage_buf(const Group& G, int idx) {  // 0: ms0, 1: ms1, 2..8: k1..k7
+  return (T*)G.stage + (size_t)idx * G.stage_cap * 3 * G.g.N;
+}
+
+template <typename T>
+mm_status ensure_stage(Engine& E, Group& G, int n) {
+  if (G.stage && G.stage_cap >= n) return MM_OK;
+  if (G.stage) (void)hipFree(G.stage);
+  G.stage = nullptr;
+  MMCHK(dev_alloc(&G.stage, sizeof(T) * 9 * (size_t)n * 3 * G.g.N));
+  G.stage_cap = n;
+  if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+  return MM_OK;
+}
+
+// Epilogue tables of every slot for the groups' state arrays m[i] (device).
+template <typename T>
+mm_status upload_step_epis(Engine& E, const std::vector<T*>& m, const std::vector<int>& inst0, hipStream_t s) {
+  const int ng = (int)E.groups.size();
+  for (int slot = 1; slot < kEpiSlots; ++slot) {
+    std::vector<Epi<T>> ep;
+    for (int i = 0; i < ng; ++i) {
+      const Group& G = E.groups[i];
+      Epi<T> e = epi_base<T>(G, MODE_RHS);
+      e.ctl = E.ctl + inst0[i];
+      if (slot == 1) {  // first slope k1 = f(m)
+        e.mode = MODE_RHS;
+        e.in = m[i];
+        e.out = stage_buf<T>(G, 2);
+        e.ctl = nullptr;
+      } else if (slot < 8) {  // stage st evaluates its input and forms the next one
+        const int st = slot;
+        const int in = (st % 2 == 0) ? 0 : 1;  // ms0 feeds even stages, ms1 odd stages
+        e.mode = st < 7 ? MODE_STAGE : MODE_ERROR;
+        e.in = stage_buf<T>(G, in);
+        e.out = stage_buf<T>(G, 2 + st - 1);
+        e.mbase = m[i];
+        e.msn = stage_buf<T>(G, 1 - in);
+        for (int j = 0; j < st - 1; ++j) e.kprev[j] = stage_buf<T>(G, 2 + j);
+        e.nk = st;
+        for (int j = 0; j < st; ++j) e.coef[j] = st < 7 ? kDP.a[st + 1][j] : kDP.e[j];
+      } else {  // step begin
+        e.bm = m[i];
+        e.bms0 = stage_buf<T>(G, 0);
+        e.bms1 = stage_buf<T>(G, 1);
+        e.bk1 = stage_buf<T>(G, 2);
+        e.bk7 = stage_buf<T>(G, 8);
+        e.a21 = kDP.a[2][0];
+      }
+      ep.push_back(e);
+    }
+    MMCHK(upload_epis<T>(E, slot, ep, s));
+  }
+  return MM_OK;
+}
+
+template <typename T>
+mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStream_t s) {
+  HIPCHK(launch_begin<T>(gs, epi_slot<T>(E, 8), s));
+  for (int st = 2; st <= 7; ++st) HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, st), demag_on(E), s));
+  HIPCHK(launch_controller(E.ctl, n_total, E.replay, s));
+  return MM_OK;
+}
+
+// Integrate the instances of every group.  m[i]: contiguous state of group i's
+// nb[i] instances; q / st / t_end: per instance, in group order.
+template <typename T>
+mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& nb,
+                   const std::vector<const mm_params*>& q, std::vector<mm_rk45_state*>& st,
+                   const std::vector<double>& t_end, long long max_steps, const double* replay_h,
+                   long long n_replay, bool single, std::vector<int>& status, hipStream_t s) {
+  const int ng = (int)E.groups.size();
+  const int n_total = (int)q.size();
+  std::vector<int> grp;
+  for (int i = 0; i < ng; ++i) grp.insert(grp.end(), nb[i], i);
+  for (int i = 0; i < ng; ++i) MMCHK(ensure_stage<T>(E, E.groups[i], std::max(nb[i], 1)));
+  MMCHK(upload_params(E, q, grp, s));
+  GroupSet<T> gs;
+  std::vector<int> inst0;
+  MMCHK(make_set<T>(E, nb, gs, inst0, s));
+  bool need_k1 = false;
+  for (int b = 0; b < n_total; ++b) {
+    const mm_rk45_state& r = *st[b];
     if (!(r.rtol > 0) || !is_fin(r.rtol) || !(r.h > 0) || !(r.h_min > 0) || !(r.h_max >= r.h_min) ||
         !is_fin(r.t) || !is_fin(r.h) || !is_fin(r.h_max))
       return fail(MM_E_ARG, "invalid rk45 state (rtol, h, h_min, h_max)");
@@ -579,99 +812,90 @@ mm_status rk45_impl(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45
     if (n_replay < 1) return fail(MM_E_ARG, "n_replay must be >= 1");
     for (long long i = 0; i < n_replay; ++i)
       if (!(replay_h[i] > 0) || !is_fin(replay_h[i])) return fail(MM_E_ARG, "replay step sizes must be > 0");
-    if (n_replay > p->replay_cap) {
-      if (p->replay) (void)hipFree(p->replay);
-      p->replay = nullptr;
-      HIPCHK(hipMalloc(&p->replay, sizeof(double) * n_replay));
-      p->replay_cap = n_replay;
-      if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+    if (n_replay > E.replay_cap) {
+      if (E.replay) (void)hipFree(E.replay);
+      E.replay = nullptr;
+      MMCHK(dev_alloc((void**)&E.replay, sizeof(double) * n_replay));
+      E.replay_cap = n_replay;
+      if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
     }
-    HIPCHK(hipMemcpy(p->replay, replay_h, sizeof(double) * n_replay, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(E.replay, replay_h, sizeof(double) * n_replay, hipMemcpyHostToDevice));
   }
-  for (int b = 0; b < batch; ++b) {
-    const mm_rk45_state& r = st[b];
-    DevCtl& c = p->hctl[b];
+  for (int b = 0; b < n_total; ++b) {
+    const mm_rk45_state& r = *st[b];
+    DevCtl& c = E.hctl[b];
     std::memset(&c, 0, sizeof(c));
     c.t = r.t; c.h = r.h; c.rtol = r.rtol; c.h_min = r.h_min; c.h_max = r.h_max;
-    c.t_end = replay_h ? HUGE_VAL : t_end;
+    c.t_end = replay_h ? HUGE_VAL : t_end[b];
     c.n_accept = r.n_accept; c.n_reject = r.n_reject;
     c.max_attempt = max_steps;
     c.replay_n = replay_h ? n_replay : 0;
     if (replay_h) {
       c.h_att = replay_h[0];
     } else {
-      c.h_att = std::min(std::min(r.h, r.h_max), t_end - r.t);
-      if (!(t_end - r.t > r.h_min)) c.done = 1;  // arrived (a remainder below h_min counts as arrived)
+      c.h_att = std::min(std::min(r.h, r.h_max), t_end[b] - r.t);
+      if (!(t_end[b] - r.t > r.h_min)) c.done = 1;  // arrived (a remainder below h_min counts as arrived)
       else if (c.h_att < r.h_min) return fail(MM_E_STEP_UNDERFLOW, "initial step below h_min");
     }
   }
-  HIPCHK(hipMemcpyAsync(p->ctl, p->hctl, sizeof(DevCtl) * batch, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(E.ctl, E.hctl, sizeof(DevCtl) * n_total, hipMemcpyHostToDevice, s));
+  MMCHK(upload_step_epis<T>(E, m, inst0, s));
   long long extra_rhs = 0;
   if (need_k1) {
-    Epi<T> e = epi_base<T>(p, MODE_RHS);
-    e.out = stage_buf<T>(p, 2);
-    MMCHK(eval_call<T>(p, batch, m, e, s));
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 1), demag_on(E), s));
     extra_rhs = 1;
   }
-  const bool dbg = getenv("MMX_DEBUG_CTL") != nullptr;
-  auto dump = [&](const char* tag) {
-    std::vector<DevCtl> v(batch);
-    (void)hipMemcpyAsync(v.data(), p->ctl, sizeof(DevCtl) * batch, hipMemcpyDeviceToHost, s);
-    (void)hipStreamSynchronize(s);
-    fprintf(stderr, "[ctl %s] t=%g h=%g h_att=%g h_max=%g h_min=%g t_end=%g rtol=%g err=%g na=%lld nr=%lld done=%d st=%d\n",
-            tag, v[0].t, v[0].h, v[0].h_att, v[0].h_max, v[0].h_min, v[0].t_end, v[0].rtol, v[0].last_err,
-            v[0].n_accept, v[0].n_reject, v[0].done, v[0].status);
-  };
-  if (dbg) dump("upload");
   if (single) {
-    MMCHK(enqueue_attempt<T>(p, batch, m, s));
-    if (dbg) dump("attempt");
+    MMCHK(enqueue_attempt<T>(E, gs, n_total, s));
   } else {
     const int K = 8;  // attempts per graph launch between host polls
-    if (!p->gexec || p->g_m != mv || p->g_batch != batch) {
-      if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
-      HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    std::vector<const void*> key;
+    for (int i = 0; i < ng; ++i) {
+      key.push_back(m[i]);
+      key.push_back((const void*)(intptr_t)nb[i]);
+    }
+    key.push_back((const void*)(intptr_t)(demag_on(E) ? 1 : 0));
+    if (!E.gexec || E.g_key != key) {
+      if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+      HIPCHK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
       mm_status cs = MM_OK;
-      for (int k = 0; k < K && cs == MM_OK; ++k) cs = enqueue_attempt<T>(p, batch, m, p->cap);
+      for (int k = 0; k < K && cs == MM_OK; ++k) cs = enqueue_attempt<T>(E, gs, n_total, E.cap);
       hipGraph_t graph = nullptr;
-      hipError_t ee = hipStreamEndCapture(p->cap, &graph);
+      hipError_t ee = hipStreamEndCapture(E.cap, &graph);
       if (cs != MM_OK) { if (graph) (void)hipGraphDestroy(graph); return cs; }
       if (ee != hipSuccess) return fail(MM_E_HIP, std::string("capture: ") + hipGetErrorString(ee));
-      ee = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+      ee = hipGraphInstantiate(&E.gexec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
-      if (ee != hipSuccess) { p->gexec = nullptr; return fail(MM_E_HIP, std::string("instantiate: ") + hipGetErrorString(ee)); }
-      p->g_m = mv;
-      p->g_batch = batch;
-      p->g_steps = K;
+      if (ee != hipSuccess) { E.gexec = nullptr; return fail(MM_E_HIP, std::string("instantiate: ") + hipGetErrorString(ee)); }
+      E.g_key = key;
     }
     for (;;) {
-      HIPCHK(hipGraphLaunch(p->gexec, s));
-      HIPCHK(hipMemcpyAsync(p->hctl, p->ctl, sizeof(DevCtl) * batch, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipGraphLaunch(E.gexec, s));
+      HIPCHK(hipMemcpyAsync(E.hctl, E.ctl, sizeof(DevCtl) * n_total, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (dbg) dump("poll");
       bool all = true;
-      for (int b = 0; b < batch; ++b) all = all && p->hctl[b].done;
+      for (int b = 0; b < n_total; ++b) all = all && E.hctl[b].done;
       if (all) break;
     }
   }
   // finish: project the last accepted y5 and move k7 into k1
-  HIPCHK(launch_begin<T>(p->g, batch, m, stage_buf<T>(p, 0), stage_buf<T>(p, 1), stage_buf<T>(p, 2),
-                         stage_buf<T>(p, 8), kDP.a[2][0], p->ctl, s));
-  HIPCHK(hipMemcpyAsync(p->hctl, p->ctl, sizeof(DevCtl) * batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_begin<T>(gs, epi_slot<T>(E, 8), s));
+  HIPCHK(hipMemcpyAsync(E.hctl, E.ctl, sizeof(DevCtl) * n_total, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  status.assign(n_total, MM_OK);
   mm_status worst = MM_OK;
-  for (int b = 0; b < batch; ++b) {
-    const DevCtl& c = p->hctl[b];
-    mm_rk45_state& r = st[b];
+  for (int b = 0; b < n_total; ++b) {
+    const DevCtl& c = E.hctl[b];
+    mm_rk45_state& r = *st[b];
     r.t = c.t;
     r.h = c.h;
-    const long long attempts = c.n_attempt;
-    r.n_rhs += 6 * attempts + extra_rhs;
+    r.n_rhs += 6 * c.n_attempt + extra_rhs;
     r.n_accept = c.n_accept;
     r.n_reject = c.n_reject;
     r.last_err = c.last_err;
     r.last_accepted = c.last_accepted;
     r.fsal_valid = 1;
+    status[b] = c.status;
     if (c.status != MM_OK && worst == MM_OK) worst = (mm_status)c.status;
   }
   if (worst != MM_OK) return fail(worst, "integration stopped: " + std::string(mm_status_string(worst)));
@@ -679,60 +903,119 @@ mm_status rk45_impl(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45
 }
 
 template <typename T>
-mm_status energy_impl(mm_plan* p, const mm_params* q, int batch, const void* m, double* E, hipStream_t s) {
-  MMCHK(upload_params(p, q, batch, s));
-  Epi<T> e = epi_base<T>(p, MODE_ENERGY);
-  e.partial = p->partial;
-  MMCHK(eval_call<T>(p, batch, m, e, s));
-  HIPCHK(launch_energy_reduce(p->partial, batch, eval_blocks_per_inst(p->g, p->tu), p->e5, s));
-  HIPCHK(hipMemcpyAsync(p->he5, p->e5, sizeof(double) * 5 * batch, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+mm_status plan_rk45(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45_state* st, double t_end,
+                    long long max_steps, const double* replay_h, long long n_replay, bool single, hipStream_t s) {
+  std::vector<const mm_params*> qv(batch);
+  std::vector<mm_rk45_state*> sv(batch);
   for (int b = 0; b < batch; ++b) {
-    const double c = kMu0 * q[b].Ms * p->g.dV;
-    for (int k = 0; k < 5; ++k) E[5 * b + k] = -(k == 4 ? 1.0 : 0.5) * c * p->he5[5 * b + k];
+    qv[b] = &q[b];
+    sv[b] = &st[b];
   }
-  return MM_OK;
+  std::vector<int> status;
+  return run_core<T>(p->e, std::vector<T*>{(T*)mv}, std::vector<int>{batch}, qv, sv,
+                     std::vector<double>(batch, t_end), max_steps, replay_h, n_replay, single, status, s);
+}
+
+template <typename T>
+mm_status batch_run(mm_batch* bt, mm_instance* inst, int n, long long max_steps, hipStream_t s) {
+  Engine& E = bt->e;
+  const int ng = (int)E.groups.size();
+  std::vector<int> nb(ng, 0);
+  std::vector<std::vector<int>> members(ng);
+  for (int i = 0; i < n; ++i) members[inst[i].mesh_id].push_back(i);
+  for (int g = 0; g < ng; ++g) nb[g] = (int)members[g].size();
+  MMCHK(engine_reserve(E, nb));
+  // gather every group's instances into its contiguous state buffer
+  std::vector<T*> m(ng, nullptr);
+  for (int g = 0; g < ng; ++g) {
+    Group& G = E.groups[g];
+    const size_t S = 3 * (size_t)G.g.N;
+    if (nb[g] > G.mbuf_cap) {
+      if (G.mbuf) (void)hipFree(G.mbuf);
+      G.mbuf = nullptr;
+      MMCHK(dev_alloc(&G.mbuf, sizeof(T) * S * nb[g]));
+      G.mbuf_cap = nb[g];
+      if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+    }
+    m[g] = (T*)G.mbuf;
+    for (int k = 0; k < nb[g]; ++k)
+      HIPCHK(hipMemcpyAsync(m[g] + k * S, inst[members[g][k]].m, sizeof(T) * S, hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<const mm_params*> q;
+  std::vector<mm_rk45_state*> st;
+  std::vector<double> t_end;
+  std::vector<int> order;
+  for (int g = 0; g < ng; ++g)
+    for (int i : members[g]) {
+      q.push_back(&inst[i].p);
+      st.push_back(&inst[i].st);
+      t_end.push_back(inst[i].t_end);
+      order.push_back(i);
+    }
+  std::vector<int> status;
+  mm_status r = run_core<T>(E, m, nb, q, st, t_end, max_steps, nullptr, 0, false, status, s);
+  // scatter back (also after an integration error: m holds the last accepted state)
+  for (int g = 0; g < ng; ++g) {
+    const size_t S = 3 * (size_t)E.groups[g].g.N;
+    for (int k = 0; k < nb[g]; ++k)
+      HIPCHK(hipMemcpyAsync(inst[members[g][k]].m, m[g] + k * S, sizeof(T) * S, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  for (size_t j = 0; j < order.size(); ++j) inst[order[j]].status = j < status.size() ? status[j] : (int)r;
+  return r;
 }
 
 template <typename T>
 mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, double k, double h, long long n_iter,
                    double* E_out, hipStream_t s) {
-  const size_t S = 3 * (size_t)p->g.N;
-  if (!p->nebH) {
-    HIPCHK(hipMalloc(&p->nebH, sizeof(T) * S * p->maxb));
-    HIPCHK(hipMalloc(&p->nebB, sizeof(T) * S * p->maxb));
-    const long long bpi = (p->g.N + 255) / 256;
-    HIPCHK(hipMalloc(&p->nebS, sizeof(double) * 3 * p->maxb));
-    HIPCHK(hipMalloc(&p->nebP, sizeof(double) * 3 * p->maxb * bpi));
+  Engine& E = p->e;
+  const Group& G = E.groups[0];
+  const size_t S = 3 * (size_t)G.g.N;
+  if (E.neb_cap < n_img) {
+    void* bufs[] = {E.nebH, E.nebB, E.nebS, E.nebP};
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
+    const long long bpi = (G.g.N + 255) / 256;
+    MMCHK(dev_alloc(&E.nebH, sizeof(T) * S * n_img));
+    MMCHK(dev_alloc(&E.nebB, sizeof(T) * S * n_img));
+    MMCHK(dev_alloc((void**)&E.nebS, sizeof(double) * 3 * n_img));
+    MMCHK(dev_alloc((void**)&E.nebP, sizeof(double) * 3 * n_img * bpi));
+    E.neb_cap = n_img;
   }
-  std::vector<mm_params> qs(n_img, *q);
-  MMCHK(upload_params(p, qs.data(), n_img, s));
+  std::vector<const mm_params*> qv(n_img, q);
+  MMCHK(upload_params(E, qv, std::vector<int>(n_img, 0), s));
+  GroupSet<T> gs;
+  std::vector<int> inst0;
+  MMCHK(make_set<T>(E, std::vector<int>{n_img}, gs, inst0, s));
   T* A = (T*)images;
-  T* B = (T*)p->nebB;
+  T* B = (T*)E.nebB;
+  // slot 2 evaluates A, slot 3 evaluates B (fields and energy partials)
+  for (int slot = 2; slot <= 3; ++slot) {
+    std::vector<Epi<T>> ep(1, epi_base<T>(G, MODE_FIELD_ENERGY));
+    ep[0].in = slot == 2 ? A : B;
+    ep[0].out = (T*)E.nebH;
+    ep[0].partial = E.partial;
+    MMCHK(upload_epis<T>(E, slot, ep, s));
+  }
   HIPCHK(hipMemcpyAsync(B, A, sizeof(T) * S * n_img, hipMemcpyDeviceToDevice, s));
-  const double cq = -0.5 * kMu0 * q->Ms * p->g.dV, cz = -kMu0 * q->Ms * p->g.dV;
+  const double cq = -0.5 * kMu0 * q->Ms * G.g.dV, cz = -kMu0 * q->Ms * G.g.dV;
   const double hg2 = h * (-q->alpha * q->gamma / (1 + q->alpha * q->alpha));
-  auto iteration = [&](T* cur, T* nxt) -> mm_status {
-    Epi<T> e = epi_base<T>(p, MODE_FIELD_ENERGY);
-    e.out = (T*)p->nebH;
-    e.partial = p->partial;
-    MMCHK(eval_call<T>(p, n_img, cur, e, s));
-    HIPCHK(launch_energy_reduce(p->partial, n_img, eval_blocks_per_inst(p->g, p->tu), p->e5, s));
-    HIPCHK(launch_neb<T>(p->g, n_img, cur, nxt, (const T*)p->nebH, p->e5, cq, cz, p->nebS, p->nebP, k, hg2, 0, s));
-    HIPCHK(launch_neb<T>(p->g, n_img, cur, nxt, (const T*)p->nebH, p->e5, cq, cz, p->nebS, p->nebP, k, hg2, 1, s));
+  const int bpi = eval_blocks_per_inst(G.g, G.tu);
+  auto iteration = [&](T* cur, T* nxt, hipStream_t ss) -> mm_status {
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, cur == A ? 2 : 3), demag_on(E), ss));
+    HIPCHK(launch_energy_reduce(E.partial, n_img, bpi, E.e5, ss));
+    HIPCHK(launch_neb<T>(G.g, n_img, cur, nxt, (const T*)E.nebH, E.e5, cq, cz, E.nebS, E.nebP, k, hg2, 0, ss));
+    HIPCHK(launch_neb<T>(G.g, n_img, cur, nxt, (const T*)E.nebH, E.e5, cq, cz, E.nebS, E.nebP, k, hg2, 1, ss));
     return MM_OK;
   };
   // two iterations per captured graph (A -> B -> A)
   hipGraphExec_t ge = nullptr;
   if (n_iter >= 2) {
-    HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-    hipStream_t keep = s;
-    s = p->cap;
-    mm_status cs = iteration(A, B);
-    if (cs == MM_OK) cs = iteration(B, A);
-    s = keep;
+    HIPCHK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
+    mm_status cs = iteration(A, B, E.cap);
+    if (cs == MM_OK) cs = iteration(B, A, E.cap);
     hipGraph_t graph = nullptr;
-    hipError_t ee = hipStreamEndCapture(p->cap, &graph);
+    hipError_t ee = hipStreamEndCapture(E.cap, &graph);
     if (cs != MM_OK) { if (graph) (void)hipGraphDestroy(graph); return cs; }
     if (ee != hipSuccess) return fail(MM_E_HIP, std::string("capture: ") + hipGetErrorString(ee));
     ee = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
@@ -746,7 +1029,7 @@ mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, doub
     if (ee != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(ee));
   }
   if (st == MM_OK && it < n_iter) {
-    st = iteration(A, B);
+    st = iteration(A, B, s);
     if (st == MM_OK) {
       hipError_t ee = hipMemcpyAsync(A, B, sizeof(T) * S * n_img, hipMemcpyDeviceToDevice, s);
       if (ee != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(ee));
@@ -754,14 +1037,20 @@ mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, doub
   }
   if (ge) (void)hipGraphExecDestroy(ge);
   if (st != MM_OK) return st;
-  HIPCHK(hipMemcpyAsync(p->he5, p->e5, sizeof(double) * 5 * n_img, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(E.he5, E.e5, sizeof(double) * 5 * n_img, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (E_out)
     for (int n = 0; n < n_img; ++n) {
-      const double* v = p->he5 + 5 * n;
+      const double* v = E.he5 + 5 * n;
       E_out[n] = cq * (v[0] + v[1] + v[2] + v[3]) + cz * v[4];
     }
   return MM_OK;
+}
+
+mm_status plan_checks(mm_plan* p, const mm_params* q, int batch) {
+  if (!p) return fail(MM_E_ARG, "plan is null");
+  if (batch < 1 || batch > p->maxb) return fail(MM_E_ARG, "batch must be in [1, max_batch]");
+  return check_params(p->e, q, batch);
 }
 
 }  // namespace
@@ -794,59 +1083,18 @@ mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec, 
   if (max_batch < 1) return fail(MM_E_ARG, "max_batch must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
   mm_plan* p = new mm_plan();
-  p->mesh = *mesh;
-  p->prec = prec;
-  p->terms = terms;
   p->maxb = max_batch;
-  p->ncomp = mesh->nz == 1 ? 4 : 6;
-  p->csz = prec == MM_F32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
-  p->rsz = prec == MM_F32 ? sizeof(float) : sizeof(double);
-  Geo& g = p->g;
-  g.nx = mesh->nx; g.ny = mesh->ny; g.nz = mesh->nz;
-  g.Px = pick_padded(g.nx, true);
-  g.Py = pick_padded(g.ny, false);
-  g.Pz = pick_padded(g.nz, false);
-  g.Lx = g.Px / 2;
-  g.Xp = g.Lx + 1;
-  g.Ky = g.Py / 2 + 1;
-  g.Kz = g.Pz / 2 + 1;
-  g.N = (long long)g.nx * g.ny * g.nz;
-  g.sx = 3LL * g.nz * g.Xp * g.ny;
-  g.sy = 3LL * g.nz * g.Xp * g.Py;
-  g.dV = mesh->dx * mesh->dy * mesh->dz;
-  mm_status st = choose_tuning(p);
-  if (st != MM_OK) { free_plan(p); return st; }
-  auto alloc = [&](void** d, size_t bytes) -> mm_status {
-    hipError_t e = hipMalloc(d, std::max<size_t>(bytes, 16));
-    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MM_E_NOMEM : MM_E_HIP, hipGetErrorString(e));
-    return MM_OK;
-  };
-  do {
-    hipError_t e = hipGetDevice(&p->devid);
-    if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("no HIP device: ") + hipGetErrorString(e)); break; }
-    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
-    if (e != hipSuccess) { st = fail(MM_E_HIP, hipGetErrorString(e)); break; }
-    const int bpi = eval_blocks_per_inst(g, p->tu);
-    if ((st = alloc((void**)&p->prm, sizeof(DevParams) * max_batch)) != MM_OK) break;
-    if ((st = alloc((void**)&p->ctl, sizeof(DevCtl) * max_batch)) != MM_OK) break;
-    if ((st = alloc((void**)&p->partial, sizeof(double) * 5 * (size_t)bpi * max_batch)) != MM_OK) break;
-    if ((st = alloc((void**)&p->e5, sizeof(double) * 5 * max_batch)) != MM_OK) break;
-    e = hipHostMalloc((void**)&p->hctl, sizeof(DevCtl) * max_batch);
-    if (e != hipSuccess) { st = fail(MM_E_NOMEM, "pinned host buffer"); break; }
-    e = hipHostMalloc((void**)&p->he5, sizeof(double) * 5 * max_batch);
-    if (e != hipSuccess) { st = fail(MM_E_NOMEM, "pinned host buffer"); break; }
-    std::memset(p->hctl, 0, sizeof(DevCtl) * max_batch);
-    if (terms & MM_DEMAG) {
-      if ((st = alloc(&p->Sx, p->csz * g.sx * max_batch)) != MM_OK) break;
-      if (g.nz > 1 && (st = alloc(&p->Sy, p->csz * g.sy * max_batch)) != MM_OK) break;
-      if ((st = alloc(&p->kt, p->rsz * p->ncomp * (size_t)g.Kz * g.Xp * g.Ky)) != MM_OK) break;
-      st = prec == MM_F32 ? upload_tables<float>(p) : upload_tables<double>(p);
-      if (st != MM_OK) break;
-      st = prec == MM_F32 ? build_spectrum<float>(p, s) : build_spectrum<double>(p, s);
-      if (st != MM_OK) break;
-    }
-  } while (false);
-  if (st != MM_OK) { free_plan(p); return st; }
+  mm_status st = engine_init(p->e, prec, terms);
+  if (st == MM_OK) {
+    p->e.groups.emplace_back();
+    st = make_group(p->e, *mesh, s, p->e.groups[0]);
+  }
+  if (st == MM_OK) st = engine_reserve(p->e, std::vector<int>{max_batch});
+  if (st != MM_OK) {
+    free_engine(p->e);
+    delete p;
+    return st;
+  }
   *out = p;
   return MM_OK;
 }
@@ -854,13 +1102,15 @@ mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec, 
 mm_status mm_plan_destroy(mm_plan* plan) {
   if (!plan) return fail(MM_E_ARG, "plan is null");
   (void)hipDeviceSynchronize();
-  free_plan(plan);
+  free_engine(plan->e);
+  delete plan;
   return MM_OK;
 }
 
 mm_status mm_plan_padded(const mm_plan* p, int32_t* Px, int32_t* Py, int32_t* Pz) {
   if (!p || !Px || !Py || !Pz) return fail(MM_E_ARG, "null argument");
-  *Px = p->g.Px; *Py = p->g.Py; *Pz = p->g.Pz;
+  const Geo& g = p->e.groups[0].g;
+  *Px = g.Px; *Py = g.Py; *Pz = g.Pz;
   return MM_OK;
 }
 
@@ -880,87 +1130,119 @@ mm_status mm_demag_tensor(const mm_mesh* mesh, const int32_t* disp, int64_t n, d
 
 mm_status mm_effective_field(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* H,
                              void* hip_stream) {
-  MMCHK(common_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch));
   if (!m || !H) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
-  MMCHK(upload_params(p, q, batch, s));
-  if (p->prec == MM_F32) {
-    Epi<float> e = epi_base<float>(p, MODE_FIELD);
-    e.out = (float*)H;
-    return eval_call<float>(p, batch, m, e, s);
-  }
-  Epi<double> e = epi_base<double>(p, MODE_FIELD);
-  e.out = (double*)H;
-  return eval_call<double>(p, batch, m, e, s);
+  return p->e.prec == MM_F32 ? single_eval<float>(p, batch, q, m, H, MODE_FIELD, nullptr, s)
+                             : single_eval<double>(p, batch, q, m, H, MODE_FIELD, nullptr, s);
 }
 
 mm_status mm_llg_rhs(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* dmdt, void* hip_stream) {
-  MMCHK(common_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch));
   if (!m || !dmdt) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
-  MMCHK(upload_params(p, q, batch, s));
-  if (p->prec == MM_F32) {
-    Epi<float> e = epi_base<float>(p, MODE_RHS);
-    e.out = (float*)dmdt;
-    return eval_call<float>(p, batch, m, e, s);
-  }
-  Epi<double> e = epi_base<double>(p, MODE_RHS);
-  e.out = (double*)dmdt;
-  return eval_call<double>(p, batch, m, e, s);
+  return p->e.prec == MM_F32 ? single_eval<float>(p, batch, q, m, dmdt, MODE_RHS, nullptr, s)
+                             : single_eval<double>(p, batch, q, m, dmdt, MODE_RHS, nullptr, s);
 }
 
 mm_status mm_energy(mm_plan* p, const mm_params* q, int32_t batch, const void* m, double* E_out, void* hip_stream) {
-  MMCHK(common_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch));
   if (!m || !E_out) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
-  return p->prec == MM_F32 ? energy_impl<float>(p, q, batch, m, E_out, s)
-                           : energy_impl<double>(p, q, batch, m, E_out, s);
+  return p->e.prec == MM_F32 ? energy_impl<float>(p, q, batch, m, E_out, s)
+                             : energy_impl<double>(p, q, batch, m, E_out, s);
 }
 
 mm_status mm_rk45_step(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm_rk45_state* st,
                        void* hip_stream) {
-  MMCHK(common_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch));
   if (!m || !st) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
-  const long long cap = 1;
-  return p->prec == MM_F32 ? rk45_impl<float>(p, q, batch, m, st, HUGE_VAL, cap + 1, nullptr, 0, true, s)
-                           : rk45_impl<double>(p, q, batch, m, st, HUGE_VAL, cap + 1, nullptr, 0, true, s);
+  return p->e.prec == MM_F32 ? plan_rk45<float>(p, q, batch, m, st, HUGE_VAL, 2, nullptr, 0, true, s)
+                             : plan_rk45<double>(p, q, batch, m, st, HUGE_VAL, 2, nullptr, 0, true, s);
 }
 
 mm_status mm_rk45_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm_rk45_state* st, double t_end,
                       int64_t max_steps, const double* replay_h, int64_t n_replay, void* hip_stream) {
-  MMCHK(common_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch));
   if (!m || !st) return fail(MM_E_ARG, "null array");
   if (max_steps < 1) return fail(MM_E_ARG, "max_steps must be >= 1");
   if (!replay_h && !is_fin(t_end)) return fail(MM_E_ARG, "t_end must be finite");
   hipStream_t s = (hipStream_t)hip_stream;
-  return p->prec == MM_F32
-             ? rk45_impl<float>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s)
-             : rk45_impl<double>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s);
+  return p->e.prec == MM_F32
+             ? plan_rk45<float>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s)
+             : plan_rk45<double>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s);
 }
 
 mm_status mm_profile_passes(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work, int32_t reps,
                             double* us_out, int32_t* n_pass, void* hip_stream) {
-  MMCHK(common_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch));
   if (!m || !work || !us_out || !n_pass) return fail(MM_E_ARG, "null argument");
   if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
-  MMCHK(upload_params(p, q, batch, s));
-  *n_pass = pass_count(p);
-  return p->prec == MM_F32 ? profile_impl<float>(p, batch, m, work, reps, us_out, s)
-                           : profile_impl<double>(p, batch, m, work, reps, us_out, s);
+  mm_status st = p->e.prec == MM_F32 ? profile_impl<float>(p, q, batch, m, work, reps, us_out, s)
+                                     : profile_impl<double>(p, q, batch, m, work, reps, us_out, s);
+  *n_pass = pass_count(p->e);
+  return st;
 }
 
 mm_status mm_neb_run(mm_plan* p, const mm_params* q, void* images, int32_t n_img, double k_spring, double h,
                      int64_t n_iter, double* E_out, void* hip_stream) {
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (n_img < 3 || n_img > p->maxb) return fail(MM_E_ARG, "n_img must be in [3, max_batch]");
-  MMCHK(check_params(p, q, 1));
+  MMCHK(check_params(p->e, q, 1));
   if (!images) return fail(MM_E_ARG, "images is null");
   if (!is_fin(k_spring) || !is_fin(h) || h <= 0 || n_iter < 1) return fail(MM_E_ARG, "invalid k_spring, h or n_iter");
   hipStream_t s = (hipStream_t)hip_stream;
-  return p->prec == MM_F32 ? neb_impl<float>(p, q, images, n_img, k_spring, h, n_iter, E_out, s)
-                           : neb_impl<double>(p, q, images, n_img, k_spring, h, n_iter, E_out, s);
+  return p->e.prec == MM_F32 ? neb_impl<float>(p, q, images, n_img, k_spring, h, n_iter, E_out, s)
+                             : neb_impl<double>(p, q, images, n_img, k_spring, h, n_iter, E_out, s);
+}
+
+mm_status mm_batch_create(mm_batch** out, const mm_mesh* meshes, int32_t n_meshes, mm_precision prec,
+                          uint32_t terms, void* hip_stream) {
+  if (!out) return fail(MM_E_ARG, "out is null");
+  *out = nullptr;
+  if (!meshes || n_meshes < 1 || n_meshes > kMaxGroups)
+    return fail(MM_E_ARG, "need 1 to 16 meshes");
+  for (int i = 0; i < n_meshes; ++i) MMCHK(check_mesh(&meshes[i]));
+  if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
+  if (terms & ~MM_ALL_TERMS) return fail(MM_E_ARG, "unknown term bits");
+  hipStream_t s = (hipStream_t)hip_stream;
+  mm_batch* b = new mm_batch();
+  mm_status st = engine_init(b->e, prec, terms);
+  b->e.groups.resize(n_meshes);
+  for (int i = 0; i < n_meshes && st == MM_OK; ++i) st = make_group(b->e, meshes[i], s, b->e.groups[i]);
+  if (st != MM_OK) {
+    free_engine(b->e);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return MM_OK;
+}
+
+mm_status mm_batch_run(mm_batch* bt, mm_instance* inst, int32_t n_inst, int64_t max_steps, void* hip_stream) {
+  if (!bt || !inst) return fail(MM_E_ARG, "null argument");
+  if (n_inst < 1) return fail(MM_E_ARG, "n_inst must be >= 1");
+  if (max_steps < 1) return fail(MM_E_ARG, "max_steps must be >= 1");
+  const int ng = (int)bt->e.groups.size();
+  for (int i = 0; i < n_inst; ++i) {
+    if (inst[i].mesh_id < 0 || inst[i].mesh_id >= ng) return fail(MM_E_ARG, "mesh_id out of range");
+    if (!inst[i].m) return fail(MM_E_ARG, "instance m is null");
+    if (!is_fin(inst[i].t_end)) return fail(MM_E_ARG, "t_end must be finite");
+    MMCHK(check_params(bt->e, &inst[i].p, 1));
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  return bt->e.prec == MM_F32 ? batch_run<float>(bt, inst, n_inst, max_steps, s)
+                              : batch_run<double>(bt, inst, n_inst, max_steps, s);
+}
+
+mm_status mm_batch_destroy(mm_batch* bt) {
+  if (!bt) return fail(MM_E_ARG, "batch is null");
+  (void)hipDeviceSynchronize();
+  free_engine(bt->e);
+  delete bt;
+  return MM_OK;
 }
 
 }  // extern "C"

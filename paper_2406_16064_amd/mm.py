@@ -44,6 +44,11 @@ class RK45State(ctypes.Structure):
                 ("fsal_valid", ctypes.c_int32)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("mesh_id", ctypes.c_int32), ("p", Params), ("m", ctypes.c_void_p), ("st", RK45State),
+                ("t_end", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
 _vp, _i32, _i64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _P = ctypes.POINTER
 _sigs = {
@@ -58,6 +63,9 @@ _sigs = {
     "mm_rk45_run": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _i64, _vp],
     "mm_neb_run": [_vp, _P(Params), _vp, _i32, _dbl, _dbl, _i64, _P(_dbl), _vp],
     "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
+    "mm_batch_create": [_P(_vp), _P(Mesh), _i32, ctypes.c_int, ctypes.c_uint32, _vp],
+    "mm_batch_run": [_vp, _P(Instance), _i32, _i64, _vp],
+    "mm_batch_destroy": [_vp],
 }
 for _n, _a in _sigs.items():
     _f = getattr(_lib, _n)
@@ -216,6 +224,44 @@ class Plan:
     def close(self):
         if self._h:
             _lib.mm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Instances of up to 16 different meshes advanced together (mm_batch_*)."""
+
+    def __init__(self, meshes, precision="f32", terms=ALL_TERMS, stream=None):
+        self.meshes = [tuple(msh) for msh in meshes]
+        arr = (Mesh * len(meshes))(*[Mesh(*msh) for msh in meshes])
+        self.prec = MM_F32 if precision in ("f32", MM_F32) else MM_F64
+        self._h = ctypes.c_void_p()
+        _check(_lib.mm_batch_create(ctypes.byref(self._h), arr, len(meshes), self.prec, terms, _stream(stream)),
+               "mm_batch_create")
+
+    def run(self, instances, max_steps=10 ** 9, stream=None, check=True):
+        """instances: list of dicts with mesh_id, params (Params), m (device tensor), t_end
+        and optional state (RK45State).  Returns (status, list of (state, status))."""
+        arr = (Instance * len(instances))()
+        for i, d in enumerate(instances):
+            arr[i].mesh_id = d["mesh_id"]
+            arr[i].p = d["params"]
+            arr[i].m = _ptr(d["m"])
+            arr[i].st = d.get("state") or new_states(1, rtol=d.get("rtol", 1e-6))[0]
+            arr[i].t_end = d["t_end"]
+        st = _lib.mm_batch_run(self._h, arr, len(instances), max_steps, _stream(stream))
+        if check:
+            _check(st, "mm_batch_run")
+        return st, [(arr[i].st, arr[i].status) for i in range(len(instances))]
+
+    def close(self):
+        if self._h:
+            _lib.mm_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -255,3 +255,58 @@ def test_neb_iterations(mm, prec):
     for i in range(6):
         assert np.max(np.linalg.norm(out[i] - imgs[i], axis=0)) <= tol, i
     np.testing.assert_allclose(Eg, E, rtol=1e-9 if prec == "f64" else 1e-4)
+
+
+# ----------------------------------------------------------------------------- uneven batch
+
+BATCH_MESHES = [(32, 32, 1, 2e-9, 2e-9, 2e-9), (40, 24, 2, 2e-9, 2e-9, 2e-9), (24, 24, 1, 2e-9, 2e-9, 2e-9)]
+
+
+def _sweep_like(i):
+    rng = np.random.Generator(np.random.PCG64(900 + i))
+    d = rng.standard_normal(3)
+    d /= np.linalg.norm(d)
+    return dict(Ms=rng.uniform(4e5, 1.2e6), A=rng.uniform(5e-12, 2e-11), D=rng.uniform(0, 4e-3),
+                Ku=rng.uniform(0, 1e6), u=(0, 0, 1), H=tuple(rng.uniform(0, 3e5) * d),
+                alpha=rng.uniform(0.01, 0.5))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_uneven_batch_matches_one_by_one(mm, prec):
+    """Instances of three meshes in one batched run equal their one-by-one plan runs."""
+    mesh_of = [0, 1, 2, 1, 0, 2, 1]
+    pars = [gpu_params(mm, _sweep_like(i), mm.ALL_TERMS) for i in range(len(mesh_of))]
+    m0 = [representable(_rand_m(BATCH_MESHES[k], 40 + i), DT[prec]) for i, k in enumerate(mesh_of)]
+    t_end = [2e-12 * (1 + i % 3) for i in range(len(mesh_of))]
+    batch = mm.Batch(BATCH_MESHES, prec, terms=mm.ALL_TERMS)
+    devs = [to_dev(m, DT[prec]) for m in m0]
+    insts = [dict(mesh_id=k, params=pars[i], m=devs[i], t_end=t_end[i]) for i, k in enumerate(mesh_of)]
+    st, res = batch.run(insts)
+    plans = [mm.Plan(msh, prec, terms=mm.ALL_TERMS) for msh in BATCH_MESHES]
+    for i, k in enumerate(mesh_of):
+        md = to_dev(m0[i], DT[prec])
+        s1 = mm.new_states(1, rtol=1e-6)
+        plans[k].rk45_run(pars[i], md, s1, t_end=t_end[i])
+        bst, bstatus = res[i]
+        assert bstatus == mm.MM_OK
+        assert bst.n_accept == s1[0].n_accept and bst.n_reject == s1[0].n_reject
+        assert bst.t == s1[0].t == t_end[i]
+        assert np.array_equal(devs[i].cpu().numpy(), md.cpu().numpy()), i
+
+
+def test_uneven_batch_fp64_against_oracle(mm):
+    mesh_of = [0, 1]
+    pars = [_sweep_like(10 + i) for i in range(2)]
+    m0 = [_rand_m(BATCH_MESHES[k], 60 + i) for i, k in enumerate(mesh_of)]
+    batch = mm.Batch(BATCH_MESHES[:2], "f64", terms=mm.ALL_TERMS)
+    devs = [to_dev(m, torch.float64) for m in m0]
+    insts = [dict(mesh_id=k, params=gpu_params(mm, pars[i], mm.ALL_TERMS), m=devs[i], t_end=3e-12)
+             for i, k in enumerate(mesh_of)]
+    batch.run(insts)
+    for i, k in enumerate(mesh_of):
+        mesh = BATCH_MESHES[k]
+        op = oracle_params(pars[i], F.ALL_TERMS)
+        f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+        ost = dp45.State(rtol=1e-6)
+        mo = dp45.run(f, m0[i].copy(), ost, t_end=3e-12)
+        assert np.max(np.abs(devs[i].cpu().numpy() - mo)) <= 1e-9
