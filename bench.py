@@ -110,6 +110,87 @@ def run_workload(mm, inputs, torch, idx, prec, steps, warmup, mesh=None):
     return out, plan, params, m, mesh
 
 
+def sweep_bench(mm, inputs, torch, n_inst=256, steps=16, warmup=8):
+    """Parameter sweep of n_inst instances of uneven meshes: one batched run (one
+    launch per pass across all meshes) against the same instances run one by one
+    through one plan per mesh.  Both time `steps` adaptive attempts per instance."""
+    w = inputs.workload(4)
+    insts = [inputs.sweep_instance(i) for i in range(n_inst)]
+    meshes = sorted({tuple(x["mesh"]) for x in insts})
+    mid = {msh: i for i, msh in enumerate(meshes)}
+    params = [mm.make_params(terms=w["terms"], **x["params"]) for x in insts]
+    cells = [x["mesh"][0] * x["mesh"][1] * x["mesh"][2] for x in insts]
+    batch = mm.Batch(meshes, "f32", terms=w["terms"])
+    devs = [torch.tensor(x["m"], dtype=torch.float32, device="cuda") for x in insts]
+    states = [mm.new_states(1, rtol=w["rtol"])[0] for _ in insts]
+
+    def one_batched(k):
+        desc = [dict(mesh_id=mid[tuple(x["mesh"])], params=params[i], m=devs[i], t_end=w["t_end"],
+                     state=states[i]) for i, x in enumerate(insts)]
+        _, res = batch.run(desc, max_steps=k, check=False)
+        for i, (st, status) in enumerate(res):
+            states[i] = st
+            if status not in (mm.MM_OK, mm.MM_E_MAXSTEPS):
+                raise RuntimeError("sweep instance %d failed: %s" % (i, mm.status_string(status)))
+
+    one_batched(warmup)
+    n0 = [s.n_rhs for s in states]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    one_batched(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    evals_b = sum(c * (s.n_rhs - n) for c, s, n in zip(cells, states, n0))
+    # one by one, same instances, one plan per mesh (set-up not timed)
+    plans = {msh: mm.Plan(msh, "f32", terms=w["terms"]) for msh in meshes}
+    devs1 = [torch.tensor(x["m"], dtype=torch.float32, device="cuda") for x in insts]
+    st1 = [mm.new_states(1, rtol=w["rtol"]) for _ in insts]
+    for i, x in enumerate(insts):
+        plans[tuple(x["mesh"])].rk45_run(params[i], devs1[i], st1[i], t_end=w["t_end"], max_steps=warmup,
+                                          check=False)
+    n1 = [s[0].n_rhs for s in st1]
+    torch.cuda.synchronize()
+    e0.record()
+    for i, x in enumerate(insts):
+        plans[tuple(x["mesh"])].rk45_run(params[i], devs1[i], st1[i], t_end=w["t_end"], max_steps=steps,
+                                          check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_1 = e0.elapsed_time(e1)
+    evals_1 = sum(c * (s[0].n_rhs - n) for c, s, n in zip(cells, st1, n1))
+    rb = evals_b / (ms_b * 1e-3)
+    r1 = evals_1 / (ms_1 * 1e-3)
+    return {"workload": w["name"], "instances": n_inst, "meshes": [list(m) for m in meshes],
+            "cells_total": sum(cells), "attempts_per_instance": steps,
+            "batched_cell_evals_per_s": rb, "batched_ms": ms_b,
+            "one_by_one_cell_evals_per_s": r1, "one_by_one_ms": ms_1,
+            "batched_over_one_by_one": rb / r1}
+
+
+def neb_bench(mm, inputs, torch, iters=100):
+    """32-image NEB chain on 128x128x1: one launch per pass for all images."""
+    import numpy as np
+    w = inputs.workload(3)
+    chain = np.stack(inputs.neb_chain())
+    plan = mm.Plan(w["mesh"], "f32", terms=w["terms"], max_batch=w["n_images"])
+    params = mm.make_params(terms=w["terms"], **w["params"])
+    dev = torch.tensor(chain, dtype=torch.float32, device="cuda")
+    plan.neb_run(params, dev, w["k_spring"], w["h"], 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    E = plan.neb_run(params, dev, w["k_spring"], w["h"], iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = w["n_images"] * w["mesh"][0] * w["mesh"][1]
+    return {"workload": w["name"], "iterations": iters, "ms_per_iteration": ms / iters,
+            "cell_evals_per_s": cells * iters / (ms * 1e-3),
+            "barrier_estimate_J": float(np.max(E) - E[0])}
+
+
 def roofline(res, traffic):
     dom = max(res["passes"], key=lambda p: p["us"])
     ach = dom["gbs"]
@@ -207,8 +288,12 @@ def main():
             extra["slab3d_" + prec] = r3
         extra["slab3d_fp32_over_fp64"] = (extra["slab3d_f32"]["cell_evals_per_s"] /
                                           extra["slab3d_f64"]["cell_evals_per_s"])
-        extra["slab3d_f32"]["roofline"] = roofline(extra["slab3d_f32"],
-                                                   load_traffic("slab3d_f32", None))
+        dom3 = max(extra["slab3d_f32"]["passes"], key=lambda p: p["us"])["kernel"]
+        extra["slab3d_f32"]["roofline"] = roofline(extra["slab3d_f32"], load_traffic("slab3d_f32", dom3))
+        print("bench: sweep batched vs one by one", file=sys.stderr, flush=True)
+        extra["sweep"] = sweep_bench(mm, inputs, torch)
+        print("bench: neb", file=sys.stderr, flush=True)
+        extra["neb"] = neb_bench(mm, inputs, torch)
     cpu = None
     if not args.no_cpu:
         print("bench: cpu oracle", file=sys.stderr, flush=True)

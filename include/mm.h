@@ -182,6 +182,15 @@ mm_status mm_batch_run(mm_batch* batch, mm_instance* inst, int32_t n_inst, int64
                        void* hip_stream);
 mm_status mm_batch_destroy(mm_batch* batch);
 
+/* Autotuner: times candidate launch shapes of every kernel pass (rows or
+ * columns per workgroup, threads per transform, workgroup size) on `reps`
+ * dm/dt evaluations of m (output scratch in `work`, same layout) and keeps the
+ * fastest per pass.  shape_out (nullable, 8 ints) receives the chosen shapes:
+ * x-forward rows, x-forward threads, y columns, y threads per column, y
+ * threads, x-inverse rows, x-inverse threads, 0.  Synchronises. */
+mm_status mm_plan_autotune(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
+                           void* work, int32_t reps, int32_t* shape_out, void* hip_stream);
+
 /* Measurement aid: runs `reps` dm/dt evaluations of `batch` instances (output
  * written to `work`, same layout as m) with a HIP event before every kernel
  * pass and after the last one, and returns in us_out[0..*n_pass) the mean

@@ -1047,6 +1047,131 @@ mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, doub
   return MM_OK;
 }
 
+// Whether a launch shape is valid for a group (LDS, butterfly budget, cells
+// per thread, workgroup size).
+bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
+  const Geo& g = G.g;
+  auto tmin = [&](int L) {
+    return prec == MM_F32 ? min_tpc(make_fft<float>(L, nullptr)) : min_tpc(make_fft<double>(L, nullptr));
+  };
+  const size_t lim = 160 * 1024;
+  const size_t rowb = (size_t)col_stride(g.Lx) * csz;
+  if (t.ty_f < 1 || t.ty_f > g.ny || t.nt_f > 512 || t.nt_f < 64 || t.tpc_f * t.ty_f > t.nt_f) return false;
+  if (t.tpc_f < tmin(g.Lx) || (size_t)t.ty_f * rowb > lim) return false;
+  if (t.ty_x < 1 || t.ty_x > g.ny || t.nt_i > 512 || t.nt_i < 64 || t.tpc_x * t.ty_x > t.nt_i) return false;
+  if (t.tpc_x < tmin(g.Lx) || (size_t)t.ty_x * rowb > lim || t.ty_x * g.nx > 8 * t.nt_i) return false;
+  const size_t colb = (size_t)col_stride(g.Py) * csz;
+  if (g.nz == 1) {
+    if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
+    if (3 * t.cb_y2 * colb > lim) return false;
+  } else {
+    if (t.cb_y < 1 || t.nt_y > 512 || t.tpc_y < tmin(g.Py) || t.cb_y * t.tpc_y > t.nt_y) return false;
+    if (t.cb_y * colb > lim) return false;
+  }
+  return true;
+}
+
+// Per-pass timing of `reps` dm/dt evaluations with the group's current shapes.
+template <typename T>
+mm_status time_passes(Engine& E, int batch, int reps, std::vector<double>& us, hipStream_t s) {
+  GroupSet<T> gs;
+  std::vector<int> inst0;
+  MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
+  const int np = pass_count(E);
+  std::vector<hipEvent_t> ev((size_t)(np + 1) * reps);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  mm_status st = MM_OK;
+  for (int r = 0; r < reps && st == MM_OK; ++r) {
+    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), demag_on(E), s, ev.data() + (size_t)r * (np + 1));
+    if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
+  }
+  if (st == MM_OK) {
+    hipError_t er = hipStreamSynchronize(s);
+    if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
+  }
+  us.assign(np, 0.0);
+  for (int i = 0; i < np && st == MM_OK; ++i) {
+    for (int r = 0; r < reps; ++r) {
+      float ms = 0.f;
+      hipError_t er = hipEventElapsedTime(&ms, ev[(size_t)r * (np + 1) + i], ev[(size_t)r * (np + 1) + i + 1]);
+      if (er != hipSuccess) { st = fail(MM_E_HIP, hipGetErrorString(er)); break; }
+      us[i] += 1e3 * ms / reps;
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  return st;
+}
+
+// Measure candidate launch shapes of each pass on the device and keep the
+// fastest per pass (the passes' shapes are independent of each other).
+template <typename T>
+mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m, void* work, int reps,
+                        hipStream_t s) {
+  Engine& E = p->e;
+  Group& G = E.groups[0];
+  MMCHK(single_eval<T>(p, batch, q, m, work, MODE_RHS, nullptr, s));
+  const Tuning base = G.tu;
+  const int np = pass_count(E);
+  const int last = np - 1;  // the inverse-x pass
+  auto try_all = [&](const std::vector<Tuning>& cands, std::vector<int> passes, Tuning& best) -> mm_status {
+    double best_us = 1e300;
+    for (const Tuning& c : cands) {
+      if (!tuning_ok(G, c, E.prec, E.csz)) continue;
+      G.tu = c;
+      MMCHK(engine_reserve(E, std::vector<int>{p->maxb}));
+      std::vector<double> us;
+      MMCHK(time_passes<T>(E, batch, reps, us, s));
+      double t = 0.0;
+      for (int k : passes) t += us[k];
+      if (t < best_us) {
+        best_us = t;
+        best = c;
+      }
+    }
+    G.tu = best;
+    return MM_OK;
+  };
+  Tuning best = base;
+  if (demag_on(E)) {
+    std::vector<Tuning> c;
+    for (int ty : {1, 2, 4, 8, 16})
+      for (int nt : {64, 128, 256, 512}) {
+        Tuning t = best;
+        t.ty_f = ty; t.nt_f = nt; t.tpc_f = nt / ty;
+        c.push_back(t);
+      }
+    MMCHK(try_all(c, {0}, best));
+    c.clear();
+    for (int cb : {1, 2, 3, 4, 6, 8})
+      for (int tf : {1, 2, 4}) {
+        Tuning t = best;
+        const int tmin = E.prec == MM_F32 ? min_tpc(make_fft<float>(G.g.Py, nullptr))
+                                          : min_tpc(make_fft<double>(G.g.Py, nullptr));
+        if (G.g.nz == 1) {
+          t.cb_y2 = cb; t.tpc_y2 = tmin * tf; t.nt_y = 3 * cb * t.tpc_y2;
+        } else {
+          t.cb_y = cb; t.tpc_y = tmin * tf; t.nt_y = cb * t.tpc_y;
+        }
+        c.push_back(t);
+      }
+    MMCHK(try_all(c, G.g.nz > 1 ? std::vector<int>{1, 3} : std::vector<int>{1}, best));
+  }
+  {
+    std::vector<Tuning> c;
+    for (int ty : {1, 2, 4, 8, 16})
+      for (int nt : {128, 256, 512}) {
+        Tuning t = best;
+        t.ty_x = ty; t.nt_i = nt; t.tpc_x = nt / ty;
+        c.push_back(t);
+      }
+    MMCHK(try_all(c, {last}, best));
+  }
+  G.tu = best;
+  MMCHK(engine_reserve(E, std::vector<int>{p->maxb}));
+  if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+  return MM_OK;
+}
+
 mm_status plan_checks(mm_plan* p, const mm_params* q, int batch) {
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (batch < 1 || batch > p->maxb) return fail(MM_E_ARG, "batch must be in [1, max_batch]");
@@ -1184,6 +1309,23 @@ mm_status mm_profile_passes(mm_plan* p, const mm_params* q, int32_t batch, const
                                      : profile_impl<double>(p, q, batch, m, work, reps, us_out, s);
   *n_pass = pass_count(p->e);
   return st;
+}
+
+mm_status mm_plan_autotune(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work, int32_t reps,
+                           int32_t* shape_out, void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch));
+  if (!m || !work) return fail(MM_E_ARG, "null array");
+  if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
+  hipStream_t s = (hipStream_t)hip_stream;
+  MMCHK(p->e.prec == MM_F32 ? autotune_impl<float>(p, q, batch, m, work, reps, s)
+                            : autotune_impl<double>(p, q, batch, m, work, reps, s));
+  if (shape_out) {
+    const Tuning& t = p->e.groups[0].tu;
+    const int v[8] = {t.ty_f, t.nt_f, p->e.groups[0].g.nz == 1 ? t.cb_y2 : t.cb_y,
+                      p->e.groups[0].g.nz == 1 ? t.tpc_y2 : t.tpc_y, t.nt_y, t.ty_x, t.nt_i, 0};
+    for (int i = 0; i < 8; ++i) shape_out[i] = v[i];
+  }
+  return MM_OK;
 }
 
 mm_status mm_neb_run(mm_plan* p, const mm_params* q, void* images, int32_t n_img, double k_spring, double h,

@@ -63,6 +63,7 @@ _sigs = {
     "mm_rk45_run": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _i64, _vp],
     "mm_neb_run": [_vp, _P(Params), _vp, _i32, _dbl, _dbl, _i64, _P(_dbl), _vp],
     "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
+    "mm_plan_autotune": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
     "mm_batch_create": [_P(_vp), _P(Mesh), _i32, ctypes.c_int, ctypes.c_uint32, _vp],
     "mm_batch_run": [_vp, _P(Instance), _i32, _i64, _vp],
     "mm_batch_destroy": [_vp],
@@ -210,6 +211,16 @@ class Plan:
         _check(_lib.mm_neb_run(self._h, _params_array(params), _ptr(images), n_img, k_spring, h, n_iter,
                                E, _stream(stream)), "mm_neb_run")
         return np.array(E[:])
+
+    def autotune(self, params, m, reps=10, stream=None):
+        """Pick the fastest launch shape of every pass on the device; returns the shapes."""
+        import torch
+        work = torch.empty_like(m)
+        shape = (ctypes.c_int32 * 8)()
+        _check(_lib.mm_plan_autotune(self._h, _params_array(params), self._batch(m), _ptr(m), _ptr(work), reps,
+                                     shape, _stream(stream)), "mm_plan_autotune")
+        keys = ("ty_f", "nt_f", "cb_y", "tpc_y", "nt_y", "ty_x", "nt_i")
+        return dict(zip(keys, shape[:7]))
 
     def profile_passes(self, params, m, reps=20, stream=None):
         """Mean duration (us) of each kernel pass of one dm/dt evaluation."""

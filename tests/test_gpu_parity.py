@@ -310,3 +310,37 @@ def test_uneven_batch_fp64_against_oracle(mm):
         ost = dp45.State(rtol=1e-6)
         mo = dp45.run(f, m0[i].copy(), ost, t_end=3e-12)
         assert np.max(np.abs(devs[i].cpu().numpy() - mo)) <= 1e-9
+
+
+def test_damped_relaxation_lowers_energy_fp32(mm):
+    """Thin-film terms, alpha = 0.3, static field: the energy never rises over
+    successive adaptive runs (up to FP32 rounding of the energy sums)."""
+    w = inputs.workload(1)
+    mesh = (48, 40, 1) + w["mesh"][3:]
+    plan = mm.Plan(mesh, "f32", terms=w["terms"])
+    gp = gpu_params(mm, w["params"], w["terms"])
+    m = to_dev(inputs.initial_state(1, mesh), torch.float32)
+    st = mm.new_states(1, rtol=w["rtol"])
+    E_prev = np.sum(plan.energy(gp, m)[0])
+    for k in range(1, 6):
+        plan.rk45_run(gp, m, st, t_end=4e-12 * k)
+        E = np.sum(plan.energy(gp, m)[0])
+        assert E <= E_prev + 1e-6 * abs(E_prev), (k, E, E_prev)
+        E_prev = E
+    norms = np.linalg.norm(m.cpu().numpy(), axis=0)
+    assert np.max(np.abs(norms - 1)) < 1e-6
+
+
+def test_autotune_keeps_results(mm):
+    """Any launch shape the autotuner picks gives the same field (FP32 rounding)."""
+    mesh = (96, 70, 3, 2e-9, 2e-9, 2e-9)
+    m = representable(_rand_m(mesh, 70), torch.float32)
+    plan = mm.Plan(mesh, "f32", terms=mm.ALL_TERMS)
+    gp = gpu_params(mm, PAR, mm.ALL_TERMS)
+    md = to_dev(m, torch.float32)
+    before = plan.llg_rhs(gp, md).cpu().numpy()
+    shape = plan.autotune(gp, md, reps=2)
+    after = plan.llg_rhs(gp, md).cpu().numpy()
+    assert field_err(after, before) <= 1e-6, shape
+    ref = F.llg_rhs(m, F.Mesh(*mesh), oracle_params(PAR, F.ALL_TERMS), _kernel(mesh))
+    assert field_err(after, ref) <= 1e-5
