@@ -215,6 +215,78 @@ def load_traffic(workload, kernel):
     return None if rec is None else rec.get("bytes_per_launch")
 
 
+# kernel-name fragments of each pass in rocprofv3 output
+PASS_KERNELS = {"x_fwd": "k_fwd_x<", "y_fused_product": "k_ypass<", "y_fwd": "k_ypass<",
+                "z_product": "k_z3d_pair<", "y_inv": "k_yinv<", "x_inv_fused_llg": "k_inv_x<"}
+COPY_BYTES = 1 << 30
+
+
+def copy_reference(torch):
+    """Plain device-to-device copies of COPY_BYTES: the reference the HBM
+    counters are scaled by (bytes read = bytes written = COPY_BYTES each)."""
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes": COPY_BYTES, "copies": 5}
+
+
+def _counter_rows(path):
+    import csv
+    rows = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return rows
+
+
+def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload, reps, mesh_nz):
+    """Per-launch HBM bytes of each pass from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    (KiB per dispatch; the last `reps` dispatches of each kernel are the timed
+    dm/dt evaluations), scaled by what the same counters read for a copy of
+    COPY_BYTES.  Writes profiles/traffic_counters.json for this source hash."""
+    cf = _counter_rows(copy_fetch_csv)
+    cw = _counter_rows(copy_write_csv)
+    big_f = max(v for k, vs in cf.items() if "copyBuffer" in k for v in vs)
+    big_w = max(v for k, vs in cw.items() if "copyBuffer" in k for v in vs)
+    kf = COPY_BYTES / (big_f * 1024.0)
+    kw = COPY_BYTES / (big_w * 1024.0)
+    fr = _counter_rows(fetch_csv)
+    wr = _counter_rows(write_csv)
+    out = {}
+    for name in pass_names(mesh_nz):
+        frag = PASS_KERNELS[name]
+        if name == "x_inv_fused_llg":
+            keys = [k for k in fr if frag in k and k.rstrip(")").find(", 1>") > 0]
+        else:
+            keys = [k for k in fr if frag in k]
+        if not keys:
+            continue
+        k = keys[0]
+        f = fr[k][-reps:]
+        w = wr.get(k, [0.0])[-reps:]
+        fb = sum(f) / len(f) * 1024.0 * kf
+        wb = sum(w) / len(w) * 1024.0 * kw
+        out[name] = {"kernel": k, "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    d = {}
+    if os.path.exists(path):
+        try:
+            d = json.load(open(path))
+        except ValueError:
+            d = {}
+    if d.get("source_hash") != source_hash():
+        d = {"source_hash": source_hash(), "workloads": {}}
+    d["calibration"] = {"copy_bytes": COPY_BYTES, "fetch_kib": big_f, "write_kib": big_w,
+                        "fetch_scale": kf, "write_scale": kw}
+    d["workloads"][workload] = out
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    return d
+
+
 def cpu_baseline(inputs, mesh, budget_s=12.0):
     """The FP64 oracle's dm/dt evaluation timed on this host (as it stands: NumPy +
     scipy.fft with their default single worker)."""
@@ -258,9 +330,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--only", choices=["slab3d"], default=None,
-                    help="profiling aid: run only the 512x512x16 slab (FP32) and print its record")
+    ap.add_argument("--only", choices=["slab3d", "copy"], default=None,
+                    help="profiling aids: slab3d runs only the 512x512x16 slab (FP32) and prints its "
+                         "record; copy runs only the plain 1 GiB copies the HBM counters are scaled by")
+    ap.add_argument("--ingest-counters", nargs=5, default=None,
+                    metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="turn rocprofv3 FETCH_SIZE/WRITE_SIZE counter files into per-launch HBM bytes "
+                         "(profiles/traffic_counters.json); WORKLOAD is thinfilm_f32 or slab3d_f32")
     args = ap.parse_args()
+    if args.ingest_counters:
+        wl, fcsv, wcsv, cfcsv, cwcsv = args.ingest_counters
+        d = ingest_counters(fcsv, wcsv, cfcsv, cwcsv, wl, 30, 16 if wl.startswith("slab") else 1)
+        print(json.dumps(d, indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
@@ -270,6 +352,9 @@ def main():
     from paper_2406_16064_amd import mm
 
     torch.cuda.set_device(0)
+    if args.only == "copy":
+        print(json.dumps(copy_reference(torch)))
+        return
     if args.only == "slab3d":
         r3, *_ = run_workload(mm, inputs, torch, 2, "f32", args.steps, args.warmup)
         print(json.dumps(r3))

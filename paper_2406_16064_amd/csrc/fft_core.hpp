@@ -9,7 +9,7 @@
 // Twiddles come from a table exp(-2 pi i m / L) computed in FP64 on the host.
 #pragma once
 
-#include "mm_internal.hpp"
+#include "gmem.hpp"
 
 namespace mmx {
 
@@ -86,7 +86,19 @@ __device__ __forceinline__ void dftR(Cx<T>* v) {
 
 // One Stockham stage of radix R on every column of the workgroup.
 // Per thread at most NB = 16/R butterflies (host guarantees L/R <= NB*tpc).
-template <typename T, int R, bool INV>
+// Twiddle read: from a table in LDS (TWL, copied there by the kernel) or in
+// global memory.
+template <typename T, bool TWL>
+__device__ __forceinline__ Cx<T> twiddle(const Cx<T>* tw, int i) {
+  if constexpr (TWL) return tw[i];
+  else return gld(tw + i);
+}
+
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+template <typename T, int R, bool INV, bool TWL = false>
 __device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns, int lane, int tpc,
                                           bool active, const Cx<T>* __restrict__ tw) {
   constexpr int NB = 16 / R;
@@ -110,7 +122,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = tw[r * kk * tstep];
+          Cx<T> w = twiddle<T, TWL>(tw, r * kk * tstep);
           if (INV) w.y = -w.y;
           v[k][r] = cmul(v[k][r], w);
         }
@@ -126,20 +138,30 @@ __device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns
 
 // Full transform of every column.  Must be called by all threads of the
 // workgroup (it contains barriers); threads with active == false only sync.
-template <typename T, bool INV>
-__device__ void fft_columns(Cx<T>* lds, const FftPlan<T>& p, int cs, int ncol, int tpc) {
+// tw: the twiddle table to use (p.tw, or its copy in LDS when TWL).
+template <typename T, bool INV, bool TWL = false>
+__device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc,
+                                            const Cx<T>* tw) {
   const int c = threadIdx.x / tpc;
   const int lane = threadIdx.x % tpc;
   const bool active = c < ncol;
   Cx<T>* col = lds + (active ? c : 0) * cs;
+  int ns = 1;
   for (int s = 0; s < p.nst; ++s) {
-    switch (p.rad[s]) {
-      case 8: fft_stage<T, 8, INV>(col, p.L, p.ns[s], lane, tpc, active, p.tw); break;
-      case 4: fft_stage<T, 4, INV>(col, p.L, p.ns[s], lane, tpc, active, p.tw); break;
-      case 3: fft_stage<T, 3, INV>(col, p.L, p.ns[s], lane, tpc, active, p.tw); break;
-      default: fft_stage<T, 2, INV>(col, p.L, p.ns[s], lane, tpc, active, p.tw); break;
+    const int R = radix_of(p.code, s);
+    switch (R) {
+      case 8: fft_stage<T, 8, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
+      case 4: fft_stage<T, 4, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
+      case 3: fft_stage<T, 3, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
+      default: fft_stage<T, 2, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
     }
+    ns *= R;
   }
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc) {
+  fft_columns<T, INV, false>(lds, p, cs, ncol, tpc, p.tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -150,9 +172,10 @@ __device__ void fft_columns(Cx<T>* lds, const FftPlan<T>& p, int cs, int ncol, i
 // end.  The caller makes sure LDS is free before the call when GIN, and syncs
 // before reusing LDS after the call when GOUT.
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool INV, bool GIN, bool GOUT, class Load, class Store>
+template <typename T, int R, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook>
 __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int L, int Ns, int lane, int tpc,
-                                             bool active, const Cx<T>* __restrict__ tw, Load& ld, Store& st) {
+                                             bool active, const Cx<T>* __restrict__ tw, Load& ld, Store& st,
+                                             Hook& hook) {
   constexpr int NB = 16 / R;
   const int nbf = L / R;
   Cx<T> v[NB][R];
@@ -168,6 +191,7 @@ __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int
     }
   }
   if constexpr (!GIN) __syncthreads();
+  if constexpr (GIN) hook();  // runs with this stage's global loads in flight
   const int tstep = L / (Ns * R);
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
@@ -177,7 +201,7 @@ __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = tw[r * kk * tstep];
+          Cx<T> w = twiddle<T, TWL>(tw, r * kk * tstep);
           if (INV) w.y = -w.y;
           v[k][r] = cmul(v[k][r], w);
         }
@@ -194,24 +218,30 @@ __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int
   if constexpr (!GOUT) __syncthreads();
 }
 
-template <typename T, bool INV, bool GIN, bool GOUT, class Load, class Store>
-__device__ __forceinline__ void fft_stage_any(Cx<T>* col, int c, const FftPlan<T>& p, int s, int lane, int tpc,
-                                              bool active, Load& ld, Store& st) {
-  switch (p.rad[s]) {
-    case 8: fft_stage_io<T, 8, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
-    case 4: fft_stage_io<T, 4, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
-    case 3: fft_stage_io<T, 3, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
-    default: fft_stage_io<T, 2, INV, GIN, GOUT>(col, c, p.L, p.ns[s], lane, tpc, active, p.tw, ld, st); break;
+template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook>
+__device__ __forceinline__ void fft_stage_any(Cx<T>* col, int c, const FftDesc<T>& p, const Cx<T>* tw, int s,
+                                              int ns, int lane, int tpc, bool active, Load& ld, Store& st,
+                                              Hook& hook) {
+  switch (radix_of(p.code, s)) {
+    case 8: fft_stage_io<T, 8, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
+    case 4: fft_stage_io<T, 4, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
+    case 3: fft_stage_io<T, 3, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
+    default: fft_stage_io<T, 2, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
   }
 }
 
-template <typename T, bool INV, bool GIN, bool GOUT, class Load, class Store>
-__device__ void fft_columns_io(Cx<T>* lds, const FftPlan<T>& p, int cs, int ncol, int tpc, Load ld, Store st) {
+// hook(): called once by every thread inside the first stage, after that
+// stage's global loads are issued (GIN only) -- e.g. to copy a twiddle table
+// into LDS while the data loads are in flight.  tw as for fft_columns.
+template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook>
+__device__ __forceinline__ void fft_columns_io(Cx<T>* lds, const FftDesc<T>& p, const Cx<T>* tw, int cs, int ncol,
+                                               int tpc, Load ld, Store st, Hook hook) {
   const int c = threadIdx.x / tpc;
   const int lane = threadIdx.x % tpc;
   const bool active = c < ncol;
   Cx<T>* col = lds + (active ? c : 0) * cs;
   if (p.nst == 0) {  // length 1: identity
+    if constexpr (GIN) hook();
     if (active && lane == 0) {
       Cx<T> v;
       if constexpr (GIN) v = ld(c, 0);
@@ -223,12 +253,22 @@ __device__ void fft_columns_io(Cx<T>* lds, const FftPlan<T>& p, int cs, int ncol
     return;
   }
   if (p.nst == 1) {
-    fft_stage_any<T, INV, GIN, GOUT>(col, c, p, 0, lane, tpc, active, ld, st);
+    fft_stage_any<T, INV, GIN, GOUT, TWL>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
     return;
   }
-  fft_stage_any<T, INV, GIN, false>(col, c, p, 0, lane, tpc, active, ld, st);
-  for (int s = 1; s + 1 < p.nst; ++s) fft_stage_any<T, INV, false, false>(col, c, p, s, lane, tpc, active, ld, st);
-  fft_stage_any<T, INV, false, GOUT>(col, c, p, p.nst - 1, lane, tpc, active, ld, st);
+  fft_stage_any<T, INV, GIN, false, TWL>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
+  int ns = radix_of(p.code, 0);
+  for (int s = 1; s + 1 < p.nst; ++s) {
+    fft_stage_any<T, INV, false, false, TWL>(col, c, p, tw, s, ns, lane, tpc, active, ld, st, hook);
+    ns *= radix_of(p.code, s);
+  }
+  fft_stage_any<T, INV, false, GOUT, TWL>(col, c, p, tw, p.nst - 1, ns, lane, tpc, active, ld, st, hook);
+}
+
+template <typename T, bool INV, bool GIN, bool GOUT, class Load, class Store>
+__device__ __forceinline__ void fft_columns_io(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc, Load ld,
+                                               Store st) {
+  fft_columns_io<T, INV, GIN, GOUT, false>(lds, p, p.tw, cs, ncol, tpc, ld, st, NoHook{});
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -241,14 +281,15 @@ __device__ __forceinline__ long long xcd_tile(long long bid, long long nblk) {
 
 // ---------------------------------------------------------------------------
 // Register-resident transform of compile-time length L held by one thread
-// (Stockham stages unrolled at compile time; radices 8/4/2/3; the twiddles are
-// read from the uniform table tw[m] = exp(-2 pi i m / L)).
+// (Stockham stages unrolled at compile time; radices 8/4/2/3).  Twiddles come
+// from the uniform table tw[TS * m] = exp(-2 pi i m / L): TS = 1 for a table
+// of length L, TS = 2 when the table belongs to a transform twice as long.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int reg_radix(int rem) {
   return (rem % 8 == 0 && rem != 16) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : 3;
 }
 
-template <typename T, int L, int Ns, bool INV>
+template <typename T, int L, int Ns, bool INV, int TS = 1>
 struct RegFft {
   static __device__ __forceinline__ void run(Cx<T>* v, const Cx<T>* __restrict__ tw) {
     constexpr int R = reg_radix(L / Ns);
@@ -263,7 +304,7 @@ struct RegFft {
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = tw[r * kk * (L / (Ns * R))];
+          Cx<T> w = ldu(tw + TS * (r * kk * (L / (Ns * R))));  // same entry in every lane
           if (INV) w.y = -w.y;
           a[r] = cmul(a[r], w);
         }
@@ -275,12 +316,12 @@ struct RegFft {
     }
 #pragma unroll
     for (int i = 0; i < L; ++i) v[i] = o[i];
-    RegFft<T, L, Ns * R, INV>::run(v, tw);
+    RegFft<T, L, Ns * R, INV, TS>::run(v, tw);
   }
 };
 
-template <typename T, int L, bool INV>
-struct RegFft<T, L, L, INV> {
+template <typename T, int L, bool INV, int TS>
+struct RegFft<T, L, L, INV, TS> {
   static __device__ __forceinline__ void run(Cx<T>*, const Cx<T>*) {}
 };
 

@@ -39,7 +39,6 @@
 namespace mmx {
 
 constexpr int kNT = 256;   // threads of the pointwise kernels and the register z pass
-constexpr int kCPT = 8;    // cells owned by one thread in the fused x-inverse epilogue
 constexpr int kUnroll = 8; // global loads kept in flight per thread when filling LDS
 
 template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
@@ -54,6 +53,35 @@ __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
+
+// Copy of small read-only tables (twiddles, post-processing factors) into LDS:
+// issue() starts the global loads into registers, store() writes them to LDS
+// (and copies any entries beyond NPER per thread directly).  Issuing before
+// a pass's data loads and storing after them lets one memory latency cover both.
+template <typename T, int NPER>
+struct TableCopy {
+  Cx<T> r[NPER];
+  const Cx<T>* a;
+  const Cx<T>* b;
+  int na, nb;
+  __device__ __forceinline__ Cx<T> src(int i) const { return i < na ? gld(a + i) : gld(b + (i - na)); }
+  __device__ __forceinline__ void issue(const Cx<T>* a_, int na_, const Cx<T>* b_, int nb_) {
+    a = a_; b = b_; na = na_; nb = nb_;
+#pragma unroll
+    for (int j = 0; j < NPER; ++j) {
+      const int i = threadIdx.x + j * blockDim.x;
+      if (i < na + nb) r[j] = src(i);
+    }
+  }
+  __device__ __forceinline__ void store(Cx<T>* dst) const {
+#pragma unroll
+    for (int j = 0; j < NPER; ++j) {
+      const int i = threadIdx.x + j * blockDim.x;
+      if (i < na + nb) dst[i] = r[j];
+    }
+    for (int i = threadIdx.x + NPER * blockDim.x; i < na + nb; i += blockDim.x) dst[i] = src(i);
+  }
+};
 
 // Group of this workgroup and its index inside the group (XCD-ordered).
 template <typename T>
@@ -78,8 +106,8 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T>& hp = L.hps[gi];
-  const Epi<T>& ep = L.epis[gi];
+  const HotPlan<T> hp = ldu(L.hps + gi);
+  const Epi<T> ep = ldu(L.epis + gi);
   const Geo& g = hp.g;
   if (bid >= fwd_blocks(g, hp.tu, hp.batch)) return;
   const int TY = hp.tu.ty_f;
@@ -88,11 +116,17 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   const int z = bid % g.nz; bid /= g.nz;
   const int c = bid % 3;
   const int b = (int)(bid / 3);
-  if (ep.ctl && ep.ctl[b].done) return;
+  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
   const int y0 = tile * TY;
   const int cs = col_stride(g.Lx);
+  // LDS: TY columns, then the twiddle table (Lx) and the post factors (Lx + 1)
+  Cx<T>* const twl = lds + TY * cs;
+  Cx<T>* const postl = twl + g.Lx;
+  TableCopy<T, 4> tab;
+  tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
   const T* src = ep.in + ((size_t)b * 3 + c) * g.N + (size_t)z * g.ny * g.nx;
   const int ny = g.ny, nx = g.nx;
+  const bool pairs = (nx & 1) == 0;  // rows start 8-byte aligned: load x[2n], x[2n+1] at once
   // element n of row r packs x[2n] + i x[2n+1] (zero beyond nx and past the last row)
   auto ld = [=](int r, int n) -> Cx<T> {
     Cx<T> v = {T(0), T(0)};
@@ -100,13 +134,18 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
     if (y < ny) {
       const T* row = src + (size_t)y * nx;
       const int i0 = 2 * n;
-      if (i0 < nx) v.x = row[i0];
-      if (i0 + 1 < nx) v.y = row[i0 + 1];
+      if (pairs) {
+        if (i0 < nx) v = gld(reinterpret_cast<const Cx<T>*>(row) + n);
+      } else {
+        if (i0 < nx) v.x = gld(row + i0);
+        if (i0 + 1 < nx) v.y = gld(row + i0 + 1);
+      }
     }
     return v;
   };
   auto st = [](int, int, Cx<T>) {};
-  fft_columns_io<T, false, true, false>(lds, hp.fp[0], cs, TY, (int)blockDim.x / TY, ld, st);
+  auto hook = [&]() { tab.store(twl); };
+  fft_columns_io<T, false, true, false, true>(lds, hp.fd[0], twl, cs, TY, (int)blockDim.x / TY, ld, st, hook);
   Cx<T>* dst = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny;
   const int tot2 = TY * g.Xp;
   for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
@@ -118,7 +157,7 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
     const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
     const Cx<T> D = cscale(csub(Zk, Zc), T(0.5));
     const Cx<T> O = {D.y, -D.x};  // D / i
-    dst[(size_t)k * g.ny + y] = cadd(E, cmul(hp.post[k], O));
+    gst(dst + (size_t)k * g.ny + y, cadd(E, cmul(postl[k], O)));
   }
 }
 
@@ -135,14 +174,14 @@ __device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int k
   const T sz = kz > g.Pz - kz ? T(-1) : T(1);
   const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
   const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
-  const T kxx = hp.kt[off] * s;
-  const T kyy = hp.kt[cstride + off] * s;
-  const T kzz = hp.kt[2 * cstride + off] * s;
-  const T kxy = hp.kt[3 * cstride + off] * (s * sy);
+  const T kxx = gld(hp.kt + off) * s;
+  const T kyy = gld(hp.kt + cstride + off) * s;
+  const T kzz = gld(hp.kt + 2 * cstride + off) * s;
+  const T kxy = gld(hp.kt + 3 * cstride + off) * (s * sy);
   T kxz = T(0), kyz = T(0);
   if (hp.ncomp == 6) {
-    kxz = hp.kt[4 * cstride + off] * (s * sz);
-    kyz = hp.kt[5 * cstride + off] * (s * sy * sz);
+    kxz = gld(hp.kt + 4 * cstride + off) * (s * sz);
+    kyz = gld(hp.kt + 5 * cstride + off) * (s * sy * sz);
   }
   const Cx<T> a = m0, b = m1, c = m2;
   m0 = {kxx * a.x + kxy * b.x + kxz * c.x, kxx * a.y + kxy * b.y + kxz * c.y};
@@ -169,7 +208,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   const int tiles = (g.Xp + CB - 1) / CB;
   const int tile = (int)(bid % tiles);
   const int b = (int)(bid / tiles);
-  if (ep.ctl && ep.ctl[b].done) return;
+  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
   const int kx0 = tile * CB;
   const int ncol = 3 * CB;
   const int cs = col_stride(g.Py);
@@ -179,15 +218,20 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   auto ld = [=](int col, int y) -> Cx<T> {
     const int c = col / CB, j = col - c * CB;
     const bool ok = y < ny && kx0 + j < Xp;
-    return ok ? base[((size_t)c * Xp + kx0 + j) * ny + y] : Cx<T>{T(0), T(0)};
+    return ok ? gld(base + ((size_t)c * Xp + kx0 + j) * ny + y) : Cx<T>{T(0), T(0)};
   };
   auto st = [=](int col, int y, Cx<T> v) {
     const int c = col / CB, j = col - c * CB;
-    if (y < ny && kx0 + j < Xp) base[((size_t)c * Xp + kx0 + j) * ny + y] = v;
+    if (y < ny && kx0 + j < Xp) gst(base + ((size_t)c * Xp + kx0 + j) * ny + y, v);
   };
   const int tpc = blockDim.x / ncol;
-  fft_columns_io<T, false, true, false>(lds, hp.fp[1], cs, ncol, tpc, ld, st);
-  const T s = T(hp.prm[b].demag_scale);
+  // twiddle table (Py) in LDS after the columns, copied while the first loads fly
+  Cx<T>* const twl = lds + ncol * cs;
+  TableCopy<T, 4> tab;
+  tab.issue(hp.fd[1].tw, g.Py, nullptr, 0);
+  auto hook = [&]() { tab.store(twl); };
+  fft_columns_io<T, false, true, false, true>(lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, hook);
+  const T s = T(ldu(&hp.prm[b].demag_scale));
   for (int t = threadIdx.x; t < CB * g.Py; t += blockDim.x) {
     const int j = t / g.Py, ky = t - j * g.Py;
     const int kx = kx0 + j;
@@ -196,7 +240,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
                  lds[(2 * CB + j) * cs + pidx(ky)]);
   }
   __syncthreads();
-  fft_columns_io<T, true, false, true>(lds, hp.fp[1], cs, ncol, tpc, ld, st);
+  fft_columns_io<T, true, false, true, true>(lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, NoHook{});
 }
 
 template <typename T, bool INV>
@@ -207,7 +251,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
   const long long tiles = (rows_per_inst + CB - 1) / CB;
   const long long tile = bid % tiles;
   const int b = (int)(bid / tiles);
-  if (ep.ctl && ep.ctl[b].done) return;
+  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
   const long long row0 = tile * CB;
   const int ncol = (int)((rows_per_inst - row0) < CB ? (rows_per_inst - row0) : CB);
   const int cs = col_stride(g.Py);
@@ -216,12 +260,12 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
   const Cx<T>* src = (INV ? hp.Sy + (size_t)b * g.sy : hp.Sx + (size_t)b * g.sx) + (size_t)row0 * nin;
   Cx<T>* dst = (INV ? hp.Sx + (size_t)b * g.sx : hp.Sy + (size_t)b * g.sy) + (size_t)row0 * nout;
   auto ld = [=](int c, int e) -> Cx<T> {
-    return e < nin ? src[(size_t)c * nin + e] : Cx<T>{T(0), T(0)};
+    return e < nin ? gld(src + (size_t)c * nin + e) : Cx<T>{T(0), T(0)};
   };
   auto st = [=](int c, int e, Cx<T> v) {
-    if (e < nout) dst[(size_t)c * nout + e] = v;
+    if (e < nout) gst(dst + (size_t)c * nout + e, v);
   };
-  fft_columns_io<T, INV, true, true>(lds, hp.fp[1], cs, ncol, (int)blockDim.x / CB, ld, st);
+  fft_columns_io<T, INV, true, true>(lds, hp.fd[1], cs, ncol, (int)blockDim.x / CB, ld, st);
 }
 
 // Forward y pass of every group: fused 2-D or 3-D forward rows.
@@ -231,13 +275,13 @@ __global__ void __launch_bounds__(512) k_ypass(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T>& hp = L.hps[gi];
+  const HotPlan<T> hp = ldu(L.hps + gi);
   if (hp.g.nz == 1) {
     if (bid >= y2d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_fused2d(hp, L.epis[gi], bid, lds);
+    y_fused2d(hp, ldu(L.epis + gi), bid, lds);
   } else {
     if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_rows3d<T, false>(hp, L.epis[gi], bid, lds);
+    y_rows3d<T, false>(hp, ldu(L.epis + gi), bid, lds);
   }
 }
 
@@ -247,9 +291,9 @@ __global__ void __launch_bounds__(512) k_yinv(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T>& hp = L.hps[gi];
+  const HotPlan<T> hp = ldu(L.hps + gi);
   if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-  y_rows3d<T, true>(hp, L.epis[gi], bid, lds);
+  y_rows3d<T, true>(hp, ldu(L.epis + gi), bid, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -266,8 +310,8 @@ __global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T>& hp = L.hps[gi];
-  const Epi<T>& ep = L.epis[gi];
+  const HotPlan<T> hp = ldu(L.hps + gi);
+  const Epi<T> ep = ldu(L.epis + gi);
   const Geo& g = hp.g;
   if (bid >= zlds_blocks(g, hp.tu, hp.batch)) return;
   const int QZ = hp.tu.qz;
@@ -275,7 +319,7 @@ __global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
   const long long tiles = (nq + QZ - 1) / QZ;
   const long long tile = bid % tiles;
   const int b = (int)(bid / tiles);
-  if (ep.ctl && ep.ctl[b].done) return;
+  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
   const long long q0 = tile * QZ;
   const int nqt = (int)((nq - q0) < QZ ? (nq - q0) : QZ);
   const int cs = col_stride(g.Pz);
@@ -291,7 +335,7 @@ __global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
       const int cz = t / QZ;
       const int c = cz / g.Pz, z = cz - c * g.Pz;
       v[u] = {T(0), T(0)};
-      if (t < 3 * g.Pz * QZ && z < g.nz && j < nqt) v[u] = base[((size_t)c * g.nz + z) * plane + q0 + j];
+      if (t < 3 * g.Pz * QZ && z < g.nz && j < nqt) v[u] = gld(base + ((size_t)c * g.nz + z) * plane + q0 + j);
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -306,8 +350,8 @@ __global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
   }
   __syncthreads();
   const int tpc = blockDim.x / (3 * QZ);
-  fft_columns<T, false>(lds, hp.fp[2], cs, 3 * QZ, tpc);
-  const T s = T(hp.prm[b].demag_scale);
+  fft_columns<T, false>(lds, hp.fd[2], cs, 3 * QZ, tpc);
+  const T s = T(ldu(&hp.prm[b].demag_scale));
   for (int t = threadIdx.x; t < QZ * g.Pz; t += blockDim.x) {
     const int j = t % QZ, kz = t / QZ;
     if (j >= nqt) continue;
@@ -317,12 +361,12 @@ __global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
                  lds[(1 * QZ + j) * cs + pidx(kz)], lds[(2 * QZ + j) * cs + pidx(kz)]);
   }
   __syncthreads();
-  fft_columns<T, true>(lds, hp.fp[2], cs, 3 * QZ, tpc);
+  fft_columns<T, true>(lds, hp.fd[2], cs, 3 * QZ, tpc);
   for (int t = threadIdx.x; t < 3 * g.nz * QZ; t += blockDim.x) {
     const int j = t % QZ;
     const int cz = t / QZ;
     const int c = cz / g.nz, z = cz - c * g.nz;
-    if (j < nqt) base[((size_t)c * g.nz + z) * plane + q0 + j] = lds[(c * QZ + j) * cs + pidx(z)];
+    if (j < nqt) gst(base + ((size_t)c * g.nz + z) * plane + q0 + j, lds[(c * QZ + j) * cs + pidx(z)]);
   }
 }
 
@@ -334,18 +378,20 @@ __host__ __device__ inline long long zreg_blocks(const Geo& g, int batch) {
   return (long long)batch * (((long long)g.Xp * g.Py + kNT - 1) / kNT);
 }
 
-template <typename T, int PZ>
-__global__ void __launch_bounds__(kNT) k_z3d_reg(Launch<T> L) {
+// HALF: nz == Pz / 2 (the usual padding), so the upper half of every input
+// column is a compile-time zero and only the lower half of the output is kept.
+template <typename T, int PZ, bool HALF>
+__device__ __forceinline__ void z3d_reg_body(const Launch<T>& L) {
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T>& hp = L.hps[gi];
-  const Epi<T>& ep = L.epis[gi];
+  const HotPlan<T> hp = ldu(L.hps + gi);
+  const Epi<T> ep = ldu(L.epis + gi);
   const Geo& g = hp.g;
   if (bid >= zreg_blocks(g, hp.batch)) return;
   const long long nq = (long long)g.Xp * g.Py;
   const long long qb = (nq + kNT - 1) / kNT;
   const int b = (int)(bid / qb);
-  if (ep.ctl && ep.ctl[b].done) return;
+  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
   const long long q = (bid % qb) * kNT + threadIdx.x;
   if (q >= nq) return;
   Cx<T>* base = hp.Sy + (size_t)b * g.sy + q;
@@ -356,26 +402,30 @@ __global__ void __launch_bounds__(kNT) k_z3d_reg(Launch<T> L) {
 #pragma unroll
     for (int z = 0; z < PZ; ++z) {
       v[c][z] = {T(0), T(0)};
-      if (z < g.nz) v[c][z] = base[((size_t)c * g.nz + z) * plane];
+      if (HALF ? z < PZ / 2 : z < g.nz) v[c][z] = gld(base + ((size_t)c * g.nz + z) * plane);
     }
+  // the stores recompute their addresses from an opaque copy of the column
+  // pointer: keeping the 3 nz load addresses alive through the transforms
+  // would cost two registers each
+  asm volatile("" : "+v"(base));
 #pragma unroll
   for (int c = 0; c < 3; ++c) RegFft<T, PZ, 1, false>::run(v[c], hp.twz);
-  const int kx = (int)(q / g.Py), ky = (int)(q - (long long)kx * g.Py);
+  const int kx = (int)q / g.Py, ky = (int)q - kx * g.Py;
   const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
   const T sy = ky > g.Py - ky ? T(-1) : T(1);
   const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
-  const T s = T(hp.prm[b].demag_scale);
+  const T s = T(ldu(&hp.prm[b].demag_scale));
 #pragma unroll
   for (int kz = 0; kz < PZ; ++kz) {
     const int kzf = kz <= PZ - kz ? kz : PZ - kz;
     const T sz = kz > PZ - kz ? T(-1) : T(1);
     const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
-    const T kxx = hp.kt[off] * s;
-    const T kyy = hp.kt[cstride + off] * s;
-    const T kzz = hp.kt[2 * cstride + off] * s;
-    const T kxy = hp.kt[3 * cstride + off] * (s * sy);
-    const T kxz = hp.kt[4 * cstride + off] * (s * sz);
-    const T kyz = hp.kt[5 * cstride + off] * (s * sy * sz);
+    const T kxx = gld(hp.kt + off) * s;
+    const T kyy = gld(hp.kt + cstride + off) * s;
+    const T kzz = gld(hp.kt + 2 * cstride + off) * s;
+    const T kxy = gld(hp.kt + 3 * cstride + off) * (s * sy);
+    const T kxz = gld(hp.kt + 4 * cstride + off) * (s * sz);
+    const T kyz = gld(hp.kt + 5 * cstride + off) * (s * sy * sz);
     const Cx<T> a = v[0][kz], bb = v[1][kz], cc = v[2][kz];
     v[0][kz] = {kxx * a.x + kxy * bb.x + kxz * cc.x, kxx * a.y + kxy * bb.y + kxz * cc.y};
     v[1][kz] = {kxy * a.x + kyy * bb.x + kyz * cc.x, kxy * a.y + kyy * bb.y + kyz * cc.y};
@@ -387,7 +437,137 @@ __global__ void __launch_bounds__(kNT) k_z3d_reg(Launch<T> L) {
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int z = 0; z < PZ; ++z)
-      if (z < g.nz) base[((size_t)c * g.nz + z) * plane] = v[c][z];
+      if (HALF ? z < PZ / 2 : z < g.nz) gst(base + ((size_t)c * g.nz + z) * plane, v[c][z]);
+}
+
+// Two waves per SIMD fit the half-zero columns (up to 32 points in FP32)
+// without spilling; the general columns keep the default register budget.
+template <typename T, int PZ>
+__global__ void __launch_bounds__(kNT, 2) k_z3d_reg_half(Launch<T> L) {
+  z3d_reg_body<T, PZ, true>(L);
+}
+
+template <typename T, int PZ>
+__global__ void __launch_bounds__(kNT) k_z3d_reg(Launch<T> L) {
+  z3d_reg_body<T, PZ, false>(L);
+}
+
+// ---------------------------------------------------------------------------
+// 3-D z pass for even Pz = 2M, one (kx, ky) column per lane pair.  The input
+// is zero beyond z = M - 1 (nz <= M), so the even outputs of the length-2M
+// transform are the length-M transform of x and the odd ones that of
+// x[z] exp(-2 pi i z / 2M).  Lane p of the pair computes the outputs with
+// kz = 2k + p, multiplies by the tensor there and transforms back over M
+// points; the inverse over 2M points is the sum of the two halves, the odd
+// half multiplied by exp(+2 pi i z / 2M).  Each lane ends with the z of its
+// parity, after one exchange with its partner.  Half the registers of the
+// one-lane version, so twice to four times the waves per SIMD.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline long long zpair_blocks(const Geo& g, int batch) {
+  return (long long)batch * (((long long)g.Xp * g.Py + kNT / 2 - 1) / (kNT / 2));
+}
+
+// value of the partner lane (lane ^ 1), within a quad
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(kNT) k_z3d_pair(Launch<T> L) {
+  constexpr int PZ = 2 * M;
+  long long bid;
+  const int gi = group_of(L, bid);
+  const HotPlan<T> hp = ldu(L.hps + gi);
+  const Geo& g = hp.g;
+  if (bid >= zpair_blocks(g, hp.batch)) return;
+  const long long nq = (long long)g.Xp * g.Py;
+  const long long qb = (nq + kNT / 2 - 1) / (kNT / 2);
+  const int b = (int)(bid / qb);
+  DevCtl* const ctl = ldu(&L.epis[gi].ctl);
+  if (ctl && ldu(&ctl[b].done)) return;
+  const int p = threadIdx.x & 1;
+  const long long q = (bid % qb) * (kNT / 2) + (threadIdx.x >> 1);
+  // both lanes of a pair are in range or out of range together (the exchange
+  // below needs the partner); out-of-range pairs compute on zeros and store nothing
+  const bool live = q < nq;
+  const int ql = live ? (int)q : 0;  // out-of-range lanes read element 0 and store nothing
+  const uint32_t qoff = (uint32_t)ql * (uint32_t)sizeof(Cx<T>);
+  Cx<T>* const Syb = hp.Sy + (size_t)b * g.sy;  // plane (c, z) starts at Syb + (c nz + z) nq
+  const int nz = g.nz;
+  Cx<T> v[3][M];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < M; ++z) {
+      v[c][z] = {T(0), T(0)};
+      if (z < nz) v[c][z] = gldo(Syb + ((size_t)c * nz + z) * nq, qoff);  // uniform branch
+    }
+  // odd lanes: pre-multiply by exp(-2 pi i z / 2M)
+#pragma unroll
+  for (int z = 1; z < M; ++z) {
+    Cx<T> w = ldu(hp.twz + z);
+    if (!p) w = Cx<T>{T(1), T(0)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][z] = cmul(v[c][z], w);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) RegFft<T, M, 1, false, 2>::run(v[c], hp.twz);
+  const int kx = ql / g.Py, ky = ql - kx * g.Py;
+  const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
+  const T sy = ky > g.Py - ky ? T(-1) : T(1);
+  const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
+  const T s = T(ldu(&hp.prm[b].demag_scale));
+  const uint32_t XK = (uint32_t)g.Xp * (uint32_t)g.Ky;
+  const uint32_t kxy0 = (uint32_t)kx * (uint32_t)g.Ky + (uint32_t)kyf;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int kz = 2 * k + p;
+    const int kzf = kz <= PZ - kz ? kz : PZ - kz;
+    const T sz = kz > PZ - kz ? T(-1) : T(1);
+    const uint32_t ko = ((uint32_t)kzf * XK + kxy0) * (uint32_t)sizeof(T);
+    const T kxx = gldo(hp.kt, ko) * s;
+    const T kyy = gldo(hp.kt + cstride, ko) * s;
+    const T kzz = gldo(hp.kt + 2 * cstride, ko) * s;
+    const T kxy = gldo(hp.kt + 3 * cstride, ko) * (s * sy);
+    const T kxz = gldo(hp.kt + 4 * cstride, ko) * (s * sz);
+    const T kyz = gldo(hp.kt + 5 * cstride, ko) * (s * sy * sz);
+    const Cx<T> a = v[0][k], bb = v[1][k], cc = v[2][k];
+    v[0][k] = {kxx * a.x + kxy * bb.x + kxz * cc.x, kxx * a.y + kxy * bb.y + kxz * cc.y};
+    v[1][k] = {kxy * a.x + kyy * bb.x + kyz * cc.x, kxy * a.y + kyy * bb.y + kyz * cc.y};
+    v[2][k] = {kxz * a.x + kyz * bb.x + kzz * cc.x, kxz * a.y + kyz * bb.y + kzz * cc.y};
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) RegFft<T, M, 1, true, 2>::run(v[c], hp.twz);
+  // odd lanes: post-multiply by exp(+2 pi i z / 2M)
+#pragma unroll
+  for (int z = 1; z < M; ++z) {
+    Cx<T> w = ldu(hp.twz + z);
+    w.y = -w.y;
+    if (!p) w = Cx<T>{T(1), T(0)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][z] = cmul(v[c][z], w);
+  }
+  // z of parity p: own half + partner's half.  Lane p sends the partner the
+  // value at the partner's parity.
+#pragma unroll
+  for (int z0 = 0; z0 < M; z0 += 2) {
+    const int ze = z0, zo = z0 + 1 < M ? z0 + 1 : z0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const Cx<T> send = p ? v[c][ze] : v[c][zo];
+      const Cx<T> got = {pair_swap(send.x), pair_swap(send.y)};
+      const Cx<T> mine = p ? v[c][zo] : v[c][ze];
+      const Cx<T> sum = cadd(mine, got);
+      const int zz = p ? zo : ze;
+      if (live && zz < nz && (p == 0 || z0 + 1 < M)) gsto(Syb + ((size_t)c * nz + zz) * nq, qoff, sum);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -397,15 +577,37 @@ template <typename T> struct V3 { T x, y, z; };
 
 template <typename T>
 __device__ __forceinline__ V3<T> ld3(const T* __restrict__ p, long long N, long long i) {
-  return {p[i], p[N + i], p[2 * N + i]};
+  return {gld(p + i), gld(p + N + i), gld(p + 2 * N + i)};
 }
 
 struct LocalTerms {
   double ex, dmi, an, ze;  // m . H_term (FP64), for energies
 };
 
+// Coefficients of the local terms in the working precision (kept in scalar
+// registers for the whole epilogue).
+template <typename T> struct LocalCoef {
+  T cex[3], cdmi[2], can, u[3], H[3];
+  uint32_t terms;
+};
+
+template <typename T>
+__device__ __forceinline__ LocalCoef<T> local_coef(const DevParams& P) {
+  LocalCoef<T> c;
+  for (int a = 0; a < 3; ++a) {
+    c.cex[a] = T(P.cex[a]);
+    c.u[a] = T(P.u[a]);
+    c.H[a] = T(P.H[a]);
+  }
+  c.cdmi[0] = T(P.cdmi[0]);
+  c.cdmi[1] = T(P.cdmi[1]);
+  c.can = T(P.can);
+  c.terms = P.terms;
+  return c;
+}
+
 template <typename T, bool ENERGY>
-__device__ __forceinline__ V3<T> local_field(const Geo& g, const DevParams& P, const T* __restrict__ mb,
+__device__ __forceinline__ V3<T> local_field(const Geo& g, const LocalCoef<T>& P, const T* __restrict__ mb,
                                              int x, int y, int z, V3<T> mi, LocalTerms* lt) {
   const long long N = g.N;
   const long long i = ((long long)z * g.ny + y) * g.nx + x;
@@ -423,7 +625,7 @@ __device__ __forceinline__ V3<T> local_field(const Geo& g, const DevParams& P, c
     if (hzp) zp = ld3(mb, N, i + (long long)g.nx * g.ny);
   }
   if (P.terms & MM_EXCHANGE) {
-    const T cx = T(P.cex[0]), cy = T(P.cex[1]), cz = T(P.cex[2]);
+    const T cx = P.cex[0], cy = P.cex[1], cz = P.cex[2];
     V3<T> e = {T(0), T(0), T(0)};
     auto acc = [&](bool has, V3<T> nb, T c) {
       if (has) {
@@ -441,7 +643,7 @@ __device__ __forceinline__ V3<T> local_field(const Geo& g, const DevParams& P, c
   if (P.terms & MM_DMI_INTERFACIAL) {
     // x neighbours: -(D/mu0Ms dx) e_y x (m_{+x} - m_{-x});  e_y x v = (v_z, 0, -v_x)
     // y neighbours: -(D/mu0Ms dy) e_x x (m_{-y} - m_{+y});  e_x x v = (0, -v_z, v_y)
-    const T cx = T(P.cdmi[0]), cy = T(P.cdmi[1]);
+    const T cx = P.cdmi[0], cy = P.cdmi[1];
     const V3<T> dx = {xp.x - xm.x, xp.y - xm.y, xp.z - xm.z};
     const V3<T> dy = {ym.x - yp.x, ym.y - yp.y, ym.z - yp.z};
     V3<T> d = {-cx * dx.z, cy * dy.z, cx * dx.x - cy * dy.y};
@@ -449,13 +651,13 @@ __device__ __forceinline__ V3<T> local_field(const Geo& g, const DevParams& P, c
     if (ENERGY) lt->dmi = (double)mi.x * d.x + (double)mi.y * d.y + (double)mi.z * d.z;
   }
   if (P.terms & MM_ANIS_UNIAXIAL) {
-    const T ux = T(P.u[0]), uy = T(P.u[1]), uz = T(P.u[2]);
-    const T s = T(P.can) * (mi.x * ux + mi.y * uy + mi.z * uz);
+    const T ux = P.u[0], uy = P.u[1], uz = P.u[2];
+    const T s = P.can * (mi.x * ux + mi.y * uy + mi.z * uz);
     H.x += s * ux; H.y += s * uy; H.z += s * uz;
     if (ENERGY) lt->an = (double)s * ((double)mi.x * ux + (double)mi.y * uy + (double)mi.z * uz);
   }
   if (P.terms & MM_ZEEMAN) {
-    H.x += T(P.H[0]); H.y += T(P.H[1]); H.z += T(P.H[2]);
+    H.x += P.H[0]; H.y += P.H[1]; H.z += P.H[2];
     if (ENERGY) lt->ze = (double)mi.x * P.H[0] + (double)mi.y * P.H[1] + (double)mi.z * P.H[2];
   }
   return H;
@@ -470,8 +672,10 @@ __device__ __forceinline__ V3<T> ll_rhs(V3<T> m, V3<T> H, T g1, T g2) {
 
 // ---------------------------------------------------------------------------
 // x inverse (complex-to-real) + local fields + LL + epilogue.  One workgroup:
-// TY rows of one z plane of one instance, 3 components.  DEMAG = false skips
-// the transform (H_d = 0) and uses no LDS for it.
+// TY rows of one z plane of one instance.  The 3 x TY spectra are loaded
+// together, transformed together (one column per component and row) and left
+// in LDS, where the epilogue picks H_d up cell by cell.  DEMAG = false skips
+// the transform (H_d = 0) and uses no LDS for it.  MODE is the epilogue.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline long long inv_blocks(const Geo& g, const Tuning& tu, int batch) {
   return (long long)batch * g.nz * ((g.ny + tu.ty_x - 1) / tu.ty_x);
@@ -481,15 +685,15 @@ int eval_blocks_per_inst(const Geo& g, const Tuning& tu) {
   return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz;
 }
 
-template <typename T, bool DEMAG>
+template <typename T, bool DEMAG, int MODE>
 __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   __shared__ double red[5][512 / 64];
+  constexpr bool energy = MODE == MODE_ENERGY || MODE == MODE_FIELD_ENERGY;
   long long bid0;
   const int gi = group_of(L, bid0);
-  const HotPlan<T>& hp = L.hps[gi];
-  const Epi<T>& epi = L.epis[gi];
+  const HotPlan<T> hp = ldu(L.hps + gi);
   const Geo& g = hp.g;
   if (bid0 >= inv_blocks(g, hp.tu, hp.batch)) return;
   const int TY = hp.tu.ty_x;
@@ -498,154 +702,163 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   const int tile = bid % tiles; bid /= tiles;
   const int z = bid % g.nz;
   const int b = (int)(bid / g.nz);
-  if (epi.ctl && epi.ctl[b].done) return;
-  const DevParams P = hp.prm[b];
-  const bool add_hd = DEMAG && (P.terms & MM_DEMAG);
+  DevCtl* const ctl = ldu(&L.epis[gi].ctl);
+  if (ctl && ldu(&ctl[b].done)) return;
+  const bool add_hd = DEMAG && (ldu(&hp.prm[b].terms) & MM_DEMAG);
   const int y0 = tile * TY;
-  const int ncell = TY * g.nx;
-  T Hd[3][kCPT];
-#pragma unroll
-  for (int k = 0; k < kCPT; ++k) Hd[0][k] = Hd[1][k] = Hd[2][k] = T(0);
+  const int nrow = g.ny - y0 < TY ? g.ny - y0 : TY;
+  const int cs = col_stride(g.Lx);
 
+  // LDS: 3 TY columns, then the twiddle table (Lx) and the post factors (Lx + 1)
+  Cx<T>* const twl = lds + 3 * TY * cs;
+  Cx<T>* const postl = twl + g.Lx;
   if (DEMAG) {
-    const int cs = col_stride(g.Lx);
-    const int tpc = blockDim.x / TY;
-    for (int c = 0; c < 3; ++c) {
-      const Cx<T>* src = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny;
-      for (int t0 = threadIdx.x; t0 < TY * g.Xp; t0 += kUnroll * blockDim.x) {
-        Cx<T> v[kUnroll];
+    TableCopy<T, 4> tab;
+    tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
+    // column c * TY + r holds component c of row y0 + r; rows past the mesh are zero
+    const int ncol = 3 * TY;
+    const size_t cstride = (size_t)g.nz * g.Xp * g.ny;
+    const Cx<T>* src = hp.Sx + (size_t)b * g.sx + (size_t)z * g.Xp * g.ny + y0;
+    const int tot = ncol * g.Xp;
+    for (int t0 = threadIdx.x; t0 < tot; t0 += kUnroll * blockDim.x) {
+      Cx<T> v[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int t = t0 + u * blockDim.x;
-          const int k = t / TY, r = t - k * TY;
-          const int y = y0 + r;
-          v[u] = {T(0), T(0)};
-          if (t < TY * g.Xp && y < g.ny) v[u] = src[(size_t)k * g.ny + y];
-        }
+      for (int u = 0; u < kUnroll; ++u) {
+        const int t = t0 + u * blockDim.x;
+        const int r = t % TY, q = t / TY;
+        const int k = q % g.Xp, c = q / g.Xp;
+        v[u] = {T(0), T(0)};
+        if (t < tot && r < nrow) v[u] = gld(src + c * cstride + (size_t)k * g.ny + r);
+      }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int t = t0 + u * blockDim.x;
-          if (t < TY * g.Xp) {
-            const int k = t / TY, r = t - k * TY;
-            lds[r * cs + pidx(k)] = v[u];
-          }
+      for (int u = 0; u < kUnroll; ++u) {
+        const int t = t0 + u * blockDim.x;
+        if (t < tot) {
+          const int r = t % TY, q = t / TY;
+          const int k = q % g.Xp, c = q / g.Xp;
+          lds[(c * TY + r) * cs + pidx(k)] = v[u];
         }
       }
-      __syncthreads();
-      // Z2[k] = (X[k] + conj X[Lx-k]) + i (X[k] - conj X[Lx-k]) conj(W^k), k in [0, Lx)
-      const int half = g.Lx / 2;
-      for (int t = threadIdx.x; t < TY * (half + 1); t += blockDim.x) {
-        const int r = t / (half + 1), k = t - r * (half + 1);
-        Cx<T>* col = lds + r * cs;
-        const int k2 = g.Lx - k;
-        const Cx<T> Xa = col[pidx(k)], Xb = col[pidx(k2)];
-        {
-          const Cx<T> s = cadd(Xa, cconj(Xb));
-          const Cx<T> d = cmul(csub(Xa, cconj(Xb)), cconj(hp.post[k]));
-          col[pidx(k)] = Cx<T>{s.x - d.y, s.y + d.x};
-        }
-        if (k > 0 && k < k2) {
-          const Cx<T> s = cadd(Xb, cconj(Xa));
-          const Cx<T> d = cmul(csub(Xb, cconj(Xa)), cconj(hp.post[k2]));
-          col[pidx(k2)] = Cx<T>{s.x - d.y, s.y + d.x};
-        }
-      }
-      __syncthreads();
-      fft_columns<T, true>(lds, hp.fp[0], cs, TY, tpc);
-#pragma unroll
-      for (int k = 0; k < kCPT; ++k) {
-        const int e = threadIdx.x + k * blockDim.x;
-        if (e < ncell) {
-          const int r = e / g.nx, x = e - r * g.nx;
-          const Cx<T> v = lds[r * cs + pidx(x >> 1)];
-          Hd[c][k] = (x & 1) ? v.y : v.x;
-        }
-      }
-      __syncthreads();
     }
+    tab.store(twl);
+    __syncthreads();
+    // Z2[k] = (X[k] + conj X[Lx-k]) + i (X[k] - conj X[Lx-k]) conj(W^k), k in [0, Lx)
+    const int half = g.Lx / 2;
+    for (int t = threadIdx.x; t < ncol * (half + 1); t += blockDim.x) {
+      const int col = t / (half + 1), k = t - col * (half + 1);
+      Cx<T>* cp = lds + col * cs;
+      const int k2 = g.Lx - k;
+      const Cx<T> Xa = cp[pidx(k)], Xb = cp[pidx(k2)];
+      {
+        const Cx<T> s = cadd(Xa, cconj(Xb));
+        const Cx<T> d = cmul(csub(Xa, cconj(Xb)), cconj(postl[k]));
+        cp[pidx(k)] = Cx<T>{s.x - d.y, s.y + d.x};
+      }
+      if (k > 0 && k < k2) {
+        const Cx<T> s = cadd(Xb, cconj(Xa));
+        const Cx<T> d = cmul(csub(Xb, cconj(Xa)), cconj(postl[k2]));
+        cp[pidx(k2)] = Cx<T>{s.x - d.y, s.y + d.x};
+      }
+    }
+    __syncthreads();
+    fft_columns<T, true, true>(lds, hp.fd[0], cs, ncol, (int)blockDim.x / ncol, twl);
   }
 
-  // ----- epilogue -----
-  const T g1 = T(P.g1), g2 = T(P.g2);
+  // ----- epilogue ----- (its arguments are read only now, which keeps the
+  // scalar registers free during the transform)
+  const Epi<T> epi = ldu(L.epis + gi);
+  const DevParams Pd = ldu(hp.prm + b);
+  const LocalCoef<T> P = local_coef<T>(Pd);
+  const T g1 = T(Pd.g1), g2 = T(Pd.g2);
   const long long N = g.N;
   const T* mb = epi.in + (size_t)b * epi.inst_stride;
-  const bool energy = epi.mode == MODE_ENERGY || epi.mode == MODE_FIELD_ENERGY;
   double esum[5] = {0, 0, 0, 0, 0};
   double emax = 0.0;
-  double hcoef[7];
-  if (epi.mode == MODE_STAGE || epi.mode == MODE_ERROR) {
-    const double h = epi.ctl[b].h_att;
-    for (int j = 0; j < 7; ++j) hcoef[j] = h * epi.coef[j];
-  }
+  // h * coefficients; hlast multiplies the k of this stage (entry nk - 1).
+  // Loops over the 7 slots are unrolled so that every index is a constant.
+  T hcoef[7] = {0, 0, 0, 0, 0, 0, 0};
+  T hlast = T(0);
+  if constexpr (MODE == MODE_STAGE || MODE == MODE_ERROR) {
+    const double h = ldu(&ctl[b].h_att);
 #pragma unroll
-  for (int k = 0; k < kCPT; ++k) {
-    const int e = threadIdx.x + k * blockDim.x;
-    if (e >= ncell) continue;
+    for (int j = 0; j < 7; ++j) {
+      hcoef[j] = j + 1 < epi.nk ? T(h * epi.coef[j]) : T(0);
+      if (j + 1 == epi.nk) hlast = T(h * epi.coef[j]);
+    }
+  }
+  const int ncell = nrow * g.nx;
+  for (int e = threadIdx.x; e < ncell; e += blockDim.x) {
     const int r = e / g.nx, x = e - r * g.nx;
     const int y = y0 + r;
-    if (y >= g.ny) continue;
     const long long i = ((long long)z * g.ny + y) * g.nx + x;
     const V3<T> mi = ld3(mb, N, i);
     LocalTerms lt = {0, 0, 0, 0};
     V3<T> H;
-    if (energy) H = local_field<T, true>(g, P, mb, x, y, z, mi, &lt);
+    if constexpr (energy) H = local_field<T, true>(g, P, mb, x, y, z, mi, &lt);
     else H = local_field<T, false>(g, P, mb, x, y, z, mi, nullptr);
+    V3<T> hd = {T(0), T(0), T(0)};
     if (add_hd) {
-      H.x += Hd[0][k]; H.y += Hd[1][k]; H.z += Hd[2][k];
+      const int kk = pidx(x >> 1);
+      const Cx<T> a = lds[(0 * TY + r) * cs + kk], bq = lds[(1 * TY + r) * cs + kk];
+      const Cx<T> cq = lds[(2 * TY + r) * cs + kk];
+      hd = (x & 1) ? V3<T>{a.y, bq.y, cq.y} : V3<T>{a.x, bq.x, cq.x};
+      H.x += hd.x; H.y += hd.y; H.z += hd.z;
     }
     const size_t o = (size_t)b * epi.inst_stride + i;
-    if (epi.mode == MODE_FIELD || epi.mode == MODE_FIELD_ENERGY) {
-      epi.out[o] = H.x; epi.out[o + N] = H.y; epi.out[o + 2 * N] = H.z;
+    if constexpr (MODE == MODE_FIELD || MODE == MODE_FIELD_ENERGY) {
+      gst(epi.out + o, H.x); gst(epi.out + o + N, H.y); gst(epi.out + o + 2 * N, H.z);
     }
-    if (energy) {
+    if constexpr (energy) {
       esum[0] += lt.ex;
-      if (add_hd) esum[1] += (double)mi.x * Hd[0][k] + (double)mi.y * Hd[1][k] + (double)mi.z * Hd[2][k];
+      if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
       esum[2] += lt.dmi;
       esum[3] += lt.an;
       esum[4] += lt.ze;
-      continue;
     }
-    if (epi.mode == MODE_FIELD) continue;
-    const V3<T> kk = ll_rhs(mi, H, g1, g2);
-    epi.out[o] = kk.x; epi.out[o + N] = kk.y; epi.out[o + 2 * N] = kk.z;
-    if (epi.mode == MODE_STAGE) {
-      // next stage input: m + h sum_j a_j k_j (k of this stage is the last term)
-      V3<T> acc = ld3(epi.mbase + (size_t)b * epi.inst_stride, N, i);
-      for (int j = 0; j + 1 < epi.nk; ++j) {
-        if (hcoef[j] == 0.0) continue;
-        const V3<T> kj = ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
-        const T cj = T(hcoef[j]);
-        acc.x += cj * kj.x; acc.y += cj * kj.y; acc.z += cj * kj.z;
+    if constexpr (MODE == MODE_RHS || MODE == MODE_STAGE || MODE == MODE_ERROR) {
+      const V3<T> kk = ll_rhs(mi, H, g1, g2);
+      gst(epi.out + o, kk.x); gst(epi.out + o + N, kk.y); gst(epi.out + o + 2 * N, kk.z);
+      if constexpr (MODE == MODE_STAGE) {
+        // next stage input: m + h sum_j a_j k_j (k of this stage is the last term)
+        V3<T> acc = ld3(epi.mbase + (size_t)b * epi.inst_stride, N, i);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          if (hcoef[j] == T(0)) continue;
+          const V3<T> kj = ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
+          const T cj = hcoef[j];
+          acc.x += cj * kj.x; acc.y += cj * kj.y; acc.z += cj * kj.z;
+        }
+        const T cl = hlast;
+        acc.x += cl * kk.x; acc.y += cl * kk.y; acc.z += cl * kk.z;
+        gst(epi.msn + o, acc.x); gst(epi.msn + o + N, acc.y); gst(epi.msn + o + 2 * N, acc.z);
+      } else if constexpr (MODE == MODE_ERROR) {
+        double ex = 0, ey = 0, ez = 0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          if (hcoef[j] == T(0)) continue;
+          const V3<T> kj = ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
+          const T cj = hcoef[j];
+          ex += (double)(cj * kj.x); ey += (double)(cj * kj.y); ez += (double)(cj * kj.z);
+        }
+        const T cl = hlast;
+        ex += (double)(cl * kk.x); ey += (double)(cl * kk.y); ez += (double)(cl * kk.z);
+        double en = sqrt(ex * ex + ey * ey + ez * ez);
+        if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
+        emax = fmax(emax, en);
       }
-      const T cl = T(hcoef[epi.nk - 1]);
-      acc.x += cl * kk.x; acc.y += cl * kk.y; acc.z += cl * kk.z;
-      epi.msn[o] = acc.x; epi.msn[o + N] = acc.y; epi.msn[o + 2 * N] = acc.z;
-    } else if (epi.mode == MODE_ERROR) {
-      double ex = 0, ey = 0, ez = 0;
-      for (int j = 0; j + 1 < epi.nk; ++j) {
-        if (hcoef[j] == 0.0) continue;
-        const V3<T> kj = ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
-        const T cj = T(hcoef[j]);
-        ex += (double)(cj * kj.x); ey += (double)(cj * kj.y); ez += (double)(cj * kj.z);
-      }
-      const T cl = T(hcoef[epi.nk - 1]);
-      ex += (double)(cl * kk.x); ey += (double)(cl * kk.y); ez += (double)(cl * kk.z);
-      double en = sqrt(ex * ex + ey * ey + ez * ez);
-      if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
-      emax = fmax(emax, en);
     }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (epi.mode == MODE_ERROR) {
+  if constexpr (MODE == MODE_ERROR) {
     const double w = wave_max(emax);
     if (lane == 0) red[0][wave] = w;
     __syncthreads();
     if (threadIdx.x == 0) {
       double v = red[0][0];
       for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
-      atomicMax(&epi.ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
+      atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
     }
-  } else if (energy) {
+  } else if constexpr (energy) {
     for (int q = 0; q < 5; ++q) {
       const double w = wave_sum(esum[q]);
       if (lane == 0) red[q][wave] = w;
@@ -656,7 +869,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
       const int bpi = tiles * g.nz;
       const int lb = (int)(bid0 % bpi);
-      epi.partial[((size_t)b * bpi + lb) * 5 + threadIdx.x] = v;
+      gst(epi.partial + ((size_t)b * bpi + lb) * 5 + threadIdx.x, v);
     }
   }
 }
@@ -673,8 +886,8 @@ template <typename T>
 __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T>& hp = L.hps[gi];
-  const Epi<T>& ep = L.epis[gi];
+  const HotPlan<T> hp = ldu(L.hps + gi);
+  const Epi<T> ep = ldu(L.epis + gi);
   const Geo& g = hp.g;
   if (bid >= begin_blocks(g, hp.batch)) return;
   const long long N = g.N;
@@ -682,27 +895,27 @@ __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
   const int b = (int)(bid / blocks_per);
   const long long i = (bid % blocks_per) * kNT + threadIdx.x;
   if (i >= N) return;
-  const DevCtl& C = ep.ctl[b];
+  const DevCtl C = ldu(ep.ctl + b);
   const size_t o = (size_t)b * 3 * N + i;
   V3<T> mi;
   V3<T> kv;
   if (C.pending_finish) {
-    const V3<T> y = {ep.bms1[o], ep.bms1[o + N], ep.bms1[o + 2 * N]};
+    const V3<T> y = ld3(ep.bms1, N, (long long)o);
     const T s = rsqrt_t<T>(y.x * y.x + y.y * y.y + y.z * y.z);
     mi = {y.x * s, y.y * s, y.z * s};
-    ep.bm[o] = mi.x; ep.bm[o + N] = mi.y; ep.bm[o + 2 * N] = mi.z;
-    kv = {ep.bk7[o], ep.bk7[o + N], ep.bk7[o + 2 * N]};
-    ep.bk1[o] = kv.x; ep.bk1[o + N] = kv.y; ep.bk1[o + 2 * N] = kv.z;
+    gst(ep.bm + o, mi.x); gst(ep.bm + o + N, mi.y); gst(ep.bm + o + 2 * N, mi.z);
+    kv = ld3(ep.bk7, N, (long long)o);
+    gst(ep.bk1 + o, kv.x); gst(ep.bk1 + o + N, kv.y); gst(ep.bk1 + o + 2 * N, kv.z);
   } else {
     if (C.done) return;
-    mi = {ep.bm[o], ep.bm[o + N], ep.bm[o + 2 * N]};
-    kv = {ep.bk1[o], ep.bk1[o + N], ep.bk1[o + 2 * N]};
+    mi = ld3(ep.bm, N, (long long)o);
+    kv = ld3(ep.bk1, N, (long long)o);
   }
   if (C.done) return;
   const T c = T(C.h_att * ep.a21);
-  ep.bms0[o] = mi.x + c * kv.x;
-  ep.bms0[o + N] = mi.y + c * kv.y;
-  ep.bms0[o + 2 * N] = mi.z + c * kv.z;
+  gst(ep.bms0 + o, mi.x + c * kv.x);
+  gst(ep.bms0 + o + N, mi.y + c * kv.y);
+  gst(ep.bms0 + o + 2 * N, mi.z + c * kv.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -911,12 +1124,51 @@ struct LaunchBuilder {
 };
 
 template <typename T, int PZ>
-void z_reg_launch(const Launch<T>& L, long long total, hipStream_t s) {
-  if constexpr (!(sizeof(T) == 8 && PZ > 16)) {  // FP64 columns beyond 16 points use LDS
+void z_reg_launch(const Launch<T>& L, long long total, bool half, hipStream_t s) {
+  if constexpr (!(sizeof(T) == 8 && PZ > 16)) {  // FP64 columns beyond 16 points use lane pairs
+    if constexpr (PZ % 2 == 0) {
+      if (half) {
+        k_z3d_reg_half<T, PZ><<<dim3((unsigned)total), kNT, 0, s>>>(L);
+        return;
+      }
+    }
     k_z3d_reg<T, PZ><<<dim3((unsigned)total), kNT, 0, s>>>(L);
   }
 }
 
+template <typename T, int M>
+void z_pair_launch(const Launch<T>& L, long long total, hipStream_t s) {
+  k_z3d_pair<T, M><<<dim3((unsigned)total), kNT, 0, s>>>(L);
+}
+
+// Lane-pair register z pass: even Pz with Pz / 2 in {1,2,3,4,6,8,9,12,16}.
+bool z_pair_supported(int Pz) {
+  switch (Pz) {
+    case 2: case 4: case 6: case 8: case 12: case 16: case 18: case 24: case 32:
+      return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T>
+void z_pair_dispatch(int Pz, const Launch<T>& L, long long total, hipStream_t s) {
+  switch (Pz) {
+    case 2: z_pair_launch<T, 1>(L, total, s); break;
+    case 4: z_pair_launch<T, 2>(L, total, s); break;
+    case 6: z_pair_launch<T, 3>(L, total, s); break;
+    case 8: z_pair_launch<T, 4>(L, total, s); break;
+    case 12: z_pair_launch<T, 6>(L, total, s); break;
+    case 16: z_pair_launch<T, 8>(L, total, s); break;
+    case 18: z_pair_launch<T, 9>(L, total, s); break;
+    case 24: z_pair_launch<T, 12>(L, total, s); break;
+    case 32: z_pair_launch<T, 16>(L, total, s); break;
+    default: break;
+  }
+}
+
+// One lane per column: register transforms of every 3-smooth Pz up to 32
+// (FP64: up to 16; beyond that the lane-pair pass holds half the registers).
 template <typename T>
 bool z_reg_supported(int Pz) {
   const int lim = sizeof(T) == 4 ? 32 : 16;
@@ -929,28 +1181,52 @@ bool z_reg_supported(int Pz) {
 }
 
 template <typename T>
-void z_reg_dispatch(int Pz, const Launch<T>& L, long long total, hipStream_t s) {
+void z_reg_dispatch(int Pz, const Launch<T>& L, long long total, bool half, hipStream_t s) {
   switch (Pz) {
-    case 2: z_reg_launch<T, 2>(L, total, s); break;
-    case 3: z_reg_launch<T, 3>(L, total, s); break;
-    case 4: z_reg_launch<T, 4>(L, total, s); break;
-    case 6: z_reg_launch<T, 6>(L, total, s); break;
-    case 8: z_reg_launch<T, 8>(L, total, s); break;
-    case 9: z_reg_launch<T, 9>(L, total, s); break;
-    case 12: z_reg_launch<T, 12>(L, total, s); break;
-    case 16: z_reg_launch<T, 16>(L, total, s); break;
-    case 18: z_reg_launch<T, 18>(L, total, s); break;
-    case 24: z_reg_launch<T, 24>(L, total, s); break;
-    case 27: z_reg_launch<T, 27>(L, total, s); break;
-    case 32: z_reg_launch<T, 32>(L, total, s); break;
+    case 2: z_reg_launch<T, 2>(L, total, half, s); break;
+    case 3: z_reg_launch<T, 3>(L, total, half, s); break;
+    case 4: z_reg_launch<T, 4>(L, total, half, s); break;
+    case 6: z_reg_launch<T, 6>(L, total, half, s); break;
+    case 8: z_reg_launch<T, 8>(L, total, half, s); break;
+    case 9: z_reg_launch<T, 9>(L, total, half, s); break;
+    case 12: z_reg_launch<T, 12>(L, total, half, s); break;
+    case 16: z_reg_launch<T, 16>(L, total, half, s); break;
+    case 18: z_reg_launch<T, 18>(L, total, half, s); break;
+    case 24: z_reg_launch<T, 24>(L, total, half, s); break;
+    case 27: z_reg_launch<T, 27>(L, total, half, s); break;
+    case 32: z_reg_launch<T, 32>(L, total, half, s); break;
     default: break;
   }
 }
 
+// z pass of a group: 0 lane pairs, 1 one lane per column, 2 LDS.  Measured on
+// the 512x512x16 slab: one lane per column is fastest where it fits (FP32);
+// FP64 columns of 32 points go to lane pairs.
+template <typename T>
+int z_kind(int Pz) {
+  if (z_reg_supported<T>(Pz)) return 1;
+  if (z_pair_supported(Pz)) return 0;
+  return 2;
+}
+
 }  // namespace
 
+template <typename T, bool DEMAG>
+void inv_x_launch(int mode, const Launch<T>& L, long long total, int nt, size_t lds, hipStream_t s) {
+  const dim3 grid((unsigned)total);
+  switch (mode) {
+    case MODE_FIELD: k_inv_x<T, DEMAG, MODE_FIELD><<<grid, nt, lds, s>>>(L); break;
+    case MODE_RHS: k_inv_x<T, DEMAG, MODE_RHS><<<grid, nt, lds, s>>>(L); break;
+    case MODE_STAGE: k_inv_x<T, DEMAG, MODE_STAGE><<<grid, nt, lds, s>>>(L); break;
+    case MODE_ERROR: k_inv_x<T, DEMAG, MODE_ERROR><<<grid, nt, lds, s>>>(L); break;
+    case MODE_ENERGY: k_inv_x<T, DEMAG, MODE_ENERGY><<<grid, nt, lds, s>>>(L); break;
+    default: k_inv_x<T, DEMAG, MODE_FIELD_ENERGY><<<grid, nt, lds, s>>>(L); break;
+  }
+}
+
 template <typename T>
-hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hipStream_t s, hipEvent_t* ev) {
+hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool demag, hipStream_t s,
+                       hipEvent_t* ev) {
   const size_t csz = sizeof(Cx<T>);
   int e = 0;
   auto mark = [&]() {
@@ -967,7 +1243,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hi
         const HotPlan<T>& h = gs.h[i];
         lb.set(i, fwd_blocks(h.g, h.tu, h.batch));
         nt = std::max(nt, h.tu.nt_f);
-        lds = std::max(lds, (size_t)h.tu.ty_f * col_stride(h.g.Lx) * csz);
+        lds = std::max(lds, ((size_t)h.tu.ty_f * col_stride(h.g.Lx) + 2 * h.g.Lx + 1) * csz);
       }
       mark();
       k_fwd_x<T><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
@@ -980,7 +1256,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hi
         const HotPlan<T>& h = gs.h[i];
         if (h.g.nz == 1) {
           lb.set(i, y2d_blocks(h.g, h.tu, h.batch));
-          lds = std::max(lds, (size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) * csz);
+          lds = std::max(lds, ((size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) + h.g.Py) * csz);
         } else {
           lb.set(i, y3d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);
@@ -996,26 +1272,32 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hi
       int done_pz[kMaxGroups];
       int ndone = 0;
       mark();
+      // one launch per (Pz, nz == Pz/2) among the groups
       for (int i = 0; i < gs.n; ++i) {
         const HotPlan<T>& hi = gs.h[i];
-        if (hi.g.nz == 1 || !z_reg_supported<T>(hi.g.Pz)) continue;
+        const int kind = z_kind<T>(hi.g.Pz);
+        if (hi.g.nz == 1 || kind == 2) continue;
+        const bool half = 2 * hi.g.nz == hi.g.Pz;
+        const int key = 2 * hi.g.Pz + (half ? 1 : 0);
         bool seen = false;
-        for (int k = 0; k < ndone; ++k) seen = seen || done_pz[k] == hi.g.Pz;
+        for (int k = 0; k < ndone; ++k) seen = seen || done_pz[k] == key;
         if (seen) continue;
-        done_pz[ndone++] = hi.g.Pz;
+        done_pz[ndone++] = key;
         LaunchBuilder<T> lb(gs, epis);
         for (int j = 0; j < gs.n; ++j) {
           const HotPlan<T>& h = gs.h[j];
-          lb.set(j, (h.g.nz > 1 && h.g.Pz == hi.g.Pz) ? zreg_blocks(h.g, h.batch) : 0);
+          const bool use = h.g.nz > 1 && 2 * h.g.Pz + (2 * h.g.nz == h.g.Pz ? 1 : 0) == key;
+          lb.set(j, use ? (kind == 0 ? zpair_blocks(h.g, h.batch) : zreg_blocks(h.g, h.batch)) : 0);
         }
-        z_reg_dispatch<T>(hi.g.Pz, lb.L, lb.total, s);
+        if (kind == 0) z_pair_dispatch<T>(hi.g.Pz, lb.L, lb.total, s);
+        else z_reg_dispatch<T>(hi.g.Pz, lb.L, lb.total, half, s);
       }
       LaunchBuilder<T> lz(gs, epis);
       int nt = 0;
       size_t lds = 0;
       for (int j = 0; j < gs.n; ++j) {
         const HotPlan<T>& h = gs.h[j];
-        const bool use = h.g.nz > 1 && !z_reg_supported<T>(h.g.Pz);
+        const bool use = h.g.nz > 1 && z_kind<T>(h.g.Pz) == 2;
         lz.set(j, use ? zlds_blocks(h.g, h.tu, h.batch) : 0);
         if (use) {
           nt = std::max(nt, 3 * h.tu.qz * h.tu.tpc_z);
@@ -1048,11 +1330,11 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hi
       const HotPlan<T>& h = gs.h[i];
       lb.set(i, inv_blocks(h.g, h.tu, h.batch));
       nt = std::max(nt, h.tu.nt_i);
-      if (demag) lds = std::max(lds, (size_t)h.tu.ty_x * col_stride(h.g.Lx) * csz);
+      if (demag) lds = std::max(lds, ((size_t)3 * h.tu.ty_x * col_stride(h.g.Lx) + 2 * h.g.Lx + 1) * csz);
     }
     mark();
-    if (demag) k_inv_x<T, true><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
-    else k_inv_x<T, false><<<dim3((unsigned)lb.total), nt, 0, s>>>(lb.L);
+    if (demag) inv_x_launch<T, true>(mode, lb.L, lb.total, nt, lds, s);
+    else inv_x_launch<T, false>(mode, lb.L, lb.total, nt, 0, s);
   }
   mark();
   return hipGetLastError();
@@ -1090,7 +1372,7 @@ hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T
 }
 
 #define MMX_INST(T)                                                                               \
-  template hipError_t launch_eval<T>(const GroupSet<T>&, const Epi<T>*, bool, hipStream_t,         \
+  template hipError_t launch_eval<T>(const GroupSet<T>&, const Epi<T>*, int, bool, hipStream_t,    \
                                      hipEvent_t*);                                                \
   template hipError_t launch_begin<T>(const GroupSet<T>&, const Epi<T>*, hipStream_t);            \
   template hipError_t launch_neb<T>(const Geo&, int, const T*, T*, const T*, const double*, double, \

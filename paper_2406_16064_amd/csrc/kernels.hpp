@@ -56,7 +56,7 @@ struct Tuning {
   int tpc_f;    // threads per row of its transform
   int nt_f;     // threads per workgroup
   int ty_x;     // rows per workgroup of the inverse x pass + epilogue
-  int tpc_x;
+  int tpc_x;    // threads per column there (3 * ty_x columns)
   int nt_i;
   int cb_y;     // columns per workgroup of the 3-D y passes
   int tpc_y;
@@ -71,7 +71,7 @@ struct Tuning {
 template <typename T> struct HotPlan {
   Geo g;
   Tuning tu;
-  const FftPlan<T>* fp;    // device array: x (length Px/2), y (Py), z (Pz) radix plans
+  FftDesc<T> fd[3];        // x (length Px/2), y (Py), z (Pz) radix plans
   const Cx<T>* twz;        // z twiddles (register z pass)
   const Cx<T>* post;       // exp(-2 pi i k / Px), k = 0..Lx
   const T* kt;             // tensor spectrum [ncomp][Kz][Xp][Ky]
@@ -102,10 +102,11 @@ template <typename T> struct GroupSet {
 };
 
 // One effective-field evaluation with the fused epilogue for every group
-// (epis: device array [n]).  With ev != nullptr an event is recorded before
-// each pass and after the last one (pass timing; single group only).
+// (epis: device array [n], all with epilogue `mode`).  With ev != nullptr an
+// event is recorded before each pass and after the last one (pass timing;
+// single group only).
 template <typename T>
-hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, bool demag, hipStream_t s,
+hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool demag, hipStream_t s,
                        hipEvent_t* ev = nullptr);
 
 template <typename T>

@@ -13,7 +13,8 @@ constexpr double kMu0 = 4e-7 * 3.14159265358979323846264338327950288;
 constexpr int kMaxFFT = 2048;     // longest 1-D transform supported
 constexpr int kMaxStages = 12;    // radix stages of one transform
 
-template <typename T> struct Cx { T x, y; };
+// Aligned to its full size so that one complex moves in one 8- or 16-byte access.
+template <typename T> struct alignas(2 * sizeof(T)) Cx { T x, y; };
 
 template <typename T> __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T> __device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
@@ -32,6 +33,34 @@ template <typename T> struct FftPlan {
   int ns[kMaxStages];
   const Cx<T>* tw;
 };
+
+// The same plan in the form the kernels take: the radices packed two bits a
+// stage (0: 2, 1: 3, 2: 4, 3: 8), first stage in the lowest bits; the spans
+// follow as running products.  Scalars only, so it lives in scalar registers.
+template <typename T> struct FftDesc {
+  int L;
+  int nst;
+  uint32_t code;
+  uint32_t pad;
+  const Cx<T>* tw;
+};
+
+__host__ __device__ inline int radix_of(uint32_t code, int s) {
+  const uint32_t c = (code >> (2 * s)) & 3u;
+  return c == 0 ? 2 : c == 1 ? 3 : c == 2 ? 4 : 8;
+}
+
+template <typename T> inline FftDesc<T> describe(const FftPlan<T>& p) {
+  FftDesc<T> d{};
+  d.L = p.L;
+  d.nst = p.nst;
+  d.tw = p.tw;
+  for (int s = 0; s < p.nst; ++s) {
+    const uint32_t c = p.rad[s] == 2 ? 0u : p.rad[s] == 3 ? 1u : p.rad[s] == 4 ? 2u : 3u;
+    d.code |= c << (2 * s);
+  }
+  return d;
+}
 
 // Per-instance coefficients, precomputed in FP64 on the host.
 struct DevParams {

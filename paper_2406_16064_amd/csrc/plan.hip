@@ -220,7 +220,6 @@ struct Group {
   void* twx = nullptr;
   void* twy = nullptr;
   void* twz = nullptr;
-  void* fplans = nullptr;
   void* stage = nullptr;  // ms0, ms1, k1..k7: 9 x stage_cap x 3N
   void* mbuf = nullptr;   // contiguous m of the group's instances (batch runs)
   double imag_ratio = 0.0;
@@ -326,35 +325,36 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
   };
   const int tpx = tpc_for(g.Lx);
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
+  const size_t xtab = (size_t)(2 * g.Lx + 1) * csz;  // twiddle + post tables in LDS
+  const size_t ytab = (size_t)g.Py * csz;
   {  // forward x: rows of one component
     const long long rows = 3LL * g.nz * g.ny;
     int ty = 16;
-    while (ty > 1 && ((size_t)ty * rowb > budget || ty * tpx > 512 || rows / ty < want)) ty /= 2;
+    while (ty > 1 && ((size_t)ty * rowb + xtab > budget || ty * tpx > 512 || rows / ty < want)) ty /= 2;
     ty = std::min(ty, g.ny);
-    if ((size_t)ty * rowb > 160 * 1024 || ty * tpx > 512) return fail(MM_E_ARG, "mesh too long along x");
+    if ((size_t)ty * rowb + xtab > 160 * 1024 || ty * tpx > 512) return fail(MM_E_ARG, "mesh too long along x");
     t.ty_f = ty;
     t.nt_f = std::min(512, std::max(64, pow2ceil(std::max(ty * tpx, ty * g.Lx / 4))));
     t.tpc_f = t.nt_f / ty;
   }
-  {  // inverse x + epilogue: rows of all 3 components, at most 8 cells per thread
+  {  // inverse x + epilogue: rows of all 3 components (3 columns per row)
     const long long rows = (long long)g.nz * g.ny;
     int ty = 16;
-    while (ty > 1 && ((size_t)ty * rowb > budget || ty * tpx > 512 || ty * g.nx > 8 * 512 || rows / ty < want))
-      ty /= 2;
+    while (ty > 1 && ((size_t)3 * ty * rowb + xtab > budget || 3 * ty * tpx > 512 || rows / ty < want)) ty /= 2;
     ty = std::min(ty, g.ny);
-    if ((size_t)ty * rowb > 160 * 1024 || ty * tpx > 512 || ty * g.nx > 8 * 512)
+    if ((size_t)3 * ty * rowb + xtab > 160 * 1024 || 3 * ty * tpx > 512)
       return fail(MM_E_ARG, "mesh too long along x");
     t.ty_x = ty;
-    t.nt_i = std::min(512, std::max(64, pow2ceil(std::max(ty * tpx, ty * g.nx))));
-    t.tpc_x = t.nt_i / ty;
+    t.nt_i = std::min(512, std::max(64, pow2ceil(std::max(3 * ty * tpx, ty * g.nx))));
+    t.tpc_x = t.nt_i / (3 * ty);
   }
   const int tmin = tpc_for(g.Py);
   if (g.nz == 1) {
     const int tpc = std::max(tmin, std::min(2 * tmin, 64));
     const size_t colb = 3 * (size_t)col_stride(g.Py) * csz;
     int cb = 8;
-    while (cb > 1 && (cb * colb > budget || 3 * cb * tpc > 512 || g.Xp / cb < want)) cb /= 2;
-    if (cb * colb > 160 * 1024 || 3 * cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
+    while (cb > 1 && (cb * colb + ytab > budget || 3 * cb * tpc > 512 || g.Xp / cb < want)) cb /= 2;
+    if (cb * colb + ytab > 160 * 1024 || 3 * cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y2 = cb;
     t.tpc_y2 = tpc;
     t.nt_y = 3 * cb * tpc;
@@ -395,10 +395,6 @@ mm_status upload_tables(Group& G) {
     post[k] = Cx<T>{(T)std::cos(a), (T)std::sin(a)};
   }
   MMCHK(up(&G.post, post));
-  const FftPlan<T> fp[3] = {make_fft<T>(G.g.Lx, (const Cx<T>*)G.twx), make_fft<T>(G.g.Py, (const Cx<T>*)G.twy),
-                            make_fft<T>(G.g.Pz, (const Cx<T>*)G.twz)};
-  HIPCHK(hipMalloc(&G.fplans, sizeof(fp)));
-  HIPCHK(hipMemcpy(G.fplans, fp, sizeof(fp), hipMemcpyHostToDevice));
   return MM_OK;
 }
 
@@ -431,7 +427,7 @@ mm_status build_spectrum(Group& G, hipStream_t s) {
       e = hipMemcpy(d, tw.data(), sizeof(Cx<double>) * tw.size(), hipMemcpyHostToDevice);
       if (e != hipSuccess) { st = fail(MM_E_HIP, hipGetErrorString(e)); break; }
       FftPlan<double> fp = make_fft<double>(Ls[a], (const Cx<double>*)d);
-      e = setup_fft_axis(F, inner[a], outer[a], fp, min_tpc(fp), s);
+      e = setup_fft_axis(F, inner[a], outer[a], describe(fp), min_tpc(fp), s);
       if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("tensor fft: ") + hipGetErrorString(e)); break; }
     }
     if (st != MM_OK) break;
@@ -466,7 +462,7 @@ mm_status dev_alloc(void** d, size_t bytes) {
 }
 
 void free_group(Group& G) {
-  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.fplans, G.stage, G.mbuf};
+  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.stage, G.mbuf};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   G = Group();
@@ -600,7 +596,9 @@ mm_status make_set(Engine& E, const std::vector<int>& nb, GroupSet<T>& gs, std::
     std::memset(&h, 0, sizeof(h));
     h.g = G.g;
     h.tu = G.tu;
-    h.fp = (const FftPlan<T>*)G.fplans;
+    h.fd[0] = describe(make_fft<T>(G.g.Lx, (const Cx<T>*)G.twx));
+    h.fd[1] = describe(make_fft<T>(G.g.Py, (const Cx<T>*)G.twy));
+    h.fd[2] = describe(make_fft<T>(G.g.Pz, (const Cx<T>*)G.twz));
     h.twz = (const Cx<T>*)G.twz;
     h.post = (const Cx<T>*)G.post;
     h.kt = (const T*)G.kt;
@@ -659,7 +657,7 @@ mm_status single_eval(mm_plan* p, int batch, const mm_params* q, const void* m, 
   ep[0].out = (T*)out;
   ep[0].partial = partial;
   MMCHK(upload_epis<T>(E, 0, ep, s));
-  HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 0), demag_on(E), s, ev));
+  HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 0), mode, demag_on(E), s, ev));
   return MM_OK;
 }
 
@@ -681,7 +679,7 @@ mm_status profile_impl(mm_plan* p, const mm_params* q, int batch, const void* m,
   std::vector<int> inst0;
   mm_status st = make_set<T>(E, std::vector<int>{batch}, gs, inst0, s);
   for (int r = 0; r < reps && st == MM_OK; ++r) {
-    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), demag_on(E), s, ev.data() + (size_t)r * (np + 1));
+    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), MODE_RHS, demag_on(E), s, ev.data() + (size_t)r * (np + 1));
     if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
   }
   if (st == MM_OK) {
@@ -779,7 +777,8 @@ mm_status upload_step_epis(Engine& E, const std::vector<T*>& m, const std::vecto
 template <typename T>
 mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStream_t s) {
   HIPCHK(launch_begin<T>(gs, epi_slot<T>(E, 8), s));
-  for (int st = 2; st <= 7; ++st) HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, st), demag_on(E), s));
+  for (int st = 2; st <= 7; ++st)
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, st), st < 7 ? MODE_STAGE : MODE_ERROR, demag_on(E), s));
   HIPCHK(launch_controller(E.ctl, n_total, E.replay, s));
   return MM_OK;
 }
@@ -842,7 +841,7 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
   MMCHK(upload_step_epis<T>(E, m, inst0, s));
   long long extra_rhs = 0;
   if (need_k1) {
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 1), demag_on(E), s));
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 1), MODE_RHS, demag_on(E), s));
     extra_rhs = 1;
   }
   if (single) {
@@ -1002,7 +1001,7 @@ mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, doub
   const double hg2 = h * (-q->alpha * q->gamma / (1 + q->alpha * q->alpha));
   const int bpi = eval_blocks_per_inst(G.g, G.tu);
   auto iteration = [&](T* cur, T* nxt, hipStream_t ss) -> mm_status {
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, cur == A ? 2 : 3), demag_on(E), ss));
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, cur == A ? 2 : 3), MODE_FIELD_ENERGY, demag_on(E), ss));
     HIPCHK(launch_energy_reduce(E.partial, n_img, bpi, E.e5, ss));
     HIPCHK(launch_neb<T>(G.g, n_img, cur, nxt, (const T*)E.nebH, E.e5, cq, cz, E.nebS, E.nebP, k, hg2, 0, ss));
     HIPCHK(launch_neb<T>(G.g, n_img, cur, nxt, (const T*)E.nebH, E.e5, cq, cz, E.nebS, E.nebP, k, hg2, 1, ss));
@@ -1056,14 +1055,16 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   };
   const size_t lim = 160 * 1024;
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
+  const size_t xtab = (size_t)(2 * g.Lx + 1) * csz;
+  const size_t ytab = (size_t)g.Py * csz;
   if (t.ty_f < 1 || t.ty_f > g.ny || t.nt_f > 512 || t.nt_f < 64 || t.tpc_f * t.ty_f > t.nt_f) return false;
-  if (t.tpc_f < tmin(g.Lx) || (size_t)t.ty_f * rowb > lim) return false;
-  if (t.ty_x < 1 || t.ty_x > g.ny || t.nt_i > 512 || t.nt_i < 64 || t.tpc_x * t.ty_x > t.nt_i) return false;
-  if (t.tpc_x < tmin(g.Lx) || (size_t)t.ty_x * rowb > lim || t.ty_x * g.nx > 8 * t.nt_i) return false;
+  if (t.tpc_f < tmin(g.Lx) || (size_t)t.ty_f * rowb + xtab > lim) return false;
+  if (t.ty_x < 1 || t.ty_x > g.ny || t.nt_i > 512 || t.nt_i < 64 || 3 * t.tpc_x * t.ty_x > t.nt_i) return false;
+  if (t.tpc_x < tmin(g.Lx) || (size_t)3 * t.ty_x * rowb + xtab > lim) return false;
   const size_t colb = (size_t)col_stride(g.Py) * csz;
   if (g.nz == 1) {
     if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
-    if (3 * t.cb_y2 * colb > lim) return false;
+    if (3 * t.cb_y2 * colb + ytab > lim) return false;
   } else {
     if (t.cb_y < 1 || t.nt_y > 512 || t.tpc_y < tmin(g.Py) || t.cb_y * t.tpc_y > t.nt_y) return false;
     if (t.cb_y * colb > lim) return false;
@@ -1082,7 +1083,7 @@ mm_status time_passes(Engine& E, int batch, int reps, std::vector<double>& us, h
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   mm_status st = MM_OK;
   for (int r = 0; r < reps && st == MM_OK; ++r) {
-    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), demag_on(E), s, ev.data() + (size_t)r * (np + 1));
+    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), MODE_RHS, demag_on(E), s, ev.data() + (size_t)r * (np + 1));
     if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
   }
   if (st == MM_OK) {
@@ -1161,7 +1162,7 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
     for (int ty : {1, 2, 4, 8, 16})
       for (int nt : {128, 256, 512}) {
         Tuning t = best;
-        t.ty_x = ty; t.nt_i = nt; t.tpc_x = nt / ty;
+        t.ty_x = ty; t.nt_i = nt; t.tpc_x = nt / (3 * ty);
         c.push_back(t);
       }
     MMCHK(try_all(c, {last}, best));

@@ -159,7 +159,7 @@ __global__ void k_newell_list(mm_mesh mesh, const int32_t* __restrict__ disp, lo
 // Workgroup: cb columns; columns are consecutive outer rows when inner == 1,
 // else consecutive inner positions of one outer row.
 __global__ void __launch_bounds__(512) k_fft_axis(Cx<double>* __restrict__ data, long long inner,
-                                                 long long outer, int cb, int tpc, FftPlan<double> p) {
+                                                 long long outer, int cb, int tpc, FftDesc<double> p) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<double>* lds = reinterpret_cast<Cx<double>*>(smem);
   const int L = p.L;
@@ -226,7 +226,7 @@ hipError_t setup_newell_list(const mm_mesh& mesh, const int32_t* disp, long long
   return hipGetLastError();
 }
 
-hipError_t setup_fft_axis(Cx<double>* data, long long inner, long long outer, const FftPlan<double>& p,
+hipError_t setup_fft_axis(Cx<double>* data, long long inner, long long outer, const FftDesc<double>& p,
                           int tpc, hipStream_t s) {
   if (p.L == 1) return hipSuccess;
   const size_t colb = (size_t)col_stride(p.L) * sizeof(Cx<double>);

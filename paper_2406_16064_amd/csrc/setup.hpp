@@ -10,7 +10,7 @@ hipError_t setup_newell_grid(const mm_mesh& mesh, int Px, int Py, int Pz, int nc
                              hipStream_t s);
 hipError_t setup_newell_list(const mm_mesh& mesh, const int32_t* disp, long long n, double* out,
                              hipStream_t s);
-hipError_t setup_fft_axis(Cx<double>* data, long long inner, long long outer, const FftPlan<double>& p,
+hipError_t setup_fft_axis(Cx<double>* data, long long inner, long long outer, const FftDesc<double>& p,
                           int tpc, hipStream_t s);
 template <typename T>
 hipError_t setup_extract(const Cx<double>* F, int Px, int Py, int Pz, int c, T* kt, unsigned long long* stats,
