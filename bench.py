@@ -72,6 +72,7 @@ def run_workload(mm, inputs, torch, idx, prec, steps, warmup, mesh=None):
     plan = mm.Plan(mesh, prec, terms=w["terms"])
     params = mm.make_params(terms=w["terms"], **w["params"])
     m = torch.tensor(inputs.initial_state(idx, mesh), dtype=dt, device="cuda")
+    shapes = plan.autotune(params, m, reps=5)  # launch shapes measured on this device (not timed)
     st = mm.new_states(1, rtol=w["rtol"])
     t_end = w["t_end"]
     s = plan.rk45_run(params, m, st, t_end=t_end, max_steps=warmup, check=False)
@@ -104,6 +105,7 @@ def run_workload(mm, inputs, torch, idx, prec, steps, warmup, mesh=None):
         "cell_evals_per_s": N * evals / (ms * 1e-3), "ms_per_step": ms / max(attempts, 1),
         "steps": attempts, "rhs_evals": evals, "t_sim": st[0].t, "h": st[0].h,
         "passes": passes,
+        "launch_shapes": shapes,
         "eval_us": round(sum(us), 3),
         "demag_pipeline_gbs": round(sum(pb) / (sum(us) * 1e-6) / 1e9, 1),
     }

@@ -120,11 +120,15 @@ __device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns
     if (active && j < nbf) {
       const int kk = j % Ns;
       if (Ns > 1) {
+        // one table read per butterfly: w^r by repeated products (r < 8 keeps
+        // the extra rounding to a few ulp)
+        Cx<T> w1 = twiddle<T, TWL>(tw, kk * tstep);
+        if (INV) w1.y = -w1.y;
+        Cx<T> w = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = twiddle<T, TWL>(tw, r * kk * tstep);
-          if (INV) w.y = -w.y;
           v[k][r] = cmul(v[k][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
         }
       }
       dftR<T, R, INV>(v[k]);
@@ -199,11 +203,15 @@ __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int
     if (active && j < nbf) {
       const int kk = j % Ns;
       if (Ns > 1) {
+        // one table read per butterfly: w^r by repeated products (r < 8 keeps
+        // the extra rounding to a few ulp)
+        Cx<T> w1 = twiddle<T, TWL>(tw, kk * tstep);
+        if (INV) w1.y = -w1.y;
+        Cx<T> w = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = twiddle<T, TWL>(tw, r * kk * tstep);
-          if (INV) w.y = -w.y;
           v[k][r] = cmul(v[k][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
         }
       }
       dftR<T, R, INV>(v[k]);
