@@ -83,6 +83,36 @@ struct TableCopy {
   }
 };
 
+// The same for nseg segments of a real array: segment k is seg_len entries
+// starting at src + k * seg_stride, stored one after the other in LDS.
+template <typename T, int NPER>
+struct SegTableCopy {
+  T r[NPER];
+  const T* src;
+  size_t stride;
+  int len, n;
+  __device__ __forceinline__ T at(int i) const {
+    const int k = i / len, e = i - k * len;
+    return gld(src + k * stride + e);
+  }
+  __device__ __forceinline__ void issue(const T* src_, size_t stride_, int len_, int nseg) {
+    src = src_; stride = stride_; len = len_; n = len_ * nseg;
+#pragma unroll
+    for (int j = 0; j < NPER; ++j) {
+      const int i = threadIdx.x + j * blockDim.x;
+      if (i < n) r[j] = at(i);
+    }
+  }
+  __device__ __forceinline__ void store(T* dst) const {
+#pragma unroll
+    for (int j = 0; j < NPER; ++j) {
+      const int i = threadIdx.x + j * blockDim.x;
+      if (i < n) dst[i] = r[j];
+    }
+    for (int i = threadIdx.x + NPER * blockDim.x; i < n; i += blockDim.x) dst[i] = at(i);
+  }
+};
+
 // Group of this workgroup and its index inside the group (XCD-ordered).
 template <typename T>
 __device__ __forceinline__ int group_of(const Launch<T>& L, long long& lb) {
@@ -225,19 +255,37 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
     if (y < ny && kx0 + j < Xp) gst(base + ((size_t)c * Xp + kx0 + j) * ny + y, v);
   };
   const int tpc = blockDim.x / ncol;
-  // twiddle table (Py) in LDS after the columns, copied while the first loads fly
+  // LDS after the columns: the twiddle table (Py) and the tensor rows of this
+  // tile, kt[a][j][ky] for the components a = xx, yy, zz, xy and the CB kx
+  // (nz = 1: one kz plane), both copied while the first stage's loads fly
   Cx<T>* const twl = lds + ncol * cs;
+  T* const ktl = reinterpret_cast<T*>(twl + g.Py);
+  const int ncb = Xp - kx0 < CB ? Xp - kx0 : CB;  // kx of this tile inside the spectrum
   TableCopy<T, 4> tab;
   tab.issue(hp.fd[1].tw, g.Py, nullptr, 0);
-  auto hook = [&]() { tab.store(twl); };
+  SegTableCopy<T, 8> ktab;
+  ktab.issue(hp.kt + (size_t)kx0 * g.Ky, (size_t)g.Kz * g.Xp * g.Ky, ncb * g.Ky, 4);
+  auto hook = [&]() {
+    tab.store(twl);
+    ktab.store(ktl);
+  };
   fft_columns_io<T, false, true, false, true>(lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, hook);
   const T s = T(ldu(&hp.prm[b].demag_scale));
-  for (int t = threadIdx.x; t < CB * g.Py; t += blockDim.x) {
+  const int seg = ncb * g.Ky;
+  for (int t = threadIdx.x; t < ncb * g.Py; t += blockDim.x) {
     const int j = t / g.Py, ky = t - j * g.Py;
-    const int kx = kx0 + j;
-    if (kx >= g.Xp) continue;
-    tensor_apply(hp, kx, ky, 0, s, lds[(0 * CB + j) * cs + pidx(ky)], lds[(1 * CB + j) * cs + pidx(ky)],
-                 lds[(2 * CB + j) * cs + pidx(ky)]);
+    const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
+    const T sy = ky > g.Py - ky ? T(-1) : T(1);
+    const int o = j * g.Ky + kyf;
+    const T kxx = ktl[o] * s, kyy = ktl[seg + o] * s, kzz = ktl[2 * seg + o] * s;
+    const T kxy = ktl[3 * seg + o] * (s * sy);
+    Cx<T>& m0 = lds[(0 * CB + j) * cs + pidx(ky)];
+    Cx<T>& m1 = lds[(1 * CB + j) * cs + pidx(ky)];
+    Cx<T>& m2 = lds[(2 * CB + j) * cs + pidx(ky)];
+    const Cx<T> a = m0, bq = m1, c = m2;
+    m0 = {kxx * a.x + kxy * bq.x, kxx * a.y + kxy * bq.y};
+    m1 = {kxy * a.x + kyy * bq.x, kxy * a.y + kyy * bq.y};
+    m2 = {kzz * c.x, kzz * c.y};
   }
   __syncthreads();
   fft_columns_io<T, true, false, true, true>(lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, NoHook{});
@@ -606,24 +654,37 @@ __device__ __forceinline__ LocalCoef<T> local_coef(const DevParams& P) {
   return c;
 }
 
-template <typename T, bool ENERGY>
-__device__ __forceinline__ V3<T> local_field(const Geo& g, const LocalCoef<T>& P, const T* __restrict__ mb,
-                                             int x, int y, int z, V3<T> mi, LocalTerms* lt) {
+// m at a cell and its six neighbours (zero where the mesh ends or no term needs them)
+template <typename T> struct Nbr { V3<T> mi, xm, xp, ym, yp, zm, zp; };
+
+template <typename T>
+__device__ __forceinline__ Nbr<T> load_nbr(const Geo& g, uint32_t terms, const T* __restrict__ mb, int x, int y,
+                                           int z) {
   const long long N = g.N;
   const long long i = ((long long)z * g.ny + y) * g.nx + x;
+  Nbr<T> n;
+  n.mi = ld3(mb, N, i);
+  n.xm = {T(0), T(0), T(0)};
+  n.xp = n.xm; n.ym = n.xm; n.yp = n.xm; n.zm = n.xm; n.zp = n.xm;
+  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL)) {
+    if (x > 0) n.xm = ld3(mb, N, i - 1);
+    if (x + 1 < g.nx) n.xp = ld3(mb, N, i + 1);
+    if (y > 0) n.ym = ld3(mb, N, i - g.nx);
+    if (y + 1 < g.ny) n.yp = ld3(mb, N, i + g.nx);
+    if (z > 0) n.zm = ld3(mb, N, i - (long long)g.nx * g.ny);
+    if (z + 1 < g.nz) n.zp = ld3(mb, N, i + (long long)g.nx * g.ny);
+  }
+  return n;
+}
+
+template <typename T, bool ENERGY>
+__device__ __forceinline__ V3<T> local_field(const Geo& g, const LocalCoef<T>& P, const Nbr<T>& nb, int x, int y,
+                                             int z, LocalTerms* lt) {
+  const V3<T> mi = nb.mi;
   V3<T> H = {T(0), T(0), T(0)};
-  const bool need_nb = (P.terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL)) != 0;
-  V3<T> xm = {T(0), T(0), T(0)}, xp = xm, ym = xm, yp = xm, zm = xm, zp = xm;
+  const V3<T> xm = nb.xm, xp = nb.xp, ym = nb.ym, yp = nb.yp, zm = nb.zm, zp = nb.zp;
   const bool hxm = x > 0, hxp = x + 1 < g.nx, hym = y > 0, hyp = y + 1 < g.ny;
   const bool hzm = z > 0, hzp = z + 1 < g.nz;
-  if (need_nb) {
-    if (hxm) xm = ld3(mb, N, i - 1);
-    if (hxp) xp = ld3(mb, N, i + 1);
-    if (hym) ym = ld3(mb, N, i - g.nx);
-    if (hyp) yp = ld3(mb, N, i + g.nx);
-    if (hzm) zm = ld3(mb, N, i - (long long)g.nx * g.ny);
-    if (hzp) zp = ld3(mb, N, i + (long long)g.nx * g.ny);
-  }
   if (P.terms & MM_EXCHANGE) {
     const T cx = P.cex[0], cy = P.cex[1], cz = P.cex[2];
     V3<T> e = {T(0), T(0), T(0)};
@@ -685,8 +746,18 @@ int eval_blocks_per_inst(const Geo& g, const Tuning& tu) {
   return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz;
 }
 
-template <typename T, bool DEMAG, int MODE>
+// CPT > 0: every thread owns at most CPT cells (the host checks TY nx <= CPT
+// threads) and the cell loop is unrolled; CPT == 1 also loads the cell's
+// epilogue inputs (m and neighbours, the step's m and slopes) before the
+// transform, so their latency overlaps it.  CPT == 0: any number of cells.
+// FUSE (MODE_STAGE, DEMAG, CPT > 0): the next stage input just formed for
+// these rows is transformed forward along x here, into the same Sx rows this
+// workgroup read (no other workgroup touches them), which takes the forward x
+// pass of the next evaluation off the critical path.
+template <typename T, bool DEMAG, int MODE, int CPT, bool FUSE>
 __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
+  constexpr bool PREF = CPT == 1;
+  static_assert(!FUSE || (MODE == MODE_STAGE && DEMAG && CPT > 0), "fused forward pass needs a stage epilogue");
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   __shared__ double red[5][512 / 64];
@@ -699,15 +770,44 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   const int TY = hp.tu.ty_x;
   const int tiles = (g.ny + TY - 1) / TY;
   long long bid = bid0;
-  const int tile = bid % tiles; bid /= tiles;
-  const int z = bid % g.nz;
-  const int b = (int)(bid / g.nz);
+  // z varies fastest: the workgroups of planes z - 1, z, z + 1 of a tile (which
+  // read each other's m as the z halo) are neighbours in the XCD-ordered grid
+  const int z = bid % g.nz; bid /= g.nz;
+  const int tile = bid % tiles;
+  const int b = (int)(bid / tiles);
   DevCtl* const ctl = ldu(&L.epis[gi].ctl);
   if (ctl && ldu(&ctl[b].done)) return;
   const bool add_hd = DEMAG && (ldu(&hp.prm[b].terms) & MM_DEMAG);
   const int y0 = tile * TY;
   const int nrow = g.ny - y0 < TY ? g.ny - y0 : TY;
   const int cs = col_stride(g.Lx);
+  const int ncell = nrow * g.nx;
+  const long long N = g.N;
+
+  // prefetch of the single cell's epilogue inputs (PREF)
+  Nbr<T> pnb;
+  V3<T> pbase = {T(0), T(0), T(0)};
+  V3<T> pk[6];
+  if constexpr (PREF) {
+    const Epi<T>* ep = L.epis + gi;
+    const int e = threadIdx.x;
+    const int r = e / g.nx, x = e - r * g.nx;
+    const int ec = e < ncell ? e : 0;  // idle lanes read the first cell and drop it
+    const int rc = ec / g.nx, xc = ec - rc * g.nx;
+    (void)r; (void)x;
+    const size_t ib = (size_t)b * ldu(&ep->inst_stride);
+    const long long i = ((long long)z * g.ny + y0 + rc) * g.nx + xc;
+    pnb = load_nbr<T>(g, ldu(&hp.prm[b].terms), ldu(&ep->in) + ib, xc, y0 + rc, z);
+    if constexpr (MODE == MODE_STAGE) pbase = ld3(ldu(&ep->mbase) + ib, N, i);
+    if constexpr (MODE == MODE_STAGE || MODE == MODE_ERROR) {
+      const int nk = ldu(&ep->nk);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        pk[j] = {T(0), T(0), T(0)};
+        if (j + 1 < nk && ldu(&ep->coef[j]) != 0.0) pk[j] = ld3(ldu(&ep->kprev[j]) + ib, N, i);
+      }
+    }
+  }
 
   // LDS: 3 TY columns, then the twiddle table (Lx) and the post factors (Lx + 1)
   Cx<T>* const twl = lds + 3 * TY * cs;
@@ -770,7 +870,6 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   const DevParams Pd = ldu(hp.prm + b);
   const LocalCoef<T> P = local_coef<T>(Pd);
   const T g1 = T(Pd.g1), g2 = T(Pd.g2);
-  const long long N = g.N;
   const T* mb = epi.in + (size_t)b * epi.inst_stride;
   double esum[5] = {0, 0, 0, 0, 0};
   double emax = 0.0;
@@ -786,16 +885,17 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       if (j + 1 == epi.nk) hlast = T(h * epi.coef[j]);
     }
   }
-  const int ncell = nrow * g.nx;
-  for (int e = threadIdx.x; e < ncell; e += blockDim.x) {
+  V3<T> mnext[CPT > 0 ? CPT : 1];
+  auto cell = [&](int e, int slot) {
     const int r = e / g.nx, x = e - r * g.nx;
     const int y = y0 + r;
     const long long i = ((long long)z * g.ny + y) * g.nx + x;
-    const V3<T> mi = ld3(mb, N, i);
+    const Nbr<T> nb = PREF ? pnb : load_nbr<T>(g, P.terms, mb, x, y, z);
+    const V3<T> mi = nb.mi;
     LocalTerms lt = {0, 0, 0, 0};
     V3<T> H;
-    if constexpr (energy) H = local_field<T, true>(g, P, mb, x, y, z, mi, &lt);
-    else H = local_field<T, false>(g, P, mb, x, y, z, mi, nullptr);
+    if constexpr (energy) H = local_field<T, true>(g, P, nb, x, y, z, &lt);
+    else H = local_field<T, false>(g, P, nb, x, y, z, nullptr);
     V3<T> hd = {T(0), T(0), T(0)};
     if (add_hd) {
       const int kk = pidx(x >> 1);
@@ -820,23 +920,24 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       gst(epi.out + o, kk.x); gst(epi.out + o + N, kk.y); gst(epi.out + o + 2 * N, kk.z);
       if constexpr (MODE == MODE_STAGE) {
         // next stage input: m + h sum_j a_j k_j (k of this stage is the last term)
-        V3<T> acc = ld3(epi.mbase + (size_t)b * epi.inst_stride, N, i);
+        V3<T> acc = PREF ? pbase : ld3(epi.mbase + (size_t)b * epi.inst_stride, N, i);
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
           if (hcoef[j] == T(0)) continue;
-          const V3<T> kj = ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
+          const V3<T> kj = PREF ? pk[j] : ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
           const T cj = hcoef[j];
           acc.x += cj * kj.x; acc.y += cj * kj.y; acc.z += cj * kj.z;
         }
         const T cl = hlast;
         acc.x += cl * kk.x; acc.y += cl * kk.y; acc.z += cl * kk.z;
         gst(epi.msn + o, acc.x); gst(epi.msn + o + N, acc.y); gst(epi.msn + o + 2 * N, acc.z);
+        if constexpr (FUSE) mnext[slot] = acc;
       } else if constexpr (MODE == MODE_ERROR) {
         double ex = 0, ey = 0, ez = 0;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
           if (hcoef[j] == T(0)) continue;
-          const V3<T> kj = ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
+          const V3<T> kj = PREF ? pk[j] : ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
           const T cj = hcoef[j];
           ex += (double)(cj * kj.x); ey += (double)(cj * kj.y); ez += (double)(cj * kj.z);
         }
@@ -846,6 +947,59 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
         if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
         emax = fmax(emax, en);
       }
+    }
+    (void)slot;
+  };
+  if constexpr (CPT == 0) {
+    for (int e = threadIdx.x; e < ncell; e += blockDim.x) cell(e, 0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int e = threadIdx.x + k * blockDim.x;
+      if (e < ncell) cell(e, k);
+    }
+  }
+
+  if constexpr (FUSE) {
+    // forward x transform of the next stage input of these rows, into Sx
+    const int ncol = 3 * TY;
+    __syncthreads();  // every thread is done reading H_d from the columns
+    // real view of column col: x -> 2 pidx(x >> 1) + (x & 1); zero beyond nx
+    T* const re = reinterpret_cast<T*>(lds);
+    const int rcs = 2 * cs;
+    for (int t = threadIdx.x; t < ncol * (2 * g.Lx - g.nx); t += blockDim.x) {
+      const int col = t / (2 * g.Lx - g.nx), x = g.nx + (t - col * (2 * g.Lx - g.nx));
+      re[col * rcs + 2 * pidx(x >> 1) + (x & 1)] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int e = threadIdx.x + k * blockDim.x;
+      if (e < ncell) {
+        const int r = e / g.nx, x = e - r * g.nx;
+        const int off = 2 * pidx(x >> 1) + (x & 1);
+        re[(0 * TY + r) * rcs + off] = mnext[k].x;
+        re[(1 * TY + r) * rcs + off] = mnext[k].y;
+        re[(2 * TY + r) * rcs + off] = mnext[k].z;
+      }
+    }
+    __syncthreads();
+    fft_columns<T, false, true>(lds, hp.fd[0], cs, ncol, (int)blockDim.x / ncol, twl);
+    // real-to-complex post-processing and transposed store (the rows this
+    // workgroup read at the start)
+    const size_t cstride = (size_t)g.nz * g.Xp * g.ny;
+    Cx<T>* dst = hp.Sx + (size_t)b * g.sx + (size_t)z * g.Xp * g.ny + y0;
+    const int tot = ncol * g.Xp;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+      const int r = t % TY, q = t / TY;
+      const int k = q % g.Xp, c = q / g.Xp;
+      if (r >= nrow) continue;
+      const Cx<T>* cp = lds + (c * TY + r) * cs;
+      const Cx<T> Zk = cp[pidx(k == g.Lx ? 0 : k)];
+      const Cx<T> Zc = cconj(cp[pidx(k == 0 ? 0 : g.Lx - k)]);
+      const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
+      const Cx<T> D = cscale(csub(Zk, Zc), T(0.5));
+      const Cx<T> O = {D.y, -D.x};  // D / i
+      gst(dst + c * cstride + (size_t)k * g.ny + r, cadd(E, cmul(postl[k], O)));
     }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1211,22 +1365,64 @@ int z_kind(int Pz) {
 
 }  // namespace
 
-template <typename T, bool DEMAG>
-void inv_x_launch(int mode, const Launch<T>& L, long long total, int nt, size_t lds, hipStream_t s) {
+template <typename T, bool DEMAG, int CPT>
+void inv_x_launch_c(int mode, bool fuse, const Launch<T>& L, long long total, int nt, size_t lds, hipStream_t s) {
   const dim3 grid((unsigned)total);
   switch (mode) {
-    case MODE_FIELD: k_inv_x<T, DEMAG, MODE_FIELD><<<grid, nt, lds, s>>>(L); break;
-    case MODE_RHS: k_inv_x<T, DEMAG, MODE_RHS><<<grid, nt, lds, s>>>(L); break;
-    case MODE_STAGE: k_inv_x<T, DEMAG, MODE_STAGE><<<grid, nt, lds, s>>>(L); break;
-    case MODE_ERROR: k_inv_x<T, DEMAG, MODE_ERROR><<<grid, nt, lds, s>>>(L); break;
-    case MODE_ENERGY: k_inv_x<T, DEMAG, MODE_ENERGY><<<grid, nt, lds, s>>>(L); break;
-    default: k_inv_x<T, DEMAG, MODE_FIELD_ENERGY><<<grid, nt, lds, s>>>(L); break;
+    case MODE_FIELD: k_inv_x<T, DEMAG, MODE_FIELD, CPT, false><<<grid, nt, lds, s>>>(L); break;
+    case MODE_RHS: k_inv_x<T, DEMAG, MODE_RHS, CPT, false><<<grid, nt, lds, s>>>(L); break;
+    case MODE_STAGE:
+      if constexpr (DEMAG && CPT > 0) {
+        if (fuse) {
+          k_inv_x<T, DEMAG, MODE_STAGE, CPT, true><<<grid, nt, lds, s>>>(L);
+          break;
+        }
+      }
+      k_inv_x<T, DEMAG, MODE_STAGE, CPT, false><<<grid, nt, lds, s>>>(L);
+      break;
+    case MODE_ERROR: k_inv_x<T, DEMAG, MODE_ERROR, CPT, false><<<grid, nt, lds, s>>>(L); break;
+    case MODE_ENERGY: k_inv_x<T, DEMAG, MODE_ENERGY, CPT, false><<<grid, nt, lds, s>>>(L); break;
+    default: k_inv_x<T, DEMAG, MODE_FIELD_ENERGY, CPT, false><<<grid, nt, lds, s>>>(L); break;
   }
+}
+
+// cpt: cells per thread of the unrolled epilogue (1, 2, 4, 8) or 0 (loop)
+template <typename T, bool DEMAG>
+void inv_x_launch(int mode, int cpt, bool fuse, const Launch<T>& L, long long total, int nt, size_t lds,
+                  hipStream_t s) {
+  switch (cpt) {
+    case 1: inv_x_launch_c<T, DEMAG, 1>(mode, fuse, L, total, nt, lds, s); break;
+    case 2: inv_x_launch_c<T, DEMAG, 2>(mode, fuse, L, total, nt, lds, s); break;
+    case 4: inv_x_launch_c<T, DEMAG, 4>(mode, fuse, L, total, nt, lds, s); break;
+    case 8: inv_x_launch_c<T, DEMAG, 8>(mode, fuse, L, total, nt, lds, s); break;
+    default: inv_x_launch_c<T, DEMAG, 0>(mode, false, L, total, nt, lds, s); break;
+  }
+}
+
+// Cells per thread of the unrolled inverse-x epilogue for a launch with nt
+// threads (0: none of 1, 2, 4, 8 fits every group).
+template <typename T>
+int inv_cpt(const GroupSet<T>& gs, int nt) {
+  int need = 1;
+  for (int i = 0; i < gs.n; ++i) {
+    const int c = (gs.h[i].tu.ty_x * gs.h[i].g.nx + nt - 1) / nt;
+    need = std::max(need, c);
+  }
+  for (int c : {1, 2, 4, 8})
+    if (need <= c) return c;
+  return 0;
+}
+
+template <typename T>
+bool eval_fusable(const GroupSet<T>& gs) {
+  int nt = 64;
+  for (int i = 0; i < gs.n; ++i) nt = std::max(nt, gs.h[i].tu.nt_i);
+  return inv_cpt(gs, nt) > 0;
 }
 
 template <typename T>
 hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool demag, hipStream_t s,
-                       hipEvent_t* ev) {
+                       hipEvent_t* ev, bool skip_fwd, bool fuse_next) {
   const size_t csz = sizeof(Cx<T>);
   int e = 0;
   auto mark = [&]() {
@@ -1235,7 +1431,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
   bool any3d = false;
   for (int i = 0; i < gs.n; ++i) any3d = any3d || gs.h[i].g.nz > 1;
   if (demag) {
-    {  // x forward
+    if (!skip_fwd) {  // x forward (skipped when the previous stage's inverse-x pass did it)
       LaunchBuilder<T> lb(gs, epis);
       int nt = 64;
       size_t lds = 0;
@@ -1256,7 +1452,8 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         const HotPlan<T>& h = gs.h[i];
         if (h.g.nz == 1) {
           lb.set(i, y2d_blocks(h.g, h.tu, h.batch));
-          lds = std::max(lds, ((size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) + h.g.Py) * csz);
+          lds = std::max(lds, ((size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) + h.g.Py) * csz +
+                                  (size_t)4 * h.tu.cb_y2 * h.g.Ky * (csz / 2));
         } else {
           lb.set(i, y3d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);
@@ -1332,9 +1529,11 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
       nt = std::max(nt, h.tu.nt_i);
       if (demag) lds = std::max(lds, ((size_t)3 * h.tu.ty_x * col_stride(h.g.Lx) + 2 * h.g.Lx + 1) * csz);
     }
+    const int cpt = inv_cpt(gs, nt);
+    const bool fuse = fuse_next && demag && mode == MODE_STAGE && cpt > 0;
     mark();
-    if (demag) inv_x_launch<T, true>(mode, lb.L, lb.total, nt, lds, s);
-    else inv_x_launch<T, false>(mode, lb.L, lb.total, nt, 0, s);
+    if (demag) inv_x_launch<T, true>(mode, cpt, fuse, lb.L, lb.total, nt, lds, s);
+    else inv_x_launch<T, false>(mode, cpt, false, lb.L, lb.total, nt, 0, s);
   }
   mark();
   return hipGetLastError();
@@ -1373,7 +1572,8 @@ hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T
 
 #define MMX_INST(T)                                                                               \
   template hipError_t launch_eval<T>(const GroupSet<T>&, const Epi<T>*, int, bool, hipStream_t,    \
-                                     hipEvent_t*);                                                \
+                                     hipEvent_t*, bool, bool);                                    \
+  template bool eval_fusable<T>(const GroupSet<T>&);                                              \
   template hipError_t launch_begin<T>(const GroupSet<T>&, const Epi<T>*, hipStream_t);            \
   template hipError_t launch_neb<T>(const Geo&, int, const T*, T*, const T*, const double*, double, \
                                     double, double*, double*, double, double, int, hipStream_t);

@@ -105,9 +105,16 @@ template <typename T> struct GroupSet {
 // (epis: device array [n], all with epilogue `mode`).  With ev != nullptr an
 // event is recorded before each pass and after the last one (pass timing;
 // single group only).
+// skip_fwd: the forward x pass was already done by the previous launch's
+// inverse-x pass (fuse_next there).  fuse_next (MODE_STAGE): the inverse-x
+// pass also transforms the next stage input forward along x; ignored where
+// the launch shape does not allow it -- eval_fusable() tells in advance.
 template <typename T>
 hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool demag, hipStream_t s,
-                       hipEvent_t* ev = nullptr);
+                       hipEvent_t* ev = nullptr, bool skip_fwd = false, bool fuse_next = false);
+
+template <typename T>
+bool eval_fusable(const GroupSet<T>& gs);
 
 template <typename T>
 hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s);

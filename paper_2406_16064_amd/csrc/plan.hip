@@ -327,6 +327,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
   const size_t xtab = (size_t)(2 * g.Lx + 1) * csz;  // twiddle + post tables in LDS
   const size_t ytab = (size_t)g.Py * csz;
+  const size_t ktab2 = (size_t)4 * g.Ky * (csz / 2);  // per kx column of the fused 2-D y pass
   {  // forward x: rows of one component
     const long long rows = 3LL * g.nz * g.ny;
     int ty = 16;
@@ -353,8 +354,9 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
     const int tpc = std::max(tmin, std::min(2 * tmin, 64));
     const size_t colb = 3 * (size_t)col_stride(g.Py) * csz;
     int cb = 8;
-    while (cb > 1 && (cb * colb + ytab > budget || 3 * cb * tpc > 512 || g.Xp / cb < want)) cb /= 2;
-    if (cb * colb + ytab > 160 * 1024 || 3 * cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
+    while (cb > 1 && (cb * (colb + ktab2) + ytab > budget || 3 * cb * tpc > 512 || g.Xp / cb < want)) cb /= 2;
+    if (cb * (colb + ktab2) + ytab > 160 * 1024 || 3 * cb * tpc > 512)
+      return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y2 = cb;
     t.tpc_y2 = tpc;
     t.nt_y = 3 * cb * tpc;
@@ -777,8 +779,12 @@ mm_status upload_step_epis(Engine& E, const std::vector<T*>& m, const std::vecto
 template <typename T>
 mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStream_t s) {
   HIPCHK(launch_begin<T>(gs, epi_slot<T>(E, 8), s));
+  // stages 2..6 transform the next stage input forward along x in their
+  // inverse-x pass when the launch shape allows it; stages 3..7 then skip it
+  const bool fz = demag_on(E) && eval_fusable<T>(gs);
   for (int st = 2; st <= 7; ++st)
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, st), st < 7 ? MODE_STAGE : MODE_ERROR, demag_on(E), s));
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, st), st < 7 ? MODE_STAGE : MODE_ERROR, demag_on(E), s, nullptr,
+                          fz && st > 2, fz && st < 7));
   HIPCHK(launch_controller(E.ctl, n_total, E.replay, s));
   return MM_OK;
 }
@@ -1064,7 +1070,7 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   const size_t colb = (size_t)col_stride(g.Py) * csz;
   if (g.nz == 1) {
     if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
-    if (3 * t.cb_y2 * colb + ytab > lim) return false;
+    if (3 * t.cb_y2 * colb + ytab + (size_t)4 * t.cb_y2 * g.Ky * (csz / 2) > lim) return false;
   } else {
     if (t.cb_y < 1 || t.nt_y > 512 || t.tpc_y < tmin(g.Py) || t.cb_y * t.tpc_y > t.nt_y) return false;
     if (t.cb_y * colb > lim) return false;
