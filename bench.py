@@ -57,6 +57,46 @@ def pass_bytes(mesh, P, w):
     return [m + sx, sx + sy, sy + K + sy, sy + sx, sx + m + m]
 
 
+# Dormand-Prince slopes read by the stage combinations of stages 2..6 (entries
+# of a_{s+1,j}, j < s, that are non-zero) and by the error combination
+STAGE_KPREV = (1, 2, 3, 4, 4)
+ERROR_KPREV = 5
+
+
+def step_kernel_bytes(mesh, P, w, fused):
+    """Algorithmic HBM bytes per launch of the attempt-only kernels: the step
+    begin as timed (fresh state: read m, k1; write the stage-2 input; after an
+    accepted attempt it also projects y5 and copies k7), the inverse-x pass with the
+    stage epilogue (read Sx, stage input, m, the slopes of its combination;
+    write k_s and the next stage input, and the next x spectrum when fused;
+    mean over stages 2..6) and with the error epilogue (read Sx, stage input,
+    five slopes; write k7)."""
+    nx, ny, nz = mesh[:3]
+    Xp = P[0] // 2 + 1
+    sx = 3 * nz * Xp * ny * 2 * w
+    f = 3 * nx * ny * nz * w  # one m-like array
+    kp = sum(STAGE_KPREV) / len(STAGE_KPREV)
+    return {"step_begin": 3 * f,
+            "x_inv_stage": sx + (2 + kp) * f + 2 * f + (sx if fused else 0),
+            "x_inv_error": sx + (1 + ERROR_KPREV) * f + f}
+
+
+def attempt_breakdown(mesh, P, w, passes_us, step):
+    """Time of each kernel kind per adaptive attempt from the back-to-back
+    launch timings: (name, launches per attempt, us per launch, alg bytes)."""
+    b_us, stage_us, err_us, fused = step
+    names = pass_names(mesh[2])
+    kb = step_kernel_bytes(mesh, P, w, fused)
+    pb = dict(zip(names, pass_bytes(mesh, P, w)))
+    rows = [("step_begin", 1, b_us, kb["step_begin"])]
+    for name, us in zip(names[:-1], stage_us[:-1]):
+        n = (1 if fused else 6) if name == "x_fwd" else 6
+        rows.append((name, n, us, pb[name]))
+    rows.append(("x_inv_stage" + ("_fused_fwd" if fused else ""), 5, stage_us[-1], kb["x_inv_stage"]))
+    rows.append(("x_inv_error", 1, err_us, kb["x_inv_error"]))
+    return rows
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_2406_16064_amd", "csrc"))):
@@ -94,17 +134,24 @@ def run_workload(mm, inputs, torch, idx, prec, steps, warmup, mesh=None):
     N = mesh[0] * mesh[1] * mesh[2]
     P = plan.padded()
     us = plan.profile_passes(params, m, reps=30)
+    step = plan.profile_step(params, m, st, reps=20)
     w_bytes = 4 if prec == "f32" else 8
     pb = pass_bytes(mesh, P, w_bytes)
     passes = []
     for name, t, b in zip(pass_names(mesh[2]), us, pb):
         passes.append({"kernel": name, "us": round(t, 3), "alg_bytes": b,
                        "gbs": round(b / (t * 1e-6) / 1e9, 1)})
+    attempt = []
+    for name, n, t, b in attempt_breakdown(mesh, P, w_bytes, us, step):
+        attempt.append({"kernel": name, "per_attempt": n, "us": round(t, 3), "alg_bytes": int(b),
+                        "gbs": round(b / (t * 1e-6) / 1e9, 1), "us_per_attempt": round(n * t, 2)})
     out = {
         "workload": w["name"], "mesh": list(mesh), "padded": list(P), "dtype": prec,
         "cell_evals_per_s": N * evals / (ms * 1e-3), "ms_per_step": ms / max(attempts, 1),
         "steps": attempts, "rhs_evals": evals, "t_sim": st[0].t, "h": st[0].h,
         "passes": passes,
+        "attempt_kernels": attempt,
+        "attempt_kernel_us": round(sum(a["us_per_attempt"] for a in attempt), 2),
         "launch_shapes": shapes,
         "eval_us": round(sum(us), 3),
         "demag_pipeline_gbs": round(sum(pb) / (sum(us) * 1e-6) / 1e9, 1),
@@ -193,12 +240,16 @@ def neb_bench(mm, inputs, torch, iters=100):
             "barrier_estimate_J": float(np.max(E) - E[0])}
 
 
-def roofline(res, traffic):
-    dom = max(res["passes"], key=lambda p: p["us"])
+def roofline(res, workload):
+    """Roofline of the kernel that takes the most time per adaptive attempt
+    (launches per attempt x back-to-back launch duration)."""
+    dom = max(res["attempt_kernels"], key=lambda p: p["us_per_attempt"])
     ach = dom["gbs"]
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["kernel"],
-            "alg_bytes_per_launch": dom["alg_bytes"], "us_per_launch": dom["us"]}
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(workload, dom["kernel"]),
+            "kernel": dom["kernel"], "alg_bytes_per_launch": dom["alg_bytes"], "us_per_launch": dom["us"],
+            "launches_per_attempt": dom["per_attempt"], "share_of_attempt": round(
+                dom["us_per_attempt"] / res["attempt_kernel_us"], 3)}
 
 
 def load_traffic(workload, kernel):
@@ -218,8 +269,9 @@ def load_traffic(workload, kernel):
 
 
 # kernel-name fragments of each pass in rocprofv3 output
-PASS_KERNELS = {"x_fwd": "k_fwd_x<", "y_fused_product": "k_ypass<", "y_fwd": "k_ypass<",
-                "z_product": "k_z3d_pair<", "y_inv": "k_yinv<", "x_inv_fused_llg": "k_inv_x<"}
+PASS_KERNELS = {"x_fwd": ("k_fwd_x<",), "y_fused_product": ("k_ypass<",), "y_fwd": ("k_ypass<",),
+                "z_product": ("k_z3d_reg_half<", "k_z3d_reg<", "k_z3d_pair<", "k_z3d<"), "y_inv": ("k_yinv<",),
+                "x_inv_fused_llg": ("k_inv_x<",)}
 COPY_BYTES = 1 << 30
 
 
@@ -258,11 +310,11 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     wr = _counter_rows(write_csv)
     out = {}
     for name in pass_names(mesh_nz):
-        frag = PASS_KERNELS[name]
-        if name == "x_inv_fused_llg":
-            keys = [k for k in fr if frag in k and k.rstrip(")").find(", 1>") > 0]
+        frags = PASS_KERNELS[name]
+        if name == "x_inv_fused_llg":  # the dm/dt (MODE_RHS = 1) instance with the demag transform
+            keys = [k for k in fr if frags[0] in k and ", true, 1," in k]
         else:
-            keys = [k for k in fr if frag in k]
+            keys = [k for f in frags for k in fr if f in k]
         if not keys:
             continue
         k = keys[0]
@@ -271,6 +323,22 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
         fb = sum(f) / len(f) * 1024.0 * kf
         wb = sum(w) / len(w) * 1024.0 * kw
         out[name] = {"kernel": k, "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
+    # the attempt-only kernels: mean over every dispatch (the stage kernel runs
+    # stages 2..6 in equal numbers in the graph replays and in the step timing)
+    step_kinds = {"step_begin": lambda k: "k_begin<" in k,
+                  "x_inv_stage": lambda k: "k_inv_x<" in k and ", true, 2," in k and k.split("(")[0].endswith("false>"),
+                  "x_inv_stage_fused_fwd": lambda k: "k_inv_x<" in k and ", true, 2," in k and
+                  k.split("(")[0].endswith("true>"),
+                  "x_inv_error": lambda k: "k_inv_x<" in k and ", true, 3," in k}
+    for name, sel in step_kinds.items():
+        keys = [k for k in fr if sel(k)]
+        if not keys:
+            continue
+        f = [v for k in keys for v in fr[k]]
+        w = [v for k in keys for v in wr.get(k, [])] or [0.0]
+        fb = sum(f) / len(f) * 1024.0 * kf
+        wb = sum(w) / len(w) * 1024.0 * kw
+        out[name] = {"kernel": "; ".join(keys), "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     d = {}
     if os.path.exists(path):
@@ -375,8 +443,7 @@ def main():
             extra["slab3d_" + prec] = r3
         extra["slab3d_fp32_over_fp64"] = (extra["slab3d_f32"]["cell_evals_per_s"] /
                                           extra["slab3d_f64"]["cell_evals_per_s"])
-        dom3 = max(extra["slab3d_f32"]["passes"], key=lambda p: p["us"])["kernel"]
-        extra["slab3d_f32"]["roofline"] = roofline(extra["slab3d_f32"], load_traffic("slab3d_f32", dom3))
+        extra["slab3d_f32"]["roofline"] = roofline(extra["slab3d_f32"], "slab3d_f32")
         print("bench: sweep batched vs one by one", file=sys.stderr, flush=True)
         extra["sweep"] = sweep_bench(mm, inputs, torch)
         print("bench: neb", file=sys.stderr, flush=True)
@@ -386,8 +453,7 @@ def main():
         print("bench: cpu oracle", file=sys.stderr, flush=True)
         cpu, kern = cpu_baseline(inputs, mesh)
         extra["field_rel_err_f32"] = field_error(mm, torch, plan, params, inputs, mesh, kern)
-    rl = roofline(res, None)
-    rl["traffic"] = load_traffic("thinfilm_f32", rl["kernel"])
+    rl = roofline(res, "thinfilm_f32")
     line = {
         "metric": METRIC,
         "value": res["cell_evals_per_s"],

@@ -191,16 +191,31 @@ mm_status mm_batch_destroy(mm_batch* batch);
 mm_status mm_plan_autotune(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
                            void* work, int32_t reps, int32_t* shape_out, void* hip_stream);
 
-/* Measurement aid: runs `reps` dm/dt evaluations of `batch` instances (output
- * written to `work`, same layout as m) with a HIP event before every kernel
- * pass and after the last one, and returns in us_out[0..*n_pass) the mean
- * duration of each pass in microseconds, in launch order: x forward, y (2-D:
- * fused forward/product/inverse; 3-D: forward, z with product, inverse),
- * x inverse with the fused local fields and LL.  Without demag there is one
- * pass.  us_out must hold at least 5 entries.  Synchronises. */
+/* Measurement aid: after one dm/dt evaluation of `batch` instances (output
+ * written to `work`, same layout as m), launches each kernel pass `reps`
+ * times back to back between two HIP events on hip_stream and returns in
+ * us_out[0..*n_pass) the mean duration of one launch of each pass in
+ * microseconds, in launch order: x forward, y (2-D: fused forward/product/
+ * inverse; 3-D: forward, z with product, inverse), x inverse with the fused
+ * local fields and LL (dm/dt epilogue).  Without demag there is one pass.
+ * us_out must hold at least 5 entries.  Synchronises. */
 mm_status mm_profile_passes(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
                             void* work, int32_t reps, double* us_out, int32_t* n_pass,
                             void* hip_stream);
+
+/* Measurement aid for the adaptive step: sets up one Dormand-Prince attempt of
+ * `batch` instances from m and the states st (as mm_rk45_run would; neither m
+ * nor st is advanced; the stage buffers and the first slope are computed),
+ * then times each kernel of the attempt `reps` times back to back between two
+ * HIP events on hip_stream.  us_out[0]: the step-begin kernel; us_out[1 .. n-2]:
+ * the passes of one stage evaluation in launch order, the last of them the
+ * inverse-x pass with the stage epilogue (mean over stages 2..6, in the form
+ * the captured attempt runs: with the next stage's forward x transform when
+ * *fused_out is 1); us_out[n-1]: the inverse-x pass with the error epilogue.
+ * *n_out = passes + 2 (at most 7); us_out must hold 8 entries.  Synchronises. */
+mm_status mm_profile_step(mm_plan* plan, const mm_params* params, int32_t batch, void* m,
+                          const mm_rk45_state* st, int32_t reps, double* us_out, int32_t* n_out,
+                          int32_t* fused_out, void* hip_stream);
 
 const char* mm_status_string(mm_status s);
 const char* mm_last_error(void);

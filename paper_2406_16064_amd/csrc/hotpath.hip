@@ -1422,7 +1422,7 @@ bool eval_fusable(const GroupSet<T>& gs) {
 
 template <typename T>
 hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool demag, hipStream_t s,
-                       hipEvent_t* ev, bool skip_fwd, bool fuse_next) {
+                       hipEvent_t* ev, bool skip_fwd, bool fuse_next, unsigned pass_mask) {
   const size_t csz = sizeof(Cx<T>);
   int e = 0;
   auto mark = [&]() {
@@ -1430,8 +1430,11 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
   };
   bool any3d = false;
   for (int i = 0; i < gs.n; ++i) any3d = any3d || gs.h[i].g.nz > 1;
+  // pass numbers: 0 x forward, 1 y, 2 z (3-D), 3 y inverse (3-D), last x inverse
+  auto on = [&](int p) { return ((pass_mask >> p) & 1u) != 0; };
+  const int p_inv = demag ? (any3d ? 4 : 2) : 0;
   if (demag) {
-    if (!skip_fwd) {  // x forward (skipped when the previous stage's inverse-x pass did it)
+    if (!skip_fwd && on(0)) {  // x forward (skipped when the previous stage's inverse-x pass did it)
       LaunchBuilder<T> lb(gs, epis);
       int nt = 64;
       size_t lds = 0;
@@ -1444,7 +1447,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
       mark();
       k_fwd_x<T><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
     }
-    {  // y forward (2-D groups: fused forward / product / inverse)
+    if (on(1)) {  // y forward (2-D groups: fused forward / product / inverse)
       LaunchBuilder<T> lb(gs, epis);
       int nt = 64;
       size_t lds = 0;
@@ -1470,7 +1473,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
       int ndone = 0;
       mark();
       // one launch per (Pz, nz == Pz/2) among the groups
-      for (int i = 0; i < gs.n; ++i) {
+      for (int i = 0; i < gs.n && on(2); ++i) {
         const HotPlan<T>& hi = gs.h[i];
         const int kind = z_kind<T>(hi.g.Pz);
         if (hi.g.nz == 1 || kind == 2) continue;
@@ -1501,7 +1504,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
           lds = std::max(lds, (size_t)3 * h.tu.qz * col_stride(h.g.Pz) * csz);
         }
       }
-      if (nt > 0) k_z3d<T><<<dim3((unsigned)lz.total), nt, lds, s>>>(lz.L);
+      if (nt > 0 && on(2)) k_z3d<T><<<dim3((unsigned)lz.total), nt, lds, s>>>(lz.L);
       // y inverse
       LaunchBuilder<T> ly(gs, epis);
       int nty = 64;
@@ -1516,10 +1519,10 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         }
       }
       mark();
-      k_yinv<T><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
+      if (on(3)) k_yinv<T><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
     }
   }
-  {  // x inverse + epilogue
+  if (on(p_inv)) {  // x inverse + epilogue
     LaunchBuilder<T> lb(gs, epis);
     int nt = 64;
     size_t lds = 0;
@@ -1572,7 +1575,7 @@ hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T
 
 #define MMX_INST(T)                                                                               \
   template hipError_t launch_eval<T>(const GroupSet<T>&, const Epi<T>*, int, bool, hipStream_t,    \
-                                     hipEvent_t*, bool, bool);                                    \
+                                     hipEvent_t*, bool, bool, unsigned);                          \
   template bool eval_fusable<T>(const GroupSet<T>&);                                              \
   template hipError_t launch_begin<T>(const GroupSet<T>&, const Epi<T>*, hipStream_t);            \
   template hipError_t launch_neb<T>(const Geo&, int, const T*, T*, const T*, const double*, double, \

@@ -109,9 +109,13 @@ template <typename T> struct GroupSet {
 // inverse-x pass (fuse_next there).  fuse_next (MODE_STAGE): the inverse-x
 // pass also transforms the next stage input forward along x; ignored where
 // the launch shape does not allow it -- eval_fusable() tells in advance.
+// pass_mask: bit p launches pass p (0 x forward, 1 y, 2 z, 3 y inverse, then
+// x inverse: bit 4 in 3-D, bit 2 in 2-D, bit 0 without demag) -- for timing
+// single passes.
 template <typename T>
 hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool demag, hipStream_t s,
-                       hipEvent_t* ev = nullptr, bool skip_fwd = false, bool fuse_next = false);
+                       hipEvent_t* ev = nullptr, bool skip_fwd = false, bool fuse_next = false,
+                       unsigned pass_mask = ~0u);
 
 template <typename T>
 bool eval_fusable(const GroupSet<T>& gs);

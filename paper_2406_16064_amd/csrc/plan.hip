@@ -668,38 +668,47 @@ int pass_count(const Engine& E) {
   return E.groups[0].g.nz == 1 ? 3 : 5;
 }
 
+// Back-to-back timing: `reps` launches of one pass between two events on the
+// launch stream, for each pass in turn (after one full evaluation that fills
+// every intermediate buffer).  us[p] = mean duration of pass p.
+template <typename T>
+mm_status time_each_pass(Engine& E, const GroupSet<T>& gs, const Epi<T>* epis, int mode, int reps, int np,
+                         double* us, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t er = hipEventCreate(&e1);
+  if (er != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(MM_E_HIP, hipGetErrorString(er));
+  }
+  mm_status st = MM_OK;
+  er = launch_eval<T>(gs, epis, mode, demag_on(E), s);
+  for (int i = 0; i < np && er == hipSuccess; ++i) {
+    const unsigned bit = (unsigned)i;  // pass i in launch order has bit i (see launch_eval)
+    er = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && er == hipSuccess; ++r)
+      er = launch_eval<T>(gs, epis, mode, demag_on(E), s, nullptr, false, false, 1u << bit);
+    if (er == hipSuccess) er = hipEventRecord(e1, s);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+    us[i] = 1e3 * ms / reps;
+  }
+  if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 template <typename T>
 mm_status profile_impl(mm_plan* p, const mm_params* q, int batch, const void* m, void* out, int reps, double* us,
                        hipStream_t s) {
   Engine& E = p->e;
-  // first call sets parameters and tables; then time `reps` evaluations
   MMCHK(single_eval<T>(p, batch, q, m, out, MODE_RHS, nullptr, s));
-  const int np = pass_count(E);
-  std::vector<hipEvent_t> ev((size_t)(np + 1) * reps);
-  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   GroupSet<T> gs;
   std::vector<int> inst0;
-  mm_status st = make_set<T>(E, std::vector<int>{batch}, gs, inst0, s);
-  for (int r = 0; r < reps && st == MM_OK; ++r) {
-    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), MODE_RHS, demag_on(E), s, ev.data() + (size_t)r * (np + 1));
-    if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
-  }
-  if (st == MM_OK) {
-    hipError_t er = hipStreamSynchronize(s);
-    if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
-  }
-  for (int i = 0; i < np && st == MM_OK; ++i) {
-    double acc = 0.0;
-    for (int r = 0; r < reps; ++r) {
-      float ms = 0.f;
-      hipError_t er = hipEventElapsedTime(&ms, ev[(size_t)r * (np + 1) + i], ev[(size_t)r * (np + 1) + i + 1]);
-      if (er != hipSuccess) { st = fail(MM_E_HIP, hipGetErrorString(er)); break; }
-      acc += ms;
-    }
-    us[i] = 1e3 * acc / reps;
-  }
-  for (auto& x : ev) (void)hipEventDestroy(x);
-  return st;
+  MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
+  return time_each_pass<T>(E, gs, epi_slot<T>(E, 0), MODE_RHS, reps, pass_count(E), us, s);
 }
 
 template <typename T>
@@ -789,13 +798,76 @@ mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStre
   return MM_OK;
 }
 
+// Timing of the kernels of one adaptive attempt (measurement aid): us[0] the
+// step-begin kernel, us[1 .. np] the passes of a stage evaluation with its
+// inverse-x pass in the form the captured attempt uses (stage epilogue, fused
+// forward x when fused), us[np + 1] the inverse-x pass with the error
+// epilogue.  Stage-epilogue and the forward-x figures average stages 2..6.
+struct StepProfile {
+  int reps = 0;
+  double us[16] = {};
+  int n = 0;
+  int fused = 0;
+};
+
+template <typename T>
+mm_status profile_step(Engine& E, const GroupSet<T>& gs, StepProfile& pr, hipStream_t s) {
+  const int np = pass_count(E);
+  const bool fz = demag_on(E) && eval_fusable<T>(gs);
+  pr.fused = fz ? 1 : 0;
+  pr.n = np + 2;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t er = hipEventCreate(&e1);
+  if (er != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(MM_E_HIP, hipGetErrorString(er));
+  }
+  auto timed = [&](auto&& launch) -> double {
+    float ms = 0.f;
+    if (er == hipSuccess) er = hipEventRecord(e0, s);
+    for (int r = 0; r < pr.reps && er == hipSuccess; ++r) er = launch();
+    if (er == hipSuccess) er = hipEventRecord(e1, s);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+    return 1e3 * ms / pr.reps;
+  };
+  // the step-begin kernel (stage-2 input from m and k1), then one full stage
+  // so that every intermediate buffer holds data
+  pr.us[0] = timed([&]() { return launch_begin<T>(gs, epi_slot<T>(E, 8), s); });
+  if (er == hipSuccess) er = launch_eval<T>(gs, epi_slot<T>(E, 2), MODE_STAGE, demag_on(E), s);
+  for (int i = 0; i < np && er == hipSuccess; ++i) {
+    const unsigned bit = 1u << i;
+    double acc = 0.0;
+    if (i + 1 < np) {  // transform passes: the same kernels in every stage
+      acc = timed([&]() { return launch_eval<T>(gs, epi_slot<T>(E, 2), MODE_STAGE, demag_on(E), s, nullptr, false,
+                                                false, bit); });
+    } else {  // inverse x with the stage epilogue: mean over stages 2..6
+      for (int stg = 2; stg <= 6 && er == hipSuccess; ++stg)
+        acc += timed([&]() { return launch_eval<T>(gs, epi_slot<T>(E, stg), MODE_STAGE, demag_on(E), s, nullptr,
+                                                   false, fz, bit); });
+      acc /= 5.0;
+    }
+    pr.us[1 + i] = acc;
+  }
+  const unsigned last = 1u << (np - 1);
+  pr.us[np + 1] = timed([&]() { return launch_eval<T>(gs, epi_slot<T>(E, 7), MODE_ERROR, demag_on(E), s, nullptr,
+                                                      false, false, last); });
+  mm_status st = er == hipSuccess ? MM_OK : fail(MM_E_HIP, hipGetErrorString(er));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 // Integrate the instances of every group.  m[i]: contiguous state of group i's
-// nb[i] instances; q / st / t_end: per instance, in group order.
+// nb[i] instances; q / st / t_end: per instance, in group order.  With prof
+// set, only times the attempt's kernels after the set-up (no state advance).
 template <typename T>
 mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& nb,
                    const std::vector<const mm_params*>& q, std::vector<mm_rk45_state*>& st,
                    const std::vector<double>& t_end, long long max_steps, const double* replay_h,
-                   long long n_replay, bool single, std::vector<int>& status, hipStream_t s) {
+                   long long n_replay, bool single, std::vector<int>& status, hipStream_t s,
+                   StepProfile* prof = nullptr) {
   const int ng = (int)E.groups.size();
   const int n_total = (int)q.size();
   std::vector<int> grp;
@@ -850,6 +922,7 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
     HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 1), MODE_RHS, demag_on(E), s));
     extra_rhs = 1;
   }
+  if (prof) return profile_step<T>(E, gs, *prof, s);
   if (single) {
     MMCHK(enqueue_attempt<T>(E, gs, n_total, s));
   } else {
@@ -909,7 +982,8 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
 
 template <typename T>
 mm_status plan_rk45(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45_state* st, double t_end,
-                    long long max_steps, const double* replay_h, long long n_replay, bool single, hipStream_t s) {
+                    long long max_steps, const double* replay_h, long long n_replay, bool single, hipStream_t s,
+                    StepProfile* prof = nullptr) {
   std::vector<const mm_params*> qv(batch);
   std::vector<mm_rk45_state*> sv(batch);
   for (int b = 0; b < batch; ++b) {
@@ -918,7 +992,7 @@ mm_status plan_rk45(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45
   }
   std::vector<int> status;
   return run_core<T>(p->e, std::vector<T*>{(T*)mv}, std::vector<int>{batch}, qv, sv,
-                     std::vector<double>(batch, t_end), max_steps, replay_h, n_replay, single, status, s);
+                     std::vector<double>(batch, t_end), max_steps, replay_h, n_replay, single, status, s, prof);
 }
 
 template <typename T>
@@ -1164,14 +1238,42 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
     MMCHK(try_all(c, G.g.nz > 1 ? std::vector<int>{1, 3} : std::vector<int>{1}, best));
   }
   {
-    std::vector<Tuning> c;
+    // inverse-x shapes are chosen for the adaptive step, where the pass runs
+    // with the stage epilogues (and, where the shape allows, the next stage's
+    // forward x transform): cost = the inverse-x and forward-x launches of
+    // one attempt, timed back to back from a temporary state
+    std::vector<mm_rk45_state> tmp(batch);
+    for (auto& r : tmp) {
+      std::memset(&r, 0, sizeof(r));
+      r.h = 1e-13; r.rtol = 1e-6; r.h_min = 1e-20; r.h_max = 1e-10;
+    }
+    std::vector<const mm_params*> qv(batch);
+    std::vector<mm_rk45_state*> sv(batch);
+    for (int b = 0; b < batch; ++b) { qv[b] = &q[b]; sv[b] = &tmp[b]; }
+    double best_us = 1e300;
+    Tuning pick = best;
     for (int ty : {1, 2, 4, 8, 16})
       for (int nt : {128, 256, 512}) {
         Tuning t = best;
         t.ty_x = ty; t.nt_i = nt; t.tpc_x = nt / (3 * ty);
-        c.push_back(t);
+        if (!tuning_ok(G, t, E.prec, E.csz)) continue;
+        G.tu = t;
+        MMCHK(engine_reserve(E, std::vector<int>{p->maxb}));
+        StepProfile pr;
+        pr.reps = reps;
+        std::vector<int> status;
+        MMCHK(run_core<T>(E, std::vector<T*>{(T*)const_cast<void*>(m)}, std::vector<int>{batch}, qv, sv,
+                          std::vector<double>(batch, 1.0), 1, nullptr, 0, true, status, s, &pr));
+        const int n = pr.n;  // begin, passes..., error
+        double cost = 5.0 * pr.us[n - 2] + pr.us[n - 1];
+        if (demag_on(E)) cost += (pr.fused ? 1.0 : 6.0) * pr.us[1];
+        if (cost < best_us) {
+          best_us = cost;
+          pick = t;
+        }
       }
-    MMCHK(try_all(c, {last}, best));
+    best = pick;
+    (void)last;
   }
   G.tu = best;
   MMCHK(engine_reserve(E, std::vector<int>{p->maxb}));
@@ -1304,6 +1406,27 @@ mm_status mm_rk45_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm
   return p->e.prec == MM_F32
              ? plan_rk45<float>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s)
              : plan_rk45<double>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s);
+}
+
+mm_status mm_profile_step(mm_plan* p, const mm_params* q, int32_t batch, void* m, const mm_rk45_state* st,
+                          int32_t reps, double* us_out, int32_t* n_out, int32_t* fused_out, void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch));
+  if (!m || !st || !us_out || !n_out || !fused_out) return fail(MM_E_ARG, "null argument");
+  if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<mm_rk45_state> copy(st, st + batch);  // the caller's states are not advanced
+  StepProfile pr;
+  pr.reps = reps;
+  const double t_end = copy[0].t + 1.0;  // any end beyond one step
+  mm_status r = p->e.prec == MM_F32
+                    ? plan_rk45<float>(p, q, batch, m, copy.data(), t_end, 1, nullptr, 0, true, s, &pr)
+                    : plan_rk45<double>(p, q, batch, m, copy.data(), t_end, 1, nullptr, 0, true, s, &pr);
+  if (r != MM_OK) return r;
+  HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < pr.n; ++i) us_out[i] = pr.us[i];
+  *n_out = pr.n;
+  *fused_out = pr.fused;
+  return MM_OK;
 }
 
 mm_status mm_profile_passes(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work, int32_t reps,

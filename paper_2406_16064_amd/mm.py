@@ -63,6 +63,7 @@ _sigs = {
     "mm_rk45_run": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _i64, _vp],
     "mm_neb_run": [_vp, _P(Params), _vp, _i32, _dbl, _dbl, _i64, _P(_dbl), _vp],
     "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
+    "mm_profile_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _i32, _P(_dbl), _P(_i32), _P(_i32), _vp],
     "mm_plan_autotune": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
     "mm_batch_create": [_P(_vp), _P(Mesh), _i32, ctypes.c_int, ctypes.c_uint32, _vp],
     "mm_batch_run": [_vp, _P(Instance), _i32, _i64, _vp],
@@ -231,6 +232,17 @@ class Plan:
         _check(_lib.mm_profile_passes(self._h, _params_array(params), self._batch(m), _ptr(m), _ptr(work),
                                       reps, us, ctypes.byref(n), _stream(stream)), "mm_profile_passes")
         return list(us[:n.value])
+
+    def profile_step(self, params, m, states, reps=20, stream=None):
+        """Mean duration (us) of each kernel of one adaptive attempt, launched back to back:
+        returns (begin_us, [stage pass us...], error_x_inverse_us, fused)."""
+        us = (ctypes.c_double * 8)()
+        n = _i32()
+        fused = _i32()
+        _check(_lib.mm_profile_step(self._h, _params_array(params), self._batch(m), _ptr(m), states, reps, us,
+                                    ctypes.byref(n), ctypes.byref(fused), _stream(stream)), "mm_profile_step")
+        v = list(us[:n.value])
+        return v[0], v[1:-1], v[-1], bool(fused.value)
 
     def close(self):
         if self._h:

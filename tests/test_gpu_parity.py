@@ -344,3 +344,25 @@ def test_autotune_keeps_results(mm):
     assert field_err(after, before) <= 1e-6, shape
     ref = F.llg_rhs(m, F.Mesh(*mesh), oracle_params(PAR, F.ALL_TERMS), _kernel(mesh))
     assert field_err(after, ref) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_profile_step_leaves_state(mm):
+    """The attempt-kernel timing advances neither m nor the state, and a run
+    after it matches a run without it (bit for bit)."""
+    mesh = (40, 24, 2, 2e-9, 2e-9, 2e-9)
+    m = representable(_rand_m(mesh, 71), torch.float32)
+    gp = gpu_params(mm, PAR, mm.ALL_TERMS)
+    outs = []
+    for prof in (False, True):
+        plan = mm.Plan(mesh, "f32", terms=mm.ALL_TERMS)
+        md = to_dev(m, torch.float32)
+        st = mm.new_states(1, rtol=1e-5, h=1e-13)
+        if prof:
+            b, stage, err, fused = plan.profile_step(gp, md, st, reps=2)
+            assert b > 0 and err > 0 and all(t > 0 for t in stage) and len(stage) == 5
+            assert st[0].t == 0.0 and st[0].n_rhs == 0
+            assert torch.equal(md.cpu(), torch.from_numpy(m).float())
+        plan.rk45_run(gp, md, st, t_end=1e-12, max_steps=20, check=False)
+        outs.append((md.cpu().numpy(), st[0].t, st[0].n_accept))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
