@@ -286,12 +286,17 @@ def copy_reference(torch):
     return {"copy_bytes": COPY_BYTES, "copies": 5}
 
 
-def _counter_rows(path):
+def _counter_rows(path, full=False):
+    """Kernel name -> counter values in dispatch order (full: also the launch
+    signature (grid, workgroup, LDS) of each dispatch)."""
     import csv
     rows = {}
     with open(path) as fh:
         for r in csv.DictReader(fh):
-            rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+            v = float(r["Counter_Value"])
+            if full:
+                v = (v, (r["Grid_Size"], r["Workgroup_Size"], r["LDS_Block_Size"]))
+            rows.setdefault(r["Kernel_Name"], []).append(v)
     return rows
 
 
@@ -323,22 +328,28 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
         fb = sum(f) / len(f) * 1024.0 * kf
         wb = sum(w) / len(w) * 1024.0 * kw
         out[name] = {"kernel": k, "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
-    # the attempt-only kernels: mean over every dispatch (the stage kernel runs
-    # stages 2..6 in equal numbers in the graph replays and in the step timing)
+    # the attempt-only kernels: mean over the dispatches with the launch shape
+    # of the last one (the autotuner's pick; the stage kernel runs stages 2..6
+    # in equal numbers in the graph replays and in the step timing)
+    frf = _counter_rows(fetch_csv, True)
+    wrf = _counter_rows(write_csv, True)
     step_kinds = {"step_begin": lambda k: "k_begin<" in k,
                   "x_inv_stage": lambda k: "k_inv_x<" in k and ", true, 2," in k and k.split("(")[0].endswith("false>"),
                   "x_inv_stage_fused_fwd": lambda k: "k_inv_x<" in k and ", true, 2," in k and
                   k.split("(")[0].endswith("true>"),
                   "x_inv_error": lambda k: "k_inv_x<" in k and ", true, 3," in k}
     for name, sel in step_kinds.items():
-        keys = [k for k in fr if sel(k)]
+        keys = [k for k in frf if sel(k)]
         if not keys:
             continue
-        f = [v for k in keys for v in fr[k]]
-        w = [v for k in keys for v in wr.get(k, [])] or [0.0]
+        k = max(keys, key=lambda kk: len(frf[kk]))  # the instantiation the timed attempts ran
+        sig = frf[k][-1][1]
+        f = [v for v, g in frf[k] if g == sig]
+        w = [v for v, g in wrf.get(k, []) if g == sig] or [0.0]
         fb = sum(f) / len(f) * 1024.0 * kf
         wb = sum(w) / len(w) * 1024.0 * kw
-        out[name] = {"kernel": "; ".join(keys), "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
+        out[name] = {"kernel": k, "launch": "grid %s, workgroup %s, LDS %s" % sig, "dispatches": len(f),
+                     "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     d = {}
     if os.path.exists(path):
@@ -474,6 +485,8 @@ def main():
         "roofline": rl,
         "cpu_baseline": cpu,
         "passes": res["passes"],
+        "attempt_kernels": res["attempt_kernels"],
+        "launch_shapes": res["launch_shapes"],
         "extra": extra,
         "source_hash": source_hash(),
     }

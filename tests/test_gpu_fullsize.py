@@ -1,0 +1,216 @@
+"""GPU parity at the benchmark's full sizes, in the launch shapes bench.py times.
+
+* 256x256x1 thin film (FP32, FP64): the whole field and dm/dt against the
+  oracle, element by element, and an FP32 trajectory replaying the oracle's
+  accepted steps.
+* 512x512x16 slab (FP32, FP64): a sparse-source state (a few unit vectors in an
+  otherwise empty mesh), so that the oracle computes sampled cells one by one:
+  demag as the plain sum over the sources of -Ms N(r_i - r_s) m_s with the
+  oracle's Newell tensor, the local terms on the clipped 3x3x3 neighbourhood.
+* 32-image NEB chain on 128x128x1 and the uneven sweep's largest meshes
+  against the oracle.
+
+Plans are autotuned first (as bench.py does) except the batch, which bench.py
+runs with its default shapes.
+"""
+import numpy as np
+import pytest
+
+from oracle import dp45, neb, newell
+from oracle import fields as F
+from paper_2406_16064_amd import inputs
+
+from _util import field_err, gpu_params, oracle_params, representable, to_dev
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f32": torch.float32, "f64": torch.float64}
+TOL = {"f32": 1e-5, "f64": 1e-10}
+MU0 = 4e-7 * np.pi
+
+
+@pytest.fixture(scope="module")
+def mm():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_2406_16064_amd import mm as m
+    return m
+
+
+_kern = {}
+
+
+def _kernel(mesh):
+    if mesh not in _kern:
+        _kern[mesh] = F.DemagKernel(F.Mesh(*mesh))
+    return _kern[mesh]
+
+
+# ----------------------------------------------------------------------------- thin film
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_thin_film_full_size_dense(mm, prec):
+    w = inputs.workload(1)
+    mesh = tuple(w["mesh"])
+    m = representable(inputs.initial_state(1), DT[prec])
+    plan = mm.Plan(mesh, prec, terms=w["terms"])
+    gp = gpu_params(mm, w["params"], w["terms"])
+    md = to_dev(m, DT[prec])
+    plan.autotune(gp, md, reps=2)
+    op = oracle_params(w["params"], w["terms"])
+    Href = F.effective_field(m, F.Mesh(*mesh), op, _kernel(mesh))
+    assert field_err(plan.effective_field(gp, md).cpu().numpy(), Href) <= TOL[prec]
+    kref = F.llg_rhs_from_field(m, Href, op)
+    assert field_err(plan.llg_rhs(gp, md).cpu().numpy(), kref) <= TOL[prec]
+
+
+def test_thin_film_full_size_replay_fp32(mm):
+    """Ten accepted oracle steps replayed by the autotuned FP32 graph: m within 1e-4."""
+    w = inputs.workload(1)
+    mesh = tuple(w["mesh"])
+    m0 = representable(inputs.initial_state(1), torch.float32)
+    op = oracle_params(w["params"], w["terms"])
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+    ost = dp45.State(rtol=w["rtol"])
+    mo = dp45.run(f, m0.copy(), ost, max_accept=10)
+    plan = mm.Plan(mesh, "f32", terms=w["terms"])
+    gp = gpu_params(mm, w["params"], w["terms"])
+    md = to_dev(m0, torch.float32)
+    plan.autotune(gp, md, reps=2)
+    st = mm.new_states(1, rtol=w["rtol"])
+    plan.rk45_run(gp, md, st, replay_h=ost.accepted_h)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-4
+
+
+# ----------------------------------------------------------------------------- 3-D slab
+
+
+def _sparse_slab(nsrc, seed):
+    """The slab mesh with nsrc random unit vectors at distinct random cells, zero elsewhere."""
+    w = inputs.workload(2)
+    nx, ny, nz = w["mesh"][:3]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    flat = rng.choice(nx * ny * nz, size=nsrc, replace=False)
+    src = np.stack(np.unravel_index(flat, (nz, ny, nx)), axis=1)  # (k, j, i)
+    m = np.zeros((3, nz, ny, nx))
+    v = inputs.random_unit(nsrc, 1, 1, rng)[:, 0, 0, :]
+    m[:, src[:, 0], src[:, 1], src[:, 2]] = v
+    return m, src
+
+
+def _samples(src, shape, rng, n_random):
+    nz, ny, nx = shape
+    cells = [tuple(s) for s in src]
+    for k, j, i in src:
+        for dk, dj, di in ((0, 0, 1), (0, -1, 0), (1, 0, 0), (-1, 0, 0)):
+            c = (k + dk, j + dj, i + di)
+            if 0 <= c[0] < nz and 0 <= c[1] < ny and 0 <= c[2] < nx:
+                cells.append(c)
+    cells += [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz // 2, 0, nx - 1)]
+    for _ in range(n_random):
+        cells.append((int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))))
+    return sorted(set(cells))
+
+
+def _oracle_at(m, src, cells, mesh, op, terms):
+    """H_eff at the given cells: demag as the sum over the nonzero sources, the local
+    terms from the oracle's field functions on the clipped neighbourhood block."""
+    nz, ny, nx = m.shape[1:]
+    msh = F.Mesh(*mesh)
+    out = np.zeros((3, len(cells)))
+    ms = m[:, src[:, 0], src[:, 1], src[:, 2]]  # [3, nsrc]
+    for t, (k, j, i) in enumerate(cells):
+        H = np.zeros(3)
+        if terms & F.DEMAG:
+            N = newell.as_matrix(newell.tensor(i - src[:, 2], j - src[:, 1], k - src[:, 0],
+                                               mesh[3], mesh[4], mesh[5]))  # [nsrc, 3, 3]
+            H += -op.Ms * np.einsum("sab,bs->a", N, ms)
+        k0, k1 = max(k - 1, 0), min(k + 2, nz)
+        j0, j1 = max(j - 1, 0), min(j + 2, ny)
+        i0, i1 = max(i - 1, 0), min(i + 2, nx)
+        blk = np.ascontiguousarray(m[:, k0:k1, j0:j1, i0:i1])
+        c = (slice(None), k - k0, j - j0, i - i0)
+        if terms & F.EXCHANGE:
+            H += F.exchange_field(blk, msh, op)[c]
+        if terms & F.DMI:
+            H += F.dmi_field(blk, msh, op)[c]
+        if terms & F.ANIS:
+            H += F.anisotropy_field(blk, op)[c]
+        if terms & F.ZEEMAN:
+            H += F.zeeman_field(blk, op)[c]
+        out[:, t] = H
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("which", ["demag", "config"])
+def test_slab_full_size_sampled(mm, prec, which):
+    w = inputs.workload(2)
+    mesh = tuple(w["mesh"])
+    terms = F.DEMAG if which == "demag" else w["terms"]
+    m, src = _sparse_slab(8, 77)
+    plan = mm.Plan(mesh, prec, terms=w["terms"])
+    gp = gpu_params(mm, w["params"], terms)
+    md = to_dev(m, DT[prec])
+    plan.autotune(gp, md, reps=1)
+    H = plan.effective_field(gp, md).cpu().numpy()
+    cells = _samples(src, m.shape[1:], np.random.Generator(np.random.PCG64(78)), 40)
+    ref = _oracle_at(m, src, cells, mesh, oracle_params(w["params"], terms), terms)
+    idx = tuple(np.array(cells).T)
+    got = H[(slice(None),) + idx]
+    assert field_err(got, ref) <= TOL[prec]
+
+
+# ----------------------------------------------------------------------------- NEB, sweep
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_neb_full_size(mm, prec):
+    """The 32-image 128x128 chain: three iterations against the oracle."""
+    w = inputs.workload(3)
+    mesh = tuple(w["mesh"])
+    chain = [representable(c, DT[prec]) for c in inputs.neb_chain()]
+    op = oracle_params(w["params"], w["terms"])
+    imgs = [c.copy() for c in chain]
+    for _ in range(3):
+        imgs, E = neb.neb_iteration(imgs, F.Mesh(*mesh), op, _kernel(mesh), w["k_spring"], w["h"])
+    plan = mm.Plan(mesh, prec, terms=w["terms"], max_batch=w["n_images"])
+    dev = to_dev(np.stack(chain), DT[prec])
+    Eg = plan.neb_run(gpu_params(mm, w["params"], w["terms"]), dev, w["k_spring"], w["h"], 3)
+    out = dev.cpu().numpy()
+    tol = 1e-10 if prec == "f64" else 1e-4
+    for i in range(w["n_images"]):
+        assert np.max(np.linalg.norm(out[i] - imgs[i], axis=0)) <= tol, i
+    scale = np.max(np.abs(E))
+    assert np.max(np.abs(np.asarray(Eg) - E)) <= (1e-9 if prec == "f64" else 1e-4) * scale
+
+
+def test_sweep_largest_meshes_fp64(mm):
+    """Two sweep instances on the sweep's largest meshes (256x256x2, 192x192x1) in one
+    batched FP64 run against the oracle integrator."""
+    meshes = [(256, 256, 2, 2e-9, 2e-9, 2e-9), (192, 192, 1, 2e-9, 2e-9, 2e-9)]
+    pars = []
+    m0 = []
+    for k, msh in enumerate(meshes):
+        rng = np.random.Generator(np.random.PCG64(3100 + k))
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        pars.append(dict(Ms=rng.uniform(4e5, 1.2e6), A=rng.uniform(5e-12, 2e-11), D=rng.uniform(0, 4e-3),
+                         Ku=rng.uniform(0, 1e6), u=(0, 0, 1), H=tuple(rng.uniform(0, 3e5) * d),
+                         alpha=rng.uniform(0.01, 0.5)))
+        m0.append(inputs.random_unit(msh[0], msh[1], msh[2], rng))
+    batch = mm.Batch(meshes, "f64", terms=mm.ALL_TERMS)
+    devs = [to_dev(m, torch.float64) for m in m0]
+    t_end = 1e-13
+    insts = [dict(mesh_id=k, params=gpu_params(mm, pars[k], mm.ALL_TERMS), m=devs[k], t_end=t_end)
+             for k in range(2)]
+    batch.run(insts)
+    for k, msh in enumerate(meshes):
+        op = oracle_params(pars[k], F.ALL_TERMS)
+        f = lambda y: F.llg_rhs(y, F.Mesh(*msh), op, _kernel(msh))
+        ost = dp45.State(rtol=1e-6)
+        mo = dp45.run(f, m0[k].copy(), ost, t_end=t_end)
+        assert np.max(np.abs(devs[k].cpu().numpy() - mo)) <= 1e-9, k
