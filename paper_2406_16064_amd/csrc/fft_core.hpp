@@ -76,22 +76,94 @@ __device__ __forceinline__ void dft8(Cx<T>* v) {
   v[7] = csub(e[3], o3);
 }
 
+// 16 points as 4 x 4: length-4 transforms over n1 of x[4 n1 + n2], twiddles
+// W16^(n2 k1), length-4 transforms over n2; output in natural order.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(Cx<T>* v) {
+  Cx<T> a[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    a[n2][0] = v[n2]; a[n2][1] = v[4 + n2]; a[n2][2] = v[8 + n2]; a[n2][3] = v[12 + n2];
+    dft4<T, INV>(a[n2]);
+  }
+  const T c1 = T(0.92387953251128675612818318939679);  // cos(pi/8)
+  const T s1 = T(0.38268343236508977172845998403040);  // sin(pi/8)
+  const T r2 = T(0.70710678118654752440084436210485);  // cos(pi/4)
+  // W16^m = exp(-+ 2 pi i m / 16) for the products m = n2 k1 (n2, k1 = 1..3)
+  auto tw = [&](Cx<T> x, int m) -> Cx<T> {
+    T c, s;
+    switch (m) {
+      case 1: c = c1; s = s1; break;
+      case 2: c = r2; s = r2; break;
+      case 3: c = s1; s = c1; break;
+      case 4: c = T(0); s = T(1); break;
+      case 6: c = -r2; s = r2; break;
+      default: c = -c1; s = -s1; break;  // m = 9: cos(9 pi/8), sin(9 pi/8) -> (-c1, -s1)
+    }
+    if (!INV) s = -s;  // forward: exp(-i theta)
+    return Cx<T>{x.x * c - x.y * s, x.x * s + x.y * c};
+  };
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) a[n2][k1] = tw(a[n2][k1], n2 * k1);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    Cx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4<T, INV>(b);
+    v[k1] = b[0]; v[k1 + 4] = b[1]; v[k1 + 8] = b[2]; v[k1 + 12] = b[3];
+  }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dftR(Cx<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 3) dft3<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
-  else dft8<T, INV>(v);
+  else if constexpr (R == 8) dft8<T, INV>(v);
+  else dft16<T, INV>(v);
 }
 
-// One Stockham stage of radix R on every column of the workgroup.
-// Per thread at most NB = 16/R butterflies (host guarantees L/R <= NB*tpc).
+
+// One Stockham stage of radix R (2, 3, 4, 8, 16) on every column of the
+// workgroup.  Per thread at most NB = max(1, 16/R) butterflies (host
+// guarantees L/R <= NB*tpc).
 // Twiddle read: from a table in LDS (TWL, copied there by the kernel) or in
 // global memory.
 template <typename T, bool TWL>
 __device__ __forceinline__ Cx<T> twiddle(const Cx<T>* tw, int i) {
   if constexpr (TWL) return tw[i];
   else return gld(tw + i);
+}
+
+// v[r] *= w^r, r = 1..R-1, with w = table[i] (conjugated for INV): one table
+// read per butterfly, the powers by products (r < 8: a chain of at most 6;
+// R = 16 also reads w^4 = table[4 i] so that every power is within 5 products)
+template <typename T, int R, bool INV, bool TWL>
+__device__ __forceinline__ void twiddle_powers(Cx<T>* v, const Cx<T>* tw, int i) {
+  Cx<T> w1 = twiddle<T, TWL>(tw, i);
+  if (INV) w1.y = -w1.y;
+  if constexpr (R == 16) {
+    Cx<T> w4 = twiddle<T, TWL>(tw, 4 * i);
+    if (INV) w4.y = -w4.y;
+    const Cx<T> w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+    const Cx<T> w8 = cmul(w4, w4), w12 = cmul(w8, w4);
+    const Cx<T> lo[4] = {Cx<T>{T(1), T(0)}, w1, w2, w3};
+    const Cx<T> hi[4] = {Cx<T>{T(1), T(0)}, w4, w8, w12};
+#pragma unroll
+    for (int r = 1; r < 16; ++r) {
+      const int a = r >> 2, b = r & 3;
+      const Cx<T> w = a == 0 ? lo[b] : (b == 0 ? hi[a] : cmul(hi[a], lo[b]));
+      v[r] = cmul(v[r], w);
+    }
+  } else {
+    Cx<T> w = w1;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      v[r] = cmul(v[r], w);
+      if (r + 1 < R) w = cmul(w, w1);
+    }
+  }
 }
 
 struct NoHook {
@@ -101,7 +173,7 @@ struct NoHook {
 template <typename T, int R, bool INV, bool TWL = false>
 __device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns, int lane, int tpc,
                                           bool active, const Cx<T>* __restrict__ tw) {
-  constexpr int NB = 16 / R;
+  constexpr int NB = R >= 16 ? 1 : 16 / R;
   const int nbf = L / R;
   Cx<T> v[NB][R];
 #pragma unroll
@@ -119,18 +191,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns
     const int j = lane + k * tpc;
     if (active && j < nbf) {
       const int kk = j % Ns;
-      if (Ns > 1) {
-        // one table read per butterfly: w^r by repeated products (r < 8 keeps
-        // the extra rounding to a few ulp)
-        Cx<T> w1 = twiddle<T, TWL>(tw, kk * tstep);
-        if (INV) w1.y = -w1.y;
-        Cx<T> w = w1;
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          v[k][r] = cmul(v[k][r], w);
-          if (r + 1 < R) w = cmul(w, w1);
-        }
-      }
+      if (Ns > 1) twiddle_powers<T, R, INV, TWL>(v[k], tw, kk * tstep);
       dftR<T, R, INV>(v[k]);
       const int base = (j / Ns) * Ns * R + kk;
 #pragma unroll
@@ -143,7 +204,9 @@ __device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns
 // Full transform of every column.  Must be called by all threads of the
 // workgroup (it contains barriers); threads with active == false only sync.
 // tw: the twiddle table to use (p.tw, or its copy in LDS when TWL).
-template <typename T, bool INV, bool TWL = false>
+// R16: the plan may hold radix-16 stages (otherwise their code is left out,
+// which keeps the register count of kernels that never need them lower).
+template <typename T, bool INV, bool TWL = false, bool R16 = false>
 __device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc,
                                             const Cx<T>* tw) {
   const int c = threadIdx.x / tpc;
@@ -154,6 +217,9 @@ __device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int
   for (int s = 0; s < p.nst; ++s) {
     const int R = radix_of(p.code, s);
     switch (R) {
+      case 16:
+        if constexpr (R16) fft_stage<T, 16, INV, TWL>(col, p.L, ns, lane, tpc, active, tw);
+        break;
       case 8: fft_stage<T, 8, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
       case 4: fft_stage<T, 4, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
       case 3: fft_stage<T, 3, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
@@ -163,9 +229,9 @@ __device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int
   }
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, bool R16 = false>
 __device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc) {
-  fft_columns<T, INV, false>(lds, p, cs, ncol, tpc, p.tw);
+  fft_columns<T, INV, false, R16>(lds, p, cs, ncol, tpc, p.tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,7 +246,7 @@ template <typename T, int R, bool INV, bool GIN, bool GOUT, bool TWL, class Load
 __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int L, int Ns, int lane, int tpc,
                                              bool active, const Cx<T>* __restrict__ tw, Load& ld, Store& st,
                                              Hook& hook) {
-  constexpr int NB = 16 / R;
+  constexpr int NB = R >= 16 ? 1 : 16 / R;
   const int nbf = L / R;
   Cx<T> v[NB][R];
 #pragma unroll
@@ -202,18 +268,7 @@ __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int
     const int j = lane + k * tpc;
     if (active && j < nbf) {
       const int kk = j % Ns;
-      if (Ns > 1) {
-        // one table read per butterfly: w^r by repeated products (r < 8 keeps
-        // the extra rounding to a few ulp)
-        Cx<T> w1 = twiddle<T, TWL>(tw, kk * tstep);
-        if (INV) w1.y = -w1.y;
-        Cx<T> w = w1;
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          v[k][r] = cmul(v[k][r], w);
-          if (r + 1 < R) w = cmul(w, w1);
-        }
-      }
+      if (Ns > 1) twiddle_powers<T, R, INV, TWL>(v[k], tw, kk * tstep);
       dftR<T, R, INV>(v[k]);
       const int base = (j / Ns) * Ns * R + kk;
 #pragma unroll
@@ -226,11 +281,14 @@ __device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int
   if constexpr (!GOUT) __syncthreads();
 }
 
-template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook>
+template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, bool R16, class Load, class Store, class Hook>
 __device__ __forceinline__ void fft_stage_any(Cx<T>* col, int c, const FftDesc<T>& p, const Cx<T>* tw, int s,
                                               int ns, int lane, int tpc, bool active, Load& ld, Store& st,
                                               Hook& hook) {
   switch (radix_of(p.code, s)) {
+    case 16:
+      if constexpr (R16) fft_stage_io<T, 16, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook);
+      break;
     case 8: fft_stage_io<T, 8, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
     case 4: fft_stage_io<T, 4, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
     case 3: fft_stage_io<T, 3, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
@@ -241,7 +299,8 @@ __device__ __forceinline__ void fft_stage_any(Cx<T>* col, int c, const FftDesc<T
 // hook(): called once by every thread inside the first stage, after that
 // stage's global loads are issued (GIN only) -- e.g. to copy a twiddle table
 // into LDS while the data loads are in flight.  tw as for fft_columns.
-template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook>
+template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook,
+          bool R16 = false>
 __device__ __forceinline__ void fft_columns_io(Cx<T>* lds, const FftDesc<T>& p, const Cx<T>* tw, int cs, int ncol,
                                                int tpc, Load ld, Store st, Hook hook) {
   const int c = threadIdx.x / tpc;
@@ -261,22 +320,22 @@ __device__ __forceinline__ void fft_columns_io(Cx<T>* lds, const FftDesc<T>& p, 
     return;
   }
   if (p.nst == 1) {
-    fft_stage_any<T, INV, GIN, GOUT, TWL>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
+    fft_stage_any<T, INV, GIN, GOUT, TWL, R16>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
     return;
   }
-  fft_stage_any<T, INV, GIN, false, TWL>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
+  fft_stage_any<T, INV, GIN, false, TWL, R16>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
   int ns = radix_of(p.code, 0);
   for (int s = 1; s + 1 < p.nst; ++s) {
-    fft_stage_any<T, INV, false, false, TWL>(col, c, p, tw, s, ns, lane, tpc, active, ld, st, hook);
+    fft_stage_any<T, INV, false, false, TWL, R16>(col, c, p, tw, s, ns, lane, tpc, active, ld, st, hook);
     ns *= radix_of(p.code, s);
   }
-  fft_stage_any<T, INV, false, GOUT, TWL>(col, c, p, tw, p.nst - 1, ns, lane, tpc, active, ld, st, hook);
+  fft_stage_any<T, INV, false, GOUT, TWL, R16>(col, c, p, tw, p.nst - 1, ns, lane, tpc, active, ld, st, hook);
 }
 
-template <typename T, bool INV, bool GIN, bool GOUT, class Load, class Store>
+template <typename T, bool INV, bool GIN, bool GOUT, bool R16 = false, class Load, class Store>
 __device__ __forceinline__ void fft_columns_io(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc, Load ld,
                                                Store st) {
-  fft_columns_io<T, INV, GIN, GOUT, false>(lds, p, p.tw, cs, ncol, tpc, ld, st, NoHook{});
+  fft_columns_io<T, INV, GIN, GOUT, false, Load, Store, NoHook, R16>(lds, p, p.tw, cs, ncol, tpc, ld, st, NoHook{});
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

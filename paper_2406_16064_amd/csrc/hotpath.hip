@@ -231,7 +231,7 @@ __host__ __device__ inline long long y3d_blocks(const Geo& g, const Tuning& tu, 
   return (long long)batch * ((3LL * g.nz * g.Xp + tu.cb_y - 1) / tu.cb_y);
 }
 
-template <typename T>
+template <typename T, bool R16>
 __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y2;
@@ -269,7 +269,8 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
     tab.store(twl);
     ktab.store(ktl);
   };
-  fft_columns_io<T, false, true, false, true>(lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, hook);
+  fft_columns_io<T, false, true, false, true, decltype(ld), decltype(st), decltype(hook), R16>(
+      lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, hook);
   const T s = T(ldu(&hp.prm[b].demag_scale));
   const int seg = ncb * g.Ky;
   for (int t = threadIdx.x; t < ncb * g.Py; t += blockDim.x) {
@@ -288,10 +289,11 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
     m2 = {kzz * c.x, kzz * c.y};
   }
   __syncthreads();
-  fft_columns_io<T, true, false, true, true>(lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, NoHook{});
+  fft_columns_io<T, true, false, true, true, decltype(ld), decltype(st), NoHook, R16>(lds, hp.fd[1], twl, cs, ncol,
+                                                                                    tpc, ld, st, NoHook{});
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, bool R16>
 __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y;
@@ -313,11 +315,12 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
   auto st = [=](int c, int e, Cx<T> v) {
     if (e < nout) gst(dst + (size_t)c * nout + e, v);
   };
-  fft_columns_io<T, INV, true, true>(lds, hp.fd[1], cs, ncol, (int)blockDim.x / CB, ld, st);
+  fft_columns_io<T, INV, true, true, R16>(lds, hp.fd[1], cs, ncol, (int)blockDim.x / CB, ld, st);
 }
 
 // Forward y pass of every group: fused 2-D or 3-D forward rows.
-template <typename T>
+// R16: the y plans hold radix-16 stages (lengths beyond 512 points).
+template <typename T, bool R16>
 __global__ void __launch_bounds__(512) k_ypass(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
@@ -326,14 +329,14 @@ __global__ void __launch_bounds__(512) k_ypass(Launch<T> L) {
   const HotPlan<T> hp = ldu(L.hps + gi);
   if (hp.g.nz == 1) {
     if (bid >= y2d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_fused2d(hp, ldu(L.epis + gi), bid, lds);
+    y_fused2d<T, R16>(hp, ldu(L.epis + gi), bid, lds);
   } else {
     if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_rows3d<T, false>(hp, ldu(L.epis + gi), bid, lds);
+    y_rows3d<T, false, R16>(hp, ldu(L.epis + gi), bid, lds);
   }
 }
 
-template <typename T>
+template <typename T, bool R16>
 __global__ void __launch_bounds__(512) k_yinv(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
@@ -341,7 +344,7 @@ __global__ void __launch_bounds__(512) k_yinv(Launch<T> L) {
   const int gi = group_of(L, bid);
   const HotPlan<T> hp = ldu(L.hps + gi);
   if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-  y_rows3d<T, true>(hp, ldu(L.epis + gi), bid, lds);
+  y_rows3d<T, true, R16>(hp, ldu(L.epis + gi), bid, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1433,6 +1436,9 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
   // pass numbers: 0 x forward, 1 y, 2 z (3-D), 3 y inverse (3-D), last x inverse
   auto on = [&](int p) { return ((pass_mask >> p) & 1u) != 0; };
   const int p_inv = demag ? (any3d ? 4 : 2) : 0;
+  bool y16 = false;  // some group's y plan has radix-16 stages
+  for (int i = 0; i < gs.n; ++i)
+    for (int st = 0; st < gs.h[i].fd[1].nst; ++st) y16 = y16 || radix_of(gs.h[i].fd[1].code, st) == 16;
   if (demag) {
     if (!skip_fwd && on(0)) {  // x forward (skipped when the previous stage's inverse-x pass did it)
       LaunchBuilder<T> lb(gs, epis);
@@ -1464,7 +1470,8 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         nt = std::max(nt, h.tu.nt_y);
       }
       mark();
-      k_ypass<T><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
+      if (y16) k_ypass<T, true><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
+      else k_ypass<T, false><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
     }
     if (any3d) {
       // z: register transform for every supported Pz (one launch per distinct
@@ -1519,7 +1526,8 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         }
       }
       mark();
-      if (on(3)) k_yinv<T><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
+      if (on(3) && y16) k_yinv<T, true><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
+      else if (on(3)) k_yinv<T, false><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
     }
   }
   if (on(p_inv)) {  // x inverse + epilogue

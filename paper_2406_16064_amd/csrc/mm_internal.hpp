@@ -34,9 +34,10 @@ template <typename T> struct FftPlan {
   const Cx<T>* tw;
 };
 
-// The same plan in the form the kernels take: the radices packed two bits a
-// stage (0: 2, 1: 3, 2: 4, 3: 8), first stage in the lowest bits; the spans
-// follow as running products.  Scalars only, so it lives in scalar registers.
+// The same plan in the form the kernels take: the radices packed three bits a
+// stage (0: 2, 1: 3, 2: 4, 3: 8, 4: 16; at most 10 stages), first stage in the
+// lowest bits; the spans follow as running products.  Scalars only, so it
+// lives in scalar registers.
 template <typename T> struct FftDesc {
   int L;
   int nst;
@@ -46,8 +47,8 @@ template <typename T> struct FftDesc {
 };
 
 __host__ __device__ inline int radix_of(uint32_t code, int s) {
-  const uint32_t c = (code >> (2 * s)) & 3u;
-  return c == 0 ? 2 : c == 1 ? 3 : c == 2 ? 4 : 8;
+  const uint32_t c = (code >> (3 * s)) & 7u;
+  return c == 0 ? 2 : c == 1 ? 3 : c == 2 ? 4 : c == 3 ? 8 : 16;
 }
 
 template <typename T> inline FftDesc<T> describe(const FftPlan<T>& p) {
@@ -56,8 +57,8 @@ template <typename T> inline FftDesc<T> describe(const FftPlan<T>& p) {
   d.nst = p.nst;
   d.tw = p.tw;
   for (int s = 0; s < p.nst; ++s) {
-    const uint32_t c = p.rad[s] == 2 ? 0u : p.rad[s] == 3 ? 1u : p.rad[s] == 4 ? 2u : 3u;
-    d.code |= c << (2 * s);
+    const uint32_t c = p.rad[s] == 2 ? 0u : p.rad[s] == 3 ? 1u : p.rad[s] == 4 ? 2u : p.rad[s] == 8 ? 3u : 4u;
+    d.code |= c << (3 * s);
   }
   return d;
 }

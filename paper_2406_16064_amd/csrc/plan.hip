@@ -62,26 +62,37 @@ int pick_padded(int n, bool even) {
     if (smooth3(P) && (!even || P % 2 == 0)) return P;
 }
 
-std::vector<int> radices(int L) {
+// Radices of a 3-smooth length: the power of two as 8s (a remainder as 4, 4+4
+// or 2), then the 3s.  Where that takes more than three stages of powers of
+// two, 16s replace the 8s when allow16 (the y passes, whose kernels carry the
+// radix-16 code): one LDS round trip less (measured: the 1024-point y
+// transforms gain, while at 512 and below the larger butterfly's registers
+// cost more than the stage it saves).
+std::vector<int> radices(int L, bool allow16) {
   std::vector<int> r;
   int a = 0, b = 0;
   while (L % 2 == 0) { L /= 2; ++a; }
   while (L % 3 == 0) { L /= 3; ++b; }
-  int n8 = a / 3, rem = a % 3;
-  if (rem == 1 && n8 > 0) { --n8; r.push_back(4); r.push_back(4); }
-  else if (rem == 1) r.push_back(2);
-  else if (rem == 2) r.push_back(4);
-  for (int i = 0; i < n8; ++i) r.insert(r.begin(), 8);
+  if (allow16 && a > 9) {
+    for (int i = 0; i < a / 4; ++i) r.push_back(16);
+    if (a % 4) r.push_back(1 << (a % 4));
+  } else {
+    int n8 = a / 3, rem = a % 3;
+    if (rem == 1 && n8 > 0) { --n8; r.push_back(4); r.push_back(4); }
+    else if (rem == 1) r.push_back(2);
+    else if (rem == 2) r.push_back(4);
+    for (int i = 0; i < n8; ++i) r.insert(r.begin(), 8);
+  }
   for (int i = 0; i < b; ++i) r.push_back(3);
   return r;
 }
 
 template <typename T>
-FftPlan<T> make_fft(int L, const Cx<T>* tw) {
+FftPlan<T> make_fft(int L, const Cx<T>* tw, bool allow16 = false) {
   FftPlan<T> p{};
   p.L = L;
   p.tw = tw;
-  std::vector<int> r = L > 1 ? radices(L) : std::vector<int>{};
+  std::vector<int> r = L > 1 ? radices(L, allow16) : std::vector<int>{};
   p.nst = (int)r.size();
   int ns = 1;
   for (int s = 0; s < p.nst; ++s) {
@@ -319,9 +330,9 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
   Tuning& t = G.tu;
   const size_t budget = 80 * 1024;
   const long long want = 4 * 256;  // workgroups per pass worth aiming for
-  auto tpc_for = [&](int L) {
-    if (prec == MM_F32) return min_tpc(make_fft<float>(L, nullptr));
-    return min_tpc(make_fft<double>(L, nullptr));
+  auto tpc_for = [&](int L, bool allow16 = false) {
+    if (prec == MM_F32) return min_tpc(make_fft<float>(L, nullptr, allow16));
+    return min_tpc(make_fft<double>(L, nullptr, allow16));
   };
   const int tpx = tpc_for(g.Lx);
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
@@ -349,7 +360,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
     t.nt_i = std::min(512, std::max(64, pow2ceil(std::max(3 * ty * tpx, ty * g.nx))));
     t.tpc_x = t.nt_i / (3 * ty);
   }
-  const int tmin = tpc_for(g.Py);
+  const int tmin = tpc_for(g.Py, true);
   if (g.nz == 1) {
     const int tpc = std::max(tmin, std::min(2 * tmin, 64));
     const size_t colb = 3 * (size_t)col_stride(g.Py) * csz;
@@ -599,7 +610,7 @@ mm_status make_set(Engine& E, const std::vector<int>& nb, GroupSet<T>& gs, std::
     h.g = G.g;
     h.tu = G.tu;
     h.fd[0] = describe(make_fft<T>(G.g.Lx, (const Cx<T>*)G.twx));
-    h.fd[1] = describe(make_fft<T>(G.g.Py, (const Cx<T>*)G.twy));
+    h.fd[1] = describe(make_fft<T>(G.g.Py, (const Cx<T>*)G.twy, true));
     h.fd[2] = describe(make_fft<T>(G.g.Pz, (const Cx<T>*)G.twz));
     h.twz = (const Cx<T>*)G.twz;
     h.post = (const Cx<T>*)G.post;
@@ -1130,8 +1141,9 @@ mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, doub
 // per thread, workgroup size).
 bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   const Geo& g = G.g;
-  auto tmin = [&](int L) {
-    return prec == MM_F32 ? min_tpc(make_fft<float>(L, nullptr)) : min_tpc(make_fft<double>(L, nullptr));
+  auto tmin = [&](int L, bool allow16 = false) {
+    return prec == MM_F32 ? min_tpc(make_fft<float>(L, nullptr, allow16))
+                          : min_tpc(make_fft<double>(L, nullptr, allow16));
   };
   const size_t lim = 160 * 1024;
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
@@ -1143,10 +1155,10 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   if (t.tpc_x < tmin(g.Lx) || (size_t)3 * t.ty_x * rowb + xtab > lim) return false;
   const size_t colb = (size_t)col_stride(g.Py) * csz;
   if (g.nz == 1) {
-    if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
+    if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py, true) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
     if (3 * t.cb_y2 * colb + ytab + (size_t)4 * t.cb_y2 * g.Ky * (csz / 2) > lim) return false;
   } else {
-    if (t.cb_y < 1 || t.nt_y > 512 || t.tpc_y < tmin(g.Py) || t.cb_y * t.tpc_y > t.nt_y) return false;
+    if (t.cb_y < 1 || t.nt_y > 512 || t.tpc_y < tmin(g.Py, true) || t.cb_y * t.tpc_y > t.nt_y) return false;
     if (t.cb_y * colb > lim) return false;
   }
   return true;
@@ -1226,8 +1238,8 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
     for (int cb : {1, 2, 3, 4, 6, 8})
       for (int tf : {1, 2, 4}) {
         Tuning t = best;
-        const int tmin = E.prec == MM_F32 ? min_tpc(make_fft<float>(G.g.Py, nullptr))
-                                          : min_tpc(make_fft<double>(G.g.Py, nullptr));
+        const int tmin = E.prec == MM_F32 ? min_tpc(make_fft<float>(G.g.Py, nullptr, true))
+                                          : min_tpc(make_fft<double>(G.g.Py, nullptr, true));
         if (G.g.nz == 1) {
           t.cb_y2 = cb; t.tpc_y2 = tmin * tf; t.nt_y = 3 * cb * t.tpc_y2;
         } else {
