@@ -112,7 +112,7 @@ def run_workload(mm, inputs, torch, idx, prec, steps, warmup, mesh=None):
     plan = mm.Plan(mesh, prec, terms=w["terms"])
     params = mm.make_params(terms=w["terms"], **w["params"])
     m = torch.tensor(inputs.initial_state(idx, mesh), dtype=dt, device="cuda")
-    shapes = plan.autotune(params, m, reps=5)  # launch shapes measured on this device (not timed)
+    shapes = plan.autotune(params, m, reps=20)  # launch shapes measured on this device (not timed)
     st = mm.new_states(1, rtol=w["rtol"])
     t_end = w["t_end"]
     s = plan.rk45_run(params, m, st, t_end=t_end, max_steps=warmup, check=False)

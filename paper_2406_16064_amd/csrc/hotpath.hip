@@ -271,6 +271,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   };
   fft_columns_io<T, false, true, false, true, decltype(ld), decltype(st), decltype(hook), R16>(
       lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, hook);
+  Cx<T>* const spec = lds;
   const T s = T(ldu(&hp.prm[b].demag_scale));
   const int seg = ncb * g.Ky;
   for (int t = threadIdx.x; t < ncb * g.Py; t += blockDim.x) {
@@ -280,9 +281,9 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
     const int o = j * g.Ky + kyf;
     const T kxx = ktl[o] * s, kyy = ktl[seg + o] * s, kzz = ktl[2 * seg + o] * s;
     const T kxy = ktl[3 * seg + o] * (s * sy);
-    Cx<T>& m0 = lds[(0 * CB + j) * cs + pidx(ky)];
-    Cx<T>& m1 = lds[(1 * CB + j) * cs + pidx(ky)];
-    Cx<T>& m2 = lds[(2 * CB + j) * cs + pidx(ky)];
+    Cx<T>& m0 = spec[(0 * CB + j) * cs + pidx(ky)];
+    Cx<T>& m1 = spec[(1 * CB + j) * cs + pidx(ky)];
+    Cx<T>& m2 = spec[(2 * CB + j) * cs + pidx(ky)];
     const Cx<T> a = m0, bq = m1, c = m2;
     m0 = {kxx * a.x + kxy * bq.x, kxx * a.y + kxy * bq.y};
     m1 = {kxy * a.x + kyy * bq.x, kxy * a.y + kyy * bq.y};
@@ -749,6 +750,10 @@ int eval_blocks_per_inst(const Geo& g, const Tuning& tu) {
   return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz;
 }
 
+// Dormand-Prince decision of one instance after its error norm is complete
+// (defined with the controller kernel below).
+__device__ void control_step(DevCtl& C, const double* __restrict__ replay_h);
+
 // CPT > 0: every thread owns at most CPT cells (the host checks TY nx <= CPT
 // threads) and the cell loop is unrolled; CPT == 1 also loads the cell's
 // epilogue inputs (m and neighbours, the step's m and slopes) before the
@@ -1014,6 +1019,16 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       double v = red[0][0];
       for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
       atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
+      // the last workgroup of this instance to arrive takes the step decision
+      // (the fence orders this workgroup's maximum before its arrival)
+      __threadfence();
+      const int bpi = tiles * g.nz;
+      if (atomicAdd(&ctl[b].arrive, 1) == bpi - 1) {
+        __threadfence();
+        ctl[b].arrive = 0;
+        ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);  // the complete maximum
+        control_step(ctl[b], epi.replay);
+      }
     }
   } else if constexpr (energy) {
     for (int q = 0; q < 5; ++q) {
@@ -1078,10 +1093,7 @@ __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
 // ---------------------------------------------------------------------------
 // Device-side Dormand-Prince controller, one thread per instance (FP64).
 // ---------------------------------------------------------------------------
-__global__ void k_controller(DevCtl* ctl, int n, const double* __restrict__ replay_h) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
-  DevCtl& C = ctl[b];
+__device__ void control_step(DevCtl& C, const double* __restrict__ replay_h) {
   if (C.done) {
     C.pending_finish = 0;
     C.err_bits = 0ull;
@@ -1152,6 +1164,12 @@ __global__ void k_controller(DevCtl* ctl, int n, const double* __restrict__ repl
     return;
   }
   C.h_att = hn;
+}
+
+__global__ void k_controller(DevCtl* ctl, int n, const double* __restrict__ replay_h) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  control_step(ctl[b], replay_h);
 }
 
 // Fixed-order reduction of per-block partial sums: out[b][q] = sum_j partial[b][j][q].

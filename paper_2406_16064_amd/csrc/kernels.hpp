@@ -41,6 +41,7 @@ template <typename T> struct Epi {
   int nk;                 // number of k entries combined (including the current one)
   double* partial;        // energy partials [batch][blocks_per_inst][5]
   DevCtl* ctl;            // per-instance controller (skip done instances; h_att; err)
+  const double* replay;   // MODE_ERROR: replayed step sizes (controller in the last workgroup)
   long long inst_stride;  // elements per instance of m-like arrays (3N)
   // step begin
   T* bm;

@@ -91,6 +91,8 @@ struct DevCtl {
   int status;             // mm_status of this instance
   int last_accepted;
   int nonfinite;          // consecutive attempts with a non-finite error norm
+  int arrive;             // workgroups of the error pass done with this instance's norm
+  int pad;
 };
 
 }  // namespace mmx

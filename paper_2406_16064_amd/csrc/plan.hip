@@ -780,6 +780,7 @@ mm_status upload_step_epis(Engine& E, const std::vector<T*>& m, const std::vecto
         e.msn = stage_buf<T>(G, 1 - in);
         for (int j = 0; j < st - 1; ++j) e.kprev[j] = stage_buf<T>(G, 2 + j);
         e.nk = st;
+        e.replay = E.replay;
         for (int j = 0; j < st; ++j) e.coef[j] = st < 7 ? kDP.a[st + 1][j] : kDP.e[j];
       } else {  // step begin
         e.bm = m[i];
@@ -805,7 +806,10 @@ mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStre
   for (int st = 2; st <= 7; ++st)
     HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, st), st < 7 ? MODE_STAGE : MODE_ERROR, demag_on(E), s, nullptr,
                           fz && st > 2, fz && st < 7));
-  HIPCHK(launch_controller(E.ctl, n_total, E.replay, s));
+  // the step decision runs in the last workgroup of each instance in the error
+  // pass; instances already done keep their pending projection, which the next
+  // step-begin repeats idempotently
+  (void)n_total;
   return MM_OK;
 }
 
@@ -814,6 +818,10 @@ mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStre
 // inverse-x pass in the form the captured attempt uses (stage epilogue, fused
 // forward x when fused), us[np + 1] the inverse-x pass with the error
 // epilogue.  Stage-epilogue and the forward-x figures average stages 2..6.
+// attempt limit of the timing runs (the error pass decides steps as it is
+// timed; the limit must not stop the instance)
+constexpr long long kNoLimit = 1LL << 60;
+
 struct StepProfile {
   int reps = 0;
   double us[16] = {};
@@ -1164,35 +1172,16 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   return true;
 }
 
-// Per-pass timing of `reps` dm/dt evaluations with the group's current shapes.
+// Per-pass timing with the group's current shapes: each pass launched `reps`
+// times back to back between two events (as mm_profile_passes does).
 template <typename T>
 mm_status time_passes(Engine& E, int batch, int reps, std::vector<double>& us, hipStream_t s) {
   GroupSet<T> gs;
   std::vector<int> inst0;
   MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
   const int np = pass_count(E);
-  std::vector<hipEvent_t> ev((size_t)(np + 1) * reps);
-  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  mm_status st = MM_OK;
-  for (int r = 0; r < reps && st == MM_OK; ++r) {
-    hipError_t er = launch_eval<T>(gs, epi_slot<T>(E, 0), MODE_RHS, demag_on(E), s, ev.data() + (size_t)r * (np + 1));
-    if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
-  }
-  if (st == MM_OK) {
-    hipError_t er = hipStreamSynchronize(s);
-    if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
-  }
   us.assign(np, 0.0);
-  for (int i = 0; i < np && st == MM_OK; ++i) {
-    for (int r = 0; r < reps; ++r) {
-      float ms = 0.f;
-      hipError_t er = hipEventElapsedTime(&ms, ev[(size_t)r * (np + 1) + i], ev[(size_t)r * (np + 1) + i + 1]);
-      if (er != hipSuccess) { st = fail(MM_E_HIP, hipGetErrorString(er)); break; }
-      us[i] += 1e3 * ms / reps;
-    }
-  }
-  for (auto& x : ev) (void)hipEventDestroy(x);
-  return st;
+  return time_each_pass<T>(E, gs, epi_slot<T>(E, 0), MODE_RHS, reps, np, us.data(), s);
 }
 
 // Measure candidate launch shapes of each pass on the device and keep the
@@ -1275,7 +1264,7 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
         pr.reps = reps;
         std::vector<int> status;
         MMCHK(run_core<T>(E, std::vector<T*>{(T*)const_cast<void*>(m)}, std::vector<int>{batch}, qv, sv,
-                          std::vector<double>(batch, 1.0), 1, nullptr, 0, true, status, s, &pr));
+                          std::vector<double>(batch, 1.0), kNoLimit, nullptr, 0, true, status, s, &pr));
         const int n = pr.n;  // begin, passes..., error
         double cost = 5.0 * pr.us[n - 2] + pr.us[n - 1];
         if (demag_on(E)) cost += (pr.fused ? 1.0 : 6.0) * pr.us[1];
@@ -1431,8 +1420,8 @@ mm_status mm_profile_step(mm_plan* p, const mm_params* q, int32_t batch, void* m
   pr.reps = reps;
   const double t_end = copy[0].t + 1.0;  // any end beyond one step
   mm_status r = p->e.prec == MM_F32
-                    ? plan_rk45<float>(p, q, batch, m, copy.data(), t_end, 1, nullptr, 0, true, s, &pr)
-                    : plan_rk45<double>(p, q, batch, m, copy.data(), t_end, 1, nullptr, 0, true, s, &pr);
+                    ? plan_rk45<float>(p, q, batch, m, copy.data(), t_end, kNoLimit, nullptr, 0, true, s, &pr)
+                    : plan_rk45<double>(p, q, batch, m, copy.data(), t_end, kNoLimit, nullptr, 0, true, s, &pr);
   if (r != MM_OK) return r;
   HIPCHK(hipStreamSynchronize(s));
   for (int i = 0; i < pr.n; ++i) us_out[i] = pr.us[i];
