@@ -1018,13 +1018,15 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     if (threadIdx.x == 0) {
       double v = red[0][0];
       for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
-      atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
-      // the last workgroup of this instance to arrive takes the step decision
-      // (the fence orders this workgroup's maximum before its arrival)
-      __threadfence();
+      const unsigned long long prev = atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
+      // the last workgroup of this instance to arrive takes the step decision.
+      // The arrival uses the maximum's returned value (its top bit, always 0
+      // for a non-negative double), so it is issued only once the maximum is
+      // complete; the two atomics are performed where every XCD sees them, so
+      // no fence (an L2 write-back on this part) is needed.
+      const int inc = 1 + (int)(prev >> 63);
       const int bpi = tiles * g.nz;
-      if (atomicAdd(&ctl[b].arrive, 1) == bpi - 1) {
-        __threadfence();
+      if (atomicAdd(&ctl[b].arrive, inc) == bpi - 1) {
         ctl[b].arrive = 0;
         ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);  // the complete maximum
         control_step(ctl[b], epi.replay);
