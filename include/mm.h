@@ -96,6 +96,8 @@ typedef struct mm_plan mm_plan;
  * spectrum is shared; parameters are per instance).  Builds the Newell tensor
  * (FP64) and its spectrum on the device, then casts it to the plan precision.
  * `terms` is the set of terms any later call may enable.  Synchronises.
+ * MM_E_ARG also when one instance's [3][nx ny nz] array would take 4 GiB or
+ * more (the kernels address it with 32-bit offsets).
  * Paper: section "Magnetostatic energy" (Newell tensor, FFT acceleration). */
 mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec,
                          uint32_t terms, int32_t max_batch, void* hip_stream);

@@ -11,7 +11,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmmx.so")
-SOURCES = ("hotpath.hip", "setup.hip", "plan.hip")
+SOURCES = ("hotpath.hip", "invx_f32_demag.hip", "invx_f32_local.hip", "invx_f64_demag.hip",
+           "invx_f64_local.hip", "setup.hip", "plan.hip")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -1,11 +1,12 @@
 // LDS-resident mixed-radix Stockham FFT for gfx950 workgroups.
 //
 // A workgroup holds `ncol` complex columns of length L in LDS (column c starts
-// at c*cs, element i sits at pidx(i) -- one padding slot every 8 elements
-// breaks the power-of-two strides of the first stages across the LDS banks).
+// at c*cs, element i sits at pidx(i, sh): with sh = 3 one padding slot every 8
+// elements breaks the power-of-two strides across the LDS banks; sh = 31 is
+// no padding, for the plans whose strides would not keep addresses linear).
 // Threads are split into ncol groups of tpc threads; each group transforms its
-// own column, stage by stage, with the butterflies of radix 2, 3, 4 or 8 held
-// in registers.  Stockham autosort: the output comes out in natural order.
+// own column, stage by stage, with the butterflies of radix 2, 3, 4, 8 or 16
+// held in registers.  Stockham autosort: the output comes out in natural order.
 // Twiddles come from a table exp(-2 pi i m / L) computed in FP64 on the host.
 #pragma once
 
@@ -13,7 +14,7 @@
 
 namespace mmx {
 
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+__device__ __forceinline__ int pidx(int i, int sh) { return i + (i >> sh); }
 __host__ __device__ inline int col_stride(int L) { return L + (L >> 3) + 1; }
 
 template <typename T, bool INV>
@@ -136,11 +137,22 @@ __device__ __forceinline__ Cx<T> twiddle(const Cx<T>* tw, int i) {
   else return gld(tw + i);
 }
 
-// v[r] *= w^r, r = 1..R-1, with w = table[i] (conjugated for INV): one table
-// read per butterfly, the powers by products (r < 8: a chain of at most 6;
-// R = 16 also reads w^4 = table[4 i] so that every power is within 5 products)
+// v[r] *= w^r, r = 1..R-1, with w^r = table[r i] (conjugated for INV).
+// Table in LDS (TWL): every power is read (LDS reads instead of the products,
+// which would occupy the vector ALU).  Table in global memory: one read, the
+// powers by products (r < 8: a chain of at most 6; R = 16 also reads
+// w^4 = table[4 i] so that every power is within 5 products).
 template <typename T, int R, bool INV, bool TWL>
 __device__ __forceinline__ void twiddle_powers(Cx<T>* v, const Cx<T>* tw, int i) {
+  if constexpr (TWL) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      Cx<T> w = tw[r * i];
+      if (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    return;
+  }
   Cx<T> w1 = twiddle<T, TWL>(tw, i);
   if (INV) w1.y = -w1.y;
   if constexpr (R == 16) {
@@ -170,172 +182,294 @@ struct NoHook {
   __device__ __forceinline__ void operator()() const {}
 };
 
-template <typename T, int R, bool INV, bool TWL = false>
-__device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int L, int Ns, int lane, int tpc,
-                                          bool active, const Cx<T>* __restrict__ tw) {
+// Quotient of small non-negative integers by a divisor that is the same in
+// every lane, from one float product.  With r = 1/d rounded to nearest and
+// h = r/2, fma(n, r, h) = (n + 1/2)/d (1 + e) with |e| < 2^-22.9; for
+// n < 2^21 that is off by less than 1/(2d), while (n + 1/2)/d is at least
+// 1/(2d) away from the integers on either side, so truncation gives floor(n/d).
+// Five full-rate instructions per quotient and remainder instead of the
+// integer division sequence (two of whose multiplies issue at quarter rate).
+struct FDiv {
+  int d;
+  float r, h;
+};
+__device__ __forceinline__ FDiv fdiv_of(int d) {
+  const float r = 1.0f / (float)d;
+  return FDiv{d, r, 0.5f * r};
+}
+__device__ __forceinline__ int fdiv_q(int n, const FDiv& D) { return (int)__builtin_fmaf((float)n, D.r, D.h); }
+// a * b for operands below 2^24 (full-rate 24-bit multiply)
+__device__ __forceinline__ int mul24(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
+
+// One Stockham stage of radix R on one column per thread group (tpc threads;
+// each thread at most NB = max(1, 16/R) butterflies, the host guarantees
+// L/R <= NB tpc).  Source and destination are the LDS column (element i at
+// pidx(i, sh)) or, with GIN / GOUT, the caller's global loads and stores:
+// ld.template get<CHK>(column, index), st.template put<CHK>(column, index, v),
+// CHK = false where the index is known to be inside the data.
+// FIRST: the span-1 stage (no twiddles; outputs j R + r).
+// HIN: inputs at index >= L/2 are zero and the ones below are all present
+// (read without checks, the upper half not at all); HOUT: outputs at index
+// >= L/2 are not needed.  Both need an even R.
+// LDS addresses are linear in r: with padding (sh = 3) the host keeps every
+// stride (L/R for the reads, the span for the writes) a multiple of 8 and
+// the first radix a power of two, without padding (sh = 31) anything goes.
+template <typename T, int R, bool INV, bool GIN, bool GOUT, bool TWL, bool FIRST, bool HIN, bool HOUT, class Load,
+          class Store, class Hook>
+__device__ __forceinline__ void fft_stage(Cx<T>* __restrict__ col, int c, int L, int Ns, int lane, int tpc,
+                                          bool active, int sh, const Cx<T>* __restrict__ tw, Load& ld, Store& st,
+                                          Hook& hook) {
+  static_assert(!(HIN || HOUT) || R % 2 == 0, "half-length ends need an even radix");
   constexpr int NB = R >= 16 ? 1 : 16 / R;
+  constexpr int RI = HIN ? R / 2 : R;
+  constexpr int RO = HOUT ? R / 2 : R;
   const int nbf = L / R;
   Cx<T> v[NB][R];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const int j = lane + k * tpc;
     if (active && j < nbf) {
+      if constexpr (GIN) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k][r] = col[pidx(j + r * nbf)];
-    }
-  }
-  __syncthreads();
-  const int tstep = L / (Ns * R);
+        for (int r = 0; r < RI; ++r) v[k][r] = ld.template get<!HIN>(c, j + r * nbf);
+      } else {
+        const int a = j + (j >> sh);
+        const int nbp = nbf + (nbf >> sh);
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const int j = lane + k * tpc;
-    if (active && j < nbf) {
-      const int kk = j % Ns;
-      if (Ns > 1) twiddle_powers<T, R, INV, TWL>(v[k], tw, kk * tstep);
-      dftR<T, R, INV>(v[k]);
-      const int base = (j / Ns) * Ns * R + kk;
-#pragma unroll
-      for (int r = 0; r < R; ++r) col[pidx(base + r * Ns)] = v[k][r];
-    }
-  }
-  __syncthreads();
-}
-
-// Full transform of every column.  Must be called by all threads of the
-// workgroup (it contains barriers); threads with active == false only sync.
-// tw: the twiddle table to use (p.tw, or its copy in LDS when TWL).
-// R16: the plan may hold radix-16 stages (otherwise their code is left out,
-// which keeps the register count of kernels that never need them lower).
-template <typename T, bool INV, bool TWL = false, bool R16 = false>
-__device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc,
-                                            const Cx<T>* tw) {
-  const int c = threadIdx.x / tpc;
-  const int lane = threadIdx.x % tpc;
-  const bool active = c < ncol;
-  Cx<T>* col = lds + (active ? c : 0) * cs;
-  int ns = 1;
-  for (int s = 0; s < p.nst; ++s) {
-    const int R = radix_of(p.code, s);
-    switch (R) {
-      case 16:
-        if constexpr (R16) fft_stage<T, 16, INV, TWL>(col, p.L, ns, lane, tpc, active, tw);
-        break;
-      case 8: fft_stage<T, 8, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
-      case 4: fft_stage<T, 4, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
-      case 3: fft_stage<T, 3, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
-      default: fft_stage<T, 2, INV, TWL>(col, p.L, ns, lane, tpc, active, tw); break;
-    }
-    ns *= R;
-  }
-}
-
-template <typename T, bool INV, bool R16 = false>
-__device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc) {
-  fft_columns<T, INV, false, R16>(lds, p, cs, ncol, tpc, p.tw);
-}
-
-// ---------------------------------------------------------------------------
-// Same transform with the first stage reading its inputs straight from global
-// memory (ld(c, e) -> element e of column c, zero padding included) and/or the
-// last stage writing straight to global memory (st(c, e, v)); the stages in
-// between go through LDS.  Saves one LDS round trip and one barrier at each
-// end.  The caller makes sure LDS is free before the call when GIN, and syncs
-// before reusing LDS after the call when GOUT.
-// ---------------------------------------------------------------------------
-template <typename T, int R, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook>
-__device__ __forceinline__ void fft_stage_io(Cx<T>* __restrict__ col, int c, int L, int Ns, int lane, int tpc,
-                                             bool active, const Cx<T>* __restrict__ tw, Load& ld, Store& st,
-                                             Hook& hook) {
-  constexpr int NB = R >= 16 ? 1 : 16 / R;
-  const int nbf = L / R;
-  Cx<T> v[NB][R];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const int j = lane + k * tpc;
-    if (active && j < nbf) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if constexpr (GIN) v[k][r] = ld(c, j + r * nbf);
-        else v[k][r] = col[pidx(j + r * nbf)];
+        for (int r = 0; r < RI; ++r) v[k][r] = col[a + r * nbp];
       }
+#pragma unroll
+      for (int r = RI; r < R; ++r) v[k][r] = Cx<T>{T(0), T(0)};
     }
   }
   if constexpr (!GIN) __syncthreads();
   if constexpr (GIN) hook();  // runs with this stage's global loads in flight
-  const int tstep = L / (Ns * R);
+  FDiv dn{1, 1.0f, 0.5f};
+  int tstep = 0;
+  if constexpr (!FIRST) {
+    dn = fdiv_of(Ns);
+    tstep = fdiv_q(nbf, dn);  // L / (Ns R)
+  }
+  const int span = Ns * R;
+  const int nsp = Ns + (Ns >> sh);
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const int j = lane + k * tpc;
     if (active && j < nbf) {
-      const int kk = j % Ns;
-      if (Ns > 1) twiddle_powers<T, R, INV, TWL>(v[k], tw, kk * tstep);
+      int q = j, kk = 0;
+      if constexpr (!FIRST) {
+        q = fdiv_q(j, dn);
+        kk = j - mul24(q, Ns);
+        twiddle_powers<T, R, INV, TWL>(v[k], tw, mul24(kk, tstep));
+      }
       dftR<T, R, INV>(v[k]);
-      const int base = (j / Ns) * Ns * R + kk;
+      const int base = mul24(q, span) + kk;
+      if constexpr (GOUT) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if constexpr (GOUT) st(c, base + r * Ns, v[k][r]);
-        else col[pidx(base + r * Ns)] = v[k][r];
+        for (int r = 0; r < RO; ++r) st.template put<!HOUT>(c, base + r * Ns, v[k][r]);
+      } else if constexpr (FIRST) {
+        const int a = base + (base >> sh);
+        const int hi = 8 >> sh;  // radix 16: one more padding slot from r = 8 on
+#pragma unroll
+        for (int r = 0; r < RO; ++r) col[a + r + (r >= 8 ? hi : 0)] = v[k][r];
+      } else {
+        const int a = base + (base >> sh);
+#pragma unroll
+        for (int r = 0; r < RO; ++r) col[a + r * nsp] = v[k][r];
       }
     }
   }
   if constexpr (!GOUT) __syncthreads();
 }
 
-template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, bool R16, class Load, class Store, class Hook>
-__device__ __forceinline__ void fft_stage_any(Cx<T>* col, int c, const FftDesc<T>& p, const Cx<T>* tw, int s,
-                                              int ns, int lane, int tpc, bool active, Load& ld, Store& st,
-                                              Hook& hook) {
+// The stage of radix radix_of(code, s).  EVEN: only even radices can occur
+// (a half-length end).
+template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, bool R16, bool FIRST, bool HIN, bool HOUT, class Load,
+          class Store, class Hook>
+__device__ __forceinline__ void fft_stage_any(Cx<T>* col, int c, const FftDesc<T>& p, const Cx<T>* tw, int s, int ns,
+                                              int lane, int tpc, bool active, Load& ld, Store& st, Hook& hook) {
+  constexpr bool EVEN = HIN || HOUT;
+#define MMX_STAGE(R) \
+  fft_stage<T, R, INV, GIN, GOUT, TWL, FIRST, HIN, HOUT>(col, c, p.L, ns, lane, tpc, active, p.psh, tw, ld, st, hook)
   switch (radix_of(p.code, s)) {
     case 16:
-      if constexpr (R16) fft_stage_io<T, 16, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook);
+      if constexpr (R16) MMX_STAGE(16);
       break;
-    case 8: fft_stage_io<T, 8, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
-    case 4: fft_stage_io<T, 4, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
-    case 3: fft_stage_io<T, 3, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
-    default: fft_stage_io<T, 2, INV, GIN, GOUT, TWL>(col, c, p.L, ns, lane, tpc, active, tw, ld, st, hook); break;
+    case 8: MMX_STAGE(8); break;
+    case 4: MMX_STAGE(4); break;
+    case 3:
+      if constexpr (!EVEN) MMX_STAGE(3);
+      break;
+    default: MMX_STAGE(2); break;
   }
+#undef MMX_STAGE
 }
 
-// hook(): called once by every thread inside the first stage, after that
-// stage's global loads are issued (GIN only) -- e.g. to copy a twiddle table
-// into LDS while the data loads are in flight.  tw as for fft_columns.
-template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, class Load, class Store, class Hook,
-          bool R16 = false>
-__device__ __forceinline__ void fft_columns_io(Cx<T>* lds, const FftDesc<T>& p, const Cx<T>* tw, int cs, int ncol,
-                                               int tpc, Load ld, Store st, Hook hook) {
+// Transform of ncol columns, column c = threadIdx.x / tpc.  Without GIN the
+// input is the LDS column, without GOUT the output is (natural order).
+// hin / hout as HIN / HOUT above; the caller passes them only where the data
+// lengths allow (exactly L/2 inputs / outputs), and they are dropped unless the
+// plan's end radix is even.  The first stage's loads are issued before hook().
+template <typename T, bool INV, bool GIN, bool GOUT, bool TWL, bool R16 = false, class Load, class Store,
+          class Hook>
+__device__ __forceinline__ void fft_run(Cx<T>* lds, const FftDesc<T>& p, const Cx<T>* tw, int cs, int ncol, int tpc,
+                                        bool hin, bool hout, Load ld, Store st, Hook hook) {
   const int c = threadIdx.x / tpc;
-  const int lane = threadIdx.x % tpc;
+  const int lane = threadIdx.x - c * tpc;
   const bool active = c < ncol;
   Cx<T>* col = lds + (active ? c : 0) * cs;
+  hin = hin && (p.code & kFftFirstEven) && p.nst > 1;
+  hout = hout && (p.code & kFftLastEven) && p.nst > 1;
   if (p.nst == 0) {  // length 1: identity
     if constexpr (GIN) hook();
     if (active && lane == 0) {
       Cx<T> v;
-      if constexpr (GIN) v = ld(c, 0);
+      if constexpr (GIN) v = ld.template get<true>(c, 0);
       else v = col[0];
-      if constexpr (GOUT) st(c, 0, v);
+      if constexpr (GOUT) st.template put<true>(c, 0, v);
       else col[0] = v;
     }
     if constexpr (!GOUT) __syncthreads();
     return;
   }
   if (p.nst == 1) {
-    fft_stage_any<T, INV, GIN, GOUT, TWL, R16>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
+    fft_stage_any<T, INV, GIN, GOUT, TWL, R16, true, false, false>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st,
+                                                                   hook);
     return;
   }
-  fft_stage_any<T, INV, GIN, false, TWL, R16>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st, hook);
+  if (hin)
+    fft_stage_any<T, INV, GIN, false, TWL, R16, true, true, false>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st,
+                                                                   hook);
+  else
+    fft_stage_any<T, INV, GIN, false, TWL, R16, true, false, false>(col, c, p, tw, 0, 1, lane, tpc, active, ld, st,
+                                                                    hook);
+  NoHook nh;
   int ns = radix_of(p.code, 0);
   for (int s = 1; s + 1 < p.nst; ++s) {
-    fft_stage_any<T, INV, false, false, TWL, R16>(col, c, p, tw, s, ns, lane, tpc, active, ld, st, hook);
+    fft_stage_any<T, INV, false, false, TWL, R16, false, false, false>(col, c, p, tw, s, ns, lane, tpc, active, ld,
+                                                                       st, nh);
     ns *= radix_of(p.code, s);
   }
-  fft_stage_any<T, INV, false, GOUT, TWL, R16>(col, c, p, tw, p.nst - 1, ns, lane, tpc, active, ld, st, hook);
+  if (hout)
+    fft_stage_any<T, INV, false, GOUT, TWL, R16, false, false, true>(col, c, p, tw, p.nst - 1, ns, lane, tpc, active,
+                                                                     ld, st, nh);
+  else
+    fft_stage_any<T, INV, false, GOUT, TWL, R16, false, false, false>(col, c, p, tw, p.nst - 1, ns, lane, tpc,
+                                                                      active, ld, st, nh);
 }
 
-template <typename T, bool INV, bool GIN, bool GOUT, bool R16 = false, class Load, class Store>
-__device__ __forceinline__ void fft_columns_io(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc, Load ld,
-                                               Store st) {
-  fft_columns_io<T, INV, GIN, GOUT, false, Load, Store, NoHook, R16>(lds, p, p.tw, cs, ncol, tpc, ld, st, NoHook{});
+// The same transform for one length L fixed at compile time (a power of two,
+// the plan p2_radix(log2 L, A16, s)) with L/16 threads per column: every
+// index, stride and LDS offset is a constant and no butterfly is predicated,
+// which keeps the kernels that use it small in registers.
+template <typename T, int R, int L, int NS, int SH, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT,
+          class Load, class Store, class Hook>
+__device__ __forceinline__ void fft_stage_s(Cx<T>* __restrict__ col, int c, int lane, bool active,
+                                            const Cx<T>* __restrict__ tw, Load& ld, Store& st, Hook& hook) {
+  static_assert(!(HIN || HOUT) || R % 2 == 0, "half-length ends need an even radix");
+  constexpr bool FIRST = NS == 1;
+  constexpr int TPC = L / 16;
+  constexpr int NB = R >= 16 ? 1 : 16 / R;
+  constexpr int NBF = L / R;
+  static_assert(NB * TPC == NBF, "L/16 threads cover every butterfly");
+  constexpr int RI = HIN ? R / 2 : R;
+  constexpr int RO = HOUT ? R / 2 : R;
+  constexpr int NBP = NBF + (NBF >> SH);
+  constexpr int NSP = NS + (NS >> SH);
+  constexpr int TSTEP = L / (NS * R);
+  Cx<T> v[NB][R];
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int j = lane + k * TPC;
+      if constexpr (GIN) {
+#pragma unroll
+        for (int r = 0; r < RI; ++r) v[k][r] = ld.template get<!HIN>(c, j + r * NBF);
+      } else {
+        const int a = j + (j >> SH);
+#pragma unroll
+        for (int r = 0; r < RI; ++r) v[k][r] = col[a + r * NBP];
+      }
+#pragma unroll
+      for (int r = RI; r < R; ++r) v[k][r] = Cx<T>{T(0), T(0)};
+    }
+  }
+  if constexpr (!GIN) __syncthreads();
+  if constexpr (GIN) hook();
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int j = lane + k * TPC;
+      const int q = j / NS, kk = j % NS;
+      if constexpr (!FIRST) twiddle_powers<T, R, INV, TWL>(v[k], tw, kk * TSTEP);
+      dftR<T, R, INV>(v[k]);
+      const int base = q * NS * R + kk;
+      if constexpr (GOUT) {
+#pragma unroll
+        for (int r = 0; r < RO; ++r) st.template put<!HOUT>(c, base + r * NS, v[k][r]);
+      } else if constexpr (FIRST) {
+        const int a = base + (base >> SH);
+#pragma unroll
+        for (int r = 0; r < RO; ++r) col[a + r + (r >= 8 ? (8 >> SH) : 0)] = v[k][r];
+      } else {
+        const int a = base + (base >> SH);
+#pragma unroll
+        for (int r = 0; r < RO; ++r) col[a + r * NSP] = v[k][r];
+      }
+    }
+  }
+  if constexpr (!GOUT) __syncthreads();
+}
+
+template <typename T, int L, bool A16, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT, int S, int NS,
+          class Load, class Store, class Hook>
+__device__ __forceinline__ void fft_static_from(Cx<T>* col, int c, int lane, bool active, const Cx<T>* tw, Load& ld,
+                                                Store& st, Hook& hook) {
+  constexpr int A = ilog2c(L);
+  constexpr int NST = p2_nst(A, A16);
+  constexpr int R = p2_radix(A, A16, S);
+  constexpr int SH = p2_psh(L, A16);
+  constexpr bool FIRST = S == 0, LAST = S == NST - 1;
+  fft_stage_s<T, R, L, NS, SH, INV, GIN && FIRST, GOUT && LAST, TWL, HIN && FIRST, HOUT && LAST>(col, c, lane, active,
+                                                                                                 tw, ld, st, hook);
+  if constexpr (!LAST) {
+    NoHook nh;
+    fft_static_from<T, L, A16, INV, false, GOUT, TWL, false, HOUT, S + 1, NS * R>(col, c, lane, active, tw, ld, st, nh);
+  }
+}
+
+// Column c = threadIdx.x / (L/16) of ncol; ends as for fft_run (HIN / HOUT
+// compile-time here: exactly L/2 inputs / outputs).
+template <typename T, int L, bool A16, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT, class Load,
+          class Store, class Hook>
+__device__ __forceinline__ void fft_static(Cx<T>* lds, const Cx<T>* tw, int cs, int ncol, Load ld, Store st,
+                                           Hook hook) {
+  static_assert((L & (L - 1)) == 0 && L >= 64, "power-of-two lengths of 64 and more");
+  constexpr int TPC = L / 16;
+  const int c = (int)threadIdx.x / TPC;
+  const int lane = (int)threadIdx.x & (TPC - 1);
+  const bool active = c < ncol;
+  Cx<T>* col = lds + (active ? c : 0) * cs;
+  fft_static_from<T, L, A16, INV, GIN, GOUT, TWL, HIN, HOUT, 0, 1>(col, c, lane, active, tw, ld, st, hook);
+}
+
+// Loads / stores that are never called (LDS input or output)
+template <typename T>
+struct NoLoad {
+  template <bool CHK>
+  __device__ __forceinline__ Cx<T> get(int, int) const { return Cx<T>{T(0), T(0)}; }
+};
+template <typename T>
+struct NoStore {
+  template <bool CHK>
+  __device__ __forceinline__ void put(int, int, Cx<T>) const {}
+};
+
+// LDS to LDS transform of ncol columns
+template <typename T, bool INV, bool TWL, bool R16 = false>
+__device__ __forceinline__ void fft_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, int tpc,
+                                            const Cx<T>* tw, bool hin = false, bool hout = false) {
+  fft_run<T, INV, false, false, TWL, R16>(lds, p, tw, cs, ncol, tpc, hin, hout, NoLoad<T>{}, NoStore<T>{}, NoHook{});
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

@@ -1,1052 +1,20 @@
-// Hot-path kernels for gfx950: demag FFT passes, Fourier-space tensor product,
-// fused local-field + Landau-Lifshitz + Dormand-Prince epilogue, controller,
-// reductions, NEB passes.
-//
-// Effective field per cell (paper, section "Micromagnetics"):
-//   exchange  H = 2A/(mu0 Ms) sum_j (m_j - m_i)/D_ij^2      (open boundaries)
-//   DMI       H = -(D/(mu0 Ms)) sum_j (e_ij x m_j)/D_ij, e_ij = {-e_y,+e_y,+e_x,-e_x,0,0}
-//   anis.     H = 2Ku/(mu0 Ms) (m.u) u
-//   Zeeman    H = H_app
-//   demag     H_i = -sum_j N_{i-j} M_j (eq_hd1), by the convolution theorem on a
-//             zero-padded grid.
-// LL right-hand side (eq_llg2): dm/dt = g1 m x H + g2 m x (m x H).
-//
-// Demag data flow for one evaluation (all FP32 or all FP64):
-//   x pass   m[3][nz][ny][nx] -> real-to-complex along x (two reals packed per
-//            complex, half-length transform) -> Sx[3][nz][Xp][ny] (transposed,
-//            so the y transform reads contiguous rows)
-//   y pass   3-D: Sx -> Sy[3][nz][Xp][Py];  2-D: forward y, tensor product,
-//            inverse y fused, in place in Sx
-//   z pass   3-D: forward z (zero padded in registers or LDS), tensor product,
-//            inverse z, in place in Sy (only the nz physical planes are stored)
-//   y inv    3-D: Sy -> Sx (only the ny physical rows)
-//   x inv    complex-to-real along x for the 3 components of TY rows, then the
-//            local fields, H_eff, LL and the integrator epilogue per cell.
-//
-// Every launch covers a set of groups (instances sharing a mesh): workgroup
-// ranges per group come with the launch, each group's geometry, tables and
-// buffers from device memory, so instances of different meshes advance in one
-// launch per pass.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cfloat>
-#include <cmath>
-
-#include "fft_core.hpp"
-#include "kernels.hpp"
+// Launchers and the remaining kernels of the hot path (the kernels and the
+// inverse-x launcher are in hotpath.hpp; the inverse-x instantiations are
+// compiled in invx_*.hip, one translation unit each).
+#include "hotpath.hpp"
 
 namespace mmx {
 
-constexpr int kNT = 256;   // threads of the pointwise kernels and the register z pass
-constexpr int kUnroll = 8; // global loads kept in flight per thread when filling LDS
+int eval_blocks_per_inst(const Geo& g, const Tuning& tu) { return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz; }
 
-template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
-template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return 1.0f / sqrtf(v); }
-template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Copy of small read-only tables (twiddles, post-processing factors) into LDS:
-// issue() starts the global loads into registers, store() writes them to LDS
-// (and copies any entries beyond NPER per thread directly).  Issuing before
-// a pass's data loads and storing after them lets one memory latency cover both.
-template <typename T, int NPER>
-struct TableCopy {
-  Cx<T> r[NPER];
-  const Cx<T>* a;
-  const Cx<T>* b;
-  int na, nb;
-  __device__ __forceinline__ Cx<T> src(int i) const { return i < na ? gld(a + i) : gld(b + (i - na)); }
-  __device__ __forceinline__ void issue(const Cx<T>* a_, int na_, const Cx<T>* b_, int nb_) {
-    a = a_; b = b_; na = na_; nb = nb_;
-#pragma unroll
-    for (int j = 0; j < NPER; ++j) {
-      const int i = threadIdx.x + j * blockDim.x;
-      if (i < na + nb) r[j] = src(i);
-    }
-  }
-  __device__ __forceinline__ void store(Cx<T>* dst) const {
-#pragma unroll
-    for (int j = 0; j < NPER; ++j) {
-      const int i = threadIdx.x + j * blockDim.x;
-      if (i < na + nb) dst[i] = r[j];
-    }
-    for (int i = threadIdx.x + NPER * blockDim.x; i < na + nb; i += blockDim.x) dst[i] = src(i);
-  }
-};
-
-// The same for nseg segments of a real array: segment k is seg_len entries
-// starting at src + k * seg_stride, stored one after the other in LDS.
-template <typename T, int NPER>
-struct SegTableCopy {
-  T r[NPER];
-  const T* src;
-  size_t stride;
-  int len, n;
-  __device__ __forceinline__ T at(int i) const {
-    const int k = i / len, e = i - k * len;
-    return gld(src + k * stride + e);
-  }
-  __device__ __forceinline__ void issue(const T* src_, size_t stride_, int len_, int nseg) {
-    src = src_; stride = stride_; len = len_; n = len_ * nseg;
-#pragma unroll
-    for (int j = 0; j < NPER; ++j) {
-      const int i = threadIdx.x + j * blockDim.x;
-      if (i < n) r[j] = at(i);
-    }
-  }
-  __device__ __forceinline__ void store(T* dst) const {
-#pragma unroll
-    for (int j = 0; j < NPER; ++j) {
-      const int i = threadIdx.x + j * blockDim.x;
-      if (i < n) dst[i] = r[j];
-    }
-    for (int i = threadIdx.x + NPER * blockDim.x; i < n; i += blockDim.x) dst[i] = at(i);
-  }
-};
-
-// Group of this workgroup and its index inside the group (XCD-ordered).
-template <typename T>
-__device__ __forceinline__ int group_of(const Launch<T>& L, long long& lb) {
-  int gi = 0;
-  while (gi + 1 < L.ngroups && (long long)blockIdx.x >= L.off[gi + 1]) ++gi;
-  const long long nb = L.off[gi + 1] - L.off[gi];
-  lb = xcd_tile((long long)blockIdx.x - L.off[gi], nb);
-  return gi;
-}
-
-// ---------------------------------------------------------------------------
-// x forward: real-to-complex of TY rows (fixed b, c, z), transposed store.
-// ---------------------------------------------------------------------------
-__host__ __device__ inline long long fwd_blocks(const Geo& g, const Tuning& tu, int batch) {
-  return (long long)batch * 3 * g.nz * ((g.ny + tu.ty_f - 1) / tu.ty_f);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
-  long long bid;
-  const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
-  const Epi<T> ep = ldu(L.epis + gi);
-  const Geo& g = hp.g;
-  if (bid >= fwd_blocks(g, hp.tu, hp.batch)) return;
-  const int TY = hp.tu.ty_f;
-  const int tiles = (g.ny + TY - 1) / TY;
-  const int tile = bid % tiles; bid /= tiles;
-  const int z = bid % g.nz; bid /= g.nz;
-  const int c = bid % 3;
-  const int b = (int)(bid / 3);
-  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
-  const int y0 = tile * TY;
-  const int cs = col_stride(g.Lx);
-  // LDS: TY columns, then the twiddle table (Lx) and the post factors (Lx + 1)
-  Cx<T>* const twl = lds + TY * cs;
-  Cx<T>* const postl = twl + g.Lx;
-  TableCopy<T, 4> tab;
-  tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
-  const T* src = ep.in + ((size_t)b * 3 + c) * g.N + (size_t)z * g.ny * g.nx;
-  const int ny = g.ny, nx = g.nx;
-  const bool pairs = (nx & 1) == 0;  // rows start 8-byte aligned: load x[2n], x[2n+1] at once
-  // element n of row r packs x[2n] + i x[2n+1] (zero beyond nx and past the last row)
-  auto ld = [=](int r, int n) -> Cx<T> {
-    Cx<T> v = {T(0), T(0)};
-    const int y = y0 + r;
-    if (y < ny) {
-      const T* row = src + (size_t)y * nx;
-      const int i0 = 2 * n;
-      if (pairs) {
-        if (i0 < nx) v = gld(reinterpret_cast<const Cx<T>*>(row) + n);
-      } else {
-        if (i0 < nx) v.x = gld(row + i0);
-        if (i0 + 1 < nx) v.y = gld(row + i0 + 1);
-      }
-    }
-    return v;
-  };
-  auto st = [](int, int, Cx<T>) {};
-  auto hook = [&]() { tab.store(twl); };
-  fft_columns_io<T, false, true, false, true>(lds, hp.fd[0], twl, cs, TY, (int)blockDim.x / TY, ld, st, hook);
-  Cx<T>* dst = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny;
-  const int tot2 = TY * g.Xp;
-  for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
-    const int k = t / TY, r = t - k * TY;
-    const int y = y0 + r;
-    if (y >= g.ny) continue;
-    const Cx<T> Zk = lds[r * cs + pidx(k == g.Lx ? 0 : k)];
-    const Cx<T> Zc = cconj(lds[r * cs + pidx(k == 0 ? 0 : g.Lx - k)]);
-    const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
-    const Cx<T> D = cscale(csub(Zk, Zc), T(0.5));
-    const Cx<T> O = {D.y, -D.x};  // D / i
-    gst(dst + (size_t)k * g.ny + y, cadd(E, cmul(postl[k], O)));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Tensor product at one spectral point: H_a = s * sum_b K_ab M_b (K real).
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int ky, int kz, T s,
-                                             Cx<T>& m0, Cx<T>& m1, Cx<T>& m2) {
-  const Geo& g = hp.g;
-  const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
-  const int kzf = kz <= g.Pz - kz ? kz : g.Pz - kz;
-  const T sy = ky > g.Py - ky ? T(-1) : T(1);
-  const T sz = kz > g.Pz - kz ? T(-1) : T(1);
-  const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
-  const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
-  const T kxx = gld(hp.kt + off) * s;
-  const T kyy = gld(hp.kt + cstride + off) * s;
-  const T kzz = gld(hp.kt + 2 * cstride + off) * s;
-  const T kxy = gld(hp.kt + 3 * cstride + off) * (s * sy);
-  T kxz = T(0), kyz = T(0);
-  if (hp.ncomp == 6) {
-    kxz = gld(hp.kt + 4 * cstride + off) * (s * sz);
-    kyz = gld(hp.kt + 5 * cstride + off) * (s * sy * sz);
-  }
-  const Cx<T> a = m0, b = m1, c = m2;
-  m0 = {kxx * a.x + kxy * b.x + kxz * c.x, kxx * a.y + kxy * b.y + kxz * c.y};
-  m1 = {kxy * a.x + kyy * b.x + kyz * c.x, kxy * a.y + kyy * b.y + kyz * c.y};
-  m2 = {kxz * a.x + kyz * b.x + kzz * c.x, kxz * a.y + kyz * b.y + kzz * c.y};
-}
-
-// ---------------------------------------------------------------------------
-// y pass.  2-D groups (nz = 1): forward y, tensor product, inverse y for cb_y2
-// kx values and the 3 components, in place in Sx.  3-D groups: rows of fixed
-// (b, c, z, kx); forward Sx(ny) -> Sy(Py) or inverse Sy(Py) -> Sx(ny).
-// ---------------------------------------------------------------------------
-__host__ __device__ inline long long y2d_blocks(const Geo& g, const Tuning& tu, int batch) {
-  return (long long)batch * ((g.Xp + tu.cb_y2 - 1) / tu.cb_y2);
-}
-__host__ __device__ inline long long y3d_blocks(const Geo& g, const Tuning& tu, int batch) {
-  return (long long)batch * ((3LL * g.nz * g.Xp + tu.cb_y - 1) / tu.cb_y);
-}
-
-template <typename T, bool R16>
-__device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid, Cx<T>* lds) {
-  const Geo& g = hp.g;
-  const int CB = hp.tu.cb_y2;
-  const int tiles = (g.Xp + CB - 1) / CB;
-  const int tile = (int)(bid % tiles);
-  const int b = (int)(bid / tiles);
-  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
-  const int kx0 = tile * CB;
-  const int ncol = 3 * CB;
-  const int cs = col_stride(g.Py);
-  Cx<T>* base = hp.Sx + (size_t)b * g.sx;  // [3][1][Xp][ny]
-  // column col = c*CB + j holds component c of kx = kx0 + j
-  const int Xp = g.Xp, ny = g.ny;
-  auto ld = [=](int col, int y) -> Cx<T> {
-    const int c = col / CB, j = col - c * CB;
-    const bool ok = y < ny && kx0 + j < Xp;
-    return ok ? gld(base + ((size_t)c * Xp + kx0 + j) * ny + y) : Cx<T>{T(0), T(0)};
-  };
-  auto st = [=](int col, int y, Cx<T> v) {
-    const int c = col / CB, j = col - c * CB;
-    if (y < ny && kx0 + j < Xp) gst(base + ((size_t)c * Xp + kx0 + j) * ny + y, v);
-  };
-  const int tpc = blockDim.x / ncol;
-  // LDS after the columns: the twiddle table (Py) and the tensor rows of this
-  // tile, kt[a][j][ky] for the components a = xx, yy, zz, xy and the CB kx
-  // (nz = 1: one kz plane), both copied while the first stage's loads fly
-  Cx<T>* const twl = lds + ncol * cs;
-  T* const ktl = reinterpret_cast<T*>(twl + g.Py);
-  const int ncb = Xp - kx0 < CB ? Xp - kx0 : CB;  // kx of this tile inside the spectrum
-  TableCopy<T, 4> tab;
-  tab.issue(hp.fd[1].tw, g.Py, nullptr, 0);
-  SegTableCopy<T, 8> ktab;
-  ktab.issue(hp.kt + (size_t)kx0 * g.Ky, (size_t)g.Kz * g.Xp * g.Ky, ncb * g.Ky, 4);
-  auto hook = [&]() {
-    tab.store(twl);
-    ktab.store(ktl);
-  };
-  fft_columns_io<T, false, true, false, true, decltype(ld), decltype(st), decltype(hook), R16>(
-      lds, hp.fd[1], twl, cs, ncol, tpc, ld, st, hook);
-  Cx<T>* const spec = lds;
-  const T s = T(ldu(&hp.prm[b].demag_scale));
-  const int seg = ncb * g.Ky;
-  for (int t = threadIdx.x; t < ncb * g.Py; t += blockDim.x) {
-    const int j = t / g.Py, ky = t - j * g.Py;
-    const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
-    const T sy = ky > g.Py - ky ? T(-1) : T(1);
-    const int o = j * g.Ky + kyf;
-    const T kxx = ktl[o] * s, kyy = ktl[seg + o] * s, kzz = ktl[2 * seg + o] * s;
-    const T kxy = ktl[3 * seg + o] * (s * sy);
-    Cx<T>& m0 = spec[(0 * CB + j) * cs + pidx(ky)];
-    Cx<T>& m1 = spec[(1 * CB + j) * cs + pidx(ky)];
-    Cx<T>& m2 = spec[(2 * CB + j) * cs + pidx(ky)];
-    const Cx<T> a = m0, bq = m1, c = m2;
-    m0 = {kxx * a.x + kxy * bq.x, kxx * a.y + kxy * bq.y};
-    m1 = {kxy * a.x + kyy * bq.x, kxy * a.y + kyy * bq.y};
-    m2 = {kzz * c.x, kzz * c.y};
-  }
-  __syncthreads();
-  fft_columns_io<T, true, false, true, true, decltype(ld), decltype(st), NoHook, R16>(lds, hp.fd[1], twl, cs, ncol,
-                                                                                    tpc, ld, st, NoHook{});
-}
-
-template <typename T, bool INV, bool R16>
-__device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid, Cx<T>* lds) {
-  const Geo& g = hp.g;
-  const int CB = hp.tu.cb_y;
-  const long long rows_per_inst = 3LL * g.nz * g.Xp;
-  const long long tiles = (rows_per_inst + CB - 1) / CB;
-  const long long tile = bid % tiles;
-  const int b = (int)(bid / tiles);
-  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
-  const long long row0 = tile * CB;
-  const int ncol = (int)((rows_per_inst - row0) < CB ? (rows_per_inst - row0) : CB);
-  const int cs = col_stride(g.Py);
-  const int nin = INV ? g.Py : g.ny;
-  const int nout = INV ? g.ny : g.Py;
-  const Cx<T>* src = (INV ? hp.Sy + (size_t)b * g.sy : hp.Sx + (size_t)b * g.sx) + (size_t)row0 * nin;
-  Cx<T>* dst = (INV ? hp.Sx + (size_t)b * g.sx : hp.Sy + (size_t)b * g.sy) + (size_t)row0 * nout;
-  auto ld = [=](int c, int e) -> Cx<T> {
-    return e < nin ? gld(src + (size_t)c * nin + e) : Cx<T>{T(0), T(0)};
-  };
-  auto st = [=](int c, int e, Cx<T> v) {
-    if (e < nout) gst(dst + (size_t)c * nout + e, v);
-  };
-  fft_columns_io<T, INV, true, true, R16>(lds, hp.fd[1], cs, ncol, (int)blockDim.x / CB, ld, st);
-}
-
-// Forward y pass of every group: fused 2-D or 3-D forward rows.
-// R16: the y plans hold radix-16 stages (lengths beyond 512 points).
-template <typename T, bool R16>
-__global__ void __launch_bounds__(512) k_ypass(Launch<T> L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
-  long long bid;
-  const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
-  if (hp.g.nz == 1) {
-    if (bid >= y2d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_fused2d<T, R16>(hp, ldu(L.epis + gi), bid, lds);
-  } else {
-    if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_rows3d<T, false, R16>(hp, ldu(L.epis + gi), bid, lds);
-  }
-}
-
-template <typename T, bool R16>
-__global__ void __launch_bounds__(512) k_yinv(Launch<T> L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
-  long long bid;
-  const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
-  if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-  y_rows3d<T, true, R16>(hp, ldu(L.epis + gi), bid, lds);
-}
-
-// ---------------------------------------------------------------------------
-// 3-D z pass (LDS version, any Pz): forward z, tensor product, inverse z for
-// qz consecutive (kx,ky) points and the 3 components, in place in Sy.
-// ---------------------------------------------------------------------------
-__host__ __device__ inline long long zlds_blocks(const Geo& g, const Tuning& tu, int batch) {
-  return (long long)batch * (((long long)g.Xp * g.Py + tu.qz - 1) / tu.qz);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
-  long long bid;
-  const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
-  const Epi<T> ep = ldu(L.epis + gi);
-  const Geo& g = hp.g;
-  if (bid >= zlds_blocks(g, hp.tu, hp.batch)) return;
-  const int QZ = hp.tu.qz;
-  const long long nq = (long long)g.Xp * g.Py;
-  const long long tiles = (nq + QZ - 1) / QZ;
-  const long long tile = bid % tiles;
-  const int b = (int)(bid / tiles);
-  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
-  const long long q0 = tile * QZ;
-  const int nqt = (int)((nq - q0) < QZ ? (nq - q0) : QZ);
-  const int cs = col_stride(g.Pz);
-  Cx<T>* base = hp.Sy + (size_t)b * g.sy;  // [3][nz][Xp*Py]
-  const size_t plane = (size_t)nq;
-  // column col = c*QZ + j, element z
-  for (int t0 = threadIdx.x; t0 < 3 * g.Pz * QZ; t0 += kUnroll * blockDim.x) {
-    Cx<T> v[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int t = t0 + u * blockDim.x;
-      const int j = t % QZ;
-      const int cz = t / QZ;
-      const int c = cz / g.Pz, z = cz - c * g.Pz;
-      v[u] = {T(0), T(0)};
-      if (t < 3 * g.Pz * QZ && z < g.nz && j < nqt) v[u] = gld(base + ((size_t)c * g.nz + z) * plane + q0 + j);
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int t = t0 + u * blockDim.x;
-      if (t < 3 * g.Pz * QZ) {
-        const int j = t % QZ;
-        const int cz = t / QZ;
-        const int c = cz / g.Pz, z = cz - c * g.Pz;
-        lds[(c * QZ + j) * cs + pidx(z)] = v[u];
-      }
-    }
-  }
-  __syncthreads();
-  const int tpc = blockDim.x / (3 * QZ);
-  fft_columns<T, false>(lds, hp.fd[2], cs, 3 * QZ, tpc);
-  const T s = T(ldu(&hp.prm[b].demag_scale));
-  for (int t = threadIdx.x; t < QZ * g.Pz; t += blockDim.x) {
-    const int j = t % QZ, kz = t / QZ;
-    if (j >= nqt) continue;
-    const long long q = q0 + j;
-    const int kx = (int)(q / g.Py), ky = (int)(q - (long long)kx * g.Py);
-    tensor_apply(hp, kx, ky, kz, s, lds[(0 * QZ + j) * cs + pidx(kz)],
-                 lds[(1 * QZ + j) * cs + pidx(kz)], lds[(2 * QZ + j) * cs + pidx(kz)]);
-  }
-  __syncthreads();
-  fft_columns<T, true>(lds, hp.fd[2], cs, 3 * QZ, tpc);
-  for (int t = threadIdx.x; t < 3 * g.nz * QZ; t += blockDim.x) {
-    const int j = t % QZ;
-    const int cz = t / QZ;
-    const int c = cz / g.nz, z = cz - c * g.nz;
-    if (j < nqt) gst(base + ((size_t)c * g.nz + z) * plane + q0 + j, lds[(c * QZ + j) * cs + pidx(z)]);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// 3-D z pass with the transform in registers: one thread owns the Pz-point
-// columns of the 3 components at one (kx, ky); no LDS, no barriers.
-// ---------------------------------------------------------------------------
-__host__ __device__ inline long long zreg_blocks(const Geo& g, int batch) {
-  return (long long)batch * (((long long)g.Xp * g.Py + kNT - 1) / kNT);
-}
-
-// HALF: nz == Pz / 2 (the usual padding), so the upper half of every input
-// column is a compile-time zero and only the lower half of the output is kept.
-template <typename T, int PZ, bool HALF>
-__device__ __forceinline__ void z3d_reg_body(const Launch<T>& L) {
-  long long bid;
-  const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
-  const Epi<T> ep = ldu(L.epis + gi);
-  const Geo& g = hp.g;
-  if (bid >= zreg_blocks(g, hp.batch)) return;
-  const long long nq = (long long)g.Xp * g.Py;
-  const long long qb = (nq + kNT - 1) / kNT;
-  const int b = (int)(bid / qb);
-  if (ep.ctl && ldu(&ep.ctl[b].done)) return;
-  const long long q = (bid % qb) * kNT + threadIdx.x;
-  if (q >= nq) return;
-  Cx<T>* base = hp.Sy + (size_t)b * g.sy + q;
-  const size_t plane = (size_t)nq;
-  Cx<T> v[3][PZ];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int z = 0; z < PZ; ++z) {
-      v[c][z] = {T(0), T(0)};
-      if (HALF ? z < PZ / 2 : z < g.nz) v[c][z] = gld(base + ((size_t)c * g.nz + z) * plane);
-    }
-  // the stores recompute their addresses from an opaque copy of the column
-  // pointer: keeping the 3 nz load addresses alive through the transforms
-  // would cost two registers each
-  asm volatile("" : "+v"(base));
-#pragma unroll
-  for (int c = 0; c < 3; ++c) RegFft<T, PZ, 1, false>::run(v[c], hp.twz);
-  const int kx = (int)q / g.Py, ky = (int)q - kx * g.Py;
-  const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
-  const T sy = ky > g.Py - ky ? T(-1) : T(1);
-  const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
-  const T s = T(ldu(&hp.prm[b].demag_scale));
-#pragma unroll
-  for (int kz = 0; kz < PZ; ++kz) {
-    const int kzf = kz <= PZ - kz ? kz : PZ - kz;
-    const T sz = kz > PZ - kz ? T(-1) : T(1);
-    const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
-    const T kxx = gld(hp.kt + off) * s;
-    const T kyy = gld(hp.kt + cstride + off) * s;
-    const T kzz = gld(hp.kt + 2 * cstride + off) * s;
-    const T kxy = gld(hp.kt + 3 * cstride + off) * (s * sy);
-    const T kxz = gld(hp.kt + 4 * cstride + off) * (s * sz);
-    const T kyz = gld(hp.kt + 5 * cstride + off) * (s * sy * sz);
-    const Cx<T> a = v[0][kz], bb = v[1][kz], cc = v[2][kz];
-    v[0][kz] = {kxx * a.x + kxy * bb.x + kxz * cc.x, kxx * a.y + kxy * bb.y + kxz * cc.y};
-    v[1][kz] = {kxy * a.x + kyy * bb.x + kyz * cc.x, kxy * a.y + kyy * bb.y + kyz * cc.y};
-    v[2][kz] = {kxz * a.x + kyz * bb.x + kzz * cc.x, kxz * a.y + kyz * bb.y + kzz * cc.y};
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) RegFft<T, PZ, 1, true>::run(v[c], hp.twz);
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int z = 0; z < PZ; ++z)
-      if (HALF ? z < PZ / 2 : z < g.nz) gst(base + ((size_t)c * g.nz + z) * plane, v[c][z]);
-}
-
-// Two waves per SIMD fit the half-zero columns (up to 32 points in FP32)
-// without spilling; the general columns keep the default register budget.
-template <typename T, int PZ>
-__global__ void __launch_bounds__(kNT, 2) k_z3d_reg_half(Launch<T> L) {
-  z3d_reg_body<T, PZ, true>(L);
-}
-
-template <typename T, int PZ>
-__global__ void __launch_bounds__(kNT) k_z3d_reg(Launch<T> L) {
-  z3d_reg_body<T, PZ, false>(L);
-}
-
-// ---------------------------------------------------------------------------
-// 3-D z pass for even Pz = 2M, one (kx, ky) column per lane pair.  The input
-// is zero beyond z = M - 1 (nz <= M), so the even outputs of the length-2M
-// transform are the length-M transform of x and the odd ones that of
-// x[z] exp(-2 pi i z / 2M).  Lane p of the pair computes the outputs with
-// kz = 2k + p, multiplies by the tensor there and transforms back over M
-// points; the inverse over 2M points is the sum of the two halves, the odd
-// half multiplied by exp(+2 pi i z / 2M).  Each lane ends with the z of its
-// parity, after one exchange with its partner.  Half the registers of the
-// one-lane version, so twice to four times the waves per SIMD.
-// ---------------------------------------------------------------------------
-__host__ __device__ inline long long zpair_blocks(const Geo& g, int batch) {
-  return (long long)batch * (((long long)g.Xp * g.Py + kNT / 2 - 1) / (kNT / 2));
-}
-
-// value of the partner lane (lane ^ 1), within a quad
-__device__ __forceinline__ float pair_swap(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double pair_swap(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-template <typename T, int M>
-__global__ void __launch_bounds__(kNT) k_z3d_pair(Launch<T> L) {
-  constexpr int PZ = 2 * M;
-  long long bid;
-  const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
-  const Geo& g = hp.g;
-  if (bid >= zpair_blocks(g, hp.batch)) return;
-  const long long nq = (long long)g.Xp * g.Py;
-  const long long qb = (nq + kNT / 2 - 1) / (kNT / 2);
-  const int b = (int)(bid / qb);
-  DevCtl* const ctl = ldu(&L.epis[gi].ctl);
-  if (ctl && ldu(&ctl[b].done)) return;
-  const int p = threadIdx.x & 1;
-  const long long q = (bid % qb) * (kNT / 2) + (threadIdx.x >> 1);
-  // both lanes of a pair are in range or out of range together (the exchange
-  // below needs the partner); out-of-range pairs compute on zeros and store nothing
-  const bool live = q < nq;
-  const int ql = live ? (int)q : 0;  // out-of-range lanes read element 0 and store nothing
-  const uint32_t qoff = (uint32_t)ql * (uint32_t)sizeof(Cx<T>);
-  Cx<T>* const Syb = hp.Sy + (size_t)b * g.sy;  // plane (c, z) starts at Syb + (c nz + z) nq
-  const int nz = g.nz;
-  Cx<T> v[3][M];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int z = 0; z < M; ++z) {
-      v[c][z] = {T(0), T(0)};
-      if (z < nz) v[c][z] = gldo(Syb + ((size_t)c * nz + z) * nq, qoff);  // uniform branch
-    }
-  // odd lanes: pre-multiply by exp(-2 pi i z / 2M)
-#pragma unroll
-  for (int z = 1; z < M; ++z) {
-    Cx<T> w = ldu(hp.twz + z);
-    if (!p) w = Cx<T>{T(1), T(0)};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) v[c][z] = cmul(v[c][z], w);
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) RegFft<T, M, 1, false, 2>::run(v[c], hp.twz);
-  const int kx = ql / g.Py, ky = ql - kx * g.Py;
-  const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
-  const T sy = ky > g.Py - ky ? T(-1) : T(1);
-  const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
-  const T s = T(ldu(&hp.prm[b].demag_scale));
-  const uint32_t XK = (uint32_t)g.Xp * (uint32_t)g.Ky;
-  const uint32_t kxy0 = (uint32_t)kx * (uint32_t)g.Ky + (uint32_t)kyf;
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const int kz = 2 * k + p;
-    const int kzf = kz <= PZ - kz ? kz : PZ - kz;
-    const T sz = kz > PZ - kz ? T(-1) : T(1);
-    const uint32_t ko = ((uint32_t)kzf * XK + kxy0) * (uint32_t)sizeof(T);
-    const T kxx = gldo(hp.kt, ko) * s;
-    const T kyy = gldo(hp.kt + cstride, ko) * s;
-    const T kzz = gldo(hp.kt + 2 * cstride, ko) * s;
-    const T kxy = gldo(hp.kt + 3 * cstride, ko) * (s * sy);
-    const T kxz = gldo(hp.kt + 4 * cstride, ko) * (s * sz);
-    const T kyz = gldo(hp.kt + 5 * cstride, ko) * (s * sy * sz);
-    const Cx<T> a = v[0][k], bb = v[1][k], cc = v[2][k];
-    v[0][k] = {kxx * a.x + kxy * bb.x + kxz * cc.x, kxx * a.y + kxy * bb.y + kxz * cc.y};
-    v[1][k] = {kxy * a.x + kyy * bb.x + kyz * cc.x, kxy * a.y + kyy * bb.y + kyz * cc.y};
-    v[2][k] = {kxz * a.x + kyz * bb.x + kzz * cc.x, kxz * a.y + kyz * bb.y + kzz * cc.y};
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) RegFft<T, M, 1, true, 2>::run(v[c], hp.twz);
-  // odd lanes: post-multiply by exp(+2 pi i z / 2M)
-#pragma unroll
-  for (int z = 1; z < M; ++z) {
-    Cx<T> w = ldu(hp.twz + z);
-    w.y = -w.y;
-    if (!p) w = Cx<T>{T(1), T(0)};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) v[c][z] = cmul(v[c][z], w);
-  }
-  // z of parity p: own half + partner's half.  Lane p sends the partner the
-  // value at the partner's parity.
-#pragma unroll
-  for (int z0 = 0; z0 < M; z0 += 2) {
-    const int ze = z0, zo = z0 + 1 < M ? z0 + 1 : z0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const Cx<T> send = p ? v[c][ze] : v[c][zo];
-      const Cx<T> got = {pair_swap(send.x), pair_swap(send.y)};
-      const Cx<T> mine = p ? v[c][zo] : v[c][ze];
-      const Cx<T> sum = cadd(mine, got);
-      const int zz = p ? zo : ze;
-      if (live && zz < nz && (p == 0 || z0 + 1 < M)) gsto(Syb + ((size_t)c * nz + zz) * nq, qoff, sum);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Local fields at one cell.  Returns the separate terms when ENERGY is set.
-// ---------------------------------------------------------------------------
-template <typename T> struct V3 { T x, y, z; };
-
-template <typename T>
-__device__ __forceinline__ V3<T> ld3(const T* __restrict__ p, long long N, long long i) {
-  return {gld(p + i), gld(p + N + i), gld(p + 2 * N + i)};
-}
-
-struct LocalTerms {
-  double ex, dmi, an, ze;  // m . H_term (FP64), for energies
-};
-
-// Coefficients of the local terms in the working precision (kept in scalar
-// registers for the whole epilogue).
-template <typename T> struct LocalCoef {
-  T cex[3], cdmi[2], can, u[3], H[3];
-  uint32_t terms;
-};
-
-template <typename T>
-__device__ __forceinline__ LocalCoef<T> local_coef(const DevParams& P) {
-  LocalCoef<T> c;
-  for (int a = 0; a < 3; ++a) {
-    c.cex[a] = T(P.cex[a]);
-    c.u[a] = T(P.u[a]);
-    c.H[a] = T(P.H[a]);
-  }
-  c.cdmi[0] = T(P.cdmi[0]);
-  c.cdmi[1] = T(P.cdmi[1]);
-  c.can = T(P.can);
-  c.terms = P.terms;
-  return c;
-}
-
-// m at a cell and its six neighbours (zero where the mesh ends or no term needs them)
-template <typename T> struct Nbr { V3<T> mi, xm, xp, ym, yp, zm, zp; };
-
-template <typename T>
-__device__ __forceinline__ Nbr<T> load_nbr(const Geo& g, uint32_t terms, const T* __restrict__ mb, int x, int y,
-                                           int z) {
-  const long long N = g.N;
-  const long long i = ((long long)z * g.ny + y) * g.nx + x;
-  Nbr<T> n;
-  n.mi = ld3(mb, N, i);
-  n.xm = {T(0), T(0), T(0)};
-  n.xp = n.xm; n.ym = n.xm; n.yp = n.xm; n.zm = n.xm; n.zp = n.xm;
-  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL)) {
-    if (x > 0) n.xm = ld3(mb, N, i - 1);
-    if (x + 1 < g.nx) n.xp = ld3(mb, N, i + 1);
-    if (y > 0) n.ym = ld3(mb, N, i - g.nx);
-    if (y + 1 < g.ny) n.yp = ld3(mb, N, i + g.nx);
-    if (z > 0) n.zm = ld3(mb, N, i - (long long)g.nx * g.ny);
-    if (z + 1 < g.nz) n.zp = ld3(mb, N, i + (long long)g.nx * g.ny);
-  }
-  return n;
-}
-
-template <typename T, bool ENERGY>
-__device__ __forceinline__ V3<T> local_field(const Geo& g, const LocalCoef<T>& P, const Nbr<T>& nb, int x, int y,
-                                             int z, LocalTerms* lt) {
-  const V3<T> mi = nb.mi;
-  V3<T> H = {T(0), T(0), T(0)};
-  const V3<T> xm = nb.xm, xp = nb.xp, ym = nb.ym, yp = nb.yp, zm = nb.zm, zp = nb.zp;
-  const bool hxm = x > 0, hxp = x + 1 < g.nx, hym = y > 0, hyp = y + 1 < g.ny;
-  const bool hzm = z > 0, hzp = z + 1 < g.nz;
-  if (P.terms & MM_EXCHANGE) {
-    const T cx = P.cex[0], cy = P.cex[1], cz = P.cex[2];
-    V3<T> e = {T(0), T(0), T(0)};
-    auto acc = [&](bool has, V3<T> nb, T c) {
-      if (has) {
-        e.x += c * (nb.x - mi.x);
-        e.y += c * (nb.y - mi.y);
-        e.z += c * (nb.z - mi.z);
-      }
-    };
-    acc(hxm, xm, cx); acc(hxp, xp, cx);
-    acc(hym, ym, cy); acc(hyp, yp, cy);
-    acc(hzm, zm, cz); acc(hzp, zp, cz);
-    H.x += e.x; H.y += e.y; H.z += e.z;
-    if (ENERGY) lt->ex = (double)mi.x * e.x + (double)mi.y * e.y + (double)mi.z * e.z;
-  }
-  if (P.terms & MM_DMI_INTERFACIAL) {
-    // x neighbours: -(D/mu0Ms dx) e_y x (m_{+x} - m_{-x});  e_y x v = (v_z, 0, -v_x)
-    // y neighbours: -(D/mu0Ms dy) e_x x (m_{-y} - m_{+y});  e_x x v = (0, -v_z, v_y)
-    const T cx = P.cdmi[0], cy = P.cdmi[1];
-    const V3<T> dx = {xp.x - xm.x, xp.y - xm.y, xp.z - xm.z};
-    const V3<T> dy = {ym.x - yp.x, ym.y - yp.y, ym.z - yp.z};
-    V3<T> d = {-cx * dx.z, cy * dy.z, cx * dx.x - cy * dy.y};
-    H.x += d.x; H.y += d.y; H.z += d.z;
-    if (ENERGY) lt->dmi = (double)mi.x * d.x + (double)mi.y * d.y + (double)mi.z * d.z;
-  }
-  if (P.terms & MM_ANIS_UNIAXIAL) {
-    const T ux = P.u[0], uy = P.u[1], uz = P.u[2];
-    const T s = P.can * (mi.x * ux + mi.y * uy + mi.z * uz);
-    H.x += s * ux; H.y += s * uy; H.z += s * uz;
-    if (ENERGY) lt->an = (double)s * ((double)mi.x * ux + (double)mi.y * uy + (double)mi.z * uz);
-  }
-  if (P.terms & MM_ZEEMAN) {
-    H.x += P.H[0]; H.y += P.H[1]; H.z += P.H[2];
-    if (ENERGY) lt->ze = (double)mi.x * P.H[0] + (double)mi.y * P.H[1] + (double)mi.z * P.H[2];
-  }
-  return H;
-}
-
-template <typename T>
-__device__ __forceinline__ V3<T> ll_rhs(V3<T> m, V3<T> H, T g1, T g2) {
-  const V3<T> a = {m.y * H.z - m.z * H.y, m.z * H.x - m.x * H.z, m.x * H.y - m.y * H.x};
-  const V3<T> b = {m.y * a.z - m.z * a.y, m.z * a.x - m.x * a.z, m.x * a.y - m.y * a.x};
-  return {g1 * a.x + g2 * b.x, g1 * a.y + g2 * b.y, g1 * a.z + g2 * b.z};
-}
-
-// ---------------------------------------------------------------------------
-// x inverse (complex-to-real) + local fields + LL + epilogue.  One workgroup:
-// TY rows of one z plane of one instance.  The 3 x TY spectra are loaded
-// together, transformed together (one column per component and row) and left
-// in LDS, where the epilogue picks H_d up cell by cell.  DEMAG = false skips
-// the transform (H_d = 0) and uses no LDS for it.  MODE is the epilogue.
-// ---------------------------------------------------------------------------
-__host__ __device__ inline long long inv_blocks(const Geo& g, const Tuning& tu, int batch) {
-  return (long long)batch * g.nz * ((g.ny + tu.ty_x - 1) / tu.ty_x);
-}
-
-int eval_blocks_per_inst(const Geo& g, const Tuning& tu) {
-  return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz;
-}
-
-// Dormand-Prince decision of one instance after its error norm is complete
-// (defined with the controller kernel below).
-__device__ void control_step(DevCtl& C, const double* __restrict__ replay_h);
-
-// CPT > 0: every thread owns at most CPT cells (the host checks TY nx <= CPT
-// threads) and the cell loop is unrolled; CPT == 1 also loads the cell's
-// epilogue inputs (m and neighbours, the step's m and slopes) before the
-// transform, so their latency overlaps it.  CPT == 0: any number of cells.
-// FUSE (MODE_STAGE, DEMAG, CPT > 0): the next stage input just formed for
-// these rows is transformed forward along x here, into the same Sx rows this
-// workgroup read (no other workgroup touches them), which takes the forward x
-// pass of the next evaluation off the critical path.
-template <typename T, bool DEMAG, int MODE, int CPT, bool FUSE>
-__global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
-  constexpr bool PREF = CPT == 1;
-  static_assert(!FUSE || (MODE == MODE_STAGE && DEMAG && CPT > 0), "fused forward pass needs a stage epilogue");
-  extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
-  __shared__ double red[5][512 / 64];
-  constexpr bool energy = MODE == MODE_ENERGY || MODE == MODE_FIELD_ENERGY;
-  long long bid0;
-  const int gi = group_of(L, bid0);
-  const HotPlan<T> hp = ldu(L.hps + gi);
-  const Geo& g = hp.g;
-  if (bid0 >= inv_blocks(g, hp.tu, hp.batch)) return;
-  const int TY = hp.tu.ty_x;
-  const int tiles = (g.ny + TY - 1) / TY;
-  long long bid = bid0;
-  // z varies fastest: the workgroups of planes z - 1, z, z + 1 of a tile (which
-  // read each other's m as the z halo) are neighbours in the XCD-ordered grid
-  const int z = bid % g.nz; bid /= g.nz;
-  const int tile = bid % tiles;
-  const int b = (int)(bid / tiles);
-  DevCtl* const ctl = ldu(&L.epis[gi].ctl);
-  if (ctl && ldu(&ctl[b].done)) return;
-  const bool add_hd = DEMAG && (ldu(&hp.prm[b].terms) & MM_DEMAG);
-  const int y0 = tile * TY;
-  const int nrow = g.ny - y0 < TY ? g.ny - y0 : TY;
-  const int cs = col_stride(g.Lx);
-  const int ncell = nrow * g.nx;
-  const long long N = g.N;
-
-  // prefetch of the single cell's epilogue inputs (PREF)
-  Nbr<T> pnb;
-  V3<T> pbase = {T(0), T(0), T(0)};
-  V3<T> pk[6];
-  if constexpr (PREF) {
-    const Epi<T>* ep = L.epis + gi;
-    const int e = threadIdx.x;
-    const int r = e / g.nx, x = e - r * g.nx;
-    const int ec = e < ncell ? e : 0;  // idle lanes read the first cell and drop it
-    const int rc = ec / g.nx, xc = ec - rc * g.nx;
-    (void)r; (void)x;
-    const size_t ib = (size_t)b * ldu(&ep->inst_stride);
-    const long long i = ((long long)z * g.ny + y0 + rc) * g.nx + xc;
-    pnb = load_nbr<T>(g, ldu(&hp.prm[b].terms), ldu(&ep->in) + ib, xc, y0 + rc, z);
-    if constexpr (MODE == MODE_STAGE) pbase = ld3(ldu(&ep->mbase) + ib, N, i);
-    if constexpr (MODE == MODE_STAGE || MODE == MODE_ERROR) {
-      const int nk = ldu(&ep->nk);
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        pk[j] = {T(0), T(0), T(0)};
-        if (j + 1 < nk && ldu(&ep->coef[j]) != 0.0) pk[j] = ld3(ldu(&ep->kprev[j]) + ib, N, i);
-      }
-    }
-  }
-
-  // LDS: 3 TY columns, then the twiddle table (Lx) and the post factors (Lx + 1)
-  Cx<T>* const twl = lds + 3 * TY * cs;
-  Cx<T>* const postl = twl + g.Lx;
-  if (DEMAG) {
-    TableCopy<T, 4> tab;
-    tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
-    // column c * TY + r holds component c of row y0 + r; rows past the mesh are zero
-    const int ncol = 3 * TY;
-    const size_t cstride = (size_t)g.nz * g.Xp * g.ny;
-    const Cx<T>* src = hp.Sx + (size_t)b * g.sx + (size_t)z * g.Xp * g.ny + y0;
-    const int tot = ncol * g.Xp;
-    for (int t0 = threadIdx.x; t0 < tot; t0 += kUnroll * blockDim.x) {
-      Cx<T> v[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int t = t0 + u * blockDim.x;
-        const int r = t % TY, q = t / TY;
-        const int k = q % g.Xp, c = q / g.Xp;
-        v[u] = {T(0), T(0)};
-        if (t < tot && r < nrow) v[u] = gld(src + c * cstride + (size_t)k * g.ny + r);
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int t = t0 + u * blockDim.x;
-        if (t < tot) {
-          const int r = t % TY, q = t / TY;
-          const int k = q % g.Xp, c = q / g.Xp;
-          lds[(c * TY + r) * cs + pidx(k)] = v[u];
-        }
-      }
-    }
-    tab.store(twl);
-    __syncthreads();
-    // Z2[k] = (X[k] + conj X[Lx-k]) + i (X[k] - conj X[Lx-k]) conj(W^k), k in [0, Lx)
-    const int half = g.Lx / 2;
-    for (int t = threadIdx.x; t < ncol * (half + 1); t += blockDim.x) {
-      const int col = t / (half + 1), k = t - col * (half + 1);
-      Cx<T>* cp = lds + col * cs;
-      const int k2 = g.Lx - k;
-      const Cx<T> Xa = cp[pidx(k)], Xb = cp[pidx(k2)];
-      {
-        const Cx<T> s = cadd(Xa, cconj(Xb));
-        const Cx<T> d = cmul(csub(Xa, cconj(Xb)), cconj(postl[k]));
-        cp[pidx(k)] = Cx<T>{s.x - d.y, s.y + d.x};
-      }
-      if (k > 0 && k < k2) {
-        const Cx<T> s = cadd(Xb, cconj(Xa));
-        const Cx<T> d = cmul(csub(Xb, cconj(Xa)), cconj(postl[k2]));
-        cp[pidx(k2)] = Cx<T>{s.x - d.y, s.y + d.x};
-      }
-    }
-    __syncthreads();
-    fft_columns<T, true, true>(lds, hp.fd[0], cs, ncol, (int)blockDim.x / ncol, twl);
-  }
-
-  // ----- epilogue ----- (its arguments are read only now, which keeps the
-  // scalar registers free during the transform)
-  const Epi<T> epi = ldu(L.epis + gi);
-  const DevParams Pd = ldu(hp.prm + b);
-  const LocalCoef<T> P = local_coef<T>(Pd);
-  const T g1 = T(Pd.g1), g2 = T(Pd.g2);
-  const T* mb = epi.in + (size_t)b * epi.inst_stride;
-  double esum[5] = {0, 0, 0, 0, 0};
-  double emax = 0.0;
-  // h * coefficients; hlast multiplies the k of this stage (entry nk - 1).
-  // Loops over the 7 slots are unrolled so that every index is a constant.
-  T hcoef[7] = {0, 0, 0, 0, 0, 0, 0};
-  T hlast = T(0);
-  if constexpr (MODE == MODE_STAGE || MODE == MODE_ERROR) {
-    const double h = ldu(&ctl[b].h_att);
-#pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      hcoef[j] = j + 1 < epi.nk ? T(h * epi.coef[j]) : T(0);
-      if (j + 1 == epi.nk) hlast = T(h * epi.coef[j]);
-    }
-  }
-  V3<T> mnext[CPT > 0 ? CPT : 1];
-  auto cell = [&](int e, int slot) {
-    const int r = e / g.nx, x = e - r * g.nx;
-    const int y = y0 + r;
-    const long long i = ((long long)z * g.ny + y) * g.nx + x;
-    const Nbr<T> nb = PREF ? pnb : load_nbr<T>(g, P.terms, mb, x, y, z);
-    const V3<T> mi = nb.mi;
-    LocalTerms lt = {0, 0, 0, 0};
-    V3<T> H;
-    if constexpr (energy) H = local_field<T, true>(g, P, nb, x, y, z, &lt);
-    else H = local_field<T, false>(g, P, nb, x, y, z, nullptr);
-    V3<T> hd = {T(0), T(0), T(0)};
-    if (add_hd) {
-      const int kk = pidx(x >> 1);
-      const Cx<T> a = lds[(0 * TY + r) * cs + kk], bq = lds[(1 * TY + r) * cs + kk];
-      const Cx<T> cq = lds[(2 * TY + r) * cs + kk];
-      hd = (x & 1) ? V3<T>{a.y, bq.y, cq.y} : V3<T>{a.x, bq.x, cq.x};
-      H.x += hd.x; H.y += hd.y; H.z += hd.z;
-    }
-    const size_t o = (size_t)b * epi.inst_stride + i;
-    if constexpr (MODE == MODE_FIELD || MODE == MODE_FIELD_ENERGY) {
-      gst(epi.out + o, H.x); gst(epi.out + o + N, H.y); gst(epi.out + o + 2 * N, H.z);
-    }
-    if constexpr (energy) {
-      esum[0] += lt.ex;
-      if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
-      esum[2] += lt.dmi;
-      esum[3] += lt.an;
-      esum[4] += lt.ze;
-    }
-    if constexpr (MODE == MODE_RHS || MODE == MODE_STAGE || MODE == MODE_ERROR) {
-      const V3<T> kk = ll_rhs(mi, H, g1, g2);
-      gst(epi.out + o, kk.x); gst(epi.out + o + N, kk.y); gst(epi.out + o + 2 * N, kk.z);
-      if constexpr (MODE == MODE_STAGE) {
-        // next stage input: m + h sum_j a_j k_j (k of this stage is the last term)
-        V3<T> acc = PREF ? pbase : ld3(epi.mbase + (size_t)b * epi.inst_stride, N, i);
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          if (hcoef[j] == T(0)) continue;
-          const V3<T> kj = PREF ? pk[j] : ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
-          const T cj = hcoef[j];
-          acc.x += cj * kj.x; acc.y += cj * kj.y; acc.z += cj * kj.z;
-        }
-        const T cl = hlast;
-        acc.x += cl * kk.x; acc.y += cl * kk.y; acc.z += cl * kk.z;
-        gst(epi.msn + o, acc.x); gst(epi.msn + o + N, acc.y); gst(epi.msn + o + 2 * N, acc.z);
-        if constexpr (FUSE) mnext[slot] = acc;
-      } else if constexpr (MODE == MODE_ERROR) {
-        double ex = 0, ey = 0, ez = 0;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          if (hcoef[j] == T(0)) continue;
-          const V3<T> kj = PREF ? pk[j] : ld3(epi.kprev[j] + (size_t)b * epi.inst_stride, N, i);
-          const T cj = hcoef[j];
-          ex += (double)(cj * kj.x); ey += (double)(cj * kj.y); ez += (double)(cj * kj.z);
-        }
-        const T cl = hlast;
-        ex += (double)(cl * kk.x); ey += (double)(cl * kk.y); ez += (double)(cl * kk.z);
-        double en = sqrt(ex * ex + ey * ey + ez * ez);
-        if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
-        emax = fmax(emax, en);
-      }
-    }
-    (void)slot;
-  };
-  if constexpr (CPT == 0) {
-    for (int e = threadIdx.x; e < ncell; e += blockDim.x) cell(e, 0);
-  } else {
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      const int e = threadIdx.x + k * blockDim.x;
-      if (e < ncell) cell(e, k);
-    }
-  }
-
-  if constexpr (FUSE) {
-    // forward x transform of the next stage input of these rows, into Sx
-    const int ncol = 3 * TY;
-    __syncthreads();  // every thread is done reading H_d from the columns
-    // real view of column col: x -> 2 pidx(x >> 1) + (x & 1); zero beyond nx
-    T* const re = reinterpret_cast<T*>(lds);
-    const int rcs = 2 * cs;
-    for (int t = threadIdx.x; t < ncol * (2 * g.Lx - g.nx); t += blockDim.x) {
-      const int col = t / (2 * g.Lx - g.nx), x = g.nx + (t - col * (2 * g.Lx - g.nx));
-      re[col * rcs + 2 * pidx(x >> 1) + (x & 1)] = T(0);
-    }
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      const int e = threadIdx.x + k * blockDim.x;
-      if (e < ncell) {
-        const int r = e / g.nx, x = e - r * g.nx;
-        const int off = 2 * pidx(x >> 1) + (x & 1);
-        re[(0 * TY + r) * rcs + off] = mnext[k].x;
-        re[(1 * TY + r) * rcs + off] = mnext[k].y;
-        re[(2 * TY + r) * rcs + off] = mnext[k].z;
-      }
-    }
-    __syncthreads();
-    fft_columns<T, false, true>(lds, hp.fd[0], cs, ncol, (int)blockDim.x / ncol, twl);
-    // real-to-complex post-processing and transposed store (the rows this
-    // workgroup read at the start)
-    const size_t cstride = (size_t)g.nz * g.Xp * g.ny;
-    Cx<T>* dst = hp.Sx + (size_t)b * g.sx + (size_t)z * g.Xp * g.ny + y0;
-    const int tot = ncol * g.Xp;
-    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-      const int r = t % TY, q = t / TY;
-      const int k = q % g.Xp, c = q / g.Xp;
-      if (r >= nrow) continue;
-      const Cx<T>* cp = lds + (c * TY + r) * cs;
-      const Cx<T> Zk = cp[pidx(k == g.Lx ? 0 : k)];
-      const Cx<T> Zc = cconj(cp[pidx(k == 0 ? 0 : g.Lx - k)]);
-      const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
-      const Cx<T> D = cscale(csub(Zk, Zc), T(0.5));
-      const Cx<T> O = {D.y, -D.x};  // D / i
-      gst(dst + c * cstride + (size_t)k * g.ny + r, cadd(E, cmul(postl[k], O)));
-    }
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if constexpr (MODE == MODE_ERROR) {
-    const double w = wave_max(emax);
-    if (lane == 0) red[0][wave] = w;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = red[0][0];
-      for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
-      const unsigned long long prev = atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
-      // the last workgroup of this instance to arrive takes the step decision.
-      // The arrival uses the maximum's returned value (its top bit, always 0
-      // for a non-negative double), so it is issued only once the maximum is
-      // complete; the two atomics are performed where every XCD sees them, so
-      // no fence (an L2 write-back on this part) is needed.
-      const int inc = 1 + (int)(prev >> 63);
-      const int bpi = tiles * g.nz;
-      if (atomicAdd(&ctl[b].arrive, inc) == bpi - 1) {
-        ctl[b].arrive = 0;
-        ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);  // the complete maximum
-        control_step(ctl[b], epi.replay);
-      }
-    }
-  } else if constexpr (energy) {
-    for (int q = 0; q < 5; ++q) {
-      const double w = wave_sum(esum[q]);
-      if (lane == 0) red[q][wave] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) {
-      double v = 0;
-      for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
-      const int bpi = tiles * g.nz;
-      const int lb = (int)(bid0 % bpi);
-      gst(epi.partial + ((size_t)b * bpi + lb) * 5 + threadIdx.x, v);
-    }
-  }
-}
+extern template void inv_x_launch<float, true>(int, int, bool, const Launch<float>&, long long, int, size_t,
+                                               hipStream_t);
+extern template void inv_x_launch<float, false>(int, int, bool, const Launch<float>&, long long, int, size_t,
+                                                hipStream_t);
+extern template void inv_x_launch<double, true>(int, int, bool, const Launch<double>&, long long, int, size_t,
+                                                hipStream_t);
+extern template void inv_x_launch<double, false>(int, int, bool, const Launch<double>&, long long, int, size_t,
+                                                 hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Step begin: finish the previous accepted attempt (project y5, FSAL copy),
@@ -1090,82 +58,6 @@ __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
   gst(ep.bms0 + o, mi.x + c * kv.x);
   gst(ep.bms0 + o + N, mi.y + c * kv.y);
   gst(ep.bms0 + o + 2 * N, mi.z + c * kv.z);
-}
-
-// ---------------------------------------------------------------------------
-// Device-side Dormand-Prince controller, one thread per instance (FP64).
-// ---------------------------------------------------------------------------
-__device__ void control_step(DevCtl& C, const double* __restrict__ replay_h) {
-  if (C.done) {
-    C.pending_finish = 0;
-    C.err_bits = 0ull;
-    return;
-  }
-  const double h = C.h_att;
-  const double err = __longlong_as_double((long long)C.err_bits) / C.rtol;
-  C.err_bits = 0ull;
-  C.last_err = err;
-  C.n_attempt += 1;
-  bool accept;
-  const bool finite_err = err <= DBL_MAX;  // false for NaN and Inf
-  if (!finite_err) {
-    // overflowed stages or NaN in m: reject with the smallest factor; give up
-    // after ten in a row
-    C.nonfinite += 1;
-    if (C.nonfinite >= 10 || C.replay_n > 0) {
-      C.status = MM_E_NONFINITE;
-      C.done = 1;
-      C.pending_finish = 0;
-      C.last_accepted = 0;
-      return;
-    }
-    accept = false;
-  } else {
-    C.nonfinite = 0;
-    accept = C.replay_n > 0 ? true : err <= 1.0;
-  }
-  if (accept) {
-    C.t = (h == C.t_end - C.t) ? C.t_end : C.t + h;
-    C.n_accept += 1;
-    double fac = err == 0.0 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(err, -0.2)));
-    if (C.after_reject) fac = fmin(fac, 1.0);
-    C.after_reject = 0;
-    C.h = fmin(h * fac, C.h_max);
-  } else {
-    C.n_reject += 1;
-    C.after_reject = 1;
-    C.h = finite_err ? h * fmax(0.2, 0.9 * pow(err, -0.2)) : h * 0.2;
-  }
-  C.pending_finish = accept ? 1 : 0;
-  C.last_accepted = accept ? 1 : 0;
-  // next attempt
-  double hn;
-  if (C.replay_n > 0) {
-    C.replay_pos += 1;
-    if (C.replay_pos >= C.replay_n) {
-      C.done = 1;
-      return;
-    }
-    hn = replay_h[C.replay_pos];
-  } else {
-    if (!(C.t_end - C.t > C.h_min)) {  // arrived; a remainder below h_min counts as arrived
-      C.t = C.t_end;
-      C.done = 1;
-      return;
-    }
-    hn = fmin(fmin(C.h, C.h_max), C.t_end - C.t);
-    if (hn < C.h_min) {
-      C.status = MM_E_STEP_UNDERFLOW;
-      C.done = 1;
-      return;
-    }
-  }
-  if (C.n_attempt >= C.max_attempt) {
-    C.status = MM_E_MAXSTEPS;
-    C.done = 1;
-    return;
-  }
-  C.h_att = hn;
 }
 
 __global__ void k_controller(DevCtl* ctl, int n, const double* __restrict__ replay_h) {
@@ -1388,40 +280,6 @@ int z_kind(int Pz) {
 
 }  // namespace
 
-template <typename T, bool DEMAG, int CPT>
-void inv_x_launch_c(int mode, bool fuse, const Launch<T>& L, long long total, int nt, size_t lds, hipStream_t s) {
-  const dim3 grid((unsigned)total);
-  switch (mode) {
-    case MODE_FIELD: k_inv_x<T, DEMAG, MODE_FIELD, CPT, false><<<grid, nt, lds, s>>>(L); break;
-    case MODE_RHS: k_inv_x<T, DEMAG, MODE_RHS, CPT, false><<<grid, nt, lds, s>>>(L); break;
-    case MODE_STAGE:
-      if constexpr (DEMAG && CPT > 0) {
-        if (fuse) {
-          k_inv_x<T, DEMAG, MODE_STAGE, CPT, true><<<grid, nt, lds, s>>>(L);
-          break;
-        }
-      }
-      k_inv_x<T, DEMAG, MODE_STAGE, CPT, false><<<grid, nt, lds, s>>>(L);
-      break;
-    case MODE_ERROR: k_inv_x<T, DEMAG, MODE_ERROR, CPT, false><<<grid, nt, lds, s>>>(L); break;
-    case MODE_ENERGY: k_inv_x<T, DEMAG, MODE_ENERGY, CPT, false><<<grid, nt, lds, s>>>(L); break;
-    default: k_inv_x<T, DEMAG, MODE_FIELD_ENERGY, CPT, false><<<grid, nt, lds, s>>>(L); break;
-  }
-}
-
-// cpt: cells per thread of the unrolled epilogue (1, 2, 4, 8) or 0 (loop)
-template <typename T, bool DEMAG>
-void inv_x_launch(int mode, int cpt, bool fuse, const Launch<T>& L, long long total, int nt, size_t lds,
-                  hipStream_t s) {
-  switch (cpt) {
-    case 1: inv_x_launch_c<T, DEMAG, 1>(mode, fuse, L, total, nt, lds, s); break;
-    case 2: inv_x_launch_c<T, DEMAG, 2>(mode, fuse, L, total, nt, lds, s); break;
-    case 4: inv_x_launch_c<T, DEMAG, 4>(mode, fuse, L, total, nt, lds, s); break;
-    case 8: inv_x_launch_c<T, DEMAG, 8>(mode, fuse, L, total, nt, lds, s); break;
-    default: inv_x_launch_c<T, DEMAG, 0>(mode, false, L, total, nt, lds, s); break;
-  }
-}
-
 // Cells per thread of the unrolled inverse-x epilogue for a launch with nt
 // threads (0: none of 1, 2, 4, 8 fits every group).
 template <typename T>
@@ -1441,6 +299,29 @@ bool eval_fusable(const GroupSet<T>& gs) {
   int nt = 64;
   for (int i = 0; i < gs.n; ++i) nt = std::max(nt, gs.h[i].tu.nt_i);
   return inv_cpt(gs, nt) > 0;
+}
+
+// Length of the y kernels compiled for one Py (k_ypass_s / k_yinv_s), 0 for
+// the general ones: every group of the pass (3-D groups only for the inverse)
+// has Py = 2 ny = SL for one SL in {256, 512, 1024}, and its tile of columns
+// times SL/16 threads fits a workgroup.  nt: the threads to launch.
+template <typename T>
+int static_y(const GroupSet<T>& gs, bool inv, int& nt) {
+  int sl = 0;
+  nt = 64;
+  for (int i = 0; i < gs.n; ++i) {
+    const HotPlan<T>& h = gs.h[i];
+    if (inv && h.g.nz == 1) continue;
+    const int L = h.g.Py;
+    if (L != 2 * h.g.ny || (L != 256 && L != 512 && L != 1024)) return 0;
+    if (sl != 0 && sl != L) return 0;
+    sl = L;
+    const int cols = h.g.nz == 1 ? 3 * h.tu.cb_y2 : h.tu.cb_y;
+    const int t = (cols * (L / 16) + 63) / 64 * 64;
+    if (t > 512) return 0;
+    nt = std::max(nt, t);
+  }
+  return sl;
 }
 
 template <typename T>
@@ -1490,8 +371,16 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         nt = std::max(nt, h.tu.nt_y);
       }
       mark();
-      if (y16) k_ypass<T, true><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
-      else k_ypass<T, false><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
+      int nts = 0;
+      const dim3 grid((unsigned)lb.total);
+      switch (static_y(gs, false, nts)) {
+        case 256: k_ypass_s<T, 256><<<grid, nts, lds, s>>>(lb.L); break;
+        case 512: k_ypass_s<T, 512><<<grid, nts, lds, s>>>(lb.L); break;
+        case 1024: k_ypass_s<T, 1024><<<grid, nts, lds, s>>>(lb.L); break;
+        default:
+          if (y16) k_ypass<T, true><<<grid, nt, lds, s>>>(lb.L);
+          else k_ypass<T, false><<<grid, nt, lds, s>>>(lb.L);
+      }
     }
     if (any3d) {
       // z: register transform for every supported Pz (one launch per distinct
@@ -1546,8 +435,16 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         }
       }
       mark();
-      if (on(3) && y16) k_yinv<T, true><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
-      else if (on(3)) k_yinv<T, false><<<dim3((unsigned)ly.total), nty, ldsy, s>>>(ly.L);
+      int nts = 0;
+      const dim3 gridy((unsigned)ly.total);
+      if (on(3)) switch (static_y(gs, true, nts)) {
+          case 256: k_yinv_s<T, 256><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 512: k_yinv_s<T, 512><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 1024: k_yinv_s<T, 1024><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          default:
+            if (y16) k_yinv<T, true><<<gridy, nty, ldsy, s>>>(ly.L);
+            else k_yinv<T, false><<<gridy, nty, ldsy, s>>>(ly.L);
+        }
     }
   }
   if (on(p_inv)) {  // x inverse + epilogue

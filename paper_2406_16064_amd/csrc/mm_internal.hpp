@@ -36,13 +36,57 @@ template <typename T> struct FftPlan {
 
 // The same plan in the form the kernels take: the radices packed three bits a
 // stage (0: 2, 1: 3, 2: 4, 3: 8, 4: 16; at most 10 stages), first stage in the
-// lowest bits; the spans follow as running products.  Scalars only, so it
-// lives in scalar registers.
+// lowest bits, and two flags above them (first / last radix even, so that a
+// half-length input / output end can be specialised); the spans follow as
+// running products.  psh: the LDS padding shift (3: one slot every 8
+// elements; 31: none), 3 only where every stage's strides keep LDS addresses
+// linear.  Scalars only, so it lives in scalar registers.
+// Radices of a power-of-two length 2^a, as plans take them (radix-3 stages,
+// for 3-smooth lengths, are inserted after the first stage by the host):
+// with a16 and a > 9, sixteens then the remainder 2^(a mod 4); otherwise
+// eights, then the remainder as 4 (a mod 3 = 2), 4 + 4 in place of one 8
+// (a mod 3 = 1, a > 3) or 2 (a = 1).  Shared by the host plans and the
+// kernels compiled for one fixed length.
+__host__ __device__ constexpr int p2_nst(int a, bool a16) {
+  if (a16 && a > 9) return a / 4 + (a % 4 != 0 ? 1 : 0);
+  const int n8 = a / 3, rem = a % 3;
+  if (rem == 1 && n8 > 0) return n8 + 1;
+  return n8 + (rem != 0 ? 1 : 0);
+}
+__host__ __device__ constexpr int p2_radix(int a, bool a16, int s) {
+  if (a16 && a > 9) return s < a / 4 ? 16 : 1 << (a % 4);
+  int n8 = a / 3;
+  const int rem = a % 3;
+  int t0 = 0, t1 = 0;
+  if (rem == 1 && n8 > 0) { --n8; t0 = 4; t1 = 4; }
+  else if (rem == 1) t0 = 2;
+  else if (rem == 2) t0 = 4;
+  return s < n8 ? 8 : s == n8 ? t0 : t1;
+}
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+// LDS padding shift of the plan of a power-of-two length (the rule of
+// describe() below: 3 when every stage keeps LDS addresses linear)
+__host__ __device__ constexpr int p2_psh(int L, bool a16) {
+  const int a = ilog2c(L);
+  int ns = 1;
+  bool lin = a > 0;
+  for (int s = 0; s < p2_nst(a, a16); ++s) {
+    const int R = p2_radix(a, a16, s);
+    if ((L / R) % 8 != 0) lin = false;
+    if (s > 0 && ns % 8 != 0) lin = false;
+    ns *= R;
+  }
+  return lin ? 3 : 31;
+}
+
+constexpr uint32_t kFftFirstEven = 1u << 30;
+constexpr uint32_t kFftLastEven = 1u << 31;
+
 template <typename T> struct FftDesc {
   int L;
   int nst;
   uint32_t code;
-  uint32_t pad;
+  int psh;
   const Cx<T>* tw;
 };
 
@@ -56,10 +100,19 @@ template <typename T> inline FftDesc<T> describe(const FftPlan<T>& p) {
   d.L = p.L;
   d.nst = p.nst;
   d.tw = p.tw;
+  // padding keeps addresses linear when the reads' stride L/R and (after the
+  // first stage) the span are multiples of 8 and the first radix divides 16
+  bool lin = p.nst > 0;
   for (int s = 0; s < p.nst; ++s) {
-    const uint32_t c = p.rad[s] == 2 ? 0u : p.rad[s] == 3 ? 1u : p.rad[s] == 4 ? 2u : p.rad[s] == 8 ? 3u : 4u;
+    const int R = p.rad[s];
+    const uint32_t c = R == 2 ? 0u : R == 3 ? 1u : R == 4 ? 2u : R == 8 ? 3u : 4u;
     d.code |= c << (3 * s);
+    if ((p.L / R) % 8 != 0) lin = false;
+    if (s == 0 ? R == 3 : p.ns[s] % 8 != 0) lin = false;
   }
+  if (p.nst > 0 && p.rad[0] % 2 == 0) d.code |= kFftFirstEven;
+  if (p.nst > 0 && p.rad[p.nst - 1] % 2 == 0) d.code |= kFftLastEven;
+  d.psh = lin ? 3 : 31;
   return d;
 }
 

@@ -63,7 +63,7 @@ int pick_padded(int n, bool even) {
 }
 
 // Radices of a 3-smooth length: the power of two as 8s (a remainder as 4, 4+4
-// or 2), then the 3s.  Where that takes more than three stages of powers of
+// or 2), the 3s placed after the first stage.  Where that takes more than three stages of powers of
 // two, 16s replace the 8s when allow16 (the y passes, whose kernels carry the
 // radix-16 code): one LDS round trip less (measured: the 1024-point y
 // transforms gain, while at 512 and below the larger butterfly's registers
@@ -73,17 +73,10 @@ std::vector<int> radices(int L, bool allow16) {
   int a = 0, b = 0;
   while (L % 2 == 0) { L /= 2; ++a; }
   while (L % 3 == 0) { L /= 3; ++b; }
-  if (allow16 && a > 9) {
-    for (int i = 0; i < a / 4; ++i) r.push_back(16);
-    if (a % 4) r.push_back(1 << (a % 4));
-  } else {
-    int n8 = a / 3, rem = a % 3;
-    if (rem == 1 && n8 > 0) { --n8; r.push_back(4); r.push_back(4); }
-    else if (rem == 1) r.push_back(2);
-    else if (rem == 2) r.push_back(4);
-    for (int i = 0; i < n8; ++i) r.insert(r.begin(), 8);
-  }
-  for (int i = 0; i < b; ++i) r.push_back(3);
+  for (int s = 0; s < p2_nst(a, allow16); ++s) r.push_back(p2_radix(a, allow16, s));
+  // radix-3 stages right after the first stage: spans stay multiples of the
+  // first radix and both ends keep an even radix where L allows
+  r.insert(r.empty() ? r.end() : r.begin() + 1, b, 3);
   return r;
 }
 
@@ -203,6 +196,14 @@ mm_status check_mesh(const mm_mesh* m) {
     return fail(MM_E_ARG, "mesh sizes must satisfy 2 <= nx <= 1024, 1 <= ny, nz <= 1024");
   if (!(is_fin(m->dx) && is_fin(m->dy) && is_fin(m->dz)) || m->dx <= 0 || m->dy <= 0 || m->dz <= 0)
     return fail(MM_E_ARG, "cell sizes must be finite and > 0");
+  return MM_OK;
+}
+
+// The hot-path kernels address one instance's [3][N] arrays with 32-bit byte
+// offsets.
+mm_status check_cells(const mm_mesh* m, mm_precision prec) {
+  const double bytes = 3.0 * m->nx * m->ny * m->nz * (prec == MM_F64 ? 8.0 : 4.0);
+  if (bytes >= 4294967296.0) return fail(MM_E_ARG, "mesh too large: 3 nx ny nz element bytes must stay below 4 GiB");
   return MM_OK;
 }
 
@@ -343,7 +344,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
     const long long rows = 3LL * g.nz * g.ny;
     int ty = 16;
     while (ty > 1 && ((size_t)ty * rowb + xtab > budget || ty * tpx > 512 || rows / ty < want)) ty /= 2;
-    ty = std::min(ty, g.ny);
+    while (ty > g.ny) ty /= 2;  // a power of two (the kernels split rows by shifts)
     if ((size_t)ty * rowb + xtab > 160 * 1024 || ty * tpx > 512) return fail(MM_E_ARG, "mesh too long along x");
     t.ty_f = ty;
     t.nt_f = std::min(512, std::max(64, pow2ceil(std::max(ty * tpx, ty * g.Lx / 4))));
@@ -353,7 +354,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
     const long long rows = (long long)g.nz * g.ny;
     int ty = 16;
     while (ty > 1 && ((size_t)3 * ty * rowb + xtab > budget || 3 * ty * tpx > 512 || rows / ty < want)) ty /= 2;
-    ty = std::min(ty, g.ny);
+    while (ty > g.ny) ty /= 2;  // a power of two (the kernels split rows by shifts)
     if ((size_t)3 * ty * rowb + xtab > 160 * 1024 || 3 * ty * tpx > 512)
       return fail(MM_E_ARG, "mesh too long along x");
     t.ty_x = ty;
@@ -1157,6 +1158,8 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
   const size_t xtab = (size_t)(2 * g.Lx + 1) * csz;
   const size_t ytab = (size_t)g.Py * csz;
+  auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (!pow2(t.ty_f) || !pow2(t.ty_x)) return false;
   if (t.ty_f < 1 || t.ty_f > g.ny || t.nt_f > 512 || t.nt_f < 64 || t.tpc_f * t.ty_f > t.nt_f) return false;
   if (t.tpc_f < tmin(g.Lx) || (size_t)t.ty_f * rowb + xtab > lim) return false;
   if (t.ty_x < 1 || t.ty_x > g.ny || t.nt_i > 512 || t.nt_i < 64 || 3 * t.tpc_x * t.ty_x > t.nt_i) return false;
@@ -1314,6 +1317,7 @@ mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec, 
   *out = nullptr;
   MMCHK(check_mesh(mesh));
   if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
+  MMCHK(check_cells(mesh, prec));
   if (terms & ~MM_ALL_TERMS) return fail(MM_E_ARG, "unknown term bits");
   if (max_batch < 1) return fail(MM_E_ARG, "max_batch must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -1479,6 +1483,7 @@ mm_status mm_batch_create(mm_batch** out, const mm_mesh* meshes, int32_t n_meshe
     return fail(MM_E_ARG, "need 1 to 16 meshes");
   for (int i = 0; i < n_meshes; ++i) MMCHK(check_mesh(&meshes[i]));
   if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
+  for (int i = 0; i < n_meshes; ++i) MMCHK(check_cells(&meshes[i], prec));
   if (terms & ~MM_ALL_TERMS) return fail(MM_E_ARG, "unknown term bits");
   hipStream_t s = (hipStream_t)hip_stream;
   mm_batch* b = new mm_batch();

@@ -174,14 +174,14 @@ __global__ void __launch_bounds__(512) k_fft_axis(Cx<double>* __restrict__ data,
   for (int t = threadIdx.x; t < cb * L; t += blockDim.x) {
     int cl, e;
     if (inner == 1) { cl = t / L; e = t - cl * L; } else { cl = t % cb; e = t / cb; }
-    if (cl < ncol) lds[cl * cs + pidx(e)] = data[addr(c0 + cl, e)];
+    if (cl < ncol) lds[cl * cs + pidx(e, p.psh)] = data[addr(c0 + cl, e)];
   }
   __syncthreads();
-  fft_columns<double, false>(lds, p, cs, ncol, tpc);
+  fft_columns<double, false, false>(lds, p, cs, ncol, tpc, p.tw);
   for (int t = threadIdx.x; t < cb * L; t += blockDim.x) {
     int cl, e;
     if (inner == 1) { cl = t / L; e = t - cl * L; } else { cl = t % cb; e = t / cb; }
-    if (cl < ncol) data[addr(c0 + cl, e)] = lds[cl * cs + pidx(e)];
+    if (cl < ncol) data[addr(c0 + cl, e)] = lds[cl * cs + pidx(e, p.psh)];
   }
 }
 

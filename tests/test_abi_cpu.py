@@ -48,6 +48,12 @@ def test_invalid_arguments_rejected_before_hip(mm):
            mm.Mesh(8, 8, 1, -1e-9, 1e-9, 1e-9),      # negative cell
            mm.Mesh(8, 8, 1, float("nan"), 1e-9, 1e-9),
            mm.Mesh(4096, 8, 1, 1e-9, 1e-9, 1e-9)]    # beyond the supported size
+    # one instance's [3][N] array at 4 GiB or more (32-bit offsets in the kernels):
+    # 1024 x 1024 x 256 cells in FP64 (6 GiB) and 1024^3 in FP32 (12 GiB)
+    big = [(mm.Mesh(1024, 1024, 256, 1e-9, 1e-9, 1e-9), 1), (mm.Mesh(1024, 1024, 1024, 1e-9, 1e-9, 1e-9), 0)]
+    for msh, prec in big:
+        assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(msh), prec, 31, 1, None) == mm.MM_E_ARG
+        assert b"4 GiB" in lib.mm_last_error()
     for msh in bad:
         assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(msh), 0, 31, 1, None) == mm.MM_E_ARG
         assert lib.mm_last_error()

@@ -44,6 +44,9 @@ MESHES = [
     (40, 1, 1, 1e-9, 1e-9, 1e-9),      # 1-D chain (Py = Pz = 1)
     (2, 1, 1, 1e-9, 2e-9, 3e-9),       # smallest mesh
     (96, 70, 3, 2e-9, 2e-9, 2e-9),     # several tiles in x and y, Py = 144
+    (64, 128, 2, 2e-9, 2e-9, 2e-9),    # Py = 256 = 2 ny: y passes compiled for that length
+    (16, 512, 2, 2e-9, 2e-9, 2e-9),    # Py = 1024 (radix-16 plan), 3-D
+    (32, 256, 1, 2e-9, 2e-9, 2e-9),    # Py = 512, 2-D fused y pass
 ]
 
 _kern_cache = {}
