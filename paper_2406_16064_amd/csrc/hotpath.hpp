@@ -189,8 +189,18 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   auto hook = [&]() { tab.store(twl); };
   // all nx / 2 packed inputs present and the rest zero when nx = Lx (even)
   const bool hin = ld.pairs && g.nx == g.Lx;
-  fft_run<T, false, true, false, true>(lds, hp.fd[0], twl, cs, nrow, (int)blockDim.x >> lty, hin, false, ld,
-                                       NoStore<T>{}, hook);
+  const NoStore<T> nst;
+  switch (hin ? g.Lx : 0) {  // compiled for the power-of-two lengths (L/16 threads a row)
+    case 128: fft_static<T, 128, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook); break;
+    case 256: fft_static<T, 256, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook); break;
+    case 512: fft_static<T, 512, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook); break;
+    case 1024:
+      fft_static<T, 1024, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook);
+      break;
+    default:
+      fft_run<T, false, true, false, true>(lds, hp.fd[0], twl, cs, nrow, (int)blockDim.x >> lty, hin, false, ld, nst,
+                                           hook);
+  }
   Cx<T>* dst = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny + y0;
   const int tot2 = g.Xp << lty;
   for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
@@ -842,6 +852,30 @@ __device__ __forceinline__ V3<T> ll_rhs(V3<T> m, V3<T> H, T g1, T g2) {
   return {g1 * a.x + g2 * b.x, g1 * a.y + g2 * b.y, g1 * a.z + g2 * b.z};
 }
 
+// x transform of the inverse-x kernel, LDS to LDS, TWL table twl: compiled for
+// the power-of-two lengths 128 to 1024 (L/16 threads a column; the host's
+// launch shapes give every column that many), the general plan otherwise.
+// Inverse: only the first half of the output is kept; forward: hin as for
+// fft_run (the input's upper half is zero and not read).
+template <typename T, bool INV>
+__device__ __forceinline__ void x_columns(Cx<T>* lds, const FftDesc<T>& p, int cs, int ncol, const Cx<T>* twl,
+                                          bool hin) {
+  constexpr bool HIN = !INV, HOUT = INV;
+  const NoLoad<T> nl;
+  const NoStore<T> nst;
+  const NoHook nh;
+  if (INV || hin) {
+    switch (p.L) {
+      case 128: fft_static<T, 128, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
+      case 256: fft_static<T, 256, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
+      case 512: fft_static<T, 512, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
+      case 1024: fft_static<T, 1024, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
+      default: break;
+    }
+  }
+  fft_columns<T, INV, true>(lds, p, cs, ncol, (int)blockDim.x / ncol, twl, hin, INV);
+}
+
 // ---------------------------------------------------------------------------
 // x inverse (complex-to-real) + local fields + LL + epilogue.  One workgroup:
 // TY rows of one z plane of one instance.  The 3 x TY spectra are loaded
@@ -1054,7 +1088,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     }
     __syncthreads();
     // the epilogue reads complex entries below ceil(nx / 2) <= Lx / 2 only
-    fft_columns<T, true, true>(lds, hp.fd[0], cs, ncol, (int)blockDim.x / ncol, twl, false, true);
+    x_columns<T, true>(lds, hp.fd[0], cs, ncol, twl, false);
   }
 
   // ----- epilogue ----- (its arguments are read only now, which keeps the
@@ -1181,7 +1215,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       }
     }
     __syncthreads();
-    fft_columns<T, false, true>(lds, hp.fd[0], cs, ncol, (int)blockDim.x / ncol, twl, hin, false);
+    x_columns<T, false>(lds, hp.fd[0], cs, ncol, twl, hin);
     // real-to-complex post-processing and transposed store (the rows this
     // workgroup read at the start)
     const size_t cstride = (size_t)g.nz * g.Xp * g.ny;
