@@ -201,17 +201,32 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
       fft_run<T, false, true, false, true>(lds, hp.fd[0], twl, cs, nrow, (int)blockDim.x >> lty, hin, false, ld, nst,
                                            hook);
   }
-  Cx<T>* dst = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.Xp * g.ny + y0;
-  const int tot2 = g.Xp << lty;
-  for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
-    const int k = t >> lty, r = t & (TY - 1);
-    if (r >= nrow) continue;
+  // real-to-complex post-processing: X[k] of row r
+  auto post = [&](int r, int k) -> Cx<T> {
     const Cx<T> Zk = lds[r * cs + pidx(k == g.Lx ? 0 : k, sh)];
     const Cx<T> Zc = cconj(lds[r * cs + pidx(k == 0 ? 0 : g.Lx - k, sh)]);
     const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
     const Cx<T> D = cscale(csub(Zk, Zc), T(0.5));
     const Cx<T> O = {D.y, -D.x};  // D / i
-    gsto(dst, (uint32_t)(k * g.ny + r) * (uint32_t)sizeof(Cx<T>), cadd(E, cmul(postl[k], O)));
+    return cadd(E, cmul(postl[k], O));
+  };
+  if (g.nz > 1) {  // 3-D: Sx [3][nz][XB][ny][kSxB], kSxB TY contiguous entries per block
+    const int lq = lty + 2;  // kSxB = 4
+    Cx<T>* dst = hp.Sx + (size_t)b * g.sx + ((size_t)c * g.nz + z) * g.XB * kSxB * g.ny + kSxB * y0;
+    for (int t = threadIdx.x; t < (g.XB << lq); t += blockDim.x) {
+      const int kb = t >> lq, q = t & ((1 << lq) - 1);
+      const int r = q >> 2, k = kb * kSxB + (q & 3);
+      if (r < nrow && k < g.Xp)
+        gsto(dst, (uint32_t)(kb * kSxB * g.ny + q) * (uint32_t)sizeof(Cx<T>), post(r, k));
+    }
+  } else {  // 2-D: Sx transposed [3][Xp][ny] (the fused y pass reads columns)
+    Cx<T>* dst = hp.Sx + (size_t)b * g.sx + (size_t)c * g.Xp * g.ny + y0;
+    const int tot2 = g.Xp << lty;
+    for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
+      const int k = t >> lty, r = t & (TY - 1);
+      if (r >= nrow) continue;
+      gsto(dst, (uint32_t)(k * g.ny + r) * (uint32_t)sizeof(Cx<T>), post(r, k));
+    }
   }
 }
 
@@ -251,8 +266,9 @@ __device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int k
 __host__ __device__ inline long long y2d_blocks(const Geo& g, const Tuning& tu, int batch) {
   return (long long)batch * ((g.Xp + tu.cb_y2 - 1) / tu.cb_y2);
 }
+// 3-D groups: tiles of cb_y consecutive kx inside one (component, z) plane
 __host__ __device__ inline long long y3d_blocks(const Geo& g, const Tuning& tu, int batch) {
-  return (long long)batch * ((3LL * g.nz * g.Xp + tu.cb_y - 1) / tu.cb_y);
+  return (long long)batch * 3 * g.nz * ((g.Xp + tu.cb_y - 1) / tu.cb_y);
 }
 
 // Global column access of the y passes: this thread's column starts coff
@@ -278,6 +294,31 @@ struct ColStore {
   __device__ __forceinline__ void put(int, int e, Cx<T> v) const {
     if (CHK && e >= n) return;
     gsto(base, coff + (uint32_t)e * (uint32_t)sizeof(Cx<T>), v);
+  }
+};
+
+// The same with entries sb bytes apart (a column inside the x-pass buffer's
+// kx blocks).
+template <typename T>
+struct ColLoadS {
+  const Cx<T>* base;
+  uint32_t coff, sb;
+  int n;
+  template <bool CHK>
+  __device__ __forceinline__ Cx<T> get(int, int e) const {
+    if (CHK && e >= n) return Cx<T>{T(0), T(0)};
+    return gldo(base, coff + (uint32_t)e * sb);
+  }
+};
+template <typename T>
+struct ColStoreS {
+  Cx<T>* base;
+  uint32_t coff, sb;
+  int n;
+  template <bool CHK>
+  __device__ __forceinline__ void put(int, int e, Cx<T> v) const {
+    if (CHK && e >= n) return;
+    gsto(base, coff + (uint32_t)e * sb, v);
   }
 };
 
@@ -353,34 +394,109 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
                                              ColStore<T>{base, coff, ny}, NoHook{});
 }
 
+// 3-D groups keep Sx in kx blocks, [3][nz][XB][ny][kSxB].  A y tile is cb_y
+// consecutive kx of one (component, z) plane.  cb_y a multiple of kSxB: whole
+// blocks, staged through LDS on the Sx side (the forward pass copies the
+// contiguous blocks into the LDS columns and transforms from there; the
+// inverse transforms into LDS and copies the first ny entries of each column
+// back the same way).  cb_y below kSxB (one or two columns of one block, for
+// more workgroups per CU): the transform reads and writes the column straight
+// from the block, entries kSxB apart.  Sy [3][nz][Xp][Py] is read and written
+// row by row by the transform itself.
 template <typename T, bool INV, bool R16, int SL = 0>
 __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid0, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y;
-  const int rows_per_inst = 3 * g.nz * g.Xp;
-  const unsigned tiles = (unsigned)((rows_per_inst + CB - 1) / CB);
-  const unsigned bid = (unsigned)bid0;
-  const int tile = (int)(bid % tiles);
-  const int b = (int)(bid / tiles);
+  const unsigned tiles = (unsigned)((g.Xp + CB - 1) / CB);  // per (component, z) plane
+  unsigned bid = (unsigned)bid0;
+  const int tile = (int)(bid % tiles); bid /= tiles;
+  const int cz = (int)(bid % (3u * (unsigned)g.nz));
+  const int b = (int)(bid / (3u * (unsigned)g.nz));
   if (ep.ctl && ldu(&ep.ctl[b].done)) return;
-  const int row0 = tile * CB;
-  const int ncol = rows_per_inst - row0 < CB ? rows_per_inst - row0 : CB;
+  const int kx0 = tile * CB;
+  const int ncol = g.Xp - kx0 < CB ? g.Xp - kx0 : CB;
   const int cs = col_stride(g.Py);
-  const int nin = INV ? g.Py : g.ny;
-  const int nout = INV ? g.ny : g.Py;
-  const Cx<T>* src = (INV ? hp.Sy + (size_t)b * g.sy : hp.Sx + (size_t)b * g.sx) + (size_t)row0 * nin;
-  Cx<T>* dst = (INV ? hp.Sx + (size_t)b * g.sx : hp.Sy + (size_t)b * g.sy) + (size_t)row0 * nout;
+  const int sh = hp.fd[1].psh;
+  const int ny = g.ny;
+  // Sx blocks kx0 / kSxB ... of this plane; Sy rows cz Xp + kx0 + i
+  Cx<T>* const sx = hp.Sx + (size_t)b * g.sx + (size_t)cz * g.XB * kSxB * ny + (size_t)kx0 * ny;
+  Cx<T>* const sy = hp.Sy + (size_t)b * g.sy + ((size_t)cz * g.Xp + kx0) * g.Py;
   const int tpc = SL > 0 ? SL / 16 : (int)blockDim.x / CB;
   const int c = (int)threadIdx.x / tpc;
   const int cc = c < ncol ? c : 0;
-  const bool half = g.Py == 2 * g.ny;
-  const ColLoad<T> ld{src, (uint32_t)(cc * nin) * (uint32_t)sizeof(Cx<T>), nin};
-  const ColStore<T> st{dst, (uint32_t)(cc * nout) * (uint32_t)sizeof(Cx<T>), nout};
-  if constexpr (SL > 0)
-    fft_static<T, SL, true, INV, true, true, false, !INV, INV>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
-  else
-    fft_run<T, INV, true, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, !INV && half, INV && half, ld,
-                                            st, NoHook{});
+  const bool half = g.Py == 2 * ny;
+  if (CB < kSxB) {
+    Cx<T>* const sxp = hp.Sx + (size_t)b * g.sx + (size_t)cz * g.XB * kSxB * ny;  // plane
+    const int kxc = kx0 + cc;
+    const uint32_t coff = (uint32_t)((kxc >> 2) * kSxB * ny + (kxc & 3)) * (uint32_t)sizeof(Cx<T>);
+    constexpr uint32_t sb = kSxB * sizeof(Cx<T>);
+    const uint32_t yoff = (uint32_t)(cc * g.Py) * (uint32_t)sizeof(Cx<T>);
+    if constexpr (!INV) {
+      const ColLoadS<T> ld{sxp, coff, sb, ny};
+      const ColStore<T> st{sy, yoff, g.Py};
+      if constexpr (SL > 0)
+        fft_static<T, SL, true, false, true, true, false, true, false>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
+      else
+        fft_run<T, false, true, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, half, false, ld, st,
+                                                  NoHook{});
+    } else {
+      const ColLoad<T> ld{sy, yoff, g.Py};
+      const ColStoreS<T> st{sxp, coff, sb, ny};
+      if constexpr (SL > 0)
+        fft_static<T, SL, true, true, true, true, false, false, true>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
+      else
+        fft_run<T, true, true, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, false, half, ld, st,
+                                                 NoHook{});
+    }
+    return;
+  }
+  // entry t of the staged blocks: column i = kSxB (t / (kSxB ny)) + t % kSxB, row
+  // (t / kSxB) % ny; the tile's blocks (ncol rounded up) are contiguous from sx
+  const int nblk = (ncol + kSxB - 1) / kSxB;
+  const FDiv dbl = fdiv_of(kSxB * ny);
+  auto ent = [&](int t, int& i, int& y) {
+    const int q = fdiv_q(t, dbl), e = t - mul24(q, kSxB * ny);
+    y = e >> 2;
+    i = q * kSxB + (e & 3);
+  };
+  if constexpr (!INV) {
+    for (int t = threadIdx.x; t < nblk * kSxB * ny; t += blockDim.x) {  // stage in
+      int i, y;
+      ent(t, i, y);
+      if (i < ncol) lds[i * cs + pidx(y, sh)] = gldo(sx, (uint32_t)t * (uint32_t)sizeof(Cx<T>));
+    }
+    // zero padding of the columns, unless the transform leaves the upper half unread
+    const bool hin = SL > 0 || (half && (hp.fd[1].code & kFftFirstEven) && hp.fd[1].nst > 1);
+    if (!hin) {
+      const int nz0 = g.Py - ny;
+      const FDiv dz = fdiv_of(nz0);
+      for (int t = threadIdx.x; t < CB * nz0; t += blockDim.x) {
+        const int i = fdiv_q(t, dz), y = ny + (t - mul24(i, nz0));
+        lds[i * cs + pidx(y, sh)] = Cx<T>{T(0), T(0)};
+      }
+    }
+    __syncthreads();
+    const ColStore<T> st{sy, (uint32_t)(cc * g.Py) * (uint32_t)sizeof(Cx<T>), g.Py};
+    if constexpr (SL > 0)
+      fft_static<T, SL, true, false, false, true, false, true, false>(lds, hp.fd[1].tw, cs, ncol, NoLoad<T>{}, st,
+                                                                      NoHook{});
+    else
+      fft_run<T, false, false, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, half, false, NoLoad<T>{},
+                                                 st, NoHook{});
+  } else {
+    const ColLoad<T> ld{sy, (uint32_t)(cc * g.Py) * (uint32_t)sizeof(Cx<T>), g.Py};
+    if constexpr (SL > 0)
+      fft_static<T, SL, true, true, true, false, false, false, true>(lds, hp.fd[1].tw, cs, ncol, ld, NoStore<T>{},
+                                                                     NoHook{});
+    else
+      fft_run<T, true, true, false, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, false, half, ld,
+                                                NoStore<T>{}, NoHook{});
+    for (int t = threadIdx.x; t < nblk * kSxB * ny; t += blockDim.x) {  // stage out
+      int i, y;
+      ent(t, i, y);
+      if (i < ncol) gsto(sx, (uint32_t)t * (uint32_t)sizeof(Cx<T>), lds[i * cs + pidx(y, sh)]);
+    }
+  }
 }
 
 // Forward y pass of every group: fused 2-D or 3-D forward rows.
@@ -1038,28 +1154,47 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     // column c * TY + r holds component c of row y0 + r (rows past the mesh
     // are left out: only the epilogue's rows are read back)
     const int ncol = 3 * TY;
-    const size_t cstride = (size_t)g.nz * g.Xp * g.ny;
-    const Cx<T>* src0 = hp.Sx + (size_t)b * g.sx + (size_t)z * g.Xp * g.ny + y0;
-    const int tot = g.Xp << lty;  // (k, r) pairs of one component
+    const size_t plane = g.nz > 1 ? (size_t)g.XB * kSxB * g.ny : (size_t)g.Xp * g.ny;
+    const size_t cstride = (size_t)g.nz * plane;
+    // 3-D groups: Sx [3][nz][XB][ny][kSxB], the tile of a component is XB
+    // runs of kSxB TY entries; 2-D groups: Sx [3][Xp][ny], TY entries of each
+    // kx column
+    const bool blk = g.nz > 1;
+    const Cx<T>* src0 = hp.Sx + (size_t)b * g.sx + (size_t)z * plane + (blk ? kSxB * y0 : y0);
+    const int lq = lty + 2;  // kSxB = 4
+    const int tot = blk ? g.XB << lq : g.Xp << lty;
+    // entry t of a component's tile: row r, kx k; returns its offset from src0
+    auto tile = [&](int t, int& r, int& k) -> uint32_t {
+      if (blk) {
+        const int kb = t >> lq, q = t & ((1 << lq) - 1);
+        r = q >> 2;
+        k = kb * kSxB + (q & 3);
+        return (uint32_t)(kb * kSxB * g.ny + q);
+      }
+      r = t & (TY - 1);
+      k = t >> lty;
+      return (uint32_t)(k * g.ny + r);
+    };
     constexpr int U = 4;
     for (int t0 = threadIdx.x; t0 < tot; t0 += U * blockDim.x) {
       Cx<T> v[U][3];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int t = t0 + u * blockDim.x;
-        const int r = t & (TY - 1), k = t >> lty;
-        const uint32_t off = (uint32_t)(k * g.ny + r) * (uint32_t)sizeof(Cx<T>);
+        int r, k;
+        const uint32_t off = tile(t, r, k) * (uint32_t)sizeof(Cx<T>);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           v[u][c] = {T(0), T(0)};
-          if (t < tot && r < nrow) v[u][c] = gldo(src0 + c * cstride, off);
+          if (t < tot && r < nrow && k < g.Xp) v[u][c] = gldo(src0 + c * cstride, off);
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int t = t0 + u * blockDim.x;
-        const int r = t & (TY - 1), k = t >> lty;
-        if (t < tot) {
+        int r, k;
+        (void)tile(t, r, k);
+        if (t < tot && k < g.Xp) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) lds[(c * TY + r) * cs + pidx(k, sh)] = v[u][c];
         }
@@ -1218,13 +1353,28 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     x_columns<T, false>(lds, hp.fd[0], cs, ncol, twl, hin);
     // real-to-complex post-processing and transposed store (the rows this
     // workgroup read at the start)
-    const size_t cstride = (size_t)g.nz * g.Xp * g.ny;
-    Cx<T>* dst0 = hp.Sx + (size_t)b * g.sx + (size_t)z * g.Xp * g.ny + y0;
-    const int tot = g.Xp << lty;
+    // layouts as for the load at the start
+    const bool blk = g.nz > 1;
+    const size_t plane = blk ? (size_t)g.XB * kSxB * g.ny : (size_t)g.Xp * g.ny;
+    const size_t cstride = (size_t)g.nz * plane;
+    Cx<T>* dst0 = hp.Sx + (size_t)b * g.sx + (size_t)z * plane + (blk ? kSxB * y0 : y0);
+    const int lq = lty + 2;
+    const int tot = blk ? g.XB << lq : g.Xp << lty;
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-      const int r = t & (TY - 1), k = t >> lty;
-      if (r >= nrow) continue;
-      const uint32_t off = (uint32_t)(k * g.ny + r) * (uint32_t)sizeof(Cx<T>);
+      int r, k;
+      uint32_t o;
+      if (blk) {
+        const int kb = t >> lq, q = t & ((1 << lq) - 1);
+        r = q >> 2;
+        k = kb * kSxB + (q & 3);
+        o = (uint32_t)(kb * kSxB * g.ny + q);
+      } else {
+        r = t & (TY - 1);
+        k = t >> lty;
+        o = (uint32_t)(k * g.ny + r);
+      }
+      if (r >= nrow || k >= g.Xp) continue;
+      const uint32_t off = o * (uint32_t)sizeof(Cx<T>);
       const Cx<T> pk = postl[k];
       const int ka = pidx(k == g.Lx ? 0 : k, sh), kb = pidx(k == 0 ? 0 : g.Lx - k, sh);
 #pragma unroll

@@ -5,6 +5,13 @@
 
 namespace mmx {
 
+// x-pass buffer Sx, per instance and component:
+//   2-D groups (nz = 1): [Xp][ny] -- columns of the fused y pass contiguous;
+//   3-D groups: [nz][XB][ny][kSxB] -- kx in blocks of kSxB, so that the x passes
+//     (TY rows: kSxB TY contiguous entries per block) and the y passes (a tile
+//     of kSxB columns: one contiguous block) both move whole cache lines.
+constexpr int kSxB = 4;
+
 // Mesh and padded-grid geometry shared by every pass.
 struct Geo {
   int nx, ny, nz;
@@ -12,8 +19,10 @@ struct Geo {
   int Lx;          // Px / 2: length of the packed complex x transform
   int Xp;          // Lx + 1: number of kx kept after the real-to-complex transform
   int Ky, Kz;      // Py/2 + 1, Pz/2 + 1: folded extents of the tensor spectrum
+  int XB;          // 3-D groups: kx blocks of kSxB in the x-pass buffer, ceil(Xp / kSxB)
+  int pad_;
   long long N;     // cells per instance
-  long long sx;    // complex elements of the x-pass buffer per instance: 3*nz*Xp*ny
+  long long sx;    // complex elements of the x-pass buffer per instance (layouts below)
   long long sy;    // complex elements of the y-pass buffer per instance: 3*nz*Xp*Py
   double dV;       // cell volume
 };
@@ -78,7 +87,7 @@ template <typename T> struct HotPlan {
   const T* kt;             // tensor spectrum [ncomp][Kz][Xp][Ky]
   int ncomp;               // 4 (nz = 1) or 6
   int batch;               // instances in the group
-  Cx<T>* Sx;               // [batch][3][nz][Xp][ny]
+  Cx<T>* Sx;               // [batch][sx] (layout above)
   Cx<T>* Sy;               // [batch][3][nz][Xp][Py] (3-D only)
   const DevParams* prm;    // [batch]
 };

@@ -376,8 +376,8 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
     const int tpc = std::max(tmin, std::min(2 * tmin, 64));
     const size_t colb = (size_t)col_stride(g.Py) * csz;
     const long long rows = 3LL * g.nz * g.Xp;
-    int cb = 16;
-    while (cb > 1 && (cb * colb > budget || cb * tpc > 512 || rows / cb < want)) --cb;
+    int cb = 16;  // whole kx blocks of the x-pass buffer
+    while (cb > kSxB && (cb * colb > budget || cb * tpc > 512 || rows / cb < want)) cb -= kSxB;
     if (cb * colb > 160 * 1024 || cb * tpc > 512) return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y = cb;
     t.tpc_y = tpc;
@@ -508,7 +508,8 @@ mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
   g.Ky = g.Py / 2 + 1;
   g.Kz = g.Pz / 2 + 1;
   g.N = (long long)g.nx * g.ny * g.nz;
-  g.sx = 3LL * g.nz * g.Xp * g.ny;
+  g.XB = (g.Xp + kSxB - 1) / kSxB;
+  g.sx = g.nz == 1 ? 3LL * g.Xp * g.ny : 3LL * g.nz * g.XB * kSxB * g.ny;
   g.sy = 3LL * g.nz * g.Xp * g.Py;
   g.dV = mesh.dx * mesh.dy * mesh.dz;
   MMCHK(choose_tuning(G, E.prec, E.csz));
@@ -1169,7 +1170,8 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
     if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py, true) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
     if (3 * t.cb_y2 * colb + ytab + (size_t)4 * t.cb_y2 * g.Ky * (csz / 2) > lim) return false;
   } else {
-    if (t.cb_y < 1 || t.nt_y > 512 || t.tpc_y < tmin(g.Py, true) || t.cb_y * t.tpc_y > t.nt_y) return false;
+    if (t.cb_y < 1 || (t.cb_y % kSxB != 0 && kSxB % t.cb_y != 0) || t.nt_y > 512 || t.tpc_y < tmin(g.Py, true) || t.cb_y * t.tpc_y > t.nt_y)
+      return false;
     if (t.cb_y * colb > lim) return false;
   }
   return true;
@@ -1227,7 +1229,8 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
       }
     MMCHK(try_all(c, {0}, best));
     c.clear();
-    for (int cb : {1, 2, 3, 4, 6, 8})
+    const std::vector<int> cbs = G.g.nz == 1 ? std::vector<int>{1, 2, 3, 4, 6, 8} : std::vector<int>{1, 2, 4, 8, 12, 16};
+    for (int cb : cbs)
       for (int tf : {1, 2, 4}) {
         Tuning t = best;
         const int tmin = E.prec == MM_F32 ? min_tpc(make_fft<float>(G.g.Py, nullptr, true))
