@@ -359,19 +359,22 @@ __device__ __forceinline__ void fft_run(Cx<T>* lds, const FftDesc<T>& p, const C
 }
 
 // The same transform for one length L fixed at compile time (a power of two,
-// the plan p2_radix(log2 L, A16, s)) with L/16 threads per column: every
-// index, stride and LDS offset is a constant and no butterfly is predicated,
-// which keeps the kernels that use it small in registers.
-template <typename T, int R, int L, int NS, int SH, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT,
-          class Load, class Store, class Hook>
+// the plan p2_radix(log2 L, A16, s)) with EPT entries per thread and stage
+// (16, or 8 for plans without radix 16: L/EPT threads per column, which
+// shortens each stage where a transform has few columns to share the CU):
+// every index, stride and LDS offset is a constant and no butterfly is
+// predicated, which keeps the kernels that use it small in registers.
+template <typename T, int R, int L, int NS, int SH, int EPT, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN,
+          bool HOUT, class Load, class Store, class Hook>
 __device__ __forceinline__ void fft_stage_s(Cx<T>* __restrict__ col, int c, int lane, bool active,
                                             const Cx<T>* __restrict__ tw, Load& ld, Store& st, Hook& hook) {
   static_assert(!(HIN || HOUT) || R % 2 == 0, "half-length ends need an even radix");
   constexpr bool FIRST = NS == 1;
-  constexpr int TPC = L / 16;
-  constexpr int NB = R >= 16 ? 1 : 16 / R;
+  static_assert(R <= EPT, "a butterfly fits the entries of one thread");
+  constexpr int TPC = L / EPT;
+  constexpr int NB = EPT / R;
   constexpr int NBF = L / R;
-  static_assert(NB * TPC == NBF, "L/16 threads cover every butterfly");
+  static_assert(NB * TPC == NBF, "L/EPT threads cover every butterfly");
   constexpr int RI = HIN ? R / 2 : R;
   constexpr int RO = HOUT ? R / 2 : R;
   constexpr int NBP = NBF + (NBF >> SH);
@@ -421,8 +424,8 @@ __device__ __forceinline__ void fft_stage_s(Cx<T>* __restrict__ col, int c, int 
   if constexpr (!GOUT) __syncthreads();
 }
 
-template <typename T, int L, bool A16, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT, int S, int NS,
-          class Load, class Store, class Hook>
+template <typename T, int L, bool A16, int EPT, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT, int S,
+          int NS, class Load, class Store, class Hook>
 __device__ __forceinline__ void fft_static_from(Cx<T>* col, int c, int lane, bool active, const Cx<T>* tw, Load& ld,
                                                 Store& st, Hook& hook) {
   constexpr int A = ilog2c(L);
@@ -430,27 +433,28 @@ __device__ __forceinline__ void fft_static_from(Cx<T>* col, int c, int lane, boo
   constexpr int R = p2_radix(A, A16, S);
   constexpr int SH = p2_psh(L, A16);
   constexpr bool FIRST = S == 0, LAST = S == NST - 1;
-  fft_stage_s<T, R, L, NS, SH, INV, GIN && FIRST, GOUT && LAST, TWL, HIN && FIRST, HOUT && LAST>(col, c, lane, active,
-                                                                                                 tw, ld, st, hook);
+  fft_stage_s<T, R, L, NS, SH, EPT, INV, GIN && FIRST, GOUT && LAST, TWL, HIN && FIRST, HOUT && LAST>(
+      col, c, lane, active, tw, ld, st, hook);
   if constexpr (!LAST) {
     NoHook nh;
-    fft_static_from<T, L, A16, INV, false, GOUT, TWL, false, HOUT, S + 1, NS * R>(col, c, lane, active, tw, ld, st, nh);
+    fft_static_from<T, L, A16, EPT, INV, false, GOUT, TWL, false, HOUT, S + 1, NS * R>(col, c, lane, active, tw, ld,
+                                                                                      st, nh);
   }
 }
 
-// Column c = threadIdx.x / (L/16) of ncol; ends as for fft_run (HIN / HOUT
+// Column c = threadIdx.x / (L/EPT) of ncol; ends as for fft_run (HIN / HOUT
 // compile-time here: exactly L/2 inputs / outputs).
-template <typename T, int L, bool A16, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT, class Load,
-          class Store, class Hook>
+template <typename T, int L, bool A16, bool INV, bool GIN, bool GOUT, bool TWL, bool HIN, bool HOUT, int EPT = 16,
+          class Load, class Store, class Hook>
 __device__ __forceinline__ void fft_static(Cx<T>* lds, const Cx<T>* tw, int cs, int ncol, Load ld, Store st,
                                            Hook hook) {
   static_assert((L & (L - 1)) == 0 && L >= 64, "power-of-two lengths of 64 and more");
-  constexpr int TPC = L / 16;
+  constexpr int TPC = L / EPT;
   const int c = (int)threadIdx.x / TPC;
   const int lane = (int)threadIdx.x & (TPC - 1);
   const bool active = c < ncol;
   Cx<T>* col = lds + (active ? c : 0) * cs;
-  fft_static_from<T, L, A16, INV, GIN, GOUT, TWL, HIN, HOUT, 0, 1>(col, c, lane, active, tw, ld, st, hook);
+  fft_static_from<T, L, A16, EPT, INV, GIN, GOUT, TWL, HIN, HOUT, 0, 1>(col, c, lane, active, tw, ld, st, hook);
 }
 
 // Loads / stores that are never called (LDS input or output)

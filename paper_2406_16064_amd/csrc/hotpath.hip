@@ -304,11 +304,12 @@ bool eval_fusable(const GroupSet<T>& gs) {
 // Length of the y kernels compiled for one Py (k_ypass_s / k_yinv_s), 0 for
 // the general ones: every group of the pass (3-D groups only for the inverse)
 // has Py = 2 ny = SL for one SL in {256, 512, 1024}, and its tile of columns
-// times SL/16 threads fits a workgroup.  nt: the threads to launch.
+// times SL/16 threads fits a workgroup.  ept: entries per thread and stage,
+// 8 (SL/8 threads a column) where the plan has no radix 16 and the workgroup
+// still fits, else 16.  nt: the threads to launch.
 template <typename T>
-int static_y(const GroupSet<T>& gs, bool inv, int& nt) {
-  int sl = 0;
-  nt = 64;
+int static_y(const GroupSet<T>& gs, bool inv, int& nt, int& ept) {
+  int sl = 0, cmax = 0;
   for (int i = 0; i < gs.n; ++i) {
     const HotPlan<T>& h = gs.h[i];
     if (inv && h.g.nz == 1) continue;
@@ -316,11 +317,11 @@ int static_y(const GroupSet<T>& gs, bool inv, int& nt) {
     if (L != 2 * h.g.ny || (L != 256 && L != 512 && L != 1024)) return 0;
     if (sl != 0 && sl != L) return 0;
     sl = L;
-    const int cols = h.g.nz == 1 ? 3 * h.tu.cb_y2 : h.tu.cb_y;
-    const int t = (cols * (L / 16) + 63) / 64 * 64;
-    if (t > 512) return 0;
-    nt = std::max(nt, t);
+    cmax = std::max(cmax, h.g.nz == 1 ? 3 * h.tu.cb_y2 : h.tu.cb_y);
   }
+  if (sl == 0 || cmax * (sl / 16) > 512) return 0;
+  ept = p2_maxradix(sl, true) <= 8 && cmax * (sl / 8) <= 512 ? 8 : 16;
+  nt = std::max(64, (cmax * (sl / ept) + 63) / 64 * 64);
   return sl;
 }
 
@@ -371,12 +372,15 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         nt = std::max(nt, h.tu.nt_y);
       }
       mark();
-      int nts = 0;
+      int nts = 0, ept = 16;
       const dim3 grid((unsigned)lb.total);
-      switch (static_y(gs, false, nts)) {
-        case 256: k_ypass_s<T, 256><<<grid, nts, lds, s>>>(lb.L); break;
-        case 512: k_ypass_s<T, 512><<<grid, nts, lds, s>>>(lb.L); break;
-        case 1024: k_ypass_s<T, 1024><<<grid, nts, lds, s>>>(lb.L); break;
+      const int sly = static_y(gs, false, nts, ept);
+      switch (sly * 100 + (sly ? ept : 0)) {
+        case 25608: k_ypass_s<T, 256, 8><<<grid, nts, lds, s>>>(lb.L); break;
+        case 25616: k_ypass_s<T, 256, 16><<<grid, nts, lds, s>>>(lb.L); break;
+        case 51208: k_ypass_s<T, 512, 8><<<grid, nts, lds, s>>>(lb.L); break;
+        case 51216: k_ypass_s<T, 512, 16><<<grid, nts, lds, s>>>(lb.L); break;
+        case 102416: k_ypass_s<T, 1024, 16><<<grid, nts, lds, s>>>(lb.L); break;
         default:
           if (y16) k_ypass<T, true><<<grid, nt, lds, s>>>(lb.L);
           else k_ypass<T, false><<<grid, nt, lds, s>>>(lb.L);
@@ -435,12 +439,15 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         }
       }
       mark();
-      int nts = 0;
+      int nts = 0, ept = 16;
       const dim3 gridy((unsigned)ly.total);
-      if (on(3)) switch (static_y(gs, true, nts)) {
-          case 256: k_yinv_s<T, 256><<<gridy, nts, ldsy, s>>>(ly.L); break;
-          case 512: k_yinv_s<T, 512><<<gridy, nts, ldsy, s>>>(ly.L); break;
-          case 1024: k_yinv_s<T, 1024><<<gridy, nts, ldsy, s>>>(ly.L); break;
+      const int sly = on(3) ? static_y(gs, true, nts, ept) : 0;
+      if (on(3)) switch (sly * 100 + (sly ? ept : 0)) {
+          case 25608: k_yinv_s<T, 256, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 25616: k_yinv_s<T, 256, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 51208: k_yinv_s<T, 512, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 51216: k_yinv_s<T, 512, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 102416: k_yinv_s<T, 1024, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
           default:
             if (y16) k_yinv<T, true><<<gridy, nty, ldsy, s>>>(ly.L);
             else k_yinv<T, false><<<gridy, nty, ldsy, s>>>(ly.L);

@@ -190,17 +190,24 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   // all nx / 2 packed inputs present and the rest zero when nx = Lx (even)
   const bool hin = ld.pairs && g.nx == g.Lx;
   const NoStore<T> nst;
-  switch (hin ? g.Lx : 0) {  // compiled for the power-of-two lengths (L/16 threads a row)
-    case 128: fft_static<T, 128, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook); break;
-    case 256: fft_static<T, 256, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook); break;
-    case 512: fft_static<T, 512, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook); break;
-    case 1024:
-      fft_static<T, 1024, false, false, true, false, true, true, false>(lds, twl, cs, nrow, ld, nst, hook);
-      break;
+  // compiled for the power-of-two lengths (L/8 threads a row where the
+  // workgroup has them, else L/16)
+  const bool e8 = nrow * (g.Lx / 8) <= (int)blockDim.x;
+#define MMX_FS(LL)                                                                                             \
+  case LL:                                                                                                     \
+    if (e8) fft_static<T, LL, false, false, true, false, true, true, false, 8>(lds, twl, cs, nrow, ld, nst, hook); \
+    else fft_static<T, LL, false, false, true, false, true, true, false, 16>(lds, twl, cs, nrow, ld, nst, hook);   \
+    break;
+  switch (hin ? g.Lx : 0) {
+    MMX_FS(128)
+    MMX_FS(256)
+    MMX_FS(512)
+    MMX_FS(1024)
     default:
       fft_run<T, false, true, false, true>(lds, hp.fd[0], twl, cs, nrow, (int)blockDim.x >> lty, hin, false, ld, nst,
                                            hook);
   }
+#undef MMX_FS
   // real-to-complex post-processing: X[k] of row r
   auto post = [&](int r, int k) -> Cx<T> {
     const Cx<T> Zk = lds[r * cs + pidx(k == g.Lx ? 0 : k, sh)];
@@ -322,8 +329,8 @@ struct ColStoreS {
   }
 };
 
-// SL > 0: compiled for Py = SL = 2 ny (fft_static, SL/16 threads a column).
-template <typename T, bool R16, int SL = 0>
+// SL > 0: compiled for Py = SL = 2 ny (fft_static, SL/EPT threads a column).
+template <typename T, bool R16, int SL = 0, int EPT = 16>
 __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid0, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y2;
@@ -338,7 +345,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   const int cs = col_stride(g.Py);
   const int sh = hp.fd[1].psh;
   const int Xp = g.Xp, ny = g.ny;
-  const int tpc = SL > 0 ? SL / 16 : blockDim.x / (3 * CB);
+  const int tpc = SL > 0 ? SL / EPT : blockDim.x / (3 * CB);
   // this thread's column, in Sx = [3][1][Xp][ny] of the instance
   const int mc = (int)threadIdx.x / tpc;
   const int cc = mc < ncol ? mc : 0;
@@ -360,8 +367,8 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   };
   const bool half = g.Py == 2 * ny;  // ny inputs / outputs of Py points
   if constexpr (SL > 0)
-    fft_static<T, SL, true, false, true, false, true, true, false>(lds, twl, cs, ncol, ColLoad<T>{base, coff, ny},
-                                                                  NoStore<T>{}, hook);
+    fft_static<T, SL, true, false, true, false, true, true, false, EPT>(lds, twl, cs, ncol,
+                                                                       ColLoad<T>{base, coff, ny}, NoStore<T>{}, hook);
   else
     fft_run<T, false, true, false, true, R16>(lds, hp.fd[1], twl, cs, ncol, tpc, half, false,
                                               ColLoad<T>{base, coff, ny}, NoStore<T>{}, hook);
@@ -387,8 +394,8 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   }
   __syncthreads();
   if constexpr (SL > 0)
-    fft_static<T, SL, true, true, false, true, true, false, true>(lds, twl, cs, ncol, NoLoad<T>{},
-                                                                 ColStore<T>{base, coff, ny}, NoHook{});
+    fft_static<T, SL, true, true, false, true, true, false, true, EPT>(lds, twl, cs, ncol, NoLoad<T>{},
+                                                                      ColStore<T>{base, coff, ny}, NoHook{});
   else
     fft_run<T, true, false, true, true, R16>(lds, hp.fd[1], twl, cs, ncol, tpc, false, half, NoLoad<T>{},
                                              ColStore<T>{base, coff, ny}, NoHook{});
@@ -403,7 +410,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
 // more workgroups per CU): the transform reads and writes the column straight
 // from the block, entries kSxB apart.  Sy [3][nz][Xp][Py] is read and written
 // row by row by the transform itself.
-template <typename T, bool INV, bool R16, int SL = 0>
+template <typename T, bool INV, bool R16, int SL = 0, int EPT = 16>
 __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid0, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y;
@@ -421,7 +428,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
   // Sx blocks kx0 / kSxB ... of this plane; Sy rows cz Xp + kx0 + i
   Cx<T>* const sx = hp.Sx + (size_t)b * g.sx + (size_t)cz * g.XB * kSxB * ny + (size_t)kx0 * ny;
   Cx<T>* const sy = hp.Sy + (size_t)b * g.sy + ((size_t)cz * g.Xp + kx0) * g.Py;
-  const int tpc = SL > 0 ? SL / 16 : (int)blockDim.x / CB;
+  const int tpc = SL > 0 ? SL / EPT : (int)blockDim.x / CB;
   const int c = (int)threadIdx.x / tpc;
   const int cc = c < ncol ? c : 0;
   const bool half = g.Py == 2 * ny;
@@ -435,7 +442,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
       const ColLoadS<T> ld{sxp, coff, sb, ny};
       const ColStore<T> st{sy, yoff, g.Py};
       if constexpr (SL > 0)
-        fft_static<T, SL, true, false, true, true, false, true, false>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
+        fft_static<T, SL, true, false, true, true, false, true, false, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
       else
         fft_run<T, false, true, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, half, false, ld, st,
                                                   NoHook{});
@@ -443,7 +450,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
       const ColLoad<T> ld{sy, yoff, g.Py};
       const ColStoreS<T> st{sxp, coff, sb, ny};
       if constexpr (SL > 0)
-        fft_static<T, SL, true, true, true, true, false, false, true>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
+        fft_static<T, SL, true, true, true, true, false, false, true, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
       else
         fft_run<T, true, true, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, false, half, ld, st,
                                                  NoHook{});
@@ -478,7 +485,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
     __syncthreads();
     const ColStore<T> st{sy, (uint32_t)(cc * g.Py) * (uint32_t)sizeof(Cx<T>), g.Py};
     if constexpr (SL > 0)
-      fft_static<T, SL, true, false, false, true, false, true, false>(lds, hp.fd[1].tw, cs, ncol, NoLoad<T>{}, st,
+      fft_static<T, SL, true, false, false, true, false, true, false, EPT>(lds, hp.fd[1].tw, cs, ncol, NoLoad<T>{}, st,
                                                                       NoHook{});
     else
       fft_run<T, false, false, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, half, false, NoLoad<T>{},
@@ -486,7 +493,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
   } else {
     const ColLoad<T> ld{sy, (uint32_t)(cc * g.Py) * (uint32_t)sizeof(Cx<T>), g.Py};
     if constexpr (SL > 0)
-      fft_static<T, SL, true, true, true, false, false, false, true>(lds, hp.fd[1].tw, cs, ncol, ld, NoStore<T>{},
+      fft_static<T, SL, true, true, true, false, false, false, true, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, NoStore<T>{},
                                                                      NoHook{});
     else
       fft_run<T, true, true, false, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, false, half, ld,
@@ -529,8 +536,8 @@ __global__ void __launch_bounds__(512) k_yinv(Launch<T> L) {
 }
 
 // The y passes compiled for one length: every group of the launch has
-// Py = SL = 2 ny (the host checks), SL/16 threads per column.
-template <typename T, int SL>
+// Py = SL = 2 ny (the host checks), SL/EPT threads per column.
+template <typename T, int SL, int EPT>
 __global__ void __launch_bounds__(512) k_ypass_s(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
@@ -539,14 +546,14 @@ __global__ void __launch_bounds__(512) k_ypass_s(Launch<T> L) {
   const HotPlan<T> hp = ldu(L.hps + gi);
   if (hp.g.nz == 1) {
     if (bid >= y2d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_fused2d<T, false, SL>(hp, ldu(L.epis + gi), bid, lds);
+    y_fused2d<T, false, SL, EPT>(hp, ldu(L.epis + gi), bid, lds);
   } else {
     if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-    y_rows3d<T, false, false, SL>(hp, ldu(L.epis + gi), bid, lds);
+    y_rows3d<T, false, false, SL, EPT>(hp, ldu(L.epis + gi), bid, lds);
   }
 }
 
-template <typename T, int SL>
+template <typename T, int SL, int EPT>
 __global__ void __launch_bounds__(512) k_yinv_s(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
@@ -554,7 +561,7 @@ __global__ void __launch_bounds__(512) k_yinv_s(Launch<T> L) {
   const int gi = group_of(L, bid);
   const HotPlan<T> hp = ldu(L.hps + gi);
   if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
-  y_rows3d<T, true, false, SL>(hp, ldu(L.epis + gi), bid, lds);
+  y_rows3d<T, true, false, SL, EPT>(hp, ldu(L.epis + gi), bid, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,13 +988,21 @@ __device__ __forceinline__ void x_columns(Cx<T>* lds, const FftDesc<T>& p, int c
   const NoStore<T> nst;
   const NoHook nh;
   if (INV || hin) {
+    // 8 entries per thread where the workgroup has the threads (shorter stages)
+    const bool e8 = ncol * (p.L / 8) <= (int)blockDim.x;
+#define MMX_XS(LL)                                                                                      \
+  case LL:                                                                                              \
+    if (e8) fft_static<T, LL, false, INV, false, false, true, HIN, HOUT, 8>(lds, twl, cs, ncol, nl, nst, nh); \
+    else fft_static<T, LL, false, INV, false, false, true, HIN, HOUT, 16>(lds, twl, cs, ncol, nl, nst, nh);   \
+    return;
     switch (p.L) {
-      case 128: fft_static<T, 128, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
-      case 256: fft_static<T, 256, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
-      case 512: fft_static<T, 512, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
-      case 1024: fft_static<T, 1024, false, INV, false, false, true, HIN, HOUT>(lds, twl, cs, ncol, nl, nst, nh); return;
+      MMX_XS(128)
+      MMX_XS(256)
+      MMX_XS(512)
+      MMX_XS(1024)
       default: break;
     }
+#undef MMX_XS
   }
   fft_columns<T, INV, true>(lds, p, cs, ncol, (int)blockDim.x / ncol, twl, hin, INV);
 }

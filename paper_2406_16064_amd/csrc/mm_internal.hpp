@@ -64,6 +64,12 @@ __host__ __device__ constexpr int p2_radix(int a, bool a16, int s) {
   return s < n8 ? 8 : s == n8 ? t0 : t1;
 }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+// Largest radix of that plan
+__host__ __device__ constexpr int p2_maxradix(int L, bool a16) {
+  int r = 1;
+  for (int s = 0; s < p2_nst(ilog2c(L), a16); ++s) r = p2_radix(ilog2c(L), a16, s) > r ? p2_radix(ilog2c(L), a16, s) : r;
+  return r;
+}
 // LDS padding shift of the plan of a power-of-two length (the rule of
 // describe() below: 3 when every stage keeps LDS addresses linear)
 __host__ __device__ constexpr int p2_psh(int L, bool a16) {
