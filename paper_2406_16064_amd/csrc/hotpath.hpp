@@ -1263,11 +1263,38 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     }
   }
   V3<T> mnext[CPT > 0 ? CPT : 1];
+  // CPT > 1: the cells' results are stored after all of them are computed, so
+  // that no store sits between one cell's loads and the next (the compiler
+  // may then issue the loads of every cell of the thread together)
+  constexpr bool DEFER = CPT > 1;
+  constexpr int NS = DEFER ? CPT : 1;
+  V3<T> res1[NS], res2[NS];
+  COff cos[NS];
   auto cell = [&](int e, int slot) {
     const int r = fdiv_q(e, dnx), x = e - mul24(r, g.nx);
     const int y = y0 + r;
     const COff co = coff_of<T>(N, (z * g.ny + y) * g.nx + x);
     const Nbr<T> nb = PREF ? pnb : load_nbr<T>(g, P.terms, mb, co, x, y, z);
+    const size_t ib = (size_t)b * epi.inst_stride;
+    // the stage's earlier slopes (and m for the stage input), all issued
+    // before any of them is used: one memory round trip per cell, not one per
+    // slope
+    V3<T> kb[6];
+    V3<T> mbv = {T(0), T(0), T(0)};
+    if constexpr (MODE == MODE_STAGE || MODE == MODE_ERROR) {
+      if constexpr (PREF) {
+        mbv = pbase;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) kb[j] = pk[j];
+      } else {
+        if constexpr (MODE == MODE_STAGE) mbv = ld3o(epi.mbase + ib, co);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          if (hcoef[j] != T(0)) kb[j] = ld3o(epi.kprev[j] + ib, co);
+          else kb[j] = {T(0), T(0), T(0)};
+        }
+      }
+    }
     const V3<T> mi = nb.mi;
     LocalTerms lt = {0, 0, 0, 0};
     V3<T> H;
@@ -1281,8 +1308,11 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       hd = (x & 1) ? V3<T>{a.y, bq.y, cq.y} : V3<T>{a.x, bq.x, cq.x};
       H.x += hd.x; H.y += hd.y; H.z += hd.z;
     }
-    const size_t ib = (size_t)b * epi.inst_stride;
-    if constexpr (MODE == MODE_FIELD || MODE == MODE_FIELD_ENERGY) st3o(epi.out + ib, co, H);
+    if constexpr (DEFER) cos[slot] = co;
+    if constexpr (MODE == MODE_FIELD || MODE == MODE_FIELD_ENERGY) {
+      if constexpr (DEFER) res1[slot] = H;
+      else st3o(epi.out + ib, co, H);
+    }
     if constexpr (energy) {
       esum[0] += lt.ex;
       if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
@@ -1292,29 +1322,28 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     }
     if constexpr (MODE == MODE_RHS || MODE == MODE_STAGE || MODE == MODE_ERROR) {
       const V3<T> kk = ll_rhs(mi, H, g1, g2);
-      st3o(epi.out + ib, co, kk);
+      if constexpr (DEFER) res1[slot] = kk;
+      else st3o(epi.out + ib, co, kk);
       if constexpr (MODE == MODE_STAGE) {
-        // next stage input: m + h sum_j a_j k_j (k of this stage is the last term)
-        V3<T> acc = PREF ? pbase : ld3o(epi.mbase + ib, co);
+        // next stage input: m + h sum_j a_j k_j (k of this stage is the last term;
+        // slots with a zero coefficient hold zeros)
+        V3<T> acc = mbv;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-          if (hcoef[j] == T(0)) continue;
-          const V3<T> kj = PREF ? pk[j] : ld3o(epi.kprev[j] + ib, co);
           const T cj = hcoef[j];
-          acc.x += cj * kj.x; acc.y += cj * kj.y; acc.z += cj * kj.z;
+          acc.x += cj * kb[j].x; acc.y += cj * kb[j].y; acc.z += cj * kb[j].z;
         }
         const T cl = hlast;
         acc.x += cl * kk.x; acc.y += cl * kk.y; acc.z += cl * kk.z;
-        st3o(epi.msn + ib, co, acc);
+        if constexpr (DEFER) res2[slot] = acc;
+        else st3o(epi.msn + ib, co, acc);
         if constexpr (FUSE) mnext[slot] = acc;
       } else if constexpr (MODE == MODE_ERROR) {
         double ex = 0, ey = 0, ez = 0;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-          if (hcoef[j] == T(0)) continue;
-          const V3<T> kj = PREF ? pk[j] : ld3o(epi.kprev[j] + ib, co);
           const T cj = hcoef[j];
-          ex += (double)(cj * kj.x); ey += (double)(cj * kj.y); ez += (double)(cj * kj.z);
+          ex += (double)(cj * kb[j].x); ey += (double)(cj * kb[j].y); ez += (double)(cj * kb[j].z);
         }
         const T cl = hlast;
         ex += (double)(cl * kk.x); ey += (double)(cl * kk.y); ez += (double)(cl * kk.z);
@@ -1332,6 +1361,17 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     for (int k = 0; k < CPT; ++k) {
       const int e = threadIdx.x + k * blockDim.x;
       if (e < ncell) cell(e, k);
+    }
+    if constexpr (DEFER && MODE != MODE_ENERGY) {
+      const size_t ib = (size_t)b * epi.inst_stride;
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        const int e = threadIdx.x + k * blockDim.x;
+        if (e < ncell) {
+          st3o(epi.out + ib, cos[k], res1[k]);
+          if constexpr (MODE == MODE_STAGE) st3o(epi.msn + ib, cos[k], res2[k]);
+        }
+      }
     }
   }
 
