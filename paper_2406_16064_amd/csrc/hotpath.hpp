@@ -1126,13 +1126,68 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   const int z = (int)(bid % (unsigned)g.nz); bid /= (unsigned)g.nz;
   const int tile = (int)(bid % (unsigned)tiles);
   const int b = (int)(bid / (unsigned)tiles);
-  DevCtl* const ctl = ldu(&L.epis[gi].ctl);
-  if (ctl && ldu(&ctl[b].done)) return;
-  const bool add_hd = DEMAG && (ldu(&hp.prm[b].terms) & MM_DEMAG);
   const int y0 = tile * TY;
   const int nrow = g.ny - y0 < TY ? g.ny - y0 : TY;
   const int cs = col_stride(g.Lx);
   const int sh = hp.fd[0].psh;
+
+  // Spectrum tile: column c * TY + r holds component c of row y0 + r (rows past
+  // the mesh are left out: only the epilogue's rows are read back).
+  // 3-D groups: Sx [3][nz][XB][ny][kSxB], the tile of a component is XB runs
+  // of kSxB TY entries; 2-D groups: Sx [3][Xp][ny], TY entries of each kx
+  // column.  Its first batch of loads is issued before anything else waits
+  // (the controller flag, the epilogue's arguments and prefetch).
+  const int ncol = 3 * TY;
+  const bool blk = g.nz > 1;
+  const size_t plane = blk ? (size_t)g.XB * kSxB * g.ny : (size_t)g.Xp * g.ny;
+  const size_t cstride = (size_t)g.nz * plane;
+  const Cx<T>* src0 = hp.Sx + (size_t)b * g.sx + (size_t)z * plane + (blk ? kSxB * y0 : y0);
+  const int lq = lty + 2;  // kSxB = 4
+  const int tot = DEMAG ? (blk ? g.XB << lq : g.Xp << lty) : 0;
+  // entry t of a component's tile: row r, kx k; returns its offset from src0
+  auto tile_ent = [&](int t, int& r, int& k) -> uint32_t {
+    if (blk) {
+      const int kb = t >> lq, q = t & ((1 << lq) - 1);
+      r = q >> 2;
+      k = kb * kSxB + (q & 3);
+      return (uint32_t)(kb * kSxB * g.ny + q);
+    }
+    r = t & (TY - 1);
+    k = t >> lty;
+    return (uint32_t)(k * g.ny + r);
+  };
+  constexpr int U = 4;
+  auto load_batch = [&](int t0, Cx<T> (&v)[U][3]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * blockDim.x;
+      int r, k;
+      const uint32_t off = tile_ent(t, r, k) * (uint32_t)sizeof(Cx<T>);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v[u][c] = {T(0), T(0)};
+        if (t < tot && r < nrow && k < g.Xp) v[u][c] = gldo(src0 + c * cstride, off);
+      }
+    }
+  };
+  auto store_batch = [&](int t0, const Cx<T> (&v)[U][3]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * blockDim.x;
+      int r, k;
+      (void)tile_ent(t, r, k);
+      if (t < tot && k < g.Xp) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lds[(c * TY + r) * cs + pidx(k, sh)] = v[u][c];
+      }
+    }
+  };
+  Cx<T> v0[U][3];
+  if constexpr (DEMAG) load_batch((int)threadIdx.x, v0);
+
+  DevCtl* const ctl = ldu(&L.epis[gi].ctl);
+  if (ctl && ldu(&ctl[b].done)) return;
+  const bool add_hd = DEMAG && (ldu(&hp.prm[b].terms) & MM_DEMAG);
   const int ncell = nrow * g.nx;
   const long long N = g.N;
   const FDiv dnx = fdiv_of(g.nx);
@@ -1166,54 +1221,11 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   if (DEMAG) {
     TableCopy<T, 4> tab;
     tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
-    // column c * TY + r holds component c of row y0 + r (rows past the mesh
-    // are left out: only the epilogue's rows are read back)
-    const int ncol = 3 * TY;
-    const size_t plane = g.nz > 1 ? (size_t)g.XB * kSxB * g.ny : (size_t)g.Xp * g.ny;
-    const size_t cstride = (size_t)g.nz * plane;
-    // 3-D groups: Sx [3][nz][XB][ny][kSxB], the tile of a component is XB
-    // runs of kSxB TY entries; 2-D groups: Sx [3][Xp][ny], TY entries of each
-    // kx column
-    const bool blk = g.nz > 1;
-    const Cx<T>* src0 = hp.Sx + (size_t)b * g.sx + (size_t)z * plane + (blk ? kSxB * y0 : y0);
-    const int lq = lty + 2;  // kSxB = 4
-    const int tot = blk ? g.XB << lq : g.Xp << lty;
-    // entry t of a component's tile: row r, kx k; returns its offset from src0
-    auto tile = [&](int t, int& r, int& k) -> uint32_t {
-      if (blk) {
-        const int kb = t >> lq, q = t & ((1 << lq) - 1);
-        r = q >> 2;
-        k = kb * kSxB + (q & 3);
-        return (uint32_t)(kb * kSxB * g.ny + q);
-      }
-      r = t & (TY - 1);
-      k = t >> lty;
-      return (uint32_t)(k * g.ny + r);
-    };
-    constexpr int U = 4;
-    for (int t0 = threadIdx.x; t0 < tot; t0 += U * blockDim.x) {
+    store_batch((int)threadIdx.x, v0);
+    for (int t0 = threadIdx.x + U * blockDim.x; t0 < tot; t0 += U * blockDim.x) {
       Cx<T> v[U][3];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int t = t0 + u * blockDim.x;
-        int r, k;
-        const uint32_t off = tile(t, r, k) * (uint32_t)sizeof(Cx<T>);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          v[u][c] = {T(0), T(0)};
-          if (t < tot && r < nrow && k < g.Xp) v[u][c] = gldo(src0 + c * cstride, off);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int t = t0 + u * blockDim.x;
-        int r, k;
-        (void)tile(t, r, k);
-        if (t < tot && k < g.Xp) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) lds[(c * TY + r) * cs + pidx(k, sh)] = v[u][c];
-        }
-      }
+      load_batch(t0, v);
+      store_batch(t0, v);
     }
     tab.store(twl);
     __syncthreads();
