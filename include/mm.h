@@ -193,6 +193,19 @@ mm_status mm_batch_destroy(mm_batch* batch);
 mm_status mm_plan_autotune(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
                            void* work, int32_t reps, int32_t* shape_out, void* hip_stream);
 
+/* The plan's current launch shapes (8 ints, the layout above).  Host only. */
+mm_status mm_plan_shapes(const mm_plan* plan, int32_t* shape_out);
+
+/* Set the launch shapes (8 ints as above; the last is ignored), e.g. ones an
+ * earlier autotune reported for this mesh, precision and device.  Every shape
+ * is checked against the plan (LDS per workgroup, threads per transform and
+ * per workgroup, rows per workgroup a power of two no larger than ny, y
+ * columns whole kx blocks or a divisor of one in 3-D); MM_E_ARG and nothing
+ * changed otherwise.  Results do not depend on the shapes beyond FP rounding.
+ * Host only (may reallocate the plan's scratch; not while its work is in
+ * flight). */
+mm_status mm_plan_set_shapes(mm_plan* plan, const int32_t* shape);
+
 /* Measurement aid: after one dm/dt evaluation of `batch` instances (output
  * written to `work`, same layout as m), launches each kernel pass `reps`
  * times back to back between two HIP events on hip_stream and returns in

@@ -1449,6 +1449,14 @@ mm_status mm_profile_passes(mm_plan* p, const mm_params* q, int32_t batch, const
   return st;
 }
 
+// Launch shapes in the layout mm_plan_autotune reports.
+static void shapes_of(const mm_plan* p, int32_t* out) {
+  const Tuning& t = p->e.groups[0].tu;
+  const bool d2 = p->e.groups[0].g.nz == 1;
+  const int v[8] = {t.ty_f, t.nt_f, d2 ? t.cb_y2 : t.cb_y, d2 ? t.tpc_y2 : t.tpc_y, t.nt_y, t.ty_x, t.nt_i, 0};
+  for (int i = 0; i < 8; ++i) out[i] = v[i];
+}
+
 mm_status mm_plan_autotune(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work, int32_t reps,
                            int32_t* shape_out, void* hip_stream) {
   MMCHK(plan_checks(p, q, batch));
@@ -1457,11 +1465,40 @@ mm_status mm_plan_autotune(mm_plan* p, const mm_params* q, int32_t batch, const 
   hipStream_t s = (hipStream_t)hip_stream;
   MMCHK(p->e.prec == MM_F32 ? autotune_impl<float>(p, q, batch, m, work, reps, s)
                             : autotune_impl<double>(p, q, batch, m, work, reps, s));
-  if (shape_out) {
-    const Tuning& t = p->e.groups[0].tu;
-    const int v[8] = {t.ty_f, t.nt_f, p->e.groups[0].g.nz == 1 ? t.cb_y2 : t.cb_y,
-                      p->e.groups[0].g.nz == 1 ? t.tpc_y2 : t.tpc_y, t.nt_y, t.ty_x, t.nt_i, 0};
-    for (int i = 0; i < 8; ++i) shape_out[i] = v[i];
+  if (shape_out) shapes_of(p, shape_out);
+  return MM_OK;
+}
+
+mm_status mm_plan_shapes(const mm_plan* p, int32_t* shape_out) {
+  if (!p || !shape_out) return fail(MM_E_ARG, "null pointer");
+  shapes_of(p, shape_out);
+  return MM_OK;
+}
+
+mm_status mm_plan_set_shapes(mm_plan* p, const int32_t* shape) {
+  if (!p || !shape) return fail(MM_E_ARG, "null pointer");
+  Group& G = p->e.groups[0];
+  Tuning t = G.tu;
+  t.ty_f = shape[0];
+  t.nt_f = shape[1];
+  t.tpc_f = t.ty_f > 0 ? t.nt_f / t.ty_f : 0;
+  if (G.g.nz == 1) {
+    t.cb_y2 = shape[2];
+    t.tpc_y2 = shape[3];
+  } else {
+    t.cb_y = shape[2];
+    t.tpc_y = shape[3];
+  }
+  t.nt_y = shape[4];
+  t.ty_x = shape[5];
+  t.nt_i = shape[6];
+  t.tpc_x = t.ty_x > 0 ? t.nt_i / (3 * t.ty_x) : 0;
+  if (!tuning_ok(G, t, p->e.prec, p->e.csz)) return fail(MM_E_ARG, "launch shapes not valid for this plan");
+  G.tu = t;
+  MMCHK(engine_reserve(p->e, std::vector<int>{p->maxb}));
+  if (p->e.gexec) {
+    (void)hipGraphExecDestroy(p->e.gexec);
+    p->e.gexec = nullptr;
   }
   return MM_OK;
 }

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libmmx.so")
 MM_OK, MM_E_ARG, MM_E_NOMEM, MM_E_HIP = 0, -1, -2, -3
 MM_E_NONFINITE, MM_E_STEP_UNDERFLOW, MM_E_MAXSTEPS, MM_E_STATE = -4, -5, -6, -7
 MM_F32, MM_F64 = 0, 1
+# launch shapes: x-forward rows and threads, y columns, threads per column and threads, x-inverse rows and threads
+SHAPE_KEYS = ("ty_f", "nt_f", "cb_y", "tpc_y", "nt_y", "ty_x", "nt_i")
 EXCHANGE, DEMAG, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
 ALL_TERMS = 31
 
@@ -65,6 +67,8 @@ _sigs = {
     "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
     "mm_profile_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _i32, _P(_dbl), _P(_i32), _P(_i32), _vp],
     "mm_plan_autotune": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
+    "mm_plan_shapes": [_vp, _P(_i32)],
+    "mm_plan_set_shapes": [_vp, _P(_i32)],
     "mm_batch_create": [_P(_vp), _P(Mesh), _i32, ctypes.c_int, ctypes.c_uint32, _vp],
     "mm_batch_run": [_vp, _P(Instance), _i32, _i64, _vp],
     "mm_batch_destroy": [_vp],
@@ -220,8 +224,20 @@ class Plan:
         shape = (ctypes.c_int32 * 8)()
         _check(_lib.mm_plan_autotune(self._h, _params_array(params), self._batch(m), _ptr(m), _ptr(work), reps,
                                      shape, _stream(stream)), "mm_plan_autotune")
-        keys = ("ty_f", "nt_f", "cb_y", "tpc_y", "nt_y", "ty_x", "nt_i")
-        return dict(zip(keys, shape[:7]))
+        return dict(zip(SHAPE_KEYS, shape[:7]))
+
+    def shapes(self):
+        """The plan's current launch shapes (as autotune reports them)."""
+        shape = (ctypes.c_int32 * 8)()
+        _check(_lib.mm_plan_shapes(self._h, shape), "mm_plan_shapes")
+        return dict(zip(SHAPE_KEYS, shape[:7]))
+
+    def set_shapes(self, shapes):
+        """Set the launch shapes (a dict as shapes() returns; unnamed keys keep their value)."""
+        cur = self.shapes()
+        cur.update(shapes)
+        shape = (ctypes.c_int32 * 8)(*[int(cur[k]) for k in SHAPE_KEYS], 0)
+        _check(_lib.mm_plan_set_shapes(self._h, shape), "mm_plan_set_shapes")
 
     def profile_passes(self, params, m, reps=20, stream=None):
         """Mean duration (us) of each kernel pass of one dm/dt evaluation."""

@@ -349,6 +349,39 @@ def test_autotune_keeps_results(mm):
     assert field_err(after, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("mesh", [(64, 128, 2, 2e-9, 2e-9, 2e-9),     # Py = 256 = 2 ny: fixed-length y kernels
+                                  (96, 70, 3, 2e-9, 2e-9, 2e-9),      # Py = 144: general ones
+                                  (32, 256, 1, 2e-9, 2e-9, 2e-9)])    # 2-D fused y pass, Py = 512
+def test_every_launch_shape_kind(mm, mesh):
+    """Launch shapes set by hand cover each code path the autotuner can pick
+    (y tiles staged through LDS or read with stride, 8 or 16 transform entries
+    per thread, one or several cells per thread): dm/dt against the oracle."""
+    m = representable(_rand_m(mesh, 72), torch.float32)
+    plan = mm.Plan(mesh, "f32", terms=mm.ALL_TERMS)
+    gp = gpu_params(mm, PAR, mm.ALL_TERMS)
+    md = to_dev(m, torch.float32)
+    ref = F.llg_rhs(m, F.Mesh(*mesh), oracle_params(PAR, F.ALL_TERMS), _kernel(mesh))
+    base = plan.shapes()
+    tpc_y = base["tpc_y"]
+    cbs = [1, 2, 3] if mesh[2] == 1 else [1, 2, 4, 8]
+    tried = 0
+    for cb in cbs:
+        for ty_x, nt_i in ((1, 128), (2, 256), (4, 512), (1, 512)):
+            for ty_f, nt_f in ((1, 64), (4, 256)):
+                ncols = 3 * cb if mesh[2] == 1 else cb
+                shape = dict(cb_y=cb, tpc_y=tpc_y, nt_y=ncols * tpc_y, ty_x=ty_x, nt_i=nt_i, ty_f=ty_f, nt_f=nt_f)
+                try:
+                    plan.set_shapes(shape)
+                except mm.MMError:
+                    continue
+                tried += 1
+                got = plan.llg_rhs(gp, md).cpu().numpy()
+                assert field_err(got, ref) <= 1e-5, shape
+    assert tried >= 8, tried
+    with pytest.raises(mm.MMError):
+        plan.set_shapes(dict(ty_x=3))  # rows per workgroup must be a power of two
+
+
 @pytest.mark.gpu
 def test_profile_step_leaves_state(mm):
     """The attempt-kernel timing advances neither m nor the state, and a run
