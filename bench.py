@@ -272,7 +272,7 @@ def load_traffic(workload, kernel):
 # (the y passes: kernels compiled for one length, k_*_s, or the general ones)
 PASS_KERNELS = {"x_fwd": ("k_fwd_x<",), "y_fused_product": ("k_ypass_s<", "k_ypass<"),
                 "y_fwd": ("k_ypass_s<", "k_ypass<"),
-                "z_product": ("k_z3d_reg_half<", "k_z3d_reg<", "k_z3d_pair<", "k_z3d<"),
+                "z_product": ("k_z3d_reg_half<", "k_z3d_reg<", "k_z3d_s<", "k_z3d_pair<", "k_z3d<"),
                 "y_inv": ("k_yinv_s<", "k_yinv<"), "x_inv_fused_llg": ("k_inv_x<",)}
 COPY_BYTES = 1 << 30
 

@@ -448,7 +448,7 @@ template <typename T, int L, bool A16, bool INV, bool GIN, bool GOUT, bool TWL, 
           class Load, class Store, class Hook>
 __device__ __forceinline__ void fft_static(Cx<T>* lds, const Cx<T>* tw, int cs, int ncol, Load ld, Store st,
                                            Hook hook) {
-  static_assert((L & (L - 1)) == 0 && L >= 64, "power-of-two lengths of 64 and more");
+  static_assert((L & (L - 1)) == 0 && L >= 16, "power-of-two lengths of 16 and more");
   constexpr int TPC = L / EPT;
   const int c = (int)threadIdx.x / TPC;
   const int lane = (int)threadIdx.x & (TPC - 1);

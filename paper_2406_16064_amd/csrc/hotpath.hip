@@ -268,14 +268,40 @@ void z_reg_dispatch(int Pz, const Launch<T>& L, long long total, bool half, hipS
   }
 }
 
-// z pass of a group: 0 lane pairs, 1 one lane per column, 2 LDS.  Measured on
-// the 512x512x16 slab: one lane per column is fastest where it fits (FP32);
-// FP64 columns of 32 points go to lane pairs.
+// z pass of a group: 0 lane pairs, 1 one lane per column (registers), 2 LDS
+// (any Pz), 3 LDS with the transform compiled for Pz (nz = Pz/2, Pz in
+// {16, 32, 64}; the instance's y buffer within 32-bit offsets).  One lane per
+// column is fastest where it fits (FP32 up to 32 points); FP64 takes the
+// compiled LDS kernel (a 32-point FP64 column does not fit one lane).
 template <typename T>
-int z_kind(int Pz) {
+int z_kind(const Geo& g) {
+  const int Pz = g.Pz;
+  const bool half = 2 * g.nz == Pz;
+  const bool fits = (double)g.sy * sizeof(Cx<T>) < 4294967296.0;
+  if (half && fits && (Pz == 16 || Pz == 32 || Pz == 64) && (sizeof(T) == 8 || Pz == 64)) return 3;
   if (z_reg_supported<T>(Pz)) return 1;
   if (z_pair_supported(Pz)) return 0;
   return 2;
+}
+
+// (kx,ky) columns per workgroup and transform entries per thread of k_z3d_s:
+// 3 Q Pz/E threads (at most 384) and 3 Q col_stride(Pz) entries of LDS
+// (at most 57 KB)
+template <typename T> constexpr int zs_q(int Pz) {
+  return Pz == 16 ? (sizeof(T) == 8 ? 32 : 64) : Pz == 32 ? 32 : (sizeof(T) == 8 ? 16 : 32);
+}
+constexpr int zs_e(int Pz) { return Pz == 64 ? 16 : 8; }
+
+template <typename T>
+void zs_dispatch(int Pz, const Launch<T>& L, long long total, hipStream_t s) {
+  const dim3 grid((unsigned)total);
+  const size_t lds = (size_t)3 * zs_q<T>(Pz) * col_stride(Pz) * sizeof(Cx<T>);
+  const int nt = 3 * zs_q<T>(Pz) * (Pz / zs_e(Pz));
+  switch (Pz) {
+    case 16: k_z3d_s<T, 16, zs_q<T>(16), zs_e(16)><<<grid, nt, lds, s>>>(L); break;
+    case 32: k_z3d_s<T, 32, zs_q<T>(32), zs_e(32)><<<grid, nt, lds, s>>>(L); break;
+    default: k_z3d_s<T, 64, zs_q<T>(64), zs_e(64)><<<grid, nt, lds, s>>>(L); break;
+  }
 }
 
 }  // namespace
@@ -395,10 +421,10 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
       // one launch per (Pz, nz == Pz/2) among the groups
       for (int i = 0; i < gs.n && on(2); ++i) {
         const HotPlan<T>& hi = gs.h[i];
-        const int kind = z_kind<T>(hi.g.Pz);
+        const int kind = z_kind<T>(hi.g);
         if (hi.g.nz == 1 || kind == 2) continue;
         const bool half = 2 * hi.g.nz == hi.g.Pz;
-        const int key = 2 * hi.g.Pz + (half ? 1 : 0);
+        const int key = (2 * hi.g.Pz + (half ? 1 : 0)) * 4 + kind;
         bool seen = false;
         for (int k = 0; k < ndone; ++k) seen = seen || done_pz[k] == key;
         if (seen) continue;
@@ -406,10 +432,14 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         LaunchBuilder<T> lb(gs, epis);
         for (int j = 0; j < gs.n; ++j) {
           const HotPlan<T>& h = gs.h[j];
-          const bool use = h.g.nz > 1 && 2 * h.g.Pz + (2 * h.g.nz == h.g.Pz ? 1 : 0) == key;
-          lb.set(j, use ? (kind == 0 ? zpair_blocks(h.g, h.batch) : zreg_blocks(h.g, h.batch)) : 0);
+          const bool use = h.g.nz > 1 && (2 * h.g.Pz + (2 * h.g.nz == h.g.Pz ? 1 : 0)) * 4 + z_kind<T>(h.g) == key;
+          const long long nb = kind == 0 ? zpair_blocks(h.g, h.batch)
+                               : kind == 3 ? zs_blocks(h.g, h.batch, zs_q<T>(h.g.Pz))
+                                           : zreg_blocks(h.g, h.batch);
+          lb.set(j, use ? nb : 0);
         }
         if (kind == 0) z_pair_dispatch<T>(hi.g.Pz, lb.L, lb.total, s);
+        else if (kind == 3) zs_dispatch<T>(hi.g.Pz, lb.L, lb.total, s);
         else z_reg_dispatch<T>(hi.g.Pz, lb.L, lb.total, half, s);
       }
       LaunchBuilder<T> lz(gs, epis);
@@ -417,7 +447,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
       size_t lds = 0;
       for (int j = 0; j < gs.n; ++j) {
         const HotPlan<T>& h = gs.h[j];
-        const bool use = h.g.nz > 1 && z_kind<T>(h.g.Pz) == 2;
+        const bool use = h.g.nz > 1 && z_kind<T>(h.g) == 2;
         lz.set(j, use ? zlds_blocks(h.g, h.tu, h.batch) : 0);
         if (use) {
           nt = std::max(nt, 3 * h.tu.qz * h.tu.tpc_z);

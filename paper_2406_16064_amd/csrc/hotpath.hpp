@@ -640,6 +640,86 @@ __global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
 }
 
 // ---------------------------------------------------------------------------
+// 3-D z pass with nz = PZ/2 and PZ a power of two, through LDS with a
+// transform compiled for PZ: Q consecutive (kx,ky) points of one instance,
+// the 3 components' nz planes loaded as Q-long contiguous runs, forward z
+// (upper half zero, not read), tensor product, inverse z (only the nz
+// physical planes formed), stored the same way.  For FP64, whose 32-point
+// columns do not fit one lane's registers.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline long long zs_blocks(const Geo& g, int batch, int Q) {
+  return (long long)batch * (((long long)g.Xp * g.Py + Q - 1) / Q);
+}
+
+template <typename T, int PZ, int Q, int EPT>
+__global__ void __launch_bounds__(512) k_z3d_s(Launch<T> L) {
+  constexpr int NZ = PZ / 2;
+  constexpr int LQ = ilog2c(Q), LNZ = ilog2c(NZ);
+  static_assert((1 << LQ) == Q && (1 << LNZ) == NZ, "powers of two");
+  constexpr int SH = p2_psh(PZ, false);
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  long long bid0;
+  const int gi = group_of(L, bid0);
+  const HotPlan<T> hp = ldu(L.hps + gi);
+  const Geo& g = hp.g;
+  if (bid0 >= zs_blocks(g, hp.batch, Q)) return;
+  const int nq = g.Xp * g.Py;
+  const unsigned tiles = (unsigned)((nq + Q - 1) / Q);
+  const unsigned bid = (unsigned)bid0;
+  const int tile = (int)(bid % tiles);
+  const int b = (int)(bid / tiles);
+  DevCtl* const ctl = ldu(&L.epis[gi].ctl);
+  if (ctl && ldu(&ctl[b].done)) return;
+  const int q0 = tile * Q;
+  const int nqt = nq - q0 < Q ? nq - q0 : Q;
+  const int cs = col_stride(PZ);
+  // Sy [3][nz][Xp Py] of the instance, from point q0 on: entry (c, z, j) at
+  // (c nz + z) nq + j
+  const Cx<T>* src = hp.Sy + (size_t)b * g.sy + q0;
+  Cx<T>* dst = hp.Sy + (size_t)b * g.sy + q0;
+  constexpr int NE = 3 * NZ * Q;
+  constexpr int U = 4;
+  for (int t0 = threadIdx.x; t0 < NE; t0 += U * blockDim.x) {  // column (c, j) = c Q + j, entry z
+    Cx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * blockDim.x, j = t & (Q - 1), cz = t >> LQ;
+      v[u] = Cx<T>{T(0), T(0)};
+      if (t < NE && j < nqt) v[u] = gldo(src, (uint32_t)(cz * nq + j) * (uint32_t)sizeof(Cx<T>));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * blockDim.x, j = t & (Q - 1), cz = t >> LQ;
+      if (t < NE) lds[((cz >> LNZ) * Q + j) * cs + pidx(cz & (NZ - 1), SH)] = v[u];
+    }
+  }
+  __syncthreads();
+  const NoLoad<T> nl;
+  const NoStore<T> nst;
+  const NoHook nh;
+  fft_static<T, PZ, false, false, false, false, false, true, false, EPT>(lds, hp.fd[2].tw, cs, 3 * Q, nl, nst, nh);
+  const T s = T(ldu(&hp.prm[b].demag_scale));
+  const FDiv dpy = fdiv_of(g.Py);
+  for (int t = threadIdx.x; t < Q * PZ; t += blockDim.x) {
+    const int j = t & (Q - 1), kz = t >> LQ;
+    if (j >= nqt) continue;
+    const int q = q0 + j;
+    const int kx = fdiv_q(q, dpy), ky = q - mul24(kx, g.Py);
+    const int o = pidx(kz, SH);
+    tensor_apply(hp, kx, ky, kz, s, lds[(0 * Q + j) * cs + o], lds[(1 * Q + j) * cs + o], lds[(2 * Q + j) * cs + o]);
+  }
+  __syncthreads();
+  fft_static<T, PZ, false, true, false, false, false, false, true, EPT>(lds, hp.fd[2].tw, cs, 3 * Q, nl, nst, nh);
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    const int j = t & (Q - 1), cz = t >> LQ;
+    if (j < nqt)
+      gsto(dst, (uint32_t)(cz * nq + j) * (uint32_t)sizeof(Cx<T>),
+           lds[((cz >> LNZ) * Q + j) * cs + pidx(cz & (NZ - 1), SH)]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 3-D z pass with the transform in registers: one thread owns the Pz-point
 // columns of the 3 components at one (kx, ky); no LDS, no barriers.
 // ---------------------------------------------------------------------------

@@ -47,6 +47,8 @@ MESHES = [
     (64, 128, 2, 2e-9, 2e-9, 2e-9),    # Py = 256 = 2 ny: y passes compiled for that length
     (16, 512, 2, 2e-9, 2e-9, 2e-9),    # Py = 1024 (radix-16 plan), 3-D
     (32, 256, 1, 2e-9, 2e-9, 2e-9),    # Py = 512, 2-D fused y pass
+    (16, 12, 8, 2e-9, 2e-9, 2e-9),     # Pz = 16 = 2 nz: FP64 z pass through LDS compiled for Pz
+    (8, 8, 32, 2e-9, 2e-9, 1e-9),      # Pz = 64 = 2 nz: the same in FP32 and FP64
 ]
 
 _kern_cache = {}
