@@ -413,9 +413,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--only", choices=["slab3d", "copy"], default=None,
-                    help="profiling aids: slab3d runs only the 512x512x16 slab (FP32) and prints its "
-                         "record; copy runs only the plain 1 GiB copies the HBM counters are scaled by")
+    ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "copy"], default=None,
+                    help="profiling aids: slab3d (slab3d_f64) runs only the 512x512x16 slab in FP32 (FP64) "
+                         "and prints its record; copy runs only the plain 1 GiB copies the HBM counters "
+                         "are scaled by")
     ap.add_argument("--ingest-counters", nargs=5, default=None,
                     metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="turn rocprofv3 FETCH_SIZE/WRITE_SIZE counter files into per-launch HBM bytes "
@@ -438,8 +439,9 @@ def main():
     if args.only == "copy":
         print(json.dumps(copy_reference(torch)))
         return
-    if args.only == "slab3d":
-        r3, *_ = run_workload(mm, inputs, torch, 2, "f32", args.steps, args.warmup)
+    if args.only in ("slab3d", "slab3d_f64"):
+        r3, *_ = run_workload(mm, inputs, torch, 2, "f64" if args.only == "slab3d_f64" else "f32", args.steps,
+                              args.warmup)
         print(json.dumps(r3))
         return
     print("bench: thin film fp32", file=sys.stderr, flush=True)

@@ -286,9 +286,10 @@ int z_kind(const Geo& g) {
 
 // (kx,ky) columns per workgroup and transform entries per thread of k_z3d_s:
 // 3 Q Pz/E threads (at most 384) and 3 Q col_stride(Pz) entries of LDS
-// (at most 57 KB)
+// (at most 57 KB; 28 KB for the FP64 32-point columns, whose workgroups are
+// latency-bound and gain from more of them per CU)
 template <typename T> constexpr int zs_q(int Pz) {
-  return Pz == 16 ? (sizeof(T) == 8 ? 32 : 64) : Pz == 32 ? 32 : (sizeof(T) == 8 ? 16 : 32);
+  return Pz == 16 ? (sizeof(T) == 8 ? 32 : 64) : Pz == 32 ? 16 : (sizeof(T) == 8 ? 16 : 32);
 }
 constexpr int zs_e(int Pz) { return Pz == 64 ? 16 : 8; }
 

@@ -240,9 +240,14 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
 // ---------------------------------------------------------------------------
 // Tensor product at one spectral point: H_a = s * sum_b K_ab M_b (K real).
 // ---------------------------------------------------------------------------
+// The six (or four, nz = 1) entries at one point, scaled by s, with the
+// parity signs of the folded spectrum applied.
 template <typename T>
-__device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int ky, int kz, T s,
-                                             Cx<T>& m0, Cx<T>& m1, Cx<T>& m2) {
+struct Ten {
+  T xx, yy, zz, xy, xz, yz;
+};
+template <typename T>
+__device__ __forceinline__ Ten<T> tensor_load(const HotPlan<T>& hp, int kx, int ky, int kz, T s) {
   const Geo& g = hp.g;
   const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
   const int kzf = kz <= g.Pz - kz ? kz : g.Pz - kz;
@@ -250,19 +255,30 @@ __device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int k
   const T sz = kz > g.Pz - kz ? T(-1) : T(1);
   const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
   const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
-  const T kxx = gld(hp.kt + off) * s;
-  const T kyy = gld(hp.kt + cstride + off) * s;
-  const T kzz = gld(hp.kt + 2 * cstride + off) * s;
-  const T kxy = gld(hp.kt + 3 * cstride + off) * (s * sy);
-  T kxz = T(0), kyz = T(0);
+  Ten<T> t;
+  t.xx = gld(hp.kt + off) * s;
+  t.yy = gld(hp.kt + cstride + off) * s;
+  t.zz = gld(hp.kt + 2 * cstride + off) * s;
+  t.xy = gld(hp.kt + 3 * cstride + off) * (s * sy);
+  t.xz = T(0);
+  t.yz = T(0);
   if (hp.ncomp == 6) {
-    kxz = gld(hp.kt + 4 * cstride + off) * (s * sz);
-    kyz = gld(hp.kt + 5 * cstride + off) * (s * sy * sz);
+    t.xz = gld(hp.kt + 4 * cstride + off) * (s * sz);
+    t.yz = gld(hp.kt + 5 * cstride + off) * (s * sy * sz);
   }
+  return t;
+}
+template <typename T>
+__device__ __forceinline__ void tensor_mul(const Ten<T>& t, Cx<T>& m0, Cx<T>& m1, Cx<T>& m2) {
   const Cx<T> a = m0, b = m1, c = m2;
-  m0 = {kxx * a.x + kxy * b.x + kxz * c.x, kxx * a.y + kxy * b.y + kxz * c.y};
-  m1 = {kxy * a.x + kyy * b.x + kyz * c.x, kxy * a.y + kyy * b.y + kyz * c.y};
-  m2 = {kxz * a.x + kyz * b.x + kzz * c.x, kxz * a.y + kyz * b.y + kzz * c.y};
+  m0 = {t.xx * a.x + t.xy * b.x + t.xz * c.x, t.xx * a.y + t.xy * b.y + t.xz * c.y};
+  m1 = {t.xy * a.x + t.yy * b.x + t.yz * c.x, t.xy * a.y + t.yy * b.y + t.yz * c.y};
+  m2 = {t.xz * a.x + t.yz * b.x + t.zz * c.x, t.xz * a.y + t.yz * b.y + t.zz * c.y};
+}
+template <typename T>
+__device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int ky, int kz, T s,
+                                             Cx<T>& m0, Cx<T>& m1, Cx<T>& m2) {
+  tensor_mul(tensor_load(hp, kx, ky, kz, s), m0, m1, m2);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,20 +710,31 @@ __global__ void __launch_bounds__(512) k_z3d_s(Launch<T> L) {
       if (t < NE) lds[((cz >> LNZ) * Q + j) * cs + pidx(cz & (NZ - 1), SH)] = v[u];
     }
   }
+  // this thread's tensor points (t = threadIdx.x + i NTH, the kernel runs NTH
+  // threads), loaded before the transform so that their latency overlaps it
+  constexpr int NTH = 3 * Q * (PZ / EPT);
+  constexpr int IT = (Q * PZ + NTH - 1) / NTH;
+  const T s = T(ldu(&hp.prm[b].demag_scale));
+  const FDiv dpy = fdiv_of(g.Py);
+  Ten<T> ten[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NTH, j = t & (Q - 1), kz = t >> LQ;
+    const int q = q0 + (j < nqt ? j : 0);
+    const int kx = fdiv_q(q, dpy), ky = q - mul24(kx, g.Py);
+    if (t < Q * PZ) ten[i] = tensor_load(hp, kx, ky, kz < PZ ? kz : 0, s);
+  }
   __syncthreads();
   const NoLoad<T> nl;
   const NoStore<T> nst;
   const NoHook nh;
   fft_static<T, PZ, false, false, false, false, false, true, false, EPT>(lds, hp.fd[2].tw, cs, 3 * Q, nl, nst, nh);
-  const T s = T(ldu(&hp.prm[b].demag_scale));
-  const FDiv dpy = fdiv_of(g.Py);
-  for (int t = threadIdx.x; t < Q * PZ; t += blockDim.x) {
-    const int j = t & (Q - 1), kz = t >> LQ;
-    if (j >= nqt) continue;
-    const int q = q0 + j;
-    const int kx = fdiv_q(q, dpy), ky = q - mul24(kx, g.Py);
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NTH, j = t & (Q - 1), kz = t >> LQ;
+    if (t >= Q * PZ || j >= nqt) continue;
     const int o = pidx(kz, SH);
-    tensor_apply(hp, kx, ky, kz, s, lds[(0 * Q + j) * cs + o], lds[(1 * Q + j) * cs + o], lds[(2 * Q + j) * cs + o]);
+    tensor_mul(ten[i], lds[(0 * Q + j) * cs + o], lds[(1 * Q + j) * cs + o], lds[(2 * Q + j) * cs + o]);
   }
   __syncthreads();
   fft_static<T, PZ, false, true, false, false, false, false, true, EPT>(lds, hp.fd[2].tw, cs, 3 * Q, nl, nst, nh);
