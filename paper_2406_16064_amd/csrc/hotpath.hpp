@@ -418,13 +418,13 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
 }
 
 // 3-D groups keep Sx in kx blocks, [3][nz][XB][ny][kSxB].  A y tile is cb_y
-// consecutive kx of one (component, z) plane.  cb_y a multiple of kSxB: whole
-// blocks, staged through LDS on the Sx side (the forward pass copies the
-// contiguous blocks into the LDS columns and transforms from there; the
-// inverse transforms into LDS and copies the first ny entries of each column
-// back the same way).  cb_y below kSxB (one or two columns of one block, for
-// more workgroups per CU): the transform reads and writes the column straight
-// from the block, entries kSxB apart.  Sy [3][nz][Xp][Py] is read and written
+// consecutive kx of one (component, z) plane.  cb_y up to kSxB (columns of
+// one block): the transform reads and writes its column straight from the
+// block, entries kSxB apart.  cb_y a larger multiple of kSxB: whole blocks,
+// staged through LDS on the Sx side (the forward pass copies the contiguous
+// blocks into the LDS columns and transforms from there; the inverse
+// transforms into LDS and copies the first ny entries of each column back the
+// same way).  Sy [3][nz][Xp][Py] is read and written
 // row by row by the transform itself.
 template <typename T, bool INV, bool R16, int SL = 0, int EPT = 16>
 __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid0, Cx<T>* lds) {
@@ -448,7 +448,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
   const int c = (int)threadIdx.x / tpc;
   const int cc = c < ncol ? c : 0;
   const bool half = g.Py == 2 * ny;
-  if (CB < kSxB) {
+  if (CB <= kSxB) {
     Cx<T>* const sxp = hp.Sx + (size_t)b * g.sx + (size_t)cz * g.XB * kSxB * ny;  // plane
     const int kxc = kx0 + cc;
     const uint32_t coff = (uint32_t)((kxc >> 2) * kSxB * ny + (kxc & 3)) * (uint32_t)sizeof(Cx<T>);
