@@ -256,6 +256,8 @@ struct Engine {
   void* dhot = nullptr;  // device HotPlan<T>[kMaxGroups]
   void* depi = nullptr;  // device Epi<T>[kEpiSlots][kMaxGroups]
   DevCtl* hctl = nullptr;
+  DevCtl* hctl2 = nullptr;      // second host copy of the controllers (graph launches overlap host polls)
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   double* he5 = nullptr;
   bool any_demag = false;
   // graph cache of the Dormand-Prince attempt sequence
@@ -490,6 +492,9 @@ void free_engine(Engine& E) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (E.hctl) (void)hipHostFree(E.hctl);
+  if (E.hctl2) (void)hipHostFree(E.hctl2);
+  for (hipEvent_t& ev : E.poll_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (E.he5) (void)hipHostFree(E.he5);
   if (E.cap) (void)hipStreamDestroy(E.cap);
 }
@@ -563,12 +568,14 @@ mm_status engine_reserve(Engine& E, const std::vector<int>& per_group) {
     if (E.ctl) (void)hipFree(E.ctl);
     if (E.e5) (void)hipFree(E.e5);
     if (E.hctl) (void)hipHostFree(E.hctl);
+    if (E.hctl2) (void)hipHostFree(E.hctl2);
     if (E.he5) (void)hipHostFree(E.he5);
-    E.prm = nullptr; E.ctl = nullptr; E.e5 = nullptr; E.hctl = nullptr; E.he5 = nullptr;
+    E.prm = nullptr; E.ctl = nullptr; E.e5 = nullptr; E.hctl = nullptr; E.hctl2 = nullptr; E.he5 = nullptr;
     MMCHK(dev_alloc((void**)&E.prm, sizeof(DevParams) * total));
     MMCHK(dev_alloc((void**)&E.ctl, sizeof(DevCtl) * total));
     MMCHK(dev_alloc((void**)&E.e5, sizeof(double) * 5 * total));
     HIPCHK(hipHostMalloc((void**)&E.hctl, sizeof(DevCtl) * total));
+    HIPCHK(hipHostMalloc((void**)&E.hctl2, sizeof(DevCtl) * total));
     HIPCHK(hipHostMalloc((void**)&E.he5, sizeof(double) * 5 * total));
     std::memset(E.hctl, 0, sizeof(DevCtl) * total);
     E.inst_cap = total;
@@ -968,14 +975,50 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
       if (ee != hipSuccess) { E.gexec = nullptr; return fail(MM_E_HIP, std::string("instantiate: ") + hipGetErrorString(ee)); }
       E.g_key = key;
     }
-    for (;;) {
+    // Up to two graph launches in flight, each followed by a copy of the
+    // controllers into its own host buffer: the host reads one while the next
+    // graph runs.  A further launch is queued only while some instance may
+    // still have attempts left after the ones in flight (bounded by its
+    // attempt limit as last seen), so a run bounded by max_steps launches no
+    // graph that has nothing to do; one that ends at t_end may queue one
+    // (every kernel of it returns at once for finished instances).
+    for (hipEvent_t& ev : E.poll_ev)
+      if (!ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    DevCtl* const hb[2] = {E.hctl, E.hctl2};
+    auto remaining = [&](const DevCtl* h, bool& all) {
+      long long r = 0;
+      all = true;
+      for (int b = 0; b < n_total; ++b) {
+        if (h[b].done) continue;
+        all = false;
+        r = std::max(r, h[b].max_attempt - h[b].n_attempt);
+      }
+      return r;
+    };
+    bool all = false;
+    long long rem = remaining(E.hctl, all);  // the state just uploaded
+    int head = 0, inflight = 0;
+    auto launch = [&]() -> mm_status {
+      const int slot = (head + inflight) & 1;
       HIPCHK(hipGraphLaunch(E.gexec, s));
-      HIPCHK(hipMemcpyAsync(E.hctl, E.ctl, sizeof(DevCtl) * n_total, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      bool all = true;
-      for (int b = 0; b < n_total; ++b) all = all && E.hctl[b].done;
-      if (all) break;
+      HIPCHK(hipMemcpyAsync(hb[slot], E.ctl, sizeof(DevCtl) * n_total, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(E.poll_ev[slot], s));
+      ++inflight;
+      return MM_OK;
+    };
+    if (!all) {
+      MMCHK(launch());
+      for (;;) {
+        if (inflight < 2 && rem > (long long)K * inflight) MMCHK(launch());
+        HIPCHK(hipEventSynchronize(E.poll_ev[head]));
+        rem = remaining(hb[head], all);
+        head ^= 1;
+        --inflight;
+        if (all) break;
+        if (inflight == 0) MMCHK(launch());
+      }
     }
+    HIPCHK(hipStreamSynchronize(s));
   }
   // finish: project the last accepted y5 and move k7 into k1
   HIPCHK(launch_begin<T>(gs, epi_slot<T>(E, 8), s));
