@@ -252,6 +252,20 @@ def roofline(res, workload):
                 dom["us_per_attempt"] / res["attempt_kernel_us"], 3)}
 
 
+def demag_pipeline(res):
+    """The demag FFT passes of one dm/dt evaluation (forward x, y, z, inverse
+    y; the inverse x pass also holds the local terms and the epilogue):
+    algorithmic bytes over the summed back-to-back pass times."""
+    names = ("x_fwd", "y_fwd", "z_product", "y_inv") if any(p["kernel"] == "z_product" for p in res["passes"]) \
+        else ("x_fwd", "y_fused_product")
+    ps = [p for p in res["passes"] if p["kernel"] in names]
+    b = sum(p["alg_bytes"] for p in ps)
+    us = sum(p["us"] for p in ps)
+    gbs = b / (us * 1e-6) / 1e9
+    return {"passes": list(names), "alg_bytes": b, "us": round(us, 3), "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def load_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
     or None when the summary is missing or the kernels changed since it was taken."""
@@ -442,6 +456,7 @@ def main():
     if args.only in ("slab3d", "slab3d_f64"):
         r3, *_ = run_workload(mm, inputs, torch, 2, "f64" if args.only == "slab3d_f64" else "f32", args.steps,
                               args.warmup)
+        r3["demag_pipeline"] = demag_pipeline(r3)
         print(json.dumps(r3))
         return
     print("bench: thin film fp32", file=sys.stderr, flush=True)
@@ -459,6 +474,8 @@ def main():
         extra["slab3d_fp32_over_fp64"] = (extra["slab3d_f32"]["cell_evals_per_s"] /
                                           extra["slab3d_f64"]["cell_evals_per_s"])
         extra["slab3d_f32"]["roofline"] = roofline(extra["slab3d_f32"], "slab3d_f32")
+        for prec in ("f32", "f64"):
+            extra["slab3d_" + prec]["demag_pipeline"] = demag_pipeline(extra["slab3d_" + prec])
         print("bench: sweep batched vs one by one", file=sys.stderr, flush=True)
         extra["sweep"] = sweep_bench(mm, inputs, torch)
         print("bench: neb", file=sys.stderr, flush=True)
