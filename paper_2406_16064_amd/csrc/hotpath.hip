@@ -28,7 +28,7 @@ template <typename T>
 __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   const Epi<T> ep = ldu(L.epis + gi);
   const Geo& g = hp.g;
   if (bid >= begin_blocks(g, hp.batch)) return;
@@ -182,6 +182,7 @@ struct LaunchBuilder {
     L.hps = gs.dh;
     L.epis = epis;
     L.ngroups = gs.n;
+    L.h0 = gs.h[0];
     for (int i = 0; i <= kMaxGroups; ++i) L.off[i] = 0;
   }
   // blocks of each group (0 = the group takes no part); padded to multiples of 8

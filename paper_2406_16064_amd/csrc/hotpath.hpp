@@ -115,6 +115,12 @@ struct SegTableCopy {
   }
 };
 
+// Plan of group gi of a launch (group 0 from the kernel arguments).
+template <typename T>
+__device__ __forceinline__ HotPlan<T> hot_plan(const Launch<T>& L, int gi) {
+  return gi == 0 ? L.h0 : ldu(L.hps + gi);
+}
+
 // Group of this workgroup and its index inside the group (XCD-ordered).
 template <typename T>
 __device__ __forceinline__ int group_of(const Launch<T>& L, long long& lb) {
@@ -162,7 +168,7 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid0;
   const int gi = group_of(L, bid0);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   const Geo& g = hp.g;
   if (bid0 >= fwd_blocks(g, hp.tu, hp.batch)) return;
   const int TY = hp.tu.ty_f;  // a power of two
@@ -530,7 +536,7 @@ __global__ void __launch_bounds__(512) k_ypass(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   if (hp.g.nz == 1) {
     if (bid >= y2d_blocks(hp.g, hp.tu, hp.batch)) return;
     y_fused2d<T, R16>(hp, ldu(L.epis + gi), bid, lds);
@@ -546,7 +552,7 @@ __global__ void __launch_bounds__(512) k_yinv(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
   y_rows3d<T, true, R16>(hp, ldu(L.epis + gi), bid, lds);
 }
@@ -559,7 +565,7 @@ __global__ void __launch_bounds__(512) k_ypass_s(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   if (hp.g.nz == 1) {
     if (bid >= y2d_blocks(hp.g, hp.tu, hp.batch)) return;
     y_fused2d<T, false, SL, EPT>(hp, ldu(L.epis + gi), bid, lds);
@@ -575,7 +581,7 @@ __global__ void __launch_bounds__(512) k_yinv_s(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   if (bid >= y3d_blocks(hp.g, hp.tu, hp.batch)) return;
   y_rows3d<T, true, false, SL, EPT>(hp, ldu(L.epis + gi), bid, lds);
 }
@@ -594,7 +600,7 @@ __global__ void __launch_bounds__(512) k_z3d(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   const Epi<T> ep = ldu(L.epis + gi);
   const Geo& g = hp.g;
   if (bid >= zlds_blocks(g, hp.tu, hp.batch)) return;
@@ -677,7 +683,7 @@ __global__ void __launch_bounds__(512) k_z3d_s(Launch<T> L) {
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
   long long bid0;
   const int gi = group_of(L, bid0);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   const Geo& g = hp.g;
   if (bid0 >= zs_blocks(g, hp.batch, Q)) return;
   const int nq = g.Xp * g.Py;
@@ -760,7 +766,7 @@ template <typename T, int PZ, bool HALF>
 __device__ __forceinline__ void z3d_reg_body(const Launch<T>& L) {
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   const Epi<T> ep = ldu(L.epis + gi);
   const Geo& g = hp.g;
   if (bid >= zreg_blocks(g, hp.batch)) return;
@@ -859,7 +865,7 @@ __global__ void __launch_bounds__(kNT) k_z3d_pair(Launch<T> L) {
   constexpr int PZ = 2 * M;
   long long bid;
   const int gi = group_of(L, bid);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   const Geo& g = hp.g;
   if (bid >= zpair_blocks(g, hp.batch)) return;
   const long long nq = (long long)g.Xp * g.Py;
@@ -1221,7 +1227,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   constexpr bool energy = MODE == MODE_ENERGY || MODE == MODE_FIELD_ENERGY;
   long long bid0;
   const int gi = group_of(L, bid0);
-  const HotPlan<T> hp = ldu(L.hps + gi);
+  const HotPlan<T> hp = hot_plan(L, gi);
   const Geo& g = hp.g;
   if (bid0 >= inv_blocks(g, hp.tu, hp.batch)) return;
   const int TY = hp.tu.ty_x;  // a power of two

@@ -102,6 +102,8 @@ template <typename T> struct Launch {
   const Epi<T>* epis;        // device [ngroups]
   int ngroups;
   int off[kMaxGroups + 1];   // off[ngroups] = grid size
+  HotPlan<T> h0;             // copy of hps[0]: group 0 reads its plan with the kernel
+                             // arguments (one scalar memory round trip less)
 };
 
 // Host-side view of a set of groups for launching.
