@@ -333,11 +333,14 @@ bool eval_fusable(const GroupSet<T>& gs) {
 // the general ones: every group of the pass (3-D groups only for the inverse)
 // has Py = 2 ny = SL for one SL in {256, 512, 1024}, and its tile of columns
 // times SL/16 threads fits a workgroup.  ept: entries per thread and stage,
-// 8 (SL/8 threads a column) where the plan has no radix 16 and the workgroup
-// still fits, else 16.  nt: the threads to launch.
+// 8 (SL/8 threads a column, the plan without radix 16, p2_radix(.., false,
+// ..), whose LDS padding is the y plan's for these lengths) where the
+// launch shapes give a column at least SL/8 threads and the workgroup still
+// fits, else 16.  nt: the threads to launch.
 template <typename T>
 int static_y(const GroupSet<T>& gs, bool inv, int& nt, int& ept) {
   int sl = 0, cmax = 0;
+  bool e8 = true;
   for (int i = 0; i < gs.n; ++i) {
     const HotPlan<T>& h = gs.h[i];
     if (inv && h.g.nz == 1) continue;
@@ -346,9 +349,10 @@ int static_y(const GroupSet<T>& gs, bool inv, int& nt, int& ept) {
     if (sl != 0 && sl != L) return 0;
     sl = L;
     cmax = std::max(cmax, h.g.nz == 1 ? 3 * h.tu.cb_y2 : h.tu.cb_y);
+    e8 = e8 && (h.g.nz == 1 ? h.tu.tpc_y2 : h.tu.tpc_y) >= L / 8;
   }
   if (sl == 0 || cmax * (sl / 16) > 512) return 0;
-  ept = p2_maxradix(sl, true) <= 8 && cmax * (sl / 8) <= 512 ? 8 : 16;
+  ept = e8 && cmax * (sl / 8) <= 512 ? 8 : 16;
   nt = std::max(64, (cmax * (sl / ept) + 63) / 64 * 64);
   return sl;
 }
@@ -408,6 +412,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         case 25616: k_ypass_s<T, 256, 16><<<grid, nts, lds, s>>>(lb.L); break;
         case 51208: k_ypass_s<T, 512, 8><<<grid, nts, lds, s>>>(lb.L); break;
         case 51216: k_ypass_s<T, 512, 16><<<grid, nts, lds, s>>>(lb.L); break;
+        case 102408: k_ypass_s<T, 1024, 8><<<grid, nts, lds, s>>>(lb.L); break;
         case 102416: k_ypass_s<T, 1024, 16><<<grid, nts, lds, s>>>(lb.L); break;
         default:
           if (y16) k_ypass<T, true><<<grid, nt, lds, s>>>(lb.L);
@@ -479,6 +484,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
           case 25616: k_yinv_s<T, 256, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
           case 51208: k_yinv_s<T, 512, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
           case 51216: k_yinv_s<T, 512, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 102408: k_yinv_s<T, 1024, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
           case 102416: k_yinv_s<T, 1024, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
           default:
             if (y16) k_yinv<T, true><<<gridy, nty, ldsy, s>>>(ly.L);

@@ -389,7 +389,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   };
   const bool half = g.Py == 2 * ny;  // ny inputs / outputs of Py points
   if constexpr (SL > 0)
-    fft_static<T, SL, true, false, true, false, true, true, false, EPT>(lds, twl, cs, ncol,
+    fft_static<T, SL, (EPT > 8), false, true, false, true, true, false, EPT>(lds, twl, cs, ncol,
                                                                        ColLoad<T>{base, coff, ny}, NoStore<T>{}, hook);
   else
     fft_run<T, false, true, false, true, R16>(lds, hp.fd[1], twl, cs, ncol, tpc, half, false,
@@ -405,7 +405,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
     const int o = jj * g.Ky + kyf;
     const T kxx = ktl[o] * s, kyy = ktl[seg + o] * s, kzz = ktl[2 * seg + o] * s;
     const T kxy = ktl[3 * seg + o] * (s * sy);
-    const int p = pidx(ky, SL > 0 ? p2_psh(SL, true) : sh);
+    const int p = pidx(ky, SL > 0 ? p2_psh(SL, EPT > 8) : sh);
     Cx<T>& m0 = spec[(0 * ncb + jj) * cs + p];
     Cx<T>& m1 = spec[(1 * ncb + jj) * cs + p];
     Cx<T>& m2 = spec[(2 * ncb + jj) * cs + p];
@@ -416,7 +416,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   }
   __syncthreads();
   if constexpr (SL > 0)
-    fft_static<T, SL, true, true, false, true, true, false, true, EPT>(lds, twl, cs, ncol, NoLoad<T>{},
+    fft_static<T, SL, (EPT > 8), true, false, true, true, false, true, EPT>(lds, twl, cs, ncol, NoLoad<T>{},
                                                                       ColStore<T>{base, coff, ny}, NoHook{});
   else
     fft_run<T, true, false, true, true, R16>(lds, hp.fd[1], twl, cs, ncol, tpc, false, half, NoLoad<T>{},
@@ -464,7 +464,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
       const ColLoadS<T> ld{sxp, coff, sb, ny};
       const ColStore<T> st{sy, yoff, g.Py};
       if constexpr (SL > 0)
-        fft_static<T, SL, true, false, true, true, false, true, false, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
+        fft_static<T, SL, (EPT > 8), false, true, true, false, true, false, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
       else
         fft_run<T, false, true, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, half, false, ld, st,
                                                   NoHook{});
@@ -472,7 +472,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
       const ColLoad<T> ld{sy, yoff, g.Py};
       const ColStoreS<T> st{sxp, coff, sb, ny};
       if constexpr (SL > 0)
-        fft_static<T, SL, true, true, true, true, false, false, true, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
+        fft_static<T, SL, (EPT > 8), true, true, true, false, false, true, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, st, NoHook{});
       else
         fft_run<T, true, true, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, false, half, ld, st,
                                                  NoHook{});
@@ -507,7 +507,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
     __syncthreads();
     const ColStore<T> st{sy, (uint32_t)(cc * g.Py) * (uint32_t)sizeof(Cx<T>), g.Py};
     if constexpr (SL > 0)
-      fft_static<T, SL, true, false, false, true, false, true, false, EPT>(lds, hp.fd[1].tw, cs, ncol, NoLoad<T>{}, st,
+      fft_static<T, SL, (EPT > 8), false, false, true, false, true, false, EPT>(lds, hp.fd[1].tw, cs, ncol, NoLoad<T>{}, st,
                                                                       NoHook{});
     else
       fft_run<T, false, false, true, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, half, false, NoLoad<T>{},
@@ -515,7 +515,7 @@ __device__ __forceinline__ void y_rows3d(const HotPlan<T>& hp, const Epi<T>& ep,
   } else {
     const ColLoad<T> ld{sy, (uint32_t)(cc * g.Py) * (uint32_t)sizeof(Cx<T>), g.Py};
     if constexpr (SL > 0)
-      fft_static<T, SL, true, true, true, false, false, false, true, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, NoStore<T>{},
+      fft_static<T, SL, (EPT > 8), true, true, false, false, false, true, EPT>(lds, hp.fd[1].tw, cs, ncol, ld, NoStore<T>{},
                                                                      NoHook{});
     else
       fft_run<T, true, true, false, false, R16>(lds, hp.fd[1], hp.fd[1].tw, cs, ncol, tpc, false, half, ld,
