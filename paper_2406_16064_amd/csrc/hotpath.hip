@@ -385,7 +385,21 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         lds = std::max(lds, ((size_t)h.tu.ty_f * col_stride(h.g.Lx) + 2 * h.g.Lx + 1) * csz);
       }
       mark();
-      k_fwd_x<T><<<dim3((unsigned)lb.total), nt, lds, s>>>(lb.L);
+      // one static length when every group has an even nx = Lx, the same Lx
+      int slx = 0;
+      for (int i = 0; i < gs.n && slx >= 0; ++i) {
+        const Geo& g = gs.h[i].g;
+        const bool st = g.nx == g.Lx && (g.Lx == 128 || g.Lx == 256 || g.Lx == 512 || g.Lx == 1024);
+        slx = st && (slx == 0 || slx == g.Lx) ? g.Lx : -1;
+      }
+      const dim3 grid((unsigned)lb.total);
+      switch (slx) {
+        case 128: k_fwd_x<T, 128><<<grid, nt, lds, s>>>(lb.L); break;
+        case 256: k_fwd_x<T, 256><<<grid, nt, lds, s>>>(lb.L); break;
+        case 512: k_fwd_x<T, 512><<<grid, nt, lds, s>>>(lb.L); break;
+        case 1024: k_fwd_x<T, 1024><<<grid, nt, lds, s>>>(lb.L); break;
+        default: k_fwd_x<T, 0><<<grid, nt, lds, s>>>(lb.L);
+      }
     }
     if (on(1)) {  // y forward (2-D groups: fused forward / product / inverse)
       LaunchBuilder<T> lb(gs, epis);

@@ -162,7 +162,9 @@ struct XRowLoad {
   }
 };
 
-template <typename T>
+// SLX: 0 for any group, else the one length Lx of every group, all with an
+// even nx = Lx (a kernel holding one static transform keeps fewer registers).
+template <typename T, int SLX>
 __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
@@ -204,14 +206,15 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
     if (e8) fft_static<T, LL, false, false, true, false, true, true, false, 8>(lds, twl, cs, nrow, ld, nst, hook); \
     else fft_static<T, LL, false, false, true, false, true, true, false, 16>(lds, twl, cs, nrow, ld, nst, hook);   \
     break;
-  switch (hin ? g.Lx : 0) {
+  switch (SLX != 0 ? SLX : hin ? g.Lx : 0) {
     MMX_FS(128)
     MMX_FS(256)
     MMX_FS(512)
     MMX_FS(1024)
     default:
-      fft_run<T, false, true, false, true>(lds, hp.fd[0], twl, cs, nrow, (int)blockDim.x >> lty, hin, false, ld, nst,
-                                           hook);
+      if constexpr (SLX == 0)
+        fft_run<T, false, true, false, true>(lds, hp.fd[0], twl, cs, nrow, (int)blockDim.x >> lty, hin, false, ld,
+                                             nst, hook);
   }
 #undef MMX_FS
   // real-to-complex post-processing: X[k] of row r
