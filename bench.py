@@ -245,8 +245,13 @@ def roofline(res, workload):
     (launches per attempt x back-to-back launch duration)."""
     dom = max(res["attempt_kernels"], key=lambda p: p["us_per_attempt"])
     ach = dom["gbs"]
+    launch = None
+    sh = res.get("launch_shapes")
+    if dom["kernel"].startswith("x_inv") and sh:  # the inverse x kernels' grid follows ty_x / nt_i
+        mesh = res["mesh"]
+        launch = "grid %d, workgroup %d," % (mesh[2] * -(-mesh[1] // sh["ty_x"]) * sh["nt_i"], sh["nt_i"])
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(workload, dom["kernel"]),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(workload, dom["kernel"], launch),
             "kernel": dom["kernel"], "alg_bytes_per_launch": dom["alg_bytes"], "us_per_launch": dom["us"],
             "launches_per_attempt": dom["per_attempt"], "share_of_attempt": round(
                 dom["us_per_attempt"] / res["attempt_kernel_us"], 3)}
@@ -266,9 +271,11 @@ def demag_pipeline(res):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def load_traffic(workload, kernel):
+def load_traffic(workload, kernel, launch=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
-    or None when the summary is missing or the kernels changed since it was taken."""
+    or None when the summary is missing, the kernels changed since it was taken,
+    or the counters were read at another launch shape than `launch`
+    ("grid G, workgroup W," of this run, when given)."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -279,7 +286,9 @@ def load_traffic(workload, kernel):
     if d.get("source_hash") != source_hash():
         return None
     rec = d.get("workloads", {}).get(workload, {}).get(kernel)
-    return None if rec is None else rec.get("bytes_per_launch")
+    if rec is None or (launch and "launch" in rec and not rec["launch"].startswith(launch)):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 # kernel-name fragments of each pass in rocprofv3 output

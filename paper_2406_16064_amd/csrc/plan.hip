@@ -1232,6 +1232,17 @@ mm_status time_passes(Engine& E, int batch, int reps, std::vector<double>& us, h
   return time_each_pass<T>(E, gs, epi_slot<T>(E, 0), MODE_RHS, reps, np, us.data(), s);
 }
 
+// The first candidate (in the fixed order they were timed) whose time is
+// within the run-to-run timing noise (3%) of the fastest: near-ties resolve
+// the same way on every run.  `none` when nothing was timed.
+inline Tuning first_near_best(const std::vector<std::pair<double, Tuning>>& timed, const Tuning& none) {
+  double tmin = 1e300;
+  for (const auto& c : timed) tmin = std::min(tmin, c.first);
+  for (const auto& c : timed)
+    if (c.first <= tmin * 1.03) return c.second;
+  return none;
+}
+
 // Measure candidate launch shapes of each pass on the device and keep the
 // fastest per pass (the passes' shapes are independent of each other).
 template <typename T>
@@ -1244,7 +1255,7 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
   const int np = pass_count(E);
   const int last = np - 1;  // the inverse-x pass
   auto try_all = [&](const std::vector<Tuning>& cands, std::vector<int> passes, Tuning& best) -> mm_status {
-    double best_us = 1e300;
+    std::vector<std::pair<double, Tuning>> timed;
     for (const Tuning& c : cands) {
       if (!tuning_ok(G, c, E.prec, E.csz)) continue;
       G.tu = c;
@@ -1253,11 +1264,9 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
       MMCHK(time_passes<T>(E, batch, reps, us, s));
       double t = 0.0;
       for (int k : passes) t += us[k];
-      if (t < best_us) {
-        best_us = t;
-        best = c;
-      }
+      timed.emplace_back(t, c);
     }
+    best = first_near_best(timed, best);
     G.tu = best;
     return MM_OK;
   };
@@ -1300,8 +1309,7 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
     std::vector<const mm_params*> qv(batch);
     std::vector<mm_rk45_state*> sv(batch);
     for (int b = 0; b < batch; ++b) { qv[b] = &q[b]; sv[b] = &tmp[b]; }
-    double best_us = 1e300;
-    Tuning pick = best;
+    std::vector<std::pair<double, Tuning>> timed;
     for (int ty : {1, 2, 4, 8, 16})
       for (int nt : {128, 256, 512}) {
         Tuning t = best;
@@ -1317,12 +1325,9 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
         const int n = pr.n;  // begin, passes..., error
         double cost = 5.0 * pr.us[n - 2] + pr.us[n - 1];
         if (demag_on(E)) cost += (pr.fused ? 1.0 : 6.0) * pr.us[1];
-        if (cost < best_us) {
-          best_us = cost;
-          pick = t;
-        }
+        timed.emplace_back(cost, t);
       }
-    best = pick;
+    best = first_near_best(timed, best);
     (void)last;
   }
   G.tu = best;

@@ -1,0 +1,85 @@
+"""Host logic of bench.py: algorithmic byte counts, the roofline's choice of
+kernel, the counter lookup and the one-GPU guard (no GPU, no library calls)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_pass_bytes_thin_film_by_hand():
+    # 256 x 256 x 1 padded to 512 x 512 x 1, FP32: X' = 257 kept x columns,
+    # spectrum of 3 components x 257 x 256 rows, 4 folded tensor components of
+    # 257 x 257 reals
+    mesh, P, w = (256, 256, 1), (512, 512, 1), 4
+    m = 3 * 256 * 256 * 4
+    sx = 3 * 257 * 256 * 8
+    K = 4 * 1 * 257 * 257 * 4
+    assert bench.pass_bytes(mesh, P, w) == [m + sx, 2 * sx + K, sx + 2 * m]
+
+
+def test_pass_bytes_slab_by_hand():
+    mesh, P, w = (512, 512, 16), (1024, 1024, 32), 8
+    m = 3 * 512 * 512 * 16 * 8
+    sx = 3 * 16 * 513 * 512 * 16
+    sy = 3 * 16 * 513 * 1024 * 16
+    K = 6 * 17 * 513 * 513 * 8
+    assert bench.pass_bytes(mesh, P, w) == [m + sx, sx + sy, 2 * sy + K, sy + sx, sx + 2 * m]
+
+
+def _res(mesh, shapes, kernel="x_inv_stage_fused_fwd"):
+    att = [{"kernel": "y_fwd", "per_attempt": 6, "us": 1.0, "alg_bytes": 10, "gbs": 10.0, "us_per_attempt": 6.0},
+           {"kernel": kernel, "per_attempt": 5, "us": 2.0, "alg_bytes": 4000, "gbs": 2000.0,
+            "us_per_attempt": 10.0}]
+    return {"attempt_kernels": att, "attempt_kernel_us": 16.0, "mesh": list(mesh), "launch_shapes": shapes}
+
+
+@pytest.fixture
+def counters(tmp_path, monkeypatch):
+    """A counter summary for the current sources in a scratch copy of the root."""
+    os.makedirs(tmp_path / "profiles")
+    rec = {"source_hash": bench.source_hash(), "workloads": {"thin": {
+        "x_inv_stage_fused_fwd": {"kernel": "k", "launch": "grid 32768, workgroup 512, LDS 0",
+                                  "bytes_per_launch": 123.0},
+        "y_fwd": {"kernel": "k", "bytes_per_launch": 7.0}}}}
+    with open(tmp_path / "profiles" / "traffic_counters.json", "w") as f:
+        json.dump(rec, f)
+    h = bench.source_hash()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: h)
+    return rec
+
+
+def test_roofline_takes_largest_time_per_attempt(counters):
+    r = bench.roofline(_res((256, 256, 1), {"ty_x": 4, "nt_i": 512}), "thin")
+    assert r["kernel"] == "x_inv_stage_fused_fwd"
+    assert r["frac"] == round(2000.0 / 8000.0, 4)
+    assert r["share_of_attempt"] == round(10.0 / 16.0, 3)
+
+
+def test_traffic_needs_the_launch_shape_it_was_counted_at(counters):
+    # 64 workgroups of 512 threads: the shape the counters were read at
+    assert bench.roofline(_res((256, 256, 1), {"ty_x": 4, "nt_i": 512}), "thin")["traffic"] == 123.0
+    # one row per workgroup: another instantiation, no counters for it
+    assert bench.roofline(_res((256, 256, 1), {"ty_x": 1, "nt_i": 512}), "thin")["traffic"] is None
+    # pass kernels carry no launch shape
+    assert bench.load_traffic("thin", "y_fwd") == 7.0
+
+
+def test_traffic_null_when_sources_changed(counters, tmp_path):
+    counters["source_hash"] = "0" * 16
+    with open(tmp_path / "profiles" / "traffic_counters.json", "w") as f:
+        json.dump(counters, f)
+    assert bench.load_traffic("thin", "y_fwd") is None
+
+
+def test_more_than_one_gpu_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode != 0
+    assert "one GPU" in p.stderr or "1 GPU" in p.stderr or "single" in p.stderr
