@@ -186,8 +186,9 @@ mm_status mm_batch_destroy(mm_batch* batch);
 
 /* Autotuner: times candidate launch shapes of every kernel pass (rows or
  * columns per workgroup, threads per transform, workgroup size) on `reps`
- * dm/dt evaluations of m (output scratch in `work`, same layout) and keeps the
- * fastest per pass.  shape_out (nullable, 8 ints) receives the chosen shapes:
+ * dm/dt evaluations of m (output scratch in `work`, same layout) and keeps, per
+ * pass, the first candidate in its fixed order whose time is within 3% of the
+ * fastest (near-ties resolve alike from run to run).  shape_out (nullable, 8 ints) receives the chosen shapes:
  * x-forward rows, x-forward threads, y columns, y threads per column, y
  * threads, x-inverse rows, x-inverse threads, 0.  Synchronises. */
 mm_status mm_plan_autotune(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
