@@ -286,7 +286,12 @@ def load_traffic(workload, kernel, launch=None):
     if d.get("source_hash") != source_hash():
         return None
     rec = d.get("workloads", {}).get(workload, {}).get(kernel)
-    if rec is None or (launch and "launch" in rec and not rec["launch"].startswith(launch)):
+    if rec is None:
+        return None
+    if launch and "launch" in rec:
+        for sig, r in rec.get("by_launch", {rec["launch"]: rec}).items():
+            if sig.startswith(launch):
+                return r.get("bytes_per_launch")
         return None
     return rec.get("bytes_per_launch")
 
@@ -339,23 +344,29 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     fr = _counter_rows(fetch_csv)
     wr = _counter_rows(write_csv)
     out = {}
+
+    def per_launch(f, w):
+        fb = sum(f) / len(f) * 1024.0 * kf
+        wb = sum(w) / len(w) * 1024.0 * kw
+        return {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
+
     for name in pass_names(mesh_nz):
         frags = PASS_KERNELS[name]
         if name == "x_inv_fused_llg":  # the dm/dt (MODE_RHS = 1) instance with the demag transform
             keys = [k for k in fr if frags[0] in k and ", true, 1," in k]
         else:
             keys = [k for f in frags for k in fr if f in k]
+        # read in both runs; the instantiation the timed run used is the one
+        # launched most (graph replays and the pass timings)
+        keys = [k for k in keys if k in wr]
         if not keys:
             continue
-        k = keys[0]
-        f = fr[k][-reps:]
-        w = wr.get(k, [0.0])[-reps:]
-        fb = sum(f) / len(f) * 1024.0 * kf
-        wb = sum(w) / len(w) * 1024.0 * kw
-        out[name] = {"kernel": k, "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
-    # the attempt-only kernels: mean over the dispatches with the launch shape
-    # of the last one (the autotuner's pick; the stage kernel runs stages 2..6
-    # in equal numbers in the graph replays and in the step timing)
+        k = max(keys, key=lambda kk: len(fr[kk]))
+        out[name] = dict(kernel=k, **per_launch(fr[k][-reps:], wr[k][-reps:]))
+    # the attempt-only kernels, per instantiation and launch shape read in both
+    # runs (the autotuner's candidates included); the headline record is the
+    # shape launched most (the autotuner's pick: the stage kernel runs stages
+    # 2..6 in equal numbers in the graph replays and in the step timing)
     frf = _counter_rows(fetch_csv, True)
     wrf = _counter_rows(write_csv, True)
     step_kinds = {"step_begin": lambda k: "k_begin<" in k,
@@ -364,17 +375,19 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
                   k.split("(")[0].endswith("true>"),
                   "x_inv_error": lambda k: "k_inv_x<" in k and ", true, 3," in k}
     for name, sel in step_kinds.items():
-        keys = [k for k in frf if sel(k)]
-        if not keys:
+        combos = {}
+        for src, col in ((frf, 0), (wrf, 1)):
+            for k, vs in src.items():
+                if sel(k):
+                    for v, g in vs:
+                        combos.setdefault((k, g), ([], []))[col].append(v)
+        both = {kg: fw for kg, fw in combos.items() if fw[0] and fw[1]}
+        if not both:
             continue
-        k = max(keys, key=lambda kk: len(frf[kk]))  # the instantiation the timed attempts ran
-        sig = frf[k][-1][1]
-        f = [v for v, g in frf[k] if g == sig]
-        w = [v for v, g in wrf.get(k, []) if g == sig] or [0.0]
-        fb = sum(f) / len(f) * 1024.0 * kf
-        wb = sum(w) / len(w) * 1024.0 * kw
-        out[name] = {"kernel": k, "launch": "grid %s, workgroup %s, LDS %s" % sig, "dispatches": len(f),
-                     "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
+        sig = lambda g: "grid %s, workgroup %s, LDS %s" % g
+        by = {sig(g): dict(kernel=k, dispatches=len(f), **per_launch(f, w)) for (k, g), (f, w) in both.items()}
+        k, g = max(both, key=lambda kg: len(both[kg][0]))
+        out[name] = dict(by[sig(g)], launch=sig(g), by_launch=by)
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     d = {}
     if os.path.exists(path):

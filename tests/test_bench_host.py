@@ -45,7 +45,10 @@ def counters(tmp_path, monkeypatch):
     os.makedirs(tmp_path / "profiles")
     rec = {"source_hash": bench.source_hash(), "workloads": {"thin": {
         "x_inv_stage_fused_fwd": {"kernel": "k", "launch": "grid 32768, workgroup 512, LDS 0",
-                                  "bytes_per_launch": 123.0},
+                                  "bytes_per_launch": 123.0, "by_launch": {
+                                      "grid 32768, workgroup 512, LDS 0": {"bytes_per_launch": 123.0},
+                                      "grid 65536, workgroup 256, LDS 0": {"bytes_per_launch": 150.0}}},
+        "x_inv_error": {"kernel": "k", "launch": "grid 32768, workgroup 512, LDS 512", "bytes_per_launch": 9.0},
         "y_fwd": {"kernel": "k", "bytes_per_launch": 7.0}}}}
     with open(tmp_path / "profiles" / "traffic_counters.json", "w") as f:
         json.dump(rec, f)
@@ -63,10 +66,17 @@ def test_roofline_takes_largest_time_per_attempt(counters):
 
 
 def test_traffic_needs_the_launch_shape_it_was_counted_at(counters):
-    # 64 workgroups of 512 threads: the shape the counters were read at
+    # 64 workgroups of 512 threads: the shape the timed counter run used
     assert bench.roofline(_res((256, 256, 1), {"ty_x": 4, "nt_i": 512}), "thin")["traffic"] == 123.0
-    # one row per workgroup: another instantiation, no counters for it
+    # one row per workgroup, 256 threads: an autotuner candidate the counters also read
+    assert bench.roofline(_res((256, 256, 1), {"ty_x": 1, "nt_i": 256}), "thin")["traffic"] == 150.0
+    # one row per workgroup, 512 threads: no counters for it
     assert bench.roofline(_res((256, 256, 1), {"ty_x": 1, "nt_i": 512}), "thin")["traffic"] is None
+    # a record without per-shape entries matches its own launch only
+    res = _res((256, 256, 1), {"ty_x": 4, "nt_i": 512}, "x_inv_error")
+    assert bench.roofline(res, "thin")["traffic"] == 9.0
+    res = _res((256, 256, 1), {"ty_x": 2, "nt_i": 512}, "x_inv_error")
+    assert bench.roofline(res, "thin")["traffic"] is None
     # pass kernels carry no launch shape
     assert bench.load_traffic("thin", "y_fwd") == 7.0
 
@@ -83,3 +93,41 @@ def test_more_than_one_gpu_refused():
                        text=True, timeout=120)
     assert p.returncode != 0
     assert "one GPU" in p.stderr or "1 GPU" in p.stderr or "single" in p.stderr
+
+
+def _csv(path, rows):
+    with open(path, "w") as f:
+        f.write("Kernel_Name,Counter_Value,Grid_Size,Workgroup_Size,LDS_Block_Size\n")
+        for k, v, g, w in rows:
+            f.write('"%s",%s,%d,%d,0\n' % (k, v, g, w))
+
+
+def test_ingest_scales_by_copy_and_keeps_shapes_read_in_both_runs(tmp_path, monkeypatch):
+    h = bench.source_hash()
+    os.makedirs(tmp_path / "profiles")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: h)
+    copy = "__amd_rocclr_copyBuffer"
+    kib = bench.COPY_BYTES / 1024.0
+    # the copy's fetch counter reads half its bytes, its write counter all of them
+    _csv(tmp_path / "cf.csv", [(copy, kib / 2, 1, 1)])
+    _csv(tmp_path / "cw.csv", [(copy, kib, 1, 1)])
+    st4 = "void mmx::k_inv_x<float, true, 2, 4, true>(mmx::Launch<float>)"
+    st1 = "void mmx::k_inv_x<float, true, 2, 1, true>(mmx::Launch<float>)"
+    yk = "void mmx::k_ypass_s<float, 512, 8>(mmx::Launch<float>)"
+    yk16 = "void mmx::k_ypass_s<float, 512, 16>(mmx::Launch<float>)"
+    fetch = [(st4, 10, 100, 50)] * 3 + [(st1, 20, 400, 100)] * 2 + [(yk, 3, 1, 1)] * 4 + [(yk16, 5, 1, 1)]
+    write = [(st4, 7, 100, 50)] * 3 + [(yk, 1, 1, 1)] * 4
+    _csv(tmp_path / "f.csv", fetch)
+    _csv(tmp_path / "w.csv", write)
+    d = bench.ingest_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "cf.csv"),
+                              str(tmp_path / "cw.csv"), "thin", 2, 1)
+    rec = d["workloads"]["thin"]
+    # y: the instantiation launched most and read in both runs; fetch x 2, write x 1
+    assert rec["y_fused_product"]["kernel"] == yk
+    assert rec["y_fused_product"]["bytes_per_launch"] == 3 * 1024 * 2 + 1 * 1024
+    st = rec["x_inv_stage_fused_fwd"]
+    assert st["launch"] == "grid 100, workgroup 50, LDS 0" and st["dispatches"] == 3
+    assert st["bytes_per_launch"] == 10 * 1024 * 2 + 7 * 1024
+    # the shape only the fetch run saw has no record (its write bytes are unknown)
+    assert list(st["by_launch"]) == ["grid 100, workgroup 50, LDS 0"]
