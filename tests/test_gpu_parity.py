@@ -49,6 +49,8 @@ MESHES = [
     (32, 256, 1, 2e-9, 2e-9, 2e-9),    # Py = 512, 2-D fused y pass
     (16, 12, 8, 2e-9, 2e-9, 2e-9),     # Pz = 16 = 2 nz: FP64 z pass through LDS compiled for Pz
     (8, 8, 32, 2e-9, 2e-9, 1e-9),      # Pz = 64 = 2 nz: the same in FP32 and FP64
+    (1024, 4, 1, 2e-9, 2e-9, 1e-9),    # nx = Lx = 1024: x passes compiled for that length
+    (128, 6, 3, 2e-9, 2e-9, 2e-9),     # nx = Lx = 128, 3-D, ragged row tiles
 ]
 
 _kern_cache = {}
