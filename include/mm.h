@@ -145,6 +145,18 @@ mm_status mm_rk45_run(mm_plan* plan, const mm_params* params, int32_t batch,
                       void* m, mm_rk45_state* st, double t_end, int64_t max_steps,
                       const double* replay_h, int64_t n_replay, void* hip_stream);
 
+/* Fixed-step Heun integration (explicit trapezoid: k1 = f(m), k2 = f(m + h k1),
+ * m <- m + h (k1 + k2) / 2) of `batch` instances in place, each step followed
+ * by the projection m <- m / |m| per cell; n_steps steps of size h (seconds,
+ * finite, > 0; n_steps >= 0).  No error control.  Paper: the integrator of
+ * the section "Performance" (N x N x 1 films, demagnetisation + exchange +
+ * Zeeman); the projection as in section "LLG equation".  Uses the plan's
+ * stage buffers: a later mm_rk45_* call on the plan needs fsal_valid = 0
+ * (m changed anyway).  Asynchronous on hip_stream apart from the upload of
+ * the step tables. */
+mm_status mm_heun_run(mm_plan* plan, const mm_params* params, int32_t batch, void* m, double h,
+                      int64_t n_steps, void* hip_stream);
+
 /* Nudged elastic band on a chain of n_img images (n_img <= max_batch, >= 3)
  * stored as images[n_img][3][nz][ny][nx]: n_iter iterations of the
  * precession-free relaxation with time step h and spring constant k_spring

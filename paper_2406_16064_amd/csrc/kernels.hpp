@@ -136,6 +136,10 @@ template <typename T>
 hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s);
 
 hipError_t launch_controller(DevCtl* ctl, int n, const double* replay_h, hipStream_t s);
+// m[i] = y[i] / |y[i]| for every cell of `batch` instances of N cells
+// ([batch][3][N] arrays).
+template <typename T>
+hipError_t launch_project(T* m, const T* y, int batch, long long N, hipStream_t s);
 
 hipError_t launch_energy_reduce(const double* partial, int batch, int blocks_per_inst, double* out,
                                 hipStream_t s);

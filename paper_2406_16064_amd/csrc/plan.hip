@@ -822,6 +822,59 @@ mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStre
   return MM_OK;
 }
 
+// Fixed-step Heun (explicit trapezoid) with projection, n_steps of size h:
+// k1 = f(m), m1 = m + h k1 (stage epilogue, slot 2); k2 = f(m1),
+// y = m + h (k1 + k2) / 2 (stage epilogue, slot 3); m = y / |y| per cell.
+// The stage epilogues take h from the controllers (h_att, nothing done).
+// Buffers: stage 0 = m1, 1 = y, 2 = k1, 3 = k2 (the Dormand-Prince slopes of
+// a later adaptive call are recomputed: its state must say fsal_valid = 0).
+template <typename T>
+mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, long long n_steps, hipStream_t s) {
+  Engine& E = p->e;
+  Group& G = E.groups[0];
+  std::vector<const mm_params*> qv(batch);
+  std::vector<int> grp(batch, 0);
+  for (int b = 0; b < batch; ++b) qv[b] = &q[b];
+  MMCHK(ensure_stage<T>(E, G, batch));
+  MMCHK(upload_params(E, qv, grp, s));
+  GroupSet<T> gs;
+  std::vector<int> inst0;
+  MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
+  for (int b = 0; b < batch; ++b) {
+    std::memset(&E.hctl[b], 0, sizeof(DevCtl));
+    E.hctl[b].h_att = h;
+  }
+  HIPCHK(hipMemcpyAsync(E.ctl + inst0[0], E.hctl, sizeof(DevCtl) * batch, hipMemcpyHostToDevice, s));
+  Epi<T> e1 = epi_base<T>(G, MODE_STAGE);
+  e1.ctl = E.ctl + inst0[0];
+  Epi<T> e2 = e1;
+  e1.in = m;
+  e1.out = stage_buf<T>(G, 2);
+  e1.mbase = m;
+  e1.msn = stage_buf<T>(G, 0);
+  e1.nk = 1;
+  e1.coef[0] = 1.0;
+  e2.in = stage_buf<T>(G, 0);
+  e2.out = stage_buf<T>(G, 3);
+  e2.mbase = m;
+  e2.msn = stage_buf<T>(G, 1);
+  e2.kprev[0] = stage_buf<T>(G, 2);
+  e2.nk = 2;
+  e2.coef[0] = 0.5;
+  e2.coef[1] = 0.5;
+  MMCHK(upload_epis<T>(E, 2, std::vector<Epi<T>>{e1}, s));
+  MMCHK(upload_epis<T>(E, 3, std::vector<Epi<T>>{e2}, s));
+  // the first stage transforms m1 along x in its inverse-x pass where the
+  // launch shape allows it; the second then skips its forward x pass
+  const bool fz = demag_on(E) && eval_fusable<T>(gs);
+  for (long long i = 0; i < n_steps; ++i) {
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 2), MODE_STAGE, demag_on(E), s, nullptr, false, fz));
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 3), MODE_STAGE, demag_on(E), s, nullptr, fz, false));
+    HIPCHK(launch_project<T>(m, stage_buf<T>(G, 1), batch, G.g.N, s));
+  }
+  return MM_OK;
+}
+
 // Timing of the kernels of one adaptive attempt (measurement aid): us[0] the
 // step-begin kernel, us[1 .. np] the passes of a stage evaluation with its
 // inverse-x pass in the form the captured attempt uses (stage epilogue, fused
@@ -1462,6 +1515,17 @@ mm_status mm_rk45_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm
   return p->e.prec == MM_F32
              ? plan_rk45<float>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s)
              : plan_rk45<double>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s);
+}
+
+mm_status mm_heun_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, double h, int64_t n_steps,
+                      void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch));
+  if (!m) return fail(MM_E_ARG, "null array");
+  if (!(h > 0) || !is_fin(h)) return fail(MM_E_ARG, "h must be finite and > 0");
+  if (n_steps < 0) return fail(MM_E_ARG, "n_steps must be >= 0");
+  hipStream_t s = (hipStream_t)hip_stream;
+  return p->e.prec == MM_F32 ? heun_impl<float>(p, q, batch, (float*)m, h, n_steps, s)
+                             : heun_impl<double>(p, q, batch, (double*)m, h, n_steps, s);
 }
 
 mm_status mm_profile_step(mm_plan* p, const mm_params* q, int32_t batch, void* m, const mm_rk45_state* st,

@@ -189,6 +189,30 @@ def neb_chain(mesh=None):
     return slerp_chain(mA, mB, w["n_images"])
 
 
+# ---------------------------------------------------------------------------
+# The paper's throughput setting: N x N x 1 films with demagnetisation,
+# exchange and Zeeman terms, integrated with Heun (fixed step).  The paper
+# gives neither material nor cell size; permalloy-like values on 2 nm cubic
+# cells (below the exchange length) and a seeded random start stand in.
+# ---------------------------------------------------------------------------
+
+HEUN_SIZES = (256, 1024, 2048)
+
+
+def heun_film(n):
+    """Workload of the throughput setting for an n x n x 1 film."""
+    return dict(name="heun-%dx%dx1" % (n, n), mesh=(n, n, 1, 2e-9, 2e-9, 2e-9),
+                params=dict(Ms=8e5, A=1.3e-11, D=0.0, Ku=0.0, u=(0, 0, 1),
+                            H=(0.0, 0.0, 1e5), alpha=0.5),
+                terms=EXCHANGE | DEMAG | ZEEMAN, h=5e-14, precision="f32")
+
+
+def heun_initial(n, mesh=None):
+    """Seeded random unit start of the n x n x 1 throughput film (or of a given mesh)."""
+    nx, ny, nz = (mesh or heun_film(n)["mesh"])[:3]
+    return random_unit(nx, ny, nz, rng_for(5, n))
+
+
 SWEEP_SIZES = (32, 64, 96, 128, 192, 256)
 
 

@@ -13,7 +13,7 @@ a 1-D chain, the minimum mesh and 3-D slabs.
 import numpy as np
 import pytest
 
-from oracle import dp45, neb, newell
+from oracle import dp45, heun, neb, newell
 from oracle import fields as F
 from paper_2406_16064_amd import inputs
 
@@ -219,6 +219,45 @@ def test_rk45_fp32_replay_thin_film(mm):
     st = mm.new_states(1, rtol=w["rtol"])
     plan.rk45_run(gpu_params(mm, p, w["terms"]), md, st, replay_h=ost.accepted_h)
     assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-4
+
+
+HEUN_MESHES = [(48, 40, 1, 2e-9, 2e-9, 2e-9), (24, 20, 5, 3e-9, 3e-9, 3e-9), (1024, 4, 1, 2e-9, 2e-9, 1e-9)]
+
+
+@pytest.mark.parametrize("mesh", HEUN_MESHES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_heun_matches_oracle(mm, mesh, prec):
+    """Fixed-step Heun with projection, all five terms: 12 steps against the oracle
+    (FP64 to 1e-10 in m, FP32 to 1e-4), and |m| = 1 after every step."""
+    p = dict(Ms=5.8e5, A=1.5e-11, D=3e-3, Ku=8e5, u=(0.2, -0.3, 1.0), H=(3e4, -2e4, 2e5), alpha=0.3)
+    m0 = representable(inputs.random_unit(*mesh[:3], np.random.default_rng(7)), DT[prec])
+    op = oracle_params(p, F.ALL_TERMS)
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+    h, n = 4e-14, 12
+    mo = heun.run(f, m0.copy(), h, n)
+    plan = mm.Plan(mesh, prec, terms=F.ALL_TERMS)
+    md = to_dev(m0, DT[prec])
+    plan.heun_run(gpu_params(mm, p, F.ALL_TERMS), md, h, n)
+    got = md.cpu().numpy()
+    assert np.max(np.linalg.norm(got - mo, axis=0)) <= (1e-10 if prec == "f64" else 1e-4)
+    assert np.max(np.abs(np.linalg.norm(got.astype(np.float64), axis=0) - 1)) <= (1e-14 if prec == "f64" else 1e-6)
+
+
+def test_heun_batch_of_different_parameters_fp64(mm):
+    """Two instances with their own Ms, field and damping in one call, each against
+    the oracle; the paper's throughput terms (demag, exchange, Zeeman)."""
+    w = inputs.heun_film(256)
+    mesh = (40, 36, 1) + w["mesh"][3:]
+    ps = [dict(w["params"]), dict(w["params"], Ms=1.1e6, H=(2e4, 0.0, -5e4), alpha=0.1)]
+    m0 = np.stack([inputs.heun_initial(256, mesh), inputs.random_unit(*mesh[:3], np.random.default_rng(9))])
+    plan = mm.Plan(mesh, "f64", terms=w["terms"], max_batch=2)
+    md = to_dev(m0, torch.float64)
+    plan.heun_run([gpu_params(mm, p, w["terms"]) for p in ps], md, w["h"], 10)
+    for b, p in enumerate(ps):
+        op = oracle_params(p, w["terms"])
+        f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+        mo = heun.run(f, m0[b].copy(), w["h"], 10)
+        assert np.max(np.linalg.norm(md[b].cpu().numpy() - mo, axis=0)) <= 1e-10
 
 
 def test_rk45_errors(mm):
