@@ -240,6 +240,35 @@ def neb_bench(mm, inputs, torch, iters=100):
             "barrier_estimate_J": float(np.max(E) - E[0])}
 
 
+def heun_bench(mm, inputs, torch, steps=100):
+    """The paper's throughput setting: N x N x 1 films, demag + exchange + Zeeman,
+    fixed-step Heun with projection in FP32, m resident in HBM.  cells_per_s =
+    cells x Heun steps / s (two dm/dt evaluations per step)."""
+    out = {"paper_context": "up to ~1e9 cells/s on an NVIDIA A800 (MicroMagnetic.jl and MuMax3, "
+                            "Heun; whether steps or evaluations are counted is not stated)"}
+    for n in inputs.HEUN_SIZES:
+        w = inputs.heun_film(n)
+        plan = mm.Plan(w["mesh"], "f32", terms=w["terms"])
+        params = mm.make_params(terms=w["terms"], **w["params"])
+        m = torch.tensor(inputs.heun_initial(n), dtype=torch.float32, device="cuda")
+        plan.autotune(params, m)
+        plan.heun_run(params, m, w["h"], 4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        plan.heun_run(params, m, w["h"], steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        cells = n * n
+        out[w["name"]] = {"steps": steps, "ms_per_step": ms / steps,
+                          "cells_per_s": cells * steps / (ms * 1e-3),
+                          "cell_evals_per_s": 2 * cells * steps / (ms * 1e-3),
+                          "launch_shapes": plan.shapes()}
+        del plan
+    return out
+
+
 def roofline(res, workload):
     """Roofline of the kernel that takes the most time per adaptive attempt
     (launches per attempt x back-to-back launch duration)."""
@@ -449,10 +478,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "copy"], default=None,
+    ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "copy", "heun"], default=None,
                     help="profiling aids: slab3d (slab3d_f64) runs only the 512x512x16 slab in FP32 (FP64) "
                          "and prints its record; copy runs only the plain 1 GiB copies the HBM counters "
-                         "are scaled by")
+                         "are scaled by; heun runs only the N x N x 1 Heun throughput records")
     ap.add_argument("--ingest-counters", nargs=5, default=None,
                     metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="turn rocprofv3 FETCH_SIZE/WRITE_SIZE counter files into per-launch HBM bytes "
@@ -474,6 +503,9 @@ def main():
     torch.cuda.set_device(0)
     if args.only == "copy":
         print(json.dumps(copy_reference(torch)))
+        return
+    if args.only == "heun":
+        print(json.dumps(heun_bench(mm, inputs, torch, args.steps)))
         return
     if args.only in ("slab3d", "slab3d_f64"):
         r3, *_ = run_workload(mm, inputs, torch, 2, "f64" if args.only == "slab3d_f64" else "f32", args.steps,
@@ -502,6 +534,8 @@ def main():
         extra["sweep"] = sweep_bench(mm, inputs, torch)
         print("bench: neb", file=sys.stderr, flush=True)
         extra["neb"] = neb_bench(mm, inputs, torch)
+        print("bench: heun", file=sys.stderr, flush=True)
+        extra["heun"] = heun_bench(mm, inputs, torch)
     cpu = None
     if not args.no_cpu:
         print("bench: cpu oracle", file=sys.stderr, flush=True)

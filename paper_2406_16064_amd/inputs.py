@@ -196,7 +196,7 @@ def neb_chain(mesh=None):
 # cells (below the exchange length) and a seeded random start stand in.
 # ---------------------------------------------------------------------------
 
-HEUN_SIZES = (256, 1024, 2048)
+HEUN_SIZES = (256, 512, 1024)
 
 
 def heun_film(n):
