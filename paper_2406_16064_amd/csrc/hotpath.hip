@@ -60,21 +60,6 @@ __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
   gst(ep.bms0 + o + 2 * N, mi.z + c * kv.z);
 }
 
-// Projection onto the unit sphere after a fixed step: one thread per cell.
-template <typename T>
-__global__ void __launch_bounds__(kNT) k_project(T* __restrict__ m, const T* __restrict__ y, long long N,
-                                                 long long total) {
-  const long long t = (long long)blockIdx.x * kNT + threadIdx.x;
-  if (t >= total) return;
-  const long long b = t / N, i = t - b * N;
-  const size_t o = (size_t)b * 3 * N + i;
-  const V3<T> v = ld3(y, N, (long long)o);
-  const T s = rsqrt_t<T>(v.x * v.x + v.y * v.y + v.z * v.z);
-  gst(m + o, v.x * s);
-  gst(m + o + N, v.y * s);
-  gst(m + o + 2 * N, v.z * s);
-}
-
 __global__ void k_controller(DevCtl* ctl, int n, const double* __restrict__ replay_h) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
@@ -549,14 +534,6 @@ hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_project(T* m, const T* y, int batch, long long N, hipStream_t s) {
-  const long long total = (long long)batch * N;
-  if (total <= 0) return hipSuccess;
-  k_project<T><<<dim3((unsigned)((total + kNT - 1) / kNT)), kNT, 0, s>>>(m, y, N, total);
-  return hipGetLastError();
-}
-
 hipError_t launch_controller(DevCtl* ctl, int n, const double* replay_h, hipStream_t s) {
   k_controller<<<dim3((n + 63) / 64), 64, 0, s>>>(ctl, n, replay_h);
   return hipGetLastError();
@@ -585,7 +562,6 @@ hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T
                                      hipEvent_t*, bool, bool, unsigned);                          \
   template bool eval_fusable<T>(const GroupSet<T>&);                                              \
   template hipError_t launch_begin<T>(const GroupSet<T>&, const Epi<T>*, hipStream_t);            \
-  template hipError_t launch_project<T>(T*, const T*, int, long long, hipStream_t);                \
   template hipError_t launch_neb<T>(const Geo&, int, const T*, T*, const T*, const double*, double, \
                                     double, double*, double*, double, double, int, hipStream_t);
 MMX_INST(float)

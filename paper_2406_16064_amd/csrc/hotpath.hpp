@@ -1463,6 +1463,10 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
         }
         const T cl = hlast;
         acc.x += cl * kk.x; acc.y += cl * kk.y; acc.z += cl * kk.z;
+        if (epi.project) {  // the end of a fixed step: back onto the unit sphere
+          const T s = rsqrt_t<T>(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
+          acc.x *= s; acc.y *= s; acc.z *= s;
+        }
         if constexpr (DEFER) res2[slot] = acc;
         else st3o(epi.msn + ib, co, acc);
         if constexpr (FUSE) mnext[slot] = acc;

@@ -48,6 +48,7 @@ template <typename T> struct Epi {
   const T* kprev[7];      // k_1..k_7 (entries used by coef)
   double coef[7];         // stage: a_{s+1,j}; error: b_j - bhat_j; multiplied by h_att
   int nk;                 // number of k entries combined (including the current one)
+  int project;            // STAGE: store the next stage input projected onto |m| = 1
   double* partial;        // energy partials [batch][blocks_per_inst][5]
   DevCtl* ctl;            // per-instance controller (skip done instances; h_att; err)
   const double* replay;   // MODE_ERROR: replayed step sizes (controller in the last workgroup)
@@ -136,10 +137,6 @@ template <typename T>
 hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s);
 
 hipError_t launch_controller(DevCtl* ctl, int n, const double* replay_h, hipStream_t s);
-// m[i] = y[i] / |y[i]| for every cell of `batch` instances of N cells
-// ([batch][3][N] arrays).
-template <typename T>
-hipError_t launch_project(T* m, const T* y, int batch, long long N, hipStream_t s);
 
 hipError_t launch_energy_reduce(const double* partial, int batch, int blocks_per_inst, double* out,
                                 hipStream_t s);

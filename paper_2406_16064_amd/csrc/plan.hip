@@ -824,10 +824,14 @@ mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStre
 
 // Fixed-step Heun (explicit trapezoid) with projection, n_steps of size h:
 // k1 = f(m), m1 = m + h k1 (stage epilogue, slot 2); k2 = f(m1),
-// y = m + h (k1 + k2) / 2 (stage epilogue, slot 3); m = y / |y| per cell.
+// m <- (m + h (k1 + k2) / 2) / |...| per cell (stage epilogue, slot 3, in
+// place: each cell's m is read by its own thread only, before its store).
 // The stage epilogues take h from the controllers (h_att, nothing done).
-// Buffers: stage 0 = m1, 1 = y, 2 = k1, 3 = k2 (the Dormand-Prince slopes of
-// a later adaptive call are recomputed: its state must say fsal_valid = 0).
+// Where the launch shape allows, each stage's inverse-x pass also transforms
+// the next stage input along x (stage 2: the next step's m), so that only the
+// first stage of a call runs the forward x pass.  Buffers: stage 0 = m1,
+// 2 = k1, 3 = k2 (the Dormand-Prince slopes of a later adaptive call are
+// recomputed: its state must say fsal_valid = 0).
 template <typename T>
 mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, long long n_steps, hipStream_t s) {
   Engine& E = p->e;
@@ -857,20 +861,18 @@ mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, l
   e2.in = stage_buf<T>(G, 0);
   e2.out = stage_buf<T>(G, 3);
   e2.mbase = m;
-  e2.msn = stage_buf<T>(G, 1);
+  e2.msn = m;
+  e2.project = 1;
   e2.kprev[0] = stage_buf<T>(G, 2);
   e2.nk = 2;
   e2.coef[0] = 0.5;
   e2.coef[1] = 0.5;
   MMCHK(upload_epis<T>(E, 2, std::vector<Epi<T>>{e1}, s));
   MMCHK(upload_epis<T>(E, 3, std::vector<Epi<T>>{e2}, s));
-  // the first stage transforms m1 along x in its inverse-x pass where the
-  // launch shape allows it; the second then skips its forward x pass
   const bool fz = demag_on(E) && eval_fusable<T>(gs);
   for (long long i = 0; i < n_steps; ++i) {
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 2), MODE_STAGE, demag_on(E), s, nullptr, false, fz));
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 3), MODE_STAGE, demag_on(E), s, nullptr, fz, false));
-    HIPCHK(launch_project<T>(m, stage_buf<T>(G, 1), batch, G.g.N, s));
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 2), MODE_STAGE, demag_on(E), s, nullptr, fz && i > 0, fz));
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 3), MODE_STAGE, demag_on(E), s, nullptr, fz, fz));
   }
   return MM_OK;
 }
