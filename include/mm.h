@@ -157,6 +157,21 @@ mm_status mm_rk45_run(mm_plan* plan, const mm_params* params, int32_t batch,
 mm_status mm_heun_run(mm_plan* plan, const mm_params* params, int32_t batch, void* m, double h,
                       int64_t n_steps, void* hip_stream);
 
+/* Energy minimisation by steepest descent with Barzilai-Borwein step sizes
+ * (section "Steepest descent energy minimization", eq_update): n_iter
+ * iterations on `batch` instances in place.  Per cell, f = m x H_eff and
+ * g = m x f; (1 + tau^2 |f|^2 / 4) m' = (1 - tau^2 |f|^2 / 4) m - tau g (|m|
+ * kept).  tau (m/A, one per instance): tau0 at iteration 0; at iteration k
+ * the first rule s.s / s.y for odd k, the second s.y / y.y for even k, over
+ * all cells of the instance (s = m_k - m_{k-1}, y = g_k - g_{k-1}, FP64
+ * sums); a quotient that is not finite and positive keeps the previous tau;
+ * clipped to [tau_min, tau_max].  Needs 0 < tau_min <= tau0 <= tau_max.
+ * tau_out (host, batch doubles, nullable): the last tau.  Uses the plan's
+ * stage buffers (a later mm_rk45_* call needs fsal_valid = 0).
+ * Synchronises. */
+mm_status mm_sd_run(mm_plan* plan, const mm_params* params, int32_t batch, void* m, int64_t n_iter,
+                    double tau0, double tau_min, double tau_max, double* tau_out, void* hip_stream);
+
 /* Nudged elastic band on a chain of n_img images (n_img <= max_batch, >= 3)
  * stored as images[n_img][3][nz][ny][nx]: n_iter iterations of the
  * precession-free relaxation with time step h and spring constant k_spring

@@ -60,6 +60,92 @@ __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
   gst(ep.bms0 + o + 2 * N, mi.z + c * kv.z);
 }
 
+// ---------------------------------------------------------------------------
+// Steepest descent with Barzilai-Borwein steps (energy minimisation).
+// ---------------------------------------------------------------------------
+// g = m x (m x H) per cell (stored) and, when `stats`, per-block FP64 sums of
+// s.s, s.y and y.y with s = m - m_prev, y = g - g_prev (the differences taken
+// in FP64 from the stored values).  Blocks of kNT threads, bpi per instance.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_sd_stats(const T* __restrict__ m, const T* __restrict__ H,
+                                                  const T* __restrict__ mp, const T* __restrict__ gp,
+                                                  T* __restrict__ g, double* __restrict__ part, long long N,
+                                                  int bpi, int stats) {
+  __shared__ double red[3][kNT / 64];
+  const int b = (int)(blockIdx.x / (unsigned)bpi);
+  const int blk = (int)(blockIdx.x - (unsigned)b * (unsigned)bpi);
+  const long long i = (long long)blk * kNT + threadIdx.x;
+  double ss = 0.0, sy = 0.0, yy = 0.0;
+  if (i < N) {
+    const size_t o = (size_t)b * 3 * N + i;
+    const V3<T> mi = ld3(m, N, (long long)o), Hi = ld3(H, N, (long long)o);
+    const V3<T> f = {mi.y * Hi.z - mi.z * Hi.y, mi.z * Hi.x - mi.x * Hi.z, mi.x * Hi.y - mi.y * Hi.x};
+    const V3<T> gi = {mi.y * f.z - mi.z * f.y, mi.z * f.x - mi.x * f.z, mi.x * f.y - mi.y * f.x};
+    gst(g + o, gi.x); gst(g + o + N, gi.y); gst(g + o + 2 * N, gi.z);
+    if (stats) {
+      const V3<T> mq = ld3(mp, N, (long long)o), gq = ld3(gp, N, (long long)o);
+      const double sx = (double)mi.x - (double)mq.x, sy_ = (double)mi.y - (double)mq.y;
+      const double sz = (double)mi.z - (double)mq.z;
+      const double yx = (double)gi.x - (double)gq.x, yy_ = (double)gi.y - (double)gq.y;
+      const double yz = (double)gi.z - (double)gq.z;
+      ss = sx * sx + sy_ * sy_ + sz * sz;
+      sy = sx * yx + sy_ * yy_ + sz * yz;
+      yy = yx * yx + yy_ * yy_ + yz * yz;
+    }
+  }
+  if (!stats) return;
+  ss = wave_sum(ss); sy = wave_sum(sy); yy = wave_sum(yy);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = ss; red[1][w] = sy; red[2][w] = yy; }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+    for (int j = 0; j < kNT / 64; ++j) v += red[threadIdx.x][j];
+    part[((size_t)b * bpi + blk) * 3 + threadIdx.x] = v;
+  }
+}
+
+// One 64-thread workgroup per instance: fixed-order sums of the block
+// partials, then the step rule of iteration k >= 1 (odd k: s.s / s.y, even k:
+// s.y / y.y; a quotient that is not finite and positive keeps the previous
+// step) and the clip to [tau_min, tau_max].
+__global__ void __launch_bounds__(64) k_sd_tau(const double* __restrict__ part, int bpi, long long k,
+                                               double* __restrict__ tau, double tau_min, double tau_max) {
+  const int b = blockIdx.x;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < bpi; j += 64)
+    for (int q = 0; q < 3; ++q) v[q] += part[((size_t)b * bpi + j) * 3 + q];
+  for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
+  if (threadIdx.x != 0) return;
+  const double num = (k & 1) ? v[0] : v[1], den = (k & 1) ? v[1] : v[2];
+  double t = num / den;
+  if (!(t > 0.0) || !(t <= DBL_MAX)) t = tau[b];
+  tau[b] = fmin(fmax(t, tau_min), tau_max);
+}
+
+// m_prev <- m, g_prev <- g, then the update of the energy-minimisation section:
+// (1 + tau^2 |f|^2 / 4) m' = (1 - tau^2 |f|^2 / 4) m - tau g, f = m x H.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_sd_update(T* __restrict__ m, const T* __restrict__ H,
+                                                   const T* __restrict__ g, T* __restrict__ mp,
+                                                   T* __restrict__ gp, const double* __restrict__ tau, long long N,
+                                                   long long total) {
+  const long long t = (long long)blockIdx.x * kNT + threadIdx.x;
+  if (t >= total) return;
+  const long long b = t / N, i = t - b * N;
+  const size_t o = (size_t)b * 3 * N + i;
+  const V3<T> mi = ld3(m, N, (long long)o), Hi = ld3(H, N, (long long)o), gi = ld3(g, N, (long long)o);
+  const V3<T> f = {mi.y * Hi.z - mi.z * Hi.y, mi.z * Hi.x - mi.x * Hi.z, mi.x * Hi.y - mi.y * Hi.x};
+  const T tb = T(tau[b]);
+  const T a = T(0.25) * tb * tb * (f.x * f.x + f.y * f.y + f.z * f.z);
+  const T c0 = (T(1) - a) / (T(1) + a), c1 = tb / (T(1) + a);
+  gst(mp + o, mi.x); gst(mp + o + N, mi.y); gst(mp + o + 2 * N, mi.z);
+  gst(gp + o, gi.x); gst(gp + o + N, gi.y); gst(gp + o + 2 * N, gi.z);
+  gst(m + o, c0 * mi.x - c1 * gi.x);
+  gst(m + o + N, c0 * mi.y - c1 * gi.y);
+  gst(m + o + 2 * N, c0 * mi.z - c1 * gi.z);
+}
+
 __global__ void k_controller(DevCtl* ctl, int n, const double* __restrict__ replay_h) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
@@ -534,6 +620,17 @@ hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_sd_iteration(T* m, const T* H, T* g, T* mp, T* gp, double* part, double* tau, int batch,
+                               long long N, long long k, double tau_min, double tau_max, hipStream_t s) {
+  const int bpi = (int)((N + kNT - 1) / kNT);
+  k_sd_stats<T><<<dim3((unsigned)(batch * bpi)), kNT, 0, s>>>(m, H, mp, gp, g, part, N, bpi, k > 0 ? 1 : 0);
+  if (k > 0) k_sd_tau<<<dim3((unsigned)batch), 64, 0, s>>>(part, bpi, k, tau, tau_min, tau_max);
+  const long long total = (long long)batch * N;
+  k_sd_update<T><<<dim3((unsigned)((total + kNT - 1) / kNT)), kNT, 0, s>>>(m, H, g, mp, gp, tau, N, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_controller(DevCtl* ctl, int n, const double* replay_h, hipStream_t s) {
   k_controller<<<dim3((n + 63) / 64), 64, 0, s>>>(ctl, n, replay_h);
   return hipGetLastError();
@@ -562,6 +659,8 @@ hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T
                                      hipEvent_t*, bool, bool, unsigned);                          \
   template bool eval_fusable<T>(const GroupSet<T>&);                                              \
   template hipError_t launch_begin<T>(const GroupSet<T>&, const Epi<T>*, hipStream_t);            \
+  template hipError_t launch_sd_iteration<T>(T*, const T*, T*, T*, T*, double*, double*, int, long long,   \
+                                             long long, double, double, hipStream_t);                 \
   template hipError_t launch_neb<T>(const Geo&, int, const T*, T*, const T*, const double*, double, \
                                     double, double*, double*, double, double, int, hipStream_t);
 MMX_INST(float)

@@ -877,6 +877,56 @@ mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, l
   return MM_OK;
 }
 
+// Steepest descent with Barzilai-Borwein steps, n_iter iterations: H_eff(m)
+// by a field evaluation (epilogue slot 4), then launch_sd_iteration.  Buffers:
+// stage 4 = H, 5 = g, 6 = m_prev, 7 = g_prev (a later adaptive call needs
+// fsal_valid = 0).  tau_out (host, nullable): the last step size of each
+// instance.  Synchronises.
+template <typename T>
+mm_status sd_impl(mm_plan* p, const mm_params* q, int batch, T* m, long long n_iter, double tau0, double tau_min,
+                  double tau_max, double* tau_out, hipStream_t s) {
+  Engine& E = p->e;
+  Group& G = E.groups[0];
+  std::vector<const mm_params*> qv(batch);
+  std::vector<int> grp(batch, 0);
+  for (int b = 0; b < batch; ++b) qv[b] = &q[b];
+  MMCHK(ensure_stage<T>(E, G, batch));
+  MMCHK(upload_params(E, qv, grp, s));
+  GroupSet<T> gs;
+  std::vector<int> inst0;
+  MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
+  T* const H = stage_buf<T>(G, 4);
+  Epi<T> e = epi_base<T>(G, MODE_FIELD);
+  e.in = m;
+  e.out = H;
+  MMCHK(upload_epis<T>(E, 4, std::vector<Epi<T>>{e}, s));
+  const long long N = G.g.N;
+  const size_t bpi = (size_t)((N + 255) / 256);
+  double* part = nullptr;
+  double* tau = nullptr;
+  MMCHK(dev_alloc((void**)&part, sizeof(double) * 3 * bpi * batch));
+  mm_status st = dev_alloc((void**)&tau, sizeof(double) * batch);
+  std::vector<double> t0(batch, tau0);
+  hipError_t er = st == MM_OK ? hipMemcpyAsync(tau, t0.data(), sizeof(double) * batch, hipMemcpyHostToDevice, s)
+                              : hipSuccess;
+  for (long long k = 0; st == MM_OK && er == hipSuccess && k < n_iter; ++k) {
+    er = launch_eval<T>(gs, epi_slot<T>(E, 4), MODE_FIELD, demag_on(E), s);
+    if (er == hipSuccess)
+      er = launch_sd_iteration<T>(m, H, stage_buf<T>(G, 5), stage_buf<T>(G, 6), stage_buf<T>(G, 7), part, tau,
+                                  batch, N, k, tau_min, tau_max, s);
+  }
+  {  // the buffers are freed below: nothing may still use them
+    const hipError_t es = hipStreamSynchronize(s);
+    if (er == hipSuccess) er = es;
+  }
+  if (st == MM_OK && er == hipSuccess && tau_out) er = hipMemcpy(tau_out, tau, sizeof(double) * batch,
+                                                                 hipMemcpyDeviceToHost);
+  if (st == MM_OK && er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
+  (void)hipFree(part);
+  if (tau) (void)hipFree(tau);
+  return st;
+}
+
 // Timing of the kernels of one adaptive attempt (measurement aid): us[0] the
 // step-begin kernel, us[1 .. np] the passes of a stage evaluation with its
 // inverse-x pass in the form the captured attempt uses (stage epilogue, fused
@@ -1517,6 +1567,18 @@ mm_status mm_rk45_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm
   return p->e.prec == MM_F32
              ? plan_rk45<float>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s)
              : plan_rk45<double>(p, q, batch, m, st, t_end, max_steps, replay_h, n_replay, false, s);
+}
+
+mm_status mm_sd_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, int64_t n_iter, double tau0,
+                    double tau_min, double tau_max, double* tau_out, void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch));
+  if (!m) return fail(MM_E_ARG, "null array");
+  if (n_iter < 0) return fail(MM_E_ARG, "n_iter must be >= 0");
+  if (!(tau_min > 0) || !is_fin(tau_max) || !(tau_min <= tau0) || !(tau0 <= tau_max))
+    return fail(MM_E_ARG, "need 0 < tau_min <= tau0 <= tau_max (finite)");
+  hipStream_t s = (hipStream_t)hip_stream;
+  return p->e.prec == MM_F32 ? sd_impl<float>(p, q, batch, (float*)m, n_iter, tau0, tau_min, tau_max, tau_out, s)
+                             : sd_impl<double>(p, q, batch, (double*)m, n_iter, tau0, tau_min, tau_max, tau_out, s);
 }
 
 mm_status mm_heun_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, double h, int64_t n_steps,

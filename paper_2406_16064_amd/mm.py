@@ -65,6 +65,7 @@ _sigs = {
     "mm_rk45_run": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _i64, _vp],
     "mm_neb_run": [_vp, _P(Params), _vp, _i32, _dbl, _dbl, _i64, _P(_dbl), _vp],
     "mm_heun_run": [_vp, _P(Params), _i32, _vp, _dbl, _i64, _vp],
+    "mm_sd_run": [_vp, _P(Params), _i32, _vp, _i64, _dbl, _dbl, _dbl, _P(_dbl), _vp],
     "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
     "mm_profile_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _i32, _P(_dbl), _P(_i32), _P(_i32), _vp],
     "mm_plan_autotune": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
@@ -215,6 +216,14 @@ class Plan:
         """n_steps fixed Heun steps of size h with projection, m advanced in place."""
         _check(_lib.mm_heun_run(self._h, _params_array(params), self._batch(m), _ptr(m), h, n_steps,
                                 _stream(stream)), "mm_heun_run")
+
+    def sd_run(self, params, m, n_iter, tau0, tau_min, tau_max, stream=None):
+        """n_iter steepest-descent (Barzilai-Borwein) iterations, m in place; returns the last tau per instance."""
+        nb = self._batch(m)
+        tau = (ctypes.c_double * nb)()
+        _check(_lib.mm_sd_run(self._h, _params_array(params), nb, _ptr(m), n_iter, tau0, tau_min, tau_max, tau,
+                              _stream(stream)), "mm_sd_run")
+        return np.array(tau[:])
 
     def neb_run(self, params, images, k_spring, h, n_iter, stream=None):
         n_img = images.shape[0]
