@@ -269,6 +269,24 @@ def heun_bench(mm, inputs, torch, steps=100):
     return out
 
 
+def sd_bench(mm, inputs, torch, iters=200):
+    """Steepest-descent (Barzilai-Borwein) relaxation of the 256x256x1 thin film
+    (all five terms, FP32): iterations per second and cells x iterations / s
+    (one field evaluation per iteration), m resident in HBM."""
+    w = inputs.workload(1)
+    plan = mm.Plan(w["mesh"], "f32", terms=w["terms"])
+    params = mm.make_params(terms=w["terms"], **w["params"])
+    m = torch.tensor(inputs.initial_state(1), dtype=torch.float32, device="cuda")
+    plan.autotune(params, m)
+    plan.sd_run(params, m.clone(), 4, 1e-7, 1e-10, 1e-3)
+    t0 = time.perf_counter()
+    tau = plan.sd_run(params, m, iters, 1e-7, 1e-10, 1e-3)  # synchronises
+    s = time.perf_counter() - t0
+    cells = w["mesh"][0] * w["mesh"][1]
+    return {"workload": "sd-" + w["name"], "iterations": iters, "ms_per_iteration": 1e3 * s / iters,
+            "cell_iterations_per_s": cells * iters / s, "last_tau": float(tau[0])}
+
+
 def roofline(res, workload):
     """Roofline of the kernel that takes the most time per adaptive attempt
     (launches per attempt x back-to-back launch duration)."""
@@ -478,10 +496,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "copy", "heun"], default=None,
+    ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "copy", "heun", "sd"], default=None,
                     help="profiling aids: slab3d (slab3d_f64) runs only the 512x512x16 slab in FP32 (FP64) "
                          "and prints its record; copy runs only the plain 1 GiB copies the HBM counters "
-                         "are scaled by; heun runs only the N x N x 1 Heun throughput records")
+                         "are scaled by; heun runs only the N x N x 1 Heun throughput records, sd only the "
+                         "steepest-descent relaxation record")
     ap.add_argument("--ingest-counters", nargs=5, default=None,
                     metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="turn rocprofv3 FETCH_SIZE/WRITE_SIZE counter files into per-launch HBM bytes "
@@ -506,6 +525,9 @@ def main():
         return
     if args.only == "heun":
         print(json.dumps(heun_bench(mm, inputs, torch, args.steps)))
+        return
+    if args.only == "sd":
+        print(json.dumps(sd_bench(mm, inputs, torch)))
         return
     if args.only in ("slab3d", "slab3d_f64"):
         r3, *_ = run_workload(mm, inputs, torch, 2, "f64" if args.only == "slab3d_f64" else "f32", args.steps,
@@ -536,6 +558,8 @@ def main():
         extra["neb"] = neb_bench(mm, inputs, torch)
         print("bench: heun", file=sys.stderr, flush=True)
         extra["heun"] = heun_bench(mm, inputs, torch)
+        print("bench: steepest descent", file=sys.stderr, flush=True)
+        extra["sd"] = sd_bench(mm, inputs, torch)
     cpu = None
     if not args.no_cpu:
         print("bench: cpu oracle", file=sys.stderr, flush=True)
