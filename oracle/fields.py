@@ -32,6 +32,8 @@ Mesh = namedtuple("Mesh", "nx ny nz dx dy dz")
 
 EXCHANGE, DEMAG, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
 ALL_TERMS = EXCHANGE | DEMAG | DMI | ANIS | ZEEMAN
+# the other two DMI symmetry classes of the DMI section (same constant D)
+DMI_BULK, DMI_D2D = 32, 64
 
 
 class Params:
@@ -90,6 +92,26 @@ def dmi_field(m, mesh, p):
     """H_dmi,i = -(D/(mu0 Ms)) sum_{j in N_i} (e_ij x m_j)/Delta_ij, interfacial e_ij."""
     H = np.zeros_like(m)
     for axis, step, dname, e in _NEIGHBOURS:
+        if e == (0.0, 0.0, 0.0):
+            continue
+        mj, valid = _neighbour(m, axis, step)
+        delta = getattr(mesh, dname)
+        e = np.asarray(e).reshape(3, 1, 1, 1)
+        H += np.where(valid, np.cross(e, mj, axis=0) / delta, 0.0)
+    return -(p.D / (MU0 * p.Ms)) * H
+
+
+# DMI vectors e_ij of the unified DMI form for the neighbours -x, +x, -y, +y, -z, +z
+# (same order as _NEIGHBOURS): bulk (classes T, O) e_ij = r_ij; class D2d
+# {e_x, -e_x, -e_y, e_y, 0, 0}
+_E_BULK = ((-1.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, -1.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, -1.0), (0.0, 0.0, 1.0))
+_E_D2D = ((1.0, 0.0, 0.0), (-1.0, 0.0, 0.0), (0.0, -1.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+
+
+def dmi_field_vectors(m, mesh, p, evecs):
+    """H_dmi,i = -(D/(mu0 Ms)) sum_{j in N_i} (e_ij x m_j)/Delta_ij for DMI vectors evecs."""
+    H = np.zeros_like(m)
+    for (axis, step, dname, _), e in zip(_NEIGHBOURS, evecs):
         if e == (0.0, 0.0, 0.0):
             continue
         mj, valid = _neighbour(m, axis, step)
@@ -172,6 +194,10 @@ def effective_field_terms(m, mesh, p, kernel=None):
         out["demag"] = kernel.field(m, p.Ms)
     if p.terms & DMI:
         out["dmi"] = dmi_field(m, mesh, p)
+    if p.terms & DMI_BULK:
+        out["dmi_bulk"] = dmi_field_vectors(m, mesh, p, _E_BULK)
+    if p.terms & DMI_D2D:
+        out["dmi_d2d"] = dmi_field_vectors(m, mesh, p, _E_D2D)
     if p.terms & ANIS:
         out["anisotropy"] = anisotropy_field(m, p)
     if p.terms & ZEEMAN:
@@ -205,15 +231,15 @@ def energies(m, mesh, p, kernel=None):
     """Energies in J, in the order exchange, demag, dmi, anisotropy, zeeman.
 
     Quadratic terms: E = -(mu0/2) Ms V sum_i m_i . H_term,i; Zeeman: -mu0 Ms V sum m . H.
-    Disabled terms give 0.
+    Disabled terms give 0.  Every DMI symmetry class enabled adds to the dmi entry.
     """
     V = mesh.dx * mesh.dy * mesh.dz
     terms = effective_field_terms(m, mesh, p, kernel)
     E = np.zeros(5)
-    for n, name in enumerate(ENERGY_ORDER):
-        if name in terms:
-            f = 1.0 if name == "zeeman" else 0.5
-            E[n] = -f * MU0 * p.Ms * V * np.sum(m * terms[name])
+    for name, H in terms.items():
+        n = ENERGY_ORDER.index("dmi" if name.startswith("dmi") else name)
+        f = 1.0 if name == "zeeman" else 0.5
+        E[n] += -f * MU0 * p.Ms * V * np.sum(m * H)
     return E
 
 
