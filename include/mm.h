@@ -55,9 +55,16 @@ enum {
   MM_DEMAG = 2u,            /* Newell-tensor convolution, zero padded               */
   MM_DMI_INTERFACIAL = 4u,  /* interfacial (C_nv) DMI, e_ij = e_z x r_ij            */
   MM_ANIS_UNIAXIAL = 8u,    /* uniaxial anisotropy, easy axis u                     */
-  MM_ZEEMAN = 16u           /* uniform static applied field                         */
+  MM_ZEEMAN = 16u,          /* uniform static applied field                         */
+  MM_DMI_BULK = 32u,        /* bulk (classes T, O) DMI, e_ij = r_ij                 */
+  MM_DMI_D2D = 64u          /* class D2d DMI, e_ij = {e_x, -e_x, -e_y, e_y, 0, 0}   */
 };
+/* the five terms of the standard path; MM_TERM_MASK: every known bit.  The
+ * three DMI classes share the constant D; each enabled one adds its field
+ * (section "Dzyaloshinskii-Moriya Energy", the unified neighbour form) and
+ * its energy to the DMI entry. */
 #define MM_ALL_TERMS 31u
+#define MM_TERM_MASK 127u
 
 /* Regular mesh of nx*ny*nz cuboid cells of size dx*dy*dz (paper: FDMesh).
  * Limits: 1 <= n <= 2048 per axis, nx >= 2; d > 0 and finite. */

@@ -996,7 +996,7 @@ struct LocalTerms {
 // Coefficients of the local terms in the working precision (kept in scalar
 // registers for the whole epilogue).
 template <typename T> struct LocalCoef {
-  T cex[3], cdmi[2], can, u[3], H[3];
+  T cex[3], cdmi[3], can, u[3], H[3];
   uint32_t terms;
 };
 
@@ -1010,6 +1010,7 @@ __device__ __forceinline__ LocalCoef<T> local_coef(const DevParams& P) {
   }
   c.cdmi[0] = T(P.cdmi[0]);
   c.cdmi[1] = T(P.cdmi[1]);
+  c.cdmi[2] = T(P.cdmi[2]);
   c.can = T(P.can);
   c.terms = P.terms;
   return c;
@@ -1025,7 +1026,7 @@ __device__ __forceinline__ Nbr<T> load_nbr(const Geo& g, uint32_t terms, const T
   n.mi = ld3o(mb, co);
   n.xm = {T(0), T(0), T(0)};
   n.xp = n.xm; n.ym = n.xm; n.yp = n.xm; n.zm = n.xm; n.zp = n.xm;
-  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL)) {
+  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL | MM_DMI_BULK | MM_DMI_D2D)) {
     const long long nxy = (long long)g.nx * g.ny;
     if (x > 0) n.xm = ld3o(mb - 1, co);
     if (x + 1 < g.nx) n.xp = ld3o(mb + 1, co);
@@ -1069,7 +1070,28 @@ __device__ __forceinline__ V3<T> local_field(const Geo& g, const LocalCoef<T>& P
     const V3<T> dy = {ym.x - yp.x, ym.y - yp.y, ym.z - yp.z};
     V3<T> d = {-cx * dx.z, cy * dy.z, cx * dx.x - cy * dy.y};
     H.x += d.x; H.y += d.y; H.z += d.z;
-    if (ENERGY) lt->dmi = (double)mi.x * d.x + (double)mi.y * d.y + (double)mi.z * d.z;
+    if (ENERGY) lt->dmi += (double)mi.x * d.x + (double)mi.y * d.y + (double)mi.z * d.z;
+  }
+  if (P.terms & (MM_DMI_BULK | MM_DMI_D2D)) {
+    // a = m_{+x} - m_{-x}, b = m_{+y} - m_{-y}, c = m_{+z} - m_{-z} (missing neighbours are zero);
+    // e_x x v = (0, -v_z, v_y), e_y x v = (v_z, 0, -v_x), e_z x v = (-v_y, v_x, 0)
+    const T cx = P.cdmi[0], cy = P.cdmi[1], cz = P.cdmi[2];
+    const V3<T> a = {xp.x - xm.x, xp.y - xm.y, xp.z - xm.z};
+    const V3<T> b = {yp.x - ym.x, yp.y - ym.y, yp.z - ym.z};
+    V3<T> d = {T(0), T(0), T(0)};
+    if (P.terms & MM_DMI_BULK) {  // -(cx e_x x a + cy e_y x b + cz e_z x c)
+      const V3<T> c = {zp.x - zm.x, zp.y - zm.y, zp.z - zm.z};
+      d.x += cz * c.y - cy * b.z;
+      d.y += cx * a.z - cz * c.x;
+      d.z += cy * b.x - cx * a.y;
+    }
+    if (P.terms & MM_DMI_D2D) {  // cx e_x x a - cy e_y x b
+      d.x -= cy * b.z;
+      d.y -= cx * a.z;
+      d.z += cx * a.y + cy * b.x;
+    }
+    H.x += d.x; H.y += d.y; H.z += d.z;
+    if (ENERGY) lt->dmi += (double)mi.x * d.x + (double)mi.y * d.y + (double)mi.z * d.z;
   }
   if (P.terms & MM_ANIS_UNIAXIAL) {
     const T ux = P.u[0], uy = P.u[1], uz = P.u[2];

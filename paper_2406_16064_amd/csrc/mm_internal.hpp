@@ -126,7 +126,7 @@ template <typename T> inline FftDesc<T> describe(const FftPlan<T>& p) {
 struct DevParams {
   double Ms;
   double cex[3];     // 2A / (mu0 Ms d_a^2) for a = x, y, z
-  double cdmi[2];    // D / (mu0 Ms d_a) for a = x, y
+  double cdmi[3];    // D / (mu0 Ms d_a) for a = x, y, z
   double can;        // 2 Ku / (mu0 Ms)
   double u[3];       // easy axis, normalised
   double H[3];       // applied field

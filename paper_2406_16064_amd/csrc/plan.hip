@@ -311,6 +311,7 @@ DevParams dev_params(const mm_params& r, const Group& G) {
   o.cex[2] = 2 * r.A / (c * G.mesh.dz * G.mesh.dz);
   o.cdmi[0] = r.D / (c * G.mesh.dx);
   o.cdmi[1] = r.D / (c * G.mesh.dy);
+  o.cdmi[2] = r.D / (c * G.mesh.dz);
   o.can = 2 * r.Ku / c;
   const double un = std::sqrt(r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
   for (int k = 0; k < 3; ++k) {
@@ -1474,7 +1475,7 @@ mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec, 
   MMCHK(check_mesh(mesh));
   if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
   MMCHK(check_cells(mesh, prec));
-  if (terms & ~MM_ALL_TERMS) return fail(MM_E_ARG, "unknown term bits");
+  if (terms & ~MM_TERM_MASK) return fail(MM_E_ARG, "unknown term bits");
   if (max_batch < 1) return fail(MM_E_ARG, "max_batch must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
   mm_plan* p = new mm_plan();
@@ -1700,7 +1701,7 @@ mm_status mm_batch_create(mm_batch** out, const mm_mesh* meshes, int32_t n_meshe
   for (int i = 0; i < n_meshes; ++i) MMCHK(check_mesh(&meshes[i]));
   if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
   for (int i = 0; i < n_meshes; ++i) MMCHK(check_cells(&meshes[i], prec));
-  if (terms & ~MM_ALL_TERMS) return fail(MM_E_ARG, "unknown term bits");
+  if (terms & ~MM_TERM_MASK) return fail(MM_E_ARG, "unknown term bits");
   hipStream_t s = (hipStream_t)hip_stream;
   mm_batch* b = new mm_batch();
   mm_status st = engine_init(b->e, prec, terms);

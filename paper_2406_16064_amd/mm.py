@@ -20,6 +20,7 @@ MM_F32, MM_F64 = 0, 1
 SHAPE_KEYS = ("ty_f", "nt_f", "cb_y", "tpc_y", "nt_y", "ty_x", "nt_i")
 EXCHANGE, DEMAG, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
 ALL_TERMS = 31
+DMI_BULK, DMI_D2D = 32, 64  # the other DMI symmetry classes (same D)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmmx.so is not built; run `python -m paper_2406_16064_amd.build` "

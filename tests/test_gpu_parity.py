@@ -95,15 +95,35 @@ def test_effective_field_all_terms(mm, mesh, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("term", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("term", [1, 2, 4, 8, 16, 32, 64])
 def test_each_term(mm, term, prec):
-    mesh = (24, 20, 5, 3e-9, 3e-9, 3e-9) if term == 2 else (18, 21, 1, 2e-9, 2e-9, 1e-9)
+    mesh = (24, 20, 5, 3e-9, 3e-9, 3e-9) if term in (2, 32, 64) else (18, 21, 1, 2e-9, 2e-9, 1e-9)
     m = representable(_rand_m(mesh, 12), DT[prec])
-    plan = mm.Plan(mesh, prec, terms=mm.ALL_TERMS)
+    plan = mm.Plan(mesh, prec, terms=127)
     H = plan.effective_field(gpu_params(mm, PAR, term), to_dev(m, DT[prec]))
     ref = F.effective_field(m, F.Mesh(*mesh), oracle_params(PAR, term), _kernel(mesh))
     err = field_err(H.cpu().numpy(), ref)
     assert err <= TOL[prec], (term, err)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_three_dmi_classes_with_every_term(mm, prec):
+    """All seven term bits at once (interfacial, bulk and D2d DMI sharing D): field,
+    energies (the DMI entry sums the classes) and dm/dt against the oracle."""
+    mesh = (20, 18, 4, 2e-9, 2e-9, 2e-9)
+    m = representable(_rand_m(mesh, 31), DT[prec])
+    plan = mm.Plan(mesh, prec, terms=127)
+    gp = gpu_params(mm, PAR, 127)
+    op = oracle_params(PAR, 127)
+    md = to_dev(m, DT[prec])
+    H = plan.effective_field(gp, md).cpu().numpy()
+    assert field_err(H, F.effective_field(m, F.Mesh(*mesh), op, _kernel(mesh))) <= TOL[prec]
+    k = plan.llg_rhs(gp, md).cpu().numpy()
+    assert field_err(k, F.llg_rhs(m, F.Mesh(*mesh), op, _kernel(mesh))) <= TOL[prec]
+    E = plan.energy(gp, md)
+    ref = F.energies(m, F.Mesh(*mesh), op, _kernel(mesh))
+    tol = 1e-5 if prec == "f32" else 1e-10
+    assert np.all(np.abs(np.ravel(E) - ref) <= tol * np.sum(np.abs(ref))), (E, ref)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
