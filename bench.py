@@ -363,6 +363,25 @@ def copy_reference(torch):
     return {"copy_bytes": COPY_BYTES, "copies": 5}
 
 
+def copy_bandwidth(torch, reps=10):
+    """Attainable HBM bandwidth: a plain 1 GiB device-to-device copy (torch's copy
+    kernel), bytes read + written per second, best of `reps` timed with events."""
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * COPY_BYTES / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return round(best, 1)
+
+
 def _counter_rows(path, full=False):
     """Kernel name -> counter values in dispatch order (full: also the launch
     signature (grid, workgroup, LDS) of each dispatch)."""
@@ -566,6 +585,17 @@ def main():
         cpu, kern = cpu_baseline(inputs, mesh)
         extra["field_rel_err_f32"] = field_error(mm, torch, plan, params, inputs, mesh, kern)
     rl = roofline(res, "thinfilm_f32")
+    # fractions of the attainable bandwidth (a plain copy) next to those of the spec peak
+    cbw = copy_bandwidth(torch)
+    extra["copy_gbs"] = cbw
+    rl["frac_of_copy"] = round(rl["achieved"] / cbw, 4)
+    for key in ("slab3d_f32", "slab3d_f64"):
+        if key in extra:
+            dp = extra[key]["demag_pipeline"]
+            dp["copy_gbs"] = cbw
+            dp["frac_of_copy"] = round(dp["achieved"] / cbw, 4)
+    if "slab3d_f32" in extra:
+        extra["slab3d_f32"]["roofline"]["frac_of_copy"] = round(extra["slab3d_f32"]["roofline"]["achieved"] / cbw, 4)
     line = {
         "metric": METRIC,
         "value": res["cell_evals_per_s"],
