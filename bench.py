@@ -261,9 +261,22 @@ def heun_bench(mm, inputs, torch, steps=100):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         cells = n * n
+        # algorithmic bytes of one step on an N x N x 1 film (FP32): two fused y
+        # passes (spectrum in and out, tensor in), two inverse-x stage kernels
+        # that read the spectrum and write the next input's spectrum, the
+        # stage-1 epilogue (read m, write k1 and m1) and the stage-2 epilogue
+        # (read m1, m, k1; write m): 8 sx + 2 K + 7 x 3wN
+        Px, Py = plan.padded()[:2]
+        Xp = Px // 2 + 1
+        sx = 3 * Xp * n * 8
+        K = 4 * Xp * (Py // 2 + 1) * 4
+        b = 8 * sx + 2 * K + 7 * 3 * 4 * cells
+        gbs = b / (ms / steps * 1e-3) / 1e9
         out[w["name"]] = {"steps": steps, "ms_per_step": ms / steps,
                           "cells_per_s": cells * steps / (ms * 1e-3),
                           "cell_evals_per_s": 2 * cells * steps / (ms * 1e-3),
+                          "alg_bytes_per_step": b, "achieved_gbs": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4),
                           "launch_shapes": plan.shapes()}
         del plan
     return out
