@@ -67,7 +67,7 @@ enum {
 #define MM_TERM_MASK 127u
 
 /* Regular mesh of nx*ny*nz cuboid cells of size dx*dy*dz (paper: FDMesh).
- * Limits: 1 <= n <= 2048 per axis, nx >= 2; d > 0 and finite. */
+ * Limits: 1 <= n <= 1024 per axis, nx >= 2; d > 0 and finite. */
 typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } mm_mesh;
 
 /* Uniform material and field parameters of one instance.

@@ -417,7 +417,7 @@ bool eval_fusable(const GroupSet<T>& gs) {
 
 // Length of the y kernels compiled for one Py (k_ypass_s / k_yinv_s), 0 for
 // the general ones: every group of the pass (3-D groups only for the inverse)
-// has Py = 2 ny = SL for one SL in {256, 512, 1024}, and its tile of columns
+// has Py = 2 ny = SL for one SL in {256, 512, 1024, 2048}, and its tile of columns
 // times SL/16 threads fits a workgroup.  ept: entries per thread and stage,
 // 8 (SL/8 threads a column, the plan without radix 16, p2_radix(.., false,
 // ..), whose LDS padding is the y plan's for these lengths) where the
@@ -431,7 +431,7 @@ int static_y(const GroupSet<T>& gs, bool inv, int& nt, int& ept) {
     const HotPlan<T>& h = gs.h[i];
     if (inv && h.g.nz == 1) continue;
     const int L = h.g.Py;
-    if (L != 2 * h.g.ny || (L != 256 && L != 512 && L != 1024)) return 0;
+    if (L != 2 * h.g.ny || (L != 256 && L != 512 && L != 1024 && L != 2048)) return 0;
     if (sl != 0 && sl != L) return 0;
     sl = L;
     cmax = std::max(cmax, h.g.nz == 1 ? 3 * h.tu.cb_y2 : h.tu.cb_y);
@@ -496,7 +496,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         if (h.g.nz == 1) {
           lb.set(i, y2d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, ((size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) + h.g.Py) * csz +
-                                  (size_t)4 * h.tu.cb_y2 * h.g.Ky * (csz / 2));
+                                  (y2d_tensor_in_lds(h.g) ? (size_t)4 * h.tu.cb_y2 * h.g.Ky * (csz / 2) : 0));
         } else {
           lb.set(i, y3d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);
@@ -514,6 +514,8 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         case 51216: k_ypass_s<T, 512, 16><<<grid, nts, lds, s>>>(lb.L); break;
         case 102408: k_ypass_s<T, 1024, 8><<<grid, nts, lds, s>>>(lb.L); break;
         case 102416: k_ypass_s<T, 1024, 16><<<grid, nts, lds, s>>>(lb.L); break;
+        case 204808: k_ypass_s<T, 2048, 8><<<grid, nts, lds, s>>>(lb.L); break;
+        case 204816: k_ypass_s<T, 2048, 16><<<grid, nts, lds, s>>>(lb.L); break;
         default:
           if (y16) k_ypass<T, true><<<grid, nt, lds, s>>>(lb.L);
           else k_ypass<T, false><<<grid, nt, lds, s>>>(lb.L);
@@ -586,6 +588,8 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
           case 51216: k_yinv_s<T, 512, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
           case 102408: k_yinv_s<T, 1024, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
           case 102416: k_yinv_s<T, 1024, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 204808: k_yinv_s<T, 2048, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
+          case 204816: k_yinv_s<T, 2048, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
           default:
             if (y16) k_yinv<T, true><<<gridy, nty, ldsy, s>>>(ly.L);
             else k_yinv<T, false><<<gridy, nty, ldsy, s>>>(ly.L);

@@ -382,13 +382,14 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   // (nz = 1: one kz plane), both copied while the first stage's loads fly
   Cx<T>* const twl = lds + 3 * CB * cs;
   T* const ktl = reinterpret_cast<T*>(twl + g.Py);
+  const bool ktlds = SL > 0 ? SL <= 1024 : y2d_tensor_in_lds(g);  // the same predicate (Py = SL)
   TableCopy<T, 4> tab;
   tab.issue(hp.fd[1].tw, g.Py, nullptr, 0);
   SegTableCopy<T, 8> ktab;
-  ktab.issue(hp.kt + (size_t)kx0 * g.Ky, (size_t)g.Kz * g.Xp * g.Ky, ncb * g.Ky, 4);
+  if (ktlds) ktab.issue(hp.kt + (size_t)kx0 * g.Ky, (size_t)g.Kz * g.Xp * g.Ky, ncb * g.Ky, 4);
   auto hook = [&]() {
     tab.store(twl);
-    ktab.store(ktl);
+    if (ktlds) ktab.store(ktl);
   };
   const bool half = g.Py == 2 * ny;  // ny inputs / outputs of Py points
   if constexpr (SL > 0)
@@ -399,15 +400,20 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
                                               ColLoad<T>{base, coff, ny}, NoStore<T>{}, hook);
   Cx<T>* const spec = lds;
   const T s = T(ldu(&hp.prm[b].demag_scale));
+  // tensor entry of component a at o = jj Ky + ky (kx0 + jj): from the LDS
+  // rows, or from global memory (component stride Kz Xp Ky)
   const int seg = ncb * g.Ky;
+  const T* const ktg = hp.kt + (size_t)kx0 * g.Ky;
+  const size_t kgs = (size_t)g.Kz * g.Xp * g.Ky;
+  auto kent = [&](int a, int o) -> T { return ktlds ? ktl[a * seg + o] : gld(ktg + a * kgs + o); };
   const FDiv dpy = fdiv_of(g.Py);
   for (int t = threadIdx.x; t < ncb * g.Py; t += blockDim.x) {
     const int jj = fdiv_q(t, dpy), ky = t - mul24(jj, g.Py);
     const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
     const T sy = ky > g.Py - ky ? T(-1) : T(1);
     const int o = jj * g.Ky + kyf;
-    const T kxx = ktl[o] * s, kyy = ktl[seg + o] * s, kzz = ktl[2 * seg + o] * s;
-    const T kxy = ktl[3 * seg + o] * (s * sy);
+    const T kxx = kent(0, o) * s, kyy = kent(1, o) * s, kzz = kent(2, o) * s;
+    const T kxy = kent(3, o) * (s * sy);
     const int p = pidx(ky, SL > 0 ? p2_psh(SL, EPT > 8) : sh);
     Cx<T>& m0 = spec[(0 * ncb + jj) * cs + p];
     Cx<T>& m1 = spec[(1 * ncb + jj) * cs + p];

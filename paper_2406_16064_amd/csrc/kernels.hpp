@@ -62,6 +62,12 @@ template <typename T> struct Epi {
   double a21;
 };
 
+// The fused 2-D y pass stages the tensor rows of its kx columns in LDS up to
+// Py = 1024; longer columns read them from global memory in the product loop,
+// which keeps two workgroups per CU (three 2048-point columns and the twiddle
+// table take 71 KB of LDS).  Host and kernel size the LDS by this predicate.
+__host__ __device__ inline bool y2d_tensor_in_lds(const Geo& g) { return g.Py <= 1024; }
+
 struct Tuning {
   int ty_f;     // rows per workgroup of the forward x pass
   int tpc_f;    // threads per row of its transform

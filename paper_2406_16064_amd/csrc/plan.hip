@@ -342,7 +342,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
   const size_t rowb = (size_t)col_stride(g.Lx) * csz;
   const size_t xtab = (size_t)(2 * g.Lx + 1) * csz;  // twiddle + post tables in LDS
   const size_t ytab = (size_t)g.Py * csz;
-  const size_t ktab2 = (size_t)4 * g.Ky * (csz / 2);  // per kx column of the fused 2-D y pass
+  const size_t ktab2 = y2d_tensor_in_lds(g) ? (size_t)4 * g.Ky * (csz / 2) : 0;  // per kx column of the fused 2-D y pass
   {  // forward x: rows of one component
     const long long rows = 3LL * g.nz * g.ny;
     int ty = 16;
@@ -1317,7 +1317,8 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   const size_t colb = (size_t)col_stride(g.Py) * csz;
   if (g.nz == 1) {
     if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py, true) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
-    if (3 * t.cb_y2 * colb + ytab + (size_t)4 * t.cb_y2 * g.Ky * (csz / 2) > lim) return false;
+    if (3 * t.cb_y2 * colb + ytab + (y2d_tensor_in_lds(g) ? (size_t)4 * t.cb_y2 * g.Ky * (csz / 2) : 0) > lim)
+      return false;
   } else {
     if (t.cb_y < 1 || (t.cb_y % kSxB != 0 && kSxB % t.cb_y != 0) || t.nt_y > 512 || t.tpc_y < tmin(g.Py, true) || t.cb_y * t.tpc_y > t.nt_y)
       return false;

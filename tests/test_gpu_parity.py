@@ -51,6 +51,9 @@ MESHES = [
     (8, 8, 32, 2e-9, 2e-9, 1e-9),      # Pz = 64 = 2 nz: the same in FP32 and FP64
     (1024, 4, 1, 2e-9, 2e-9, 1e-9),    # nx = Lx = 1024: x passes compiled for that length
     (128, 6, 3, 2e-9, 2e-9, 2e-9),     # nx = Lx = 128, 3-D, ragged row tiles
+    (6, 1024, 1, 2e-9, 2e-9, 2e-9),    # Py = 2048: fused 2-D y pass compiled for that length, tensor from global memory
+    (8, 600, 1, 2e-9, 2e-9, 2e-9),     # Py > 1024 with radix-3 stages, the same
+    (4, 1024, 2, 2e-9, 2e-9, 2e-9),    # Py = 2048, 3-D: y passes compiled for that length
 ]
 
 _kern_cache = {}
