@@ -5,8 +5,10 @@ of images with fixed end images, relaxed like LLG with the precession term
 switched off, where each image's effective field keeps only the part
 perpendicular to the tangent set by its neighbours.  It prints no formulas, so
 the following reading is used (parity unpinned physically: the paper prints no
-barrier and several minimum-energy paths are valid; the tests pin only the
-structural invariants listed in tests/test_oracle_neb.py):
+barrier and several minimum-energy paths are valid; the tests pin the
+structural invariants listed in tests/test_oracle_neb.py and the update
+direction, by the first-order energy decrease of an iteration without
+springs):
 
 * distance between images: Euclidean norm over all cells and components;
 * tangent: the energy-weighted "improved tangent" of Henkelman and Jonsson

@@ -10,7 +10,11 @@
 * |m| = 1 after each accepted step; energy never increases under damping
   with a static field, and is conserved to tolerance at alpha = 0;
 * replaying the accepted step sizes reproduces the adaptive run bit for bit;
-* a rejected attempt leaves m untouched.
+* a rejected attempt leaves m untouched;
+* the step-size rule: on a problem with a constant error constant the accepted
+  error settles at 0.9^5 (fixed by the estimate being O(h^5) and the exponent
+  -1/5), a retry after a rejection lands on 0.9^5 too, and an accepted step
+  right after a rejection never grows h.
 """
 import json
 import math
@@ -187,3 +191,63 @@ def test_underflow_raises():
     st = dp45.State(rtol=1e-30, h=1e-13, h_min=1e-16)
     with pytest.raises(dp45.StepUnderflow):
         dp45.run(f, m, st, t_end=1e-9, max_steps=200)
+
+
+def _precession():
+    """Undamped macrospin precessing about H = Hz e_z from m = e_x: a uniform rotation,
+    so the local error constant of every step is the same."""
+    mesh = F.Mesh(1, 1, 1, 1e-9, 1e-9, 1e-9)
+    p = F.Params(Ms=8e5, H=(0, 0, 1e5), alpha=0.0, gamma=GAMMA, terms=F.ZEEMAN)
+    m0 = np.zeros((3, 1, 1, 1))
+    m0[0] = 1.0
+    return (lambda y: F.llg_rhs(y, mesh, p)), m0
+
+
+def test_controller_settles_at_safety_to_the_fifth():
+    """The embedded estimate is O(h^5), so with h_new = h * 0.9 err^(-1/5) the error of
+    the next step on a problem with a constant error constant is 0.9^5 err / err = 0.9^5
+    (an exponent -1/4 would settle at 0.9^4 = 0.656 instead)."""
+    f, m = _precession()
+    st = dp45.State(rtol=1e-8, h=1e-13)
+    errs = []
+    for _ in range(60):
+        m, acc = dp45.step(f, m, st)
+        assert acc  # growing from a small h never overshoots
+        errs.append(st.last_err)
+    assert st.accepted_h[-1] < 0.05 * st.h_max  # the h_max clip plays no part
+    np.testing.assert_allclose(errs[-20:], 0.9 ** 5, rtol=2e-3)
+
+
+def test_rejection_factor_lands_on_the_target_error():
+    """A rejected step retries with h * 0.9 err^(-1/5); in the asymptotic regime the retry
+    then has error 0.9^5 whatever the rejected error was (with -1/4: 0.59 err^(-1/4))."""
+    f, m = _precession()
+    for h0 in (6e-12, 8e-12, 1.1e-11):
+        st = dp45.State(rtol=1e-8, h=h0)
+        m1, acc = dp45.step(f, m.copy(), st)
+        assert not acc and 1.5 < st.last_err < 100.0  # no FAC_MIN clip
+        m1, acc = dp45.step(f, m1, st)
+        assert acc
+        assert abs(st.last_err - 0.9 ** 5) < 0.02
+
+
+def test_no_growth_right_after_a_rejection():
+    """An accepted step right after a rejection never grows h, even where the error
+    factor alone would (here by 2-8%): a stiff linear decay towards e_x started from
+    steps far outside the stability region."""
+    lam = 1e10
+    u = np.zeros((3, 1, 1, 1))
+    u[0] = 1.0
+    f = lambda y: -lam * (y - u)
+    m = np.zeros((3, 1, 1, 1))
+    m[2] = 1.0
+    st = dp45.State(rtol=1e-4, h=1000.0 / lam, h_max=1.0, h_min=1e-30)
+    prev_rejected, binding = False, 0
+    for _ in range(40):
+        m, acc = dp45.step(f, m, st)
+        if acc and prev_rejected:
+            assert st.h <= st.accepted_h[-1]
+            if 0.9 * st.last_err ** -0.2 > 1.02:
+                binding += 1
+        prev_rejected = not acc
+    assert binding >= 2

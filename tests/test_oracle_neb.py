@@ -5,7 +5,9 @@ unpinned".  What is pinned: the tangent rule's case analysis on hand-made
 energies, |t| = 1 and t_i . m_i = 0, the force identity
 G . t = k (d_{n,n+1} - d_{n-1,n}), fixed end images, unit norm after an
 iteration, and that the update is perpendicular to m cell by cell before
-normalisation.
+normalisation.  The update direction is pinned by the first-order energy
+change of a k = 0 iteration: dE = -mu0 Ms V h g (|H_perp|^2 - (H_perp . t)^2),
+which is never positive.
 """
 import numpy as np
 
@@ -60,3 +62,29 @@ def test_force_identities_and_iteration():
     for m in new:
         assert np.max(np.abs(np.linalg.norm(m, axis=0) - 1)) < 1e-14
     np.testing.assert_allclose(E0, E)
+
+
+def test_relaxation_lowers_the_middle_image_energy():
+    """With k = 0 one iteration moves the middle image by h g G_perp (g = alpha gamma /
+    (1 + alpha^2)), so to first order dE = -mu0 Ms V h g sum_i H_i . G_perp,i
+    = -mu0 Ms V h g (|H_perp|^2 - (H_perp . t)^2) <= 0 (t is a unit vector in the
+    cells' tangent planes; Cauchy-Schwarz).  The energy must fall at that rate."""
+    mesh = F.Mesh(5, 4, 1, 2e-9, 2e-9, 1e-9)
+    p = F.Params(Ms=5.8e5, A=1.5e-11, D=3e-3, Ku=5e5, H=(0, 0, 1e5), alpha=0.5)
+    kern = F.DemagKernel(mesh)
+    imgs = _chain(3, seed=4)
+    G, E = neb.neb_force(imgs, mesh, p, kern, 0.0)
+    m = imgs[1]
+    H = F.effective_field(m, mesh, p, kern)
+    t = neb.tangent(imgs[0], m, imgs[2], E[0], E[1], E[2])
+    Hp = H - np.sum(H * m, axis=0, keepdims=True) * m
+    rate = np.sum(Hp * Hp) - np.sum(Hp * t) ** 2
+    assert rate > 0.05 * np.sum(Hp * Hp)  # strictly downhill here
+    g = p.alpha * p.gamma / (1 + p.alpha ** 2)
+    V = mesh.dx * mesh.dy * mesh.dz
+    for h in (1e-16, 1e-17):
+        new, _ = neb.neb_iteration(imgs, mesh, p, kern, 0.0, h)
+        dE = neb.image_energy(new[1], mesh, p, kern) - E[1]
+        want = -F.MU0 * p.Ms * V * h * g * rate
+        assert dE < 0
+        assert abs(dE - want) <= 1e-3 * abs(want)
