@@ -87,6 +87,10 @@ typedef struct {
  * Inputs:  t, h (next step to try), rtol (> 0; also the absolute tolerance,
  *          since |m| = 1), h_min, h_max, fsal_valid (set 0 whenever m was
  *          changed outside the library, which forces a fresh first slope).
+ *          The library also recomputes the first slope by itself when the
+ *          run is on other arrays than the plan's last adaptive run, or when
+ *          a Heun, steepest-descent or autotune call (or a larger batch) has
+ *          reused the plan's stage buffers since.
  * Outputs: t, h, counters, last_err (error norm / rtol of the last attempt),
  *          last_accepted, fsal_valid. */
 typedef struct {
@@ -158,9 +162,9 @@ mm_status mm_rk45_run(mm_plan* plan, const mm_params* params, int32_t batch,
  * finite, > 0; n_steps >= 0).  No error control.  Paper: the integrator of
  * the section "Performance" (N x N x 1 films, demagnetisation + exchange +
  * Zeeman); the projection as in section "LLG equation".  Uses the plan's
- * stage buffers: a later mm_rk45_* call on the plan needs fsal_valid = 0
- * (m changed anyway).  Asynchronous on hip_stream apart from the upload of
- * the step tables. */
+ * stage buffers: a later mm_rk45_* call on the plan recomputes its first
+ * slope, whatever fsal_valid says.  Asynchronous on hip_stream apart from the
+ * upload of the step tables. */
 mm_status mm_heun_run(mm_plan* plan, const mm_params* params, int32_t batch, void* m, double h,
                       int64_t n_steps, void* hip_stream);
 
@@ -174,10 +178,40 @@ mm_status mm_heun_run(mm_plan* plan, const mm_params* params, int32_t batch, voi
  * sums); a quotient that is not finite and positive keeps the previous tau;
  * clipped to [tau_min, tau_max].  Needs 0 < tau_min <= tau0 <= tau_max.
  * tau_out (host, batch doubles, nullable): the last tau.  Uses the plan's
- * stage buffers (a later mm_rk45_* call needs fsal_valid = 0).
+ * stage buffers (a later mm_rk45_* call recomputes its first slope).
  * Synchronises. */
 mm_status mm_sd_run(mm_plan* plan, const mm_params* params, int32_t batch, void* m, int64_t n_iter,
                     double tau0, double tau_min, double tau_max, double* tau_out, void* hip_stream);
+
+/* Relaxation by steepest descent (the iteration of mm_sd_run) that stops on
+ * the largest |dm/dt| (section "Design": the relax task's stopping_dmdt).
+ * Iteration k evaluates H_eff(m_k); its measure is the largest |dm/dt| over
+ * the cells of the LL right-hand side (eq_llg2, the instance's alpha and
+ * gamma) of m_k, in degrees per nanosecond.  An instance whose measure is
+ * below stopping_dmdt (> 0, deg/ns) stops before that iteration's update, with
+ * m = m_k and k updates made; at most max_iter updates (>= 0), followed by one
+ * last check.  iters_out (host, batch int64, nullable): updates made;
+ * dmdt_out (host, batch doubles, nullable): the last measure (deg/ns);
+ * tau_out as for mm_sd_run.  MM_E_MAXSTEPS when some instance ended above the
+ * threshold (iters_out = max_iter; its m is the last iterate).  Uses the
+ * plan's stage buffers.  Synchronises (the host polls every 16 iterations and
+ * returns once every instance has stopped). */
+mm_status mm_sd_relax(mm_plan* plan, const mm_params* params, int32_t batch, void* m, double stopping_dmdt,
+                      int64_t max_iter, double tau0, double tau_min, double tau_max, int64_t* iters_out,
+                      double* dmdt_out, double* tau_out, void* hip_stream);
+
+/* Relaxation by the adaptive Dormand-Prince integration of mm_rk45_run (no
+ * end time) that stops on the largest |dm/dt| (section "Design": the relax
+ * task's stopping_dmdt).  After every accepted step the slope of the new
+ * state (the first-same-as-last slope f(y5), y5 before the projection) gives
+ * the measure, the largest |dm/dt| over the cells in degrees per nanosecond;
+ * an instance stops after the first accepted step whose measure is below
+ * stopping_dmdt (> 0, deg/ns).  At most max_steps attempts per instance
+ * (MM_E_MAXSTEPS otherwise).  st in/out as for mm_rk45_run (t advances);
+ * dmdt_out (host, batch doubles, nullable): the last measure (deg/ns).
+ * Synchronises. */
+mm_status mm_rk45_relax(mm_plan* plan, const mm_params* params, int32_t batch, void* m, mm_rk45_state* st,
+                        double stopping_dmdt, int64_t max_steps, double* dmdt_out, void* hip_stream);
 
 /* Nudged elastic band on a chain of n_img images (n_img <= max_batch, >= 3)
  * stored as images[n_img][3][nz][ny][nx]: n_iter iterations of the

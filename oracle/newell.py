@@ -183,14 +183,32 @@ def tensor(I, J, K, dx, dy, dz):
     return out.reshape(shape + (6,))
 
 
-def tensor_grid(nx, ny, nz, dx, dy, dz):
+def _grid_rows(nx, nz, j0, j1, dx, dy, dz):
+    """Rows J in [j0, j1) of the displacement grid, every I and K: [2nz-1, j1-j0, 2nx-1, 6]."""
+    K, J, I = np.meshgrid(np.arange(-nz + 1, nz), np.arange(j0, j1),
+                          np.arange(-nx + 1, nx), indexing="ij")
+    return tensor(I, J, K, dx, dy, dz)
+
+
+def _grid_rows_star(a):
+    return _grid_rows(*a)
+
+
+def tensor_grid(nx, ny, nz, dx, dy, dz, workers=1):
     """Tensor for every displacement (I,J,K), |I|<nx, |J|<ny, |K|<nz.
 
     Returns an array [2nz-1, 2ny-1, 2nx-1, 6]; index [K+nz-1, J+ny-1, I+nx-1].
+    workers > 1 evaluates bands of J rows in that many processes (every entry is
+    computed on its own, so the result is the same bit for bit).
     """
-    K, J, I = np.meshgrid(np.arange(-nz + 1, nz), np.arange(-ny + 1, ny),
-                          np.arange(-nx + 1, nx), indexing="ij")
-    return tensor(I, J, K, dx, dy, dz)
+    if workers <= 1 or ny < 2:
+        return _grid_rows(nx, nz, -ny + 1, ny, dx, dy, dz)
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    edges = np.linspace(-ny + 1, ny, min(2 * ny - 1, 4 * workers) + 1).round().astype(int)
+    parts = [(nx, nz, int(a), int(b), dx, dy, dz) for a, b in zip(edges[:-1], edges[1:]) if b > a]
+    with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn")) as ex:
+        return np.concatenate(list(ex.map(_grid_rows_star, parts)), axis=1)
 
 
 def as_matrix(t6):

@@ -65,17 +65,22 @@ __global__ void __launch_bounds__(kNT) k_begin(Launch<T> L) {
 // ---------------------------------------------------------------------------
 // g = m x (m x H) per cell (stored) and, when `stats`, per-block FP64 sums of
 // s.s, s.y and y.y with s = m - m_prev, y = g - g_prev (the differences taken
-// in FP64 from the stored values).  Blocks of kNT threads, bpi per instance.
+// in FP64 from the stored values); when `check`, the block's largest |dm/dt|^2
+// of the LL equation (g1 m x H + g2 m x (m x H), the instance's coefficients).
+// part: 4 doubles per block.  Blocks of kNT threads, bpi per instance;
+// instances whose controller says done are skipped.
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_sd_stats(const T* __restrict__ m, const T* __restrict__ H,
                                                   const T* __restrict__ mp, const T* __restrict__ gp,
                                                   T* __restrict__ g, double* __restrict__ part, long long N,
-                                                  int bpi, int stats) {
-  __shared__ double red[3][kNT / 64];
+                                                  int bpi, int stats, int check, const DevParams* __restrict__ prm,
+                                                  const DevCtl* __restrict__ ctl) {
+  __shared__ double red[4][kNT / 64];
   const int b = (int)(blockIdx.x / (unsigned)bpi);
   const int blk = (int)(blockIdx.x - (unsigned)b * (unsigned)bpi);
+  if (ctl && ctl[b].done) return;
   const long long i = (long long)blk * kNT + threadIdx.x;
-  double ss = 0.0, sy = 0.0, yy = 0.0;
+  double ss = 0.0, sy = 0.0, yy = 0.0, kk = 0.0;
   if (i < N) {
     const size_t o = (size_t)b * 3 * N + i;
     const V3<T> mi = ld3(m, N, (long long)o), Hi = ld3(H, N, (long long)o);
@@ -92,31 +97,56 @@ __global__ void __launch_bounds__(kNT) k_sd_stats(const T* __restrict__ m, const
       sy = sx * yx + sy_ * yy_ + sz * yz;
       yy = yx * yx + yy_ * yy_ + yz * yz;
     }
+    if (check) {
+      const T g1 = T(prm[b].g1), g2 = T(prm[b].g2);
+      const double kx = (double)(g1 * f.x + g2 * gi.x), ky = (double)(g1 * f.y + g2 * gi.y);
+      const double kz = (double)(g1 * f.z + g2 * gi.z);
+      kk = kx * kx + ky * ky + kz * kz;
+      if (!(kk <= DBL_MAX)) kk = HUGE_VAL;
+    }
   }
-  if (!stats) return;
-  ss = wave_sum(ss); sy = wave_sum(sy); yy = wave_sum(yy);
+  if (!stats && !check) return;
+  ss = wave_sum(ss); sy = wave_sum(sy); yy = wave_sum(yy); kk = wave_max(kk);
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { red[0][w] = ss; red[1][w] = sy; red[2][w] = yy; }
+  if ((threadIdx.x & 63) == 0) { red[0][w] = ss; red[1][w] = sy; red[2][w] = yy; red[3][w] = kk; }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < 4) {
     double v = 0.0;
-    for (int j = 0; j < kNT / 64; ++j) v += red[threadIdx.x][j];
-    part[((size_t)b * bpi + blk) * 3 + threadIdx.x] = v;
+    for (int j = 0; j < kNT / 64; ++j) v = threadIdx.x == 3 ? fmax(v, red[3][j]) : v + red[threadIdx.x][j];
+    part[((size_t)b * bpi + blk) * 4 + threadIdx.x] = v;
   }
 }
 
 // One 64-thread workgroup per instance: fixed-order sums of the block
-// partials, then the step rule of iteration k >= 1 (odd k: s.s / s.y, even k:
-// s.y / y.y; a quotient that is not finite and positive keeps the previous
-// step) and the clip to [tau_min, tau_max].
+// partials.  With `check` (a relaxation), first the stopping rule: the
+// instance's largest |dm/dt| is recorded, and below its threshold (or at the
+// last iteration, `last`) the instance is done after k updates.  Then the
+// step rule of iteration k >= 1 (odd k: s.s / s.y, even k: s.y / y.y; a
+// quotient that is not finite and positive keeps the previous step) and the
+// clip to [tau_min, tau_max].
 __global__ void __launch_bounds__(64) k_sd_tau(const double* __restrict__ part, int bpi, long long k,
-                                               double* __restrict__ tau, double tau_min, double tau_max) {
+                                               double* __restrict__ tau, double tau_min, double tau_max,
+                                               int check, int last, DevCtl* __restrict__ ctl) {
   const int b = blockIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < bpi; j += 64)
-    for (int q = 0; q < 3; ++q) v[q] += part[((size_t)b * bpi + j) * 3 + q];
+  if (ctl && ctl[b].done) return;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < bpi; j += 64) {
+    for (int q = 0; q < 3; ++q) v[q] += part[((size_t)b * bpi + j) * 4 + q];
+    v[3] = fmax(v[3], part[((size_t)b * bpi + j) * 4 + 3]);
+  }
   for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
+  v[3] = wave_max(v[3]);
   if (threadIdx.x != 0) return;
+  if (check) {
+    const double d = sqrt(v[3]);
+    ctl[b].last_dmdt = d;
+    ctl[b].n_attempt = k;
+    if (d < ctl[b].stop_dmdt || last) {
+      ctl[b].done = 1;
+      return;
+    }
+  }
+  if (k == 0) return;
   const double num = (k & 1) ? v[0] : v[1], den = (k & 1) ? v[1] : v[2];
   double t = num / den;
   if (!(t > 0.0) || !(t <= DBL_MAX)) t = tau[b];
@@ -125,14 +155,16 @@ __global__ void __launch_bounds__(64) k_sd_tau(const double* __restrict__ part, 
 
 // m_prev <- m, g_prev <- g, then the update of the energy-minimisation section:
 // (1 + tau^2 |f|^2 / 4) m' = (1 - tau^2 |f|^2 / 4) m - tau g, f = m x H.
+// Instances whose controller says done keep m.
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_sd_update(T* __restrict__ m, const T* __restrict__ H,
                                                    const T* __restrict__ g, T* __restrict__ mp,
                                                    T* __restrict__ gp, const double* __restrict__ tau, long long N,
-                                                   long long total) {
+                                                   long long total, const DevCtl* __restrict__ ctl) {
   const long long t = (long long)blockIdx.x * kNT + threadIdx.x;
   if (t >= total) return;
   const long long b = t / N, i = t - b * N;
+  if (ctl && ctl[b].done) return;
   const size_t o = (size_t)b * 3 * N + i;
   const V3<T> mi = ld3(m, N, (long long)o), Hi = ld3(H, N, (long long)o), gi = ld3(g, N, (long long)o);
   const V3<T> f = {mi.y * Hi.z - mi.z * Hi.y, mi.z * Hi.x - mi.x * Hi.z, mi.x * Hi.y - mi.y * Hi.x};
@@ -626,12 +658,18 @@ hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s
 
 template <typename T>
 hipError_t launch_sd_iteration(T* m, const T* H, T* g, T* mp, T* gp, double* part, double* tau, int batch,
-                               long long N, long long k, double tau_min, double tau_max, hipStream_t s) {
+                               long long N, long long k, double tau_min, double tau_max, const DevParams* prm,
+                               DevCtl* ctl, bool last, hipStream_t s) {
   const int bpi = (int)((N + kNT - 1) / kNT);
-  k_sd_stats<T><<<dim3((unsigned)(batch * bpi)), kNT, 0, s>>>(m, H, mp, gp, g, part, N, bpi, k > 0 ? 1 : 0);
-  if (k > 0) k_sd_tau<<<dim3((unsigned)batch), 64, 0, s>>>(part, bpi, k, tau, tau_min, tau_max);
-  const long long total = (long long)batch * N;
-  k_sd_update<T><<<dim3((unsigned)((total + kNT - 1) / kNT)), kNT, 0, s>>>(m, H, g, mp, gp, tau, N, total);
+  const int check = ctl ? 1 : 0;
+  k_sd_stats<T><<<dim3((unsigned)(batch * bpi)), kNT, 0, s>>>(m, H, mp, gp, g, part, N, bpi, k > 0 ? 1 : 0, check,
+                                                              prm, ctl);
+  if (k > 0 || check)
+    k_sd_tau<<<dim3((unsigned)batch), 64, 0, s>>>(part, bpi, k, tau, tau_min, tau_max, check, last ? 1 : 0, ctl);
+  if (!last) {
+    const long long total = (long long)batch * N;
+    k_sd_update<T><<<dim3((unsigned)((total + kNT - 1) / kNT)), kNT, 0, s>>>(m, H, g, mp, gp, tau, N, total, ctl);
+  }
   return hipGetLastError();
 }
 
@@ -664,7 +702,8 @@ hipError_t launch_neb(const Geo& g, int n_img, const T* img, T* img_out, const T
   template bool eval_fusable<T>(const GroupSet<T>&);                                              \
   template hipError_t launch_begin<T>(const GroupSet<T>&, const Epi<T>*, hipStream_t);            \
   template hipError_t launch_sd_iteration<T>(T*, const T*, T*, T*, T*, double*, double*, int, long long,   \
-                                             long long, double, double, hipStream_t);                 \
+                                             long long, double, double, const DevParams*, DevCtl*, bool,  \
+                                             hipStream_t);                                             \
   template hipError_t launch_neb<T>(const Geo&, int, const T*, T*, const T*, const double*, double, \
                                     double, double*, double*, double, double, int, hipStream_t);
 MMX_INST(float)

@@ -1174,7 +1174,9 @@ __device__ inline void control_step(DevCtl& C, const double* __restrict__ replay
   }
   const double h = C.h_att;
   const double err = __longlong_as_double((long long)C.err_bits) / C.rtol;
+  const double dmdt = __longlong_as_double((long long)C.dmdt_bits);
   C.err_bits = 0ull;
+  C.dmdt_bits = 0ull;
   C.last_err = err;
   C.n_attempt += 1;
   bool accept;
@@ -1209,6 +1211,13 @@ __device__ inline void control_step(DevCtl& C, const double* __restrict__ replay
   }
   C.pending_finish = accept ? 1 : 0;
   C.last_accepted = accept ? 1 : 0;
+  if (accept && C.stop_dmdt > 0.0) {  // relaxation: the new state's slope is k_7
+    C.last_dmdt = dmdt;
+    if (dmdt < C.stop_dmdt) {
+      C.done = 1;
+      return;
+    }
+  }
   // next attempt
   double hn;
   if (C.replay_n > 0) {
@@ -1406,6 +1415,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   const T* mb = epi.in + (size_t)b * epi.inst_stride;
   double esum[5] = {0, 0, 0, 0, 0};
   double emax = 0.0;
+  double kmax = 0.0;  // MODE_ERROR: largest |k_7|^2 (relaxations)
   // h * coefficients; hlast multiplies the k of this stage (entry nk - 1).
   // Loops over the 7 slots are unrolled so that every index is a constant.
   T hcoef[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -1510,6 +1520,9 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
         double en = sqrt(ex * ex + ey * ey + ez * ez);
         if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
         emax = fmax(emax, en);
+        double kn = (double)kk.x * kk.x + (double)kk.y * kk.y + (double)kk.z * kk.z;
+        if (!(kn <= DBL_MAX)) kn = HUGE_VAL;
+        kmax = fmax(kmax, kn);
       }
     }
     (void)slot;
@@ -1606,23 +1619,35 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if constexpr (MODE == MODE_ERROR) {
+    const bool relax = ldu(&ctl[b].stop_dmdt) > 0.0;
     const double w = wave_max(emax);
     if (lane == 0) red[0][wave] = w;
+    if (relax) {
+      const double wk = wave_max(kmax);
+      if (lane == 0) red[1][wave] = wk;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       double v = red[0][0];
       for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
       const unsigned long long prev = atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
+      unsigned long long prevk = 0ull;
+      if (relax) {
+        double vk = red[1][0];
+        for (int j = 1; j < (int)(blockDim.x >> 6); ++j) vk = fmax(vk, red[1][j]);
+        prevk = atomicMax(&ctl[b].dmdt_bits, (unsigned long long)__double_as_longlong(sqrt(vk)));
+      }
       // the last workgroup of this instance to arrive takes the step decision.
-      // The arrival uses the maximum's returned value (its top bit, always 0
-      // for a non-negative double), so it is issued only once the maximum is
-      // complete; the two atomics are performed where every XCD sees them, so
+      // The arrival uses the maxima's returned values (their top bits, always
+      // 0 for non-negative doubles), so it is issued only once the maxima are
+      // complete; the atomics are performed where every XCD sees them, so
       // no fence (an L2 write-back on this part) is needed.
-      const int inc = 1 + (int)(prev >> 63);
+      const int inc = 1 + (int)(prev >> 63) + (int)(prevk >> 63);
       const int bpi = tiles * g.nz;
       if (atomicAdd(&ctl[b].arrive, inc) == bpi - 1) {
         ctl[b].arrive = 0;
-        ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);  // the complete maximum
+        ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);  // the complete maxima
+        if (relax) ctl[b].dmdt_bits = atomicOr(&ctl[b].dmdt_bits, 0ull);
         control_step(ctl[b], epi.replay);
       }
     }

@@ -145,11 +145,15 @@ hipError_t launch_begin(const GroupSet<T>& gs, const Epi<T>* epis, hipStream_t s
 hipError_t launch_controller(DevCtl* ctl, int n, const double* replay_h, hipStream_t s);
 // One steepest-descent iteration k of `batch` instances after H = H_eff(m):
 // g = m x (m x H), for k >= 1 the Barzilai-Borwein step from the block sums
-// (part: batch x ceil(N / 256) x 3 doubles) into tau[b], then m_prev, g_prev
-// and the update of m.  Arrays [batch][3][N].
+// (part: batch x ceil(N / 256) x 4 doubles) into tau[b], then m_prev, g_prev
+// and the update of m.  Arrays [batch][3][N].  With ctl (a relaxation; prm
+// gives the LL coefficients): first the stopping rule on the largest |dm/dt|
+// of m (ctl[b].stop_dmdt, rad/s), done instances skipped from then on; `last`
+// only checks (no update) and marks every instance done.
 template <typename T>
 hipError_t launch_sd_iteration(T* m, const T* H, T* g, T* mp, T* gp, double* part, double* tau, int batch,
-                               long long N, long long k, double tau_min, double tau_max, hipStream_t s);
+                               long long N, long long k, double tau_min, double tau_max, const DevParams* prm,
+                               DevCtl* ctl, bool last, hipStream_t s);
 
 hipError_t launch_energy_reduce(const double* partial, int batch, int blocks_per_inst, double* out,
                                 hipStream_t s);

@@ -142,6 +142,9 @@ struct DevCtl {
   double h_att;           // step size of the attempt in flight
   double last_err;        // err / rtol of the last attempt
   unsigned long long err_bits;  // running max of ||e_i|| (bits of a non-negative double)
+  double stop_dmdt;       // relaxation: stop once the largest |dm/dt| (rad/s) is below; 0 = off
+  double last_dmdt;       // largest |dm/dt| (rad/s) at the last check
+  unsigned long long dmdt_bits;  // running max of |k_7,i| in the error pass (bits, as err_bits)
   long long n_accept, n_reject, n_attempt, max_attempt;
   long long replay_pos, replay_n;
   int pending_finish;     // 1: the last attempt was accepted and m not yet projected

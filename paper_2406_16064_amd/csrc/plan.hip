@@ -263,6 +263,14 @@ struct Engine {
   // graph cache of the Dormand-Prince attempt sequence
   hipGraphExec_t gexec = nullptr;
   std::vector<const void*> g_key;
+  // The first slopes k1 held in the stage buffers belong to the state arrays of
+  // the last adaptive run (its m pointers and instance counts).  Heun, steepest
+  // descent, the autotuner and a reallocation of the stage buffers overwrite
+  // them and clear k1_ok; a run on other arrays or without k1_ok recomputes k1
+  // whatever the caller's fsal_valid says.
+  std::vector<const void*> k1_key;
+  bool k1_ok = false;
+  std::vector<const void*> batch_who;  // batches: instance arrays of the last run
   // NEB scratch (group 0)
   void* nebH = nullptr;
   void* nebB = nullptr;
@@ -732,19 +740,27 @@ mm_status profile_impl(mm_plan* p, const mm_params* q, int batch, const void* m,
   return time_each_pass<T>(E, gs, epi_slot<T>(E, 0), MODE_RHS, reps, pass_count(E), us, s);
 }
 
-template <typename T>
-mm_status energy_impl(mm_plan* p, const mm_params* q, int batch, const void* m, double* E_out, hipStream_t s) {
-  Engine& E = p->e;
-  MMCHK(single_eval<T>(p, batch, q, m, nullptr, MODE_ENERGY, E.partial, s));
+// Energies from the partial sums `partial` (device, [batch][blocks][5]) of one
+// MODE_ENERGY evaluation: reduce into e5 (device, [batch][5]), copy to the
+// plan's pinned host buffer, scale to joules.
+mm_status energy_finish(Engine& E, const mm_params* q, int batch, const double* partial, double* e5,
+                        double* E_out, hipStream_t s) {
   const Group& G = E.groups[0];
-  HIPCHK(launch_energy_reduce(E.partial, batch, eval_blocks_per_inst(G.g, G.tu), E.e5, s));
-  HIPCHK(hipMemcpyAsync(E.he5, E.e5, sizeof(double) * 5 * batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_energy_reduce(partial, batch, eval_blocks_per_inst(G.g, G.tu), e5, s));
+  HIPCHK(hipMemcpyAsync(E.he5, e5, sizeof(double) * 5 * batch, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int b = 0; b < batch; ++b) {
     const double c = kMu0 * q[b].Ms * G.g.dV;
     for (int k = 0; k < 5; ++k) E_out[5 * b + k] = -(k == 4 ? 1.0 : 0.5) * c * E.he5[5 * b + k];
   }
   return MM_OK;
+}
+
+template <typename T>
+mm_status energy_impl(mm_plan* p, const mm_params* q, int batch, const void* m, double* E_out, hipStream_t s) {
+  Engine& E = p->e;
+  MMCHK(single_eval<T>(p, batch, q, m, nullptr, MODE_ENERGY, E.partial, s));
+  return energy_finish(E, q, batch, E.partial, E.e5, E_out, s);
 }
 
 // --- Dormand-Prince over every group -----------------------------------------
@@ -759,6 +775,7 @@ mm_status ensure_stage(Engine& E, Group& G, int n) {
   if (G.stage && G.stage_cap >= n) return MM_OK;
   if (G.stage) (void)hipFree(G.stage);
   G.stage = nullptr;
+  E.k1_ok = false;
   MMCHK(dev_alloc(&G.stage, sizeof(T) * 9 * (size_t)n * 3 * G.g.N));
   G.stage_cap = n;
   if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
@@ -841,6 +858,7 @@ mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, l
   std::vector<int> grp(batch, 0);
   for (int b = 0; b < batch; ++b) qv[b] = &q[b];
   MMCHK(ensure_stage<T>(E, G, batch));
+  E.k1_ok = false;  // the steps below overwrite the first-slope buffer
   MMCHK(upload_params(E, qv, grp, s));
   GroupSet<T> gs;
   std::vector<int> inst0;
@@ -880,41 +898,68 @@ mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, l
 
 // Steepest descent with Barzilai-Borwein steps, n_iter iterations: H_eff(m)
 // by a field evaluation (epilogue slot 4), then launch_sd_iteration.  Buffers:
-// stage 4 = H, 5 = g, 6 = m_prev, 7 = g_prev (a later adaptive call needs
-// fsal_valid = 0).  tau_out (host, nullable): the last step size of each
-// instance.  Synchronises.
+// stage 4 = H, 5 = g, 6 = m_prev, 7 = g_prev.  tau_out (host, nullable): the
+// last step size of each instance.  stop > 0 (rad/s): a relaxation -- each
+// iteration first checks the largest |dm/dt| of its m, instances below stop
+// are done (their later launches return at once), and one last check follows
+// the n_iter-th update; the host polls the controllers every kPollSd
+// iterations and ends early once every instance is done.  iters_out /
+// dmdt_out (host, nullable): updates made and the last largest |dm/dt|
+// (rad/s).  Synchronises.
+constexpr long long kPollSd = 16;
+
 template <typename T>
 mm_status sd_impl(mm_plan* p, const mm_params* q, int batch, T* m, long long n_iter, double tau0, double tau_min,
-                  double tau_max, double* tau_out, hipStream_t s) {
+                  double tau_max, double* tau_out, double stop, long long* iters_out, double* dmdt_out,
+                  hipStream_t s) {
   Engine& E = p->e;
   Group& G = E.groups[0];
+  const bool relax = stop > 0.0;
   std::vector<const mm_params*> qv(batch);
   std::vector<int> grp(batch, 0);
   for (int b = 0; b < batch; ++b) qv[b] = &q[b];
   MMCHK(ensure_stage<T>(E, G, batch));
+  E.k1_ok = false;  // stage buffers 4..7 hold the iteration's vectors (k3..k6 of an adaptive run)
   MMCHK(upload_params(E, qv, grp, s));
   GroupSet<T> gs;
   std::vector<int> inst0;
   MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
+  DevCtl* const ctl = relax ? E.ctl + inst0[0] : nullptr;
+  if (relax) {
+    for (int b = 0; b < batch; ++b) {
+      std::memset(&E.hctl[b], 0, sizeof(DevCtl));
+      E.hctl[b].stop_dmdt = stop;
+    }
+    HIPCHK(hipMemcpyAsync(ctl, E.hctl, sizeof(DevCtl) * batch, hipMemcpyHostToDevice, s));
+  }
   T* const H = stage_buf<T>(G, 4);
   Epi<T> e = epi_base<T>(G, MODE_FIELD);
   e.in = m;
   e.out = H;
+  e.ctl = ctl;
   MMCHK(upload_epis<T>(E, 4, std::vector<Epi<T>>{e}, s));
   const long long N = G.g.N;
   const size_t bpi = (size_t)((N + 255) / 256);
   double* part = nullptr;
   double* tau = nullptr;
-  MMCHK(dev_alloc((void**)&part, sizeof(double) * 3 * bpi * batch));
+  MMCHK(dev_alloc((void**)&part, sizeof(double) * 4 * bpi * batch));
   mm_status st = dev_alloc((void**)&tau, sizeof(double) * batch);
   std::vector<double> t0(batch, tau0);
   hipError_t er = st == MM_OK ? hipMemcpyAsync(tau, t0.data(), sizeof(double) * batch, hipMemcpyHostToDevice, s)
                               : hipSuccess;
-  for (long long k = 0; st == MM_OK && er == hipSuccess && k < n_iter; ++k) {
+  const long long n_launch = relax ? n_iter + 1 : n_iter;
+  for (long long k = 0; st == MM_OK && er == hipSuccess && k < n_launch; ++k) {
     er = launch_eval<T>(gs, epi_slot<T>(E, 4), MODE_FIELD, demag_on(E), s);
     if (er == hipSuccess)
       er = launch_sd_iteration<T>(m, H, stage_buf<T>(G, 5), stage_buf<T>(G, 6), stage_buf<T>(G, 7), part, tau,
-                                  batch, N, k, tau_min, tau_max, s);
+                                  batch, N, k, tau_min, tau_max, E.prm + inst0[0], ctl, relax && k == n_iter, s);
+    if (relax && er == hipSuccess && (k + 1) % kPollSd == 0 && k + 1 < n_launch) {
+      er = hipMemcpyAsync(E.hctl, ctl, sizeof(DevCtl) * batch, hipMemcpyDeviceToHost, s);
+      if (er == hipSuccess) er = hipStreamSynchronize(s);
+      bool all = er == hipSuccess;
+      for (int b = 0; b < batch && all; ++b) all = E.hctl[b].done != 0;
+      if (all) break;
+    }
   }
   {  // the buffers are freed below: nothing may still use them
     const hipError_t es = hipStreamSynchronize(s);
@@ -922,10 +967,20 @@ mm_status sd_impl(mm_plan* p, const mm_params* q, int batch, T* m, long long n_i
   }
   if (st == MM_OK && er == hipSuccess && tau_out) er = hipMemcpy(tau_out, tau, sizeof(double) * batch,
                                                                  hipMemcpyDeviceToHost);
+  if (st == MM_OK && er == hipSuccess && relax) er = hipMemcpy(E.hctl, ctl, sizeof(DevCtl) * batch,
+                                                               hipMemcpyDeviceToHost);
   if (st == MM_OK && er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
   (void)hipFree(part);
   if (tau) (void)hipFree(tau);
-  return st;
+  if (st != MM_OK || !relax) return st;
+  bool all_stopped = true;
+  for (int b = 0; b < batch; ++b) {
+    if (iters_out) iters_out[b] = E.hctl[b].n_attempt;
+    if (dmdt_out) dmdt_out[b] = E.hctl[b].last_dmdt;
+    all_stopped = all_stopped && E.hctl[b].last_dmdt < stop;
+  }
+  if (!all_stopped) return fail(MM_E_MAXSTEPS, "relaxation: the largest |dm/dt| stayed above the threshold");
+  return MM_OK;
 }
 
 // Timing of the kernels of one adaptive attempt (measurement aid): us[0] the
@@ -1001,7 +1056,7 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
                    const std::vector<const mm_params*>& q, std::vector<mm_rk45_state*>& st,
                    const std::vector<double>& t_end, long long max_steps, const double* replay_h,
                    long long n_replay, bool single, std::vector<int>& status, hipStream_t s,
-                   StepProfile* prof = nullptr) {
+                   StepProfile* prof = nullptr, double stop = 0.0) {
   const int ng = (int)E.groups.size();
   const int n_total = (int)q.size();
   std::vector<int> grp;
@@ -1011,7 +1066,12 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
   GroupSet<T> gs;
   std::vector<int> inst0;
   MMCHK(make_set<T>(E, nb, gs, inst0, s));
-  bool need_k1 = false;
+  std::vector<const void*> k1_key;
+  for (int i = 0; i < ng; ++i) {
+    k1_key.push_back(m[i]);
+    k1_key.push_back((const void*)(intptr_t)nb[i]);
+  }
+  bool need_k1 = !E.k1_ok || E.k1_key != k1_key;
   for (int b = 0; b < n_total; ++b) {
     const mm_rk45_state& r = *st[b];
     if (!(r.rtol > 0) || !is_fin(r.rtol) || !(r.h > 0) || !(r.h_min > 0) || !(r.h_max >= r.h_min) ||
@@ -1040,6 +1100,7 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
     c.t_end = replay_h ? HUGE_VAL : t_end[b];
     c.n_accept = r.n_accept; c.n_reject = r.n_reject;
     c.max_attempt = max_steps;
+    c.stop_dmdt = stop;
     c.replay_n = replay_h ? n_replay : 0;
     if (replay_h) {
       c.h_att = replay_h[0];
@@ -1053,9 +1114,12 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
   MMCHK(upload_step_epis<T>(E, m, inst0, s));
   long long extra_rhs = 0;
   if (need_k1) {
+    E.k1_ok = false;
     HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 1), MODE_RHS, demag_on(E), s));
     extra_rhs = 1;
   }
+  E.k1_ok = true;  // k1 of these arrays from here on (the finishing step keeps it so)
+  E.k1_key = k1_key;
   if (prof) return profile_step<T>(E, gs, *prof, s);
   if (single) {
     MMCHK(enqueue_attempt<T>(E, gs, n_total, s));
@@ -1153,7 +1217,7 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
 template <typename T>
 mm_status plan_rk45(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45_state* st, double t_end,
                     long long max_steps, const double* replay_h, long long n_replay, bool single, hipStream_t s,
-                    StepProfile* prof = nullptr) {
+                    StepProfile* prof = nullptr, double stop = 0.0) {
   std::vector<const mm_params*> qv(batch);
   std::vector<mm_rk45_state*> sv(batch);
   for (int b = 0; b < batch; ++b) {
@@ -1162,7 +1226,8 @@ mm_status plan_rk45(mm_plan* p, const mm_params* q, int batch, void* mv, mm_rk45
   }
   std::vector<int> status;
   return run_core<T>(p->e, std::vector<T*>{(T*)mv}, std::vector<int>{batch}, qv, sv,
-                     std::vector<double>(batch, t_end), max_steps, replay_h, n_replay, single, status, s, prof);
+                     std::vector<double>(batch, t_end), max_steps, replay_h, n_replay, single, status, s, prof,
+                     stop);
 }
 
 template <typename T>
@@ -1194,13 +1259,19 @@ mm_status batch_run(mm_batch* bt, mm_instance* inst, int n, long long max_steps,
   std::vector<mm_rk45_state*> st;
   std::vector<double> t_end;
   std::vector<int> order;
+  std::vector<const void*> who;  // the instances' own arrays, in group order
   for (int g = 0; g < ng; ++g)
     for (int i : members[g]) {
       q.push_back(&inst[i].p);
       st.push_back(&inst[i].st);
       t_end.push_back(inst[i].t_end);
       order.push_back(i);
+      who.push_back(inst[i].m);
     }
+  // the group buffers are the same for every run: the first slopes they hold
+  // belong to the instances of the last run only
+  if (who != E.batch_who) E.k1_ok = false;
+  E.batch_who = who;
   std::vector<int> status;
   mm_status r = run_core<T>(E, m, nb, q, st, t_end, max_steps, nullptr, 0, false, status, s);
   // scatter back (also after an integration error: m holds the last accepted state)
@@ -1438,6 +1509,7 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
     (void)last;
   }
   G.tu = best;
+  E.k1_ok = false;  // the timing runs' stages used the stage buffers for its own state
   MMCHK(engine_reserve(E, std::vector<int>{p->maxb}));
   if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
   return MM_OK;
@@ -1579,8 +1651,55 @@ mm_status mm_sd_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, int6
   if (!(tau_min > 0) || !is_fin(tau_max) || !(tau_min <= tau0) || !(tau0 <= tau_max))
     return fail(MM_E_ARG, "need 0 < tau_min <= tau0 <= tau_max (finite)");
   hipStream_t s = (hipStream_t)hip_stream;
-  return p->e.prec == MM_F32 ? sd_impl<float>(p, q, batch, (float*)m, n_iter, tau0, tau_min, tau_max, tau_out, s)
-                             : sd_impl<double>(p, q, batch, (double*)m, n_iter, tau0, tau_min, tau_max, tau_out, s);
+  return p->e.prec == MM_F32
+             ? sd_impl<float>(p, q, batch, (float*)m, n_iter, tau0, tau_min, tau_max, tau_out, 0.0, nullptr, nullptr, s)
+             : sd_impl<double>(p, q, batch, (double*)m, n_iter, tau0, tau_min, tau_max, tau_out, 0.0, nullptr, nullptr,
+                               s);
+}
+
+// stopping_dmdt in degrees per nanosecond -> rad/s
+static double dmdt_rad_s(double deg_ns) { return deg_ns * (M_PI / 180.0) * 1e9; }
+
+mm_status mm_sd_relax(mm_plan* p, const mm_params* q, int32_t batch, void* m, double stopping_dmdt, int64_t max_iter,
+                      double tau0, double tau_min, double tau_max, int64_t* iters_out, double* dmdt_out,
+                      double* tau_out, void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch));
+  if (!m) return fail(MM_E_ARG, "null array");
+  if (!(stopping_dmdt > 0) || !is_fin(stopping_dmdt)) return fail(MM_E_ARG, "stopping_dmdt must be finite and > 0");
+  if (max_iter < 0) return fail(MM_E_ARG, "max_iter must be >= 0");
+  if (!(tau_min > 0) || !is_fin(tau_max) || !(tau_min <= tau0) || !(tau0 <= tau_max))
+    return fail(MM_E_ARG, "need 0 < tau_min <= tau0 <= tau_max (finite)");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<long long> it(batch, 0);
+  std::vector<double> dm(batch, 0.0);
+  const double stop = dmdt_rad_s(stopping_dmdt);
+  mm_status r = p->e.prec == MM_F32
+                    ? sd_impl<float>(p, q, batch, (float*)m, max_iter, tau0, tau_min, tau_max, tau_out, stop, it.data(),
+                                     dm.data(), s)
+                    : sd_impl<double>(p, q, batch, (double*)m, max_iter, tau0, tau_min, tau_max, tau_out, stop,
+                                      it.data(), dm.data(), s);
+  if (r == MM_OK || r == MM_E_MAXSTEPS)
+    for (int b = 0; b < batch; ++b) {
+      if (iters_out) iters_out[b] = it[b];
+      if (dmdt_out) dmdt_out[b] = dm[b] / dmdt_rad_s(1.0);
+    }
+  return r;
+}
+
+mm_status mm_rk45_relax(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm_rk45_state* st,
+                        double stopping_dmdt, int64_t max_steps, double* dmdt_out, void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch));
+  if (!m || !st) return fail(MM_E_ARG, "null array");
+  if (!(stopping_dmdt > 0) || !is_fin(stopping_dmdt)) return fail(MM_E_ARG, "stopping_dmdt must be finite and > 0");
+  if (max_steps < 1) return fail(MM_E_ARG, "max_steps must be >= 1");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const double stop = dmdt_rad_s(stopping_dmdt);
+  mm_status r = p->e.prec == MM_F32
+                    ? plan_rk45<float>(p, q, batch, m, st, HUGE_VAL, max_steps, nullptr, 0, false, s, nullptr, stop)
+                    : plan_rk45<double>(p, q, batch, m, st, HUGE_VAL, max_steps, nullptr, 0, false, s, nullptr, stop);
+  if (dmdt_out && (r == MM_OK || r == MM_E_MAXSTEPS))
+    for (int b = 0; b < batch; ++b) dmdt_out[b] = p->e.hctl[b].last_dmdt / dmdt_rad_s(1.0);
+  return r;
 }
 
 mm_status mm_heun_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, double h, int64_t n_steps,

@@ -67,6 +67,8 @@ _sigs = {
     "mm_neb_run": [_vp, _P(Params), _vp, _i32, _dbl, _dbl, _i64, _P(_dbl), _vp],
     "mm_heun_run": [_vp, _P(Params), _i32, _vp, _dbl, _i64, _vp],
     "mm_sd_run": [_vp, _P(Params), _i32, _vp, _i64, _dbl, _dbl, _dbl, _P(_dbl), _vp],
+    "mm_sd_relax": [_vp, _P(Params), _i32, _vp, _dbl, _i64, _dbl, _dbl, _dbl, _P(_i64), _P(_dbl), _P(_dbl), _vp],
+    "mm_rk45_relax": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _vp],
     "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
     "mm_profile_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _i32, _P(_dbl), _P(_i32), _P(_i32), _vp],
     "mm_plan_autotune": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
@@ -225,6 +227,30 @@ class Plan:
         _check(_lib.mm_sd_run(self._h, _params_array(params), nb, _ptr(m), n_iter, tau0, tau_min, tau_max, tau,
                               _stream(stream)), "mm_sd_run")
         return np.array(tau[:])
+
+    def sd_relax(self, params, m, stopping_dmdt, max_iter, tau0, tau_min, tau_max, stream=None, check=True):
+        """Steepest descent until the largest |dm/dt| (deg/ns) is below stopping_dmdt (mm_sd_relax).
+        Returns (status, iterations, last measures in deg/ns, last taus) per instance arrays."""
+        nb = self._batch(m)
+        it = (ctypes.c_int64 * nb)()
+        dm = (ctypes.c_double * nb)()
+        tau = (ctypes.c_double * nb)()
+        st = _lib.mm_sd_relax(self._h, _params_array(params), nb, _ptr(m), stopping_dmdt, max_iter, tau0, tau_min,
+                              tau_max, it, dm, tau, _stream(stream))
+        if check:
+            _check(st, "mm_sd_relax")
+        return st, np.array(it[:]), np.array(dm[:]), np.array(tau[:])
+
+    def rk45_relax(self, params, m, states, stopping_dmdt, max_steps=10 ** 9, stream=None, check=True):
+        """Adaptive Dormand-Prince until the largest |dm/dt| (deg/ns) after an accepted step is below
+        stopping_dmdt (mm_rk45_relax).  Returns (status, last measures in deg/ns)."""
+        nb = self._batch(m)
+        dm = (ctypes.c_double * nb)()
+        st = _lib.mm_rk45_relax(self._h, _params_array(params), nb, _ptr(m), states, stopping_dmdt, max_steps, dm,
+                                _stream(stream))
+        if check:
+            _check(st, "mm_rk45_relax")
+        return st, np.array(dm[:])
 
     def neb_run(self, params, images, k_spring, h, n_iter, stream=None):
         n_img = images.shape[0]

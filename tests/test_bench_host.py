@@ -131,3 +131,24 @@ def test_ingest_scales_by_copy_and_keeps_shapes_read_in_both_runs(tmp_path, monk
     assert st["bytes_per_launch"] == 10 * 1024 * 2 + 7 * 1024
     # the shape only the fetch run saw has no record (its write bytes are unknown)
     assert list(st["by_launch"]) == ["grid 100, workgroup 50, LDS 0"]
+
+
+def test_demag_pipeline_counts_every_pass_of_an_evaluation():
+    """The pipeline figure covers the inverse-x complex-to-real pass too (with its
+    fused epilogue), not only the forward transforms, the product and inverse y."""
+    names = bench.pass_names(16)
+    res = {"passes": [{"kernel": n, "us": 1.0 + i, "alg_bytes": 1000 * (i + 1)} for i, n in enumerate(names)]}
+    dp = bench.demag_pipeline(res)
+    assert list(dp["passes"]) == names and "x_inv_fused_llg" in dp["passes"]
+    assert dp["alg_bytes"] == 15000 and dp["us"] == 15.0
+    assert dp["frac"] == round(15000 / 15e-6 / 1e9 / 8000.0, 4)
+
+
+def test_tuned_table_round_trip(tmp_path):
+    from paper_2406_16064_amd import tuned
+    path = str(tmp_path / "t.json")
+    assert tuned.lookup((512, 512, 16), "f32", path) is None
+    sh = {"ty_f": 4, "nt_f": 256, "cb_y": 4, "tpc_y": 64, "nt_y": 256, "ty_x": 4, "nt_i": 512}
+    tuned.store((512, 512, 16, 5e-9, 5e-9, 5e-9), "f32", sh, path)
+    assert tuned.lookup((512, 512, 16), "f32", path) == sh
+    assert tuned.lookup((512, 512, 16), "f64", path) is None

@@ -283,6 +283,32 @@ def test_heun_batch_of_different_parameters_fp64(mm):
         assert np.max(np.linalg.norm(md[b].cpu().numpy() - mo, axis=0)) <= 1e-10
 
 
+def test_first_slope_recomputed_after_heun(mm):
+    """Adaptive steps, then Heun steps (which reuse the plan's stage buffers), then
+    adaptive steps again with the state of the first run (fsal_valid = 1): the
+    second run must start from a fresh first slope, as the oracle does, FP64."""
+    mesh = (24, 20, 1, 2e-9, 2e-9, 1e-9)
+    m0 = inputs.random_unit(*mesh[:3], np.random.default_rng(12))
+    op = oracle_params(PAR, F.ALL_TERMS)
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+    ost = dp45.State(rtol=1e-6)
+    mo = dp45.run(f, m0.copy(), ost, max_accept=5)
+    h1 = list(ost.accepted_h)
+    mo = heun.run(f, mo, 2e-14, 3)
+    ost.k1 = None  # m changed outside the integrator
+    mo = dp45.run(f, mo, ost, max_accept=10)
+    h2 = ost.accepted_h[5:]
+    plan = mm.Plan(mesh, "f64", terms=F.ALL_TERMS)
+    gp = gpu_params(mm, PAR, F.ALL_TERMS)
+    md = to_dev(m0, torch.float64)
+    st = mm.new_states(1, rtol=1e-6)
+    plan.rk45_run(gp, md, st, replay_h=h1)
+    assert st[0].fsal_valid == 1
+    plan.heun_run(gp, md, 2e-14, 3)
+    plan.rk45_run(gp, md, st, replay_h=h2)
+    assert np.max(np.abs(md.cpu().numpy() - mo)) <= 1e-9
+
+
 SD_MESHES = [(12, 10, 1, 2e-9, 2e-9, 2e-9), (20, 16, 3, 3e-9, 3e-9, 3e-9)]
 SD_PAR = dict(Ms=5.8e5, A=1.5e-11, D=3e-3, Ku=8e5, u=(0, 0, 1), H=(1e4, 0.0, 1e5), alpha=0.5)
 
