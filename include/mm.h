@@ -183,6 +183,22 @@ mm_status mm_heun_run(mm_plan* plan, const mm_params* params, int32_t batch, voi
 mm_status mm_sd_run(mm_plan* plan, const mm_params* params, int32_t batch, void* m, int64_t n_iter,
                     double tau0, double tau_min, double tau_max, double* tau_out, void* hip_stream);
 
+/* mm_sd_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same iteration, kernels and results, but the per-call scratch that mm_sd_run
+ * allocates and frees (FP64 partial sums, 4 per 256 cells per instance, and
+ * the step sizes) comes from a fixed 16 MiB array in device memory that every
+ * GPU the library runs on holds until the process ends.  This call allocates
+ * nothing: MM_E_ARG when the batch needs more scratch than that
+ * (32 * ceil(nx ny nz / 256) * batch bytes, rounded up to 256, plus 8 * batch;
+ * e.g. 16 instances of 512 x 512 x 16 cells), MM_E_STATE when the plan's stage
+ * buffers do not yet hold `batch` instances (one earlier mm_sd_run,
+ * mm_heun_run or mm_rk45_* call on the plan with at least `batch` instances
+ * allocates them).  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (other streams or host threads) race.  Synchronises. */
+mm_status mm_sd_run_noalloc(mm_plan* plan, const mm_params* params, int32_t batch, void* m, int64_t n_iter,
+                            double tau0, double tau_min, double tau_max, double* tau_out, void* hip_stream);
+
 /* Relaxation by steepest descent (the iteration of mm_sd_run) that stops on
  * the largest |dm/dt| (section "Design": the relax task's stopping_dmdt).
  * Iteration k evaluates H_eff(m_k); its measure is the largest |dm/dt| over

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -908,13 +909,27 @@ mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, l
 // (rad/s).  Synchronises.
 constexpr long long kPollSd = 16;
 
+// Bytes of per-call scratch of sd_impl for `batch` instances of G: the block
+// partial sums (4 doubles per block), padded to 256 bytes, then the step sizes.
+size_t sd_part_bytes(const Group& G, int batch) {
+  const size_t bpi = (size_t)((G.g.N + 255) / 256);
+  return (sizeof(double) * 4 * bpi * batch + 255) / 256 * 256;
+}
+size_t sd_scratch_bytes(const Group& G, int batch) { return sd_part_bytes(G, batch) + sizeof(double) * batch; }
+
+// ext (device, nullable): caller-provided scratch of sd_scratch_bytes(G, batch)
+// bytes; then nothing is allocated or freed, and the stage buffers must already
+// hold `batch` instances (MM_E_STATE otherwise).
 template <typename T>
 mm_status sd_impl(mm_plan* p, const mm_params* q, int batch, T* m, long long n_iter, double tau0, double tau_min,
                   double tau_max, double* tau_out, double stop, long long* iters_out, double* dmdt_out,
-                  hipStream_t s) {
+                  hipStream_t s, unsigned char* ext = nullptr) {
   Engine& E = p->e;
   Group& G = E.groups[0];
   const bool relax = stop > 0.0;
+  if (ext && !(G.stage && G.stage_cap >= batch))
+    return fail(MM_E_STATE, "the plan's stage buffers do not hold this batch yet: one mm_sd_run, mm_heun_run or "
+                            "mm_rk45_* call with at least as many instances allocates them");
   std::vector<const mm_params*> qv(batch);
   std::vector<int> grp(batch, 0);
   for (int b = 0; b < batch; ++b) qv[b] = &q[b];
@@ -942,8 +957,14 @@ mm_status sd_impl(mm_plan* p, const mm_params* q, int batch, T* m, long long n_i
   const size_t bpi = (size_t)((N + 255) / 256);
   double* part = nullptr;
   double* tau = nullptr;
-  MMCHK(dev_alloc((void**)&part, sizeof(double) * 4 * bpi * batch));
-  mm_status st = dev_alloc((void**)&tau, sizeof(double) * batch);
+  mm_status st = MM_OK;
+  if (ext) {
+    part = (double*)ext;
+    tau = (double*)(ext + sd_part_bytes(G, batch));
+  } else {
+    MMCHK(dev_alloc((void**)&part, sizeof(double) * 4 * bpi * batch));
+    st = dev_alloc((void**)&tau, sizeof(double) * batch);
+  }
   std::vector<double> t0(batch, tau0);
   hipError_t er = st == MM_OK ? hipMemcpyAsync(tau, t0.data(), sizeof(double) * batch, hipMemcpyHostToDevice, s)
                               : hipSuccess;
@@ -970,8 +991,10 @@ mm_status sd_impl(mm_plan* p, const mm_params* q, int batch, T* m, long long n_i
   if (st == MM_OK && er == hipSuccess && relax) er = hipMemcpy(E.hctl, ctl, sizeof(DevCtl) * batch,
                                                                hipMemcpyDeviceToHost);
   if (st == MM_OK && er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
-  (void)hipFree(part);
-  if (tau) (void)hipFree(tau);
+  if (!ext) {
+    (void)hipFree(part);
+    if (tau) (void)hipFree(tau);
+  }
   if (st != MM_OK || !relax) return st;
   bool all_stopped = true;
   for (int b = 0; b < batch; ++b) {
@@ -1523,6 +1546,36 @@ mm_status plan_checks(mm_plan* p, const mm_params* q, int batch) {
 
 }  // namespace
 
+// --- allocation-free steepest descent ---------------------------------------
+// mm_sd_run allocates its per-block partial sums and step sizes on every call;
+// mm_sd_run_noalloc takes them from `scratch`, a fixed array in device memory
+// of kScratchBytes.  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code the array's name is not a device address: the
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current, and only that address is passed to kernels and copies.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+namespace {
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_at[kScratchDevices] = {};
+
+mm_status scratch_address(unsigned char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(MM_E_HIP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(MM_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_at[dev] = (unsigned char*)ptr;
+  }
+  *out = g_scratch_at[dev];
+  return MM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* mm_status_string(mm_status s) {
@@ -1655,6 +1708,27 @@ mm_status mm_sd_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, int6
              ? sd_impl<float>(p, q, batch, (float*)m, n_iter, tau0, tau_min, tau_max, tau_out, 0.0, nullptr, nullptr, s)
              : sd_impl<double>(p, q, batch, (double*)m, n_iter, tau0, tau_min, tau_max, tau_out, 0.0, nullptr, nullptr,
                                s);
+}
+
+mm_status mm_sd_run_noalloc(mm_plan* p, const mm_params* q, int32_t batch, void* m, int64_t n_iter, double tau0,
+                            double tau_min, double tau_max, double* tau_out, void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch));
+  if (!m) return fail(MM_E_ARG, "null array");
+  if (n_iter < 0) return fail(MM_E_ARG, "n_iter must be >= 0");
+  if (!(tau_min > 0) || !is_fin(tau_max) || !(tau_min <= tau0) || !(tau0 <= tau_max))
+    return fail(MM_E_ARG, "need 0 < tau_min <= tau0 <= tau_max (finite)");
+  const size_t need = sd_scratch_bytes(p->e.groups[0], batch);
+  if (need > kScratchBytes)
+    return fail(MM_E_ARG, "mm_sd_run_noalloc needs " + std::to_string(need) + " bytes of scratch for this batch; "
+                          "the fixed scratch holds " + std::to_string(kScratchBytes));
+  unsigned char* ptr = nullptr;
+  MMCHK(scratch_address(&ptr));
+  hipStream_t s = (hipStream_t)hip_stream;
+  return p->e.prec == MM_F32
+             ? sd_impl<float>(p, q, batch, (float*)m, n_iter, tau0, tau_min, tau_max, tau_out, 0.0, nullptr, nullptr, s,
+                              ptr)
+             : sd_impl<double>(p, q, batch, (double*)m, n_iter, tau0, tau_min, tau_max, tau_out, 0.0, nullptr, nullptr,
+                               s, ptr);
 }
 
 // stopping_dmdt in degrees per nanosecond -> rad/s

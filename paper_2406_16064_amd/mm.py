@@ -67,6 +67,7 @@ _sigs = {
     "mm_neb_run": [_vp, _P(Params), _vp, _i32, _dbl, _dbl, _i64, _P(_dbl), _vp],
     "mm_heun_run": [_vp, _P(Params), _i32, _vp, _dbl, _i64, _vp],
     "mm_sd_run": [_vp, _P(Params), _i32, _vp, _i64, _dbl, _dbl, _dbl, _P(_dbl), _vp],
+    "mm_sd_run_noalloc": [_vp, _P(Params), _i32, _vp, _i64, _dbl, _dbl, _dbl, _P(_dbl), _vp],
     "mm_sd_relax": [_vp, _P(Params), _i32, _vp, _dbl, _i64, _dbl, _dbl, _dbl, _P(_i64), _P(_dbl), _P(_dbl), _vp],
     "mm_rk45_relax": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _vp],
     "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
@@ -227,6 +228,17 @@ class Plan:
         _check(_lib.mm_sd_run(self._h, _params_array(params), nb, _ptr(m), n_iter, tau0, tau_min, tau_max, tau,
                               _stream(stream)), "mm_sd_run")
         return np.array(tau[:])
+
+    def sd_run_noalloc(self, params, m, n_iter, tau0, tau_min, tau_max, stream=None, check=True):
+        """sd_run without device allocation (mm_sd_run_noalloc: the library's fixed scratch).
+        Returns (status, last tau per instance)."""
+        nb = self._batch(m)
+        tau = (ctypes.c_double * nb)()
+        st = _lib.mm_sd_run_noalloc(self._h, _params_array(params), nb, _ptr(m), n_iter, tau0, tau_min, tau_max,
+                                    tau, _stream(stream))
+        if check:
+            _check(st, "mm_sd_run_noalloc")
+        return st, np.array(tau[:])
 
     def sd_relax(self, params, m, stopping_dmdt, max_iter, tau0, tau_min, tau_max, stream=None, check=True):
         """Steepest descent until the largest |dm/dt| (deg/ns) is below stopping_dmdt (mm_sd_relax).

@@ -68,4 +68,5 @@ def test_invalid_arguments_rejected_before_hip(mm):
     assert lib.mm_neb_run(None, None, None, 3, 1e5, 1e-14, 1, None, None) == mm.MM_E_ARG
     assert lib.mm_heun_run(None, None, 1, None, 1e-13, 1, None) == mm.MM_E_ARG
     assert lib.mm_sd_run(None, None, 1, None, 1, 1e-7, 1e-9, 1e-3, None, None) == mm.MM_E_ARG
+    assert lib.mm_sd_run_noalloc(None, None, 1, None, 1, 1e-7, 1e-9, 1e-3, None, None) == mm.MM_E_ARG
     assert lib.mm_demag_tensor(ctypes.byref(bad[0]), None, 1, None, None) == mm.MM_E_ARG
