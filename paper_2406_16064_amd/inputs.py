@@ -233,3 +233,25 @@ def sweep_instance(i):
     m = random_unit(n, n, nz, rng)
     return dict(mesh=mesh, params=dict(Ms=Ms, A=A, D=D, Ku=Ku, u=(0, 0, 1), H=tuple(Hm * d),
                                        alpha=alpha), m=m)
+
+
+def disk_material(nx, ny, nz, dx, dy, rng, Ms=(8e5, 5.8e5), A=(1.3e-11, 1.5e-11), D=(0.0, 3e-3),
+                  spread=0.05, radius_frac=0.45):
+    """Cell-based material of a two-grain disk: cells farther than radius_frac * min(Lx, Ly)
+    from the film's centre are empty (Ms = 0, a shape made by the magnetisation as with a
+    function-valued set_Ms); inside, the left half is grain 0 and the right half grain 1,
+    each value scaled per cell by 1 + spread * U(-1, 1).  Returns (Ms, A, D), each
+    (nz, ny, nx) FP64."""
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    px, py = np.meshgrid(x, y, indexing="xy")
+    cx, cy = 0.5 * nx * dx, 0.5 * ny * dy
+    inside = np.hypot(px - cx, py - cy) <= radius_frac * min(nx * dx, ny * dy)
+    right = px >= cx
+    out = []
+    for pair in (Ms, A, D):
+        v = np.where(right, pair[1], pair[0])[None].repeat(nz, axis=0)
+        v = v * (1.0 + spread * rng.uniform(-1.0, 1.0, size=v.shape))
+        out.append(v)
+    out[0] = np.where(inside[None], out[0], 0.0)
+    return tuple(out)
