@@ -57,14 +57,15 @@ enum {
   MM_ANIS_UNIAXIAL = 8u,    /* uniaxial anisotropy, easy axis u                     */
   MM_ZEEMAN = 16u,          /* uniform static applied field                         */
   MM_DMI_BULK = 32u,        /* bulk (classes T, O) DMI, e_ij = r_ij                 */
-  MM_DMI_D2D = 64u          /* class D2d DMI, e_ij = {e_x, -e_x, -e_y, e_y, 0, 0}   */
+  MM_DMI_D2D = 64u,         /* class D2d DMI, e_ij = {e_x, -e_x, -e_y, e_y, 0, 0}   */
+  MM_CELLS = 128u           /* cell-based Ms, A, D of the instance (mm_plan_set_cells) */
 };
 /* the five terms of the standard path; MM_TERM_MASK: every known bit.  The
  * three DMI classes share the constant D; each enabled one adds its field
  * (section "Dzyaloshinskii-Moriya Energy", the unified neighbour form) and
  * its energy to the DMI entry. */
 #define MM_ALL_TERMS 31u
-#define MM_TERM_MASK 127u
+#define MM_TERM_MASK 255u
 
 /* Regular mesh of nx*ny*nz cuboid cells of size dx*dy*dz (paper: FDMesh).
  * Limits: 1 <= n <= 1024 per axis, nx >= 2; d > 0 and finite. */
@@ -113,6 +114,28 @@ typedef struct mm_plan mm_plan;
 mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec,
                          uint32_t terms, int32_t max_batch, void* hip_stream);
 mm_status mm_plan_destroy(mm_plan* plan);
+
+/* Cell-based material of instance slot `instance` (0 <= instance < max_batch)
+ * of a plan created with MM_CELLS among its terms: per-cell saturation
+ * magnetisation Ms (A/m, >= 0), exchange constant A (J/m, >= 0) and DMI
+ * constant D (J/m^2), host FP64 arrays [nz][ny][nx] (x fastest), copied (in
+ * the plan precision) before the call returns.  Instances whose params.terms
+ * include MM_CELLS use them in place of params.Ms, A and D (which are then
+ * ignored; Ku, u, H, alpha, gamma stay uniform).  Paper: section "Design"
+ * (set_Ms with a function of position: cells with Ms = 0 lie outside the
+ * sample), section "Exchange energy" (cell-based A_i, pair coefficient
+ * A_ij = 2 A_i A_j / (A_i + A_j)) and the last sentence of section
+ * "Dzyaloshinskii-Moriya Energy" (D_ij = 2 D_i D_j / (D_i + D_j)).  Readings:
+ * an empty cell (Ms = 0) has H = 0 and dm/dt = 0 and is nobody's neighbour;
+ * D_ij = 0 unless D_i D_j > 0; A_ij = 0 when A_i + A_j = 0; the demag input is
+ * M = Ms_i m_i; energies weight each cell by its Ms_i.  m must hold unit
+ * vectors in every cell, empty ones included (they are carried unchanged).
+ * All instances of one call either use MM_CELLS or none does (MM_E_ARG);
+ * MM_E_STATE when a call's instance uses MM_CELLS before its slot was set.
+ * Batches (mm_batch_*) and NEB chains take uniform material only.
+ * Allocates the plan's cell arrays on first use; synchronises. */
+mm_status mm_plan_set_cells(mm_plan* plan, int32_t instance, const double* Ms, const double* A, const double* D,
+                            void* hip_stream);
 
 /* Padded FFT grid chosen for the plan (each P >= 2n-1; x even). */
 mm_status mm_plan_padded(const mm_plan* plan, int32_t* Px, int32_t* Py, int32_t* Pz);

@@ -7,14 +7,22 @@ namespace mmx {
 
 int eval_blocks_per_inst(const Geo& g, const Tuning& tu) { return ((g.ny + tu.ty_x - 1) / tu.ty_x) * g.nz; }
 
-extern template void inv_x_launch<float, true>(int, int, bool, const Launch<float>&, long long, int, size_t,
-                                               hipStream_t);
-extern template void inv_x_launch<float, false>(int, int, bool, const Launch<float>&, long long, int, size_t,
-                                                hipStream_t);
-extern template void inv_x_launch<double, true>(int, int, bool, const Launch<double>&, long long, int, size_t,
-                                                hipStream_t);
-extern template void inv_x_launch<double, false>(int, int, bool, const Launch<double>&, long long, int, size_t,
-                                                 hipStream_t);
+extern template void inv_x_launch<float, true, false>(int, int, bool, const Launch<float>&, long long, int, size_t,
+                                                       hipStream_t);
+extern template void inv_x_launch<float, true, true>(int, int, bool, const Launch<float>&, long long, int, size_t,
+                                                       hipStream_t);
+extern template void inv_x_launch<float, false, false>(int, int, bool, const Launch<float>&, long long, int, size_t,
+                                                       hipStream_t);
+extern template void inv_x_launch<float, false, true>(int, int, bool, const Launch<float>&, long long, int, size_t,
+                                                       hipStream_t);
+extern template void inv_x_launch<double, true, false>(int, int, bool, const Launch<double>&, long long, int, size_t,
+                                                       hipStream_t);
+extern template void inv_x_launch<double, true, true>(int, int, bool, const Launch<double>&, long long, int, size_t,
+                                                       hipStream_t);
+extern template void inv_x_launch<double, false, false>(int, int, bool, const Launch<double>&, long long, int, size_t,
+                                                       hipStream_t);
+extern template void inv_x_launch<double, false, true>(int, int, bool, const Launch<double>&, long long, int, size_t,
+                                                       hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Step begin: finish the previous accepted attempt (project y5, FSAL copy),
@@ -641,8 +649,15 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
     const int cpt = inv_cpt(gs, nt);
     const bool fuse = fuse_next && demag && mode == MODE_STAGE && cpt > 0;
     mark();
-    if (demag) inv_x_launch<T, true>(mode, cpt, fuse, lb.L, lb.total, nt, lds, s);
-    else inv_x_launch<T, false>(mode, cpt, false, lb.L, lb.total, nt, 0, s);
+    // cell-based material: single-group launches whose instances all use it
+    const bool cells = gs.n == 1 && gs.h[0].cells != nullptr;
+    if (cells) {
+      if (demag) inv_x_launch<T, true, true>(mode, cpt, fuse, lb.L, lb.total, nt, lds, s);
+      else inv_x_launch<T, false, true>(mode, cpt, false, lb.L, lb.total, nt, 0, s);
+    } else {
+      if (demag) inv_x_launch<T, true, false>(mode, cpt, fuse, lb.L, lb.total, nt, lds, s);
+      else inv_x_launch<T, false, false>(mode, cpt, false, lb.L, lb.total, nt, 0, s);
+    }
   }
   mark();
   return hipGetLastError();

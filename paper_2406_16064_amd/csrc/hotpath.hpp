@@ -141,22 +141,35 @@ __host__ __device__ inline long long fwd_blocks(const Geo& g, const Tuning& tu, 
 // Row loads of the forward x transform: element n of column r packs
 // x[2n] + i x[2n+1] of row y0 + r (zero beyond nx).  Offsets in bytes from
 // the z plane's first row.
+// ms (nullable): per-cell saturation magnetisation at the same offsets (cell-based
+// material), by which each m component is scaled (M = Ms m).
 template <typename T>
 struct XRowLoad {
   const T* src;
   int nx;
   bool pairs;  // nx even: rows start 8-byte aligned, x[2n] and x[2n+1] in one load
+  const T* ms;
   template <bool CHK>
-  __device__ __forceinline__ Cx<T> get(int r, int n) const {
+  __device__ __forceinline__ Cx<T> raw(const T* a, int r, int n) const {
     const uint32_t row = (uint32_t)(r * nx);
     const int i0 = 2 * n;
     Cx<T> v = {T(0), T(0)};
-    if (!CHK) return gldo(reinterpret_cast<const Cx<T>*>(src), (row + (uint32_t)i0) * (uint32_t)sizeof(T));
+    if (!CHK) return gldo(reinterpret_cast<const Cx<T>*>(a), (row + (uint32_t)i0) * (uint32_t)sizeof(T));
     if (pairs) {
-      if (i0 < nx) v = gldo(reinterpret_cast<const Cx<T>*>(src), (row + (uint32_t)i0) * (uint32_t)sizeof(T));
+      if (i0 < nx) v = gldo(reinterpret_cast<const Cx<T>*>(a), (row + (uint32_t)i0) * (uint32_t)sizeof(T));
     } else {
-      if (i0 < nx) v.x = gldo(src, (row + (uint32_t)i0) * (uint32_t)sizeof(T));
-      if (i0 + 1 < nx) v.y = gldo(src, (row + (uint32_t)i0 + 1) * (uint32_t)sizeof(T));
+      if (i0 < nx) v.x = gldo(a, (row + (uint32_t)i0) * (uint32_t)sizeof(T));
+      if (i0 + 1 < nx) v.y = gldo(a, (row + (uint32_t)i0 + 1) * (uint32_t)sizeof(T));
+    }
+    return v;
+  }
+  template <bool CHK>
+  __device__ __forceinline__ Cx<T> get(int r, int n) const {
+    Cx<T> v = raw<CHK>(src, r, n);
+    if (ms) {
+      const Cx<T> w = raw<CHK>(ms, r, n);
+      v.x *= w.x;
+      v.y *= w.y;
     }
     return v;
   }
@@ -193,7 +206,9 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   TableCopy<T, 4> tab;
   tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
   const T* in = ldu(&L.epis[gi].in);
-  XRowLoad<T> ld{in + ((size_t)b * 3 + c) * g.N + ((size_t)z * g.ny + y0) * g.nx, g.nx, (g.nx & 1) == 0};
+  const size_t rows0 = ((size_t)z * g.ny + y0) * g.nx;
+  XRowLoad<T> ld{in + ((size_t)b * 3 + c) * g.N + rows0, g.nx, (g.nx & 1) == 0,
+                 hp.cells ? hp.cells + (size_t)b * 3 * g.N + rows0 : nullptr};
   auto hook = [&]() { tab.store(twl); };
   // all nx / 2 packed inputs present and the rest zero when nx = Lx (even)
   const bool hin = ld.pairs && g.nx == g.Lx;
@@ -1112,6 +1127,125 @@ __device__ __forceinline__ V3<T> local_field(const Geo& g, const LocalCoef<T>& P
   return H;
 }
 
+// Cell-based material (MM_CELLS): each instance's cells carry Ms, A and D in a
+// [3][N] array laid out like m (so the same byte offsets reach them).  Pair
+// couplings are the harmonic means of the exchange and DMI sections,
+// A_ij = 2 A_i A_j / (A_i + A_j) and D_ij = 2 D_i D_j / (D_i + D_j) (0 unless
+// D_i D_j > 0); a neighbour that is missing or empty (Ms = 0) couples with 0.
+// Order of the six neighbours: -x, +x, -y, +y, -z, +z.
+template <typename T> struct CellNbr {
+  T ms;     // Ms of the cell (0: empty)
+  T a[6];   // A_ij
+  T d[6];   // D_ij
+};
+
+template <typename T>
+__device__ __forceinline__ T harmonic_a(T ai, T aj) {
+  const T s = ai + aj;
+  return s > T(0) ? T(2) * ai * aj / s : T(0);
+}
+template <typename T>
+__device__ __forceinline__ T harmonic_d(T di, T dj) {
+  return di * dj > T(0) ? T(2) * di * dj / (di + dj) : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ CellNbr<T> load_cells(const Geo& g, uint32_t terms, const T* __restrict__ cb,
+                                                 const COff& co, int x, int y, int z) {
+  CellNbr<T> c;
+  const V3<T> me = ld3o(cb, co);
+  c.ms = me.x;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) { c.a[k] = T(0); c.d[k] = T(0); }
+  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL | MM_DMI_BULK | MM_DMI_D2D)) {
+    const long long nxy = (long long)g.nx * g.ny;
+    V3<T> nb[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nb[k] = {T(0), T(0), T(0)};
+    if (x > 0) nb[0] = ld3o(cb - 1, co);
+    if (x + 1 < g.nx) nb[1] = ld3o(cb + 1, co);
+    if (y > 0) nb[2] = ld3o(cb - g.nx, co);
+    if (y + 1 < g.ny) nb[3] = ld3o(cb + g.nx, co);
+    if (z > 0) nb[4] = ld3o(cb - nxy, co);
+    if (z + 1 < g.nz) nb[5] = ld3o(cb + nxy, co);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const bool on = me.x > T(0) && nb[k].x > T(0);
+      c.a[k] = on ? harmonic_a(me.y, nb[k].y) : T(0);
+      c.d[k] = on ? harmonic_d(me.z, nb[k].z) : T(0);
+    }
+  }
+  return c;
+}
+
+// Local field of a cell with cell-based material.  P holds the unit
+// coefficients of such instances: cex[a] = 2/(mu0 d_a^2), cdmi[a] = 1/(mu0 d_a),
+// can = 2 Ku / mu0; each term carries the cell's own 1/Ms_i.  An empty cell
+// has no field.  Missing or empty neighbours have zero couplings (their m,
+// zero where the mesh ends, drops out).
+template <typename T, bool ENERGY>
+__device__ __forceinline__ V3<T> local_field_cells(const LocalCoef<T>& P, const Nbr<T>& nb, const CellNbr<T>& cn,
+                                                   LocalTerms* lt) {
+  V3<T> H = {T(0), T(0), T(0)};
+  if (!(cn.ms > T(0))) return H;
+  const T inv = T(1) / cn.ms;
+  const V3<T> mi = nb.mi;
+  const V3<T> xm = nb.xm, xp = nb.xp, ym = nb.ym, yp = nb.yp, zm = nb.zm, zp = nb.zp;
+  if (P.terms & MM_EXCHANGE) {
+    V3<T> e = {T(0), T(0), T(0)};
+    auto acc = [&](V3<T> v, T c) {
+      e.x += c * (v.x - mi.x);
+      e.y += c * (v.y - mi.y);
+      e.z += c * (v.z - mi.z);
+    };
+    acc(xm, P.cex[0] * cn.a[0]); acc(xp, P.cex[0] * cn.a[1]);
+    acc(ym, P.cex[1] * cn.a[2]); acc(yp, P.cex[1] * cn.a[3]);
+    acc(zm, P.cex[2] * cn.a[4]); acc(zp, P.cex[2] * cn.a[5]);
+    e.x *= inv; e.y *= inv; e.z *= inv;
+    H.x += e.x; H.y += e.y; H.z += e.z;
+    if (ENERGY) lt->ex = (double)mi.x * e.x + (double)mi.y * e.y + (double)mi.z * e.z;
+  }
+  if (P.terms & (MM_DMI_INTERFACIAL | MM_DMI_BULK | MM_DMI_D2D)) {
+    // weighted differences: a along x, b along y, c along z (+ neighbour minus - neighbour)
+    const T cx = P.cdmi[0] * inv, cy = P.cdmi[1] * inv, cz = P.cdmi[2] * inv;
+    const V3<T> a = {cx * (cn.d[1] * xp.x - cn.d[0] * xm.x), cx * (cn.d[1] * xp.y - cn.d[0] * xm.y),
+                     cx * (cn.d[1] * xp.z - cn.d[0] * xm.z)};
+    const V3<T> b = {cy * (cn.d[3] * yp.x - cn.d[2] * ym.x), cy * (cn.d[3] * yp.y - cn.d[2] * ym.y),
+                     cy * (cn.d[3] * yp.z - cn.d[2] * ym.z)};
+    V3<T> d = {T(0), T(0), T(0)};
+    if (P.terms & MM_DMI_INTERFACIAL) {  // e_ij = {-e_y, e_y, e_x, -e_x}: -(e_y x a - e_x x b)
+      d.x -= a.z;
+      d.y -= b.z;
+      d.z += a.x + b.y;
+    }
+    if (P.terms & MM_DMI_BULK) {  // e_ij = r_ij: -(e_x x a + e_y x b + e_z x c)
+      const V3<T> c = {cz * (cn.d[5] * zp.x - cn.d[4] * zm.x), cz * (cn.d[5] * zp.y - cn.d[4] * zm.y),
+                       cz * (cn.d[5] * zp.z - cn.d[4] * zm.z)};
+      d.x += c.y - b.z;
+      d.y += a.z - c.x;
+      d.z += b.x - a.y;
+    }
+    if (P.terms & MM_DMI_D2D) {  // e_ij = {e_x, -e_x, -e_y, e_y}: -(-e_x x a + e_y x b)
+      d.x -= b.z;
+      d.y -= a.z;
+      d.z += a.y + b.x;
+    }
+    H.x += d.x; H.y += d.y; H.z += d.z;
+    if (ENERGY) lt->dmi = (double)mi.x * d.x + (double)mi.y * d.y + (double)mi.z * d.z;
+  }
+  if (P.terms & MM_ANIS_UNIAXIAL) {
+    const T ux = P.u[0], uy = P.u[1], uz = P.u[2];
+    const T s = P.can * inv * (mi.x * ux + mi.y * uy + mi.z * uz);
+    H.x += s * ux; H.y += s * uy; H.z += s * uz;
+    if (ENERGY) lt->an = (double)s * ((double)mi.x * ux + (double)mi.y * uy + (double)mi.z * uz);
+  }
+  if (P.terms & MM_ZEEMAN) {
+    H.x += P.H[0]; H.y += P.H[1]; H.z += P.H[2];
+    if (ENERGY) lt->ze = (double)mi.x * P.H[0] + (double)mi.y * P.H[1] + (double)mi.z * P.H[2];
+  }
+  return H;
+}
+
 template <typename T>
 __device__ __forceinline__ V3<T> ll_rhs(V3<T> m, V3<T> H, T g1, T g2) {
   const V3<T> a = {m.y * H.z - m.z * H.y, m.z * H.x - m.x * H.z, m.x * H.y - m.y * H.x};
@@ -1257,7 +1391,11 @@ __device__ inline void control_step(DevCtl& C, const double* __restrict__ replay
 // these rows is transformed forward along x here, into the same Sx rows this
 // workgroup read (no other workgroup touches them), which takes the forward x
 // pass of the next evaluation off the critical path.
-template <typename T, bool DEMAG, int MODE, int CPT, bool FUSE>
+// CELLS: cell-based material (every instance of the launch has MM_CELLS):
+// the local terms use the cells' Ms, A, D (local_field_cells), an empty cell
+// gets no demag field either, energies weight each cell by its Ms, and the
+// fused forward transform takes Ms m.
+template <typename T, bool DEMAG, int MODE, int CPT, bool FUSE, bool CELLS>
 __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   constexpr bool PREF = CPT == 1;
   static_assert(!FUSE || (MODE == MODE_STAGE && DEMAG && CPT > 0), "fused forward pass needs a stage epilogue");
@@ -1347,6 +1485,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
 
   // prefetch of the single cell's epilogue inputs (PREF)
   Nbr<T> pnb;
+  CellNbr<T> pcn;
   V3<T> pbase = {T(0), T(0), T(0)};
   V3<T> pk[6];
   if constexpr (PREF) {
@@ -1357,6 +1496,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     const size_t ib = (size_t)b * ldu(&ep->inst_stride);
     const COff co = coff_of<T>(N, (z * g.ny + y0 + rc) * g.nx + xc);
     pnb = load_nbr<T>(g, ldu(&hp.prm[b].terms), ldu(&ep->in) + ib, co, xc, y0 + rc, z);
+    if constexpr (CELLS) pcn = load_cells<T>(g, ldu(&hp.prm[b].terms), hp.cells + (size_t)b * 3 * N, co, xc, y0 + rc, z);
     if constexpr (MODE == MODE_STAGE) pbase = ld3o(ldu(&ep->mbase) + ib, co);
     if constexpr (MODE == MODE_STAGE || MODE == MODE_ERROR) {
       const int nk = ldu(&ep->nk);
@@ -1441,6 +1581,8 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     const int y = y0 + r;
     const COff co = coff_of<T>(N, (z * g.ny + y) * g.nx + x);
     const Nbr<T> nb = PREF ? pnb : load_nbr<T>(g, P.terms, mb, co, x, y, z);
+    CellNbr<T> cn;
+    if constexpr (CELLS) cn = PREF ? pcn : load_cells<T>(g, P.terms, hp.cells + (size_t)b * 3 * N, co, x, y, z);
     const size_t ib = (size_t)b * epi.inst_stride;
     // the stage's earlier slopes (and m for the stage input), all issued
     // before any of them is used: one memory round trip per cell, not one per
@@ -1464,10 +1606,17 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     const V3<T> mi = nb.mi;
     LocalTerms lt = {0, 0, 0, 0};
     V3<T> H;
-    if constexpr (energy) H = local_field<T, true>(g, P, nb, x, y, z, &lt);
-    else H = local_field<T, false>(g, P, nb, x, y, z, nullptr);
+    if constexpr (CELLS) {
+      if constexpr (energy) H = local_field_cells<T, true>(P, nb, cn, &lt);
+      else H = local_field_cells<T, false>(P, nb, cn, nullptr);
+    } else {
+      if constexpr (energy) H = local_field<T, true>(g, P, nb, x, y, z, &lt);
+      else H = local_field<T, false>(g, P, nb, x, y, z, nullptr);
+    }
     V3<T> hd = {T(0), T(0), T(0)};
-    if (add_hd) {
+    bool cell_hd = add_hd;
+    if constexpr (CELLS) cell_hd = add_hd && cn.ms > T(0);
+    if (cell_hd) {
       const int kk = pidx(x >> 1, sh);
       const Cx<T> a = lds[(0 * TY + r) * cs + kk], bq = lds[(1 * TY + r) * cs + kk];
       const Cx<T> cq = lds[(2 * TY + r) * cs + kk];
@@ -1480,11 +1629,13 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       else st3o(epi.out + ib, co, H);
     }
     if constexpr (energy) {
-      esum[0] += lt.ex;
-      if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
-      esum[2] += lt.dmi;
-      esum[3] += lt.an;
-      esum[4] += lt.ze;
+      double wms = 1.0;  // cell-based material: each cell weighs with its own Ms
+      if constexpr (CELLS) wms = (double)cn.ms;
+      esum[0] += wms * lt.ex;
+      if (cell_hd) esum[1] += wms * ((double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z);
+      esum[2] += wms * lt.dmi;
+      esum[3] += wms * lt.an;
+      esum[4] += wms * lt.ze;
     }
     if constexpr (MODE == MODE_RHS || MODE == MODE_STAGE || MODE == MODE_ERROR) {
       const V3<T> kk = ll_rhs(mi, H, g1, g2);
@@ -1507,7 +1658,10 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
         }
         if constexpr (DEFER) res2[slot] = acc;
         else st3o(epi.msn + ib, co, acc);
-        if constexpr (FUSE) mnext[slot] = acc;
+        if constexpr (FUSE) {
+          mnext[slot] = acc;
+          if constexpr (CELLS) mnext[slot] = {acc.x * cn.ms, acc.y * cn.ms, acc.z * cn.ms};  // M = Ms m
+        }
       } else if constexpr (MODE == MODE_ERROR) {
         double ex = 0, ey = 0, ez = 0;
 #pragma unroll
@@ -1667,37 +1821,38 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   }
 }
 
-template <typename T, bool DEMAG, int CPT>
+template <typename T, bool DEMAG, int CPT, bool CELLS>
 void inv_x_launch_c(int mode, bool fuse, const Launch<T>& L, long long total, int nt, size_t lds, hipStream_t s) {
   const dim3 grid((unsigned)total);
   switch (mode) {
-    case MODE_FIELD: k_inv_x<T, DEMAG, MODE_FIELD, CPT, false><<<grid, nt, lds, s>>>(L); break;
-    case MODE_RHS: k_inv_x<T, DEMAG, MODE_RHS, CPT, false><<<grid, nt, lds, s>>>(L); break;
+    case MODE_FIELD: k_inv_x<T, DEMAG, MODE_FIELD, CPT, false, CELLS><<<grid, nt, lds, s>>>(L); break;
+    case MODE_RHS: k_inv_x<T, DEMAG, MODE_RHS, CPT, false, CELLS><<<grid, nt, lds, s>>>(L); break;
     case MODE_STAGE:
       if constexpr (DEMAG && CPT > 0) {
         if (fuse) {
-          k_inv_x<T, DEMAG, MODE_STAGE, CPT, true><<<grid, nt, lds, s>>>(L);
+          k_inv_x<T, DEMAG, MODE_STAGE, CPT, true, CELLS><<<grid, nt, lds, s>>>(L);
           break;
         }
       }
-      k_inv_x<T, DEMAG, MODE_STAGE, CPT, false><<<grid, nt, lds, s>>>(L);
+      k_inv_x<T, DEMAG, MODE_STAGE, CPT, false, CELLS><<<grid, nt, lds, s>>>(L);
       break;
-    case MODE_ERROR: k_inv_x<T, DEMAG, MODE_ERROR, CPT, false><<<grid, nt, lds, s>>>(L); break;
-    case MODE_ENERGY: k_inv_x<T, DEMAG, MODE_ENERGY, CPT, false><<<grid, nt, lds, s>>>(L); break;
-    default: k_inv_x<T, DEMAG, MODE_FIELD_ENERGY, CPT, false><<<grid, nt, lds, s>>>(L); break;
+    case MODE_ERROR: k_inv_x<T, DEMAG, MODE_ERROR, CPT, false, CELLS><<<grid, nt, lds, s>>>(L); break;
+    case MODE_ENERGY: k_inv_x<T, DEMAG, MODE_ENERGY, CPT, false, CELLS><<<grid, nt, lds, s>>>(L); break;
+    default: k_inv_x<T, DEMAG, MODE_FIELD_ENERGY, CPT, false, CELLS><<<grid, nt, lds, s>>>(L); break;
   }
 }
 
-// cpt: cells per thread of the unrolled epilogue (1, 2, 4, 8) or 0 (loop)
-template <typename T, bool DEMAG>
+// cpt: cells per thread of the unrolled epilogue (1, 2, 4, 8) or 0 (loop);
+// CELLS: the launch's instances use cell-based material
+template <typename T, bool DEMAG, bool CELLS>
 void inv_x_launch(int mode, int cpt, bool fuse, const Launch<T>& L, long long total, int nt, size_t lds,
                   hipStream_t s) {
   switch (cpt) {
-    case 1: inv_x_launch_c<T, DEMAG, 1>(mode, fuse, L, total, nt, lds, s); break;
-    case 2: inv_x_launch_c<T, DEMAG, 2>(mode, fuse, L, total, nt, lds, s); break;
-    case 4: inv_x_launch_c<T, DEMAG, 4>(mode, fuse, L, total, nt, lds, s); break;
-    case 8: inv_x_launch_c<T, DEMAG, 8>(mode, fuse, L, total, nt, lds, s); break;
-    default: inv_x_launch_c<T, DEMAG, 0>(mode, false, L, total, nt, lds, s); break;
+    case 1: inv_x_launch_c<T, DEMAG, 1, CELLS>(mode, fuse, L, total, nt, lds, s); break;
+    case 2: inv_x_launch_c<T, DEMAG, 2, CELLS>(mode, fuse, L, total, nt, lds, s); break;
+    case 4: inv_x_launch_c<T, DEMAG, 4, CELLS>(mode, fuse, L, total, nt, lds, s); break;
+    case 8: inv_x_launch_c<T, DEMAG, 8, CELLS>(mode, fuse, L, total, nt, lds, s); break;
+    default: inv_x_launch_c<T, DEMAG, 0, CELLS>(mode, false, L, total, nt, lds, s); break;
   }
 }
 

@@ -1,7 +1,7 @@
-// Inverse-x pass kernels (double, demag on): one translation unit per
-// instantiation set, so that the library builds in parallel.
+// Inverse-x pass kernels (double, demag on, uniform material): one
+// translation unit per instantiation set, so that the library builds in parallel.
 #include "hotpath.hpp"
 
 namespace mmx {
-template void inv_x_launch<double, true>(int, int, bool, const Launch<double>&, long long, int, size_t, hipStream_t);
+template void inv_x_launch<double, true, false>(int, int, bool, const Launch<double>&, long long, int, size_t, hipStream_t);
 }  // namespace mmx

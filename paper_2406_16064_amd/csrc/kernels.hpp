@@ -97,6 +97,7 @@ template <typename T> struct HotPlan {
   Cx<T>* Sx;               // [batch][sx] (layout above)
   Cx<T>* Sy;               // [batch][3][nz][Xp][Py] (3-D only)
   const DevParams* prm;    // [batch]
+  const T* cells;          // cell-based material [batch][3][N] (Ms, A, D per cell) or null
 };
 
 constexpr int kMaxGroups = 16;

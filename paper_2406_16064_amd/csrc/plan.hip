@@ -233,6 +233,8 @@ struct Group {
   void* twx = nullptr;
   void* twy = nullptr;
   void* twz = nullptr;
+  void* cells = nullptr;  // cell-based material [cells_cap][3][N] (Ms, A, D), plan precision
+  std::vector<char> cells_set;  // slot i holds data
   void* stage = nullptr;  // ms0, ms1, k1..k7: 9 x stage_cap x 3N
   void* mbuf = nullptr;   // contiguous m of the group's instances (batch runs)
   double imag_ratio = 0.0;
@@ -261,6 +263,7 @@ struct Engine {
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   double* he5 = nullptr;
   bool any_demag = false;
+  bool use_cells = false;  // the instances of the current call use cell-based material
   // graph cache of the Dormand-Prince attempt sequence
   hipGraphExec_t gexec = nullptr;
   std::vector<const void*> g_key;
@@ -305,6 +308,8 @@ mm_status check_params(const Engine& E, const mm_params* q, int n) {
     if ((r.terms & ~E.terms) != 0) return fail(MM_E_ARG, "params enable a term the plan was not built for");
     if ((r.terms & MM_ANIS_UNIAXIAL) && r.u[0] == 0 && r.u[1] == 0 && r.u[2] == 0)
       return fail(MM_E_ARG, "easy axis must be non-zero");
+    if (((r.terms ^ q[0].terms) & MM_CELLS) != 0)
+      return fail(MM_E_ARG, "either every instance of a call uses cell-based material (MM_CELLS) or none does");
   }
   return MM_OK;
 }
@@ -327,9 +332,18 @@ DevParams dev_params(const mm_params& r, const Group& G) {
     o.u[k] = un > 0 ? r.u[k] / un : 0.0;
     o.H[k] = r.H[k];
   }
+  if (r.terms & MM_CELLS) {  // unit coefficients: the kernels apply each cell's Ms, A_ij, D_ij
+    o.Ms = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      const double d = a == 0 ? G.mesh.dx : a == 1 ? G.mesh.dy : G.mesh.dz;
+      o.cex[a] = 2.0 / (kMu0 * d * d);
+      o.cdmi[a] = 1.0 / (kMu0 * d);
+    }
+    o.can = 2 * r.Ku / kMu0;
+  }
   o.g1 = -r.gamma / (1 + r.alpha * r.alpha);
   o.g2 = -r.alpha * r.gamma / (1 + r.alpha * r.alpha);
-  o.demag_scale = -r.Ms / P;
+  o.demag_scale = (r.terms & MM_CELLS) ? -1.0 / P : -r.Ms / P;  // cells: Ms is inside M
   o.terms = r.terms;
   return o;
 }
@@ -488,7 +502,7 @@ mm_status dev_alloc(void** d, size_t bytes) {
 }
 
 void free_group(Group& G) {
-  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.stage, G.mbuf};
+  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.stage, G.mbuf, G.cells};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   G = Group();
@@ -605,6 +619,7 @@ mm_status upload_params(Engine& E, const std::vector<const mm_params*>& q, const
                         hipStream_t s) {
   std::vector<DevParams> d(q.size());
   E.any_demag = false;
+  E.use_cells = !q.empty() && (q[0]->terms & MM_CELLS) != 0;
   for (size_t b = 0; b < q.size(); ++b) {
     d[b] = dev_params(*q[b], E.groups[grp[b]]);
     E.any_demag = E.any_demag || (q[b]->terms & MM_DEMAG) != 0;
@@ -639,6 +654,7 @@ mm_status make_set(Engine& E, const std::vector<int>& nb, GroupSet<T>& gs, std::
     h.Sx = (Cx<T>*)G.Sx;
     h.Sy = (Cx<T>*)G.Sy;
     h.prm = E.prm + acc;
+    h.cells = E.use_cells ? (const T*)G.cells : nullptr;
     inst0[i] = acc;
     acc += nb[i];
   }
@@ -751,7 +767,7 @@ mm_status energy_finish(Engine& E, const mm_params* q, int batch, const double* 
   HIPCHK(hipMemcpyAsync(E.he5, e5, sizeof(double) * 5 * batch, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int b = 0; b < batch; ++b) {
-    const double c = kMu0 * q[b].Ms * G.g.dV;
+    const double c = kMu0 * ((q[b].terms & MM_CELLS) ? 1.0 : q[b].Ms) * G.g.dV;  // cells: Ms in the sums
     for (int k = 0; k < 5; ++k) E_out[5 * b + k] = -(k == 4 ? 1.0 : 0.5) * c * E.he5[5 * b + k];
   }
   return MM_OK;
@@ -1541,7 +1557,35 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
 mm_status plan_checks(mm_plan* p, const mm_params* q, int batch) {
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (batch < 1 || batch > p->maxb) return fail(MM_E_ARG, "batch must be in [1, max_batch]");
-  return check_params(p->e, q, batch);
+  MMCHK(check_params(p->e, q, batch));
+  if (q[0].terms & MM_CELLS) {
+    const Group& G = p->e.groups[0];
+    for (int b = 0; b < batch; ++b)
+      if (b >= (int)G.cells_set.size() || !G.cells_set[b])
+        return fail(MM_E_STATE, "instance " + std::to_string(b) + " uses MM_CELLS but mm_plan_set_cells was "
+                                "not called for its slot");
+  }
+  return MM_OK;
+}
+
+template <typename T>
+mm_status set_cells_impl(mm_plan* p, int inst, const double* Ms, const double* A, const double* D, hipStream_t s) {
+  Group& G = p->e.groups[0];
+  const size_t N = (size_t)G.g.N;
+  if (!G.cells) {
+    MMCHK(dev_alloc(&G.cells, sizeof(T) * 3 * N * p->maxb));
+    G.cells_set.assign(p->maxb, 0);
+  }
+  std::vector<T> h(3 * N);
+  for (size_t i = 0; i < N; ++i) {
+    h[i] = T(Ms[i]);
+    h[N + i] = T(A[i]);
+    h[2 * N + i] = T(D[i]);
+  }
+  HIPCHK(hipMemcpyAsync((T*)G.cells + (size_t)inst * 3 * N, h.data(), sizeof(T) * 3 * N, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  G.cells_set[inst] = 1;
+  return MM_OK;
 }
 
 }  // namespace
@@ -1627,6 +1671,23 @@ mm_status mm_plan_destroy(mm_plan* plan) {
   free_engine(plan->e);
   delete plan;
   return MM_OK;
+}
+
+mm_status mm_plan_set_cells(mm_plan* p, int32_t instance, const double* Ms, const double* A, const double* D,
+                            void* hip_stream) {
+  if (!p) return fail(MM_E_ARG, "plan is null");
+  if (!(p->e.terms & MM_CELLS)) return fail(MM_E_ARG, "the plan was created without MM_CELLS");
+  if (instance < 0 || instance >= p->maxb) return fail(MM_E_ARG, "instance must be in [0, max_batch)");
+  if (!Ms || !A || !D) return fail(MM_E_ARG, "Ms, A and D must all be given");
+  const long long N = p->e.groups[0].g.N;
+  for (long long i = 0; i < N; ++i) {
+    if (!is_fin(Ms[i]) || Ms[i] < 0) return fail(MM_E_ARG, "cell Ms must be finite and >= 0");
+    if (!is_fin(A[i]) || A[i] < 0) return fail(MM_E_ARG, "cell A must be finite and >= 0");
+    if (!is_fin(D[i])) return fail(MM_E_ARG, "cell D must be finite");
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  return p->e.prec == MM_F32 ? set_cells_impl<float>(p, instance, Ms, A, D, s)
+                             : set_cells_impl<double>(p, instance, Ms, A, D, s);
 }
 
 mm_status mm_plan_padded(const mm_plan* p, int32_t* Px, int32_t* Py, int32_t* Pz) {
@@ -1879,6 +1940,7 @@ mm_status mm_neb_run(mm_plan* p, const mm_params* q, void* images, int32_t n_img
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (n_img < 3 || n_img > p->maxb) return fail(MM_E_ARG, "n_img must be in [3, max_batch]");
   MMCHK(check_params(p->e, q, 1));
+  if (q->terms & MM_CELLS) return fail(MM_E_ARG, "NEB chains take uniform material (no MM_CELLS)");
   if (!images) return fail(MM_E_ARG, "images is null");
   if (!is_fin(k_spring) || !is_fin(h) || h <= 0 || n_iter < 1) return fail(MM_E_ARG, "invalid k_spring, h or n_iter");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -1896,6 +1958,7 @@ mm_status mm_batch_create(mm_batch** out, const mm_mesh* meshes, int32_t n_meshe
   if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
   for (int i = 0; i < n_meshes; ++i) MMCHK(check_cells(&meshes[i], prec));
   if (terms & ~MM_TERM_MASK) return fail(MM_E_ARG, "unknown term bits");
+  if (terms & MM_CELLS) return fail(MM_E_ARG, "batches take uniform material (no MM_CELLS)");
   hipStream_t s = (hipStream_t)hip_stream;
   mm_batch* b = new mm_batch();
   mm_status st = engine_init(b->e, prec, terms);

@@ -21,6 +21,7 @@ SHAPE_KEYS = ("ty_f", "nt_f", "cb_y", "tpc_y", "nt_y", "ty_x", "nt_i")
 EXCHANGE, DEMAG, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
 ALL_TERMS = 31
 DMI_BULK, DMI_D2D = 32, 64  # the other DMI symmetry classes (same D)
+CELLS = 128  # cell-based Ms, A, D of the instance (Plan.set_cells)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmmx.so is not built; run `python -m paper_2406_16064_amd.build` "
@@ -58,6 +59,7 @@ _sigs = {
     "mm_plan_create": [_P(_vp), _P(Mesh), ctypes.c_int, ctypes.c_uint32, _i32, _vp],
     "mm_plan_destroy": [_vp],
     "mm_plan_padded": [_vp, _P(_i32), _P(_i32), _P(_i32)],
+    "mm_plan_set_cells": [_vp, _i32, _P(_dbl), _P(_dbl), _P(_dbl), _vp],
     "mm_demag_tensor": [_P(Mesh), _vp, _i64, _vp, _vp],
     "mm_effective_field": [_vp, _P(Params), _i32, _vp, _vp, _vp],
     "mm_llg_rhs": [_vp, _P(Params), _i32, _vp, _vp, _vp],
@@ -172,6 +174,17 @@ class Plan:
 
     def _batch(self, m):
         return 1 if m.dim() == 4 else m.shape[0]
+
+    def set_cells(self, instance, Ms, A, D, stream=None):
+        """Cell-based Ms, A, D (arrays of nz x ny x nx, FP64 on the host) of instance slot `instance`."""
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (Ms, A, D)]
+        n = self.mesh.nx * self.mesh.ny * self.mesh.nz
+        for a in arrs:
+            if a.size != n:
+                raise ValueError("cell arrays must hold nx * ny * nz values")
+        ptrs = [a.ctypes.data_as(_P(_dbl)) for a in arrs]
+        _check(_lib.mm_plan_set_cells(self._h, instance, ptrs[0], ptrs[1], ptrs[2], _stream(stream)),
+               "mm_plan_set_cells")
 
     def effective_field(self, params, m, out=None, stream=None):
         import torch

@@ -59,10 +59,11 @@ def test_invalid_arguments_rejected_before_hip(mm):
         assert lib.mm_last_error()
     good = mm.Mesh(8, 8, 1, 1e-9, 1e-9, 1e-9)
     assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 7, 31, 1, None) == mm.MM_E_ARG
-    assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 128, 1, None) == mm.MM_E_ARG
+    assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 256, 1, None) == mm.MM_E_ARG
     assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 31, 0, None) == mm.MM_E_ARG
     assert lib.mm_effective_field(None, None, 1, None, None, None) == mm.MM_E_ARG
     assert lib.mm_plan_destroy(None) == mm.MM_E_ARG
+    assert lib.mm_plan_set_cells(None, 0, None, None, None, None) == mm.MM_E_ARG
     assert lib.mm_plan_set_shapes(None, None) == mm.MM_E_ARG
     assert lib.mm_plan_shapes(None, None) == mm.MM_E_ARG
     assert lib.mm_neb_run(None, None, None, 3, 1e5, 1e-14, 1, None, None) == mm.MM_E_ARG

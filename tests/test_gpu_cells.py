@@ -1,0 +1,192 @@
+"""GPU parity of the cell-based material path (MM_CELLS) against the oracle.
+
+Cell-based Ms, A and D with harmonic-mean couplings and empty cells (a two-grain
+disk inside an empty rim, the paper's function-defined shape), every term on,
+through the C interface: fields and dm/dt (FP64 to 1e-11, FP32 to 1e-5 of
+max |H|), energies (1e-10 / 1e-5 of sum |E|), a replayed Dormand-Prince
+trajectory and Heun steps (FP64 1e-9 / 1e-10 in m, FP32 1e-4), steepest
+descent (FP64 1e-9), a batch of two instances with different cell arrays, and
+the refusals (mixed instances, unset slot).  The FP32 runs compare against
+the oracle on the FP32-rounded cell values, as for m.
+"""
+import numpy as np
+import pytest
+
+from oracle import cells as C
+from oracle import dp45, heun, sd
+from oracle import fields as F
+from paper_2406_16064_amd import inputs
+
+from _util import field_err, representable, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DT = {"f32": torch.float32, "f64": torch.float64}
+TOL = {"f32": 1e-5, "f64": 1e-11}
+ALL7 = F.ALL_TERMS | F.DMI_BULK | F.DMI_D2D
+CELLS = 128
+UNI = dict(Ku=6e5, u=(0.2, -0.3, 1.0), H=(3e4, -2e4, 1.5e5), alpha=0.3)
+MESHES = [(40, 33, 1, 2e-9, 2e-9, 1e-9), (26, 22, 3, 3e-9, 3e-9, 2e-9), (64, 48, 1, 2e-9, 2e-9, 2e-9)]
+
+
+@pytest.fixture(scope="module")
+def mm():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_2406_16064_amd import mm as m
+    return m
+
+
+_kern = {}
+
+
+def _kernel(mesh):
+    if mesh not in _kern:
+        _kern[mesh] = F.DemagKernel(F.Mesh(*mesh))
+    return _kern[mesh]
+
+
+def _material(mesh, seed, prec):
+    rng = np.random.default_rng(seed)
+    Ms, A, D = inputs.disk_material(mesh[0], mesh[1], mesh[2], mesh[3], mesh[4], rng)
+    Ms, A, D = (representable(v, DT[prec]) for v in (Ms, A, D))
+    return C.Material(Ms, A, D)
+
+
+def _state(mesh, seed, prec):
+    rng = np.random.default_rng(seed)
+    m = inputs.add_noise(np.concatenate([np.zeros((2,) + mesh[2::-1][:3]), np.ones((1,) + mesh[2::-1][:3])]),
+                         0.6, rng)
+    return representable(m, DT[prec])
+
+
+def _gpu(mm, terms, **kw):
+    p = dict(UNI, **kw)
+    return mm.make_params(Ms=1.0, A=0.0, D=0.0, terms=terms | CELLS, **p)
+
+
+def _orc(terms, **kw):
+    return F.Params(Ms=1.0, terms=terms, **dict(UNI, **kw))
+
+
+def _plan(mm, mesh, prec, mats, terms=ALL7):
+    plan = mm.Plan(mesh, prec, terms=terms | CELLS, max_batch=len(mats))
+    for i, mat in enumerate(mats):
+        plan.set_cells(i, mat.Ms, mat.A, mat.D)
+    return plan
+
+
+@pytest.mark.parametrize("mesh", MESHES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fields_rhs_energies(mm, mesh, prec):
+    mat = _material(mesh, 1, prec)
+    m = _state(mesh, 2, prec)
+    plan = _plan(mm, mesh, prec, [mat])
+    gp, op = _gpu(mm, ALL7), _orc(ALL7)
+    md = to_dev(m, DT[prec])
+    H = plan.effective_field(gp, md).cpu().numpy()
+    Href = C.effective_field(m, F.Mesh(*mesh), op, mat, _kernel(mesh))
+    assert field_err(H, Href) <= TOL[prec]
+    empty = mat.Ms == 0
+    assert np.all(H[:, empty] == 0)
+    k = plan.llg_rhs(gp, md).cpu().numpy()
+    kref = F.llg_rhs_from_field(m, Href, op)
+    assert field_err(k, kref) <= TOL[prec]
+    assert np.all(k[:, empty] == 0)
+    E = plan.energy(gp, md)[0]
+    Eref = C.energies(m, F.Mesh(*mesh), op, mat, _kernel(mesh))
+    assert np.all(np.abs(E - Eref) <= (1e-5 if prec == "f32" else 1e-10) * np.sum(np.abs(Eref))), (E, Eref)
+
+
+@pytest.mark.parametrize("bit", [F.EXCHANGE, F.DEMAG, F.DMI, F.DMI_BULK, F.DMI_D2D, F.ANIS, F.ZEEMAN])
+def test_each_term_fp64(mm, bit):
+    mesh = MESHES[1]
+    mat = _material(mesh, 3, "f64")
+    m = _state(mesh, 4, "f64")
+    plan = _plan(mm, mesh, "f64", [mat])
+    H = plan.effective_field(_gpu(mm, bit), to_dev(m, torch.float64)).cpu().numpy()
+    Href = C.effective_field(m, F.Mesh(*mesh), _orc(bit), mat, _kernel(mesh))
+    assert field_err(H, Href) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rk45_replay(mm, prec):
+    mesh = MESHES[0]
+    mat = _material(mesh, 5, prec)
+    m0 = _state(mesh, 6, prec)
+    op = _orc(ALL7)
+    f = lambda y: C.llg_rhs(y, F.Mesh(*mesh), op, mat, _kernel(mesh))
+    ost = dp45.State(rtol=1e-5)
+    mo = dp45.run(f, m0.copy(), ost, max_accept=25)
+    plan = _plan(mm, mesh, prec, [mat])
+    md = to_dev(m0, DT[prec])
+    plan.rk45_run(_gpu(mm, ALL7), md, mm.new_states(1, rtol=1e-5), replay_h=ost.accepted_h)
+    got = md.cpu().numpy()
+    assert np.max(np.linalg.norm(got - mo, axis=0)) <= (1e-9 if prec == "f64" else 1e-4)
+    # empty cells keep their m (up to the rounding of the projection after each step)
+    assert np.max(np.abs(got[:, mat.Ms == 0] - m0[:, mat.Ms == 0])) <= (1e-13 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_heun(mm, prec):
+    mesh = MESHES[1]
+    mat = _material(mesh, 7, prec)
+    m0 = _state(mesh, 8, prec)
+    op = _orc(ALL7)
+    f = lambda y: C.llg_rhs(y, F.Mesh(*mesh), op, mat, _kernel(mesh))
+    h, n = 3e-14, 10
+    mo = heun.run(f, m0.copy(), h, n)
+    plan = _plan(mm, mesh, prec, [mat])
+    md = to_dev(m0, DT[prec])
+    plan.heun_run(_gpu(mm, ALL7), md, h, n)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= (1e-10 if prec == "f64" else 1e-4)
+
+
+def test_sd_fp64(mm):
+    mesh = MESHES[0]
+    mat = _material(mesh, 9, "f64")
+    m0 = _state(mesh, 10, "f64")
+    op = _orc(ALL7)
+    field = lambda y: C.effective_field(y, F.Mesh(*mesh), op, mat, _kernel(mesh))
+    mo, taus = sd.run(field, m0.copy(), 30, 1e-7, 1e-10, 1e-3)
+    plan = _plan(mm, mesh, "f64", [mat])
+    md = to_dev(m0, torch.float64)
+    tau = plan.sd_run(_gpu(mm, ALL7), md, 30, 1e-7, 1e-10, 1e-3)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
+    assert abs(tau[0] - taus[-1]) <= 1e-9 * taus[-1]
+
+
+def test_batch_of_two_materials_fp64(mm):
+    mesh = MESHES[2]
+    mats = [_material(mesh, 11, "f64"), _material(mesh, 12, "f64")]
+    ms = np.stack([_state(mesh, 13, "f64"), _state(mesh, 14, "f64")])
+    plan = _plan(mm, mesh, "f64", mats)
+    gps = [_gpu(mm, ALL7), _gpu(mm, ALL7, H=(0.0, 5e4, -1e5), alpha=0.1)]
+    ops = [_orc(ALL7), _orc(ALL7, H=(0.0, 5e4, -1e5), alpha=0.1)]
+    k = plan.llg_rhs(gps, to_dev(ms, torch.float64)).cpu().numpy()
+    for b in range(2):
+        ref = C.llg_rhs(ms[b], F.Mesh(*mesh), ops[b], mats[b], _kernel(mesh))
+        assert field_err(k[b], ref) <= 1e-11
+
+
+def test_refusals(mm):
+    mesh = MESHES[0]
+    mat = _material(mesh, 15, "f32")
+    plan = mm.Plan(mesh, "f32", terms=ALL7 | CELLS, max_batch=2)
+    md = to_dev(np.stack([_state(mesh, 16, "f32")] * 2), torch.float32)
+    gp = _gpu(mm, ALL7)
+    with pytest.raises(mm.MMError):  # slot 0 not set yet
+        plan.llg_rhs([gp, gp], md)
+    plan.set_cells(0, mat.Ms, mat.A, mat.D)
+    with pytest.raises(mm.MMError):  # slot 1 not set
+        plan.llg_rhs([gp, gp], md)
+    uni = mm.make_params(Ms=8e5, A=1e-11, terms=ALL7, **UNI)
+    with pytest.raises(mm.MMError):  # mixed instances
+        plan.llg_rhs([gp, uni], md)
+    with pytest.raises(mm.MMError):  # negative Ms
+        plan.set_cells(1, -mat.Ms - 1.0, mat.A, mat.D)
+    plain = mm.Plan(mesh, "f32", terms=ALL7)
+    with pytest.raises(mm.MMError):  # plan without MM_CELLS
+        plain.set_cells(0, mat.Ms, mat.A, mat.D)
