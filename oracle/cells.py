@@ -23,6 +23,21 @@ Readings where the paper is silent:
 * anisotropy Ku, easy axis u, the applied field, alpha and gamma stay uniform;
   the anisotropy field is 2 Ku / (mu0 Ms_i) (m . u) u;
 * energies weight each cell by its own Ms_i (the Zeeman energy -mu0 V sum Ms_i m.H).
+
+Interlayer coupling and spin torques (sections "Interlayer Exchange
+Interaction" and "Spin transfer torques"), all as terms of the effective field
+(the paper folds the torques into H_eff since each starts with m x):
+* interlayer: w = -J m_lo . m_hi + D_int . (m_lo x m_hi) per unit area between
+  layers k_lo and k_hi, cell by cell; H = -(1/(mu0 Ms dz)) dw/dm (the paper prints
+  the k_lo side; the k_hi side follows from the same w, with -D_int); only pairs
+  of magnetic cells couple;
+* Slonczewski / spin-orbit torque -a_J m x (m x p) - b_J m x p:
+  H = (b_J p + a_J m x p) / gamma;
+* Zhang-Li -(u . grad) m + beta m x (u . grad) m, with -(u . grad) m written as
+  m x (m x (u . grad) m): H = -(m x v + beta v) / gamma, v = (u . grad) m by central
+  differences (one-sided next to a missing or empty neighbour, zero with none);
+* torques carry no energy; the interlayer exchange adds to the exchange entry
+  and the interlayer DMI to the DMI entry.
 """
 import numpy as np
 
@@ -165,3 +180,116 @@ def exchange_energy_pairs(m, mesh, mat):
         _, Aij, _ = _pairs(mat, axis, step)
         E += np.sum(Aij * np.sum(m * (m - mj), axis=0)) / getattr(mesh, dname) ** 2
     return V * E
+
+
+# ---------------------------------------------------------------------------
+# Interlayer coupling and spin torques written as effective fields
+# ---------------------------------------------------------------------------
+class Extra:
+    """Per-instance parameters of the interlayer and spin-torque terms.
+
+    Interlayer (section "Interlayer Exchange Interaction"): layers z = k_lo and
+    z = k_hi couple cell by cell with w = -J m_lo . m_hi + D_int . (m_lo x m_hi)
+    per unit area (J, D_int in J/m^2).  Slonczewski / spin-orbit torque (section
+    "Spin transfer torques", eq_llg_stt2): -a_J m x (m x p) - b_J m x p (a_J, b_J
+    in 1/s, p normalised).  Zhang-Li (eq_llg_stt): -(u . grad) m + beta m x (u . grad) m
+    (u in m/s)."""
+
+    def __init__(self, k_lo=0, k_hi=0, J=0.0, D_int=(0.0, 0.0, 0.0), a_J=0.0, b_J=0.0, p=(0.0, 0.0, 1.0),
+                 u=(0.0, 0.0, 0.0), beta=0.0):
+        self.k_lo, self.k_hi = int(k_lo), int(k_hi)
+        self.J = float(J)
+        self.D_int = np.asarray(D_int, dtype=np.float64)
+        self.a_J, self.b_J = float(a_J), float(b_J)
+        p = np.asarray(p, dtype=np.float64)
+        self.p = p / np.linalg.norm(p)
+        self.u = np.asarray(u, dtype=np.float64)
+        self.beta = float(beta)
+
+
+INTERLAYER, STT_SOT, STT_ZL = 256, 512, 1024
+
+
+def interlayer_field(m, mesh, mat, ex):
+    """H at layer k_lo: (J m_hi + D_int x m_hi) / (mu0 Ms dz); at layer k_hi:
+    (J m_lo - D_int x m_lo) / (mu0 Ms dz) (the derivative of w with respect to each
+    layer's m), where both cells of a pair are magnetic; zero elsewhere."""
+    H = np.zeros_like(m)
+    lo, hi = ex.k_lo, ex.k_hi
+    both = (mat.Ms[lo] > 0) & (mat.Ms[hi] > 0)
+    inv = _inv_mu0_ms(mat) / mesh.dz
+    D = ex.D_int.reshape(3, 1, 1)
+    H[:, lo] = np.where(both, inv[lo] * (ex.J * m[:, hi] + np.cross(D, m[:, hi], axis=0)), 0.0)
+    H[:, hi] = np.where(both, inv[hi] * (ex.J * m[:, lo] - np.cross(D, m[:, lo], axis=0)), 0.0)
+    return H
+
+
+def interlayer_energy(m, mesh, mat, ex):
+    """E = dx dy sum over the pairs of [-J m_lo . m_hi + D_int . (m_lo x m_hi)], magnetic pairs only."""
+    lo, hi = ex.k_lo, ex.k_hi
+    both = (mat.Ms[lo] > 0) & (mat.Ms[hi] > 0)
+    w = -ex.J * np.sum(m[:, lo] * m[:, hi], axis=0) + np.einsum("a,a...->...", ex.D_int,
+                                                                 np.cross(m[:, lo], m[:, hi], axis=0))
+    return mesh.dx * mesh.dy * float(np.sum(np.where(both, w, 0.0)))
+
+
+def sot_field(m, mat, ex, gamma):
+    """Slonczewski / spin-orbit torque as a field: (b_J p + a_J m x p) / gamma (magnetic cells)."""
+    p = ex.p.reshape(3, 1, 1, 1)
+    H = (ex.b_J * np.broadcast_to(p, m.shape) + ex.a_J * np.cross(m, p, axis=0)) / gamma
+    return np.where((mat.Ms > 0)[None], H, 0.0)
+
+
+def directional_derivative(m, mesh, mat, u):
+    """(u . grad) m by differences: central where both neighbours along an axis are
+    present (inside the mesh and magnetic), one-sided where one is, zero where none is."""
+    v = np.zeros_like(m)
+    mag = mat.Ms > 0
+    for axis, ua, dname in ((2, u[0], "dx"), (1, u[1], "dy"), (0, u[2], "dz")):
+        if ua == 0.0:
+            continue
+        d = getattr(mesh, dname)
+        mp = np.stack([_shift(m[c], axis, +1) for c in range(3)])
+        mm_ = np.stack([_shift(m[c], axis, -1) for c in range(3)])
+        hp = mag & (_shift(mat.Ms, axis, +1) > 0)
+        hm = mag & (_shift(mat.Ms, axis, -1) > 0)
+        g = np.where((hp & hm)[None], (mp - mm_) / (2 * d),
+                     np.where(hp[None], (mp - m) / d, np.where(hm[None], (m - mm_) / d, 0.0)))
+        v += ua * g
+    return v
+
+
+def zhang_li_field(m, mesh, mat, ex, gamma):
+    """Zhang-Li torque as a field: -(m x v + beta v) / gamma with v = (u . grad) m."""
+    v = directional_derivative(m, mesh, mat, ex.u)
+    H = -(np.cross(m, v, axis=0) + ex.beta * v) / gamma
+    return np.where((mat.Ms > 0)[None], H, 0.0)
+
+
+def full_field(m, mesh, p, mat, ex, kernel=None):
+    """The cell-based effective field plus the terms of p.terms among INTERLAYER,
+    STT_SOT and STT_ZL."""
+    H = effective_field(m, mesh, p, mat, kernel)
+    if p.terms & INTERLAYER:
+        H = H + interlayer_field(m, mesh, mat, ex)
+    if p.terms & STT_SOT:
+        H = H + sot_field(m, mat, ex, p.gamma)
+    if p.terms & STT_ZL:
+        H = H + zhang_li_field(m, mesh, mat, ex, p.gamma)
+    return H
+
+
+def full_llg_rhs(m, mesh, p, mat, ex, kernel=None):
+    return F.llg_rhs_from_field(m, full_field(m, mesh, p, mat, ex, kernel), p)
+
+
+def full_energies(m, mesh, p, mat, ex, kernel=None):
+    """Energies of the conservative terms; the interlayer exchange adds to the
+    exchange entry and the interlayer DMI to the DMI entry (torques carry none)."""
+    E = energies(m, mesh, p, mat, kernel)
+    if p.terms & INTERLAYER:
+        Jonly = Extra(ex.k_lo, ex.k_hi, J=ex.J)
+        Donly = Extra(ex.k_lo, ex.k_hi, D_int=ex.D_int)
+        E[0] += interlayer_energy(m, mesh, mat, Jonly)
+        E[2] += interlayer_energy(m, mesh, mat, Donly)
+    return E

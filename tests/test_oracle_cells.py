@@ -16,6 +16,13 @@
 * A uniformly magnetised cube of cubic cells embedded in empty cells has mean
   demag field -Ms/3 exactly.
 * An A = 0 layer decouples the exchange of the blocks on either side.
+* Interlayer coupling: a hand-worked pair across an empty spacer (fields and
+  the energy density -J m_lo.m_hi + D_int.(m_lo x m_hi)), fields as gradients
+  of that energy, and the energy recovered from the fields.
+* Spin torques folded into the field: the LL result satisfies the paper's
+  Gilbert-form equations (Slonczewski/SOT exactly; Zhang-Li on a spiral,
+  whose central differences are tangent to the sphere), and with alpha = beta
+  the Zhang-Li torque translates a spiral rigidly with velocity u.
 """
 import math
 
@@ -181,3 +188,110 @@ def test_llg_rhs_is_tangent_and_zero_in_empty_cells():
     assert np.max(np.abs(np.sum(m * k, axis=0))) <= 1e-12 * np.max(np.abs(k))
     assert np.all(k[:, Ms == 0] == 0)
     assert math.isfinite(float(np.max(np.abs(k))))
+
+
+# ----------------------------------------------------------------------------- interlayer, torques
+
+def test_interlayer_hand_worked_pair():
+    """Two magnetic layers (z = 0 and z = 2) across an empty spacer: m_lo = e_x,
+    m_hi = e_y, J = 1e-3, D_int = 2e-3 e_z.  By hand: w = -J e_x.e_y + D_int.(e_x x e_y)
+    = 2e-3 J/m^2 per column; H_lo = (J e_y + D_int x e_y)/(mu0 Ms dz) = (-2e-3, 1e-3, 0)/(mu0 Ms dz),
+    H_hi = (J e_x - D_int x e_x)/(mu0 Ms dz) = (1e-3, -2e-3, 0)/(mu0 Ms dz)."""
+    mesh = F.Mesh(2, 1, 3, 2e-9, 3e-9, 1e-9)
+    Ms = np.array([[[8e5, 8e5]], [[0.0, 0.0]], [[8e5, 8e5]]])
+    mat = C.Material(Ms, np.zeros(Ms.shape), np.zeros(Ms.shape))
+    m = np.zeros((3, 3, 1, 2))
+    m[0, 0] = 1.0
+    m[2, 1] = 1.0
+    m[1, 2] = 1.0
+    ex = C.Extra(k_lo=0, k_hi=2, J=1e-3, D_int=(0.0, 0.0, 2e-3))
+    c = 1.0 / (MU0 * 8e5 * 1e-9)
+    H = C.interlayer_field(m, mesh, mat, ex)
+    np.testing.assert_allclose(H[:, 0, 0, :], c * np.array([[-2e-3] * 2, [1e-3] * 2, [0.0] * 2]), rtol=1e-12)
+    np.testing.assert_allclose(H[:, 2, 0, :], c * np.array([[1e-3] * 2, [-2e-3] * 2, [0.0] * 2]), rtol=1e-12)
+    assert np.all(H[:, 1] == 0)
+    assert C.interlayer_energy(m, mesh, mat, ex) == pytest.approx(2 * 2e-9 * 3e-9 * 2e-3, rel=1e-12)
+    p = F.Params(Ms=1.0, terms=C.INTERLAYER)
+    E = C.full_energies(m, mesh, p, mat, ex)
+    assert E[0] == pytest.approx(0.0, abs=1e-40) and E[2] == pytest.approx(2 * 2e-9 * 3e-9 * 2e-3, rel=1e-12)
+
+
+def test_interlayer_field_is_energy_gradient():
+    mesh = F.Mesh(3, 2, 4, 2e-9, 3e-9, 1.5e-9)
+    rng = np.random.default_rng(21)
+    Ms = rng.uniform(3e5, 9e5, size=(4, 2, 3))
+    Ms[1] = 0.0
+    Ms[3, 1, 2] = 0.0
+    mat = C.Material(Ms, np.zeros(Ms.shape), np.zeros(Ms.shape))
+    m = _unit((4, 2, 3), 22)
+    ex = C.Extra(k_lo=0, k_hi=3, J=-1.5e-3, D_int=(0.4e-3, -0.7e-3, 1.1e-3))
+    V = mesh.dx * mesh.dy * mesh.dz
+    H = C.interlayer_field(m, mesh, mat, ex)
+    g = np.zeros_like(m)
+    eps = 1e-6
+    for idx in np.ndindex(*m.shape):
+        mp_, mm_ = m.copy(), m.copy()
+        mp_[idx] += eps
+        mm_[idx] -= eps
+        g[idx] = (C.interlayer_energy(mp_, mesh, mat, ex) - C.interlayer_energy(mm_, mesh, mat, ex)) / (2 * eps)
+    mag = Ms > 0
+    np.testing.assert_allclose(H[:, mag], -g[:, mag] / (MU0 * Ms[mag] * V), rtol=1e-6,
+                               atol=1e-6 * np.max(np.abs(H)))
+    assert np.all(H[:, ~mag] == 0)
+    # the energies seen through the fields: -(mu0/2) V sum Ms m.H
+    assert -0.5 * MU0 * V * np.sum(Ms[None] * m * H) == pytest.approx(C.interlayer_energy(m, mesh, mat, ex),
+                                                                       rel=1e-12)
+
+
+def _cross(a, b):
+    return np.cross(a, b, axis=0)
+
+
+def test_spin_orbit_torque_satisfies_the_printed_equation():
+    """dm/dt of the LL form with the torque folded into H satisfies the paper's
+    Gilbert form: dm/dt - alpha m x dm/dt = -a_J m x (m x p) - b_J m x p (H = 0 otherwise)."""
+    mesh = F.Mesh(4, 3, 2, 2e-9, 2e-9, 2e-9)
+    mat = _const((2, 3, 4), 6e5, 0.0, 0.0)
+    m = _unit((2, 3, 4), 31)
+    ex = C.Extra(a_J=2.3e9, b_J=-0.7e9, p=(0.3, 1.0, -0.2))
+    p = F.Params(Ms=1.0, alpha=0.27, terms=C.STT_SOT)
+    k = C.full_llg_rhs(m, mesh, p, mat, ex)
+    pv = ex.p.reshape(3, 1, 1, 1) * np.ones_like(m)
+    lhs = k - p.alpha * _cross(m, k)
+    rhs = -ex.a_J * _cross(m, _cross(m, pv)) - ex.b_J * _cross(m, pv)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12, atol=1e-12 * np.max(np.abs(rhs)))
+
+
+def test_zhang_li_translates_a_spiral_rigidly():
+    """With alpha = beta and no other term the Zhang-Li torque moves a texture with
+    velocity u: on the interior cells of a spiral m = (sin qx, 0, cos qx) the
+    central difference gives (u . grad) m = u sin(q dx)/dx (cos qx, 0, -sin qx) (worked
+    by hand), so dm/dt = -that.  For beta != alpha the printed Gilbert form holds:
+    dm/dt - alpha m x dm/dt = -(u . grad) m + beta m x (u . grad) m."""
+    nx, dx, q, u = 40, 2e-9, 2 * math.pi / 37e-9, 85.0
+    mesh = F.Mesh(nx, 3, 1, dx, 2e-9, 1e-9)
+    x = np.arange(nx) * dx
+    m = np.zeros((3, 1, 3, nx))
+    m[0], m[2] = np.sin(q * x), np.cos(q * x)
+    mat = _const((1, 3, nx), 7e5, 0.0, 0.0)
+    v = np.zeros_like(m)
+    v[0], v[2] = np.cos(q * x), -np.sin(q * x)
+    v *= u * math.sin(q * dx) / dx
+    sl = (slice(None), slice(None), slice(None), slice(1, -1))
+    ex = C.Extra(u=(u, 0.0, 0.0), beta=0.3)
+    k = C.full_llg_rhs(m, mesh, F.Params(Ms=1.0, alpha=0.3, terms=C.STT_ZL), mat, ex)
+    np.testing.assert_allclose(k[sl], -v[sl], rtol=1e-10, atol=1e-10 * np.max(np.abs(v)))
+    ex = C.Extra(u=(u, 0.0, 0.0), beta=0.05)
+    p = F.Params(Ms=1.0, alpha=0.2, terms=C.STT_ZL)
+    k = C.full_llg_rhs(m, mesh, p, mat, ex)
+    lhs = k - p.alpha * _cross(m, k)
+    rhs = -v + ex.beta * _cross(m, v)
+    np.testing.assert_allclose(lhs[sl], rhs[sl], rtol=1e-10, atol=1e-10 * np.max(np.abs(v)))
+    # one-sided differences at the ends, none across an empty cell
+    d = C.directional_derivative(m, mesh, mat, (u, 0.0, 0.0))
+    np.testing.assert_allclose(d[:, :, :, 0], u * (m[:, :, :, 1] - m[:, :, :, 0]) / dx, rtol=1e-12)
+    Ms = np.full((1, 3, nx), 7e5)
+    Ms[:, :, 10] = 0.0
+    d = C.directional_derivative(m, mesh, C.Material(Ms, Ms * 0, Ms * 0), (u, 0.0, 0.0))
+    np.testing.assert_allclose(d[:, :, :, 9], u * (m[:, :, :, 9] - m[:, :, :, 8]) / dx, rtol=1e-12)
+    assert np.all(d[:, :, :, 10] == 0)
