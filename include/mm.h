@@ -58,14 +58,17 @@ enum {
   MM_ZEEMAN = 16u,          /* uniform static applied field                         */
   MM_DMI_BULK = 32u,        /* bulk (classes T, O) DMI, e_ij = r_ij                 */
   MM_DMI_D2D = 64u,         /* class D2d DMI, e_ij = {e_x, -e_x, -e_y, e_y, 0, 0}   */
-  MM_CELLS = 128u           /* cell-based Ms, A, D of the instance (mm_plan_set_cells) */
+  MM_CELLS = 128u,          /* cell-based Ms, A, D of the instance (mm_plan_set_cells) */
+  MM_INTERLAYER = 256u,     /* RKKY and interlayer DMI between layers k_lo and k_hi   */
+  MM_STT_SOT = 512u,        /* Slonczewski / spin-orbit torque (a_J, b_J, p)          */
+  MM_STT_ZL = 1024u         /* Zhang-Li spin-transfer torque (u_zl, beta)             */
 };
 /* the five terms of the standard path; MM_TERM_MASK: every known bit.  The
  * three DMI classes share the constant D; each enabled one adds its field
  * (section "Dzyaloshinskii-Moriya Energy", the unified neighbour form) and
  * its energy to the DMI entry. */
 #define MM_ALL_TERMS 31u
-#define MM_TERM_MASK 255u
+#define MM_TERM_MASK 2047u
 
 /* Regular mesh of nx*ny*nz cuboid cells of size dx*dy*dz (paper: FDMesh).
  * Limits: 1 <= n <= 1024 per axis, nx >= 2; d > 0 and finite. */
@@ -74,13 +77,37 @@ typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } mm_mesh;
 /* Uniform material and field parameters of one instance.
  * u: easy axis (normalised by the library); H: applied field (A/m).
  * alpha >= 0, gamma > 0 (2.21e5 is the paper's value), Ms > 0.
- * terms: subset of the plan's terms that is switched on. */
+ * terms: subset of the plan's terms that is switched on.
+ * The fields after `terms` are read only when their term is on:
+ * MM_INTERLAYER (section "Interlayer Exchange Interaction"): layers
+ *   z = k_lo and z = k_hi (0 <= k_lo < k_hi < nz) couple cell by cell (x, y)
+ *   with the energy per area -J_rkky m_lo . m_hi + D_int . (m_lo x m_hi)
+ *   (J/m^2); the field at k_lo is (J_rkky m_hi + D_int x m_hi)/(mu0 Ms dz), at
+ *   k_hi (J_rkky m_lo - D_int x m_lo)/(mu0 Ms dz); only magnetic pairs couple.
+ *   Its energies add to the exchange (RKKY) and DMI (interlayer DMI) entries.
+ * MM_STT_SOT (section "Spin transfer torques", eq_llg_stt2): the torque
+ *   -a_J m x (m x p) - b_J m x p (a_J, b_J in 1/s; p normalised by the
+ *   library), folded into H_eff as (b_J p + a_J m x p)/gamma.
+ * MM_STT_ZL (eq_llg_stt, Zhang-Li): -(u . grad) m + beta m x (u . grad) m with
+ *   the drift velocity u_zl (m/s), folded into H_eff as -(m x v + beta v)/gamma,
+ *   v = (u . grad) m by central differences (one-sided next to a missing or
+ *   empty neighbour, zero with neither).
+ * Torques carry no energy.  These three terms and MM_CELLS run in the
+ * general-material form of the inverse-x epilogue (plans only; batches and
+ * NEB chains refuse them). */
 typedef struct {
   double Ms, A, D, Ku;
   double u[3];
   double H[3];
   double alpha, gamma;
   uint32_t terms;
+  int32_t k_lo, k_hi;
+  double J_rkky;
+  double D_int[3];
+  double a_J, b_J;
+  double p[3];
+  double u_zl[3];
+  double beta;
 } mm_params;
 
 /* Adaptive Dormand-Prince state of one instance (caller owned, plain data so it
@@ -130,7 +157,7 @@ mm_status mm_plan_destroy(mm_plan* plan);
  * D_ij = 0 unless D_i D_j > 0; A_ij = 0 when A_i + A_j = 0; the demag input is
  * M = Ms_i m_i; energies weight each cell by its Ms_i.  m must hold unit
  * vectors in every cell, empty ones included (they are carried unchanged).
- * All instances of one call either use MM_CELLS or none does (MM_E_ARG);
+ * Instances of one call may mix cell-based and uniform material;
  * MM_E_STATE when a call's instance uses MM_CELLS before its slot was set.
  * Batches (mm_batch_*) and NEB chains take uniform material only.
  * Allocates the plan's cell arrays on first use; synchronises. */

@@ -649,9 +649,9 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
     const int cpt = inv_cpt(gs, nt);
     const bool fuse = fuse_next && demag && mode == MODE_STAGE && cpt > 0;
     mark();
-    // cell-based material: single-group launches whose instances all use it
-    const bool cells = gs.n == 1 && gs.h[0].cells != nullptr;
-    if (cells) {
+    // general-material form (cell arrays, interlayer coupling, spin torques): plans only
+    const bool gen = gs.n == 1 && gs.h[0].gen != 0;
+    if (gen) {
       if (demag) inv_x_launch<T, true, true>(mode, cpt, fuse, lb.L, lb.total, nt, lds, s);
       else inv_x_launch<T, false, true>(mode, cpt, false, lb.L, lb.total, nt, 0, s);
     } else {

@@ -207,8 +207,9 @@ __global__ void __launch_bounds__(512) k_fwd_x(Launch<T> L) {
   tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
   const T* in = ldu(&L.epis[gi].in);
   const size_t rows0 = ((size_t)z * g.ny + y0) * g.nx;
+  const bool cellarr = hp.cells && (ldu(&hp.prm[b].terms) & MM_CELLS);
   XRowLoad<T> ld{in + ((size_t)b * 3 + c) * g.N + rows0, g.nx, (g.nx & 1) == 0,
-                 hp.cells ? hp.cells + (size_t)b * 3 * g.N + rows0 : nullptr};
+                 cellarr ? hp.cells + (size_t)b * 3 * g.N + rows0 : nullptr};
   auto hook = [&]() { tab.store(twl); };
   // all nx / 2 packed inputs present and the rest zero when nx = Lx (even)
   const bool hin = ld.pairs && g.nx == g.Lx;
@@ -1047,7 +1048,7 @@ __device__ __forceinline__ Nbr<T> load_nbr(const Geo& g, uint32_t terms, const T
   n.mi = ld3o(mb, co);
   n.xm = {T(0), T(0), T(0)};
   n.xp = n.xm; n.ym = n.xm; n.yp = n.xm; n.zm = n.xm; n.zp = n.xm;
-  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL | MM_DMI_BULK | MM_DMI_D2D)) {
+  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL | MM_DMI_BULK | MM_DMI_D2D | MM_STT_ZL)) {
     const long long nxy = (long long)g.nx * g.ny;
     if (x > 0) n.xm = ld3o(mb - 1, co);
     if (x + 1 < g.nx) n.xp = ld3o(mb + 1, co);
@@ -1127,17 +1128,41 @@ __device__ __forceinline__ V3<T> local_field(const Geo& g, const LocalCoef<T>& P
   return H;
 }
 
-// Cell-based material (MM_CELLS): each instance's cells carry Ms, A and D in a
-// [3][N] array laid out like m (so the same byte offsets reach them).  Pair
-// couplings are the harmonic means of the exchange and DMI sections,
-// A_ij = 2 A_i A_j / (A_i + A_j) and D_ij = 2 D_i D_j / (D_i + D_j) (0 unless
-// D_i D_j > 0); a neighbour that is missing or empty (Ms = 0) couples with 0.
-// Order of the six neighbours: -x, +x, -y, +y, -z, +z.
+// General-material form of the local field (instances with cell-based
+// material, interlayer coupling or spin torques).  Material per cell: with
+// MM_CELLS each instance's cells carry Ms, A and D in a [3][N] array laid out
+// like m (the same byte offsets reach them), else the instance's uniform
+// values stand for every cell.  Pair couplings are the harmonic means of the
+// exchange and DMI sections, A_ij = 2 A_i A_j / (A_i + A_j) and
+// D_ij = 2 D_i D_j / (D_i + D_j) (0 unless D_i D_j > 0); a neighbour that is
+// missing or empty (Ms = 0) couples with 0.  Neighbour order: -x, +x, -y, +y,
+// -z, +z.
 template <typename T> struct CellNbr {
-  T ms;     // Ms of the cell (0: empty)
-  T a[6];   // A_ij
-  T d[6];   // D_ij
+  T ms;       // Ms of the cell (0: empty)
+  T a[6];     // A_ij
+  T d[6];     // D_ij
+  uint32_t nbm;  // bit k: neighbour k present and magnetic
+  int il;     // interlayer partner: +1 (this is layer k_lo), -1 (k_hi), 0 none
+  V3<T> mo;   // the partner's m
 };
+
+// What the material loads need of the instance (scalar registers).
+template <typename T> struct CellCtx {
+  uint32_t terms;
+  T Mu, Au, Du;
+  int k_lo, k_hi;
+};
+template <typename T>
+__device__ __forceinline__ CellCtx<T> cell_ctx(const DevParams* p) {
+  CellCtx<T> c;
+  c.terms = ldu(&p->terms);
+  c.Mu = T(ldu(&p->Mu));
+  c.Au = T(ldu(&p->Au));
+  c.Du = T(ldu(&p->Du));
+  c.k_lo = ldu(&p->k_lo);
+  c.k_hi = ldu(&p->k_hi);
+  return c;
+}
 
 template <typename T>
 __device__ __forceinline__ T harmonic_a(T ai, T aj) {
@@ -1149,43 +1174,72 @@ __device__ __forceinline__ T harmonic_d(T di, T dj) {
   return di * dj > T(0) ? T(2) * di * dj / (di + dj) : T(0);
 }
 
+// cb: the instance's cell arrays (read only with MM_CELLS); mb: its m
 template <typename T>
-__device__ __forceinline__ CellNbr<T> load_cells(const Geo& g, uint32_t terms, const T* __restrict__ cb,
-                                                 const COff& co, int x, int y, int z) {
+__device__ __forceinline__ CellNbr<T> load_cells(const Geo& g, const CellCtx<T>& cx, const T* __restrict__ cb,
+                                                 const T* __restrict__ mb, const COff& co, int x, int y, int z) {
   CellNbr<T> c;
-  const V3<T> me = ld3o(cb, co);
+  const bool arr = (cx.terms & MM_CELLS) != 0;
+  const V3<T> me = arr ? ld3o(cb, co) : V3<T>{cx.Mu, cx.Au, cx.Du};
   c.ms = me.x;
+  c.nbm = 0u;
+  c.il = 0;
+  c.mo = {T(0), T(0), T(0)};
 #pragma unroll
   for (int k = 0; k < 6; ++k) { c.a[k] = T(0); c.d[k] = T(0); }
-  if (terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL | MM_DMI_BULK | MM_DMI_D2D)) {
-    const long long nxy = (long long)g.nx * g.ny;
-    V3<T> nb[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) nb[k] = {T(0), T(0), T(0)};
-    if (x > 0) nb[0] = ld3o(cb - 1, co);
-    if (x + 1 < g.nx) nb[1] = ld3o(cb + 1, co);
-    if (y > 0) nb[2] = ld3o(cb - g.nx, co);
-    if (y + 1 < g.ny) nb[3] = ld3o(cb + g.nx, co);
-    if (z > 0) nb[4] = ld3o(cb - nxy, co);
-    if (z + 1 < g.nz) nb[5] = ld3o(cb + nxy, co);
+  const long long nxy = (long long)g.nx * g.ny;
+  if (cx.terms & (MM_EXCHANGE | MM_DMI_INTERFACIAL | MM_DMI_BULK | MM_DMI_D2D | MM_STT_ZL)) {
+    const bool in[6] = {x > 0, x + 1 < g.nx, y > 0, y + 1 < g.ny, z > 0, z + 1 < g.nz};
+    const long long off[6] = {-1, 1, -(long long)g.nx, (long long)g.nx, -nxy, nxy};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const bool on = me.x > T(0) && nb[k].x > T(0);
-      c.a[k] = on ? harmonic_a(me.y, nb[k].y) : T(0);
-      c.d[k] = on ? harmonic_d(me.z, nb[k].z) : T(0);
+      V3<T> o = {T(0), T(0), T(0)};
+      if (in[k]) o = arr ? ld3o(cb + off[k], co) : me;
+      const bool on = me.x > T(0) && o.x > T(0);
+      c.a[k] = on ? harmonic_a(me.y, o.y) : T(0);
+      c.d[k] = on ? harmonic_d(me.z, o.z) : T(0);
+      c.nbm |= on ? (1u << k) : 0u;
     }
+  }
+  if ((cx.terms & MM_INTERLAYER) && (z == cx.k_lo || z == cx.k_hi)) {
+    const long long off = (long long)((z == cx.k_lo ? cx.k_hi : cx.k_lo) - z) * nxy;
+    const T mso = arr ? gldo(cb + off, co.o[0]) : cx.Mu;
+    c.mo = ld3o(mb + off, co);
+    c.il = me.x > T(0) && mso > T(0) ? (z == cx.k_lo ? 1 : -1) : 0;
   }
   return c;
 }
 
-// Local field of a cell with cell-based material.  P holds the unit
-// coefficients of such instances: cex[a] = 2/(mu0 d_a^2), cdmi[a] = 1/(mu0 d_a),
-// can = 2 Ku / mu0; each term carries the cell's own 1/Ms_i.  An empty cell
-// has no field.  Missing or empty neighbours have zero couplings (their m,
-// zero where the mesh ends, drops out).
+// Coefficients of the general form beyond LocalCoef (interlayer, torques).
+template <typename T> struct GenCoef {
+  T crk, cdi[3], sa, sb, sp[3], zu[3], zbeta;
+};
+template <typename T>
+__device__ __forceinline__ GenCoef<T> gen_coef(const DevParams& P) {
+  GenCoef<T> q;
+  q.crk = T(P.crk);
+  q.sa = T(P.sa);
+  q.sb = T(P.sb);
+  q.zbeta = T(P.zbeta);
+  for (int a = 0; a < 3; ++a) {
+    q.cdi[a] = T(P.cdi[a]);
+    q.sp[a] = T(P.sp[a]);
+    q.zu[a] = T(P.zu[a]);
+  }
+  return q;
+}
+
+// Local field of a cell in the general form.  P holds the unit coefficients
+// cex[a] = 2/(mu0 d_a^2), cdmi[a] = 1/(mu0 d_a), can = 2 Ku / mu0; each term
+// carries the cell's own 1/Ms_i.  An empty cell has no field.  Missing or
+// empty neighbours have zero couplings (their m, zero where the mesh ends,
+// drops out).  Interlayer: (J m_o +- D_int x m_o)/(mu0 Ms dz) (+ at layer
+// k_lo); spin-orbit torque: (b_J p + a_J m x p)/gamma; Zhang-Li:
+// -(m x v + beta v)/gamma with v = (u . grad) m (central differences, one-sided
+// next to a missing neighbour).
 template <typename T, bool ENERGY>
-__device__ __forceinline__ V3<T> local_field_cells(const LocalCoef<T>& P, const Nbr<T>& nb, const CellNbr<T>& cn,
-                                                   LocalTerms* lt) {
+__device__ __forceinline__ V3<T> local_field_cells(const LocalCoef<T>& P, const GenCoef<T>& Q, const Nbr<T>& nb,
+                                                   const CellNbr<T>& cn, LocalTerms* lt) {
   V3<T> H = {T(0), T(0), T(0)};
   if (!(cn.ms > T(0))) return H;
   const T inv = T(1) / cn.ms;
@@ -1242,6 +1296,41 @@ __device__ __forceinline__ V3<T> local_field_cells(const LocalCoef<T>& P, const 
   if (P.terms & MM_ZEEMAN) {
     H.x += P.H[0]; H.y += P.H[1]; H.z += P.H[2];
     if (ENERGY) lt->ze = (double)mi.x * P.H[0] + (double)mi.y * P.H[1] + (double)mi.z * P.H[2];
+  }
+  if (cn.il != 0) {  // interlayer exchange and DMI with the partner layer
+    const V3<T> mo = cn.mo;
+    const T cj = Q.crk * inv, sg = cn.il > 0 ? inv : -inv;
+    const V3<T> hj = {cj * mo.x, cj * mo.y, cj * mo.z};
+    const V3<T> hd = {sg * (Q.cdi[1] * mo.z - Q.cdi[2] * mo.y), sg * (Q.cdi[2] * mo.x - Q.cdi[0] * mo.z),
+                      sg * (Q.cdi[0] * mo.y - Q.cdi[1] * mo.x)};
+    H.x += hj.x + hd.x; H.y += hj.y + hd.y; H.z += hj.z + hd.z;
+    if (ENERGY) {
+      lt->ex += (double)mi.x * hj.x + (double)mi.y * hj.y + (double)mi.z * hj.z;
+      lt->dmi += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
+    }
+  }
+  if (P.terms & MM_STT_SOT) {  // (b_J p + a_J m x p) / gamma
+    const T px = Q.sp[0], py = Q.sp[1], pz = Q.sp[2];
+    H.x += Q.sb * px + Q.sa * (mi.y * pz - mi.z * py);
+    H.y += Q.sb * py + Q.sa * (mi.z * px - mi.x * pz);
+    H.z += Q.sb * pz + Q.sa * (mi.x * py - mi.y * px);
+  }
+  if (P.terms & MM_STT_ZL) {  // -(m x v + beta v) / gamma, v = (u . grad) m
+    V3<T> v = {T(0), T(0), T(0)};
+    auto axis = [&](V3<T> p_, V3<T> m_, uint32_t bp, uint32_t bm, T c) {
+      const bool hp = (cn.nbm & bp) != 0, hm = (cn.nbm & bm) != 0;
+      V3<T> g_ = {T(0), T(0), T(0)};
+      if (hp && hm) g_ = {T(0.5) * (p_.x - m_.x), T(0.5) * (p_.y - m_.y), T(0.5) * (p_.z - m_.z)};
+      else if (hp) g_ = {p_.x - mi.x, p_.y - mi.y, p_.z - mi.z};
+      else if (hm) g_ = {mi.x - m_.x, mi.y - m_.y, mi.z - m_.z};
+      v.x += c * g_.x; v.y += c * g_.y; v.z += c * g_.z;
+    };
+    axis(xp, xm, 2u, 1u, Q.zu[0]);
+    axis(yp, ym, 8u, 4u, Q.zu[1]);
+    axis(zp, zm, 32u, 16u, Q.zu[2]);
+    H.x -= (mi.y * v.z - mi.z * v.y) + Q.zbeta * v.x;
+    H.y -= (mi.z * v.x - mi.x * v.z) + Q.zbeta * v.y;
+    H.z -= (mi.x * v.y - mi.y * v.x) + Q.zbeta * v.z;
   }
   return H;
 }
@@ -1391,10 +1480,11 @@ __device__ inline void control_step(DevCtl& C, const double* __restrict__ replay
 // these rows is transformed forward along x here, into the same Sx rows this
 // workgroup read (no other workgroup touches them), which takes the forward x
 // pass of the next evaluation off the critical path.
-// CELLS: cell-based material (every instance of the launch has MM_CELLS):
-// the local terms use the cells' Ms, A, D (local_field_cells), an empty cell
-// gets no demag field either, energies weight each cell by its Ms, and the
-// fused forward transform takes Ms m.
+// CELLS: the general-material form (cell-based material, interlayer
+// coupling, spin torques; local_field_cells): every cell's terms carry its own
+// Ms, A_ij, D_ij, an empty cell gets no demag field either, energies weight
+// each cell by its Ms, and with cell arrays the fused forward transform takes
+// Ms m.
 template <typename T, bool DEMAG, int MODE, int CPT, bool FUSE, bool CELLS>
 __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   constexpr bool PREF = CPT == 1;
@@ -1496,7 +1586,9 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     const size_t ib = (size_t)b * ldu(&ep->inst_stride);
     const COff co = coff_of<T>(N, (z * g.ny + y0 + rc) * g.nx + xc);
     pnb = load_nbr<T>(g, ldu(&hp.prm[b].terms), ldu(&ep->in) + ib, co, xc, y0 + rc, z);
-    if constexpr (CELLS) pcn = load_cells<T>(g, ldu(&hp.prm[b].terms), hp.cells + (size_t)b * 3 * N, co, xc, y0 + rc, z);
+    if constexpr (CELLS)
+      pcn = load_cells<T>(g, cell_ctx<T>(hp.prm + b), hp.cells + (size_t)b * 3 * N, ldu(&ep->in) + ib, co, xc,
+                          y0 + rc, z);
     if constexpr (MODE == MODE_STAGE) pbase = ld3o(ldu(&ep->mbase) + ib, co);
     if constexpr (MODE == MODE_STAGE || MODE == MODE_ERROR) {
       const int nk = ldu(&ep->nk);
@@ -1551,6 +1643,12 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
   const Epi<T> epi = ldu(L.epis + gi);
   const DevParams Pd = ldu(hp.prm + b);
   const LocalCoef<T> P = local_coef<T>(Pd);
+  GenCoef<T> Q;
+  CellCtx<T> ccx;
+  if constexpr (CELLS) {
+    Q = gen_coef<T>(Pd);
+    ccx = cell_ctx<T>(hp.prm + b);
+  }
   const T g1 = T(Pd.g1), g2 = T(Pd.g2);
   const T* mb = epi.in + (size_t)b * epi.inst_stride;
   double esum[5] = {0, 0, 0, 0, 0};
@@ -1582,7 +1680,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     const COff co = coff_of<T>(N, (z * g.ny + y) * g.nx + x);
     const Nbr<T> nb = PREF ? pnb : load_nbr<T>(g, P.terms, mb, co, x, y, z);
     CellNbr<T> cn;
-    if constexpr (CELLS) cn = PREF ? pcn : load_cells<T>(g, P.terms, hp.cells + (size_t)b * 3 * N, co, x, y, z);
+    if constexpr (CELLS) cn = PREF ? pcn : load_cells<T>(g, ccx, hp.cells + (size_t)b * 3 * N, mb, co, x, y, z);
     const size_t ib = (size_t)b * epi.inst_stride;
     // the stage's earlier slopes (and m for the stage input), all issued
     // before any of them is used: one memory round trip per cell, not one per
@@ -1607,8 +1705,8 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
     LocalTerms lt = {0, 0, 0, 0};
     V3<T> H;
     if constexpr (CELLS) {
-      if constexpr (energy) H = local_field_cells<T, true>(P, nb, cn, &lt);
-      else H = local_field_cells<T, false>(P, nb, cn, nullptr);
+      if constexpr (energy) H = local_field_cells<T, true>(P, Q, nb, cn, &lt);
+      else H = local_field_cells<T, false>(P, Q, nb, cn, nullptr);
     } else {
       if constexpr (energy) H = local_field<T, true>(g, P, nb, x, y, z, &lt);
       else H = local_field<T, false>(g, P, nb, x, y, z, nullptr);
@@ -1660,7 +1758,8 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
         else st3o(epi.msn + ib, co, acc);
         if constexpr (FUSE) {
           mnext[slot] = acc;
-          if constexpr (CELLS) mnext[slot] = {acc.x * cn.ms, acc.y * cn.ms, acc.z * cn.ms};  // M = Ms m
+          if constexpr (CELLS)  // cell arrays: the transform takes M = Ms m
+            if (P.terms & MM_CELLS) mnext[slot] = {acc.x * cn.ms, acc.y * cn.ms, acc.z * cn.ms};
         }
       } else if constexpr (MODE == MODE_ERROR) {
         double ex = 0, ey = 0, ez = 0;

@@ -98,6 +98,8 @@ template <typename T> struct HotPlan {
   Cx<T>* Sy;               // [batch][3][nz][Xp][Py] (3-D only)
   const DevParams* prm;    // [batch]
   const T* cells;          // cell-based material [batch][3][N] (Ms, A, D per cell) or null
+  int gen;                 // launch the general-material form of the inverse-x epilogue
+  int pad_;
 };
 
 constexpr int kMaxGroups = 16;

@@ -131,9 +131,20 @@ struct DevParams {
   double u[3];       // easy axis, normalised
   double H[3];       // applied field
   double g1, g2;     // -gamma/(1+alpha^2), -alpha gamma/(1+alpha^2)
-  double demag_scale;  // -Ms / (Px Py Pz)
+  double demag_scale;  // -Ms / (Px Py Pz)  (cell-based Ms: -1 / (Px Py Pz), Ms inside M)
   uint32_t terms;
   uint32_t pad;
+  // general-material form (cell arrays, interlayer coupling, spin torques);
+  // there cex = 2/(mu0 d^2), cdmi = 1/(mu0 d), can = 2 Ku / mu0 and each cell
+  // applies its own Ms, A_ij, D_ij
+  double Mu, Au, Du;   // uniform Ms, A, D (instances without cell arrays)
+  double crk;          // J_rkky / (mu0 dz)
+  double cdi[3];       // D_int / (mu0 dz)
+  double sa, sb;       // a_J / gamma, b_J / gamma
+  double sp[3];        // polarisation p, normalised
+  double zu[3];        // u_zl[a] / (gamma d_a)
+  double zbeta;        // beta
+  int32_t k_lo, k_hi;  // interlayer layers
 };
 
 // Per-instance Dormand-Prince controller state in device memory.

@@ -263,7 +263,7 @@ struct Engine {
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   double* he5 = nullptr;
   bool any_demag = false;
-  bool use_cells = false;  // the instances of the current call use cell-based material
+  bool use_general = false;  // the current call runs the general-material form (kGeneralTerms)
   // graph cache of the Dormand-Prince attempt sequence
   hipGraphExec_t gexec = nullptr;
   std::vector<const void*> g_key;
@@ -308,13 +308,32 @@ mm_status check_params(const Engine& E, const mm_params* q, int n) {
     if ((r.terms & ~E.terms) != 0) return fail(MM_E_ARG, "params enable a term the plan was not built for");
     if ((r.terms & MM_ANIS_UNIAXIAL) && r.u[0] == 0 && r.u[1] == 0 && r.u[2] == 0)
       return fail(MM_E_ARG, "easy axis must be non-zero");
-    if (((r.terms ^ q[0].terms) & MM_CELLS) != 0)
-      return fail(MM_E_ARG, "either every instance of a call uses cell-based material (MM_CELLS) or none does");
+    if (r.terms & MM_INTERLAYER) {
+      const double v2[] = {r.J_rkky, r.D_int[0], r.D_int[1], r.D_int[2]};
+      for (double x : v2)
+        if (!is_fin(x)) return fail(MM_E_ARG, "interlayer parameters must be finite");
+    }
+    if (r.terms & MM_STT_SOT) {
+      const double v2[] = {r.a_J, r.b_J, r.p[0], r.p[1], r.p[2]};
+      for (double x : v2)
+        if (!is_fin(x)) return fail(MM_E_ARG, "spin-orbit torque parameters must be finite");
+      if (r.p[0] == 0 && r.p[1] == 0 && r.p[2] == 0) return fail(MM_E_ARG, "polarisation p must be non-zero");
+    }
+    if (r.terms & MM_STT_ZL) {
+      const double v2[] = {r.u_zl[0], r.u_zl[1], r.u_zl[2], r.beta};
+      for (double x : v2)
+        if (!is_fin(x)) return fail(MM_E_ARG, "Zhang-Li parameters must be finite");
+    }
   }
   return MM_OK;
 }
 
-DevParams dev_params(const mm_params& r, const Group& G) {
+// Terms that run in the general-material form of the inverse-x epilogue.
+constexpr uint32_t kGeneralTerms = MM_CELLS | MM_INTERLAYER | MM_STT_SOT | MM_STT_ZL;
+
+// general: the instance runs in the general-material form (unit coefficients;
+// each cell applies its Ms, A_ij, D_ij, and the extra terms' coefficients)
+DevParams dev_params(const mm_params& r, const Group& G, bool general) {
   DevParams o;
   std::memset(&o, 0, sizeof(o));
   const double P = (double)G.g.Px * G.g.Py * G.g.Pz;
@@ -332,14 +351,32 @@ DevParams dev_params(const mm_params& r, const Group& G) {
     o.u[k] = un > 0 ? r.u[k] / un : 0.0;
     o.H[k] = r.H[k];
   }
-  if (r.terms & MM_CELLS) {  // unit coefficients: the kernels apply each cell's Ms, A_ij, D_ij
-    o.Ms = 1.0;
+  if (general) {  // unit coefficients: the kernels apply each cell's Ms, A_ij, D_ij
     for (int a = 0; a < 3; ++a) {
       const double d = a == 0 ? G.mesh.dx : a == 1 ? G.mesh.dy : G.mesh.dz;
       o.cex[a] = 2.0 / (kMu0 * d * d);
       o.cdmi[a] = 1.0 / (kMu0 * d);
+      o.zu[a] = (r.terms & MM_STT_ZL) ? r.u_zl[a] / (r.gamma * d) : 0.0;
     }
     o.can = 2 * r.Ku / kMu0;
+    o.Mu = r.Ms;
+    o.Au = r.A;
+    o.Du = r.D;
+    if (r.terms & MM_INTERLAYER) {
+      o.k_lo = r.k_lo;
+      o.k_hi = r.k_hi;
+      o.crk = r.J_rkky / (kMu0 * G.mesh.dz);
+      for (int a = 0; a < 3; ++a) o.cdi[a] = r.D_int[a] / (kMu0 * G.mesh.dz);
+    } else {
+      o.k_lo = o.k_hi = -1;
+    }
+    if (r.terms & MM_STT_SOT) {
+      const double pn = std::sqrt(r.p[0] * r.p[0] + r.p[1] * r.p[1] + r.p[2] * r.p[2]);
+      o.sa = r.a_J / r.gamma;
+      o.sb = r.b_J / r.gamma;
+      for (int a = 0; a < 3; ++a) o.sp[a] = r.p[a] / pn;
+    }
+    o.zbeta = r.beta;
   }
   o.g1 = -r.gamma / (1 + r.alpha * r.alpha);
   o.g2 = -r.alpha * r.gamma / (1 + r.alpha * r.alpha);
@@ -619,9 +656,10 @@ mm_status upload_params(Engine& E, const std::vector<const mm_params*>& q, const
                         hipStream_t s) {
   std::vector<DevParams> d(q.size());
   E.any_demag = false;
-  E.use_cells = !q.empty() && (q[0]->terms & MM_CELLS) != 0;
+  E.use_general = false;
+  for (size_t b = 0; b < q.size(); ++b) E.use_general = E.use_general || (q[b]->terms & kGeneralTerms) != 0;
   for (size_t b = 0; b < q.size(); ++b) {
-    d[b] = dev_params(*q[b], E.groups[grp[b]]);
+    d[b] = dev_params(*q[b], E.groups[grp[b]], E.use_general);
     E.any_demag = E.any_demag || (q[b]->terms & MM_DEMAG) != 0;
   }
   HIPCHK(hipMemcpyAsync(E.prm, d.data(), sizeof(DevParams) * d.size(), hipMemcpyHostToDevice, s));
@@ -654,7 +692,8 @@ mm_status make_set(Engine& E, const std::vector<int>& nb, GroupSet<T>& gs, std::
     h.Sx = (Cx<T>*)G.Sx;
     h.Sy = (Cx<T>*)G.Sy;
     h.prm = E.prm + acc;
-    h.cells = E.use_cells ? (const T*)G.cells : nullptr;
+    h.cells = E.use_general ? (const T*)G.cells : nullptr;
+    h.gen = E.use_general ? 1 : 0;
     inst0[i] = acc;
     acc += nb[i];
   }
@@ -767,7 +806,7 @@ mm_status energy_finish(Engine& E, const mm_params* q, int batch, const double* 
   HIPCHK(hipMemcpyAsync(E.he5, e5, sizeof(double) * 5 * batch, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int b = 0; b < batch; ++b) {
-    const double c = kMu0 * ((q[b].terms & MM_CELLS) ? 1.0 : q[b].Ms) * G.g.dV;  // cells: Ms in the sums
+    const double c = kMu0 * (E.use_general ? 1.0 : q[b].Ms) * G.g.dV;  // general form: Ms in the sums
     for (int k = 0; k < 5; ++k) E_out[5 * b + k] = -(k == 4 ? 1.0 : 0.5) * c * E.he5[5 * b + k];
   }
   return MM_OK;
@@ -1558,12 +1597,13 @@ mm_status plan_checks(mm_plan* p, const mm_params* q, int batch) {
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (batch < 1 || batch > p->maxb) return fail(MM_E_ARG, "batch must be in [1, max_batch]");
   MMCHK(check_params(p->e, q, batch));
-  if (q[0].terms & MM_CELLS) {
-    const Group& G = p->e.groups[0];
-    for (int b = 0; b < batch; ++b)
-      if (b >= (int)G.cells_set.size() || !G.cells_set[b])
-        return fail(MM_E_STATE, "instance " + std::to_string(b) + " uses MM_CELLS but mm_plan_set_cells was "
-                                "not called for its slot");
+  const Group& G = p->e.groups[0];
+  for (int b = 0; b < batch; ++b) {
+    if ((q[b].terms & MM_CELLS) && (b >= (int)G.cells_set.size() || !G.cells_set[b]))
+      return fail(MM_E_STATE, "instance " + std::to_string(b) + " uses MM_CELLS but mm_plan_set_cells was "
+                              "not called for its slot");
+    if ((q[b].terms & MM_INTERLAYER) && !(q[b].k_lo >= 0 && q[b].k_lo < q[b].k_hi && q[b].k_hi < G.g.nz))
+      return fail(MM_E_ARG, "interlayer layers need 0 <= k_lo < k_hi < nz");
   }
   return MM_OK;
 }
@@ -1940,7 +1980,8 @@ mm_status mm_neb_run(mm_plan* p, const mm_params* q, void* images, int32_t n_img
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (n_img < 3 || n_img > p->maxb) return fail(MM_E_ARG, "n_img must be in [3, max_batch]");
   MMCHK(check_params(p->e, q, 1));
-  if (q->terms & MM_CELLS) return fail(MM_E_ARG, "NEB chains take uniform material (no MM_CELLS)");
+  if (q->terms & kGeneralTerms)
+    return fail(MM_E_ARG, "NEB chains take uniform material and no interlayer or torque terms");
   if (!images) return fail(MM_E_ARG, "images is null");
   if (!is_fin(k_spring) || !is_fin(h) || h <= 0 || n_iter < 1) return fail(MM_E_ARG, "invalid k_spring, h or n_iter");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -1958,7 +1999,8 @@ mm_status mm_batch_create(mm_batch** out, const mm_mesh* meshes, int32_t n_meshe
   if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
   for (int i = 0; i < n_meshes; ++i) MMCHK(check_cells(&meshes[i], prec));
   if (terms & ~MM_TERM_MASK) return fail(MM_E_ARG, "unknown term bits");
-  if (terms & MM_CELLS) return fail(MM_E_ARG, "batches take uniform material (no MM_CELLS)");
+  if (terms & kGeneralTerms)
+    return fail(MM_E_ARG, "batches take uniform material and no interlayer or torque terms");
   hipStream_t s = (hipStream_t)hip_stream;
   mm_batch* b = new mm_batch();
   mm_status st = engine_init(b->e, prec, terms);

@@ -22,6 +22,7 @@ EXCHANGE, DEMAG, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
 ALL_TERMS = 31
 DMI_BULK, DMI_D2D = 32, 64  # the other DMI symmetry classes (same D)
 CELLS = 128  # cell-based Ms, A, D of the instance (Plan.set_cells)
+INTERLAYER, STT_SOT, STT_ZL = 256, 512, 1024  # interlayer coupling, spin-orbit / Slonczewski and Zhang-Li torques
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmmx.so is not built; run `python -m paper_2406_16064_amd.build` "
@@ -37,7 +38,10 @@ class Mesh(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("D", ctypes.c_double),
                 ("Ku", ctypes.c_double), ("u", ctypes.c_double * 3), ("H", ctypes.c_double * 3),
-                ("alpha", ctypes.c_double), ("gamma", ctypes.c_double), ("terms", ctypes.c_uint32)]
+                ("alpha", ctypes.c_double), ("gamma", ctypes.c_double), ("terms", ctypes.c_uint32),
+                ("k_lo", ctypes.c_int32), ("k_hi", ctypes.c_int32), ("J_rkky", ctypes.c_double),
+                ("D_int", ctypes.c_double * 3), ("a_J", ctypes.c_double), ("b_J", ctypes.c_double),
+                ("p", ctypes.c_double * 3), ("u_zl", ctypes.c_double * 3), ("beta", ctypes.c_double)]
 
 
 class RK45State(ctypes.Structure):
@@ -110,14 +114,21 @@ def status_string(st):
 
 
 def make_params(Ms, A=0.0, D=0.0, Ku=0.0, u=(0.0, 0.0, 1.0), H=(0.0, 0.0, 0.0), alpha=0.5,
-                gamma=2.21e5, terms=ALL_TERMS):
-    p = Params()
-    p.Ms, p.A, p.D, p.Ku = Ms, A, D, Ku
+                gamma=2.21e5, terms=ALL_TERMS, k_lo=0, k_hi=0, J_rkky=0.0, D_int=(0.0, 0.0, 0.0), a_J=0.0,
+                b_J=0.0, p=(0.0, 0.0, 1.0), u_zl=(0.0, 0.0, 0.0), beta=0.0):
+    """mm_params of one instance (SI units; see include/mm.h for every field)."""
+    q = Params()
+    q.Ms, q.A, q.D, q.Ku = Ms, A, D, Ku
     for k in range(3):
-        p.u[k] = u[k]
-        p.H[k] = H[k]
-    p.alpha, p.gamma, p.terms = alpha, gamma, terms
-    return p
+        q.u[k] = u[k]
+        q.H[k] = H[k]
+        q.D_int[k] = D_int[k]
+        q.p[k] = p[k]
+        q.u_zl[k] = u_zl[k]
+    q.alpha, q.gamma, q.terms = alpha, gamma, terms
+    q.k_lo, q.k_hi, q.J_rkky = k_lo, k_hi, J_rkky
+    q.a_J, q.b_J, q.beta = a_J, b_J, beta
+    return q
 
 
 def _params_array(params):

@@ -59,7 +59,7 @@ def test_invalid_arguments_rejected_before_hip(mm):
         assert lib.mm_last_error()
     good = mm.Mesh(8, 8, 1, 1e-9, 1e-9, 1e-9)
     assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 7, 31, 1, None) == mm.MM_E_ARG
-    assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 256, 1, None) == mm.MM_E_ARG
+    assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 2048, 1, None) == mm.MM_E_ARG
     assert lib.mm_plan_create(ctypes.byref(out), ctypes.byref(good), 0, 31, 0, None) == mm.MM_E_ARG
     assert lib.mm_effective_field(None, None, 1, None, None, None) == mm.MM_E_ARG
     assert lib.mm_plan_destroy(None) == mm.MM_E_ARG

@@ -6,8 +6,12 @@ through the C interface: fields and dm/dt (FP64 to 1e-11, FP32 to 1e-5 of
 max |H|), energies (1e-10 / 1e-5 of sum |E|), a replayed Dormand-Prince
 trajectory and Heun steps (FP64 1e-9 / 1e-10 in m, FP32 1e-4), steepest
 descent (FP64 1e-9), a batch of two instances with different cell arrays, and
-the refusals (mixed instances, unset slot).  The FP32 runs compare against
-the oracle on the FP32-rounded cell values, as for m.
+the refusals (unset slot, bad values).  Then the other terms of the general
+form: interlayer RKKY and DMI across an empty spacer, Slonczewski/spin-orbit
+and Zhang-Li torques as fields (with cells, FP32 and FP64; each with uniform
+material; a batch mixing cell-based and uniform instances; a replayed FP32
+trajectory).  The FP32 runs compare against the oracle on the FP32-rounded
+cell values, as for m.
 """
 import numpy as np
 import pytest
@@ -182,11 +186,110 @@ def test_refusals(mm):
     plan.set_cells(0, mat.Ms, mat.A, mat.D)
     with pytest.raises(mm.MMError):  # slot 1 not set
         plan.llg_rhs([gp, gp], md)
-    uni = mm.make_params(Ms=8e5, A=1e-11, terms=ALL7, **UNI)
-    with pytest.raises(mm.MMError):  # mixed instances
-        plan.llg_rhs([gp, uni], md)
     with pytest.raises(mm.MMError):  # negative Ms
         plan.set_cells(1, -mat.Ms - 1.0, mat.A, mat.D)
     plain = mm.Plan(mesh, "f32", terms=ALL7)
     with pytest.raises(mm.MMError):  # plan without MM_CELLS
         plain.set_cells(0, mat.Ms, mat.A, mat.D)
+
+
+# ----------------------------------------------------------------------------- interlayer coupling, spin torques
+
+EXTRA = dict(k_lo=0, k_hi=3, J_rkky=-1.2e-3, D_int=(0.3e-3, -0.5e-3, 0.8e-3), a_J=3.1e9, b_J=-1.3e9,
+             p=(0.2, 1.0, -0.4), u_zl=(60.0, -35.0, 10.0), beta=0.15)
+MORE = C.INTERLAYER | C.STT_SOT | C.STT_ZL
+
+
+def _extra():
+    e = EXTRA
+    return C.Extra(e["k_lo"], e["k_hi"], e["J_rkky"], e["D_int"], e["a_J"], e["b_J"], e["p"], e["u_zl"], e["beta"])
+
+
+def _spacer_material(mesh, seed, prec):
+    """Two magnetic layers (z = 0 and 3) across an empty two-layer spacer, disk-shaped."""
+    mat = _material(mesh, seed, prec)
+    Ms = mat.Ms.copy()
+    Ms[1:3] = 0.0
+    return C.Material(Ms, mat.A, mat.D)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_interlayer_and_torques_with_cells(mm, prec):
+    mesh = (30, 26, 4, 2e-9, 2e-9, 1e-9)
+    mat = _spacer_material(mesh, 17, prec)
+    m = _state(mesh, 18, prec)
+    terms = ALL7 | MORE
+    plan = _plan(mm, mesh, prec, [mat], terms=terms)
+    gp = mm.make_params(Ms=1.0, terms=terms | CELLS, **UNI, **EXTRA)
+    op = _orc(terms)
+    md = to_dev(m, DT[prec])
+    H = plan.effective_field(gp, md).cpu().numpy()
+    Href = C.full_field(m, F.Mesh(*mesh), op, mat, _extra(), _kernel(mesh))
+    assert field_err(H, Href) <= TOL[prec]
+    k = plan.llg_rhs(gp, md).cpu().numpy()
+    assert field_err(k, F.llg_rhs_from_field(m, Href, op)) <= TOL[prec]
+    E = plan.energy(gp, md)[0]
+    Eref = C.full_energies(m, F.Mesh(*mesh), op, mat, _extra(), _kernel(mesh))
+    assert np.all(np.abs(E - Eref) <= (1e-5 if prec == "f32" else 1e-10) * np.sum(np.abs(Eref))), (E, Eref)
+
+
+@pytest.mark.parametrize("bit", [C.INTERLAYER, C.STT_SOT, C.STT_ZL])
+def test_each_extra_term_uniform_material_fp64(mm, bit):
+    """Uniform material (no cell arrays) with one interlayer or torque term: the
+    general form takes the instance's own Ms, A, D for every cell."""
+    mesh = (22, 18, 4, 2e-9, 2.5e-9, 1.5e-9)
+    par = dict(Ms=6.5e5, A=1.2e-11, D=2e-3)
+    mat = C.Material(*(np.full((4, 18, 22), par[k]) for k in ("Ms", "A", "D")))
+    m = _state(mesh, 19, "f64")
+    terms = F.EXCHANGE | F.DMI | bit
+    plan = mm.Plan(mesh, "f64", terms=terms)
+    gp = mm.make_params(terms=terms, **par, **UNI, **EXTRA)
+    H = plan.effective_field(gp, to_dev(m, torch.float64)).cpu().numpy()
+    Href = C.full_field(m, F.Mesh(*mesh), F.Params(terms=terms, **par, **UNI), mat, _extra())
+    assert field_err(H, Href) <= 1e-11
+
+
+def test_mixed_cells_and_uniform_batch_fp64(mm):
+    mesh = (30, 26, 4, 2e-9, 2e-9, 1e-9)
+    mat = _spacer_material(mesh, 20, "f64")
+    par = dict(Ms=7e5, A=1.4e-11, D=1e-3)
+    uni = C.Material(*(np.full((4, 26, 30), par[k]) for k in ("Ms", "A", "D")))
+    terms = ALL7 | MORE
+    plan = mm.Plan(mesh, "f64", terms=terms | CELLS, max_batch=2)
+    plan.set_cells(0, mat.Ms, mat.A, mat.D)
+    ms = np.stack([_state(mesh, 21, "f64"), _state(mesh, 22, "f64")])
+    gps = [mm.make_params(Ms=1.0, terms=terms | CELLS, **UNI, **EXTRA), mm.make_params(terms=terms, **par, **UNI, **EXTRA)]
+    k = plan.llg_rhs(gps, to_dev(ms, torch.float64)).cpu().numpy()
+    refs = [C.full_llg_rhs(ms[0], F.Mesh(*mesh), _orc(terms), mat, _extra(), _kernel(mesh)),
+            C.full_llg_rhs(ms[1], F.Mesh(*mesh), F.Params(terms=terms, **par, **UNI), uni, _extra(), _kernel(mesh))]
+    for b in range(2):
+        assert field_err(k[b], refs[b]) <= 1e-11
+
+
+def test_torque_trajectory_fp32_replay(mm):
+    mesh = (30, 26, 4, 2e-9, 2e-9, 1e-9)
+    mat = _spacer_material(mesh, 23, "f32")
+    m0 = _state(mesh, 24, "f32")
+    terms = ALL7 | MORE
+    op = _orc(terms)
+    f = lambda y: C.full_llg_rhs(y, F.Mesh(*mesh), op, mat, _extra(), _kernel(mesh))
+    ost = dp45.State(rtol=1e-5)
+    mo = dp45.run(f, m0.copy(), ost, max_accept=15)
+    plan = _plan(mm, mesh, "f32", [mat], terms=terms)
+    md = to_dev(m0, torch.float32)
+    plan.rk45_run(mm.make_params(Ms=1.0, terms=terms | CELLS, **UNI, **EXTRA), md, mm.new_states(1, rtol=1e-5),
+                  replay_h=ost.accepted_h)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-4
+
+
+def test_extra_term_refusals(mm):
+    mesh = (16, 12, 3, 2e-9, 2e-9, 2e-9)
+    plan = mm.Plan(mesh, "f32", terms=F.EXCHANGE | MORE)
+    md = to_dev(_state(mesh, 25, "f32"), torch.float32)
+    bad = dict(EXTRA, k_lo=1, k_hi=3)  # k_hi beyond nz - 1
+    with pytest.raises(mm.MMError):
+        plan.llg_rhs(mm.make_params(Ms=8e5, A=1e-11, terms=F.EXCHANGE | C.INTERLAYER, **bad), md)
+    with pytest.raises(mm.MMError):
+        plan.llg_rhs(mm.make_params(Ms=8e5, A=1e-11, terms=F.EXCHANGE | C.STT_SOT, **dict(EXTRA, p=(0, 0, 0))), md)
+    with pytest.raises(mm.MMError):  # batches take none of these terms
+        mm.Batch([mesh], "f32", terms=F.EXCHANGE | C.STT_ZL)
