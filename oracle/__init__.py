@@ -13,6 +13,7 @@ newell   cell-averaged demagnetisation tensor (Newell closed form near,
          Gauss-Legendre quadrature of its defining double volume integral far)
 fields   exchange, interfacial DMI, uniaxial anisotropy, Zeeman and demag
          fields, energies and the Landau-Lifshitz right-hand side
+potential  demag field through the magnetic scalar potential (vertex potential, edge differences)
 cells    cell-based Ms, A and D (harmonic means) and empty cells
 dp45     adaptive Dormand-Prince 5(4) with unit-sphere projection
 neb      nudged-elastic-band force and relaxation iteration
