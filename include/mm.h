@@ -61,14 +61,15 @@ enum {
   MM_CELLS = 128u,          /* cell-based Ms, A, D of the instance (mm_plan_set_cells) */
   MM_INTERLAYER = 256u,     /* RKKY and interlayer DMI between layers k_lo and k_hi   */
   MM_STT_SOT = 512u,        /* Slonczewski / spin-orbit torque (a_J, b_J, p)          */
-  MM_STT_ZL = 1024u         /* Zhang-Li spin-transfer torque (u_zl, beta)             */
+  MM_STT_ZL = 1024u,        /* Zhang-Li spin-transfer torque (u_zl, beta)             */
+  MM_DEMAG_POTENTIAL = 2048u /* demag through the magnetic scalar potential            */
 };
 /* the five terms of the standard path; MM_TERM_MASK: every known bit.  The
  * three DMI classes share the constant D; each enabled one adds its field
  * (section "Dzyaloshinskii-Moriya Energy", the unified neighbour form) and
  * its energy to the DMI entry. */
 #define MM_ALL_TERMS 31u
-#define MM_TERM_MASK 2047u
+#define MM_TERM_MASK 4095u
 
 /* Regular mesh of nx*ny*nz cuboid cells of size dx*dy*dz (paper: FDMesh).
  * Limits: 1 <= n <= 1024 per axis, nx >= 2; d > 0 and finite. */
@@ -163,6 +164,27 @@ mm_status mm_plan_destroy(mm_plan* plan);
  * Allocates the plan's cell arrays on first use; synchronises. */
 mm_status mm_plan_set_cells(mm_plan* plan, int32_t instance, const double* Ms, const double* A, const double* D,
                             void* hip_stream);
+
+/* MM_DEMAG_POTENTIAL: the demag field through the magnetic scalar potential,
+ * the route of section "Magnetostatic energy" that replaces the three inverse
+ * transforms of the demag field by one.  Reading (the paper prints no
+ * formulas): u(r) = sum_j Ms m_j . S(r - r_j), S the potential of a uniformly
+ * magnetised unit cuboid (the closed form of its two charged faces near the
+ * cell, quadrature of the defining integral far from it), evaluated at the
+ * cell corners; the field of a cell is -(1/(4 d_a)) times the sum over its
+ * four a-edges of u(+ end) - u(- end), which tends to the Newell field as the
+ * mesh is refined.  A plan takes MM_DEMAG_POTENTIAL in place of MM_DEMAG (not
+ * both); it needs nz >= 2 (on one-cell films the two vertex planes would
+ * still take two inverse transforms), pads to P >= 2n per axis, and serves
+ * mm_effective_field, mm_llg_rhs, mm_energy and mm_profile_passes (the
+ * integrators, autotuning and set shapes refuse such plans with MM_E_ARG);
+ * uniform material only.  Instances switch the term on with the same bit. */
+
+/* The cuboid potential S at the vertex - cell displacements
+ * ((I - 1/2) dx, (J - 1/2) dy, (K - 1/2) dz), disp[k] = (I, J, K) (device int32
+ * [n][3]); out: device double [n][3] (S_x, S_y, S_z, in m).  FP64. */
+mm_status mm_scalar_potential_kernel(const mm_mesh* mesh, const int32_t* disp, int64_t n, double* out,
+                                     void* hip_stream);
 
 /* Padded FFT grid chosen for the plan (each P >= 2n-1; x even). */
 mm_status mm_plan_padded(const mm_plan* plan, int32_t* Px, int32_t* Py, int32_t* Pz);

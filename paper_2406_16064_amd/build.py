@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmmx.so")
 SOURCES = ("hotpath.hip", "invx_f32_demag.hip", "invx_f32_local.hip", "invx_f64_demag.hip",
            "invx_f64_local.hip", "invx_f32_demag_cells.hip", "invx_f32_local_cells.hip",
-           "invx_f64_demag_cells.hip", "invx_f64_local_cells.hip", "setup.hip", "plan.hip")
+           "invx_f64_demag_cells.hip", "invx_f64_local_cells.hip", "potential.hip", "setup.hip", "plan.hip")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

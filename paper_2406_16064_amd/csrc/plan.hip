@@ -20,6 +20,7 @@
 
 #include "fft_core.hpp"
 #include "kernels.hpp"
+#include "potential.hpp"
 #include "setup.hpp"
 
 using namespace mmx;
@@ -60,6 +61,15 @@ int pick_padded(int n, bool even) {
   if (n == 1 && !even) return 1;
   if (smooth3(2 * n)) return 2 * n;
   for (int P = 2 * n - 1;; ++P)
+    if (smooth3(P) && (!even || P % 2 == 0)) return P;
+}
+
+// Padded length of the scalar-potential route: the smallest 3-smooth P >= 2n
+// (even along x), 1 for n = 1 off x (the 2n vertex - cell displacements must
+// all fit).
+int pick_padded_pot(int n, bool even) {
+  if (n == 1 && !even) return 1;
+  for (int P = 2 * n;; ++P)
     if (smooth3(P) && (!even || P % 2 == 0)) return P;
 }
 
@@ -233,6 +243,10 @@ struct Group {
   void* twx = nullptr;
   void* twy = nullptr;
   void* twz = nullptr;
+  void* kpot = nullptr;   // scalar-potential route: folded kernel spectrum [3][Kz][Xp][Ky]
+  void* phx = nullptr;    // half-cell phase tables exp(-i pi k / P) along x, y, z
+  void* phy = nullptr;
+  void* phz = nullptr;
   void* cells = nullptr;  // cell-based material [cells_cap][3][N] (Ms, A, D), plan precision
   std::vector<char> cells_set;  // slot i holds data
   void* stage = nullptr;  // ms0, ms1, k1..k7: 9 x stage_cap x 3N
@@ -263,6 +277,7 @@ struct Engine {
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   double* he5 = nullptr;
   bool any_demag = false;
+  bool any_pot = false;     // some instance of the current call uses the scalar-potential demag
   bool use_general = false;  // the current call runs the general-material form (kGeneralTerms)
   // graph cache of the Dormand-Prince attempt sequence
   hipGraphExec_t gexec = nullptr;
@@ -381,6 +396,7 @@ DevParams dev_params(const mm_params& r, const Group& G, bool general) {
   o.g1 = -r.gamma / (1 + r.alpha * r.alpha);
   o.g2 = -r.alpha * r.gamma / (1 + r.alpha * r.alpha);
   o.demag_scale = (r.terms & MM_CELLS) ? -1.0 / P : -r.Ms / P;  // cells: Ms is inside M
+  if (r.terms & MM_DEMAG_POTENTIAL) o.demag_scale = r.Ms / P;   // potential route: u = S * (Ms m)
   o.terms = r.terms;
   return o;
 }
@@ -475,6 +491,18 @@ mm_status upload_tables(Group& G) {
   return MM_OK;
 }
 
+mm_status dev_alloc(void** d, size_t bytes);
+
+// The launch shapes of the scalar-potential route fit the group's tuning.
+template <typename T>
+bool pot_fits(const Group& G) {
+  HotPlan<T> h;
+  std::memset(&h, 0, sizeof(h));
+  h.g = G.g;
+  h.tu = G.tu;
+  return pot_supported<T>(h, min_tpc(make_fft<T>(G.g.Lx, nullptr)));
+}
+
 // Tensor spectrum on the device: Newell grid (FP64) -> 3-D FFT (FP64) -> fold -> cast.
 template <typename T>
 mm_status build_spectrum(Group& G, hipStream_t s) {
@@ -532,6 +560,79 @@ mm_status build_spectrum(Group& G, hipStream_t s) {
   return st;
 }
 
+// Kernel spectrum of the scalar-potential route on the device: the cuboid
+// potential on the vertex - cell lattice (FP64) -> 3-D FFT (FP64) -> the real
+// factor C_a of S^_a = -i Phi C_a, folded and cast; phase tables on the host.
+template <typename T>
+mm_status build_potential(Group& G, hipStream_t s) {
+  const Geo& g = G.g;
+  double nodes[5][16] = {}, wts[5][16] = {};
+  const int nn[5] = {14, 9, 6, 4, 3};
+  for (int r = 0; r < 5; ++r) gauss_legendre(nn[r], nodes[r], wts[r]);
+  HIPCHK(setup_upload_pot_gauss(nodes, wts, nn));
+  const long long tot = (long long)g.Px * g.Py * g.Pz;
+  Cx<double>* F = nullptr;
+  HIPCHK(hipMalloc(&F, sizeof(Cx<double>) * tot * 3));
+  std::vector<void*> tws;
+  mm_status st = MM_OK;
+  do {
+    hipError_t e = setup_potential_grid(G.mesh, g.Px, g.Py, g.Pz, F, s);
+    if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("potential grid: ") + hipGetErrorString(e)); break; }
+    const int Ls[3] = {g.Px, g.Py, g.Pz};
+    const long long inner[3] = {1, g.Px, (long long)g.Px * g.Py};
+    const long long outer[3] = {(long long)g.Py * g.Pz * 3, (long long)g.Pz * 3, 3};
+    for (int a = 0; a < 3 && st == MM_OK; ++a) {
+      if (Ls[a] == 1) continue;
+      std::vector<Cx<double>> tw = twiddles<double>(Ls[a]);
+      void* d = nullptr;
+      e = hipMalloc(&d, sizeof(Cx<double>) * tw.size());
+      if (e != hipSuccess) { st = fail(MM_E_NOMEM, "twiddle table"); break; }
+      tws.push_back(d);
+      e = hipMemcpy(d, tw.data(), sizeof(Cx<double>) * tw.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) { st = fail(MM_E_HIP, hipGetErrorString(e)); break; }
+      FftPlan<double> fp = make_fft<double>(Ls[a], (const Cx<double>*)d);
+      e = setup_fft_axis(F, inner[a], outer[a], describe(fp), min_tpc(fp), s);
+      if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("potential fft: ") + hipGetErrorString(e)); break; }
+    }
+    if (st != MM_OK) break;
+    unsigned long long* stats = nullptr;
+    e = hipMalloc(&stats, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) { st = fail(MM_E_NOMEM, "stats"); break; }
+    tws.push_back(stats);
+    e = hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s);
+    for (int c = 0; c < 3 && e == hipSuccess; ++c)
+      e = setup_extract_pot<T>(F + (size_t)c * tot, g.Px, g.Py, g.Pz, c, (T*)G.kpot, stats, s);
+    if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("extract: ") + hipGetErrorString(e)); break; }
+    unsigned long long hs[2];
+    e = hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { st = fail(MM_E_HIP, std::string("spectrum: ") + hipGetErrorString(e)); break; }
+    double im, re;
+    std::memcpy(&im, &hs[0], 8);
+    std::memcpy(&re, &hs[1], 8);
+    G.imag_ratio = re > 0 ? im / re : 0.0;
+    if (!(G.imag_ratio < 1e-9)) st = fail(MM_E_HIP, "potential spectrum is not of the half-cell form");
+  } while (false);
+  (void)hipStreamSynchronize(s);
+  for (void* d : tws) (void)hipFree(d);
+  (void)hipFree(F);
+  if (st != MM_OK) return st;
+  auto phase = [&](void** dst, int n, int P) -> mm_status {
+    std::vector<Cx<T>> v(n);
+    for (int k = 0; k < n; ++k) {
+      const double a = -M_PI * (double)k / (double)P;
+      v[k] = Cx<T>{(T)std::cos(a), (T)std::sin(a)};
+    }
+    MMCHK(dev_alloc(dst, sizeof(Cx<T>) * n));
+    HIPCHK(hipMemcpy(*dst, v.data(), sizeof(Cx<T>) * n, hipMemcpyHostToDevice));
+    return MM_OK;
+  };
+  MMCHK(phase(&G.phx, g.Xp, g.Px));
+  MMCHK(phase(&G.phy, g.Py, g.Py));
+  MMCHK(phase(&G.phz, g.Pz, g.Pz));
+  return MM_OK;
+}
+
 mm_status dev_alloc(void** d, size_t bytes) {
   hipError_t e = hipMalloc(d, std::max<size_t>(bytes, 16));
   if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MM_E_NOMEM : MM_E_HIP, hipGetErrorString(e));
@@ -539,7 +640,8 @@ mm_status dev_alloc(void** d, size_t bytes) {
 }
 
 void free_group(Group& G) {
-  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.stage, G.mbuf, G.cells};
+  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.stage, G.mbuf, G.cells, G.kpot, G.phx,
+                  G.phy, G.phz};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   G = Group();
@@ -566,9 +668,10 @@ mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
   G.ncomp = mesh.nz == 1 ? 4 : 6;
   Geo& g = G.g;
   g.nx = mesh.nx; g.ny = mesh.ny; g.nz = mesh.nz;
-  g.Px = pick_padded(g.nx, true);
-  g.Py = pick_padded(g.ny, false);
-  g.Pz = pick_padded(g.nz, false);
+  const bool pot = (E.terms & MM_DEMAG_POTENTIAL) != 0;
+  g.Px = pot ? pick_padded_pot(g.nx, true) : pick_padded(g.nx, true);
+  g.Py = pot ? pick_padded_pot(g.ny, false) : pick_padded(g.ny, false);
+  g.Pz = pot ? pick_padded_pot(g.nz, false) : pick_padded(g.nz, false);
   g.Lx = g.Px / 2;
   g.Xp = g.Lx + 1;
   g.Ky = g.Py / 2 + 1;
@@ -583,6 +686,13 @@ mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
     MMCHK(dev_alloc(&G.kt, E.rsz * G.ncomp * (size_t)g.Kz * g.Xp * g.Ky));
     MMCHK(E.prec == MM_F32 ? upload_tables<float>(G) : upload_tables<double>(G));
     MMCHK(E.prec == MM_F32 ? build_spectrum<float>(G, s) : build_spectrum<double>(G, s));
+  }
+  if (pot) {
+    const bool fits = E.prec == MM_F32 ? pot_fits<float>(G) : pot_fits<double>(G);
+    if (!fits) return fail(MM_E_ARG, "mesh too long along x for the scalar-potential route's x pass");
+    MMCHK(dev_alloc(&G.kpot, E.rsz * 3 * (size_t)g.Kz * g.Xp * g.Ky));
+    MMCHK(E.prec == MM_F32 ? upload_tables<float>(G) : upload_tables<double>(G));
+    MMCHK(E.prec == MM_F32 ? build_potential<float>(G, s) : build_potential<double>(G, s));
   }
   return MM_OK;
 }
@@ -612,7 +722,7 @@ mm_status engine_reserve(Engine& E, const std::vector<int>& per_group) {
     const int n = per_group[i];
     total += n;
     parts = std::max(parts, 5 * n * eval_blocks_per_inst(G.g, G.tu));
-    if (n > G.cap && (E.terms & MM_DEMAG)) {
+    if (n > G.cap && (E.terms & (MM_DEMAG | MM_DEMAG_POTENTIAL))) {
       if (G.Sx) (void)hipFree(G.Sx);
       if (G.Sy) (void)hipFree(G.Sy);
       G.Sx = G.Sy = nullptr;
@@ -656,11 +766,13 @@ mm_status upload_params(Engine& E, const std::vector<const mm_params*>& q, const
                         hipStream_t s) {
   std::vector<DevParams> d(q.size());
   E.any_demag = false;
+  E.any_pot = false;
   E.use_general = false;
   for (size_t b = 0; b < q.size(); ++b) E.use_general = E.use_general || (q[b]->terms & kGeneralTerms) != 0;
   for (size_t b = 0; b < q.size(); ++b) {
     d[b] = dev_params(*q[b], E.groups[grp[b]], E.use_general);
     E.any_demag = E.any_demag || (q[b]->terms & MM_DEMAG) != 0;
+    E.any_pot = E.any_pot || (q[b]->terms & MM_DEMAG_POTENTIAL) != 0;
   }
   HIPCHK(hipMemcpyAsync(E.prm, d.data(), sizeof(DevParams) * d.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -726,6 +838,48 @@ Epi<T> epi_base(const Group& G, int mode) {
 
 bool demag_on(const Engine& E) { return (E.terms & MM_DEMAG) != 0 && E.any_demag; }
 
+template <typename T>
+PotTab<T> pot_tab(const Group& G) {
+  PotTab<T> t;
+  t.kp = (const T*)G.kpot;
+  t.phx = (const Cx<T>*)G.phx;
+  t.phy = (const Cx<T>*)G.phy;
+  t.phz = (const Cx<T>*)G.phz;
+  t.gdx = -0.25 / G.mesh.dx;
+  t.gdy = -0.25 / G.mesh.dy;
+  t.gdz = -0.25 / G.mesh.dz;
+  return t;
+}
+
+// Back-to-back timing of the five passes of the scalar-potential route
+// (after one full evaluation that fills the intermediate buffers).
+template <typename T>
+mm_status time_pot_passes(Engine& E, const GroupSet<T>& gs, const Epi<T>* epis, int reps, double* us,
+                          hipStream_t s) {
+  const PotTab<T> pt = pot_tab<T>(E.groups[0]);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t er = hipEventCreate(&e1);
+  if (er != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(MM_E_HIP, hipGetErrorString(er));
+  }
+  er = launch_potential<T>(gs, epis, pt, MODE_RHS, s);
+  for (int i = 0; i < 5 && er == hipSuccess; ++i) {
+    er = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && er == hipSuccess; ++r) er = launch_potential<T>(gs, epis, pt, MODE_RHS, s, 1u << i);
+    if (er == hipSuccess) er = hipEventRecord(e1, s);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+    us[i] = 1e3 * ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (er != hipSuccess) return fail(MM_E_HIP, hipGetErrorString(er));
+  return MM_OK;
+}
+
 // --- single-group calls (plans) ----------------------------------------------
 
 template <typename T>
@@ -744,11 +898,13 @@ mm_status single_eval(mm_plan* p, int batch, const mm_params* q, const void* m, 
   ep[0].out = (T*)out;
   ep[0].partial = partial;
   MMCHK(upload_epis<T>(E, 0, ep, s));
-  HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 0), mode, demag_on(E), s, ev));
+  if (E.any_pot) HIPCHK(launch_potential<T>(gs, epi_slot<T>(E, 0), pot_tab<T>(E.groups[0]), mode, s));
+  else HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 0), mode, demag_on(E), s, ev));
   return MM_OK;
 }
 
 int pass_count(const Engine& E) {
+  if (E.any_pot) return 5;
   if (!demag_on(E)) return 1;
   return E.groups[0].g.nz == 1 ? 3 : 5;
 }
@@ -793,6 +949,7 @@ mm_status profile_impl(mm_plan* p, const mm_params* q, int batch, const void* m,
   GroupSet<T> gs;
   std::vector<int> inst0;
   MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
+  if (E.any_pot) return time_pot_passes<T>(E, gs, epi_slot<T>(E, 0), reps, us, s);
   return time_each_pass<T>(E, gs, epi_slot<T>(E, 0), MODE_RHS, reps, pass_count(E), us, s);
 }
 
@@ -1593,10 +1750,21 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
   return MM_OK;
 }
 
-mm_status plan_checks(mm_plan* p, const mm_params* q, int batch) {
+// eval: a field, dm/dt, energy or pass-timing call (the only calls a plan of
+// the scalar-potential route serves)
+mm_status plan_checks(mm_plan* p, const mm_params* q, int batch, bool eval = false) {
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (batch < 1 || batch > p->maxb) return fail(MM_E_ARG, "batch must be in [1, max_batch]");
   MMCHK(check_params(p->e, q, batch));
+  if (p->e.terms & MM_DEMAG_POTENTIAL) {
+    if (!eval)
+      return fail(MM_E_ARG, "plans of the scalar-potential demag route serve field, dm/dt, energy and pass-timing "
+                            "calls only");
+    for (int b = 0; b < batch; ++b)
+      if (q[b].terms & kGeneralTerms)
+        return fail(MM_E_ARG, "the scalar-potential demag route takes uniform material without interlayer or "
+                              "torque terms");
+  }
   const Group& G = p->e.groups[0];
   for (int b = 0; b < batch; ++b) {
     if ((q[b].terms & MM_CELLS) && (b >= (int)G.cells_set.size() || !G.cells_set[b]))
@@ -1687,6 +1855,13 @@ mm_status mm_plan_create(mm_plan** out, const mm_mesh* mesh, mm_precision prec, 
   MMCHK(check_cells(mesh, prec));
   if (terms & ~MM_TERM_MASK) return fail(MM_E_ARG, "unknown term bits");
   if (max_batch < 1) return fail(MM_E_ARG, "max_batch must be >= 1");
+  if (terms & MM_DEMAG_POTENTIAL) {
+    if (terms & MM_DEMAG) return fail(MM_E_ARG, "MM_DEMAG_POTENTIAL replaces MM_DEMAG: not both");
+    if (mesh->nz < 2) return fail(MM_E_ARG, "the scalar-potential demag route needs nz >= 2");
+    if (terms & kGeneralTerms)
+      return fail(MM_E_ARG, "the scalar-potential demag route takes uniform material without interlayer or "
+                            "torque terms");
+  }
   hipStream_t s = (hipStream_t)hip_stream;
   mm_plan* p = new mm_plan();
   p->maxb = max_batch;
@@ -1730,6 +1905,21 @@ mm_status mm_plan_set_cells(mm_plan* p, int32_t instance, const double* Ms, cons
                              : set_cells_impl<double>(p, instance, Ms, A, D, s);
 }
 
+mm_status mm_scalar_potential_kernel(const mm_mesh* mesh, const int32_t* disp, int64_t n, double* out,
+                                     void* hip_stream) {
+  MMCHK(check_mesh(mesh));
+  if (n < 0) return fail(MM_E_ARG, "n must be >= 0");
+  if (n > 0 && (!disp || !out)) return fail(MM_E_ARG, "null pointer");
+  double nodes[5][16] = {}, wts[5][16] = {};
+  const int nn[5] = {14, 9, 6, 4, 3};
+  for (int r = 0; r < 5; ++r) gauss_legendre(nn[r], nodes[r], wts[r]);
+  HIPCHK(setup_upload_pot_gauss(nodes, wts, nn));
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIPCHK(setup_potential_list(*mesh, disp, n, out, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MM_OK;
+}
+
 mm_status mm_plan_padded(const mm_plan* p, int32_t* Px, int32_t* Py, int32_t* Pz) {
   if (!p || !Px || !Py || !Pz) return fail(MM_E_ARG, "null argument");
   const Geo& g = p->e.groups[0].g;
@@ -1753,7 +1943,7 @@ mm_status mm_demag_tensor(const mm_mesh* mesh, const int32_t* disp, int64_t n, d
 
 mm_status mm_effective_field(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* H,
                              void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, true));
   if (!m || !H) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? single_eval<float>(p, batch, q, m, H, MODE_FIELD, nullptr, s)
@@ -1761,7 +1951,7 @@ mm_status mm_effective_field(mm_plan* p, const mm_params* q, int32_t batch, cons
 }
 
 mm_status mm_llg_rhs(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* dmdt, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, true));
   if (!m || !dmdt) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? single_eval<float>(p, batch, q, m, dmdt, MODE_RHS, nullptr, s)
@@ -1769,7 +1959,7 @@ mm_status mm_llg_rhs(mm_plan* p, const mm_params* q, int32_t batch, const void* 
 }
 
 mm_status mm_energy(mm_plan* p, const mm_params* q, int32_t batch, const void* m, double* E_out, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, true));
   if (!m || !E_out) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? energy_impl<float>(p, q, batch, m, E_out, s)
@@ -1911,7 +2101,7 @@ mm_status mm_profile_step(mm_plan* p, const mm_params* q, int32_t batch, void* m
 
 mm_status mm_profile_passes(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work, int32_t reps,
                             double* us_out, int32_t* n_pass, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, true));
   if (!m || !work || !us_out || !n_pass) return fail(MM_E_ARG, "null argument");
   if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -1948,6 +2138,8 @@ mm_status mm_plan_shapes(const mm_plan* p, int32_t* shape_out) {
 }
 
 mm_status mm_plan_set_shapes(mm_plan* p, const int32_t* shape) {
+  if (p && (p->e.terms & MM_DEMAG_POTENTIAL))
+    return fail(MM_E_ARG, "plans of the scalar-potential demag route keep their launch shapes");
   if (!p || !shape) return fail(MM_E_ARG, "null pointer");
   Group& G = p->e.groups[0];
   Tuning t = G.tu;
@@ -1980,8 +2172,8 @@ mm_status mm_neb_run(mm_plan* p, const mm_params* q, void* images, int32_t n_img
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (n_img < 3 || n_img > p->maxb) return fail(MM_E_ARG, "n_img must be in [3, max_batch]");
   MMCHK(check_params(p->e, q, 1));
-  if (q->terms & kGeneralTerms)
-    return fail(MM_E_ARG, "NEB chains take uniform material and no interlayer or torque terms");
+  if ((q->terms & kGeneralTerms) || (p->e.terms & MM_DEMAG_POTENTIAL))
+    return fail(MM_E_ARG, "NEB chains take uniform material, the Newell demag and no interlayer or torque terms");
   if (!images) return fail(MM_E_ARG, "images is null");
   if (!is_fin(k_spring) || !is_fin(h) || h <= 0 || n_iter < 1) return fail(MM_E_ARG, "invalid k_spring, h or n_iter");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -1999,8 +2191,8 @@ mm_status mm_batch_create(mm_batch** out, const mm_mesh* meshes, int32_t n_meshe
   if (prec != MM_F32 && prec != MM_F64) return fail(MM_E_ARG, "precision must be MM_F32 or MM_F64");
   for (int i = 0; i < n_meshes; ++i) MMCHK(check_cells(&meshes[i], prec));
   if (terms & ~MM_TERM_MASK) return fail(MM_E_ARG, "unknown term bits");
-  if (terms & kGeneralTerms)
-    return fail(MM_E_ARG, "batches take uniform material and no interlayer or torque terms");
+  if (terms & (kGeneralTerms | MM_DEMAG_POTENTIAL))
+    return fail(MM_E_ARG, "batches take uniform material, the Newell demag and no interlayer or torque terms");
   hipStream_t s = (hipStream_t)hip_stream;
   mm_batch* b = new mm_batch();
   mm_status st = engine_init(b->e, prec, terms);

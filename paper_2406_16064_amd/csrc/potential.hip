@@ -1,0 +1,322 @@
+// Demag field through the magnetic scalar potential (the paper, section
+// "Magnetostatic energy": with the scalar potential the three inverse Fourier
+// transforms of the demag field become one).
+//
+// u(r) = sum_j M_j . S(r - r_j) at the cell corners (vertices), S the potential
+// of a uniformly magnetised unit cuboid (setup.hip); H_d of a cell is
+// -(1/(4 d_a)) times the sum over its four a-edges of u(+ end) - u(- end).  On
+// P >= 2n points per axis the vertex - cell displacements ((i - 1/2) d, i in
+// [-n+1, n]) fill the circular convolution exactly.
+//
+// Passes of one evaluation (3-D groups, nz >= 2; single group):
+//   x, y forward   the Newell route's passes (M_a -> Sy[3][nz][Xp][Py])
+//   z              forward z of the 3 components, u^ = -i Phi sum_a C_a M^_a
+//                  (scaled by Ms / (Px Py Pz)), inverse z of u^ alone; the
+//                  nz + 1 vertex planes go back to Sy, plane k at k Xp Py
+//   y inverse      columns (k, kx) of u^: inverse y, the ny + 1 vertex rows to
+//                  V = Sx as [nz+1][ny+1][Xp] (rows contiguous along kx)
+//   x inverse      2 (TY + 1) vertex rows (planes z, z + 1) of TY cell rows:
+//                  complex-to-real along x (nx + 1 vertices), the edge
+//                  differences, local fields, LL and the epilogue
+#include "hotpath.hpp"
+#include "potential.hpp"
+
+namespace mmx {
+
+// ---------------------------------------------------------------------------
+// z pass: QZ consecutive (kx, ky) points of one instance.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(512) k_pot_z(HotPlan<T> hp, PotTab<T> pt, int QZ, int tpc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  const Geo& g = hp.g;
+  const long long nq = (long long)g.Xp * g.Py;
+  const long long tiles = (nq + QZ - 1) / QZ;
+  const long long tile = (long long)blockIdx.x % tiles;
+  const int b = (int)((long long)blockIdx.x / tiles);
+  const long long q0 = tile * QZ;
+  const int nqt = (int)((nq - q0) < QZ ? (nq - q0) : QZ);
+  const int cs = col_stride(g.Pz);
+  const int sh = hp.fd[2].psh;
+  Cx<T>* base = hp.Sy + (size_t)b * g.sy;  // [3][nz][Xp Py] in, [nz + 1][Xp Py] out
+  const size_t plane = (size_t)nq;
+  for (int t = threadIdx.x; t < 3 * g.Pz * QZ; t += blockDim.x) {  // column c QZ + j, element z
+    const int j = t % QZ;
+    const int cz = t / QZ;
+    const int c = cz / g.Pz, z = cz - c * g.Pz;
+    Cx<T> v = {T(0), T(0)};
+    if (z < g.nz && j < nqt) v = gld(base + ((size_t)c * g.nz + z) * plane + q0 + j);
+    lds[(c * QZ + j) * cs + pidx(z, sh)] = v;
+  }
+  __syncthreads();
+  fft_columns<T, false, false>(lds, hp.fd[2], cs, 3 * QZ, tpc, hp.fd[2].tw);
+  __syncthreads();
+  const T s = T(ldu(&hp.prm[b].demag_scale));  // Ms / (Px Py Pz)
+  const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
+  for (int t = threadIdx.x; t < QZ * g.Pz; t += blockDim.x) {
+    const int j = t % QZ, kz = t / QZ;
+    if (j >= nqt) continue;
+    const long long q = q0 + j;
+    const int kx = (int)(q / g.Py), ky = (int)(q - (long long)kx * g.Py);
+    const bool fy = ky > g.Py - ky, fz = kz > g.Pz - kz;  // folded indices: parities below
+    const int kyf = fy ? g.Py - ky : ky, kzf = fz ? g.Pz - kz : kz;
+    const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
+    // parities of the folded kernel under ky -> Py - ky, kz -> Pz - kz (the
+    // lattice is symmetric about the half-cell shift): C_x odd in both, C_y
+    // odd in kz, C_z odd in ky
+    const T cxv = gld(pt.kp + off) * ((fy != fz) ? T(-1) : T(1));
+    const T cyv = gld(pt.kp + cstride + off) * (fz ? T(-1) : T(1));
+    const T czv = gld(pt.kp + 2 * cstride + off) * (fy ? T(-1) : T(1));
+    const int pk = pidx(kz, sh);
+    const Cx<T> mx = lds[(0 * QZ + j) * cs + pk], my = lds[(1 * QZ + j) * cs + pk];
+    const Cx<T> mz = lds[(2 * QZ + j) * cs + pk];
+    const Cx<T> w = {cxv * mx.x + cyv * my.x + czv * mz.x, cxv * mx.y + cyv * my.y + czv * mz.y};
+    // -i Phi w s, Phi = phx[kx] phy[ky] phz[kz]
+    const Cx<T> ph = cmul(cmul(gld(pt.phx + kx), gld(pt.phy + ky)), gld(pt.phz + kz));
+    const Cx<T> pw = cmul(ph, w);
+    lds[(0 * QZ + j) * cs + pk] = Cx<T>{pw.y * s, -pw.x * s};
+  }
+  __syncthreads();
+  fft_columns<T, true, false>(lds, hp.fd[2], cs, QZ, (int)blockDim.x / QZ, hp.fd[2].tw);
+  __syncthreads();
+  for (int t = threadIdx.x; t < (g.nz + 1) * QZ; t += blockDim.x) {
+    const int j = t % QZ, z = t / QZ;
+    if (j < nqt) gst(base + (size_t)z * plane + q0 + j, lds[j * cs + pidx(z, sh)]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y inverse: CB consecutive kx of vertex plane k of one instance.
+// ---------------------------------------------------------------------------
+template <typename T, bool R16>
+__global__ void __launch_bounds__(512) k_pot_yinv(HotPlan<T> hp, int CB, int tpc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  const Geo& g = hp.g;
+  const int tiles = (g.Xp + CB - 1) / CB;
+  unsigned bid = blockIdx.x;
+  const int tile = (int)(bid % (unsigned)tiles); bid /= (unsigned)tiles;
+  const int k = (int)(bid % (unsigned)(g.nz + 1));
+  const int b = (int)(bid / (unsigned)(g.nz + 1));
+  const int kx0 = tile * CB;
+  const int ncol = g.Xp - kx0 < CB ? g.Xp - kx0 : CB;
+  const int cs = col_stride(g.Py);
+  const int sh = hp.fd[1].psh;
+  const Cx<T>* src = hp.Sy + (size_t)b * g.sy + ((size_t)k * g.Xp + kx0) * g.Py;  // ncol contiguous columns
+  for (int t = threadIdx.x; t < ncol * g.Py; t += blockDim.x) {
+    const int i = t / g.Py, y = t - i * g.Py;
+    lds[i * cs + pidx(y, sh)] = gld(src + t);
+  }
+  __syncthreads();
+  fft_columns<T, true, false, R16>(lds, hp.fd[1], cs, ncol, tpc, hp.fd[1].tw);
+  __syncthreads();
+  Cx<T>* dst = hp.Sx + (size_t)b * g.sx + (size_t)k * (g.ny + 1) * g.Xp + kx0;  // V[k][y][kx]
+  for (int t = threadIdx.x; t < (g.ny + 1) * ncol; t += blockDim.x) {
+    const int y = t / ncol, i = t - y * ncol;
+    gst(dst + (size_t)y * g.Xp + i, lds[i * cs + pidx(y, sh)]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x inverse + edge differences + local fields + epilogue: TY cell rows of
+// plane z of one instance (MODE_FIELD, MODE_RHS or MODE_ENERGY).
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __restrict__ epis, int tpc, T gx, T gy,
+                                              T gz) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  __shared__ double red[5][512 / 64];
+  const Geo& g = hp.g;
+  const int TY = hp.tu.ty_x;
+  const int tiles = (g.ny + TY - 1) / TY;
+  unsigned bid = blockIdx.x;
+  const int z = (int)(bid % (unsigned)g.nz); bid /= (unsigned)g.nz;
+  const int tile = (int)(bid % (unsigned)tiles);
+  const int b = (int)(bid / (unsigned)tiles);
+  const int y0 = tile * TY;
+  const int nrow = g.ny - y0 < TY ? g.ny - y0 : TY;
+  const int cs = col_stride(g.Lx);
+  const int sh = hp.fd[0].psh;
+  const int R1 = TY + 1;      // vertex rows per plane
+  const int ncol = 2 * R1;    // column p R1 + r: vertex row y0 + r of vertex plane z + p
+  Cx<T>* const twl = lds + ncol * cs;
+  Cx<T>* const postl = twl + g.Lx;
+  const bool add_hd = (ldu(&hp.prm[b].terms) & MM_DEMAG_POTENTIAL) != 0;
+  if (add_hd) {
+    TableCopy<T, 4> tab;
+    tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
+    const Cx<T>* V = hp.Sx + (size_t)b * g.sx;
+    for (int t = threadIdx.x; t < ncol * g.Xp; t += blockDim.x) {
+      const int col = t / g.Xp, k = t - col * g.Xp;
+      const int p = col / R1, r = col - p * R1;
+      Cx<T> v = {T(0), T(0)};
+      if (r <= nrow) v = gld(V + ((size_t)(z + p) * (g.ny + 1) + y0 + r) * g.Xp + k);
+      lds[col * cs + pidx(k, sh)] = v;
+    }
+    tab.store(twl);
+    __syncthreads();
+    // complex-to-real through the half-length transform:
+    // Z[k] = (X[k] + conj X[Lx-k]) + i (X[k] - conj X[Lx-k]) conj(W^k), k in [0, Lx)
+    const int half = g.Lx / 2;
+    for (int t = threadIdx.x; t < ncol * (half + 1); t += blockDim.x) {
+      const int col = t / (half + 1), k = t - col * (half + 1);
+      Cx<T>* cp = lds + col * cs;
+      const int k2 = g.Lx - k;
+      const Cx<T> Xa = cp[pidx(k, sh)], Xb = cp[pidx(k2, sh)];
+      {
+        const Cx<T> s = cadd(Xa, cconj(Xb));
+        const Cx<T> d = cmul(csub(Xa, cconj(Xb)), cconj(postl[k]));
+        cp[pidx(k, sh)] = Cx<T>{s.x - d.y, s.y + d.x};
+      }
+      if (k > 0 && k < k2) {
+        const Cx<T> s = cadd(Xb, cconj(Xa));
+        const Cx<T> d = cmul(csub(Xb, cconj(Xa)), cconj(postl[k2]));
+        cp[pidx(k2, sh)] = Cx<T>{s.x - d.y, s.y + d.x};
+      }
+    }
+    __syncthreads();
+    fft_columns<T, true, true>(lds, hp.fd[0], cs, ncol, tpc, twl);
+    __syncthreads();
+  }
+  // u at vertex (x, row r, plane p) of this tile: real x of column p R1 + r
+  auto u = [&](int x, int r, int p) -> T {
+    const Cx<T> c = lds[(p * R1 + r) * cs + pidx(x >> 1, sh)];
+    return (x & 1) ? c.y : c.x;
+  };
+  const Epi<T> epi = ldu(epis);
+  const DevParams Pd = ldu(hp.prm + b);
+  const LocalCoef<T> P = local_coef<T>(Pd);
+  const T g1 = T(Pd.g1), g2 = T(Pd.g2);
+  const long long N = g.N;
+  const size_t ib = (size_t)b * epi.inst_stride;
+  const T* mb = epi.in + ib;
+  double esum[5] = {0, 0, 0, 0, 0};
+  for (int e = threadIdx.x; e < nrow * g.nx; e += blockDim.x) {
+    const int r = e / g.nx, x = e - r * g.nx;
+    const int y = y0 + r;
+    const COff co = coff_of<T>(N, (z * g.ny + y) * g.nx + x);
+    const Nbr<T> nb = load_nbr<T>(g, P.terms, mb, co, x, y, z);
+    LocalTerms lt = {0, 0, 0, 0};
+    V3<T> H;
+    if constexpr (MODE == MODE_ENERGY) H = local_field<T, true>(g, P, nb, x, y, z, &lt);
+    else H = local_field<T, false>(g, P, nb, x, y, z, nullptr);
+    V3<T> hd = {T(0), T(0), T(0)};
+    if (add_hd) {
+      const T a000 = u(x, r, 0), a100 = u(x + 1, r, 0), a010 = u(x, r + 1, 0), a110 = u(x + 1, r + 1, 0);
+      const T a001 = u(x, r, 1), a101 = u(x + 1, r, 1), a011 = u(x, r + 1, 1), a111 = u(x + 1, r + 1, 1);
+      hd.x = gx * ((a100 - a000) + (a110 - a010) + (a101 - a001) + (a111 - a011));
+      hd.y = gy * ((a010 - a000) + (a110 - a100) + (a011 - a001) + (a111 - a101));
+      hd.z = gz * ((a001 - a000) + (a101 - a100) + (a011 - a010) + (a111 - a110));
+      H.x += hd.x; H.y += hd.y; H.z += hd.z;
+    }
+    const V3<T> mi = nb.mi;
+    if constexpr (MODE == MODE_FIELD) st3o(epi.out + ib, co, H);
+    if constexpr (MODE == MODE_RHS) st3o(epi.out + ib, co, ll_rhs(mi, H, g1, g2));
+    if constexpr (MODE == MODE_ENERGY) {
+      esum[0] += lt.ex;
+      if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
+      esum[2] += lt.dmi;
+      esum[3] += lt.an;
+      esum[4] += lt.ze;
+    }
+  }
+  if constexpr (MODE == MODE_ENERGY) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = 0; q < 5; ++q) {
+      const double w = wave_sum(esum[q]);
+      if (lane == 0) red[q][wave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+      double v = 0;
+      for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
+      const int bpi = tiles * g.nz;
+      const int lb = (int)(blockIdx.x % (unsigned)bpi);
+      gst(epi.partial + ((size_t)b * bpi + lb) * 5 + threadIdx.x, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch shapes and the pass sequence.
+// ---------------------------------------------------------------------------
+template <typename T>
+PotShape pot_shape(const HotPlan<T>& h) {
+  PotShape p;
+  const Geo& g = h.g;
+  const size_t csz = sizeof(Cx<T>);
+  p.tpc_z = h.tu.tpc_z;
+  p.qz = h.tu.qz;
+  // y inverse: columns of Py points, at most 80 KB of LDS
+  p.tpc_y = h.tu.tpc_y;
+  int cb = 16;
+  while (cb > 1 && ((size_t)cb * col_stride(g.Py) * csz > 80 * 1024 || cb * p.tpc_y > 512)) cb /= 2;
+  p.cb_y = cb;
+  p.tpc_x = h.tu.tpc_x;
+  const int ncol = 2 * (h.tu.ty_x + 1);
+  p.nt_x = std::min(512, std::max(64, (ncol * p.tpc_x + 63) / 64 * 64));
+  p.tpc_x = p.nt_x / ncol;
+  p.lds_x = ((size_t)ncol * col_stride(g.Lx) + 2 * g.Lx + 1) * csz;
+  return p;
+}
+
+template <typename T>
+bool pot_supported(const HotPlan<T>& h, int tpc_x_min) {
+  const PotShape p = pot_shape(h);
+  return h.g.nz >= 2 && p.tpc_x >= tpc_x_min && p.lds_x <= 160 * 1024;
+}
+
+template <typename T>
+hipError_t launch_potential(const GroupSet<T>& gs, const Epi<T>* epis, const PotTab<T>& pt, int mode,
+                            hipStream_t s, unsigned pass_mask) {
+  const HotPlan<T>& h = gs.h[0];
+  const Geo& g = h.g;
+  const size_t csz = sizeof(Cx<T>);
+  const PotShape p = pot_shape(h);
+  // x and y forward: the passes of the Newell route (pass bits 0 and 1)
+  if (pass_mask & 3u) {
+    const hipError_t er = launch_eval<T>(gs, epis, mode, true, s, nullptr, false, false, pass_mask & 3u);
+    if (er != hipSuccess) return er;
+  }
+  if (pass_mask & 4u) {
+    const long long blocks = (long long)h.batch * (((long long)g.Xp * g.Py + p.qz - 1) / p.qz);
+    const size_t lds = (size_t)3 * p.qz * col_stride(g.Pz) * csz;
+    k_pot_z<T><<<dim3((unsigned)blocks), 3 * p.qz * p.tpc_z, lds, s>>>(h, pt, p.qz, p.tpc_z);
+  }
+  if (pass_mask & 8u) {
+    bool r16 = false;
+    for (int st = 0; st < h.fd[1].nst; ++st) r16 = r16 || radix_of(h.fd[1].code, st) == 16;
+    const long long blocks = (long long)h.batch * (g.nz + 1) * ((g.Xp + p.cb_y - 1) / p.cb_y);
+    const size_t lds = (size_t)p.cb_y * col_stride(g.Py) * csz;
+    const int nt = std::max(64, (p.cb_y * p.tpc_y + 63) / 64 * 64);
+    if (r16) k_pot_yinv<T, true><<<dim3((unsigned)blocks), nt, lds, s>>>(h, p.cb_y, p.tpc_y);
+    else k_pot_yinv<T, false><<<dim3((unsigned)blocks), nt, lds, s>>>(h, p.cb_y, p.tpc_y);
+  }
+  if (pass_mask & 16u) {
+    const long long blocks = (long long)h.batch * g.nz * ((g.ny + h.tu.ty_x - 1) / h.tu.ty_x);
+    const T cx = T(pt.gdx), cy = T(pt.gdy), cz = T(pt.gdz);
+    switch (mode) {
+      case MODE_FIELD:
+        k_pot_x<T, MODE_FIELD><<<dim3((unsigned)blocks), p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz);
+        break;
+      case MODE_ENERGY:
+        k_pot_x<T, MODE_ENERGY><<<dim3((unsigned)blocks), p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz);
+        break;
+      default:
+        k_pot_x<T, MODE_RHS><<<dim3((unsigned)blocks), p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz);
+    }
+  }
+  return hipGetLastError();
+}
+
+#define MMX_POT_INST(T)                                                                                      \
+  template PotShape pot_shape<T>(const HotPlan<T>&);                                                         \
+  template bool pot_supported<T>(const HotPlan<T>&, int);                                                    \
+  template hipError_t launch_potential<T>(const GroupSet<T>&, const Epi<T>*, const PotTab<T>&, int, hipStream_t, \
+                                          unsigned);
+MMX_POT_INST(float)
+MMX_POT_INST(double)
+
+}  // namespace mmx

@@ -204,6 +204,171 @@ __global__ void k_extract(const Cx<double>* __restrict__ F, int Px, int Py, int 
 }
 
 // ---------------------------------------------------------------------------
+// Scalar-potential route.  S(R) = (1/4 pi) int_cell (R - r') / |R - r'|^3 dr' is
+// the potential at R of a uniformly magnetised unit cuboid of size d centred at
+// 0 (component a for M = e_a).  Integrated along a it is the potential of the
+// two charged a-faces, (1/4 pi) [I(R_a - d_a/2) - I(R_a + d_a/2)], where I(w)
+// integrates 1/sqrt(x^2 + y^2 + w^2) over the face rectangle (in coordinates
+// relative to R), with the antiderivative
+//   G(x, y, z) = x asinh(y / sqrt(x^2 + z^2)) + y asinh(x / sqrt(y^2 + z^2)) - z atan(x y / (z r)).
+// Near the cell (|R| < 3 max d) the closed form, beyond it Gauss-Legendre
+// quadrature of the volume integral (n nodes per axis over the cell: 14, 9,
+// 6, 4, 3 from |R| / max d = 3, 6, 16, 40, 300), where the face differences of
+// the closed form would cancel.  The grid holds S at the vertex - cell
+// displacements ((i - 1/2) dx, ...), i in [-n+1, n], index i mod P.
+// ---------------------------------------------------------------------------
+__constant__ double c_pq_nodes[5][16];
+__constant__ double c_pq_wts[5][16];
+__constant__ int c_pq_n[5];
+
+__device__ __forceinline__ double face_g(double x, double y, double z) {
+  const double r = sqrt(x * x + y * y + z * z);
+  double s = 0.0;
+  const double ax = sqrt(x * x + z * z), ay = sqrt(y * y + z * z);
+  if (x != 0.0 && ax > 0.0) s += x * asinh(y / ax);
+  if (y != 0.0 && ay > 0.0) s += y * asinh(x / ay);
+  if (z != 0.0 && r > 0.0) s -= z * atan(x * y / (z * r));
+  return s;
+}
+
+__device__ __forceinline__ double face_i(double x1, double x2, double y1, double y2, double w) {
+  return face_g(x2, y2, w) - face_g(x1, y2, w) - face_g(x2, y1, w) + face_g(x1, y1, w);
+}
+
+__device__ void potential_at(double X, double Y, double Z, double dx, double dy, double dz, double out[3]) {
+  const double R[3] = {X, Y, Z}, d[3] = {dx, dy, dz};
+  const double dmax = fmax(dx, fmax(dy, dz));
+  const double rho = sqrt(X * X + Y * Y + Z * Z) / dmax;
+  if (rho < 3.0) {
+    for (int a = 0; a < 3; ++a) {
+      const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+      const double x1 = -0.5 * d[b] - R[b], x2 = 0.5 * d[b] - R[b];
+      const double y1 = -0.5 * d[c] - R[c], y2 = 0.5 * d[c] - R[c];
+      out[a] = (face_i(x1, x2, y1, y2, R[a] - 0.5 * d[a]) - face_i(x1, x2, y1, y2, R[a] + 0.5 * d[a])) /
+               (4.0 * M_PI);
+    }
+    return;
+  }
+  const int rule = rho >= 300.0 ? 4 : rho >= 40.0 ? 3 : rho >= 16.0 ? 2 : rho >= 6.0 ? 1 : 0;
+  const int n = c_pq_n[rule];
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double vx = X - 0.5 * dx * c_pq_nodes[rule][i];
+    const double wi = c_pq_wts[rule][i];
+    for (int j = 0; j < n; ++j) {
+      const double vy = Y - 0.5 * dy * c_pq_nodes[rule][j];
+      const double wij = wi * c_pq_wts[rule][j];
+      for (int k = 0; k < n; ++k) {
+        const double vz = Z - 0.5 * dz * c_pq_nodes[rule][k];
+        const double r2 = vx * vx + vy * vy + vz * vz;
+        const double ir = 1.0 / sqrt(r2);
+        const double f = wij * c_pq_wts[rule][k] * ir * ir * ir;
+        sx += f * vx;
+        sy += f * vy;
+        sz += f * vz;
+      }
+    }
+  }
+  const double c = dx * dy * dz / (8.0 * 4.0 * M_PI);
+  out[0] = c * sx; out[1] = c * sy; out[2] = c * sz;
+}
+
+// Lattice index of padded index i (P points, n cells): i for i <= n, i - P
+// when that is >= -n + 1; ok = false otherwise (the entry stays zero).
+__device__ __forceinline__ int vertex_disp(int i, int P, int n, bool& ok) {
+  const int I = i <= n ? i : i - P;
+  ok = I >= -n + 1 && I <= n;
+  return I;
+}
+
+__global__ void k_potential_grid(mm_mesh mesh, int Px, int Py, int Pz, Cx<double>* __restrict__ out) {
+  const long long tot = (long long)Px * Py * Pz;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const int ix = (int)(idx % Px);
+  const int iy = (int)((idx / Px) % Py);
+  const int iz = (int)(idx / ((long long)Px * Py));
+  bool okx, oky, okz;
+  const int I = vertex_disp(ix, Px, mesh.nx, okx);
+  const int J = vertex_disp(iy, Py, mesh.ny, oky);
+  const int K = vertex_disp(iz, Pz, mesh.nz, okz);
+  double t[3] = {0.0, 0.0, 0.0};
+  if (okx && oky && okz)
+    potential_at((I - 0.5) * mesh.dx, (J - 0.5) * mesh.dy, (K - 0.5) * mesh.dz, mesh.dx, mesh.dy, mesh.dz, t);
+  for (int c = 0; c < 3; ++c) out[(size_t)c * tot + idx] = Cx<double>{t[c], 0.0};
+}
+
+__global__ void k_potential_list(mm_mesh mesh, const int32_t* __restrict__ disp, long long n,
+                                 double* __restrict__ out) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double t[3];
+  potential_at((disp[3 * k] - 0.5) * mesh.dx, (disp[3 * k + 1] - 0.5) * mesh.dy, (disp[3 * k + 2] - 0.5) * mesh.dz,
+               mesh.dx, mesh.dy, mesh.dz, t);
+  for (int c = 0; c < 3; ++c) out[3 * k + c] = t[c];
+}
+
+// The spectrum of component c, S^_c(k) = -i Phi(k) C_c(k) with the half-cell
+// phase Phi(k) = exp(-i pi (kx/Px + ky/Py + kz/Pz)) and C_c real (the lattice
+// is symmetric about the half-cell shift): kp[c][kz][kx][ky] = C_c for
+// kx <= Px/2, ky <= Py/2, kz <= Pz/2 (the rest follows by parity); tracks the
+// largest |Im| / max |Re| of S^ i conj(Phi).
+template <typename T>
+__global__ void k_extract_pot(const Cx<double>* __restrict__ F, int Px, int Py, int Pz, int c, T* __restrict__ kp,
+                              unsigned long long* __restrict__ stats) {
+  const int Xp = Px / 2 + 1, Ky = Py / 2 + 1, Kz = Pz / 2 + 1;
+  const long long tot = (long long)Kz * Xp * Ky;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const int ky = (int)(idx % Ky);
+  const int kx = (int)((idx / Ky) % Xp);
+  const int kz = (int)(idx / ((long long)Ky * Xp));
+  const Cx<double> v = F[((size_t)kz * Py + ky) * Px + kx];
+  double sn, cn;
+  sincospi((double)kx / Px + (double)ky / Py + (double)kz / Pz, &sn, &cn);
+  // v * i * conj(Phi) = v * i * (cn + i sn) = v * (-sn + i cn)
+  const double re = -v.x * sn - v.y * cn, im = v.x * cn - v.y * sn;
+  kp[(size_t)c * tot + idx] = T(re);
+  atomicMax(&stats[0], (unsigned long long)__double_as_longlong(fabs(im)));
+  atomicMax(&stats[1], (unsigned long long)__double_as_longlong(fabs(re)));
+}
+
+// ---------------------------------------------------------------------------
+hipError_t setup_upload_pot_gauss(const double nodes[5][16], const double wts[5][16], const int n[5]) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_pq_nodes), nodes, sizeof(double) * 80);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_pq_wts), wts, sizeof(double) * 80);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_pq_n), n, sizeof(int) * 5);
+}
+
+hipError_t setup_potential_grid(const mm_mesh& mesh, int Px, int Py, int Pz, Cx<double>* out, hipStream_t s) {
+  const long long tot = (long long)Px * Py * Pz;
+  k_potential_grid<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, s>>>(mesh, Px, Py, Pz, out);
+  return hipGetLastError();
+}
+
+hipError_t setup_potential_list(const mm_mesh& mesh, const int32_t* disp, long long n, double* out,
+                                hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_potential_list<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(mesh, disp, n, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t setup_extract_pot(const Cx<double>* F, int Px, int Py, int Pz, int c, T* kp, unsigned long long* stats,
+                             hipStream_t s) {
+  const long long tot = (long long)(Pz / 2 + 1) * (Px / 2 + 1) * (Py / 2 + 1);
+  k_extract_pot<T><<<dim3((unsigned)((tot + 255) / 256)), 256, 0, s>>>(F, Px, Py, Pz, c, kp, stats);
+  return hipGetLastError();
+}
+
+template hipError_t setup_extract_pot<float>(const Cx<double>*, int, int, int, int, float*, unsigned long long*,
+                                             hipStream_t);
+template hipError_t setup_extract_pot<double>(const Cx<double>*, int, int, int, int, double*, unsigned long long*,
+                                              hipStream_t);
+
+// ---------------------------------------------------------------------------
 hipError_t setup_upload_gauss(const double nodes[5][20], const double wts[5][20], const int n[5]) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_gl_nodes), nodes, sizeof(double) * 100);
   if (e != hipSuccess) return e;

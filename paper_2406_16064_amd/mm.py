@@ -23,6 +23,7 @@ ALL_TERMS = 31
 DMI_BULK, DMI_D2D = 32, 64  # the other DMI symmetry classes (same D)
 CELLS = 128  # cell-based Ms, A, D of the instance (Plan.set_cells)
 INTERLAYER, STT_SOT, STT_ZL = 256, 512, 1024  # interlayer coupling, spin-orbit / Slonczewski and Zhang-Li torques
+DEMAG_POTENTIAL = 2048  # demag through the magnetic scalar potential (in place of DEMAG)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmmx.so is not built; run `python -m paper_2406_16064_amd.build` "
@@ -65,6 +66,7 @@ _sigs = {
     "mm_plan_padded": [_vp, _P(_i32), _P(_i32), _P(_i32)],
     "mm_plan_set_cells": [_vp, _i32, _P(_dbl), _P(_dbl), _P(_dbl), _vp],
     "mm_demag_tensor": [_P(Mesh), _vp, _i64, _vp, _vp],
+    "mm_scalar_potential_kernel": [_P(Mesh), _vp, _i64, _vp, _vp],
     "mm_effective_field": [_vp, _P(Params), _i32, _vp, _vp, _vp],
     "mm_llg_rhs": [_vp, _P(Params), _i32, _vp, _vp, _vp],
     "mm_energy": [_vp, _P(Params), _i32, _vp, _P(_dbl), _vp],
@@ -395,4 +397,15 @@ def demag_tensor(mesh, disp, stream=None):
     out = torch.empty((d.shape[0], 6), dtype=torch.float64, device="cuda")
     _check(_lib.mm_demag_tensor(ctypes.byref(Mesh(*mesh)), _ptr(d), d.shape[0], _ptr(out), _stream(stream)),
            "mm_demag_tensor")
+    return out.cpu().numpy()
+
+
+def scalar_potential_kernel(mesh, disp, stream=None):
+    """Cuboid potential S at the vertex - cell displacements ((I - 1/2) dx, (J - 1/2) dy, (K - 1/2) dz)
+    for disp (array [n,3] of I, J, K) -> numpy [n,3] (FP64, device-computed)."""
+    import torch
+    d = torch.as_tensor(np.ascontiguousarray(disp, dtype=np.int32)).cuda()
+    out = torch.empty((d.shape[0], 3), dtype=torch.float64, device="cuda")
+    _check(_lib.mm_scalar_potential_kernel(ctypes.byref(Mesh(*mesh)), _ptr(d), d.shape[0], _ptr(out),
+                                           _stream(stream)), "mm_scalar_potential_kernel")
     return out.cpu().numpy()

@@ -1,0 +1,136 @@
+"""GPU parity of the scalar-potential demag route (MM_DEMAG_POTENTIAL) against the oracle.
+
+* The cuboid potential S computed on the device (closed form near the cell,
+  quadrature far) against the oracle's, entry by entry, to 1e-12 relative.
+* H_eff, dm/dt and energies with every local term and the potential-route
+  demag, on 3-D meshes spanning several tiles with ragged tails, radix-3
+  padded lengths and the slab's kernel instantiations (512-long rows, Py =
+  1024, Pz = 32): FP64 to 1e-11 and FP32 to 1e-5 of max |H| (on FP32-exact m).
+* The slab at full size (512 x 512 x 16, FP32) on a sparse state: the fields
+  of sampled cells against the oracle's plain sums over the sources.
+* Refusals: MM_DEMAG with MM_DEMAG_POTENTIAL, one-cell films, integrators.
+"""
+import numpy as np
+import pytest
+
+from oracle import fields as F
+from oracle import potential as P
+
+from _util import field_err, representable, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DT = {"f32": torch.float32, "f64": torch.float64}
+TOL = {"f32": 1e-5, "f64": 1e-11}
+POT = 2048
+LOCAL = F.EXCHANGE | F.DMI | F.ANIS | F.ZEEMAN
+PAR = dict(Ms=8e5, A=1.3e-11, D=1.5e-3, Ku=2e5, u=(0.3, 0.1, 1.0), H=(2e4, -1e4, 5e4), alpha=0.2)
+MESHES = [(8, 6, 2, 3e-9, 3e-9, 3e-9), (13, 10, 3, 2e-9, 2.5e-9, 1.5e-9), (30, 17, 5, 2e-9, 2e-9, 2e-9),
+          (24, 20, 4, 5e-9, 5e-9, 5e-9), (64, 12, 16, 5e-9, 5e-9, 5e-9)]
+SLAB_PARTS = [(512, 4, 16, 5e-9, 5e-9, 5e-9), (8, 512, 16, 5e-9, 5e-9, 5e-9)]
+
+
+@pytest.fixture(scope="module")
+def mm():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_2406_16064_amd import mm as m
+    return m
+
+
+def _state(mesh, seed):
+    rng = np.random.default_rng(seed)
+    m = rng.normal(size=(3,) + tuple(mesh[2::-1][:3]))
+    m[0] += 1.0
+    return m / np.linalg.norm(m, axis=0)
+
+
+def test_kernel_entries(mm):
+    rng = np.random.default_rng(3)
+    for mesh in [(40, 30, 8, 5e-9, 5e-9, 5e-9), (600, 500, 20, 2e-9, 2e-9, 1e-9), (64, 64, 64, 3e-9, 2e-9, 1e-9)]:
+        n = np.array(mesh[:3])
+        disp = np.concatenate([rng.integers(-n + 1, n + 1, size=(300, 3)),
+                               rng.integers(-3, 4, size=(300, 3))]).astype(np.int32)
+        got = mm.scalar_potential_kernel(mesh, disp)
+        d = mesh[3:]
+        R = (disp - 0.5) * np.array(d)
+        ref = P.kernel(R, d)
+        scale = np.maximum(np.max(np.abs(ref), axis=1, keepdims=True), 1e-300)
+        assert np.max(np.abs(got - ref) / scale) <= 1e-12
+
+
+def _plan_and_params(mm, mesh, prec, terms):
+    plan = mm.Plan(mesh, prec, terms=terms | POT)
+    gp = mm.make_params(terms=terms | POT, **PAR)
+    op = F.Params(terms=terms | F.DEMAG, **PAR)
+    return plan, gp, op
+
+
+@pytest.mark.parametrize("mesh", MESHES + SLAB_PARTS)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fields_rhs_energies(mm, mesh, prec):
+    if mesh in SLAB_PARTS and prec == "f64":
+        pytest.skip("the slab's kernel instantiations are the FP32 ones")
+    m = representable(_state(mesh, 5), DT[prec])
+    plan, gp, op = _plan_and_params(mm, mesh, prec, LOCAL)
+    kern = P.PotentialKernel(F.Mesh(*mesh), P=tuple(plan.padded()[::-1]))
+    md = to_dev(m, DT[prec])
+    H = plan.effective_field(gp, md).cpu().numpy()
+    Href = P.effective_field(m, F.Mesh(*mesh), op, kern)
+    assert field_err(H, Href) <= TOL[prec]
+    Hd = mm.Plan(mesh, prec, terms=POT).effective_field(mm.make_params(terms=POT, **PAR), md).cpu().numpy()
+    assert field_err(Hd, P.demag_field(m, F.Mesh(*mesh), PAR["Ms"], kern)) <= TOL[prec]
+    k = plan.llg_rhs(gp, md).cpu().numpy()
+    assert field_err(k, F.llg_rhs_from_field(m, Href, op)) <= TOL[prec]
+    E = plan.energy(gp, md)[0]
+    Eref = P.energies(m, F.Mesh(*mesh), op, kern)
+    assert np.all(np.abs(E - Eref) <= (1e-5 if prec == "f32" else 1e-10) * np.sum(np.abs(Eref))), (E, Eref)
+
+
+def test_full_size_slab_sparse_fp32(mm):
+    """512 x 512 x 16 at the bench's size: eight unit sources in an otherwise empty
+    (zero) magnetisation, the field at 60 sampled cells from the oracle's potential
+    at their eight corners (plain sums over the sources)."""
+    mesh = (512, 512, 16, 5e-9, 5e-9, 5e-9)
+    rng = np.random.default_rng(8)
+    m = np.zeros((3, 16, 512, 512), dtype=np.float32)
+    src = np.stack([rng.integers(0, 16, 8), rng.integers(0, 512, 8), rng.integers(0, 512, 8)], axis=1)
+    for k, j, i in src:
+        v = rng.normal(size=3)
+        m[:, k, j, i] = v / np.linalg.norm(v)
+    plan = mm.Plan(mesh, "f32", terms=POT)
+    H = plan.effective_field(mm.make_params(terms=POT, **PAR), torch.tensor(m, device="cuda")).cpu().numpy()
+    d = np.array(mesh[3:])
+    Mv = PAR["Ms"] * m[:, src[:, 0], src[:, 1], src[:, 2]].T.astype(np.float64)  # [8, 3]
+    pos = src[:, ::-1].astype(np.float64) * d  # source centres (x, y, z)
+    cells = np.concatenate([src[:4], np.stack([rng.integers(0, 16, 56), rng.integers(0, 512, 56),
+                                               rng.integers(0, 512, 56)], axis=1)])
+    worst, scale = 0.0, 0.0
+    for k, j, i in cells:
+        u = np.zeros((2, 2, 2))
+        for a in range(2):
+            for b in range(2):
+                for c in range(2):
+                    v = np.array([(i + c - 0.5) * d[0], (j + b - 0.5) * d[1], (k + a - 0.5) * d[2]])
+                    u[a, b, c] = np.sum(P.kernel(v - pos, tuple(d)) * Mv)
+        ref = P.field_from_potential(u, F.Mesh(1, 1, 1, *d))[:, 0, 0, 0]
+        worst = max(worst, float(np.linalg.norm(H[:, k, j, i] - ref)))
+        scale = max(scale, float(np.linalg.norm(ref)))
+    assert worst <= 1e-5 * scale
+
+
+def test_refusals(mm):
+    with pytest.raises(mm.MMError):
+        mm.Plan((16, 16, 4, 2e-9, 2e-9, 2e-9), "f32", terms=POT | F.DEMAG)
+    with pytest.raises(mm.MMError):
+        mm.Plan((16, 16, 1, 2e-9, 2e-9, 2e-9), "f32", terms=POT)
+    mesh = (16, 12, 4, 2e-9, 2e-9, 2e-9)
+    plan = mm.Plan(mesh, "f32", terms=POT | LOCAL)
+    md = to_dev(_state(mesh, 1), torch.float32)
+    gp = mm.make_params(terms=POT | LOCAL, **PAR)
+    with pytest.raises(mm.MMError):
+        plan.rk45_run(gp, md, mm.new_states(1), t_end=1e-12)
+    with pytest.raises(mm.MMError):
+        plan.heun_run(gp, md, 1e-14, 2)
