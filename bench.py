@@ -60,6 +60,29 @@ def pass_bytes(mesh, P, w):
     return [m + sx, sx + sy, sy + K + sy, sy + sx, sx + m + m]
 
 
+POT_PASSES = ["x_fwd", "y_fwd", "z_potential", "y_inv_potential", "x_inv_potential_llg"]
+
+
+def pot_pass_bytes(mesh, P, w):
+    """Algorithmic HBM bytes of each pass of one dm/dt evaluation through the
+    scalar potential: the forward x and y passes as for the Newell route; z reads
+    the 3 spectra and the folded kernel spectrum (3 (Pz/2+1) Xp (Py/2+1) reals)
+    and writes the potential's nz + 1 vertex planes; the inverse y pass reads those
+    and writes ny + 1 vertex rows per plane; the last pass reads each vertex row
+    once and m, and writes dm/dt."""
+    nx, ny, nz = mesh[:3]
+    Px, Py, Pz = P
+    N = nx * ny * nz
+    Xp = Px // 2 + 1
+    sx = 3 * nz * Xp * ny * 2 * w
+    sy = 3 * nz * Xp * Py * 2 * w
+    K = 3 * (Pz // 2 + 1) * Xp * (Py // 2 + 1) * w
+    u_z = (nz + 1) * Xp * Py * 2 * w
+    u_y = (nz + 1) * (ny + 1) * Xp * 2 * w
+    m = 3 * N * w
+    return [m + sx, sx + sy, sy + K + u_z, u_z + u_y, u_y + m + m]
+
+
 # Dormand-Prince slopes read by the stage combinations of stages 2..6 (entries
 # of a_{s+1,j}, j < s, that are non-zero) and by the error combination
 STAGE_KPREV = (1, 2, 3, 4, 4)
@@ -333,6 +356,48 @@ def sd_bench(mm, inputs, torch, iters=200):
             "cell_iterations_per_s": cells * iters / s, "last_tau": float(tau[0])}
 
 
+def potential_bench(mm, inputs, torch, newell=None, reps=30):
+    """The 512 x 512 x 16 slab's dm/dt through the scalar potential (three
+    forward transforms and one inverse, FP32) next to the Newell route's
+    evaluation: back-to-back pass times, algorithmic bytes and the fraction of
+    8 TB/s, and the relative RMS difference of the two demag fields (a
+    discretisation difference that shrinks with the cell size, not an error)."""
+    w = inputs.workload(2)
+    mesh = tuple(w["mesh"])
+    terms = (w["terms"] & ~mm.DEMAG) | mm.DEMAG_POTENTIAL
+    plan = mm.Plan(mesh, "f32", terms=terms)
+    params = mm.make_params(terms=terms, **w["params"])
+    m = torch.tensor(inputs.initial_state(2, mesh), dtype=torch.float32, device="cuda")
+    from paper_2406_16064_amd import tuned
+    sh = tuned.lookup(mesh, "f32")  # the slab's shapes of the forward passes and tiles
+    if sh is not None:
+        plan.set_shapes(sh)
+    us = plan.profile_passes(params, m, reps=reps)
+    pb = pot_pass_bytes(mesh, plan.padded(), 4)
+    passes = [{"kernel": n, "us": round(t, 3), "alg_bytes": b, "gbs": round(b / (t * 1e-6) / 1e9, 1)}
+              for n, t, b in zip(POT_PASSES, us, pb)]
+    b, t = sum(pb), sum(us)
+    out = {"workload": "potential-" + w["name"], "padded": list(plan.padded()), "passes": passes,
+           "launch_shapes": plan.shapes(),
+           "eval_us": round(t, 3), "alg_bytes": b, "achieved_gbs": round(b / (t * 1e-6) / 1e9, 1),
+           "frac": round(b / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+           "cell_evals_per_s": mesh[0] * mesh[1] * mesh[2] / (t * 1e-6)}
+    # the demag fields of the two routes on this state
+    pd = mm.Plan(mesh, "f32", terms=mm.DEMAG_POTENTIAL)
+    Hp = pd.effective_field(mm.make_params(terms=mm.DEMAG_POTENTIAL, **w["params"]), m)
+    del pd
+    pn = mm.Plan(mesh, "f32", terms=mm.DEMAG)
+    Hn = pn.effective_field(mm.make_params(terms=mm.DEMAG, **w["params"]), m)
+    del pn
+    out["demag_rms_difference_vs_newell"] = float(torch.sqrt(torch.mean((Hp - Hn) ** 2) / torch.mean(Hn ** 2)))
+    if newell is not None:
+        out["newell_eval_us"] = newell["eval_us"]
+        out["newell_alg_bytes"] = newell["demag_pipeline"]["alg_bytes"]
+        out["speedup_over_newell"] = round(newell["eval_us"] / t, 3)
+        out["byte_ratio_to_newell"] = round(b / newell["demag_pipeline"]["alg_bytes"], 3)
+    return out
+
+
 def roofline(res, workload):
     """Roofline of the kernel that takes the most time per adaptive attempt
     (launches per attempt x back-to-back launch duration)."""
@@ -592,12 +657,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "thinfilm", "copy", "heun", "sd", "sweep", "neb"],
+    ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "thinfilm", "copy", "heun", "sd", "sweep", "neb",
+                                       "potential"],
                     default=None,
                     help="profiling aids: slab3d (slab3d_f64) runs only the 512x512x16 slab in FP32 (FP64), "
                          "thinfilm only the 256x256x1 film in FP32, and prints its record; copy runs only the "
-                         "plain 1 GiB copies the HBM counters are scaled by; heun, sd, sweep, neb run only that "
-                         "record")
+                         "plain 1 GiB copies the HBM counters are scaled by; heun, sd, sweep, neb, potential run "
+                         "only that record")
     ap.add_argument("--retune", default=None, metavar="TABLE",
                     help="autotune the launch shapes of the workloads run and store them in the table file TABLE")
     ap.add_argument("--ingest-counters", nargs=5, default=None,
@@ -635,6 +701,9 @@ def main():
     if args.only == "neb":
         print(json.dumps(neb_bench(mm, inputs, torch)))
         return
+    if args.only == "potential":
+        print(json.dumps(potential_bench(mm, inputs, torch)))
+        return
     if args.only in ("slab3d", "slab3d_f64", "thinfilm"):
         idx = 1 if args.only == "thinfilm" else 2
         r, *_ = run_workload(mm, inputs, torch, idx, "f64" if args.only == "slab3d_f64" else "f32", args.steps,
@@ -668,6 +737,8 @@ def main():
         extra["heun"] = heun_bench(mm, inputs, torch)
         print("bench: steepest descent", file=sys.stderr, flush=True)
         extra["sd"] = sd_bench(mm, inputs, torch)
+        print("bench: scalar-potential demag", file=sys.stderr, flush=True)
+        extra["potential_f32"] = potential_bench(mm, inputs, torch, newell=res)
     cpu = None
     if not args.no_cpu:
         print("bench: cpu oracle", file=sys.stderr, flush=True)

@@ -2138,8 +2138,6 @@ mm_status mm_plan_shapes(const mm_plan* p, int32_t* shape_out) {
 }
 
 mm_status mm_plan_set_shapes(mm_plan* p, const int32_t* shape) {
-  if (p && (p->e.terms & MM_DEMAG_POTENTIAL))
-    return fail(MM_E_ARG, "plans of the scalar-potential demag route keep their launch shapes");
   if (!p || !shape) return fail(MM_E_ARG, "null pointer");
   Group& G = p->e.groups[0];
   Tuning t = G.tu;
@@ -2158,6 +2156,13 @@ mm_status mm_plan_set_shapes(mm_plan* p, const int32_t* shape) {
   t.nt_i = shape[6];
   t.tpc_x = t.ty_x > 0 ? t.nt_i / (3 * t.ty_x) : 0;
   if (!tuning_ok(G, t, p->e.prec, p->e.csz)) return fail(MM_E_ARG, "launch shapes not valid for this plan");
+  if (p->e.terms & MM_DEMAG_POTENTIAL) {  // the scalar-potential passes derive their shapes from these
+    const Tuning keep = G.tu;
+    G.tu = t;
+    const bool fits = p->e.prec == MM_F32 ? pot_fits<float>(G) : pot_fits<double>(G);
+    G.tu = keep;
+    if (!fits) return fail(MM_E_ARG, "launch shapes do not fit the scalar-potential route's passes");
+  }
   G.tu = t;
   MMCHK(engine_reserve(p->e, std::vector<int>{p->maxb}));
   if (p->e.gexec) {

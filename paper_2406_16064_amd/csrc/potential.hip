@@ -87,6 +87,59 @@ __global__ void __launch_bounds__(512) k_pot_z(HotPlan<T> hp, PotTab<T> pt, int 
 }
 
 // ---------------------------------------------------------------------------
+// z pass with one (kx, ky) column per lane and the Pz-point transforms in
+// registers (FP32, 3-smooth Pz up to 32): the 3 forward transforms, the
+// product into the one scalar spectrum, its inverse transform.  HALF: nz =
+// Pz / 2, the upper half of every input column a compile-time zero.
+// ---------------------------------------------------------------------------
+template <typename T, int PZ, bool HALF>
+__global__ void __launch_bounds__(kNT, 2) k_pot_z_reg(HotPlan<T> hp, PotTab<T> pt) {
+  const Geo& g = hp.g;
+  const long long nq = (long long)g.Xp * g.Py;
+  const long long qb = (nq + kNT - 1) / kNT;
+  const int b = (int)((long long)blockIdx.x / qb);
+  const long long q = ((long long)blockIdx.x % qb) * kNT + threadIdx.x;
+  if (q >= nq) return;
+  Cx<T>* base = hp.Sy + (size_t)b * g.sy + q;
+  const size_t plane = (size_t)nq;
+  Cx<T> v[3][PZ];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < PZ; ++z) {
+      v[c][z] = {T(0), T(0)};
+      if (HALF ? z < PZ / 2 : z < g.nz) v[c][z] = gld(base + ((size_t)c * g.nz + z) * plane);
+    }
+  asm volatile("" : "+v"(base));  // stores recompute their addresses (fewer live registers)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) RegFft<T, PZ, 1, false>::run(v[c], hp.twz);
+  const int kx = (int)q / g.Py, ky = (int)q - kx * g.Py;
+  const bool fy = ky > g.Py - ky;
+  const int kyf = fy ? g.Py - ky : ky;
+  const size_t cstride = (size_t)g.Kz * g.Xp * g.Ky;
+  const T s = T(ldu(&hp.prm[b].demag_scale));
+  const Cx<T> pxy = cmul(gld(pt.phx + kx), gld(pt.phy + ky));
+#pragma unroll
+  for (int kz = 0; kz < PZ; ++kz) {
+    const bool fz = kz > PZ - kz;
+    const int kzf = fz ? PZ - kz : kz;
+    const size_t off = ((size_t)kzf * g.Xp + kx) * g.Ky + kyf;
+    // parities of the folded kernel: C_x odd in ky and kz, C_y in kz, C_z in ky
+    const T cxv = gld(pt.kp + off) * ((fy != fz) ? -s : s);
+    const T cyv = gld(pt.kp + cstride + off) * (fz ? -s : s);
+    const T czv = gld(pt.kp + 2 * cstride + off) * (fy ? -s : s);
+    const Cx<T> a = v[0][kz], bb = v[1][kz], cc = v[2][kz];
+    const Cx<T> w = {cxv * a.x + cyv * bb.x + czv * cc.x, cxv * a.y + cyv * bb.y + czv * cc.y};
+    const Cx<T> pw = cmul(cmul(pxy, ldu(pt.phz + kz)), w);
+    v[0][kz] = Cx<T>{pw.y, -pw.x};  // -i Phi w
+  }
+  RegFft<T, PZ, 1, true>::run(v[0], hp.twz);
+#pragma unroll
+  for (int z = 0; z < PZ; ++z)
+    if (HALF ? z <= PZ / 2 : z <= g.nz) gst(base + (size_t)z * plane, v[0][z]);
+}
+
+// ---------------------------------------------------------------------------
 // y inverse: CB consecutive kx of vertex plane k of one instance.
 // ---------------------------------------------------------------------------
 template <typename T, bool R16>
@@ -268,6 +321,37 @@ bool pot_supported(const HotPlan<T>& h, int tpc_x_min) {
   return h.g.nz >= 2 && p.tpc_x >= tpc_x_min && p.lds_x <= 160 * 1024;
 }
 
+// The register z pass where it applies (FP32, Pz a 3-smooth length up to 32);
+// false: the caller launches the LDS version.
+template <typename T>
+bool pot_z_reg(const HotPlan<T>& h, const PotTab<T>& pt, hipStream_t s) {
+  if constexpr (sizeof(T) != 4) {
+    (void)h; (void)pt; (void)s;
+    return false;
+  } else {
+    const Geo& g = h.g;
+    const dim3 grid((unsigned)((long long)h.batch * (((long long)g.Xp * g.Py + kNT - 1) / kNT)));
+    const bool half = 2 * g.nz == g.Pz;
+#define MMX_PZ(PZ)                                                             \
+  case PZ:                                                                     \
+    if (half && PZ % 2 == 0) k_pot_z_reg<T, PZ, true><<<grid, kNT, 0, s>>>(h, pt); \
+    else k_pot_z_reg<T, PZ, false><<<grid, kNT, 0, s>>>(h, pt);                \
+    return true;
+    switch (g.Pz) {
+      MMX_PZ(4)
+      MMX_PZ(6)
+      MMX_PZ(8)
+      MMX_PZ(12)
+      MMX_PZ(16)
+      MMX_PZ(18)
+      MMX_PZ(24)
+      MMX_PZ(32)
+      default: return false;
+    }
+#undef MMX_PZ
+  }
+}
+
 template <typename T>
 hipError_t launch_potential(const GroupSet<T>& gs, const Epi<T>* epis, const PotTab<T>& pt, int mode,
                             hipStream_t s, unsigned pass_mask) {
@@ -281,9 +365,11 @@ hipError_t launch_potential(const GroupSet<T>& gs, const Epi<T>* epis, const Pot
     if (er != hipSuccess) return er;
   }
   if (pass_mask & 4u) {
-    const long long blocks = (long long)h.batch * (((long long)g.Xp * g.Py + p.qz - 1) / p.qz);
-    const size_t lds = (size_t)3 * p.qz * col_stride(g.Pz) * csz;
-    k_pot_z<T><<<dim3((unsigned)blocks), 3 * p.qz * p.tpc_z, lds, s>>>(h, pt, p.qz, p.tpc_z);
+    if (!pot_z_reg<T>(h, pt, s)) {
+      const long long blocks = (long long)h.batch * (((long long)g.Xp * g.Py + p.qz - 1) / p.qz);
+      const size_t lds = (size_t)3 * p.qz * col_stride(g.Pz) * csz;
+      k_pot_z<T><<<dim3((unsigned)blocks), 3 * p.qz * p.tpc_z, lds, s>>>(h, pt, p.qz, p.tpc_z);
+    }
   }
   if (pass_mask & 8u) {
     bool r16 = false;
