@@ -370,10 +370,13 @@ mm_status mm_plan_set_shapes(mm_plan* plan, const int32_t* shape);
  * microseconds, in launch order: x forward, y (2-D: fused forward/product/
  * inverse; 3-D: forward, z with product, inverse), x inverse with the fused
  * local fields and LL (dm/dt epilogue).  Without demag there is one pass.
- * us_out must hold at least 5 entries.  Synchronises. */
+ * us_out must hold at least 5 entries.  seq_out (nullable, 5 entries): the
+ * same passes timed in evaluation order -- `reps` whole evaluations, each
+ * pass after the one whose output it reads, an event before every pass.
+ * Synchronises. */
 mm_status mm_profile_passes(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
                             void* work, int32_t reps, double* us_out, int32_t* n_pass,
-                            void* hip_stream);
+                            double* seq_out, void* hip_stream);
 
 /* Measurement aid for the adaptive step: sets up one Dormand-Prince attempt of
  * `batch` instances from m and the states st (as mm_rk45_run would; neither m
@@ -384,10 +387,15 @@ mm_status mm_profile_passes(mm_plan* plan, const mm_params* params, int32_t batc
  * inverse-x pass with the stage epilogue (mean over stages 2..6, in the form
  * the captured attempt runs: with the next stage's forward x transform when
  * *fused_out is 1); us_out[n-1]: the inverse-x pass with the error epilogue.
- * *n_out = passes + 2 (at most 7); us_out must hold 8 entries.  Synchronises. */
+ * *n_out = passes + 2 (at most 7); us_out must hold 8 entries.  seq_out
+ * (nullable, 8 entries, same layout): the same kernels timed in attempt order
+ * -- `reps` whole attempts as the captured graph runs them, each kernel after
+ * the one whose output it reads (so caches hold what they hold in a real
+ * run), an event before every kernel; the mean over every launch of a kind.
+ * These attempts run on a copy of m.  Synchronises. */
 mm_status mm_profile_step(mm_plan* plan, const mm_params* params, int32_t batch, void* m,
                           const mm_rk45_state* st, int32_t reps, double* us_out, int32_t* n_out,
-                          int32_t* fused_out, void* hip_stream);
+                          int32_t* fused_out, double* seq_out, void* hip_stream);
 
 const char* mm_status_string(mm_status s);
 const char* mm_last_error(void);

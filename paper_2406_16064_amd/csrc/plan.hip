@@ -855,7 +855,7 @@ PotTab<T> pot_tab(const Group& G) {
 // (after one full evaluation that fills the intermediate buffers).
 template <typename T>
 mm_status time_pot_passes(Engine& E, const GroupSet<T>& gs, const Epi<T>* epis, int reps, double* us,
-                          hipStream_t s) {
+                          hipStream_t s, double* seq = nullptr) {
   const PotTab<T> pt = pot_tab<T>(E.groups[0]);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -865,6 +865,27 @@ mm_status time_pot_passes(Engine& E, const GroupSet<T>& gs, const Epi<T>* epis, 
     return fail(MM_E_HIP, hipGetErrorString(er));
   }
   er = launch_potential<T>(gs, epis, pt, MODE_RHS, s);
+  if (seq) {  // in evaluation order
+    hipEvent_t ev[6] = {};
+    for (auto& e : ev)
+      if (er == hipSuccess) er = hipEventCreate(&e);
+    for (int i = 0; i < 5; ++i) seq[i] = 0.0;
+    for (int r = 0; r < reps && er == hipSuccess; ++r) {
+      for (int i = 0; i < 5 && er == hipSuccess; ++i) {
+        er = hipEventRecord(ev[i], s);
+        if (er == hipSuccess) er = launch_potential<T>(gs, epis, pt, MODE_RHS, s, 1u << i);
+      }
+      if (er == hipSuccess) er = hipEventRecord(ev[5], s);
+      if (er == hipSuccess) er = hipEventSynchronize(ev[5]);
+      for (int i = 0; i < 5 && er == hipSuccess; ++i) {
+        float ms = 0.f;
+        er = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        seq[i] += 1e3 * ms / reps;
+      }
+    }
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
   for (int i = 0; i < 5 && er == hipSuccess; ++i) {
     er = hipEventRecord(e0, s);
     for (int r = 0; r < reps && er == hipSuccess; ++r) er = launch_potential<T>(gs, epis, pt, MODE_RHS, s, 1u << i);
@@ -914,7 +935,7 @@ int pass_count(const Engine& E) {
 // every intermediate buffer).  us[p] = mean duration of pass p.
 template <typename T>
 mm_status time_each_pass(Engine& E, const GroupSet<T>& gs, const Epi<T>* epis, int mode, int reps, int np,
-                         double* us, hipStream_t s) {
+                         double* us, hipStream_t s, double* seq = nullptr) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   hipError_t er = hipEventCreate(&e1);
@@ -924,6 +945,27 @@ mm_status time_each_pass(Engine& E, const GroupSet<T>& gs, const Epi<T>* epis, i
   }
   mm_status st = MM_OK;
   er = launch_eval<T>(gs, epis, mode, demag_on(E), s);
+  if (seq) {  // in evaluation order: each pass after the one whose output it reads
+    std::vector<hipEvent_t> ev(np + 1, nullptr);
+    for (auto& e : ev)
+      if (er == hipSuccess) er = hipEventCreate(&e);
+    for (int i = 0; i < np; ++i) seq[i] = 0.0;
+    for (int r = 0; r < reps && er == hipSuccess; ++r) {
+      for (int i = 0; i < np && er == hipSuccess; ++i) {
+        er = hipEventRecord(ev[i], s);
+        if (er == hipSuccess) er = launch_eval<T>(gs, epis, mode, demag_on(E), s, nullptr, false, false, 1u << i);
+      }
+      if (er == hipSuccess) er = hipEventRecord(ev[np], s);
+      if (er == hipSuccess) er = hipEventSynchronize(ev[np]);
+      for (int i = 0; i < np && er == hipSuccess; ++i) {
+        float ms = 0.f;
+        er = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        seq[i] += 1e3 * ms / reps;
+      }
+    }
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
   for (int i = 0; i < np && er == hipSuccess; ++i) {
     const unsigned bit = (unsigned)i;  // pass i in launch order has bit i (see launch_eval)
     er = hipEventRecord(e0, s);
@@ -943,14 +985,14 @@ mm_status time_each_pass(Engine& E, const GroupSet<T>& gs, const Epi<T>* epis, i
 
 template <typename T>
 mm_status profile_impl(mm_plan* p, const mm_params* q, int batch, const void* m, void* out, int reps, double* us,
-                       hipStream_t s) {
+                       hipStream_t s, double* seq) {
   Engine& E = p->e;
   MMCHK(single_eval<T>(p, batch, q, m, out, MODE_RHS, nullptr, s));
   GroupSet<T> gs;
   std::vector<int> inst0;
   MMCHK(make_set<T>(E, std::vector<int>{batch}, gs, inst0, s));
-  if (E.any_pot) return time_pot_passes<T>(E, gs, epi_slot<T>(E, 0), reps, us, s);
-  return time_each_pass<T>(E, gs, epi_slot<T>(E, 0), MODE_RHS, reps, pass_count(E), us, s);
+  if (E.any_pot) return time_pot_passes<T>(E, gs, epi_slot<T>(E, 0), reps, us, s, seq);
+  return time_each_pass<T>(E, gs, epi_slot<T>(E, 0), MODE_RHS, reps, pass_count(E), us, s, seq);
 }
 
 // Energies from the partial sums `partial` (device, [batch][blocks][5]) of one
@@ -1230,6 +1272,8 @@ constexpr long long kNoLimit = 1LL << 60;
 struct StepProfile {
   int reps = 0;
   double us[16] = {};
+  double seq[16] = {};  // the same kernels timed in attempt order (each after the kernel it depends on)
+  bool want_seq = false;
   int n = 0;
   int fused = 0;
 };
@@ -1277,6 +1321,47 @@ mm_status profile_step(Engine& E, const GroupSet<T>& gs, StepProfile& pr, hipStr
   const unsigned last = 1u << (np - 1);
   pr.us[np + 1] = timed([&]() { return launch_eval<T>(gs, epi_slot<T>(E, 7), MODE_ERROR, demag_on(E), s, nullptr,
                                                       false, false, last); });
+  // In attempt order: whole attempts as the captured graph runs them (step
+  // begin, then stages 2..7 pass by pass, the fused forward x transforms
+  // included), an event before every kernel; seq[k] = mean duration of kernel
+  // kind k over every launch of that kind (the caller's m is a copy here).
+  if (pr.want_seq) {
+    const int nslot = 2 + 6 * np;  // begin, x forward of stage 2, then np passes per stage
+    std::vector<hipEvent_t> ev(nslot + 1, nullptr);
+    for (auto& e : ev)
+      if (er == hipSuccess) er = hipEventCreate(&e);
+    std::vector<double> acc(16, 0.0);
+    std::vector<int> cnt(16, 0);
+    for (int r = 0; r < pr.reps && er == hipSuccess; ++r) {
+      int k = 0;
+      std::vector<int> kind;
+      er = hipEventRecord(ev[k++], s);
+      if (er == hipSuccess) er = launch_begin<T>(gs, epi_slot<T>(E, 8), s);
+      kind.push_back(0);
+      for (int stg = 2; stg <= 7 && er == hipSuccess; ++stg) {
+        const int mode = stg < 7 ? MODE_STAGE : MODE_ERROR;
+        for (int i = 0; i < np && er == hipSuccess; ++i) {
+          if (i == 0 && demag_on(E) && fz && stg > 2) continue;  // done by the previous stage's fused pass
+          er = hipEventRecord(ev[k++], s);
+          if (er == hipSuccess)
+            er = launch_eval<T>(gs, epi_slot<T>(E, stg), mode, demag_on(E), s, nullptr, fz && stg > 2,
+                                fz && stg < 7, 1u << i);
+          kind.push_back(i + 1 == np ? (stg < 7 ? np : np + 1) : 1 + i);
+        }
+      }
+      if (er == hipSuccess) er = hipEventRecord(ev[k], s);
+      if (er == hipSuccess) er = hipEventSynchronize(ev[k]);
+      for (int j = 0; j < k && er == hipSuccess; ++j) {
+        float ms = 0.f;
+        er = hipEventElapsedTime(&ms, ev[j], ev[j + 1]);
+        acc[kind[j]] += 1e3 * ms;
+        cnt[kind[j]] += 1;
+      }
+    }
+    for (int i = 0; i < np + 2; ++i) pr.seq[i] = cnt[i] > 0 ? acc[i] / cnt[i] : 0.0;
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
   mm_status st = er == hipSuccess ? MM_OK : fail(MM_E_HIP, hipGetErrorString(er));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -2079,34 +2164,50 @@ mm_status mm_heun_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, do
 }
 
 mm_status mm_profile_step(mm_plan* p, const mm_params* q, int32_t batch, void* m, const mm_rk45_state* st,
-                          int32_t reps, double* us_out, int32_t* n_out, int32_t* fused_out, void* hip_stream) {
+                          int32_t reps, double* us_out, int32_t* n_out, int32_t* fused_out, double* seq_out,
+                          void* hip_stream) {
   MMCHK(plan_checks(p, q, batch));
   if (!m || !st || !us_out || !n_out || !fused_out) return fail(MM_E_ARG, "null argument");
   if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
   std::vector<mm_rk45_state> copy(st, st + batch);  // the caller's states are not advanced
+  // ... nor its m: the attempts timed in order run on a copy
+  const size_t bytes = p->e.rsz * 3 * (size_t)p->e.groups[0].g.N * batch;
+  void* mc = nullptr;
+  MMCHK(dev_alloc(&mc, bytes));
+  hipError_t e = hipMemcpyAsync(mc, m, bytes, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    (void)hipFree(mc);
+    return fail(MM_E_HIP, hipGetErrorString(e));
+  }
   StepProfile pr;
   pr.reps = reps;
+  pr.want_seq = seq_out != nullptr;
   const double t_end = copy[0].t + 1.0;  // any end beyond one step
   mm_status r = p->e.prec == MM_F32
-                    ? plan_rk45<float>(p, q, batch, m, copy.data(), t_end, kNoLimit, nullptr, 0, true, s, &pr)
-                    : plan_rk45<double>(p, q, batch, m, copy.data(), t_end, kNoLimit, nullptr, 0, true, s, &pr);
+                    ? plan_rk45<float>(p, q, batch, mc, copy.data(), t_end, kNoLimit, nullptr, 0, true, s, &pr)
+                    : plan_rk45<double>(p, q, batch, mc, copy.data(), t_end, kNoLimit, nullptr, 0, true, s, &pr);
+  e = hipStreamSynchronize(s);
+  (void)hipFree(mc);
+  p->e.k1_ok = false;  // the first slopes belong to the copy
   if (r != MM_OK) return r;
-  HIPCHK(hipStreamSynchronize(s));
+  if (e != hipSuccess) return fail(MM_E_HIP, hipGetErrorString(e));
   for (int i = 0; i < pr.n; ++i) us_out[i] = pr.us[i];
+  if (seq_out)
+    for (int i = 0; i < pr.n; ++i) seq_out[i] = pr.seq[i];
   *n_out = pr.n;
   *fused_out = pr.fused;
   return MM_OK;
 }
 
 mm_status mm_profile_passes(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work, int32_t reps,
-                            double* us_out, int32_t* n_pass, void* hip_stream) {
+                            double* us_out, int32_t* n_pass, double* seq_out, void* hip_stream) {
   MMCHK(plan_checks(p, q, batch, true));
   if (!m || !work || !us_out || !n_pass) return fail(MM_E_ARG, "null argument");
   if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
-  mm_status st = p->e.prec == MM_F32 ? profile_impl<float>(p, q, batch, m, work, reps, us_out, s)
-                                     : profile_impl<double>(p, q, batch, m, work, reps, us_out, s);
+  mm_status st = p->e.prec == MM_F32 ? profile_impl<float>(p, q, batch, m, work, reps, us_out, s, seq_out)
+                                     : profile_impl<double>(p, q, batch, m, work, reps, us_out, s, seq_out);
   *n_pass = pass_count(p->e);
   return st;
 }

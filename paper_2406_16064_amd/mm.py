@@ -78,8 +78,9 @@ _sigs = {
     "mm_sd_run_noalloc": [_vp, _P(Params), _i32, _vp, _i64, _dbl, _dbl, _dbl, _P(_dbl), _vp],
     "mm_sd_relax": [_vp, _P(Params), _i32, _vp, _dbl, _i64, _dbl, _dbl, _dbl, _P(_i64), _P(_dbl), _P(_dbl), _vp],
     "mm_rk45_relax": [_vp, _P(Params), _i32, _vp, _P(RK45State), _dbl, _i64, _P(_dbl), _vp],
-    "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _vp],
-    "mm_profile_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _i32, _P(_dbl), _P(_i32), _P(_i32), _vp],
+    "mm_profile_passes": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_dbl), _P(_i32), _P(_dbl), _vp],
+    "mm_profile_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _i32, _P(_dbl), _P(_i32), _P(_i32), _P(_dbl),
+                        _vp],
     "mm_plan_autotune": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
     "mm_plan_shapes": [_vp, _P(_i32)],
     "mm_plan_set_shapes": [_vp, _P(_i32)],
@@ -319,26 +320,38 @@ class Plan:
         shape = (ctypes.c_int32 * 8)(*[int(cur[k]) for k in SHAPE_KEYS], 0)
         _check(_lib.mm_plan_set_shapes(self._h, shape), "mm_plan_set_shapes")
 
-    def profile_passes(self, params, m, reps=20, stream=None):
-        """Mean duration (us) of each kernel pass of one dm/dt evaluation."""
+    def profile_passes(self, params, m, reps=20, stream=None, in_order=False):
+        """Mean duration (us) of each kernel pass of one dm/dt evaluation, each pass launched
+        back to back; with in_order also the passes of whole evaluations timed in their own
+        order (returns (back_to_back, in_order))."""
         import torch
         work = torch.empty_like(m)
         us = (ctypes.c_double * 8)()
+        seq = (ctypes.c_double * 8)()
         n = _i32()
         _check(_lib.mm_profile_passes(self._h, _params_array(params), self._batch(m), _ptr(m), _ptr(work),
-                                      reps, us, ctypes.byref(n), _stream(stream)), "mm_profile_passes")
+                                      reps, us, ctypes.byref(n), seq, _stream(stream)), "mm_profile_passes")
+        if in_order:
+            return list(us[:n.value]), list(seq[:n.value])
         return list(us[:n.value])
 
-    def profile_step(self, params, m, states, reps=20, stream=None):
+    def profile_step(self, params, m, states, reps=20, stream=None, in_order=False):
         """Mean duration (us) of each kernel of one adaptive attempt, launched back to back:
-        returns (begin_us, [stage pass us...], error_x_inverse_us, fused)."""
+        returns (begin_us, [stage pass us...], error_x_inverse_us, fused); with in_order also
+        the same figures from whole attempts timed in their own order (a fifth item, a tuple
+        of the first three)."""
         us = (ctypes.c_double * 8)()
+        seq = (ctypes.c_double * 8)()
         n = _i32()
         fused = _i32()
         _check(_lib.mm_profile_step(self._h, _params_array(params), self._batch(m), _ptr(m), states, reps, us,
-                                    ctypes.byref(n), ctypes.byref(fused), _stream(stream)), "mm_profile_step")
+                                    ctypes.byref(n), ctypes.byref(fused), seq, _stream(stream)), "mm_profile_step")
         v = list(us[:n.value])
-        return v[0], v[1:-1], v[-1], bool(fused.value)
+        out = (v[0], v[1:-1], v[-1], bool(fused.value))
+        if in_order:
+            w = list(seq[:n.value])
+            out = out + ((w[0], w[1:-1], w[-1]),)
+        return out
 
     def close(self):
         if self._h:
