@@ -18,10 +18,23 @@
 //   x inverse      2 (TY + 1) vertex rows (planes z, z + 1) of TY cell rows:
 //                  complex-to-real along x (nx + 1 vertices), the edge
 //                  differences, local fields, LL and the epilogue
+#include <type_traits>
+
 #include "hotpath.hpp"
 #include "potential.hpp"
 
 namespace mmx {
+
+// Vertex rows of the potential after the inverse y pass, in the x-pass buffer:
+// V[k][XB][ny + 1][kSxB] per instance (kx in blocks of kSxB, as the Newell
+// route keeps its x spectrum), so that a y tile of whole blocks writes
+// contiguous runs and an x workgroup reads kSxB (TY + 1) contiguous entries per
+// block.
+template <typename T>
+__device__ __forceinline__ Cx<T>* vaddr(const HotPlan<T>& hp, int b, int k, int kx, int y) {
+  const Geo& g = hp.g;
+  return hp.Sx + (size_t)b * g.sx + (((size_t)k * g.XB + (kx >> 2)) * (g.ny + 1) + y) * kSxB + (kx & 3);
+}
 
 // ---------------------------------------------------------------------------
 // z pass: QZ consecutive (kx, ky) points of one instance.
@@ -164,18 +177,56 @@ __global__ void __launch_bounds__(512) k_pot_yinv(HotPlan<T> hp, int CB, int tpc
   __syncthreads();
   fft_columns<T, true, false, R16>(lds, hp.fd[1], cs, ncol, tpc, hp.fd[1].tw);
   __syncthreads();
-  Cx<T>* dst = hp.Sx + (size_t)b * g.sx + (size_t)k * (g.ny + 1) * g.Xp + kx0;  // V[k][y][kx]
   for (int t = threadIdx.x; t < (g.ny + 1) * ncol; t += blockDim.x) {
     const int y = t / ncol, i = t - y * ncol;
-    gst(dst + (size_t)y * g.Xp + i, lds[i * cs + pidx(y, sh)]);
+    gst(vaddr(hp, b, k, kx0 + i, y), lds[i * cs + pidx(y, sh)]);
   }
+}
+
+// y inverse with the transform compiled for Py = SL (a power of two, SL/EPT
+// threads a column): columns read straight from global memory by the first
+// stage and the vertex rows written by the last.
+template <typename T>
+struct VStore {  // column kx0 + c of the vertex plane starting at base (V[k]); rows 0..ny only
+  Cx<T>* base;
+  int ny, kx0;
+  template <bool CHK>
+  __device__ __forceinline__ void put(int c, int e, Cx<T> v) const {
+    const int kx = kx0 + c;
+    if (e <= ny) gst(base + ((size_t)(kx >> 2) * (ny + 1) + e) * kSxB + (kx & 3), v);
+  }
+};
+
+template <typename T, int SL, int EPT>
+__global__ void __launch_bounds__(512) k_pot_yinv_s(HotPlan<T> hp, int CB) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
+  const Geo& g = hp.g;
+  const int tiles = (g.Xp + CB - 1) / CB;
+  unsigned bid = blockIdx.x;
+  const int tile = (int)(bid % (unsigned)tiles); bid /= (unsigned)tiles;
+  const int k = (int)(bid % (unsigned)(g.nz + 1));
+  const int b = (int)(bid / (unsigned)(g.nz + 1));
+  const int kx0 = tile * CB;
+  const int ncol = g.Xp - kx0 < CB ? g.Xp - kx0 : CB;
+  constexpr int TPC = SL / EPT;
+  const int c = (int)threadIdx.x / TPC;
+  const int cc = c < ncol ? c : 0;
+  const Cx<T>* src = hp.Sy + (size_t)b * g.sy + (size_t)k * g.Xp * g.Py;
+  const ColLoad<T> ld{src, (uint32_t)((kx0 + cc) * g.Py) * (uint32_t)sizeof(Cx<T>), g.Py};
+  const VStore<T> st{vaddr(hp, b, k, 0, 0), g.ny, kx0};
+  fft_static<T, SL, (EPT > 8), true, true, true, false, false, false, EPT>(lds, hp.fd[1].tw, col_stride(SL), ncol,
+                                                                          ld, st, NoHook{});
 }
 
 // ---------------------------------------------------------------------------
 // x inverse + edge differences + local fields + epilogue: TY cell rows of
-// plane z of one instance (MODE_FIELD, MODE_RHS or MODE_ENERGY).
+// plane z of one instance (MODE_FIELD, MODE_RHS or MODE_ENERGY).  The TY + 1
+// vertex rows of vertex planes z and z + 1 are loaded (kSxB (TY + 1)
+// contiguous entries per kx block), transformed together, and each cell reads
+// its eight corners from LDS.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int MODE, int CPT>
 __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __restrict__ epis, int tpc, T gx, T gy,
                                               T gz) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -184,7 +235,12 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
   const Geo& g = hp.g;
   const int TY = hp.tu.ty_x;
   const int tiles = (g.ny + TY - 1) / TY;
-  unsigned bid = blockIdx.x;
+  const long long nblk = (long long)hp.batch * g.nz * tiles;
+  // the grid is padded to a multiple of 8; consecutive tiles (neighbouring z
+  // planes, which share a vertex plane) run on the same XCD
+  const long long bidx = xcd_tile((long long)blockIdx.x, (long long)gridDim.x);
+  if (bidx >= nblk) return;
+  unsigned bid = (unsigned)bidx;
   const int z = (int)(bid % (unsigned)g.nz); bid /= (unsigned)g.nz;
   const int tile = (int)(bid % (unsigned)tiles);
   const int b = (int)(bid / (unsigned)tiles);
@@ -200,13 +256,30 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
   if (add_hd) {
     TableCopy<T, 4> tab;
     tab.issue(hp.fd[0].tw, g.Lx, hp.post, g.Lx + 1);
-    const Cx<T>* V = hp.Sx + (size_t)b * g.sx;
-    for (int t = threadIdx.x; t < ncol * g.Xp; t += blockDim.x) {
-      const int col = t / g.Xp, k = t - col * g.Xp;
-      const int p = col / R1, r = col - p * R1;
-      Cx<T> v = {T(0), T(0)};
-      if (r <= nrow) v = gld(V + ((size_t)(z + p) * (g.ny + 1) + y0 + r) * g.Xp + k);
-      lds[col * cs + pidx(k, sh)] = v;
+    // per vertex plane and kx block: the kSxB (nrow + 1) entries of rows y0 ..
+    // y0 + nrow, contiguous; U loads a thread in flight before their LDS stores
+    const int per = kSxB * R1;
+    const int tot = 2 * g.XB * per;
+    constexpr int U = 4;
+    for (int t0 = threadIdx.x; t0 < tot; t0 += U * blockDim.x) {
+      Cx<T> v[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int t = t0 + j * blockDim.x;
+        const int pb = t / per, q = t - pb * per;
+        const int p = pb / g.XB, kb = pb - p * g.XB;
+        const int r = q >> 2, k = kb * kSxB + (q & 3);
+        v[j] = {T(0), T(0)};
+        if (t < tot && r <= nrow && k < g.Xp) v[j] = gld(vaddr(hp, b, z + p, k, y0 + r));
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int t = t0 + j * blockDim.x;
+        const int pb = t / per, q = t - pb * per;
+        const int p = pb / g.XB, kb = pb - p * g.XB;
+        const int r = q >> 2, k = kb * kSxB + (q & 3);
+        if (t < tot && r <= nrow && k < g.Xp) lds[(p * R1 + r) * cs + pidx(k, sh)] = v[j];
+      }
     }
     tab.store(twl);
     __syncthreads();
@@ -219,18 +292,31 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
       const int k2 = g.Lx - k;
       const Cx<T> Xa = cp[pidx(k, sh)], Xb = cp[pidx(k2, sh)];
       {
-        const Cx<T> s = cadd(Xa, cconj(Xb));
-        const Cx<T> d = cmul(csub(Xa, cconj(Xb)), cconj(postl[k]));
-        cp[pidx(k, sh)] = Cx<T>{s.x - d.y, s.y + d.x};
+        const Cx<T> s_ = cadd(Xa, cconj(Xb));
+        const Cx<T> d_ = cmul(csub(Xa, cconj(Xb)), cconj(postl[k]));
+        cp[pidx(k, sh)] = Cx<T>{s_.x - d_.y, s_.y + d_.x};
       }
       if (k > 0 && k < k2) {
-        const Cx<T> s = cadd(Xb, cconj(Xa));
-        const Cx<T> d = cmul(csub(Xb, cconj(Xa)), cconj(postl[k2]));
-        cp[pidx(k2, sh)] = Cx<T>{s.x - d.y, s.y + d.x};
+        const Cx<T> s_ = cadd(Xb, cconj(Xa));
+        const Cx<T> d_ = cmul(csub(Xb, cconj(Xa)), cconj(postl[k2]));
+        cp[pidx(k2, sh)] = Cx<T>{s_.x - d_.y, s_.y + d_.x};
       }
     }
     __syncthreads();
-    fft_columns<T, true, true>(lds, hp.fd[0], cs, ncol, tpc, twl);
+    // the full inverse transform (vertex nx needs the entry Lx / 2); compiled
+    // for the power-of-two lengths when the workgroup has Lx / 16 threads a column
+    const bool st16 = (g.Lx == 128 || g.Lx == 256 || g.Lx == 512 || g.Lx == 1024) &&
+                      ncol * (g.Lx / 16) <= (int)blockDim.x;
+    if (st16) {
+      switch (g.Lx) {
+        case 128: fft_static<T, 128, false, true, false, false, true, false, false, 16>(lds, twl, cs, ncol, NoLoad<T>{}, NoStore<T>{}, NoHook{}); break;
+        case 256: fft_static<T, 256, false, true, false, false, true, false, false, 16>(lds, twl, cs, ncol, NoLoad<T>{}, NoStore<T>{}, NoHook{}); break;
+        case 512: fft_static<T, 512, false, true, false, false, true, false, false, 16>(lds, twl, cs, ncol, NoLoad<T>{}, NoStore<T>{}, NoHook{}); break;
+        default: fft_static<T, 1024, false, true, false, false, true, false, false, 16>(lds, twl, cs, ncol, NoLoad<T>{}, NoStore<T>{}, NoHook{}); break;
+      }
+    } else {
+      fft_columns<T, true, true>(lds, hp.fd[0], cs, ncol, tpc, twl);
+    }
     __syncthreads();
   }
   // u at vertex (x, row r, plane p) of this tile: real x of column p R1 + r
@@ -246,7 +332,13 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
   const size_t ib = (size_t)b * epi.inst_stride;
   const T* mb = epi.in + ib;
   double esum[5] = {0, 0, 0, 0, 0};
-  for (int e = threadIdx.x; e < nrow * g.nx; e += blockDim.x) {
+  const int ncell = nrow * g.nx;
+  // CPT > 0: at most CPT cells a thread, unrolled, their results stored after
+  // the last of them (so the loads of every cell can be in flight together)
+  constexpr int NS = CPT > 0 ? CPT : 1;
+  V3<T> res[NS];
+  COff cos[NS];
+  auto cell = [&](int e, int slot) {
     const int r = e / g.nx, x = e - r * g.nx;
     const int y = y0 + r;
     const COff co = coff_of<T>(N, (z * g.ny + y) * g.nx + x);
@@ -265,14 +357,33 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
       H.x += hd.x; H.y += hd.y; H.z += hd.z;
     }
     const V3<T> mi = nb.mi;
-    if constexpr (MODE == MODE_FIELD) st3o(epi.out + ib, co, H);
-    if constexpr (MODE == MODE_RHS) st3o(epi.out + ib, co, ll_rhs(mi, H, g1, g2));
+    V3<T> o = H;
+    if constexpr (MODE == MODE_RHS) o = ll_rhs(mi, H, g1, g2);
     if constexpr (MODE == MODE_ENERGY) {
       esum[0] += lt.ex;
       if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
       esum[2] += lt.dmi;
       esum[3] += lt.an;
       esum[4] += lt.ze;
+    } else if constexpr (CPT > 0) {
+      res[slot] = o;
+      cos[slot] = co;
+    } else {
+      st3o(epi.out + ib, co, o);
+    }
+  };
+  if constexpr (CPT == 0) {
+    for (int e = threadIdx.x; e < ncell; e += blockDim.x) cell(e, 0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int e = threadIdx.x + k * blockDim.x;
+      if (e < ncell) cell(e, k);
+    }
+    if constexpr (MODE != MODE_ENERGY) {
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        if ((int)threadIdx.x + k * (int)blockDim.x < ncell) st3o(epi.out + ib, cos[k], res[k]);
     }
   }
   if constexpr (MODE == MODE_ENERGY) {
@@ -286,7 +397,7 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
       double v = 0;
       for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
       const int bpi = tiles * g.nz;
-      const int lb = (int)(blockIdx.x % (unsigned)bpi);
+      const int lb = (int)(bidx % bpi);
       gst(epi.partial + ((size_t)b * bpi + lb) * 5 + threadIdx.x, v);
     }
   }
@@ -297,7 +408,7 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
 // ---------------------------------------------------------------------------
 template <typename T>
 PotShape pot_shape(const HotPlan<T>& h) {
-  PotShape p;
+  PotShape p{};
   const Geo& g = h.g;
   const size_t csz = sizeof(Cx<T>);
   p.tpc_z = h.tu.tpc_z;
@@ -309,8 +420,23 @@ PotShape pot_shape(const HotPlan<T>& h) {
   p.cb_y = cb;
   p.tpc_x = h.tu.tpc_x;
   const int ncol = 2 * (h.tu.ty_x + 1);
-  p.nt_x = std::min(512, std::max(64, (ncol * p.tpc_x + 63) / 64 * 64));
+  const bool p2 = g.Lx == 128 || g.Lx == 256 || g.Lx == 512 || g.Lx == 1024;
+  const int want = p2 && ncol * (g.Lx / 16) <= 512 ? std::max(p.tpc_x, g.Lx / 16) : p.tpc_x;
+  p.nt_x = std::min(512, std::max(64, (ncol * want + 63) / 64 * 64));
+  // epilogue cells per thread (1, 2, 4 or 8 unrolled; 0: a loop), with as many
+  // threads as that takes, up to 512
+  const int ncell = h.tu.ty_x * g.nx;
+  p.cpt_x = 0;
+  for (int c : {1, 2, 4, 8})
+    if (p.cpt_x == 0 && (ncell + c - 1) / c <= 512) p.cpt_x = c;
+  if (p.cpt_x > 0) p.nt_x = std::max(p.nt_x, std::min(512, ((ncell + p.cpt_x - 1) / p.cpt_x + 63) / 64 * 64));
   p.tpc_x = p.nt_x / ncol;
+  // y inverse compiled for Py (2^k from 256 to 2048): SL/16 threads a column
+  p.sl_y = (g.Py == 256 || g.Py == 512 || g.Py == 1024 || g.Py == 2048) ? g.Py : 0;
+  if (p.sl_y) {
+    p.cb_ys = std::max(1, 512 / (p.sl_y / 16));
+    while (p.cb_ys > 1 && (size_t)p.cb_ys * col_stride(p.sl_y) * csz > 80 * 1024) p.cb_ys /= 2;
+  }
   p.lds_x = ((size_t)ncol * col_stride(g.Lx) + 2 * g.Lx + 1) * csz;
   return p;
 }
@@ -371,7 +497,17 @@ hipError_t launch_potential(const GroupSet<T>& gs, const Epi<T>* epis, const Pot
       k_pot_z<T><<<dim3((unsigned)blocks), 3 * p.qz * p.tpc_z, lds, s>>>(h, pt, p.qz, p.tpc_z);
     }
   }
-  if (pass_mask & 8u) {
+  if ((pass_mask & 8u) && p.sl_y) {
+    const long long blocks = (long long)h.batch * (g.nz + 1) * ((g.Xp + p.cb_ys - 1) / p.cb_ys);
+    const size_t lds = (size_t)p.cb_ys * col_stride(p.sl_y) * csz;
+    const dim3 grid((unsigned)blocks), blk((unsigned)(p.cb_ys * (p.sl_y / 16)));
+    switch (p.sl_y) {
+      case 256: k_pot_yinv_s<T, 256, 16><<<grid, blk, lds, s>>>(h, p.cb_ys); break;
+      case 512: k_pot_yinv_s<T, 512, 16><<<grid, blk, lds, s>>>(h, p.cb_ys); break;
+      case 1024: k_pot_yinv_s<T, 1024, 16><<<grid, blk, lds, s>>>(h, p.cb_ys); break;
+      default: k_pot_yinv_s<T, 2048, 16><<<grid, blk, lds, s>>>(h, p.cb_ys); break;
+    }
+  } else if (pass_mask & 8u) {
     bool r16 = false;
     for (int st = 0; st < h.fd[1].nst; ++st) r16 = r16 || radix_of(h.fd[1].code, st) == 16;
     const long long blocks = (long long)h.batch * (g.nz + 1) * ((g.Xp + p.cb_y - 1) / p.cb_y);
@@ -381,17 +517,24 @@ hipError_t launch_potential(const GroupSet<T>& gs, const Epi<T>* epis, const Pot
     else k_pot_yinv<T, false><<<dim3((unsigned)blocks), nt, lds, s>>>(h, p.cb_y, p.tpc_y);
   }
   if (pass_mask & 16u) {
-    const long long blocks = (long long)h.batch * g.nz * ((g.ny + h.tu.ty_x - 1) / h.tu.ty_x);
+    const long long blocks = ((long long)h.batch * g.nz * ((g.ny + h.tu.ty_x - 1) / h.tu.ty_x) + 7) / 8 * 8;
     const T cx = T(pt.gdx), cy = T(pt.gdy), cz = T(pt.gdz);
+    const int cpt = p.cpt_x;
+    const dim3 grid((unsigned)blocks);
+    auto go = [&](auto mode_c) {
+      constexpr int MD = decltype(mode_c)::value;
+      switch (cpt) {
+        case 1: k_pot_x<T, MD, 1><<<grid, p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz); break;
+        case 2: k_pot_x<T, MD, 2><<<grid, p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz); break;
+        case 4: k_pot_x<T, MD, 4><<<grid, p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz); break;
+        case 8: k_pot_x<T, MD, 8><<<grid, p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz); break;
+        default: k_pot_x<T, MD, 0><<<grid, p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz); break;
+      }
+    };
     switch (mode) {
-      case MODE_FIELD:
-        k_pot_x<T, MODE_FIELD><<<dim3((unsigned)blocks), p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz);
-        break;
-      case MODE_ENERGY:
-        k_pot_x<T, MODE_ENERGY><<<dim3((unsigned)blocks), p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz);
-        break;
-      default:
-        k_pot_x<T, MODE_RHS><<<dim3((unsigned)blocks), p.nt_x, p.lds_x, s>>>(h, epis, p.tpc_x, cx, cy, cz);
+      case MODE_FIELD: go(std::integral_constant<int, MODE_FIELD>{}); break;
+      case MODE_ENERGY: go(std::integral_constant<int, MODE_ENERGY>{}); break;
+      default: go(std::integral_constant<int, MODE_RHS>{});
     }
   }
   return hipGetLastError();

@@ -22,7 +22,9 @@ struct PotShape {
   int qz, tpc_z;          // z pass: (kx, ky) points per workgroup, threads per transform
   int cb_y, tpc_y;        // y inverse: kx columns per workgroup, threads per transform
   int nt_x, tpc_x;        // x inverse: threads, threads per transform
+  int cpt_x;              // x inverse: epilogue cells per thread (0: a loop)
   size_t lds_x;           // x inverse LDS bytes
+  int sl_y, cb_ys;        // y inverse compiled for Py = sl_y (0: general): columns per workgroup
 };
 
 template <typename T>
