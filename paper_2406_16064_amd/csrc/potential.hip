@@ -14,7 +14,7 @@
 //                  (scaled by Ms / (Px Py Pz)), inverse z of u^ alone; the
 //                  nz + 1 vertex planes go back to Sy, plane k at k Xp Py
 //   y inverse      columns (k, kx) of u^: inverse y, the ny + 1 vertex rows to
-//                  V = Sx as [nz+1][ny+1][Xp] (rows contiguous along kx)
+//                  V = Sx as [nz+1][XB][ny+1][4] (kx in blocks of 4)
 //   x inverse      2 (TY + 1) vertex rows (planes z, z + 1) of TY cell rows:
 //                  complex-to-real along x (nx + 1 vertices), the edge
 //                  differences, local fields, LL and the epilogue

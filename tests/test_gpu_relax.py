@@ -1,0 +1,132 @@
+"""GPU parity of the relaxations that stop on the largest |dm/dt| (mm_sd_relax,
+mm_rk45_relax) against the oracle's `relax` module, FP64.
+
+The device must stop at the same iteration (steepest descent) or after the
+same accepted step (Dormand-Prince) as the oracle, with m to 1e-9 and the last
+measure to 1e-9 relative.  Each threshold is checked to lie at least 1e-6
+(relative) away from every measure the oracle takes before it stops, so that
+rounding cannot move the stop.
+"""
+import numpy as np
+import pytest
+
+from oracle import dp45, relax, sd
+from oracle import fields as F
+
+from _util import gpu_params, oracle_params, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PAR = dict(Ms=5.8e5, A=1.5e-11, D=3e-3, Ku=8e5, u=(0, 0, 1), H=(1e4, 0.0, 1e5), alpha=0.5)
+MESHES = [(12, 10, 1, 2e-9, 2e-9, 2e-9), (20, 16, 3, 3e-9, 3e-9, 3e-9)]
+MAXSTEPS = -6  # mm_status MM_E_MAXSTEPS
+
+
+@pytest.fixture(scope="module")
+def mm():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_2406_16064_amd import mm as m
+    return m
+
+
+def _start(mesh, seed):
+    rng = np.random.default_rng(seed)
+    m = np.zeros((3,) + tuple(mesh[2::-1][:3]))
+    m[2] = 1.0
+    m += 0.3 * rng.normal(size=m.shape)
+    return m / np.linalg.norm(m, axis=0, keepdims=True)
+
+
+_kern = {}
+
+
+def _oracle(mesh, par):
+    if mesh not in _kern:
+        _kern[mesh] = F.DemagKernel(F.Mesh(*mesh))
+    op = oracle_params(par, F.ALL_TERMS)
+    field = lambda y: F.effective_field(y, F.Mesh(*mesh), op, _kern[mesh])
+    rhs = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kern[mesh])
+    return op, field, rhs
+
+
+def _clear_of(measures, thr):
+    assert min(abs(v / thr - 1.0) for v in measures) > 1e-6, "threshold too close to a measure"
+
+
+@pytest.mark.parametrize("mesh", MESHES)
+@pytest.mark.parametrize("thr", [300.0, 1.0])
+def test_sd_relax_stops_where_the_oracle_stops(mm, mesh, thr):
+    m0 = _start(mesh, 4)
+    op, field, _ = _oracle(mesh, PAR)
+    mo, k, meas, taus = relax.sd_relax(field, m0.copy(), op, thr, 400, 1e-7, 1e-10, 1e-3)
+    assert meas[-1] < thr and k < 400
+    _clear_of(meas, thr)
+    plan = mm.Plan(mesh, "f64", terms=F.ALL_TERMS)
+    md = to_dev(m0, torch.float64)
+    st, it, dm, tau = plan.sd_relax(gpu_params(mm, PAR, F.ALL_TERMS), md, thr, 400, 1e-7, 1e-10, 1e-3)
+    assert st == 0 and it[0] == k, (it, k)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
+    assert abs(dm[0] - meas[-1]) <= 1e-9 * meas[-1]
+    assert abs(tau[0] - taus[-1]) <= 1e-9 * taus[-1]
+
+
+def test_sd_relax_batch_stops_each_instance_on_its_own(mm):
+    """Two instances with different parameters stop at different iterations; the
+    one that stops first keeps its state while the other goes on."""
+    mesh = MESHES[0]
+    ps = [PAR, dict(PAR, Ms=8e5, Ku=2e5, H=(-3e4, 2e4, 5e4))]
+    m0 = np.stack([_start(mesh, 8), _start(mesh, 9)])
+    thr = 20.0
+    ref = []
+    for b, p in enumerate(ps):
+        op, field, _ = _oracle(mesh, p)
+        mo, k, meas, _ = relax.sd_relax(field, m0[b].copy(), op, thr, 400, 1e-7, 1e-10, 1e-3)
+        _clear_of(meas, thr)
+        ref.append((mo, k, meas[-1]))
+    assert ref[0][1] != ref[1][1]
+    plan = mm.Plan(mesh, "f64", terms=F.ALL_TERMS, max_batch=2)
+    md = to_dev(m0, torch.float64)
+    st, it, dm, _ = plan.sd_relax([gpu_params(mm, p, F.ALL_TERMS) for p in ps], md, thr, 400, 1e-7, 1e-10, 1e-3)
+    assert st == 0
+    for b, (mo, k, last) in enumerate(ref):
+        assert it[b] == k
+        assert np.max(np.linalg.norm(md[b].cpu().numpy() - mo, axis=0)) <= 1e-9
+        assert abs(dm[b] - last) <= 1e-9 * last
+
+
+def test_sd_relax_reports_max_iterations(mm):
+    """A threshold no state reaches: MM_E_MAXSTEPS after max_iter updates, m the
+    last iterate (the oracle's plain run of that many iterations)."""
+    mesh = MESHES[0]
+    m0 = _start(mesh, 4)
+    _, field, _ = _oracle(mesh, PAR)
+    mo, _ = sd.run(field, m0.copy(), 7, 1e-7, 1e-10, 1e-3)
+    plan = mm.Plan(mesh, "f64", terms=F.ALL_TERMS)
+    md = to_dev(m0, torch.float64)
+    st, it, dm, _ = plan.sd_relax(gpu_params(mm, PAR, F.ALL_TERMS), md, 1e-30, 7, 1e-7, 1e-10, 1e-3, check=False)
+    assert st == MAXSTEPS and it[0] == 7
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
+    assert dm[0] > 0
+
+
+@pytest.mark.parametrize("mesh", MESHES)
+def test_rk45_relax_stops_after_the_oracles_step(mm, mesh):
+    thr = 200.0
+    m0 = _start(mesh, 4)
+    _, _, rhs = _oracle(mesh, PAR)
+    ost = dp45.State(rtol=1e-6)
+    mo, ok, meas = relax.dp45_relax(rhs, m0.copy(), ost, thr, 3000)
+    assert ok
+    _clear_of(meas, thr)
+    plan = mm.Plan(mesh, "f64", terms=F.ALL_TERMS)
+    md = to_dev(m0, torch.float64)
+    st = mm.new_states(1, rtol=1e-6)
+    status, dm = plan.rk45_relax(gpu_params(mm, PAR, F.ALL_TERMS), md, st, thr, 3000)
+    assert status == 0
+    assert st[0].n_accept == ost.n_accept and st[0].n_reject == ost.n_reject
+    assert abs(st[0].t - ost.t) <= 1e-9 * ost.t
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
+    assert abs(dm[0] - meas[-1]) <= 1e-9 * meas[-1]
