@@ -5,7 +5,10 @@ The device must stop at the same iteration (steepest descent) or after the
 same accepted step (Dormand-Prince) as the oracle, with m to 1e-9 and the last
 measure to 1e-9 relative.  Each threshold is checked to lie at least 1e-6
 (relative) away from every measure the oracle takes before it stops, so that
-rounding cannot move the stop.
+rounding cannot move the stop.  Barzilai-Borwein descent amplifies rounding
+differences (a 1e-13 change of m moves the stop of a 200-iteration run by up to
+ten iterations in the oracle itself), so the cases stop within about 40
+iterations, where the two sides still agree to ~1e-12.
 """
 import numpy as np
 import pytest
@@ -77,7 +80,7 @@ def test_sd_relax_batch_stops_each_instance_on_its_own(mm):
     """Two instances with different parameters stop at different iterations; the
     one that stops first keeps its state while the other goes on."""
     mesh = MESHES[0]
-    ps = [PAR, dict(PAR, Ms=8e5, Ku=2e5, H=(-3e4, 2e4, 5e4))]
+    ps = [PAR, dict(PAR, Ku=1.2e6)]
     m0 = np.stack([_start(mesh, 8), _start(mesh, 9)])
     thr = 20.0
     ref = []
@@ -114,7 +117,10 @@ def test_sd_relax_reports_max_iterations(mm):
 
 @pytest.mark.parametrize("mesh", MESHES)
 def test_rk45_relax_stops_after_the_oracles_step(mm, mesh):
-    thr = 200.0
+    """Stops after 50-60 accepted steps: longer runs reach the stability limit of
+    the explicit step, where rejections make the step sizes sensitive to rounding
+    (a 1e-13 change of m moves t by 5e-7 relative after 130 steps in the oracle)."""
+    thr = 6000.0
     m0 = _start(mesh, 4)
     _, _, rhs = _oracle(mesh, PAR)
     ost = dp45.State(rtol=1e-6)
