@@ -176,9 +176,12 @@ mm_status mm_plan_set_cells(mm_plan* plan, int32_t instance, const double* Ms, c
  * mesh is refined.  A plan takes MM_DEMAG_POTENTIAL in place of MM_DEMAG (not
  * both); it needs nz >= 2 (on one-cell films the two vertex planes would
  * still take two inverse transforms), pads to P >= 2n per axis, and serves
- * mm_effective_field, mm_llg_rhs, mm_energy and mm_profile_passes (the
- * integrators, autotuning and set shapes refuse such plans with MM_E_ARG);
- * uniform material only.  Instances switch the term on with the same bit. */
+ * mm_effective_field, mm_llg_rhs, mm_energy, mm_profile_passes,
+ * mm_plan_set_shapes and the integrators (mm_rk45_*, mm_heun_run, mm_sd_*:
+ * every stage runs the five potential passes, none fused into the previous
+ * one); mm_profile_step, mm_plan_autotune, NEB and batches refuse such plans
+ * with MM_E_ARG.  Uniform material only.  Instances switch the term on with
+ * the same bit. */
 
 /* The cuboid potential S at the vertex - cell displacements
  * ((I - 1/2) dx, (J - 1/2) dy, (K - 1/2) dz), disp[k] = (I, J, K) (device int32

@@ -1079,15 +1079,32 @@ mm_status upload_step_epis(Engine& E, const std::vector<T*>& m, const std::vecto
   return MM_OK;
 }
 
+// One evaluation of epilogue slot `slot` in `mode`, through the plan's demag
+// route: the scalar-potential passes (no fused forward pass), else the Newell
+// passes, which skip the forward x pass (skip_x) when the previous stage's
+// inverse-x pass has done it and fuse it into this one (fuse).
+template <typename T>
+hipError_t eval_slot(Engine& E, const GroupSet<T>& gs, int slot, int mode, hipStream_t s, bool skip_x = false,
+                     bool fuse = false) {
+  if (E.any_pot) return launch_potential<T>(gs, epi_slot<T>(E, slot), pot_tab<T>(E.groups[0]), mode, s);
+  return launch_eval<T>(gs, epi_slot<T>(E, slot), mode, demag_on(E), s, nullptr, skip_x, fuse);
+}
+
+// The inverse-x passes of the Runge-Kutta stages can transform the next stage
+// input forward along x (Newell route, launch shape permitting).
+template <typename T>
+bool stage_fusable(const Engine& E, const GroupSet<T>& gs) {
+  return !E.any_pot && demag_on(E) && eval_fusable<T>(gs);
+}
+
 template <typename T>
 mm_status enqueue_attempt(Engine& E, const GroupSet<T>& gs, int n_total, hipStream_t s) {
   HIPCHK(launch_begin<T>(gs, epi_slot<T>(E, 8), s));
   // stages 2..6 transform the next stage input forward along x in their
   // inverse-x pass when the launch shape allows it; stages 3..7 then skip it
-  const bool fz = demag_on(E) && eval_fusable<T>(gs);
+  const bool fz = stage_fusable<T>(E, gs);
   for (int st = 2; st <= 7; ++st)
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, st), st < 7 ? MODE_STAGE : MODE_ERROR, demag_on(E), s, nullptr,
-                          fz && st > 2, fz && st < 7));
+    HIPCHK(eval_slot<T>(E, gs, st, st < 7 ? MODE_STAGE : MODE_ERROR, s, fz && st > 2, fz && st < 7));
   // the step decision runs in the last workgroup of each instance in the error
   // pass; instances already done keep their pending projection, which the next
   // step-begin repeats idempotently
@@ -1143,10 +1160,10 @@ mm_status heun_impl(mm_plan* p, const mm_params* q, int batch, T* m, double h, l
   e2.coef[1] = 0.5;
   MMCHK(upload_epis<T>(E, 2, std::vector<Epi<T>>{e1}, s));
   MMCHK(upload_epis<T>(E, 3, std::vector<Epi<T>>{e2}, s));
-  const bool fz = demag_on(E) && eval_fusable<T>(gs);
+  const bool fz = stage_fusable<T>(E, gs);
   for (long long i = 0; i < n_steps; ++i) {
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 2), MODE_STAGE, demag_on(E), s, nullptr, fz && i > 0, fz));
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 3), MODE_STAGE, demag_on(E), s, nullptr, fz, fz));
+    HIPCHK(eval_slot<T>(E, gs, 2, MODE_STAGE, s, fz && i > 0, fz));
+    HIPCHK(eval_slot<T>(E, gs, 3, MODE_STAGE, s, fz, fz));
   }
   return MM_OK;
 }
@@ -1224,7 +1241,7 @@ mm_status sd_impl(mm_plan* p, const mm_params* q, int batch, T* m, long long n_i
                               : hipSuccess;
   const long long n_launch = relax ? n_iter + 1 : n_iter;
   for (long long k = 0; st == MM_OK && er == hipSuccess && k < n_launch; ++k) {
-    er = launch_eval<T>(gs, epi_slot<T>(E, 4), MODE_FIELD, demag_on(E), s);
+    er = eval_slot<T>(E, gs, 4, MODE_FIELD, s);
     if (er == hipSuccess)
       er = launch_sd_iteration<T>(m, H, stage_buf<T>(G, 5), stage_buf<T>(G, 6), stage_buf<T>(G, 7), part, tau,
                                   batch, N, k, tau_min, tau_max, E.prm + inst0[0], ctl, relax && k == n_iter, s);
@@ -1435,7 +1452,7 @@ mm_status run_core(Engine& E, const std::vector<T*>& m, const std::vector<int>& 
   long long extra_rhs = 0;
   if (need_k1) {
     E.k1_ok = false;
-    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 1), MODE_RHS, demag_on(E), s));
+    HIPCHK(eval_slot<T>(E, gs, 1, MODE_RHS, s));
     extra_rhs = 1;
   }
   E.k1_ok = true;  // k1 of these arrays from here on (the finishing step keeps it so)
@@ -1837,14 +1854,19 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
 
 // eval: a field, dm/dt, energy or pass-timing call (the only calls a plan of
 // the scalar-potential route serves)
-mm_status plan_checks(mm_plan* p, const mm_params* q, int batch, bool eval = false) {
+// Calls a plan of the scalar-potential route serves: evaluations and the
+// integrators (adaptive, Heun, steepest descent and their relaxations); not
+// the attempt profiler or the autotuner, which time the Newell passes.
+enum CallKind { kCallOther, kCallEval, kCallIntegrator };
+
+mm_status plan_checks(mm_plan* p, const mm_params* q, int batch, CallKind kind = kCallOther) {
   if (!p) return fail(MM_E_ARG, "plan is null");
   if (batch < 1 || batch > p->maxb) return fail(MM_E_ARG, "batch must be in [1, max_batch]");
   MMCHK(check_params(p->e, q, batch));
   if (p->e.terms & MM_DEMAG_POTENTIAL) {
-    if (!eval)
-      return fail(MM_E_ARG, "plans of the scalar-potential demag route serve field, dm/dt, energy and pass-timing "
-                            "calls only");
+    if (kind == kCallOther)
+      return fail(MM_E_ARG, "plans of the scalar-potential demag route serve evaluations and the integrators; "
+                            "the attempt profiler and the autotuner time the Newell passes");
     for (int b = 0; b < batch; ++b)
       if (q[b].terms & kGeneralTerms)
         return fail(MM_E_ARG, "the scalar-potential demag route takes uniform material without interlayer or "
@@ -2028,7 +2050,7 @@ mm_status mm_demag_tensor(const mm_mesh* mesh, const int32_t* disp, int64_t n, d
 
 mm_status mm_effective_field(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* H,
                              void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch, true));
+  MMCHK(plan_checks(p, q, batch, kCallEval));
   if (!m || !H) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? single_eval<float>(p, batch, q, m, H, MODE_FIELD, nullptr, s)
@@ -2036,7 +2058,7 @@ mm_status mm_effective_field(mm_plan* p, const mm_params* q, int32_t batch, cons
 }
 
 mm_status mm_llg_rhs(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* dmdt, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch, true));
+  MMCHK(plan_checks(p, q, batch, kCallEval));
   if (!m || !dmdt) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? single_eval<float>(p, batch, q, m, dmdt, MODE_RHS, nullptr, s)
@@ -2044,7 +2066,7 @@ mm_status mm_llg_rhs(mm_plan* p, const mm_params* q, int32_t batch, const void* 
 }
 
 mm_status mm_energy(mm_plan* p, const mm_params* q, int32_t batch, const void* m, double* E_out, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch, true));
+  MMCHK(plan_checks(p, q, batch, kCallEval));
   if (!m || !E_out) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? energy_impl<float>(p, q, batch, m, E_out, s)
@@ -2053,7 +2075,7 @@ mm_status mm_energy(mm_plan* p, const mm_params* q, int32_t batch, const void* m
 
 mm_status mm_rk45_step(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm_rk45_state* st,
                        void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, kCallIntegrator));
   if (!m || !st) return fail(MM_E_ARG, "null array");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? plan_rk45<float>(p, q, batch, m, st, HUGE_VAL, 2, nullptr, 0, true, s)
@@ -2062,7 +2084,7 @@ mm_status mm_rk45_step(mm_plan* p, const mm_params* q, int32_t batch, void* m, m
 
 mm_status mm_rk45_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm_rk45_state* st, double t_end,
                       int64_t max_steps, const double* replay_h, int64_t n_replay, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, kCallIntegrator));
   if (!m || !st) return fail(MM_E_ARG, "null array");
   if (max_steps < 1) return fail(MM_E_ARG, "max_steps must be >= 1");
   if (!replay_h && !is_fin(t_end)) return fail(MM_E_ARG, "t_end must be finite");
@@ -2074,7 +2096,7 @@ mm_status mm_rk45_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm
 
 mm_status mm_sd_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, int64_t n_iter, double tau0,
                     double tau_min, double tau_max, double* tau_out, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, kCallIntegrator));
   if (!m) return fail(MM_E_ARG, "null array");
   if (n_iter < 0) return fail(MM_E_ARG, "n_iter must be >= 0");
   if (!(tau_min > 0) || !is_fin(tau_max) || !(tau_min <= tau0) || !(tau0 <= tau_max))
@@ -2088,7 +2110,7 @@ mm_status mm_sd_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, int6
 
 mm_status mm_sd_run_noalloc(mm_plan* p, const mm_params* q, int32_t batch, void* m, int64_t n_iter, double tau0,
                             double tau_min, double tau_max, double* tau_out, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, kCallIntegrator));
   if (!m) return fail(MM_E_ARG, "null array");
   if (n_iter < 0) return fail(MM_E_ARG, "n_iter must be >= 0");
   if (!(tau_min > 0) || !is_fin(tau_max) || !(tau_min <= tau0) || !(tau0 <= tau_max))
@@ -2113,7 +2135,7 @@ static double dmdt_rad_s(double deg_ns) { return deg_ns * (M_PI / 180.0) * 1e9; 
 mm_status mm_sd_relax(mm_plan* p, const mm_params* q, int32_t batch, void* m, double stopping_dmdt, int64_t max_iter,
                       double tau0, double tau_min, double tau_max, int64_t* iters_out, double* dmdt_out,
                       double* tau_out, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, kCallIntegrator));
   if (!m) return fail(MM_E_ARG, "null array");
   if (!(stopping_dmdt > 0) || !is_fin(stopping_dmdt)) return fail(MM_E_ARG, "stopping_dmdt must be finite and > 0");
   if (max_iter < 0) return fail(MM_E_ARG, "max_iter must be >= 0");
@@ -2138,7 +2160,7 @@ mm_status mm_sd_relax(mm_plan* p, const mm_params* q, int32_t batch, void* m, do
 
 mm_status mm_rk45_relax(mm_plan* p, const mm_params* q, int32_t batch, void* m, mm_rk45_state* st,
                         double stopping_dmdt, int64_t max_steps, double* dmdt_out, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, kCallIntegrator));
   if (!m || !st) return fail(MM_E_ARG, "null array");
   if (!(stopping_dmdt > 0) || !is_fin(stopping_dmdt)) return fail(MM_E_ARG, "stopping_dmdt must be finite and > 0");
   if (max_steps < 1) return fail(MM_E_ARG, "max_steps must be >= 1");
@@ -2154,7 +2176,7 @@ mm_status mm_rk45_relax(mm_plan* p, const mm_params* q, int32_t batch, void* m, 
 
 mm_status mm_heun_run(mm_plan* p, const mm_params* q, int32_t batch, void* m, double h, int64_t n_steps,
                       void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch));
+  MMCHK(plan_checks(p, q, batch, kCallIntegrator));
   if (!m) return fail(MM_E_ARG, "null array");
   if (!(h > 0) || !is_fin(h)) return fail(MM_E_ARG, "h must be finite and > 0");
   if (n_steps < 0) return fail(MM_E_ARG, "n_steps must be >= 0");
@@ -2202,7 +2224,7 @@ mm_status mm_profile_step(mm_plan* p, const mm_params* q, int32_t batch, void* m
 
 mm_status mm_profile_passes(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work, int32_t reps,
                             double* us_out, int32_t* n_pass, double* seq_out, void* hip_stream) {
-  MMCHK(plan_checks(p, q, batch, true));
+  MMCHK(plan_checks(p, q, batch, kCallEval));
   if (!m || !work || !us_out || !n_pass) return fail(MM_E_ARG, "null argument");
   if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;

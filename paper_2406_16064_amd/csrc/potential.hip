@@ -221,7 +221,8 @@ __global__ void __launch_bounds__(512) k_pot_yinv_s(HotPlan<T> hp, int CB) {
 
 // ---------------------------------------------------------------------------
 // x inverse + edge differences + local fields + epilogue: TY cell rows of
-// plane z of one instance (MODE_FIELD, MODE_RHS or MODE_ENERGY).  The TY + 1
+// plane z of one instance (MODE_FIELD, MODE_RHS, MODE_ENERGY, and the
+// Runge-Kutta MODE_STAGE / MODE_ERROR of the integrators).  The TY + 1
 // vertex rows of vertex planes z and z + 1 are loaded (kSxB (TY + 1)
 // contiguous entries per kx block), transformed together, and each cell reads
 // its eight corners from LDS.
@@ -244,6 +245,11 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
   const int z = (int)(bid % (unsigned)g.nz); bid /= (unsigned)g.nz;
   const int tile = (int)(bid % (unsigned)tiles);
   const int b = (int)(bid / (unsigned)tiles);
+  constexpr bool RK = MODE == MODE_STAGE || MODE == MODE_ERROR;
+  DevCtl* const ctl = ldu(&epis->ctl);
+  if constexpr (RK) {
+    if (ctl && ldu(&ctl[b].done)) return;  // the whole workgroup: b is uniform
+  }
   const int y0 = tile * TY;
   const int nrow = g.ny - y0 < TY ? g.ny - y0 : TY;
   const int cs = col_stride(g.Lx);
@@ -333,16 +339,41 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
   const T* mb = epi.in + ib;
   double esum[5] = {0, 0, 0, 0, 0};
   const int ncell = nrow * g.nx;
+  // Runge-Kutta epilogues: h times the coefficients of the combination (the
+  // last entry multiplies the slope of this stage); the error pass keeps the
+  // largest error norm and |k|^2 of its cells
+  T hcoef[7] = {0, 0, 0, 0, 0, 0, 0};
+  T hlast = T(0);
+  double emax = 0.0, kmax = 0.0;
+  if constexpr (RK) {
+    const double h = ldu(&ctl[b].h_att);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      hcoef[j] = j + 1 < epi.nk ? T(h * epi.coef[j]) : T(0);
+      if (j + 1 == epi.nk) hlast = T(h * epi.coef[j]);
+    }
+  }
   // CPT > 0: at most CPT cells a thread, unrolled, their results stored after
   // the last of them (so the loads of every cell can be in flight together)
   constexpr int NS = CPT > 0 ? CPT : 1;
-  V3<T> res[NS];
+  V3<T> res[NS], res2[NS];
   COff cos[NS];
   auto cell = [&](int e, int slot) {
     const int r = e / g.nx, x = e - r * g.nx;
     const int y = y0 + r;
     const COff co = coff_of<T>(N, (z * g.ny + y) * g.nx + x);
     const Nbr<T> nb = load_nbr<T>(g, P.terms, mb, co, x, y, z);
+    // the step's m and earlier slopes, issued with the neighbours
+    V3<T> kb[6];
+    V3<T> mbv = {T(0), T(0), T(0)};
+    if constexpr (RK) {
+      if constexpr (MODE == MODE_STAGE) mbv = ld3o(epi.mbase + ib, co);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        if (hcoef[j] != T(0)) kb[j] = ld3o(epi.kprev[j] + ib, co);
+        else kb[j] = {T(0), T(0), T(0)};
+      }
+    }
     LocalTerms lt = {0, 0, 0, 0};
     V3<T> H;
     if constexpr (MODE == MODE_ENERGY) H = local_field<T, true>(g, P, nb, x, y, z, &lt);
@@ -358,7 +389,36 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
     }
     const V3<T> mi = nb.mi;
     V3<T> o = H;
-    if constexpr (MODE == MODE_RHS) o = ll_rhs(mi, H, g1, g2);
+    if constexpr (MODE == MODE_RHS || RK) o = ll_rhs(mi, H, g1, g2);
+    if constexpr (MODE == MODE_STAGE) {
+      // next stage input m + h sum_j a_j k_j (this stage's slope last)
+      V3<T> acc = mbv;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        acc.x += hcoef[j] * kb[j].x; acc.y += hcoef[j] * kb[j].y; acc.z += hcoef[j] * kb[j].z;
+      }
+      acc.x += hlast * o.x; acc.y += hlast * o.y; acc.z += hlast * o.z;
+      if (epi.project) {  // the end of a fixed step: back onto the unit sphere
+        const T sc = rsqrt_t<T>(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
+        acc.x *= sc; acc.y *= sc; acc.z *= sc;
+      }
+      if constexpr (CPT > 0) res2[slot] = acc;
+      else st3o(epi.msn + ib, co, acc);
+    }
+    if constexpr (MODE == MODE_ERROR) {
+      double ex = 0, ey = 0, ez = 0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        ex += (double)(hcoef[j] * kb[j].x); ey += (double)(hcoef[j] * kb[j].y); ez += (double)(hcoef[j] * kb[j].z);
+      }
+      ex += (double)(hlast * o.x); ey += (double)(hlast * o.y); ez += (double)(hlast * o.z);
+      double en = sqrt(ex * ex + ey * ey + ez * ez);
+      if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
+      emax = fmax(emax, en);
+      double kn = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
+      if (!(kn <= DBL_MAX)) kn = HUGE_VAL;
+      kmax = fmax(kmax, kn);
+    }
     if constexpr (MODE == MODE_ENERGY) {
       esum[0] += lt.ex;
       if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
@@ -383,7 +443,43 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
     if constexpr (MODE != MODE_ENERGY) {
 #pragma unroll
       for (int k = 0; k < CPT; ++k)
-        if ((int)threadIdx.x + k * (int)blockDim.x < ncell) st3o(epi.out + ib, cos[k], res[k]);
+        if ((int)threadIdx.x + k * (int)blockDim.x < ncell) {
+          st3o(epi.out + ib, cos[k], res[k]);
+          if constexpr (MODE == MODE_STAGE) st3o(epi.msn + ib, cos[k], res2[k]);
+        }
+    }
+  }
+  if constexpr (MODE == MODE_ERROR) {
+    // the largest error norm (and |k_7|, for relaxations) of the instance; the
+    // last of its workgroups to arrive takes the step decision (the arrival
+    // counts the maxima's returned top bits, so it follows them)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool relax = ldu(&ctl[b].stop_dmdt) > 0.0;
+    const double w = wave_max(emax);
+    if (lane == 0) red[0][wave] = w;
+    if (relax) {
+      const double wk = wave_max(kmax);
+      if (lane == 0) red[1][wave] = wk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = red[0][0];
+      for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
+      const unsigned long long prev = atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
+      unsigned long long prevk = 0ull;
+      if (relax) {
+        double vk = red[1][0];
+        for (int j = 1; j < (int)(blockDim.x >> 6); ++j) vk = fmax(vk, red[1][j]);
+        prevk = atomicMax(&ctl[b].dmdt_bits, (unsigned long long)__double_as_longlong(sqrt(vk)));
+      }
+      const int inc = 1 + (int)(prev >> 63) + (int)(prevk >> 63);
+      const int bpi = tiles * g.nz;
+      if (atomicAdd(&ctl[b].arrive, inc) == bpi - 1) {
+        ctl[b].arrive = 0;
+        ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);
+        if (relax) ctl[b].dmdt_bits = atomicOr(&ctl[b].dmdt_bits, 0ull);
+        control_step(ctl[b], epi.replay);
+      }
     }
   }
   if constexpr (MODE == MODE_ENERGY) {
@@ -534,6 +630,8 @@ hipError_t launch_potential(const GroupSet<T>& gs, const Epi<T>* epis, const Pot
     switch (mode) {
       case MODE_FIELD: go(std::integral_constant<int, MODE_FIELD>{}); break;
       case MODE_ENERGY: go(std::integral_constant<int, MODE_ENERGY>{}); break;
+      case MODE_STAGE: go(std::integral_constant<int, MODE_STAGE>{}); break;
+      case MODE_ERROR: go(std::integral_constant<int, MODE_ERROR>{}); break;
       default: go(std::integral_constant<int, MODE_RHS>{});
     }
   }

@@ -37,7 +37,9 @@ bool pot_supported(const HotPlan<T>& h, int tpc_x_min);
 
 // One evaluation (single group): x and y forward (the Newell route's passes),
 // z with the potential product, y inverse, x inverse with the edge
-// differences and the epilogue `mode` (MODE_FIELD, MODE_RHS or MODE_ENERGY).
+// differences and the epilogue `mode` (MODE_FIELD, MODE_RHS, MODE_ENERGY, or
+// the Runge-Kutta MODE_STAGE / MODE_ERROR: no fused forward pass, the error
+// pass's last workgroup of an instance takes the step decision).
 // pass_mask bit p launches pass p (0 x, 1 y, 2 z, 3 y inverse, 4 x inverse).
 template <typename T>
 hipError_t launch_potential(const GroupSet<T>& gs, const Epi<T>* epis, const PotTab<T>& pt, int mode,

@@ -8,11 +8,18 @@
   1024, Pz = 32): FP64 to 1e-11 and FP32 to 1e-5 of max |H| (on FP32-exact m).
 * The slab at full size (512 x 512 x 16, FP32) on a sparse state: the fields
   of sampled cells against the oracle's plain sums over the sources.
-* Refusals: MM_DEMAG with MM_DEMAG_POTENTIAL, one-cell films, integrators.
+* The integrators on the route: adaptive Dormand-Prince in FP64 (same
+  accepted and rejected steps, m to 1e-9) and replayed in FP32 (1e-4), Heun
+  (FP64 1e-10), steepest descent (FP64 1e-9) and the relaxation that stops on
+  the largest |dm/dt| (same stopping step), each against the oracle's
+  integrator driven by the oracle's potential-route field.
+* Refusals: MM_DEMAG with MM_DEMAG_POTENTIAL, one-cell films, the attempt
+  profiler and the autotuner.
 """
 import numpy as np
 import pytest
 
+from oracle import dp45, heun, relax, sd
 from oracle import fields as F
 from oracle import potential as P
 
@@ -131,6 +138,85 @@ def test_refusals(mm):
     md = to_dev(_state(mesh, 1), torch.float32)
     gp = mm.make_params(terms=POT | LOCAL, **PAR)
     with pytest.raises(mm.MMError):
-        plan.rk45_run(gp, md, mm.new_states(1), t_end=1e-12)
+        plan.profile_step(gp, md, mm.new_states(1))
     with pytest.raises(mm.MMError):
-        plan.heun_run(gp, md, 1e-14, 2)
+        plan.autotune(gp, md)
+
+
+# integrators on the potential route: a 3-D mesh with ragged tiles and a
+# radix-3 padded length, every local term
+INT_MESH = (13, 10, 3, 2e-9, 2.5e-9, 1.5e-9)
+
+
+def _rhs(mesh, op, kern):
+    return lambda y: F.llg_rhs_from_field(y, P.effective_field(y, F.Mesh(*mesh), op, kern), op)
+
+
+def _setup(mm, mesh, prec):
+    plan, gp, op = _plan_and_params(mm, mesh, prec, LOCAL)
+    kern = P.PotentialKernel(F.Mesh(*mesh), P=tuple(plan.padded()[::-1]))
+    return plan, gp, op, kern
+
+
+def test_rk45_trajectory_fp64(mm):
+    """30 accepted adaptive steps: the same accepted and rejected steps as the
+    oracle, the same end time, m to 1e-9."""
+    mesh = INT_MESH
+    plan, gp, op, kern = _setup(mm, mesh, "f64")
+    m0 = _state(mesh, 21)
+    ost = dp45.State(rtol=1e-6)
+    mo = dp45.run(_rhs(mesh, op, kern), m0.copy(), ost, max_accept=30)
+    md = to_dev(m0, torch.float64)
+    st = mm.new_states(1, rtol=1e-6)
+    plan.rk45_run(gp, md, st, t_end=ost.t)
+    assert abs(st[0].n_accept - ost.n_accept) <= 1 and st[0].n_reject == ost.n_reject
+    assert st[0].t == ost.t
+    assert np.max(np.abs(md.cpu().numpy() - mo)) <= 1e-9
+
+
+def test_rk45_replay_fp32(mm):
+    """The oracle's accepted step sizes replayed in FP32: m within 1e-4."""
+    mesh = INT_MESH
+    plan, gp, op, kern = _setup(mm, mesh, "f32")
+    m0 = representable(_state(mesh, 22), torch.float32)
+    ost = dp45.State(rtol=1e-6)
+    mo = dp45.run(_rhs(mesh, op, kern), m0.copy(), ost, max_accept=20)
+    md = to_dev(m0, torch.float32)
+    st = mm.new_states(1, rtol=1e-6)
+    plan.rk45_run(gp, md, st, replay_h=ost.accepted_h)
+    assert st[0].n_accept == len(ost.accepted_h)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-4
+
+
+def test_heun_fp64(mm):
+    mesh = INT_MESH
+    plan, gp, op, kern = _setup(mm, mesh, "f64")
+    m0 = _state(mesh, 23)
+    mo = heun.run(_rhs(mesh, op, kern), m0.copy(), 4e-14, 10)
+    md = to_dev(m0, torch.float64)
+    plan.heun_run(gp, md, 4e-14, 10)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-10
+
+
+def test_sd_and_relax_fp64(mm):
+    """20 steepest-descent iterations (m to 1e-9, the last step size to 1e-9),
+    then adaptive relaxation to 20000 deg/ns: the same stopping step."""
+    mesh = INT_MESH
+    plan, gp, op, kern = _setup(mm, mesh, "f64")
+    field = lambda y: P.effective_field(y, F.Mesh(*mesh), op, kern)
+    m0 = _state(mesh, 24)
+    mo, taus = sd.run(field, m0.copy(), 20, 1e-7, 1e-10, 1e-3)
+    md = to_dev(m0, torch.float64)
+    tau = plan.sd_run(gp, md, 20, 1e-7, 1e-10, 1e-3)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
+    assert abs(tau[0] - taus[-1]) <= 1e-9 * taus[-1]
+    thr = 20000.0
+    ost = dp45.State(rtol=1e-6)
+    mo, ok, meas = relax.dp45_relax(_rhs(mesh, op, kern), m0.copy(), ost, thr, 2000)
+    assert ok and min(abs(v / thr - 1.0) for v in meas) > 1e-6
+    md = to_dev(m0, torch.float64)
+    st = mm.new_states(1, rtol=1e-6)
+    status, dm = plan.rk45_relax(gp, md, st, thr, 2000)
+    assert status == 0 and st[0].n_accept == ost.n_accept and st[0].n_reject == ost.n_reject
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
+    assert abs(dm[0] - meas[-1]) <= 1e-9 * meas[-1]
