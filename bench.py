@@ -389,6 +389,28 @@ def potential_bench(mm, inputs, torch, newell=None, reps=30):
            "eval_us": round(t, 3), "alg_bytes": b, "achieved_gbs": round(b / (t * 1e-6) / 1e9, 1),
            "frac": round(b / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
            "cell_evals_per_s": mesh[0] * mesh[1] * mesh[2] / (t * 1e-6)}
+    # adaptive Dormand-Prince attempts on the route (the headline's step, with
+    # the potential passes in every stage), timed as the headline is
+    st = mm.new_states(1, rtol=w["rtol"])
+    mr = m.clone()  # the field comparison below uses the initial state
+    s = plan.rk45_run(params, mr, st, t_end=w["t_end"], max_steps=8, check=False)
+    if s not in (mm.MM_OK, mm.MM_E_MAXSTEPS):
+        raise RuntimeError("potential-route warmup failed: %s" % mm.status_string(s))
+    n0, a0 = st[0].n_rhs, st[0].n_accept + st[0].n_reject
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    s = plan.rk45_run(params, mr, st, t_end=w["t_end"], max_steps=16, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    if s not in (mm.MM_OK, mm.MM_E_MAXSTEPS):
+        raise RuntimeError("potential-route run failed: %s" % mm.status_string(s))
+    ms = e0.elapsed_time(e1)
+    att = st[0].n_accept + st[0].n_reject - a0
+    out["rk45"] = {"attempts": att, "ms_per_step": ms / max(att, 1),
+                   "cell_evals_per_s": mesh[0] * mesh[1] * mesh[2] * (st[0].n_rhs - n0) / (ms * 1e-3)}
+    if newell is not None:
+        out["rk45"]["speedup_over_newell"] = round(newell["ms_per_step"] / out["rk45"]["ms_per_step"], 3)
     # the demag fields of the two routes on this state
     pd = mm.Plan(mesh, "f32", terms=mm.DEMAG_POTENTIAL)
     Hp = pd.effective_field(mm.make_params(terms=mm.DEMAG_POTENTIAL, **w["params"]), m)
