@@ -345,6 +345,31 @@ def heun_bench(mm, inputs, torch, steps=100):
     return out
 
 
+def padding_bench(mm, inputs, torch, sizes=(96, 192), reps=20):
+    """Padded-grid choice by measurement (mm_plan_tune_padding) on sweep meshes
+    n x n x 2 (2 nm cells, the sweep's terms) whose default 3-smooth grid has a
+    power-of-two alternative (n = 96: 192 or 256 along x and y): dm/dt evaluation
+    time (sum of the passes in evaluation order) at the default grid and at the
+    grid kept."""
+    import numpy as np
+    w = inputs.workload(4)
+    terms = w["terms"]
+    p = mm.make_params(terms=terms, Ms=8e5, A=1.3e-11, D=1e-3, Ku=2e5, u=(0, 0, 1), H=(1e4, 0, 5e4), alpha=0.1)
+    out = []
+    for n in sizes:
+        mesh = (n, n, 2, 2e-9, 2e-9, 2e-9)
+        plan = mm.Plan(mesh, "f32", terms=terms)
+        m = torch.tensor(inputs.random_unit(n, n, 2, np.random.default_rng(n)), dtype=torch.float32, device="cuda")
+        P0 = plan.padded()
+        t0 = sum(plan.profile_passes(p, m, reps=reps, in_order=True)[1])
+        P1 = plan.tune_padding(p, m, reps=reps)
+        t1 = sum(plan.profile_passes(p, m, reps=reps, in_order=True)[1])
+        out.append({"mesh": [n, n, 2], "default_padded": list(P0), "eval_us_default": round(t0, 2),
+                    "kept_padded": list(P1), "eval_us_kept": round(t1, 2)})
+        del plan
+    return out
+
+
 def sd_bench(mm, inputs, torch, iters=200):
     """Steepest-descent (Barzilai-Borwein) relaxation of the 256x256x1 thin film
     (all five terms, FP32): iterations per second and cells x iterations / s
@@ -689,11 +714,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "thinfilm", "copy", "heun", "sd", "sweep", "neb",
-                                       "potential"],
+                                       "potential", "padding"],
                     default=None,
                     help="profiling aids: slab3d (slab3d_f64) runs only the 512x512x16 slab in FP32 (FP64), "
                          "thinfilm only the 256x256x1 film in FP32, and prints its record; copy runs only the "
-                         "plain 1 GiB copies the HBM counters are scaled by; heun, sd, sweep, neb, potential run "
+                         "plain 1 GiB copies the HBM counters are scaled by; heun, sd, sweep, neb, potential, "
+                         "padding run "
                          "only that record")
     ap.add_argument("--retune", default=None, metavar="TABLE",
                     help="autotune the launch shapes of the workloads run and store them in the table file TABLE")
@@ -735,6 +761,9 @@ def main():
     if args.only == "potential":
         print(json.dumps(potential_bench(mm, inputs, torch)))
         return
+    if args.only == "padding":
+        print(json.dumps(padding_bench(mm, inputs, torch)))
+        return
     if args.only in ("slab3d", "slab3d_f64", "thinfilm"):
         idx = 1 if args.only == "thinfilm" else 2
         r, *_ = run_workload(mm, inputs, torch, idx, "f64" if args.only == "slab3d_f64" else "f32", args.steps,
@@ -768,6 +797,8 @@ def main():
         extra["heun"] = heun_bench(mm, inputs, torch)
         print("bench: steepest descent", file=sys.stderr, flush=True)
         extra["sd"] = sd_bench(mm, inputs, torch)
+        print("bench: padded-grid choice", file=sys.stderr, flush=True)
+        extra["padding"] = padding_bench(mm, inputs, torch)
         print("bench: scalar-potential demag", file=sys.stderr, flush=True)
         extra["potential_f32"] = potential_bench(mm, inputs, torch, newell=res)
     cpu = None

@@ -353,6 +353,23 @@ mm_status mm_batch_destroy(mm_batch* batch);
 mm_status mm_plan_autotune(mm_plan* plan, const mm_params* params, int32_t batch, const void* m,
                            void* work, int32_t reps, int32_t* shape_out, void* hip_stream);
 
+/* Choice of the padded FFT grid by measurement.  Per axis the candidates are
+ * the plan's default (2n when 3-smooth, else the smallest 3-smooth length
+ * >= 2n - 1), the smallest 3-smooth length >= 2n - 1 and the smallest power of
+ * two >= 2n - 1 (x even; 2n in place of 2n - 1 for the scalar-potential
+ * route); every combination whose spectrum per instance stays below 4 GiB is
+ * built (its demag spectrum included) and `reps` dm/dt evaluations of the
+ * `batch` instances m (device, as mm_llg_rhs; work: device output buffer of
+ * the same size) are timed back to back.  The plan keeps the first grid, in
+ * the order above, within 3% of the fastest, with default launch shapes (run
+ * mm_plan_autotune after).  Any padded length >= 2n - 1 gives the same fields
+ * up to rounding (section "Magnetostatic energy": the zero-padded FFT
+ * convolution).  padded_out (host int32[3], nullable): Px, Py, Pz kept.
+ * Drops the plan's first slopes (the next adaptive call recomputes them) and
+ * its captured graph.  Allocates; synchronises. */
+mm_status mm_plan_tune_padding(mm_plan* plan, const mm_params* params, int32_t batch, const void* m, void* work,
+                               int32_t reps, int32_t* padded_out, void* hip_stream);
+
 /* The plan's current launch shapes (8 ints, the layout above).  Host only. */
 mm_status mm_plan_shapes(const mm_plan* plan, int32_t* shape_out);
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -662,16 +663,15 @@ void free_engine(Engine& E) {
   if (E.cap) (void)hipStreamDestroy(E.cap);
 }
 
-// Geometry, tuning, tables and (with demag) the tensor spectrum of one mesh.
-mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
-  G.mesh = mesh;
-  G.ncomp = mesh.nz == 1 ? 4 : 6;
+// Geometry of the padded grid (Px, Py, Pz), default launch shapes, the
+// transform tables and the demag spectrum (Newell tensor or scalar-potential
+// kernel) of G's mesh.  The grid's buffers (G.Sx, G.Sy) follow in engine_reserve.
+mm_status build_padded(Engine& E, Group& G, int Px, int Py, int Pz, hipStream_t s) {
   Geo& g = G.g;
-  g.nx = mesh.nx; g.ny = mesh.ny; g.nz = mesh.nz;
   const bool pot = (E.terms & MM_DEMAG_POTENTIAL) != 0;
-  g.Px = pot ? pick_padded_pot(g.nx, true) : pick_padded(g.nx, true);
-  g.Py = pot ? pick_padded_pot(g.ny, false) : pick_padded(g.ny, false);
-  g.Pz = pot ? pick_padded_pot(g.nz, false) : pick_padded(g.nz, false);
+  g.Px = Px;
+  g.Py = Py;
+  g.Pz = Pz;
   g.Lx = g.Px / 2;
   g.Xp = g.Lx + 1;
   g.Ky = g.Py / 2 + 1;
@@ -680,7 +680,7 @@ mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
   g.XB = (g.Xp + kSxB - 1) / kSxB;
   g.sx = g.nz == 1 ? 3LL * g.Xp * g.ny : 3LL * g.nz * g.XB * kSxB * g.ny;
   g.sy = 3LL * g.nz * g.Xp * g.Py;
-  g.dV = mesh.dx * mesh.dy * mesh.dz;
+  g.dV = G.mesh.dx * G.mesh.dy * G.mesh.dz;
   MMCHK(choose_tuning(G, E.prec, E.csz));
   if (E.terms & MM_DEMAG) {
     MMCHK(dev_alloc(&G.kt, E.rsz * G.ncomp * (size_t)g.Kz * g.Xp * g.Ky));
@@ -695,6 +695,35 @@ mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
     MMCHK(E.prec == MM_F32 ? build_potential<float>(G, s) : build_potential<double>(G, s));
   }
   return MM_OK;
+}
+
+// Shortest padded lengths per axis: 2n - 1 (every displacement of the
+// cell-averaged tensor fits), 2n for the scalar-potential route.
+int min_padded(int n, bool pot) { return pot ? 2 * n : 2 * n - 1; }
+
+// Geometry, tuning, tables and (with demag) the tensor spectrum of one mesh.
+mm_status make_group(Engine& E, const mm_mesh& mesh, hipStream_t s, Group& G) {
+  G.mesh = mesh;
+  G.ncomp = mesh.nz == 1 ? 4 : 6;
+  Geo& g = G.g;
+  g.nx = mesh.nx; g.ny = mesh.ny; g.nz = mesh.nz;
+  const bool pot = (E.terms & MM_DEMAG_POTENTIAL) != 0;
+  const int Px = pot ? pick_padded_pot(g.nx, true) : pick_padded(g.nx, true);
+  const int Py = pot ? pick_padded_pot(g.ny, false) : pick_padded(g.ny, false);
+  const int Pz = pot ? pick_padded_pot(g.nz, false) : pick_padded(g.nz, false);
+  return build_padded(E, G, Px, Py, Pz, s);
+}
+
+// Drop the buffers and tables that depend on the padded grid (the stage,
+// batch and cell arrays stay).
+void free_padded(Engine& E, Group& G) {
+  void* bufs[] = {G.Sx, G.Sy, G.kt, G.post, G.twx, G.twy, G.twz, G.kpot, G.phx, G.phy, G.phz};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  G.Sx = G.Sy = G.kt = G.post = G.twx = G.twy = G.twz = G.kpot = G.phx = G.phy = G.phz = nullptr;
+  G.cap = 0;
+  E.k1_ok = false;
+  if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
 }
 
 mm_status engine_init(Engine& E, mm_precision prec, uint32_t terms) {
@@ -1852,6 +1881,95 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
   return MM_OK;
 }
 
+// Candidate padded lengths of one axis, the plan's default first: the default
+// rule, the smallest 3-smooth length >= the minimum and the smallest power of
+// two >= the minimum (x even; an axis of one cell off x keeps 1).
+std::vector<int> padded_candidates(int n, bool even, bool pot) {
+  std::vector<int> c{pot ? pick_padded_pot(n, even) : pick_padded(n, even)};
+  if (n == 1 && !even) return c;
+  const int lo = min_padded(n, pot);
+  int s3 = lo;
+  while (!(smooth3(s3) && (!even || s3 % 2 == 0))) ++s3;
+  int p2 = 2;
+  while (p2 < lo) p2 *= 2;
+  for (int v : {s3, p2})
+    if (std::find(c.begin(), c.end(), v) == c.end()) c.push_back(v);
+  return c;
+}
+
+// Measure one dm/dt evaluation on every combination of the axes' candidate
+// padded lengths (each built with its spectrum and default launch shapes) and
+// keep the first within 3% of the fastest, in candidate order.
+template <typename T>
+mm_status tune_padding_impl(mm_plan* p, const mm_params* q, int batch, const void* m, void* work, int reps,
+                            hipStream_t s) {
+  Engine& E = p->e;
+  Group& G = E.groups[0];
+  const bool pot = (E.terms & MM_DEMAG_POTENTIAL) != 0;
+  if (!(E.terms & (MM_DEMAG | MM_DEMAG_POTENTIAL))) return MM_OK;  // no transforms to size
+  const std::vector<int> cx = padded_candidates(G.g.nx, true, pot);
+  const std::vector<int> cy = padded_candidates(G.g.ny, false, pot);
+  const std::vector<int> cz = padded_candidates(G.g.nz, false, pot);
+  const int P0[3] = {G.g.Px, G.g.Py, G.g.Pz};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(MM_E_HIP, "hipEventCreate failed");
+  }
+  auto rebuild = [&](int Px, int Py, int Pz) -> mm_status {
+    free_padded(E, G);
+    MMCHK(build_padded(E, G, Px, Py, Pz, s));
+    return engine_reserve(E, std::vector<int>{p->maxb});
+  };
+  std::vector<std::pair<double, std::array<int, 3>>> timed;
+  mm_status st = MM_OK;
+  for (int Px : cx)
+    for (int Py : cy)
+      for (int Pz : cz) {
+        if (st != MM_OK) break;
+        const double sy = (double)E.csz * 3.0 * G.g.nz * (Px / 2 + 1) * (double)Py;
+        if (sy >= 4294967296.0) continue;  // one instance's spectrum must stay below 4 GiB
+        st = rebuild(Px, Py, Pz);
+        if (st == MM_E_ARG) {  // the grid does not fit the kernels' limits: not a candidate
+          st = MM_OK;
+          continue;
+        }
+        if (st == MM_OK) st = single_eval<T>(p, batch, q, m, work, MODE_RHS, nullptr, s);
+        if (st != MM_OK) break;
+        GroupSet<T> gs;
+        std::vector<int> inst0;
+        st = make_set<T>(E, std::vector<int>{batch}, gs, inst0, s);
+        if (st != MM_OK) break;
+        const Epi<T>* ep = epi_slot<T>(E, 0);
+        hipError_t er = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && er == hipSuccess; ++r)
+          er = E.any_pot ? launch_potential<T>(gs, ep, pot_tab<T>(G), MODE_RHS, s)
+                         : launch_eval<T>(gs, ep, MODE_RHS, demag_on(E), s);
+        if (er == hipSuccess) er = hipEventRecord(e1, s);
+        if (er == hipSuccess) er = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+        if (er != hipSuccess) st = fail(MM_E_HIP, hipGetErrorString(er));
+        timed.push_back({(double)ms / reps, {Px, Py, Pz}});
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::array<int, 3> best = {P0[0], P0[1], P0[2]};
+  if (st == MM_OK && !timed.empty()) {
+    double tmin = 1e300;
+    for (const auto& c : timed) tmin = std::min(tmin, c.first);
+    for (const auto& c : timed)
+      if (c.first <= tmin * 1.03) {
+        best = c.second;
+        break;
+      }
+  }
+  // keep the choice (or, after a failure, go back to the default grid)
+  const mm_status rs = rebuild(best[0], best[1], best[2]);
+  return st != MM_OK ? st : rs;
+}
+
 // eval: a field, dm/dt, energy or pass-timing call (the only calls a plan of
 // the scalar-potential route serves)
 // Calls a plan of the scalar-potential route serves: evaluations and the
@@ -2251,6 +2369,22 @@ mm_status mm_plan_autotune(mm_plan* p, const mm_params* q, int32_t batch, const 
   MMCHK(p->e.prec == MM_F32 ? autotune_impl<float>(p, q, batch, m, work, reps, s)
                             : autotune_impl<double>(p, q, batch, m, work, reps, s));
   if (shape_out) shapes_of(p, shape_out);
+  return MM_OK;
+}
+
+mm_status mm_plan_tune_padding(mm_plan* p, const mm_params* q, int32_t batch, const void* m, void* work,
+                               int32_t reps, int32_t* padded_out, void* hip_stream) {
+  MMCHK(plan_checks(p, q, batch, kCallEval));
+  if (!m || !work) return fail(MM_E_ARG, "null pointer");
+  if (reps < 1) return fail(MM_E_ARG, "reps must be >= 1");
+  hipStream_t s = (hipStream_t)hip_stream;
+  MMCHK(p->e.prec == MM_F32 ? tune_padding_impl<float>(p, q, batch, m, work, reps, s)
+                            : tune_padding_impl<double>(p, q, batch, m, work, reps, s));
+  if (padded_out) {
+    padded_out[0] = p->e.groups[0].g.Px;
+    padded_out[1] = p->e.groups[0].g.Py;
+    padded_out[2] = p->e.groups[0].g.Pz;
+  }
   return MM_OK;
 }
 

@@ -82,6 +82,7 @@ _sigs = {
     "mm_profile_step": [_vp, _P(Params), _i32, _vp, _P(RK45State), _i32, _P(_dbl), _P(_i32), _P(_i32), _P(_dbl),
                         _vp],
     "mm_plan_autotune": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
+    "mm_plan_tune_padding": [_vp, _P(Params), _i32, _vp, _vp, _i32, _P(_i32), _vp],
     "mm_plan_shapes": [_vp, _P(_i32)],
     "mm_plan_set_shapes": [_vp, _P(_i32)],
     "mm_batch_create": [_P(_vp), _P(Mesh), _i32, ctypes.c_int, ctypes.c_uint32, _vp],
@@ -306,6 +307,16 @@ class Plan:
         _check(_lib.mm_plan_autotune(self._h, _params_array(params), self._batch(m), _ptr(m), _ptr(work), reps,
                                      shape, _stream(stream)), "mm_plan_autotune")
         return dict(zip(SHAPE_KEYS, shape[:7]))
+
+    def tune_padding(self, params, m, reps=5, stream=None):
+        """Pick the padded FFT grid by timing dm/dt on the candidates (mm_plan_tune_padding);
+        returns (Px, Py, Pz).  Launch shapes go back to their defaults."""
+        import torch
+        work = torch.empty_like(m)
+        out = (ctypes.c_int32 * 3)()
+        _check(_lib.mm_plan_tune_padding(self._h, _params_array(params), self._batch(m), _ptr(m), _ptr(work), reps,
+                                         out, _stream(stream)), "mm_plan_tune_padding")
+        return tuple(out[:])
 
     def shapes(self):
         """The plan's current launch shapes (as autotune reports them)."""

@@ -66,6 +66,7 @@ def test_invalid_arguments_rejected_before_hip(mm):
     assert lib.mm_plan_set_cells(None, 0, None, None, None, None) == mm.MM_E_ARG
     assert lib.mm_plan_set_shapes(None, None) == mm.MM_E_ARG
     assert lib.mm_plan_shapes(None, None) == mm.MM_E_ARG
+    assert lib.mm_plan_tune_padding(None, None, 1, None, None, 3, None, None) == mm.MM_E_ARG
     assert lib.mm_neb_run(None, None, None, 3, 1e5, 1e-14, 1, None, None) == mm.MM_E_ARG
     assert lib.mm_heun_run(None, None, 1, None, 1e-13, 1, None) == mm.MM_E_ARG
     assert lib.mm_sd_run(None, None, 1, None, 1, 1e-7, 1e-9, 1e-3, None, None) == mm.MM_E_ARG

@@ -557,3 +557,30 @@ def test_profile_step_leaves_state(mm):
         plan.rk45_run(gp, md, st, t_end=1e-12, max_steps=20, check=False)
         outs.append((md.cpu().numpy(), st[0].t, st[0].n_accept))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
+def test_tuned_padding_keeps_fields(mm):
+    """mm_plan_tune_padding on a mesh whose axes have several candidate lengths
+    (x: 216 or 256, y: 144 or 256, z: 6 or 8): the grid kept is one of them,
+    H_eff matches the oracle to the FP64 tolerance on it (any P >= 2n - 1 gives
+    the same field up to rounding), and adaptive steps run on it with fresh
+    first slopes (FP64 trajectory against the oracle)."""
+    mesh = (100, 70, 3, 2e-9, 2e-9, 2e-9)
+    m0 = _rand_m(mesh, 31)
+    op = oracle_params(PAR, F.ALL_TERMS)
+    plan = mm.Plan(mesh, "f64", terms=F.ALL_TERMS)
+    gp = gpu_params(mm, PAR, F.ALL_TERMS)
+    md = to_dev(m0, torch.float64)
+    st = mm.new_states(1, rtol=1e-6)
+    assert plan.rk45_run(gp, md, st, t_end=1e-9, max_steps=3, check=False) == mm.MM_E_MAXSTEPS  # default grid
+    m1 = md.cpu().numpy()
+    P = plan.tune_padding(gp, md, reps=3)
+    assert P[0] in (216, 256) and P[1] in (144, 256) and P[2] in (6, 8)
+    assert tuple(plan.padded()) == P
+    H = plan.effective_field(gp, md).cpu().numpy()
+    assert field_err(H, F.effective_field(m1, F.Mesh(*mesh), op, _kernel(mesh))) <= 1e-11
+    ost = dp45.State(t=st[0].t, h=st[0].h, rtol=1e-6)
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+    mo = dp45.run(f, m1.copy(), ost, max_accept=4)
+    plan.rk45_run(gp, md, st, t_end=ost.t)
+    assert np.max(np.abs(md.cpu().numpy() - mo)) <= 1e-9
