@@ -585,7 +585,11 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
           const long long nb = kind == 0 ? zpair_blocks(h.g, h.batch)
                                : kind == 3 ? zs_blocks(h.g, h.batch, zs_q<T>(h.g.Pz))
                                            : zreg_blocks(h.g, h.batch);
-          lb.set(j, use ? nb : 0);
+          // a multiple of 8 (the kernels end the extra workgroups at once), so
+          // that the XCD remap keeps the workgroups of one kx row -- whose
+          // columns ky and Py - ky read the same folded tensor entries -- on
+          // one XCD and its L2
+          lb.set(j, use ? (nb + 7) / 8 * 8 : 0);
         }
         if (kind == 0) z_pair_dispatch<T>(hi.g.Pz, lb.L, lb.total, s);
         else if (kind == 3) zs_dispatch<T>(hi.g.Pz, lb.L, lb.total, s);

@@ -110,8 +110,12 @@ __global__ void __launch_bounds__(kNT, 2) k_pot_z_reg(HotPlan<T> hp, PotTab<T> p
   const Geo& g = hp.g;
   const long long nq = (long long)g.Xp * g.Py;
   const long long qb = (nq + kNT - 1) / kNT;
-  const int b = (int)((long long)blockIdx.x / qb);
-  const long long q = ((long long)blockIdx.x % qb) * kNT + threadIdx.x;
+  // the grid is padded to a multiple of 8: the workgroups of one kx row (whose
+  // columns ky and Py - ky read the same folded kernel entries) share an XCD
+  const long long bid = xcd_tile((long long)blockIdx.x, (long long)gridDim.x);
+  if (bid >= (long long)hp.batch * qb) return;
+  const int b = (int)(bid / qb);
+  const long long q = (bid % qb) * kNT + threadIdx.x;
   if (q >= nq) return;
   Cx<T>* base = hp.Sy + (size_t)b * g.sy + q;
   const size_t plane = (size_t)nq;
@@ -552,7 +556,7 @@ bool pot_z_reg(const HotPlan<T>& h, const PotTab<T>& pt, hipStream_t s) {
     return false;
   } else {
     const Geo& g = h.g;
-    const dim3 grid((unsigned)((long long)h.batch * (((long long)g.Xp * g.Py + kNT - 1) / kNT)));
+    const dim3 grid((unsigned)(((long long)h.batch * (((long long)g.Xp * g.Py + kNT - 1) / kNT) + 7) / 8 * 8));
     const bool half = 2 * g.nz == g.Pz;
 #define MMX_PZ(PZ)                                                             \
   case PZ:                                                                     \
