@@ -91,8 +91,9 @@ ERROR_KPREV = 5
 
 def step_kernel_bytes(mesh, P, w, fused):
     """Algorithmic HBM bytes per launch of the attempt-only kernels: the step
-    begin as timed (fresh state: read m, k1; write the stage-2 input; after an
-    accepted attempt it also projects y5 and copies k7), the inverse-x pass with the
+    begin after an accepted attempt (read y5 and k7; write the projected m, k1 = k7
+    and the stage-2 input; after a rejection it reads m and k1 and writes the input
+    only), the inverse-x pass with the
     stage epilogue (read Sx, stage input, m, the slopes of its combination;
     write k_s and the next stage input, and the next x spectrum when fused;
     mean over stages 2..6) and with the error epilogue (read Sx, stage input,
@@ -102,7 +103,7 @@ def step_kernel_bytes(mesh, P, w, fused):
     sx = 3 * nz * Xp * ny * 2 * w
     f = 3 * nx * ny * nz * w  # one m-like array
     kp = sum(STAGE_KPREV) / len(STAGE_KPREV)
-    return {"step_begin": 3 * f,
+    return {"step_begin": 5 * f,
             "x_inv_stage": sx + (2 + kp) * f + 2 * f + (sx if fused else 0),
             "x_inv_error": sx + (1 + ERROR_KPREV) * f + f}
 
@@ -303,6 +304,52 @@ def neb_bench(mm, inputs, torch):
             "highest_image": imax, "highest_above_image0_J": float(E[imax] - E[0])}
 
 
+def sp4_bench(mm, inputs, torch, stop=0.01, samples=100):
+    """Standard Problem 4 as the paper describes it, in FP32: steepest-descent
+    relaxation from the uniform start until the largest |dm/dt| is below `stop`
+    (deg/ns), then 1 ns of adaptive Dormand-Prince dynamics in the applied field,
+    <m> sampled every 10 ps.  Reports the wall times, the relaxed S-state's <m>,
+    <m>(t) and the first time <m_x> changes sign (the OOMMF curves the paper
+    compares with are not available here: no reference values)."""
+    import numpy as np
+    w = inputs.sp4()
+    mesh = w["mesh"]
+    plan = mm.Plan(mesh, "f32", terms=w["terms"])
+    pr = mm.make_params(terms=w["relax_terms"], **w["relax"])
+    pd = mm.make_params(terms=w["terms"], **w["dynamics"])
+    m = torch.tensor(inputs.sp4_initial(), dtype=torch.float32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    st, it, dm, _ = plan.sd_relax(pr, m, stop, 200000, 1e-7, 1e-10, 1e-3, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    relax_ms = e0.elapsed_time(e1)
+    m_relaxed = [float(v) for v in m.mean(dim=(1, 2, 3)).cpu()]
+    states = mm.new_states(1, rtol=w["rtol"])
+    ts, mt = [0.0], [m_relaxed]
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(1, samples + 1):
+        plan.rk45_run(pd, m, states, t_end=w["t_end"] * k / samples)
+        mt.append([float(v) for v in m.mean(dim=(1, 2, 3)).cpu()])
+        ts.append(states[0].t)
+    e1.record()
+    torch.cuda.synchronize()
+    dyn_ms = e0.elapsed_time(e1)
+    mx = np.array([v[0] for v in mt])
+    cross = next((i for i in range(1, len(mx)) if mx[i] < 0 <= mx[i - 1]), None)
+    t0 = None
+    if cross is not None:  # linear interpolation between the samples
+        t0 = ts[cross - 1] + (ts[cross] - ts[cross - 1]) * mx[cross - 1] / (mx[cross - 1] - mx[cross])
+    return {"workload": w["name"], "relax_status": int(st), "relax_iterations": int(it[0]),
+            "relax_final_dmdt_deg_ns": float(dm[0]), "relax_ms": relax_ms, "s_state_mean_m": m_relaxed,
+            "dynamics_ms_per_ns": dyn_ms / (w["t_end"] * 1e9), "accepted_steps": int(states[0].n_accept),
+            "rejected_steps": int(states[0].n_reject), "rhs_evals": int(states[0].n_rhs),
+            "first_mx_zero_crossing_ns": None if t0 is None else t0 * 1e9,
+            "mean_m_every_100ps": [[round(x, 5) for x in mt[i]] for i in range(0, len(mt), 10)]}
+
+
 def heun_bench(mm, inputs, torch, steps=100):
     """The paper's throughput setting: N x N x 1 films, demag + exchange + Zeeman,
     fixed-step Heun with projection in FP32, m resident in HBM.  cells_per_s =
@@ -475,8 +522,8 @@ def demag_pipeline(res):
     """Every pass of one dm/dt evaluation: the demag FFT passes (forward x, y, z
     with the tensor product, inverse y) and the inverse-x complex-to-real pass,
     which also holds the local terms and the LL epilogue (its bytes: read the x
-    spectrum and m, write dm/dt).  Algorithmic bytes over the summed
-    back-to-back pass times."""
+    spectrum and m, write dm/dt).  Algorithmic bytes over the summed pass
+    times of whole evaluations timed in their own order."""
     names = tuple(p["kernel"] for p in res["passes"])
     ps = res["passes"]
     b = sum(p["alg_bytes"] for p in ps)
@@ -587,7 +634,7 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     for name in pass_names(mesh_nz):
         frags = PASS_KERNELS[name]
         if name == "x_inv_fused_llg":  # the dm/dt (MODE_RHS = 1) instance with the demag transform
-            keys = [k for k in fr if frags[0] in k and ", true, 1," in k]
+            keys = [k for k in fr if frags[0] in k and ", true, 1," in k and k.split("(")[0].endswith("false>")]
         else:
             keys = [k for f in frags for k in fr if f in k]
         # read in both runs; the instantiation the timed run used is the one
@@ -603,11 +650,20 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     # 2..6 in equal numbers in the graph replays and in the step timing)
     frf = _counter_rows(fetch_csv, True)
     wrf = _counter_rows(write_csv, True)
+    def inv_x_args(k):  # k_inv_x<T, demag, mode, cells per thread, fused, cell material>
+        if "k_inv_x<" not in k:
+            return None
+        return [a.strip() for a in k.split("k_inv_x<", 1)[1].split(">", 1)[0].split(",")]
+
+    def is_stage(k, fused):
+        a = inv_x_args(k)
+        return a is not None and a[1:3] == ["true", "2"] and a[4] == ("true" if fused else "false") and a[5] == "false"
+
     step_kinds = {"step_begin": lambda k: "k_begin<" in k,
-                  "x_inv_stage": lambda k: "k_inv_x<" in k and ", true, 2," in k and k.split("(")[0].endswith("false>"),
-                  "x_inv_stage_fused_fwd": lambda k: "k_inv_x<" in k and ", true, 2," in k and
-                  k.split("(")[0].endswith("true>"),
-                  "x_inv_error": lambda k: "k_inv_x<" in k and ", true, 3," in k}
+                  "x_inv_stage": lambda k: is_stage(k, False),
+                  "x_inv_stage_fused_fwd": lambda k: is_stage(k, True),
+                  "x_inv_error": lambda k: (inv_x_args(k) or [None] * 6)[1:3] == ["true", "3"] and
+                  inv_x_args(k)[5] == "false"}
     for name, sel in step_kinds.items():
         combos = {}
         for src, col in ((frf, 0), (wrf, 1)):
@@ -714,12 +770,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--only", choices=["slab3d", "slab3d_f64", "thinfilm", "copy", "heun", "sd", "sweep", "neb",
-                                       "potential", "padding"],
+                                       "potential", "padding", "sp4"],
                     default=None,
                     help="profiling aids: slab3d (slab3d_f64) runs only the 512x512x16 slab in FP32 (FP64), "
                          "thinfilm only the 256x256x1 film in FP32, and prints its record; copy runs only the "
                          "plain 1 GiB copies the HBM counters are scaled by; heun, sd, sweep, neb, potential, "
-                         "padding run "
+                         "padding, sp4 run "
                          "only that record")
     ap.add_argument("--retune", default=None, metavar="TABLE",
                     help="autotune the launch shapes of the workloads run and store them in the table file TABLE")
@@ -761,6 +817,9 @@ def main():
     if args.only == "potential":
         print(json.dumps(potential_bench(mm, inputs, torch)))
         return
+    if args.only == "sp4":
+        print(json.dumps(sp4_bench(mm, inputs, torch)))
+        return
     if args.only == "padding":
         print(json.dumps(padding_bench(mm, inputs, torch)))
         return
@@ -797,6 +856,8 @@ def main():
         extra["heun"] = heun_bench(mm, inputs, torch)
         print("bench: steepest descent", file=sys.stderr, flush=True)
         extra["sd"] = sd_bench(mm, inputs, torch)
+        print("bench: standard problem 4", file=sys.stderr, flush=True)
+        extra["sp4"] = sp4_bench(mm, inputs, torch)
         print("bench: padded-grid choice", file=sys.stderr, flush=True)
         extra["padding"] = padding_bench(mm, inputs, torch)
         print("bench: scalar-potential demag", file=sys.stderr, flush=True)

@@ -213,6 +213,29 @@ def heun_initial(n, mesh=None):
     return random_unit(nx, ny, nz, rng_for(5, n))
 
 
+def sp4():
+    """Standard Problem 4 as the paper states it (section "Standard Problem 4"): a
+    500 x 125 x 3 nm Permalloy film relaxed from the uniform m0 = (1, 0.25, 0.1),
+    then driven by mu0 H = (-24.6, 4.3, 0) mT.  Cells 2.5 x 2.5 x 3 nm (200 x 50 x 1);
+    Ms, A and the damping of the dynamics (0.02) are the problem's usual Permalloy
+    values, which the paper does not print; exchange + demag (+ Zeeman in the
+    dynamics)."""
+    mesh = (200, 50, 1, 2.5e-9, 2.5e-9, 3e-9)
+    H = (-24.6e-3 / MU0, 4.3e-3 / MU0, 0.0)
+    return dict(name="sp4-200x50x1", mesh=mesh,
+                relax=dict(Ms=8e5, A=1.3e-11, D=0.0, Ku=0.0, u=(0, 0, 1), H=(0.0, 0.0, 0.0), alpha=0.5),
+                dynamics=dict(Ms=8e5, A=1.3e-11, D=0.0, Ku=0.0, u=(0, 0, 1), H=H, alpha=0.02),
+                relax_terms=EXCHANGE | DEMAG, terms=EXCHANGE | DEMAG | ZEEMAN, t_end=1e-9, rtol=1e-6)
+
+
+def sp4_initial():
+    """The uniform start m0 = (1, 0.25, 0.1) / |.| of every cell."""
+    nx, ny, nz = sp4()["mesh"][:3]
+    m = np.zeros((3, nz, ny, nx))
+    m[0], m[1], m[2] = 1.0, 0.25, 0.1
+    return _unit(m)
+
+
 SWEEP_SIZES = (32, 64, 96, 128, 192, 256)
 
 

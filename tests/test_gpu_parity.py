@@ -584,3 +584,31 @@ def test_tuned_padding_keeps_fields(mm):
     mo = dp45.run(f, m1.copy(), ost, max_accept=4)
     plan.rk45_run(gp, md, st, t_end=ost.t)
     assert np.max(np.abs(md.cpu().numpy() - mo)) <= 1e-9
+
+
+def test_standard_problem_4_shape_fp64(mm):
+    """The paper's Standard Problem 4 set-up (200 x 50 x 1 cells of 2.5 x 2.5 x 3 nm
+    from the uniform start (1, 0.25, 0.1)): 15 steepest-descent iterations of the
+    relaxation (exchange + demag) against the oracle (m to 1e-9; longer runs from
+    this start amplify rounding beyond that in the oracle itself), then 20 accepted
+    adaptive steps in the applied field, alpha = 0.02 (FP64 trajectory, m to 1e-9)."""
+    w = inputs.sp4()
+    mesh = w["mesh"]
+    m0 = inputs.sp4_initial()
+    opr = oracle_params(w["relax"], w["relax_terms"])
+    field = lambda y: F.effective_field(y, F.Mesh(*mesh), opr, _kernel(mesh))
+    mo, taus = sd.run(field, m0.copy(), 15, 1e-7, 1e-10, 1e-3)
+    plan = mm.Plan(mesh, "f64", terms=w["terms"])
+    md = to_dev(m0, torch.float64)
+    tau = plan.sd_run(gpu_params(mm, w["relax"], w["relax_terms"]), md, 15, 1e-7, 1e-10, 1e-3)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
+    assert abs(tau[0] - taus[-1]) <= 1e-9 * taus[-1]
+    opd = oracle_params(w["dynamics"], w["terms"])
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), opd, _kernel(mesh))
+    ost = dp45.State(rtol=w["rtol"])
+    m1 = md.cpu().numpy()
+    mo = dp45.run(f, m1.copy(), ost, max_accept=20)
+    st = mm.new_states(1, rtol=w["rtol"])
+    plan.rk45_run(gpu_params(mm, w["dynamics"], w["terms"]), md, st, t_end=ost.t)
+    assert st[0].t == ost.t and st[0].n_reject == ost.n_reject
+    assert np.max(np.abs(md.cpu().numpy() - mo)) <= 1e-9
