@@ -652,18 +652,18 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     wrf = _counter_rows(write_csv, True)
     def inv_x_args(k):  # k_inv_x<T, demag, mode, cells per thread, fused, cell material>
         if "k_inv_x<" not in k:
-            return None
-        return [a.strip() for a in k.split("k_inv_x<", 1)[1].split(">", 1)[0].split(",")]
+            return [None] * 6
+        a = [x.strip() for x in k.split("k_inv_x<", 1)[1].split(">", 1)[0].split(",")]
+        return a + ["false"] * (6 - len(a))  # builds without the cell-material argument
 
     def is_stage(k, fused):
         a = inv_x_args(k)
-        return a is not None and a[1:3] == ["true", "2"] and a[4] == ("true" if fused else "false") and a[5] == "false"
+        return a[1:3] == ["true", "2"] and a[4] == ("true" if fused else "false") and a[5] == "false"
 
     step_kinds = {"step_begin": lambda k: "k_begin<" in k,
                   "x_inv_stage": lambda k: is_stage(k, False),
                   "x_inv_stage_fused_fwd": lambda k: is_stage(k, True),
-                  "x_inv_error": lambda k: (inv_x_args(k) or [None] * 6)[1:3] == ["true", "3"] and
-                  inv_x_args(k)[5] == "false"}
+                  "x_inv_error": lambda k: inv_x_args(k)[1:3] == ["true", "3"] and inv_x_args(k)[5] == "false"}
     for name, sel in step_kinds.items():
         combos = {}
         for src, col in ((frf, 0), (wrf, 1)):

@@ -112,8 +112,8 @@ def test_ingest_scales_by_copy_and_keeps_shapes_read_in_both_runs(tmp_path, monk
     # the copy's fetch counter reads half its bytes, its write counter all of them
     _csv(tmp_path / "cf.csv", [(copy, kib / 2, 1, 1)])
     _csv(tmp_path / "cw.csv", [(copy, kib, 1, 1)])
-    st4 = "void mmx::k_inv_x<float, true, 2, 4, true>(mmx::Launch<float>)"
-    st1 = "void mmx::k_inv_x<float, true, 2, 1, true>(mmx::Launch<float>)"
+    st4 = "void mmx::k_inv_x<float, true, 2, 4, true, false>(mmx::Launch<float>)"
+    st1 = "void mmx::k_inv_x<float, true, 2, 1, true, false>(mmx::Launch<float>)"
     yk = "void mmx::k_ypass_s<float, 512, 8>(mmx::Launch<float>)"
     yk16 = "void mmx::k_ypass_s<float, 512, 16>(mmx::Launch<float>)"
     fetch = [(st4, 10, 100, 50)] * 3 + [(st1, 20, 400, 100)] * 2 + [(yk, 3, 1, 1)] * 4 + [(yk16, 5, 1, 1)]
