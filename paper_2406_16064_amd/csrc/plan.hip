@@ -1970,8 +1970,6 @@ mm_status tune_padding_impl(mm_plan* p, const mm_params* q, int batch, const voi
   return st != MM_OK ? st : rs;
 }
 
-// eval: a field, dm/dt, energy or pass-timing call (the only calls a plan of
-// the scalar-potential route serves)
 // Calls a plan of the scalar-potential route serves: evaluations and the
 // integrators (adaptive, Heun, steepest descent and their relaxations); not
 // the attempt profiler or the autotuner, which time the Newell passes.

@@ -220,3 +220,27 @@ def test_sd_and_relax_fp64(mm):
     assert status == 0 and st[0].n_accept == ost.n_accept and st[0].n_reject == ost.n_reject
     assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-9
     assert abs(dm[0] - meas[-1]) <= 1e-9 * meas[-1]
+
+
+def test_batch_of_two_instances(mm):
+    """Two instances with their own material and field in one call (FP64): each
+    instance's H_eff and dm/dt against the oracle, and a Heun run of the pair
+    against the oracle's runs one by one."""
+    mesh = (13, 10, 3, 2e-9, 2.5e-9, 1.5e-9)
+    ps = [PAR, dict(PAR, Ms=6e5, A=1.1e-11, Ku=4e5, H=(-3e4, 1e4, 2e4), alpha=0.4)]
+    plan = mm.Plan(mesh, "f64", terms=POT | LOCAL, max_batch=2)
+    kern = P.PotentialKernel(F.Mesh(*mesh), P=tuple(plan.padded()[::-1]))
+    m0 = np.stack([_state(mesh, 31), _state(mesh, 32)])
+    gps = [mm.make_params(terms=POT | LOCAL, **p) for p in ps]
+    ops = [F.Params(terms=LOCAL | F.DEMAG, **p) for p in ps]
+    md = to_dev(m0, torch.float64)
+    H = plan.effective_field(gps, md).cpu().numpy()
+    k = plan.llg_rhs(gps, md).cpu().numpy()
+    for b in range(2):
+        Href = P.effective_field(m0[b], F.Mesh(*mesh), ops[b], kern)
+        assert field_err(H[b], Href) <= 1e-11
+        assert field_err(k[b], F.llg_rhs_from_field(m0[b], Href, ops[b])) <= 1e-11
+    plan.heun_run(gps, md, 3e-14, 6)
+    for b in range(2):
+        mo = heun.run(_rhs(mesh, ops[b], kern), m0[b].copy(), 3e-14, 6)
+        assert np.max(np.linalg.norm(md[b].cpu().numpy() - mo, axis=0)) <= 1e-10
