@@ -1471,6 +1471,102 @@ __device__ inline void control_step(DevCtl& C, const double* __restrict__ replay
   C.h_att = hn;
 }
 
+// End of an error pass in one workgroup: the largest error norm emax (and,
+// for relaxations, the largest |k_7|^2 kmax) of its cells go into the
+// instance's running maxima; the last of the instance's bpi workgroups to
+// arrive takes the step decision.  The arrival uses the maxima's returned
+// values (their top bits, always 0 for non-negative doubles), so it is issued
+// only once the maxima are complete; the atomics are performed where every
+// XCD sees them, so no fence (an L2 write-back on this part) is needed.
+// red: the workgroup's LDS scratch, at least [2][waves].
+__device__ __forceinline__ void error_pass_end(double emax, double kmax, DevCtl* ctl, int b, int bpi,
+                                               const double* replay, double (*red)[512 / 64]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool relax = ldu(&ctl[b].stop_dmdt) > 0.0;
+  const double w = wave_max(emax);
+  if (lane == 0) red[0][wave] = w;
+  if (relax) {
+    const double wk = wave_max(kmax);
+    if (lane == 0) red[1][wave] = wk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = red[0][0];
+    for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
+    const unsigned long long prev = atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
+    unsigned long long prevk = 0ull;
+    if (relax) {
+      double vk = red[1][0];
+      for (int j = 1; j < (int)(blockDim.x >> 6); ++j) vk = fmax(vk, red[1][j]);
+      prevk = atomicMax(&ctl[b].dmdt_bits, (unsigned long long)__double_as_longlong(sqrt(vk)));
+    }
+    const int inc = 1 + (int)(prev >> 63) + (int)(prevk >> 63);
+    if (atomicAdd(&ctl[b].arrive, inc) == bpi - 1) {
+      ctl[b].arrive = 0;
+      ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);  // the complete maxima
+      if (relax) ctl[b].dmdt_bits = atomicOr(&ctl[b].dmdt_bits, 0ull);
+      control_step(ctl[b], replay);
+    }
+  }
+}
+
+// Runge-Kutta combination of one cell: base + sum_j hc_j kb_j + hl kk (hc_j,
+// hl: h times the coefficients, zero where a slope is not used), projected
+// back onto |m| = 1 when `project` (the end of a fixed step).
+template <typename T>
+__device__ __forceinline__ V3<T> rk_combine(V3<T> base, const V3<T> (&kb)[6], const T (&hc)[7], T hl, V3<T> kk,
+                                            bool project) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    base.x += hc[j] * kb[j].x; base.y += hc[j] * kb[j].y; base.z += hc[j] * kb[j].z;
+  }
+  base.x += hl * kk.x; base.y += hl * kk.y; base.z += hl * kk.z;
+  if (project) {
+    const T s = rsqrt_t<T>(base.x * base.x + base.y * base.y + base.z * base.z);
+    base.x *= s; base.y *= s; base.z *= s;
+  }
+  return base;
+}
+
+// Embedded error of one cell, |sum_j hc_j kb_j + hl kk| (the products in the
+// plan precision, their sum in FP64), and |kk|^2, into running maxima; NaN or
+// Inf count as +Inf.
+template <typename T>
+__device__ __forceinline__ void rk_error(const V3<T> (&kb)[6], const T (&hc)[7], T hl, V3<T> kk, double& emax,
+                                         double& kmax) {
+  double ex = 0, ey = 0, ez = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    ex += (double)(hc[j] * kb[j].x); ey += (double)(hc[j] * kb[j].y); ez += (double)(hc[j] * kb[j].z);
+  }
+  ex += (double)(hl * kk.x); ey += (double)(hl * kk.y); ez += (double)(hl * kk.z);
+  double en = sqrt(ex * ex + ey * ey + ez * ez);
+  if (!(en <= DBL_MAX)) en = HUGE_VAL;
+  emax = fmax(emax, en);
+  double kn = (double)kk.x * kk.x + (double)kk.y * kk.y + (double)kk.z * kk.z;
+  if (!(kn <= DBL_MAX)) kn = HUGE_VAL;
+  kmax = fmax(kmax, kn);
+}
+
+// End of an energy pass in one workgroup: its five FP64 sums (exchange, demag,
+// DMI, anisotropy, Zeeman) to partial[(b bpi + lb) 5 + q], summed later in a
+// fixed order.  red: the workgroup's LDS scratch, [5][waves].
+__device__ __forceinline__ void energy_pass_end(const double (&esum)[5], double* partial, int b, int bpi, int lb,
+                                                double (*red)[512 / 64]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = 0; q < 5; ++q) {
+    const double w = wave_sum(esum[q]);
+    if (lane == 0) red[q][wave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double v = 0;
+    for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
+    gst(partial + ((size_t)b * bpi + lb) * 5 + threadIdx.x, v);
+  }
+}
+
+
 
 // CPT > 0: every thread owns at most CPT cells (the host checks TY nx <= CPT
 // threads) and the cell loop is unrolled; CPT == 1 also loads the cell's
@@ -1742,18 +1838,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       if constexpr (MODE == MODE_STAGE) {
         // next stage input: m + h sum_j a_j k_j (k of this stage is the last term;
         // slots with a zero coefficient hold zeros)
-        V3<T> acc = mbv;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          const T cj = hcoef[j];
-          acc.x += cj * kb[j].x; acc.y += cj * kb[j].y; acc.z += cj * kb[j].z;
-        }
-        const T cl = hlast;
-        acc.x += cl * kk.x; acc.y += cl * kk.y; acc.z += cl * kk.z;
-        if (epi.project) {  // the end of a fixed step: back onto the unit sphere
-          const T s = rsqrt_t<T>(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
-          acc.x *= s; acc.y *= s; acc.z *= s;
-        }
+        const V3<T> acc = rk_combine(mbv, kb, hcoef, hlast, kk, epi.project != 0);
         if constexpr (DEFER) res2[slot] = acc;
         else st3o(epi.msn + ib, co, acc);
         if constexpr (FUSE) {
@@ -1762,20 +1847,7 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
             if (P.terms & MM_CELLS) mnext[slot] = {acc.x * cn.ms, acc.y * cn.ms, acc.z * cn.ms};
         }
       } else if constexpr (MODE == MODE_ERROR) {
-        double ex = 0, ey = 0, ez = 0;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          const T cj = hcoef[j];
-          ex += (double)(cj * kb[j].x); ey += (double)(cj * kb[j].y); ez += (double)(cj * kb[j].z);
-        }
-        const T cl = hlast;
-        ex += (double)(cl * kk.x); ey += (double)(cl * kk.y); ez += (double)(cl * kk.z);
-        double en = sqrt(ex * ex + ey * ey + ez * ez);
-        if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
-        emax = fmax(emax, en);
-        double kn = (double)kk.x * kk.x + (double)kk.y * kk.y + (double)kk.z * kk.z;
-        if (!(kn <= DBL_MAX)) kn = HUGE_VAL;
-        kmax = fmax(kmax, kn);
+        rk_error(kb, hcoef, hlast, kk, emax, kmax);
       }
     }
     (void)slot;
@@ -1870,53 +1942,10 @@ __global__ void __launch_bounds__(512) k_inv_x(Launch<T> L) {
       }
     }
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if constexpr (MODE == MODE_ERROR) {
-    const bool relax = ldu(&ctl[b].stop_dmdt) > 0.0;
-    const double w = wave_max(emax);
-    if (lane == 0) red[0][wave] = w;
-    if (relax) {
-      const double wk = wave_max(kmax);
-      if (lane == 0) red[1][wave] = wk;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = red[0][0];
-      for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
-      const unsigned long long prev = atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
-      unsigned long long prevk = 0ull;
-      if (relax) {
-        double vk = red[1][0];
-        for (int j = 1; j < (int)(blockDim.x >> 6); ++j) vk = fmax(vk, red[1][j]);
-        prevk = atomicMax(&ctl[b].dmdt_bits, (unsigned long long)__double_as_longlong(sqrt(vk)));
-      }
-      // the last workgroup of this instance to arrive takes the step decision.
-      // The arrival uses the maxima's returned values (their top bits, always
-      // 0 for non-negative doubles), so it is issued only once the maxima are
-      // complete; the atomics are performed where every XCD sees them, so
-      // no fence (an L2 write-back on this part) is needed.
-      const int inc = 1 + (int)(prev >> 63) + (int)(prevk >> 63);
-      const int bpi = tiles * g.nz;
-      if (atomicAdd(&ctl[b].arrive, inc) == bpi - 1) {
-        ctl[b].arrive = 0;
-        ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);  // the complete maxima
-        if (relax) ctl[b].dmdt_bits = atomicOr(&ctl[b].dmdt_bits, 0ull);
-        control_step(ctl[b], epi.replay);
-      }
-    }
+    error_pass_end(emax, kmax, ctl, b, tiles * g.nz, epi.replay, red);
   } else if constexpr (energy) {
-    for (int q = 0; q < 5; ++q) {
-      const double w = wave_sum(esum[q]);
-      if (lane == 0) red[q][wave] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) {
-      double v = 0;
-      for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
-      const int bpi = tiles * g.nz;
-      const int lb = (int)(bid0 % bpi);
-      gst(epi.partial + ((size_t)b * bpi + lb) * 5 + threadIdx.x, v);
-    }
+    energy_pass_end(esum, epi.partial, b, tiles * g.nz, (int)(bid0 % (tiles * g.nz)), red);
   }
 }
 

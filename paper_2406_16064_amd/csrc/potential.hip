@@ -394,35 +394,12 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
     const V3<T> mi = nb.mi;
     V3<T> o = H;
     if constexpr (MODE == MODE_RHS || RK) o = ll_rhs(mi, H, g1, g2);
-    if constexpr (MODE == MODE_STAGE) {
-      // next stage input m + h sum_j a_j k_j (this stage's slope last)
-      V3<T> acc = mbv;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        acc.x += hcoef[j] * kb[j].x; acc.y += hcoef[j] * kb[j].y; acc.z += hcoef[j] * kb[j].z;
-      }
-      acc.x += hlast * o.x; acc.y += hlast * o.y; acc.z += hlast * o.z;
-      if (epi.project) {  // the end of a fixed step: back onto the unit sphere
-        const T sc = rsqrt_t<T>(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
-        acc.x *= sc; acc.y *= sc; acc.z *= sc;
-      }
+    if constexpr (MODE == MODE_STAGE) {  // next stage input m + h sum_j a_j k_j (this stage's slope last)
+      const V3<T> acc = rk_combine(mbv, kb, hcoef, hlast, o, epi.project != 0);
       if constexpr (CPT > 0) res2[slot] = acc;
       else st3o(epi.msn + ib, co, acc);
     }
-    if constexpr (MODE == MODE_ERROR) {
-      double ex = 0, ey = 0, ez = 0;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        ex += (double)(hcoef[j] * kb[j].x); ey += (double)(hcoef[j] * kb[j].y); ez += (double)(hcoef[j] * kb[j].z);
-      }
-      ex += (double)(hlast * o.x); ey += (double)(hlast * o.y); ez += (double)(hlast * o.z);
-      double en = sqrt(ex * ex + ey * ey + ez * ez);
-      if (!(en <= DBL_MAX)) en = HUGE_VAL;  // NaN or Inf -> +Inf (kept by max)
-      emax = fmax(emax, en);
-      double kn = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
-      if (!(kn <= DBL_MAX)) kn = HUGE_VAL;
-      kmax = fmax(kmax, kn);
-    }
+    if constexpr (MODE == MODE_ERROR) rk_error(kb, hcoef, hlast, o, emax, kmax);
     if constexpr (MODE == MODE_ENERGY) {
       esum[0] += lt.ex;
       if (add_hd) esum[1] += (double)mi.x * hd.x + (double)mi.y * hd.y + (double)mi.z * hd.z;
@@ -453,54 +430,8 @@ __global__ void __launch_bounds__(512) k_pot_x(HotPlan<T> hp, const Epi<T>* __re
         }
     }
   }
-  if constexpr (MODE == MODE_ERROR) {
-    // the largest error norm (and |k_7|, for relaxations) of the instance; the
-    // last of its workgroups to arrive takes the step decision (the arrival
-    // counts the maxima's returned top bits, so it follows them)
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool relax = ldu(&ctl[b].stop_dmdt) > 0.0;
-    const double w = wave_max(emax);
-    if (lane == 0) red[0][wave] = w;
-    if (relax) {
-      const double wk = wave_max(kmax);
-      if (lane == 0) red[1][wave] = wk;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = red[0][0];
-      for (int j = 1; j < (int)(blockDim.x >> 6); ++j) v = fmax(v, red[0][j]);
-      const unsigned long long prev = atomicMax(&ctl[b].err_bits, (unsigned long long)__double_as_longlong(v));
-      unsigned long long prevk = 0ull;
-      if (relax) {
-        double vk = red[1][0];
-        for (int j = 1; j < (int)(blockDim.x >> 6); ++j) vk = fmax(vk, red[1][j]);
-        prevk = atomicMax(&ctl[b].dmdt_bits, (unsigned long long)__double_as_longlong(sqrt(vk)));
-      }
-      const int inc = 1 + (int)(prev >> 63) + (int)(prevk >> 63);
-      const int bpi = tiles * g.nz;
-      if (atomicAdd(&ctl[b].arrive, inc) == bpi - 1) {
-        ctl[b].arrive = 0;
-        ctl[b].err_bits = atomicOr(&ctl[b].err_bits, 0ull);
-        if (relax) ctl[b].dmdt_bits = atomicOr(&ctl[b].dmdt_bits, 0ull);
-        control_step(ctl[b], epi.replay);
-      }
-    }
-  }
-  if constexpr (MODE == MODE_ENERGY) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int q = 0; q < 5; ++q) {
-      const double w = wave_sum(esum[q]);
-      if (lane == 0) red[q][wave] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) {
-      double v = 0;
-      for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v += red[threadIdx.x][j];
-      const int bpi = tiles * g.nz;
-      const int lb = (int)(bidx % bpi);
-      gst(epi.partial + ((size_t)b * bpi + lb) * 5 + threadIdx.x, v);
-    }
-  }
+  if constexpr (MODE == MODE_ERROR) error_pass_end(emax, kmax, ctl, b, tiles * g.nz, epi.replay, red);
+  if constexpr (MODE == MODE_ENERGY) energy_pass_end(esum, epi.partial, b, tiles * g.nz, (int)(bidx % (tiles * g.nz)), red);
 }
 
 // ---------------------------------------------------------------------------
