@@ -464,12 +464,13 @@ bool eval_fusable(const GroupSet<T>& gs) {
 // launch shapes give a column at least SL/8 threads and the workgroup still
 // fits, else 16.  nt: the threads to launch.
 template <typename T>
-int static_y(const GroupSet<T>& gs, bool inv, int& nt, int& ept) {
+int static_y(const GroupSet<T>& gs, bool inv, int& nt, int& ept, const bool* use = nullptr) {
   int sl = 0, cmax = 0;
   bool e8 = true;
   for (int i = 0; i < gs.n; ++i) {
     const HotPlan<T>& h = gs.h[i];
     if (inv && h.g.nz == 1) continue;
+    if (use && !use[i]) continue;
     const int L = h.g.Py;
     if (L != 2 * h.g.ny || (L != 256 && L != 512 && L != 1024 && L != 2048)) return 0;
     if (sl != 0 && sl != L) return 0;
@@ -481,6 +482,15 @@ int static_y(const GroupSet<T>& gs, bool inv, int& nt, int& ept) {
   ept = e8 && cmax * (sl / 8) <= 512 ? 8 : 16;
   nt = std::max(64, (cmax * (sl / ept) + 63) / 64 * 64);
   return sl;
+}
+
+// The y passes launch once per length with a compiled transform (Py = 2 ny of
+// 256 to 2048) among the groups, and once for the rest (the general
+// transform): key of group i, 0 for the general kernels.
+template <typename T>
+int y_key(const HotPlan<T>& h) {
+  const int L = h.g.Py;
+  return L == 2 * h.g.ny && (L == 256 || L == 512 || L == 1024 || L == 2048) ? L : 0;
 }
 
 template <typename T>
@@ -528,12 +538,25 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
       }
     }
     if (on(1)) {  // y forward (2-D groups: fused forward / product / inverse)
+      mark();
+      int keys[kMaxGroups], nkeys = 0;
+      for (int i = 0; i < gs.n; ++i) {
+        const int k = y_key(gs.h[i]);
+        bool seen = false;
+        for (int j = 0; j < nkeys; ++j) seen = seen || keys[j] == k;
+        if (!seen) keys[nkeys++] = k;
+      }
+      for (int kk = 0; kk < nkeys; ++kk) {
+      bool use[kMaxGroups];
       LaunchBuilder<T> lb(gs, epis);
       int nt = 64;
       size_t lds = 0;
       for (int i = 0; i < gs.n; ++i) {
         const HotPlan<T>& h = gs.h[i];
-        if (h.g.nz == 1) {
+        use[i] = y_key(h) == keys[kk];
+        if (!use[i]) {
+          lb.set(i, 0);
+        } else if (h.g.nz == 1) {
           lb.set(i, y2d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, ((size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) + h.g.Py) * csz +
                                   (y2d_tensor_in_lds(h.g) ? (size_t)4 * h.tu.cb_y2 * h.g.Ky * (csz / 2) : 0));
@@ -541,12 +564,11 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
           lb.set(i, y3d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);
         }
-        nt = std::max(nt, h.tu.nt_y);
+        if (use[i]) nt = std::max(nt, h.tu.nt_y);
       }
-      mark();
       int nts = 0, ept = 16;
       const dim3 grid((unsigned)lb.total);
-      const int sly = static_y(gs, false, nts, ept);
+      const int sly = static_y(gs, false, nts, ept, use);
       switch (sly * 100 + (sly ? ept : 0)) {
         case 25608: k_ypass_s<T, 256, 8><<<grid, nts, lds, s>>>(lb.L); break;
         case 25616: k_ypass_s<T, 256, 16><<<grid, nts, lds, s>>>(lb.L); break;
@@ -559,6 +581,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         default:
           if (y16) k_ypass<T, true><<<grid, nt, lds, s>>>(lb.L);
           else k_ypass<T, false><<<grid, nt, lds, s>>>(lb.L);
+      }
       }
     }
     if (any3d) {
@@ -608,24 +631,34 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         }
       }
       if (nt > 0 && on(2)) k_z3d<T><<<dim3((unsigned)lz.total), nt, lds, s>>>(lz.L);
-      // y inverse
+      // y inverse (3-D groups), one launch per key as the forward pass
+      mark();
+      int keys[kMaxGroups], nkeys = 0;
+      for (int i = 0; i < gs.n && on(3); ++i) {
+        if (gs.h[i].g.nz == 1) continue;
+        const int k = y_key(gs.h[i]);
+        bool seen = false;
+        for (int j = 0; j < nkeys; ++j) seen = seen || keys[j] == k;
+        if (!seen) keys[nkeys++] = k;
+      }
+      for (int kk = 0; kk < nkeys; ++kk) {
+      bool usey[kMaxGroups];
       LaunchBuilder<T> ly(gs, epis);
       int nty = 64;
       size_t ldsy = 0;
       for (int j = 0; j < gs.n; ++j) {
         const HotPlan<T>& h = gs.h[j];
-        const bool use = h.g.nz > 1;
-        ly.set(j, use ? y3d_blocks(h.g, h.tu, h.batch) : 0);
-        if (use) {
+        usey[j] = h.g.nz > 1 && y_key(h) == keys[kk];
+        ly.set(j, usey[j] ? y3d_blocks(h.g, h.tu, h.batch) : 0);
+        if (usey[j]) {
           nty = std::max(nty, h.tu.nt_y);
           ldsy = std::max(ldsy, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);
         }
       }
-      mark();
       int nts = 0, ept = 16;
       const dim3 gridy((unsigned)ly.total);
-      const int sly = on(3) ? static_y(gs, true, nts, ept) : 0;
-      if (on(3)) switch (sly * 100 + (sly ? ept : 0)) {
+      const int sly = static_y(gs, true, nts, ept, usey);
+      switch (sly * 100 + (sly ? ept : 0)) {
           case 25608: k_yinv_s<T, 256, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
           case 25616: k_yinv_s<T, 256, 16><<<gridy, nts, ldsy, s>>>(ly.L); break;
           case 51208: k_yinv_s<T, 512, 8><<<gridy, nts, ldsy, s>>>(ly.L); break;
@@ -638,6 +671,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
             if (y16) k_yinv<T, true><<<gridy, nty, ldsy, s>>>(ly.L);
             else k_yinv<T, false><<<gridy, nty, ldsy, s>>>(ly.L);
         }
+      }
     }
   }
   if (on(p_inv)) {  // x inverse + epilogue

@@ -252,6 +252,7 @@ struct Group {
   std::vector<char> cells_set;  // slot i holds data
   void* stage = nullptr;  // ms0, ms1, k1..k7: 9 x stage_cap x 3N
   void* mbuf = nullptr;   // contiguous m of the group's instances (batch runs)
+  int tuned_for = 1;      // batch runs: the instance count the launch shapes were chosen for
   double imag_ratio = 0.0;
 };
 
@@ -406,9 +407,10 @@ DevParams dev_params(const mm_params& r, const Group& G, bool general) {
 // per CU), the per-thread butterfly budget of the transforms is respected, and
 // tiles shrink until a pass has about 4 workgroups per CU (small meshes) or
 // reach their coalescing-friendly maximum (large meshes).
-mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
+mm_status choose_tuning(Group& G, mm_precision prec, size_t csz, int instances = 1) {
   const Geo& g = G.g;
   Tuning& t = G.tu;
+  const long long ninst = std::max(1, instances);  // the workgroups of a pass cover every instance
   const size_t budget = 80 * 1024;
   const long long want = 4 * 256;  // workgroups per pass worth aiming for
   auto tpc_for = [&](int L, bool allow16 = false) {
@@ -421,7 +423,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
   const size_t ytab = (size_t)g.Py * csz;
   const size_t ktab2 = y2d_tensor_in_lds(g) ? (size_t)4 * g.Ky * (csz / 2) : 0;  // per kx column of the fused 2-D y pass
   {  // forward x: rows of one component
-    const long long rows = 3LL * g.nz * g.ny;
+    const long long rows = 3LL * g.nz * g.ny * ninst;
     int ty = 16;
     while (ty > 1 && ((size_t)ty * rowb + xtab > budget || ty * tpx > 512 || rows / ty < want)) ty /= 2;
     while (ty > g.ny) ty /= 2;  // a power of two (the kernels split rows by shifts)
@@ -431,7 +433,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz) {
     t.tpc_f = t.nt_f / ty;
   }
   {  // inverse x + epilogue: rows of all 3 components (3 columns per row)
-    const long long rows = (long long)g.nz * g.ny;
+    const long long rows = (long long)g.nz * g.ny * ninst;
     int ty = 16;
     while (ty > 1 && ((size_t)3 * ty * rowb + xtab > budget || 3 * ty * tpx > 512 || rows / ty < want)) ty /= 2;
     while (ty > g.ny) ty /= 2;  // a power of two (the kernels split rows by shifts)
@@ -1604,6 +1606,16 @@ mm_status batch_run(mm_batch* bt, mm_instance* inst, int n, long long max_steps,
   std::vector<std::vector<int>> members(ng);
   for (int i = 0; i < n; ++i) members[inst[i].mesh_id].push_back(i);
   for (int g = 0; g < ng; ++g) nb[g] = (int)members[g].size();
+  // launch shapes for the group's instance count: one launch per pass covers
+  // every instance of every group, so rows per workgroup grow with the count
+  for (int g = 0; g < ng; ++g) {
+    Group& G = E.groups[g];
+    if (nb[g] == 0 || nb[g] == G.tuned_for) continue;
+    MMCHK(choose_tuning(G, E.prec, E.csz, nb[g]));
+    G.tuned_for = nb[g];
+    if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+    E.k1_ok = false;
+  }
   MMCHK(engine_reserve(E, nb));
   // gather every group's instances into its contiguous state buffer
   std::vector<T*> m(ng, nullptr);

@@ -214,3 +214,30 @@ def test_sweep_largest_meshes_fp64(mm):
         ost = dp45.State(rtol=1e-6)
         mo = dp45.run(f, m0[k].copy(), ost, t_end=t_end)
         assert np.max(np.abs(devs[k].cpu().numpy() - mo)) <= 1e-9, k
+
+
+def test_batch_mixes_compiled_and_general_y_transforms_fp64(mm):
+    """A batch whose 3-D groups need both the y transforms compiled for their length
+    (128 x 128 x 2: Py = 256) and the general ones (96 x 96 x 2: Py = 192), with a 2-D
+    group beside them: one y launch per length, each instance against the oracle."""
+    meshes = [(128, 128, 2, 2e-9, 2e-9, 2e-9), (96, 96, 2, 2e-9, 2e-9, 2e-9), (64, 64, 1, 2e-9, 2e-9, 2e-9)]
+    pars, m0 = [], []
+    for k, msh in enumerate(meshes):
+        rng = np.random.Generator(np.random.PCG64(3200 + k))
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        pars.append(dict(Ms=rng.uniform(4e5, 1.2e6), A=rng.uniform(5e-12, 2e-11), D=rng.uniform(0, 4e-3),
+                         Ku=rng.uniform(0, 1e6), u=(0, 0, 1), H=tuple(rng.uniform(0, 3e5) * d),
+                         alpha=rng.uniform(0.01, 0.5)))
+        m0.append(inputs.random_unit(msh[0], msh[1], msh[2], rng))
+    batch = mm.Batch(meshes, "f64", terms=mm.ALL_TERMS)
+    devs = [to_dev(m, torch.float64) for m in m0]
+    t_end = 1e-13
+    batch.run([dict(mesh_id=k, params=gpu_params(mm, pars[k], mm.ALL_TERMS), m=devs[k], t_end=t_end)
+               for k in range(3)])
+    for k, msh in enumerate(meshes):
+        op = oracle_params(pars[k], F.ALL_TERMS)
+        f = lambda y: F.llg_rhs(y, F.Mesh(*msh), op, _kernel(msh))
+        ost = dp45.State(rtol=1e-6)
+        mo = dp45.run(f, m0[k].copy(), ost, t_end=t_end)
+        assert np.max(np.abs(devs[k].cpu().numpy() - mo)) <= 1e-9, k
