@@ -511,30 +511,39 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
     for (int st = 0; st < gs.h[i].fd[1].nst; ++st) y16 = y16 || radix_of(gs.h[i].fd[1].code, st) == 16;
   if (demag) {
     if (!skip_fwd && on(0)) {  // x forward (skipped when the previous stage's inverse-x pass did it)
-      LaunchBuilder<T> lb(gs, epis);
-      int nt = 64;
-      size_t lds = 0;
-      for (int i = 0; i < gs.n; ++i) {
-        const HotPlan<T>& h = gs.h[i];
-        lb.set(i, fwd_blocks(h.g, h.tu, h.batch));
-        nt = std::max(nt, h.tu.nt_f);
-        lds = std::max(lds, ((size_t)h.tu.ty_f * col_stride(h.g.Lx) + 2 * h.g.Lx + 1) * csz);
-      }
+      // one launch per static length (every group with an even nx = Lx of
+      // 128 to 1024 shares the kernel compiled for its Lx), one for the rest
+      auto x_key = [&](const Geo& g) {
+        return g.nx == g.Lx && (g.Lx == 128 || g.Lx == 256 || g.Lx == 512 || g.Lx == 1024) ? g.Lx : 0;
+      };
       mark();
-      // one static length when every group has an even nx = Lx, the same Lx
-      int slx = 0;
-      for (int i = 0; i < gs.n && slx >= 0; ++i) {
-        const Geo& g = gs.h[i].g;
-        const bool st = g.nx == g.Lx && (g.Lx == 128 || g.Lx == 256 || g.Lx == 512 || g.Lx == 1024);
-        slx = st && (slx == 0 || slx == g.Lx) ? g.Lx : -1;
+      int keys[kMaxGroups], nkeys = 0;
+      for (int i = 0; i < gs.n; ++i) {
+        const int k = x_key(gs.h[i].g);
+        bool seen = false;
+        for (int j = 0; j < nkeys; ++j) seen = seen || keys[j] == k;
+        if (!seen) keys[nkeys++] = k;
       }
-      const dim3 grid((unsigned)lb.total);
-      switch (slx) {
-        case 128: k_fwd_x<T, 128><<<grid, nt, lds, s>>>(lb.L); break;
-        case 256: k_fwd_x<T, 256><<<grid, nt, lds, s>>>(lb.L); break;
-        case 512: k_fwd_x<T, 512><<<grid, nt, lds, s>>>(lb.L); break;
-        case 1024: k_fwd_x<T, 1024><<<grid, nt, lds, s>>>(lb.L); break;
-        default: k_fwd_x<T, 0><<<grid, nt, lds, s>>>(lb.L);
+      for (int kk = 0; kk < nkeys; ++kk) {
+        LaunchBuilder<T> lb(gs, epis);
+        int nt = 64;
+        size_t lds = 0;
+        for (int i = 0; i < gs.n; ++i) {
+          const HotPlan<T>& h = gs.h[i];
+          const bool use = x_key(h.g) == keys[kk];
+          lb.set(i, use ? fwd_blocks(h.g, h.tu, h.batch) : 0);
+          if (!use) continue;
+          nt = std::max(nt, h.tu.nt_f);
+          lds = std::max(lds, ((size_t)h.tu.ty_f * col_stride(h.g.Lx) + 2 * h.g.Lx + 1) * csz);
+        }
+        const dim3 grid((unsigned)lb.total);
+        switch (keys[kk]) {
+          case 128: k_fwd_x<T, 128><<<grid, nt, lds, s>>>(lb.L); break;
+          case 256: k_fwd_x<T, 256><<<grid, nt, lds, s>>>(lb.L); break;
+          case 512: k_fwd_x<T, 512><<<grid, nt, lds, s>>>(lb.L); break;
+          case 1024: k_fwd_x<T, 1024><<<grid, nt, lds, s>>>(lb.L); break;
+          default: k_fwd_x<T, 0><<<grid, nt, lds, s>>>(lb.L);
+        }
       }
     }
     if (on(1)) {  // y forward (2-D groups: fused forward / product / inverse)
