@@ -252,7 +252,8 @@ struct Group {
   std::vector<char> cells_set;  // slot i holds data
   void* stage = nullptr;  // ms0, ms1, k1..k7: 9 x stage_cap x 3N
   void* mbuf = nullptr;   // contiguous m of the group's instances (batch runs)
-  int tuned_for = 1;      // batch runs: the instance count the launch shapes were chosen for
+  long long tuned_for = 0;  // batch and NEB runs: the launch rows the launch shapes were chosen for
+  bool user_shapes = false;  // shapes set by mm_plan_set_shapes or the autotuner: kept as they are
   double imag_ratio = 0.0;
 };
 
@@ -407,10 +408,13 @@ DevParams dev_params(const mm_params& r, const Group& G, bool general) {
 // per CU), the per-thread butterfly budget of the transforms is respected, and
 // tiles shrink until a pass has about 4 workgroups per CU (small meshes) or
 // reach their coalescing-friendly maximum (large meshes).
-mm_status choose_tuning(Group& G, mm_precision prec, size_t csz, int instances = 1) {
+// launch_rows: rows (nz ny per instance) of every group of a batch launch, 0
+// for one instance of this group alone: the workgroup count aimed at counts
+// the whole launch, so that the meshes of a large batch take rows per
+// workgroup up to the LDS and thread limits.
+mm_status choose_tuning(Group& G, mm_precision prec, size_t csz, long long launch_rows = 0) {
   const Geo& g = G.g;
   Tuning& t = G.tu;
-  const long long ninst = std::max(1, instances);  // the workgroups of a pass cover every instance
   const size_t budget = 80 * 1024;
   const long long want = 4 * 256;  // workgroups per pass worth aiming for
   auto tpc_for = [&](int L, bool allow16 = false) {
@@ -423,7 +427,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz, int instances =
   const size_t ytab = (size_t)g.Py * csz;
   const size_t ktab2 = y2d_tensor_in_lds(g) ? (size_t)4 * g.Ky * (csz / 2) : 0;  // per kx column of the fused 2-D y pass
   {  // forward x: rows of one component
-    const long long rows = 3LL * g.nz * g.ny * ninst;
+    const long long rows = 3LL * (launch_rows > 0 ? launch_rows : (long long)g.nz * g.ny);
     int ty = 16;
     while (ty > 1 && ((size_t)ty * rowb + xtab > budget || ty * tpx > 512 || rows / ty < want)) ty /= 2;
     while (ty > g.ny) ty /= 2;  // a power of two (the kernels split rows by shifts)
@@ -433,7 +437,7 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz, int instances =
     t.tpc_f = t.nt_f / ty;
   }
   {  // inverse x + epilogue: rows of all 3 components (3 columns per row)
-    const long long rows = (long long)g.nz * g.ny * ninst;
+    const long long rows = launch_rows > 0 ? launch_rows : (long long)g.nz * g.ny;
     int ty = 16;
     while (ty > 1 && ((size_t)3 * ty * rowb + xtab > budget || 3 * ty * tpx > 512 || rows / ty < want)) ty /= 2;
     while (ty > g.ny) ty /= 2;  // a power of two (the kernels split rows by shifts)
@@ -724,6 +728,8 @@ void free_padded(Engine& E, Group& G) {
     if (b) (void)hipFree(b);
   G.Sx = G.Sy = G.kt = G.post = G.twx = G.twy = G.twz = G.kpot = G.phx = G.phy = G.phz = nullptr;
   G.cap = 0;
+  G.user_shapes = false;  // the new grid starts from the default launch shapes
+  G.tuned_for = 0;
   E.k1_ok = false;
   if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
 }
@@ -1606,13 +1612,16 @@ mm_status batch_run(mm_batch* bt, mm_instance* inst, int n, long long max_steps,
   std::vector<std::vector<int>> members(ng);
   for (int i = 0; i < n; ++i) members[inst[i].mesh_id].push_back(i);
   for (int g = 0; g < ng; ++g) nb[g] = (int)members[g].size();
-  // launch shapes for the group's instance count: one launch per pass covers
-  // every instance of every group, so rows per workgroup grow with the count
+  // launch shapes for the whole launch: one launch per pass covers every
+  // instance of every group, so each mesh takes rows per workgroup up to the
+  // LDS and thread limits when the launch has workgroups enough
+  long long launch_rows = 0;
+  for (int g = 0; g < ng; ++g) launch_rows += (long long)E.groups[g].g.nz * E.groups[g].g.ny * nb[g];
   for (int g = 0; g < ng; ++g) {
     Group& G = E.groups[g];
-    if (nb[g] == 0 || nb[g] == G.tuned_for) continue;
-    MMCHK(choose_tuning(G, E.prec, E.csz, nb[g]));
-    G.tuned_for = nb[g];
+    if (nb[g] == 0 || launch_rows == G.tuned_for) continue;
+    MMCHK(choose_tuning(G, E.prec, E.csz, launch_rows));
+    G.tuned_for = launch_rows;
     if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
     E.k1_ok = false;
   }
@@ -1667,6 +1676,17 @@ template <typename T>
 mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, double k, double h, long long n_iter,
                    double* E_out, hipStream_t s) {
   Engine& E = p->e;
+  {  // launch shapes for all the images (one launch per pass), unless set by the caller
+    Group& Gm = E.groups[0];
+    const long long rows = (long long)Gm.g.nz * Gm.g.ny * n_img;
+    if (!Gm.user_shapes && rows != Gm.tuned_for) {
+      MMCHK(choose_tuning(Gm, E.prec, E.csz, rows));
+      Gm.tuned_for = rows;
+      MMCHK(engine_reserve(E, std::vector<int>{p->maxb}));
+      if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
+      E.k1_ok = false;
+    }
+  }
   const Group& G = E.groups[0];
   const size_t S = 3 * (size_t)G.g.N;
   if (E.neb_cap < n_img) {
@@ -1887,6 +1907,7 @@ mm_status autotune_impl(mm_plan* p, const mm_params* q, int batch, const void* m
     (void)last;
   }
   G.tu = best;
+  G.user_shapes = true;
   E.k1_ok = false;  // the timing runs' stages used the stage buffers for its own state
   MMCHK(engine_reserve(E, std::vector<int>{p->maxb}));
   if (E.gexec) { (void)hipGraphExecDestroy(E.gexec); E.gexec = nullptr; }
@@ -2431,6 +2452,7 @@ mm_status mm_plan_set_shapes(mm_plan* p, const int32_t* shape) {
     if (!fits) return fail(MM_E_ARG, "launch shapes do not fit the scalar-potential route's passes");
   }
   G.tu = t;
+  G.user_shapes = true;
   MMCHK(engine_reserve(p->e, std::vector<int>{p->maxb}));
   if (p->e.gexec) {
     (void)hipGraphExecDestroy(p->e.gexec);
