@@ -568,7 +568,7 @@ hipError_t launch_eval(const GroupSet<T>& gs, const Epi<T>* epis, int mode, bool
         } else if (h.g.nz == 1) {
           lb.set(i, y2d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, ((size_t)3 * h.tu.cb_y2 * col_stride(h.g.Py) + h.g.Py) * csz +
-                                  (y2d_tensor_in_lds(h.g) ? (size_t)4 * h.tu.cb_y2 * h.g.Ky * (csz / 2) : 0));
+                                  (y2d_tensor_in_lds(h.g) ? (size_t)4 * (h.tu.cb_y2 + y2d_packed(h.g)) * h.g.Ky * (csz / 2) : 0));
         } else {
           lb.set(i, y3d_blocks(h.g, h.tu, h.batch));
           lds = std::max(lds, (size_t)h.tu.cb_y * col_stride(h.g.Py) * csz);

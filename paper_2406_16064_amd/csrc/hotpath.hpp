@@ -312,7 +312,8 @@ __device__ __forceinline__ void tensor_apply(const HotPlan<T>& hp, int kx, int k
 // (b, c, z, kx); forward Sx(ny) -> Sy(Py) or inverse Sy(Py) -> Sx(ny).
 // ---------------------------------------------------------------------------
 __host__ __device__ inline long long y2d_blocks(const Geo& g, const Tuning& tu, int batch) {
-  return (long long)batch * ((g.Xp + tu.cb_y2 - 1) / tu.cb_y2);
+  const int slots = y2d_packed(g) ? g.Lx : g.Xp;  // packed: kx = 0 and Lx share a slot
+  return (long long)batch * ((slots + tu.cb_y2 - 1) / tu.cb_y2);
 }
 // 3-D groups: tiles of cb_y consecutive kx inside one (component, z) plane
 __host__ __device__ inline long long y3d_blocks(const Geo& g, const Tuning& tu, int batch) {
@@ -342,6 +343,42 @@ struct ColStore {
   __device__ __forceinline__ void put(int, int e, Cx<T> v) const {
     if (CHK && e >= n) return;
     gsto(base, coff + (uint32_t)e * (uint32_t)sizeof(Cx<T>), v);
+  }
+};
+
+// A column of the 2-D y pass.  The kx = 0 and kx = Lx (Nyquist) columns of a
+// real field's x spectrum are real in y; the pass carries them as one complex
+// column (kx = 0 in the real part, kx = Lx in the imaginary part): coff2 is
+// the kx = Lx column for that packed column, ~0u for every other one.
+template <typename T>
+struct ColLoad2 {
+  const Cx<T>* base;
+  uint32_t coff, coff2;
+  int n;
+  template <bool CHK>
+  __device__ __forceinline__ Cx<T> get(int, int e) const {
+    if (CHK && e >= n) return Cx<T>{T(0), T(0)};
+    const uint32_t eo = (uint32_t)e * (uint32_t)sizeof(Cx<T>);
+    const Cx<T> v = gldo(base, coff + eo);
+    if (coff2 == ~0u) return v;
+    return Cx<T>{v.x, gldo(base, coff2 + eo).x};
+  }
+};
+template <typename T>
+struct ColStore2 {
+  Cx<T>* base;
+  uint32_t coff, coff2;
+  int n;
+  template <bool CHK>
+  __device__ __forceinline__ void put(int, int e, Cx<T> v) const {
+    if (CHK && e >= n) return;
+    const uint32_t eo = (uint32_t)e * (uint32_t)sizeof(Cx<T>);
+    if (coff2 == ~0u) {
+      gsto(base, coff + eo, v);
+    } else {
+      gsto(base, coff + eo, Cx<T>{v.x, T(0)});
+      gsto(base, coff2 + eo, Cx<T>{v.y, T(0)});
+    }
   }
 };
 
@@ -375,14 +412,19 @@ template <typename T, bool R16, int SL = 0, int EPT = 16>
 __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep, long long bid0, Cx<T>* lds) {
   const Geo& g = hp.g;
   const int CB = hp.tu.cb_y2;
-  const unsigned tiles = (unsigned)((g.Xp + CB - 1) / CB);
+  // column slots: slot k the column kx = k; packed (y2d_packed), Lx slots
+  // with kx = 0 and kx = Lx together in slot 0, else Lx + 1
+  const int L = g.Lx;
+  const bool pk = SL > 0 ? SL >= 1024 : y2d_packed(g);  // the same predicate (Py = SL)
+  const int nslot = pk ? L : L + 1;
+  const unsigned tiles = (unsigned)((nslot + CB - 1) / CB);
   const unsigned bid = (unsigned)bid0;
   const int tile = (int)(bid % tiles);
   const int b = (int)(bid / tiles);
   if (ep.ctl && ldu(&ep.ctl[b].done)) return;
   const int kx0 = tile * CB;
-  const int ncb = g.Xp - kx0 < CB ? g.Xp - kx0 : CB;  // kx of this tile inside the spectrum
-  const int ncol = 3 * ncb;                         // column c * ncb + j: component c of kx0 + j
+  const int ncb = nslot - kx0 < CB ? nslot - kx0 : CB;  // slots of this tile
+  const int ncol = 3 * ncb;                     // column c * ncb + j: component c of slot kx0 + j
   const int cs = col_stride(g.Py);
   const int sh = hp.fd[1].psh;
   const int Xp = g.Xp, ny = g.ny;
@@ -392,6 +434,7 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   const int cc = mc < ncol ? mc : 0;
   const int c = cc / ncb, j = cc - c * ncb;
   const uint32_t coff = (uint32_t)((c * Xp + kx0 + j) * ny) * (uint32_t)sizeof(Cx<T>);
+  const uint32_t coff2 = pk && kx0 + j == 0 ? (uint32_t)((c * Xp + L) * ny) * (uint32_t)sizeof(Cx<T>) : ~0u;
   Cx<T>* base = hp.Sx + (size_t)b * g.sx;
   // LDS after the columns: the twiddle table (Py) and the tensor rows of this
   // tile, kt[a][j][ky] for the components a = xx, yy, zz, xy and the ncb kx
@@ -403,17 +446,25 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   tab.issue(hp.fd[1].tw, g.Py, nullptr, 0);
   SegTableCopy<T, 8> ktab;
   if (ktlds) ktab.issue(hp.kt + (size_t)kx0 * g.Ky, (size_t)g.Kz * g.Xp * g.Ky, ncb * g.Ky, 4);
+  // the packed slot's tile also takes the tensor rows of kx = Lx, after the
+  // rows of a full tile (4 (Py/2 + 1) values: compiled lengths hold them all
+  // in registers while the first stage runs, 2 EPT / 3 + 1 a thread)
+  const bool packed = pk && kx0 == 0;
+  T* const ktlN = ktl + 4 * CB * g.Ky;
+  SegTableCopy<T, (SL > 0 ? 2 * EPT / 3 + 1 : 8)> ktabN;
+  if (ktlds && packed) ktabN.issue(hp.kt + (size_t)L * g.Ky, (size_t)g.Kz * g.Xp * g.Ky, g.Ky, 4);
   auto hook = [&]() {
     tab.store(twl);
     if (ktlds) ktab.store(ktl);
+    if (ktlds && packed) ktabN.store(ktlN);
   };
   const bool half = g.Py == 2 * ny;  // ny inputs / outputs of Py points
   if constexpr (SL > 0)
-    fft_static<T, SL, (EPT > 8), false, true, false, true, true, false, EPT>(lds, twl, cs, ncol,
-                                                                       ColLoad<T>{base, coff, ny}, NoStore<T>{}, hook);
+    fft_static<T, SL, (EPT > 8), false, true, false, true, true, false, EPT>(
+        lds, twl, cs, ncol, ColLoad2<T>{base, coff, coff2, ny}, NoStore<T>{}, hook);
   else
     fft_run<T, false, true, false, true, R16>(lds, hp.fd[1], twl, cs, ncol, tpc, half, false,
-                                              ColLoad<T>{base, coff, ny}, NoStore<T>{}, hook);
+                                              ColLoad2<T>{base, coff, coff2, ny}, NoStore<T>{}, hook);
   Cx<T>* const spec = lds;
   const T s = T(ldu(&hp.prm[b].demag_scale));
   // tensor entry of component a at o = jj Ky + ky (kx0 + jj): from the LDS
@@ -423,8 +474,10 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
   const size_t kgs = (size_t)g.Kz * g.Xp * g.Ky;
   auto kent = [&](int a, int o) -> T { return ktlds ? ktl[a * seg + o] : gld(ktg + a * kgs + o); };
   const FDiv dpy = fdiv_of(g.Py);
+  const int psh = SL > 0 ? p2_psh(SL, EPT > 8) : sh;
   for (int t = threadIdx.x; t < ncb * g.Py; t += blockDim.x) {
     const int jj = fdiv_q(t, dpy), ky = t - mul24(jj, g.Py);
+    if (packed && jj == 0) continue;  // below
     const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
     const T sy = ky > g.Py - ky ? T(-1) : T(1);
     const int o = jj * g.Ky + kyf;
@@ -439,13 +492,60 @@ __device__ __forceinline__ void y_fused2d(const HotPlan<T>& hp, const Epi<T>& ep
     m1 = {kxy * a.x + kyy * bq.x, kxy * a.y + kyy * bq.y};
     m2 = {kzz * cq.x, kzz * cq.y};
   }
+  if (packed) {
+    // the packed slot: Z = A + i B with A (kx = 0) and B (kx = Lx) the spectra
+    // of real sequences, so A(k) = (Z(k) + conj Z(-k)) / 2 and
+    // B(k) = (Z(k) - conj Z(-k)) / 2i; each takes the product with the tensor
+    // of its own kx, and W = H_A + i H_B goes back (its inverse transform
+    // holds the two real fields in its real and imaginary parts).  One thread
+    // a pair (k, Py - k).
+    const T* const ktL = hp.kt + (size_t)L * g.Ky;
+    auto kentN = [&](int a, int kyf) -> T { return ktlds ? ktlN[a * g.Ky + kyf] : gld(ktL + a * kgs + kyf); };
+    for (int k1 = threadIdx.x; k1 <= g.Py / 2; k1 += blockDim.x) {
+      const int k2 = k1 == 0 ? 0 : g.Py - k1;
+      Cx<T> A1[3], B1[3];
+#pragma unroll
+      for (int cp = 0; cp < 3; ++cp) {
+        const Cx<T> z1 = spec[(cp * ncb) * cs + pidx(k1, psh)];
+        const Cx<T> z2 = spec[(cp * ncb) * cs + pidx(k2, psh)];
+        A1[cp] = {T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
+        const Cx<T> d = {T(0.5) * (z1.x - z2.x), T(0.5) * (z1.y + z2.y)};
+        B1[cp] = {d.y, -d.x};
+      }
+      for (int side = 0; side < (k2 == k1 ? 1 : 2); ++side) {
+        const int ky = side == 0 ? k1 : k2;
+        const int kyf = ky <= g.Py - ky ? ky : g.Py - ky;
+        const T sy = ky > g.Py - ky ? T(-1) : T(1);
+        // A(-k) = conj A(k), B(-k) = conj B(k)
+        Cx<T> A[3], B[3];
+#pragma unroll
+        for (int cp = 0; cp < 3; ++cp) {
+          A[cp] = side == 0 ? A1[cp] : cconj(A1[cp]);
+          B[cp] = side == 0 ? B1[cp] : cconj(B1[cp]);
+        }
+        const T axx = kent(0, kyf) * s, ayy = kent(1, kyf) * s, azz = kent(2, kyf) * s;
+        const T axy = kent(3, kyf) * (s * sy);
+        const T bxx = kentN(0, kyf) * s, byy = kentN(1, kyf) * s, bzz = kentN(2, kyf) * s;
+        const T bxy = kentN(3, kyf) * (s * sy);
+        const Cx<T> ha[3] = {{axx * A[0].x + axy * A[1].x, axx * A[0].y + axy * A[1].y},
+                             {axy * A[0].x + ayy * A[1].x, axy * A[0].y + ayy * A[1].y},
+                             {azz * A[2].x, azz * A[2].y}};
+        const Cx<T> hb[3] = {{bxx * B[0].x + bxy * B[1].x, bxx * B[0].y + bxy * B[1].y},
+                             {bxy * B[0].x + byy * B[1].x, bxy * B[0].y + byy * B[1].y},
+                             {bzz * B[2].x, bzz * B[2].y}};
+#pragma unroll
+        for (int cp = 0; cp < 3; ++cp)
+          spec[(cp * ncb) * cs + pidx(ky, psh)] = Cx<T>{ha[cp].x - hb[cp].y, ha[cp].y + hb[cp].x};
+      }
+    }
+  }
   __syncthreads();
   if constexpr (SL > 0)
-    fft_static<T, SL, (EPT > 8), true, false, true, true, false, true, EPT>(lds, twl, cs, ncol, NoLoad<T>{},
-                                                                      ColStore<T>{base, coff, ny}, NoHook{});
+    fft_static<T, SL, (EPT > 8), true, false, true, true, false, true, EPT>(
+        lds, twl, cs, ncol, NoLoad<T>{}, ColStore2<T>{base, coff, coff2, ny}, NoHook{});
   else
     fft_run<T, true, false, true, true, R16>(lds, hp.fd[1], twl, cs, ncol, tpc, false, half, NoLoad<T>{},
-                                             ColStore<T>{base, coff, ny}, NoHook{});
+                                             ColStore2<T>{base, coff, coff2, ny}, NoHook{});
 }
 
 // 3-D groups keep Sx in kx blocks, [3][nz][XB][ny][kSxB].  A y tile is cb_y

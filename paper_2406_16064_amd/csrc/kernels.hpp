@@ -68,6 +68,13 @@ template <typename T> struct Epi {
 // table take 71 KB of LDS).  Host and kernel size the LDS by this predicate.
 __host__ __device__ inline bool y2d_tensor_in_lds(const Geo& g) { return g.Py <= 1024; }
 
+// From Py = 1024 on, the fused 2-D y pass carries the kx = 0 and kx = Lx
+// columns (both real in y) as one complex column, Lx workgroup slots instead
+// of Lx + 1: the extra workgroup of a kx = Lx column unbalances the CUs once
+// each column takes long (Py = 1024, 2048: 7% a pass); at Py = 512 the longer
+// packed workgroup costs more than the balance gains.
+__host__ __device__ inline bool y2d_packed(const Geo& g) { return g.Py >= 1024; }
+
 struct Tuning {
   int ty_f;     // rows per workgroup of the forward x pass
   int tpc_f;    // threads per row of its transform

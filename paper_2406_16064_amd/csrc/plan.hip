@@ -452,8 +452,10 @@ mm_status choose_tuning(Group& G, mm_precision prec, size_t csz, long long launc
     const int tpc = std::max(tmin, std::min(2 * tmin, 64));
     const size_t colb = 3 * (size_t)col_stride(g.Py) * csz;
     int cb = 8;
-    while (cb > 1 && (cb * (colb + ktab2) + ytab > budget || 3 * cb * tpc > 512 || g.Xp / cb < want)) cb /= 2;
-    if (cb * (colb + ktab2) + ytab > 160 * 1024 || 3 * cb * tpc > 512)
+    // packed: the tile of slot 0 also holds the tensor rows of kx = Lx
+    const int pk = y2d_packed(g);
+    while (cb > 1 && (cb * colb + (cb + pk) * ktab2 + ytab > budget || 3 * cb * tpc > 512 || g.Xp / cb < want)) cb /= 2;
+    if (cb * colb + (cb + pk) * ktab2 + ytab > 160 * 1024 || 3 * cb * tpc > 512)
       return fail(MM_E_ARG, "mesh too long along y");
     t.cb_y2 = cb;
     t.tpc_y2 = tpc;
@@ -1786,7 +1788,7 @@ bool tuning_ok(const Group& G, const Tuning& t, mm_precision prec, size_t csz) {
   const size_t colb = (size_t)col_stride(g.Py) * csz;
   if (g.nz == 1) {
     if (t.cb_y2 < 1 || t.nt_y > 512 || t.tpc_y2 < tmin(g.Py, true) || 3 * t.cb_y2 * t.tpc_y2 > t.nt_y) return false;
-    if (3 * t.cb_y2 * colb + ytab + (y2d_tensor_in_lds(g) ? (size_t)4 * t.cb_y2 * g.Ky * (csz / 2) : 0) > lim)
+    if (3 * t.cb_y2 * colb + ytab + (y2d_tensor_in_lds(g) ? (size_t)4 * (t.cb_y2 + y2d_packed(g)) * g.Ky * (csz / 2) : 0) > lim)
       return false;
   } else {
     if (t.cb_y < 1 || (t.cb_y % kSxB != 0 && kSxB % t.cb_y != 0) || t.nt_y > 512 || t.tpc_y < tmin(g.Py, true) || t.cb_y * t.tpc_y > t.nt_y)

@@ -47,6 +47,7 @@ MESHES = [
     (64, 128, 2, 2e-9, 2e-9, 2e-9),    # Py = 256 = 2 ny: y passes compiled for that length
     (16, 512, 2, 2e-9, 2e-9, 2e-9),    # Py = 1024 (radix-16 plan), 3-D
     (32, 256, 1, 2e-9, 2e-9, 2e-9),    # Py = 512, 2-D fused y pass
+    (16, 512, 1, 2e-9, 2e-9, 2e-9),    # Py = 1024, 2-D: kx = 0 and kx = Lx in one packed column
     (16, 12, 8, 2e-9, 2e-9, 2e-9),     # Pz = 16 = 2 nz: FP64 z pass through LDS compiled for Pz
     (8, 8, 32, 2e-9, 2e-9, 1e-9),      # Pz = 64 = 2 nz: the same in FP32 and FP64
     (1024, 4, 1, 2e-9, 2e-9, 1e-9),    # nx = Lx = 1024: x passes compiled for that length
@@ -151,8 +152,9 @@ def test_energies(mm, mesh, prec):
     assert np.all(np.abs(E - ref) <= tol * scale), (E, ref)
 
 
-def test_batch_matches_single_calls(mm):
-    mesh = (18, 21, 1, 2e-9, 2e-9, 1e-9)
+@pytest.mark.parametrize("mesh", [(18, 21, 1, 2e-9, 2e-9, 1e-9),
+                                  (16, 512, 1, 2e-9, 2e-9, 1e-9)])  # packed 2-D y column
+def test_batch_matches_single_calls(mm, mesh):
     ms = np.stack([_rand_m(mesh, 20 + i) for i in range(3)])
     pars = []
     for i in range(3):
@@ -506,7 +508,8 @@ def test_autotune_keeps_results(mm):
 
 @pytest.mark.parametrize("mesh", [(64, 128, 2, 2e-9, 2e-9, 2e-9),     # Py = 256 = 2 ny: fixed-length y kernels
                                   (96, 70, 3, 2e-9, 2e-9, 2e-9),      # Py = 144: general ones
-                                  (32, 256, 1, 2e-9, 2e-9, 2e-9)])    # 2-D fused y pass, Py = 512
+                                  (32, 256, 1, 2e-9, 2e-9, 2e-9),     # 2-D fused y pass, Py = 512
+                                  (16, 512, 1, 2e-9, 2e-9, 2e-9)])    # the same, packed, Py = 1024
 def test_every_launch_shape_kind(mm, mesh):
     """Launch shapes set by hand cover each code path the autotuner can pick
     (y tiles staged through LDS or read with stride, 8 or 16 transform entries
