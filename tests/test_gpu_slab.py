@@ -141,3 +141,28 @@ def test_slab_instantiations_batched_fp32(mm):
         assert status == mm.MM_OK and st.t == t_end
         assert st.n_accept == ost.n_accept and st.n_reject == ost.n_reject, k
         assert np.max(np.linalg.norm(devs[k].cpu().numpy() - mo, axis=0)) <= 1e-4, k
+
+
+@pytest.mark.parametrize("shape", [dict(ty_x=4, nt_i=512), dict(ty_x=2, nt_i=512), dict(ty_x=2, nt_i=256)],
+                         ids=["4rows512", "2rows512", "2rows256"])
+def test_slab_stage_epilogue_shapes_replay_fp32(mm, shape):
+    """The FP32 stage and error kernels in three inverse-x launch shapes (4 or 2
+    rows of 512 cells a workgroup, one cell or several a thread) on 512 x 6 x 16,
+    whose y tiles end in a partial one: 10 accepted oracle steps replayed, m
+    within 1e-4."""
+    mesh = (512, 6, 16) + tuple(W["mesh"][3:])
+    m0 = representable(inputs.initial_state(2, mesh), torch.float32)
+    op = oracle_params(W["params"], W["terms"])
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+    ost = dp45.State(rtol=W["rtol"])
+    mo = dp45.run(f, m0.copy(), ost, max_accept=10)
+    plan = mm.Plan(mesh, "f32", terms=W["terms"])
+    gp = gpu_params(mm, W["params"], W["terms"])
+    md = to_dev(m0, torch.float32)
+    base = plan.shapes()
+    plan.set_shapes(dict(base, **shape))
+    assert plan.shapes()["ty_x"] == shape["ty_x"] and plan.shapes()["nt_i"] == shape["nt_i"]
+    st = mm.new_states(1, rtol=W["rtol"])
+    plan.rk45_run(gp, md, st, replay_h=ost.accepted_h)
+    assert st[0].n_accept == 10
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= 1e-4
