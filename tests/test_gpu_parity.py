@@ -268,6 +268,35 @@ def test_heun_matches_oracle(mm, mesh, prec):
     assert np.max(np.abs(np.linalg.norm(got.astype(np.float64), axis=0) - 1)) <= (1e-14 if prec == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_heun_successive_calls(mm, prec):
+    """Successive calls on one plan: 40 steps, then 37 steps from another array with
+    another step size, then 34 after new launch shapes, each against the oracle
+    (FP64 1e-10, FP32 1e-4 in m); 2-D and 3-D meshes."""
+    p = dict(Ms=5.8e5, A=1.5e-11, D=3e-3, Ku=8e5, u=(0.2, -0.3, 1.0), H=(3e4, -2e4, 2e5), alpha=0.3)
+    tol = 1e-10 if prec == "f64" else 1e-4
+    for mesh in [(48, 40, 1, 2e-9, 2e-9, 2e-9), (24, 20, 5, 3e-9, 3e-9, 3e-9)]:
+        op = oracle_params(p, F.ALL_TERMS)
+        f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, _kernel(mesh))
+        plan = mm.Plan(mesh, prec, terms=F.ALL_TERMS)
+        gp = gpu_params(mm, p, F.ALL_TERMS)
+        for k, (h, n, seed) in enumerate([(4e-14, 40, 7), (2.5e-14, 37, 8), (3e-14, 34, 9)]):
+            if k == 2:
+                sh = plan.shapes()
+                for cand in (dict(sh, ty_x=2 * sh["ty_x"]), dict(sh, ty_x=max(1, sh["ty_x"] // 2))):
+                    try:
+                        plan.set_shapes(cand)
+                        break
+                    except mm.MMError:
+                        continue
+                assert plan.shapes() != sh
+            m0 = representable(inputs.random_unit(*mesh[:3], np.random.default_rng(seed)), DT[prec])
+            mo = heun.run(f, m0.copy(), h, n)
+            md = to_dev(m0, DT[prec])
+            plan.heun_run(gp, md, h, n)
+            assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= tol, (mesh, k)
+
+
 def test_heun_batch_of_different_parameters_fp64(mm):
     """Two instances with their own Ms, field and damping in one call, each against
     the oracle; the paper's throughput terms (demag, exchange, Zeeman)."""
