@@ -9,6 +9,10 @@
   oracle's Newell tensor, the local terms on the clipped 3x3x3 neighbourhood.
 * 32-image NEB chain on 128x128x1 and the uneven sweep's largest meshes
   against the oracle.
+* The largest Heun throughput film, 1024x1024x1 (the library's largest axis;
+  Py = 2048: the fused 2-D y pass compiled for that length, kx = 0 and kx = Lx
+  in one packed column, tensor rows from global memory), autotuned as the Heun
+  benchmark does: the dense field and four Heun steps against the oracle.
 
 Plans are autotuned first (as bench.py does) except the batch, which bench.py
 runs with its default shapes.
@@ -16,7 +20,7 @@ runs with its default shapes.
 import numpy as np
 import pytest
 
-from oracle import dp45, neb, newell
+from oracle import dp45, heun, neb, newell
 from oracle import fields as F
 from paper_2406_16064_amd import inputs
 
@@ -241,3 +245,40 @@ def test_batch_mixes_compiled_and_general_y_transforms_fp64(mm):
         ost = dp45.State(rtol=1e-6)
         mo = dp45.run(f, m0[k].copy(), ost, t_end=t_end)
         assert np.max(np.abs(devs[k].cpu().numpy() - mo)) <= 1e-9, k
+
+
+# ----------------------------------------------------------------------------- largest film
+
+
+def _film_kernel(mesh):
+    import os
+    if mesh not in _kern:
+        msh = F.Mesh(*mesh)
+        grid = newell.tensor_grid(msh.nx, msh.ny, msh.nz, msh.dx, msh.dy, msh.dz,
+                                  workers=max(1, min(16, os.cpu_count() or 1)))
+        _kern[mesh] = F.DemagKernel(msh, grid=grid)
+    return _kern[mesh]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_heun_film_1024_full_size(mm, prec):
+    w = inputs.heun_film(1024)
+    mesh = tuple(w["mesh"])
+    print("film 1024 %s: oracle tensor grid" % prec, flush=True)
+    kern = _film_kernel(mesh)
+    m0 = representable(inputs.heun_initial(1024), DT[prec])
+    op = oracle_params(w["params"], w["terms"])
+    plan = mm.Plan(mesh, prec, terms=w["terms"])
+    gp = gpu_params(mm, w["params"], w["terms"])
+    assert plan.padded()[1] == 2048
+    md = to_dev(m0, DT[prec])
+    plan.autotune(gp, md, reps=2)  # as the Heun benchmark does
+    print("film 1024 %s: fields" % prec, flush=True)
+    Href = F.effective_field(m0, F.Mesh(*mesh), op, kern)
+    assert field_err(plan.effective_field(gp, md).cpu().numpy(), Href) <= TOL[prec]
+    print("film 1024 %s: Heun steps" % prec, flush=True)
+    f = lambda y: F.llg_rhs(y, F.Mesh(*mesh), op, kern)
+    mo = heun.run(f, m0.copy(), w["h"], 4)
+    plan.heun_run(gp, md, w["h"], 4)
+    assert np.max(np.linalg.norm(md.cpu().numpy() - mo, axis=0)) <= (1e-10 if prec == "f64" else 1e-4)
