@@ -308,7 +308,8 @@ mm_status mm_rk45_relax(mm_plan* plan, const mm_params* params, int32_t batch, v
  * stored as images[n_img][3][nz][ny][nx]: n_iter iterations of the
  * precession-free relaxation with time step h and spring constant k_spring
  * (A/m); end images stay fixed.  E_out (host, n_img) receives the image
- * energies before the last iteration.  Synchronises.  Paper: "Miscellaneous"
+ * energies before the last iteration (n_iter = 0: of the images as given,
+ * which stay unchanged).  Synchronises.  Paper: "Miscellaneous"
  * (NEB); tangent, spring and distance follow the project's stated reading. */
 mm_status mm_neb_run(mm_plan* plan, const mm_params* params, void* images, int32_t n_img,
                      double k_spring, double h, int64_t n_iter, double* E_out,

@@ -1757,6 +1757,10 @@ mm_status neb_impl(mm_plan* p, const mm_params* q, void* images, int n_img, doub
   }
   if (ge) (void)hipGraphExecDestroy(ge);
   if (st != MM_OK) return st;
+  if (n_iter == 0) {  // no iteration: the energies of the images as given
+    HIPCHK(launch_eval<T>(gs, epi_slot<T>(E, 2), MODE_FIELD_ENERGY, demag_on(E), s));
+    HIPCHK(launch_energy_reduce(E.partial, n_img, bpi, E.e5, s));
+  }
   HIPCHK(hipMemcpyAsync(E.he5, E.e5, sizeof(double) * 5 * n_img, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (E_out)
@@ -2471,7 +2475,7 @@ mm_status mm_neb_run(mm_plan* p, const mm_params* q, void* images, int32_t n_img
   if ((q->terms & kGeneralTerms) || (p->e.terms & MM_DEMAG_POTENTIAL))
     return fail(MM_E_ARG, "NEB chains take uniform material, the Newell demag and no interlayer or torque terms");
   if (!images) return fail(MM_E_ARG, "images is null");
-  if (!is_fin(k_spring) || !is_fin(h) || h <= 0 || n_iter < 1) return fail(MM_E_ARG, "invalid k_spring, h or n_iter");
+  if (!is_fin(k_spring) || !is_fin(h) || h <= 0 || n_iter < 0) return fail(MM_E_ARG, "invalid k_spring, h or n_iter");
   hipStream_t s = (hipStream_t)hip_stream;
   return p->e.prec == MM_F32 ? neb_impl<float>(p, q, images, n_img, k_spring, h, n_iter, E_out, s)
                              : neb_impl<double>(p, q, images, n_img, k_spring, h, n_iter, E_out, s);
